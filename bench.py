@@ -1,0 +1,363 @@
+"""Benchmark of the MI355X PIPECG library.
+
+Main line (the JSON ``value``): PIPECG iterations per second on the 3-D
+7-point Poisson problem on a 128^3 grid (N = 2,097,152, nnz = 14,581,760),
+Jacobi preconditioner, x* uniform in [-1, 1] (seed 1), b = A x*, x0 = 0,
+FP64.  One step = one PIPECG iteration (fused vector updates + Jacobi + dot
+products, then SpMV with the reduction and scalar recurrences); the timed
+region is one ppcg_solve of exactly ``--steps`` fixed iterations, inputs
+resident in device memory, bracketed by device synchronisation.
+
+Beside it: effective HBM bandwidth from the algorithmic byte model, the
+roofline of the dominant kernel (average launch time from HIP events inside
+the library), the FP64 CPU oracle timed on a bounded sample of the same
+workload, and extra legs for the other workloads (64^2 latency case, mixed
+precision on the 27-point 160^3 problem, the 256-system batch, serving).
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "PPCG iters/sec + effective HBM GB/s (% of peak); solves/sec, p50/p99 latency"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ppcg_kernels.hpp", "ppcg_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2105_06176_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    e = d.get(f"{kernel}|{workload}")
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
+def sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def leg_c2(args, torch, ppcg, wl, oracle):
+    A = wl.poisson3d(128)
+    b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
+    bd = torch.as_tensor(b).cuda()
+    S = ppcg.Solver(A, fixed_iters=max(args.warmup, 1))
+    mi = S.matrix_info()
+    log(f"128^3: format={mi['format']} sigma={mi['sell_sigma']} stored={mi['nnz_stored']} setup={mi['setup_ms']:.1f}ms")
+    x = torch.empty_like(bd)
+    if args.warmup > 0:
+        S.solve(bd, out=x)
+    S.set_options(fixed_iters=args.steps)
+    sync()
+    t0 = time.perf_counter()
+    _, info = S.solve(bd, out=x)
+    sync()
+    dt = time.perf_counter() - t0
+    assert info["iters"] == args.steps, info
+    ips = args.steps / dt
+    gbs = mi["bytes_per_iter"] * ips / 1e9
+    log(f"128^3 fixed {args.steps}: {dt * 1e3:.2f} ms, {ips:.0f} it/s, {gbs:.0f} GB/s")
+    # kernel durations (HIP events around each launch on the library's stream)
+    ms_vma, ms_spmv = S.time_kernels(bd, iters=100)
+    log(f"kernel avg: vma {ms_vma * 1e3:.2f} us, spmv {ms_spmv * 1e3:.2f} us")
+    dom = "vma" if ms_vma >= ms_spmv else "spmv"
+    bytes_dom = mi["bytes_vma"] if dom == "vma" else mi["bytes_spmv"]
+    ms_dom = ms_vma if dom == "vma" else ms_spmv
+    achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
+    kname = "k_vma<double>" if dom == "vma" else "k_spmv<double,MODE_ITER>"
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(kname, "poisson3d_128"),
+            "kernel": kname, "bytes_per_launch": bytes_dom, "avg_launch_us": round(ms_dom * 1e3, 3),
+            "other_kernel_us": round((ms_spmv if dom == "vma" else ms_vma) * 1e3, 3),
+            "other_kernel_gbs": round((mi["bytes_spmv"] if dom == "vma" else mi["bytes_vma"]) /
+                                      ((ms_spmv if dom == "vma" else ms_vma) * 1e-3) / 1e9, 1)}
+    # tolerance run (after the fixed iterations; untimed in the main value)
+    S.set_options(tol=1e-10, max_iter=10000)
+    sync()
+    t0 = time.perf_counter()
+    xt, it = S.solve(bd)
+    sync()
+    ttol = time.perf_counter() - t0
+    tol_run = {"iters": it["iters"], "status": it["status"], "rel_resid_true": it["rel_resid_true"],
+               "time_s": round(ttol, 4), "restarts": it["restarts"]}
+    log(f"128^3 to 1e-10: {it['iters']} iters, true rel resid {it['rel_resid_true']:.2e}, {ttol * 1e3:.1f} ms")
+    res = {"ips": ips, "dt": dt, "gbs": gbs, "mi": mi, "roofline": roof, "tol_run": tol_run}
+    if args.cpu_baseline:
+        k = args.cpu_iters
+        t0 = time.perf_counter()
+        ref = oracle.pipecg(A, b, fixed_iters=k)
+        tc = time.perf_counter() - t0
+        ncpu, model = cpu_info()
+        res["cpu_baseline"] = {"value": round(k / tc, 3), "unit": "iters/s", "cores": 1, "kind": "oracle",
+                               "sample": f"FP64 C oracle (single thread), PIPECG {k} fixed iterations of the "
+                                         f"128^3 7-point problem incl. its initialisation, {tc:.1f} s",
+                               "host_cpus": ncpu, "host_cpu_model": model}
+        # parity of the timed configuration on the same sample
+        S.set_options(fixed_iters=k)
+        xg, _ = S.solve(bd)
+        res["parity_x_k"] = {"k": k, "rel_diff_vs_oracle": float(np.linalg.norm(xg.cpu().numpy() - ref.x) /
+                                                                  np.linalg.norm(ref.x))}
+        log(f"oracle {k} iters: {tc:.1f}s ({k / tc:.2f} it/s); GPU/oracle x_{k} rel diff "
+            f"{res['parity_x_k']['rel_diff_vs_oracle']:.2e}")
+    S.close()
+    return res
+
+
+def leg_c1(torch, ppcg, wl, oracle):
+    A = wl.poisson2d(64)
+    b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
+    bd = torch.as_tensor(b).cuda()
+    S = ppcg.Solver(A, tol=1e-8)
+    S.solve(bd)
+    ts = []
+    for _ in range(7):
+        sync()
+        t0 = time.perf_counter()
+        _, info = S.solve(bd)
+        sync()
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    ref = oracle.pipecg(A, b, tol=1e-8)
+    t0 = time.perf_counter()
+    oracle.pipecg(A, b, tol=1e-8)
+    tc = time.perf_counter() - t0
+    return {"workload": "2D 5-point Poisson 64^2, tol 1e-8", "iters": info["iters"], "oracle_iters": ref.iters,
+            "time_to_solution_ms": round(t * 1e3, 3), "us_per_iter": round(t / info["iters"] * 1e6, 2),
+            "solves_per_s": round(1 / t, 1), "rel_resid_true": info["rel_resid_true"],
+            "oracle_time_ms": round(tc * 1e3, 2)}
+
+
+def leg_c3(torch, ppcg, wl):
+    t0 = time.perf_counter()
+    A = wl.stencil27_lognormal(160, seed=0, shift=1e-3)
+    b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
+    log(f"27-pt 160^3 generated: nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
+    bd = torch.as_tensor(b).cuda()
+    out = {"workload": "3D 27-point lognormal 160^3 (N=4096000), shift 1e-3, tol 1e-10", "nnz": A.nnz}
+    xs = {}
+    for prec in ("fp64", "mixed"):
+        S = ppcg.Solver(A, tol=1e-10, precision=prec, max_iter=20000)
+        S.solve(bd)  # warm-up (graph capture, FP32 copy)
+        sync()
+        t0 = time.perf_counter()
+        x, info = S.solve(bd)
+        sync()
+        t = time.perf_counter() - t0
+        xs[prec] = x.cpu().numpy()
+        out[prec] = {"status": info["status"], "iters": info["iters"], "outer": info["outer_iters"],
+                     "restarts": info["restarts"], "rel_resid_true": info["rel_resid_true"],
+                     "time_s": round(t, 4), "solves_per_s": round(1 / t, 3)}
+        log(f"27-pt {prec}: {info}")
+        S.close()
+    out["mixed_vs_fp64_solution_rel_diff"] = float(np.linalg.norm(xs["mixed"] - xs["fp64"]) /
+                                                   np.linalg.norm(xs["fp64"]))
+    out["mixed_speedup"] = round(out["fp64"]["time_s"] / out["mixed"]["time_s"], 3)
+    return out
+
+
+def leg_c4(torch, ppcg, wl, count=256):
+    spec = wl.batch_c4(seed=0, count=count)
+    t0 = time.perf_counter()
+    mats = [wl.shifted(wl.poisson2d(side), sh) for side, sh in spec]
+    bs = [torch.as_tensor(wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1000 + i))).cuda()
+          for i, A in enumerate(mats)]
+    log(f"batch generated in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    solvers = [ppcg.Solver(A, tol=1e-10, spmv_format="sell") for A in mats]
+    setup = time.perf_counter() - t0
+    # sequential solo solves (warm: graph capture per handle excluded by a first pass)
+    for S, b in zip(solvers, bs):
+        S.solve(b)
+    sync()
+    t0 = time.perf_counter()
+    seq_iters = 0
+    for S, b in zip(solvers, bs):
+        _, info = S.solve(b)
+        seq_iters += info["iters"]
+    sync()
+    t_seq = time.perf_counter() - t0
+    ppcg.solve_batch(solvers, bs)  # warm-up
+    sync()
+    t0 = time.perf_counter()
+    xs, infos = ppcg.solve_batch(solvers, bs)
+    sync()
+    t_batch = time.perf_counter() - t0
+    ok = sum(1 for i in infos if i["status"] == 0 and i["rel_resid_true"] <= 1e-10)
+    bytes_total = sum(S.matrix_info()["bytes_per_iter"] * i["iters"] for S, i in zip(solvers, infos))
+    for S in solvers:
+        S.close()
+    return {"workload": f"{count} shifted 2D 5-point Poisson systems, side U[32,512], shift U[0,0.5), tol 1e-10",
+            "sum_n": int(sum(A.n for A in mats)), "sum_nnz": int(sum(A.nnz for A in mats)),
+            "batched_solves_per_s": round(count / t_batch, 2), "sequential_solves_per_s": round(count / t_seq, 2),
+            "batch_speedup": round(t_seq / t_batch, 3), "batch_time_s": round(t_batch, 4),
+            "sequential_time_s": round(t_seq, 4), "converged": ok, "total_iters": int(sum(i["iters"] for i in infos)),
+            "algorithmic_gbs": round(bytes_total / t_batch / 1e9, 1), "setup_s": round(setup, 2)}
+
+
+def _serve_requests(wl, n_req, seed=0):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        kind = rng.choice(3, p=[0.4, 0.3, 0.3])
+        N = float(np.exp(rng.uniform(math.log(1e3), math.log(4e6))))
+        tol = float(rng.choice([1e-6, 1e-8, 1e-10]))
+        if kind == 0:
+            A = wl.poisson2d(max(8, int(round(math.sqrt(N)))))
+        elif kind == 1:
+            A = wl.poisson3d(max(4, int(round(N ** (1 / 3)))))
+        else:
+            A = wl.random_spd(max(64, int(N)), seed=int(rng.integers(1 << 30)))
+        b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 2000 + i))
+        prec = "mixed" if tol >= 1e-8 else "fp64"
+        reqs.append((A, b, tol, prec))
+    return reqs
+
+
+def _run_server(ppcg, reqs, arrivals):
+    srv = ppcg.Server()
+    t0 = time.perf_counter()
+    i = 0
+    pending = {}
+    lat = []
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and arrivals[i] <= now:
+            A, b, tol, prec = reqs[i]
+            pending[srv.submit(A, b, tol, prec)] = arrivals[i]
+            i += 1
+        if pending:
+            srv.step()
+            for rid in list(pending):
+                r = srv.poll(rid)
+                if r is not None:
+                    lat.append(time.perf_counter() - t0 - pending.pop(rid))
+        elif i < len(reqs):
+            time.sleep(max(0.0, min(0.01, arrivals[i] - now)))
+    total = time.perf_counter() - t0
+    srv.close()
+    return total, np.array(lat)
+
+
+def leg_c5(ppcg, wl, n_req):
+    t0 = time.perf_counter()
+    reqs = _serve_requests(wl, n_req)
+    log(f"serving: {n_req} requests generated in {time.perf_counter() - t0:.1f}s")
+    _run_server(ppcg, reqs[: min(8, n_req)], np.zeros(min(8, n_req)))  # warm-up
+    total, lat = _run_server(ppcg, reqs, np.zeros(n_req))  # saturation: all at t = 0
+    sat = n_req / total
+    out = {"workload": f"{n_req} requests: 40% 2D 5-pt, 30% 3D 7-pt, 30% random SPD, N log-uniform [1e3,4e6], "
+                       "tol {1e-6,1e-8,1e-10}; FP32-inner+FP64-refinement for tol >= 1e-8",
+           "saturation_solves_per_s": round(sat, 2)}
+    rng = np.random.default_rng(0)
+    for frac in (0.5, 0.8):
+        lam = frac * sat
+        arr = np.cumsum(rng.exponential(1 / lam, size=n_req))
+        total, lat = _run_server(ppcg, reqs, arr)
+        out[f"load_{frac}"] = {"rate_per_s": round(lam, 2), "solves_per_s": round(n_req / total, 2),
+                               "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)}
+        log(f"serving at {frac} x saturation: {out[f'load_{frac}']}")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--legs", default="c1,c3,c4,c5", help="extra legs: c1,c3,c4,c5 or none")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this library runs on one GPU; multi-GPU runs are not supported "
+              "(the sharded design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import oracle
+    import workloads as wl
+    from paper_2105_06176_amd import ppcg
+
+    ppcg.lib()
+    torch.cuda.set_device(0)
+    log(f"device: {torch.cuda.get_device_name(0)}")
+    c2 = leg_c2(args, torch, ppcg, wl, oracle)
+    legs = {}
+    wanted = [x for x in args.legs.split(",") if x and x != "none"]
+    for name in wanted:
+        t0 = time.perf_counter()
+        try:
+            if name == "c1":
+                legs[name] = leg_c1(torch, ppcg, wl, oracle)
+            elif name == "c3":
+                legs[name] = leg_c3(torch, ppcg, wl)
+            elif name == "c4":
+                legs[name] = leg_c4(torch, ppcg, wl)
+            elif name == "c5":
+                legs[name] = leg_c5(ppcg, wl, args.serve_requests)
+        except Exception as e:  # a failing extra leg must not hide the main line
+            legs[name] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"leg {name} done in {time.perf_counter() - t0:.1f}s: {legs[name]}")
+    mi = c2["mi"]
+    line = {
+        "metric": METRIC, "value": round(c2["ips"], 2), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(c2["dt"] / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "PIPECG, 3D 7-point Poisson 128^3 (N=2097152, nnz=14581760), Jacobi, "
+                               "x*~U[-1,1] seed 1, b=A x*, x0=0, fixed iterations, FP64",
+                   "n": mi["n"], "nnz": mi["nnz"], "spmv_format": mi["format"], "sell_sigma": mi["sell_sigma"],
+                   "nnz_stored": mi["nnz_stored"], "bytes_per_iter": mi["bytes_per_iter"]},
+        "effective_gbs": round(c2["gbs"], 1), "pct_peak_hbm": round(100 * c2["gbs"] / PEAK_HBM_GBS, 2),
+        "roofline": c2["roofline"], "tol_1e-10": c2["tol_run"],
+    }
+    if "cpu_baseline" in c2:
+        line["cpu_baseline"] = c2["cpu_baseline"]
+        line["parity_x_k"] = c2["parity_x_k"]
+    line["legs"] = legs
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,260 @@
+/*
+ * ppcg.h -- C ABI of the MI355X (gfx950) Pipelined PCG library.
+ *
+ * The library solves A x = b for a sparse symmetric positive definite A given
+ * in CSR form, with the Jacobi preconditioner, using the pipelined
+ * preconditioned conjugate gradient method (PIPECG) of Ghysels and Vanroose
+ * as presented by Tiwari & Vadhiyar, "Efficient executions of Pipelined
+ * Conjugate Gradient Method on Heterogeneous Architectures", Algorithm 2
+ * (Section III-B).  The problem statement follows Sections I, V-A and VI of
+ * that paper: A in CSR (Section V-A), a right-hand side b, an initial guess
+ * x0, a tolerance and a maximum number of iterations (Section VI), and the
+ * Jacobi preconditioner M = diag(A) (Section V-A).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns a ppcg_status.  Nothing aborts, throws or exits
+ *     across this ABI; ppcg_last_error() gives a detail message for the most
+ *     recent failing call on the calling thread.
+ *   - Pointers are plain host or device pointers as stated per argument.
+ *     Device pointers are HIP device allocations on the device that was
+ *     current when the handle was created (torch tensors' data_ptr() work).
+ *   - Work is ordered on the HIP stream given at creation (NULL = the
+ *     default stream).  A call returns once its outputs are final.
+ *   - Handles are not thread-safe; one handle may be used by one thread at
+ *     a time and takes part in at most one solve at a time.
+ *   - Sizes: n >= 1 rows, nnz < 2^31.  Row pointers and column indices are
+ *     int32, values float64.
+ */
+#ifndef PPCG_H
+#define PPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ppcg_handle ppcg_handle; /* opaque, owned by the library */
+
+typedef enum {
+    PPCG_OK = 0,               /* converged (or ran its fixed iterations) */
+    PPCG_NOT_CONVERGED = 1,    /* reached max_iter; x holds the last iterate */
+    PPCG_BREAKDOWN = 2,        /* gamma <= 0, alpha denominator <= 0 or non-finite scalar */
+    PPCG_STAGNATED = 3,        /* recurrence converged, true residual > tol after all restarts */
+    PPCG_ERR_INVALID_ARG = -1, /* bad pointer, size, enum or option; outputs untouched */
+    PPCG_ERR_BAD_CSR = -2,     /* malformed CSR or missing / non-positive diagonal */
+    PPCG_ERR_NOMEM = -3,       /* device or pinned host allocation failed */
+    PPCG_ERR_DEVICE = -4,      /* a HIP call failed */
+    PPCG_ERR_BUDGET = -5       /* serving: request footprint exceeds the memory budget */
+} ppcg_status;
+
+/* Stopping test, evaluated at the top of every iteration (before alpha and
+ * beta, Section IV-C). */
+typedef enum {
+    PPCG_STOP_REL_RESID = 0,  /* sqrt((r,r)) <= tol * ||b||_2 on the recurrence residual;
+                                 the final true residual is checked and the solve restarted
+                                 from x when it is above tol (default) */
+    PPCG_STOP_PRECOND_ABS = 1 /* sqrt((u,u)) < tol, u = M^-1 r: the paper's absolute
+                                 preconditioned-residual test (Section VI) */
+} ppcg_stop;
+
+typedef enum {
+    PPCG_FP64 = 0,       /* every vector, matrix value and scalar in FP64 */
+    PPCG_MIXED_FP32 = 1  /* inner PIPECG with FP32 matrix values and vectors, FP64 dot
+                            products and scalars, inside an FP64 iterative-refinement
+                            loop on the FP64 operator */
+} ppcg_precision;
+
+typedef enum { PPCG_MEM_DEVICE = 0, PPCG_MEM_HOST = 1 } ppcg_mem;
+
+/* SpMV formats the autotuner chooses from (ppcg_options.spmv_format). */
+typedef enum {
+    PPCG_SPMV_AUTO = 0,      /* autotune: time the candidates on this matrix */
+    PPCG_SPMV_SELL = 1,      /* SELL-C-sigma, one lane per row, C = 64 */
+    PPCG_SPMV_CSR_VECTOR = 2 /* CSR, a group of lanes (2..64) per row */
+} ppcg_spmv_format;
+
+/* A in CSR.  Caller-owned; read only during ppcg_create (the library keeps
+ * its own device copy, so the arrays may be freed once ppcg_create returns).
+ * Requirements: row_ptr[0] = 0, row_ptr non-decreasing, row_ptr[n] = nnz,
+ * 0 <= col_idx < n, columns strictly ascending within a row, every row
+ * stores a finite diagonal entry > 0, all values finite.  Symmetry and
+ * positive definiteness are not checked (a matrix that is not SPD ends in
+ * PPCG_BREAKDOWN or PPCG_NOT_CONVERGED). */
+typedef struct {
+    size_t struct_size;      /* sizeof(ppcg_csr) */
+    int32_t n;               /* rows = columns */
+    int64_t nnz;             /* stored entries */
+    const int32_t *row_ptr;  /* [n + 1] */
+    const int32_t *col_idx;  /* [nnz] */
+    const double *values;    /* [nnz] */
+    ppcg_mem mem;            /* where the three arrays live */
+} ppcg_csr;
+
+/* Solver options; initialise with ppcg_default_options(). */
+typedef struct {
+    size_t struct_size;      /* sizeof(ppcg_options) */
+    double tol;              /* stopping tolerance (default 1e-8) */
+    int32_t max_iter;        /* maximum total iterations (default 10000, the paper's) */
+    int32_t fixed_iters;     /* > 0: run exactly this many iterations, ignore tol and
+                                max_iter; stop early only on breakdown or gamma == 0 */
+    int32_t max_restarts;    /* restarts from x allowed (default 3) */
+    ppcg_stop stop;          /* default PPCG_STOP_REL_RESID */
+    ppcg_precision precision;/* default PPCG_FP64 */
+    ppcg_mem vec_mem;        /* where b, x0 and x live (default PPCG_MEM_DEVICE) */
+    ppcg_spmv_format spmv_format; /* default PPCG_SPMV_AUTO */
+    int32_t graph_iters;     /* iterations per captured HIP graph; 0 = automatic */
+    double inner_tol;        /* mixed precision: relative reduction asked of each inner
+                                solve (0 = automatic) */
+    int32_t max_outer;       /* mixed precision: maximum refinement steps (default 30) */
+    uint32_t flags;          /* reserved, must be 0 */
+} ppcg_options;
+
+/* Per-solve report. */
+typedef struct {
+    size_t struct_size;      /* sizeof(ppcg_info) */
+    ppcg_status status;
+    int32_t iters;           /* PIPECG iterations (x-updates); total inner iterations in
+                                mixed precision */
+    int32_t outer_iters;     /* refinement steps (mixed precision), else 0 */
+    int32_t restarts;        /* restarts from x (true residual above tol, or breakdown) */
+    double rel_resid_true;   /* ||b - A x||_2 / ||b||_2 in FP64 at exit */
+    double rel_resid_recur;  /* sqrt((r,r)) / ||b|| of the recurrence at exit */
+    double precond_norm;     /* sqrt((u,u)) at exit */
+    double time_ms;          /* wall time of the solve on its stream */
+    double model_bytes;      /* algorithmic HBM bytes moved by the iterations */
+} ppcg_info;
+
+/* Static description of a handle's matrix as the library stores it. */
+typedef struct {
+    size_t struct_size;      /* sizeof(ppcg_matrix_info) */
+    int32_t n;
+    int64_t nnz;
+    int64_t nnz_stored;      /* entries stored including SELL padding */
+    ppcg_spmv_format format; /* format chosen (never AUTO) */
+    int32_t sell_c;          /* SELL chunk height */
+    int32_t sell_sigma;      /* SELL sorting window (1 = unsorted) */
+    int32_t lanes_per_row;   /* CSR-vector group size */
+    int32_t tile_rows;       /* rows per workgroup tile */
+    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration (both kernels) */
+    double bytes_vma;        /* algorithmic bytes of one fused VMA+PC+dot launch */
+    double bytes_spmv;       /* algorithmic bytes of one SpMV launch */
+    double device_bytes;     /* device memory held by the handle */
+    double setup_ms;         /* time spent in ppcg_create (validation, conversion, tuning) */
+} ppcg_matrix_info;
+
+/* Fill *opt with the defaults listed above. */
+ppcg_status ppcg_default_options(ppcg_options *opt);
+
+/* Create a solver handle for matrix A (Section V-A: CSR input, Jacobi
+ * preconditioner).  Validates A on the device, builds dinv = 1 / diag(A),
+ * converts A to the SpMV format (autotuned when spmv_format is AUTO), keeps
+ * an FP32 copy of the values when opt->precision is PPCG_MIXED_FP32, and
+ * allocates the solver vectors.  hip_stream: a hipStream_t (NULL = default
+ * stream).  On success *out receives the handle; on error *out is set to NULL
+ * and nothing is leaked.  Errors: PPCG_ERR_INVALID_ARG (null pointers,
+ * struct_size mismatch, n < 1, nnz out of range, bad options),
+ * PPCG_ERR_BAD_CSR (see ppcg_csr), PPCG_ERR_NOMEM, PPCG_ERR_DEVICE. */
+ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_stream,
+                        ppcg_handle **out);
+
+/* Replace the handle's options (tolerance, limits, stop mode, precision...).
+ * Switching to PPCG_MIXED_FP32 builds the FP32 copy on first use. */
+ppcg_status ppcg_set_options(ppcg_handle *h, const ppcg_options *opt);
+
+/* Solve A x = b with Algorithm 2 (PIPECG).  b: [n] FP64, x0: [n] FP64 or NULL
+ * (NULL = zero initial guess; x0 may alias x), x: [n] FP64 output; all three
+ * in opt.vec_mem memory and owned by the caller.  info may be NULL.
+ * Returns the solve status (also in info->status).  PPCG_NOT_CONVERGED,
+ * PPCG_BREAKDOWN and PPCG_STAGNATED still write the last iterate to x and
+ * fill info.  Argument errors leave x untouched. */
+ppcg_status ppcg_solve(ppcg_handle *h, const double *b, const double *x0, double *x, ppcg_info *info);
+
+/* Solve count independent systems in one batched launch sequence: every
+ * PIPECG iteration of all unconverged systems runs as one fused-update launch
+ * and one SpMV launch over a table of (system, row tile) work items, captured
+ * in HIP graphs; converged systems leave the table between graph launches.
+ * hs: [count] distinct handles (same device and stream as hs[0]); b, x0, x:
+ * [count] arrays of per-system pointers as in ppcg_solve (x0[i] or x0 itself
+ * may be NULL).  infos: [count] or NULL.  Returns PPCG_OK when the batch ran;
+ * per-system outcomes are in infos[i].status.  Each system's result is
+ * bitwise identical to solving it alone with ppcg_solve. */
+ppcg_status ppcg_solve_batch(int32_t count, ppcg_handle *const *hs, const double *const *b,
+                             const double *const *x0, double *const *x, ppcg_info *infos);
+
+/* y = A x with the handle's SpMV kernel (Algorithm 2's SpMV step, A in the
+ * stored format chosen at creation).  x, y: [n] FP64 in opt.vec_mem memory,
+ * caller-owned, must not alias.  Each row is summed in the CSR column order
+ * (SELL format) or by a fixed lane-strided tree (CSR-vector format). */
+ppcg_status ppcg_spmv(ppcg_handle *h, const double *x, double *y);
+
+/* Describe the stored matrix and the algorithmic byte model. */
+ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi);
+
+/* Device bytes a handle for an n x n matrix with nnz entries would hold
+ * (matrix in its SpMV format with padding estimate, dinv, the eleven solver
+ * vectors, b, partials and state; plus the FP32 copy when mixed).  Used for
+ * admission by footprint.  Returns 0 for invalid sizes. */
+double ppcg_footprint_bytes(int32_t n, int64_t nnz, ppcg_precision precision);
+
+/* Measure the two kernels of the iteration (Algorithm 2's fused vector
+ * updates + preconditioner + dot products, and its SpMV) over `iters`
+ * iterations on the handle's stream, each launch bracketed by HIP events.
+ * Runs the initialisation first, so the vectors hold a real iterate.
+ * ms_vma, ms_spmv: average launch duration in milliseconds (host pointers). */
+ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, double *ms_vma,
+                              double *ms_spmv);
+
+/* Release the handle and all its device memory.  NULL-safe.  Must not be
+ * called while a solve using the handle is in flight. */
+ppcg_status ppcg_destroy(ppcg_handle *h);
+
+/* Static string naming a status. */
+const char *ppcg_status_str(ppcg_status s);
+
+/* Detail message of the last failing call on this thread ("" if none). */
+const char *ppcg_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a continuous-batching solve server.  Requests are admitted while
+ * the sum of their device footprints (ppcg_footprint_bytes) stays within the
+ * budget; admitted requests join the batched iteration at the next graph
+ * boundary and leave it when they finish, so requests that arrive while
+ * others run overlap with them on the device.  Each request's arithmetic is
+ * independent of the others in the mix: its result is bitwise identical to
+ * a solo ppcg_solve of the same request with the same options.
+ * ------------------------------------------------------------------------- */
+typedef struct ppcg_server ppcg_server;
+
+/* Create a server on hip_stream with a device-memory budget in bytes
+ * (0 = 80% of the free device memory).  opt supplies defaults for requests. */
+ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *hip_stream,
+                            ppcg_server **out);
+
+/* Queue a request.  A: host CSR (copied before returning); b: host [n] FP64,
+ * copied; tol: this request's tolerance; precision: PPCG_FP64 or
+ * PPCG_MIXED_FP32.  *req_id receives the request's id.  PPCG_ERR_BUDGET when
+ * the request could never fit the budget. */
+ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, double tol,
+                            ppcg_precision precision, int64_t *req_id);
+
+/* Advance the server: admit queued requests that fit, run one graph chunk of
+ * iterations over every active request, retire finished ones.  *active and
+ * *queued (may be NULL) receive the counts after the step. */
+ppcg_status ppcg_srv_step(ppcg_server *s, int32_t *active, int32_t *queued);
+
+/* Fetch a finished request.  Returns PPCG_NOT_CONVERGED with *ready = 0 when
+ * it is still queued or running.  When *ready = 1, x (host [n], may be NULL)
+ * receives the solution, info (may be NULL) the report, and the request's
+ * memory is released. */
+ppcg_status ppcg_srv_poll(ppcg_server *s, int64_t req_id, int32_t *ready, double *x, ppcg_info *info);
+
+/* Destroy the server, dropping unfinished requests.  NULL-safe. */
+ppcg_status ppcg_srv_destroy(ppcg_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPCG_H */

@@ -1,0 +1,201 @@
+// ppcg_engine.hpp -- host runtime of the PIPECG library: handles, the
+// batched iteration engine and the error channel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/ppcg.h"
+#include "ppcg_internal.hpp"
+
+namespace ppcg {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define PPCG_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::ppcg::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                              __FILE__, __LINE__);                                        \
+            return e_ == hipErrorOutOfMemory ? PPCG_ERR_NOMEM : PPCG_ERR_DEVICE;          \
+        }                                                                                 \
+    } while (0)
+
+#define PPCG_TRY(expr)                        \
+    do {                                      \
+        ppcg_status s_ = (expr);              \
+        if (s_ < 0)                           \
+            return s_;                        \
+    } while (0)
+
+// ---------------------------------------------------------------- device buffers
+// A single device allocation cut into 256-byte aligned pieces.
+struct DevArena {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+    ppcg_status alloc(size_t bytes);
+    void *take(size_t bytes);
+    void release();
+};
+
+// Matrix + vectors of one precision for one handle.
+struct PrecData {
+    bool ready = false;
+    int prec = PREC_F64;
+    void *val = nullptr;   // SELL or CSR values in this precision
+    void *dinv = nullptr;
+    void *vec[11] = {};    // x r u w m nv z q s p b
+    DevArena arena;
+};
+
+enum VecIdx { VX = 0, VR, VU, VW, VM, VN, VZ, VQ, VS, VP, VB };
+
+class Engine;
+
+}  // namespace ppcg
+
+struct ppcg_handle {
+    int device = 0;
+    hipStream_t user_stream = nullptr;
+    hipStream_t stream = nullptr;  // internal stream (capturable), ordered after user_stream
+    ppcg_options opt{};
+    int n = 0;
+    int64_t nnz = 0;
+    int ntiles = 0;
+    // matrix storage (format independent pieces)
+    int fmt = ppcg::FMT_SELL;
+    int lanes = 0;
+    int sigma = 1;
+    int nchunks = 0;
+    int64_t nnz_stored = 0;
+    int64_t *cptr = nullptr;  // SELL chunk offsets
+    int *rp = nullptr;        // CSR row pointers (CSR-vector format)
+    int *col = nullptr;
+    int *perm = nullptr, *invperm = nullptr;
+    double *val64 = nullptr;  // FP64 values in the stored format
+    double *dinv64 = nullptr;
+    ppcg::DevArena mat_arena;
+    ppcg::PrecData f64, f32;
+    double *part = nullptr;   // 2 x ntiles x 4 partial sums (shared by both precisions)
+    double *part32 = nullptr; // partials of the FP32 inner solve
+    double setup_ms = 0.0;
+    ppcg::Engine *solo = nullptr;  // cached single-system engine
+    // Single-system launch description for direct kernel calls (SpMV,
+    // kernel timing, autotuning): descriptor, state, table of all tiles.
+    ppcg::SysDesc *plain_desc = nullptr;
+    ppcg::SysState *plain_st = nullptr;
+    ppcg::WorkItem *plain_tab = nullptr;
+    int *plain_cnt = nullptr;
+};
+
+namespace ppcg {
+
+// One solve in progress inside an engine.
+struct Job {
+    ppcg_handle *h = nullptr;
+    int mixed = 0;          // 1: FP32 inner PIPECG + FP64 refinement
+    int slot64 = -1;        // slot in the FP64 group (always)
+    int slot32 = -1;        // slot in the FP32 group (mixed only)
+    int stage = 0;          // JobStage
+    int restarts = 0;
+    int outer = 0;
+    int inner_iters = 0;
+    int status = PPCG_OK;
+    double tol = 0.0;
+    bool finished = false;
+    double t_start = 0.0, t_end = 0.0;
+    double rel_true = 0.0, rel_recur = 0.0, precond_norm = 0.0;
+    double bnorm2 = 0.0;
+    int iters = 0;
+};
+
+enum JobStage {
+    JS_NEED_INIT = 0,   // FP64: run the initialisation, then iterate
+    JS_ITER = 1,        // iterating in the group's table
+    JS_NEED_FINAL = 2,  // FP64: true residual, then restart or finish
+    JS_OUTER = 3,       // mixed: true residual of x, then finish or start an inner solve
+    JS_DONE = 4
+};
+
+// Per-precision set of system slots, work table and captured graph.
+struct Group {
+    int prec = PREC_F64;
+    int cap_sys = 0;
+    SysDesc *desc_d = nullptr;
+    SysState *st_d = nullptr;
+    SysState *st_h = nullptr;       // pinned mirror
+    std::vector<SysDesc> desc_h;
+    std::vector<char> slot_used;
+    WorkItem *table_d = nullptr;
+    int *count_d = nullptr;
+    int table_cap = 0;
+    WorkItem *aux_d = nullptr;
+    int *aux_count_d = nullptr;
+    int aux_cap = 0;
+    WorkItem *stage_h = nullptr;    // pinned staging for table uploads
+    int *stage_cnt_h = nullptr;
+    int stage_cap = 0;
+    std::vector<WorkItem> table_h;  // current iteration table
+    bool table_dirty = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_grid = 0, g_iters = 0;
+};
+
+class Engine {
+  public:
+    explicit Engine(hipStream_t stream) : stream_(stream) {}
+    ~Engine();
+    ppcg_status init(int cap_sys);
+    // Add a job; returns its index.
+    ppcg_status add(ppcg_handle *h, int mixed, double tol, const double *b_dev_internal, int *job_id);
+    // Advance all jobs by one scheduling step (transitions + one graph chunk).
+    ppcg_status step(int graph_iters);
+    bool all_done() const;
+    int active() const;
+    Job &job(int i) { return jobs_[i]; }
+    int njobs() const { return (int)jobs_.size(); }
+    // Release a job's slots (serving); the job entry stays for its results.
+    void retire(int job_id);
+    // Release every job and forget them.
+    void reset();
+    hipStream_t stream() const { return stream_; }
+    int remap = 1;
+
+  private:
+    ppcg_status ensure_group(Group &g, int prec, int cap_sys);
+    ppcg_status upload_desc(Group &g, int slot);
+    ppcg_status aux_launch(Group &g, const std::vector<int> &slots, int what);
+    ppcg_status ensure_table(Group &g);
+    ppcg_status ensure_graph(Group &g, int iters);
+    ppcg_status sync_states(Group &g);
+    int alloc_slot(Group &g);
+    hipStream_t stream_;
+    Group g64_, g32_;
+    std::vector<Job> jobs_;
+};
+
+// Aux operations run over a subset of slots.
+enum AuxOp { AUX_INIT = 0, AUX_RESID = 1, AUX_MIX_START = 2, AUX_MIX_CORRECT = 3 };
+
+double now_ms();
+int auto_graph_iters(const ppcg_handle *h);
+// Helpers shared by the solver API and the server.
+ppcg_status stage_inputs(ppcg_handle *h, const double *b, const double *x0);
+ppcg_status unstage_x(ppcg_handle *h, double *x);
+void fill_info(const ppcg_handle *h, const Job &j, ppcg_info *info);
+ppcg_status wait_user(ppcg_handle *h);
+ppcg_status run_engine(Engine &E, int graph_iters);
+ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double tol, int fixed, int maxit,
+                      int stop);
+ppcg_status ensure_f32(ppcg_handle *h);
+
+}  // namespace ppcg

@@ -1,0 +1,85 @@
+// ppcg_internal.hpp -- data structures shared by the HIP kernels and the host
+// runtime of the PIPECG library.
+//
+// Work decomposition.  Every system (one handle) is cut into tiles of
+// kTileRows consecutive rows.  A launch processes a table of work items
+// (system slot, tile index); one workgroup handles one work item.  A single
+// solve is a table over one system, a batched solve a table over many, and
+// the arithmetic a system sees does not depend on what else is in the table:
+// its tiles, their per-tile partial sums and the fixed-order reduction of
+// those partials are the same alone and in a mix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppcg {
+
+constexpr int kTileRows = 512;     // rows per work item (both kernels)
+constexpr int kVmaThreads = 256;   // fused update kernel: 2 rows per thread
+constexpr int kSpmvThreads = 512;  // SpMV kernel: 8 wavefronts
+constexpr int kSellC = 64;         // SELL chunk height = wavefront width
+constexpr int kSellChunksPerTile = kTileRows / kSellC;
+constexpr int kSortWindow = 1024;  // SELL sigma when sorting is used
+constexpr int kNumPartials = 4;    // (r,u), (w,u), (u,u), (r,r)
+
+enum Fmt : int { FMT_SELL = 1, FMT_CSRV = 2 };
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1 };
+
+// Status codes mirrored from ppcg.h (device code does not include it).
+enum DevStatus : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_STAGNATED = 3 };
+enum StopMode : int { STOP_REL = 0, STOP_ABS = 1 };
+
+// Per-system iteration state.  Lives in device memory, written only by the
+// designated workgroup of the SpMV launch (or by the start kernel), read by
+// every workgroup; mirrored to pinned host memory for polling.
+struct alignas(128) SysState {
+    double gamma;       // (r_i, u_i)
+    double delta;       // (w_i, u_i)
+    double uu;          // (u_i, u_i)
+    double rr;          // (r_i, r_i)
+    double alpha;       // alpha_i used by the next fused update
+    double beta;        // beta_i used by the next fused update
+    double gamma_prev;  // gamma_{i-1}
+    double alpha_prev;  // alpha_{i-1}
+    double bnorm2;      // (b, b)
+    double tnorm2;      // (b - A x, b - A x) from the last true-residual pass
+    int iter;           // x-updates so far (all starts)
+    int i_start;        // x-updates in the current start
+    int done;           // 1: stop iterating
+    int status;         // DevStatus when done
+    int phase;          // 1: the next reduction is the one that ends initialisation
+    int gen;            // incremented by every reduction (debug / polling aid)
+    int pad[2];
+};
+
+// Per-system descriptor (device-resident copy per engine slot).
+struct SysDesc {
+    int n;
+    int ntiles;
+    int fmt;            // Fmt
+    int lanes;          // CSR-vector lanes per row
+    int stop;           // StopMode
+    int maxit;
+    int fixed;          // > 0: fixed number of iterations
+    int prec;           // Prec of the vectors and values below
+    int pair;           // mixed precision: slot of the same system in the other group
+    int pad_;
+    double tol;
+    const int64_t *cptr;  // SELL chunk offsets [nchunks + 1]
+    const int *rp;        // CSR row pointers [n + 1] (CSR-vector format)
+    const int *col;       // SELL / CSR column indices
+    const void *val;      // matrix values (double or float)
+    const void *dinv;     // inverse diagonal (double or float)
+    void *x, *r, *u, *w, *m, *nv, *z, *q, *s, *p;  // solver vectors
+    const void *b;        // right-hand side (internal copy)
+    double *part;         // partial sums: 2 slots x ntiles x 4
+    SysState *st;
+};
+
+struct WorkItem {
+    int slot;  // index into the engine's SysDesc array
+    int tile;  // tile index within that system
+};
+
+}  // namespace ppcg

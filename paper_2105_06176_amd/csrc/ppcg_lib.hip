@@ -1,0 +1,1581 @@
+// ppcg_lib.hip -- the PIPECG library: matrix setup, the iteration engine and
+// the C ABI declared in include/ppcg.h.
+//
+// Method: Algorithm 2 (PIPECG) of Tiwari & Vadhiyar (Section III-B) with the
+// Jacobi preconditioner (Section V-A), solving a sparse SPD system given in
+// CSR.  See ppcg_kernels.hpp for the kernels of one iteration.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "ppcg_engine.hpp"
+#include "ppcg_kernels.hpp"
+#include "ppcg_setup.hpp"
+
+namespace ppcg {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+void clear_error() { g_err.clear(); }
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+static inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------- arena
+ppcg_status DevArena::alloc(size_t bytes)
+{
+    release();
+    if (bytes == 0)
+        bytes = 256;
+    hipError_t e = hipMalloc((void **)&base, bytes);
+    if (e != hipSuccess) {
+        base = nullptr;
+        set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? PPCG_ERR_NOMEM : PPCG_ERR_DEVICE;
+    }
+    size = bytes;
+    used = 0;
+    return PPCG_OK;
+}
+
+void *DevArena::take(size_t bytes)
+{
+    const size_t a = (used + 255) & ~(size_t)255;
+    if (a + bytes > size)
+        return nullptr;
+    used = a + bytes;
+    return base + a;
+}
+
+void DevArena::release()
+{
+    if (base)
+        (void)hipFree(base);
+    base = nullptr;
+    size = used = 0;
+}
+
+static size_t aligned(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Check that [p, p + bytes) lies inside one device allocation of the current
+// device, so that no kernel can fault on a wrong pointer or short buffer.
+static ppcg_status check_dev_range(const void *p, size_t bytes, const char *what)
+{
+    if (!p) {
+        set_error("%s is NULL", what);
+        return PPCG_ERR_INVALID_ARG;
+    }
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess || (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)) {
+        (void)hipGetLastError();
+        set_error("%s is not a device pointer", what);
+        return PPCG_ERR_INVALID_ARG;
+    }
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e == hipSuccess && base) {
+        const char *b = (const char *)base, *q = (const char *)p;
+        if (q + bytes > b + size) {
+            set_error("%s: buffer of %zu bytes at offset %zu is shorter than the %zu bytes needed", what,
+                      size, (size_t)(q - b), bytes);
+            return PPCG_ERR_INVALID_ARG;
+        }
+    } else {
+        (void)hipGetLastError();
+    }
+    return PPCG_OK;
+}
+
+// ---------------------------------------------------------------- byte model
+// Algorithmic HBM bytes of one iteration: the fused update reads 11 vectors
+// and writes 9; the SpMV reads values and column indices of every stored
+// entry, its row/chunk pointers, the input vector once, and writes one vector.
+struct ByteModel {
+    double vma, spmv;
+};
+
+static ByteModel byte_model(const ppcg_handle *h, int prec)
+{
+    const double ve = prec == PREC_F64 ? 8.0 : 4.0;
+    const double n = h->n;
+    ByteModel bm;
+    bm.vma = 20.0 * ve * n;
+    const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
+    bm.spmv = (ve + 4.0) * (double)h->nnz + ptr + 2.0 * ve * n;
+    return bm;
+}
+
+// ---------------------------------------------------------------- SELL build
+struct SellBuild {
+    int sigma = 1;
+    int nchunks = 0;
+    int64_t stored = 0;
+    int64_t *cptr = nullptr;
+    int *col = nullptr;
+    double *val = nullptr;
+    int *perm = nullptr, *invperm = nullptr;
+    void free_all()
+    {
+        if (cptr) (void)hipFree(cptr);
+        if (col) (void)hipFree(col);
+        if (val) (void)hipFree(val);
+        if (perm) (void)hipFree(perm);
+        if (invperm) (void)hipFree(invperm);
+        *this = SellBuild();
+    }
+};
+
+#define PPCG_HIP_CLEAN(call, cleanup)                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            ::ppcg::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),       \
+                              __FILE__, __LINE__);                                         \
+            cleanup;                                                                       \
+            return e_ == hipErrorOutOfMemory ? PPCG_ERR_NOMEM : PPCG_ERR_DEVICE;           \
+        }                                                                                  \
+    } while (0)
+
+// Chunk-size pass only: stored entries for a given sigma (for the autotuner).
+static ppcg_status sell_size(hipStream_t s, int n, int sigma, const int *rowlen, int64_t *stored)
+{
+    const int nchunks = (n + kSellC - 1) / kSellC;
+    int *perm = nullptr;
+    int64_t *sz = nullptr, *cp = nullptr;
+    auto clean = [&]() {
+        if (perm) (void)hipFree(perm);
+        if (sz) (void)hipFree(sz);
+        if (cp) (void)hipFree(cp);
+    };
+    PPCG_HIP_CLEAN(hipMalloc(&sz, sizeof(int64_t) * nchunks), clean());
+    PPCG_HIP_CLEAN(hipMalloc(&cp, sizeof(int64_t) * (nchunks + 1)), clean());
+    if (sigma > 1) {
+        PPCG_HIP_CLEAN(hipMalloc(&perm, sizeof(int) * n), clean());
+        k_sort_window<<<blocks_for(n, kSortWindow), kSortWindow / 2, 0, s>>>(n, rowlen, perm);
+    }
+    k_chunk_size<<<blocks_for(nchunks, 256), 256, 0, s>>>(n, nchunks, perm, rowlen, sz);
+    k_scan<<<1, 1024, 0, s>>>(nchunks, sz, cp);
+    PPCG_HIP_CLEAN(hipMemcpyAsync(stored, cp + nchunks, sizeof(int64_t), hipMemcpyDeviceToHost, s), clean());
+    PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());
+    clean();
+    return PPCG_OK;
+}
+
+static ppcg_status build_sell(hipStream_t s, int n, int sigma, const int *rp, const int *ci, const double *val,
+                              const int *rowlen, SellBuild *out)
+{
+    SellBuild sb;
+    sb.sigma = sigma;
+    sb.nchunks = (n + kSellC - 1) / kSellC;
+    int64_t *sz = nullptr;
+    auto clean = [&]() {
+        if (sz) (void)hipFree(sz);
+        sb.free_all();
+    };
+    PPCG_HIP_CLEAN(hipMalloc(&sz, sizeof(int64_t) * sb.nchunks), clean());
+    PPCG_HIP_CLEAN(hipMalloc(&sb.cptr, sizeof(int64_t) * (sb.nchunks + 1)), clean());
+    if (sigma > 1) {
+        PPCG_HIP_CLEAN(hipMalloc(&sb.perm, sizeof(int) * n), clean());
+        PPCG_HIP_CLEAN(hipMalloc(&sb.invperm, sizeof(int) * n), clean());
+        k_sort_window<<<blocks_for(n, kSortWindow), kSortWindow / 2, 0, s>>>(n, rowlen, sb.perm);
+        k_invert_perm<<<blocks_for(n, 256), 256, 0, s>>>(n, sb.perm, sb.invperm);
+    }
+    k_chunk_size<<<blocks_for(sb.nchunks, 256), 256, 0, s>>>(n, sb.nchunks, sb.perm, rowlen, sz);
+    k_scan<<<1, 1024, 0, s>>>(sb.nchunks, sz, sb.cptr);
+    PPCG_HIP_CLEAN(hipMemcpyAsync(&sb.stored, sb.cptr + sb.nchunks, sizeof(int64_t), hipMemcpyDeviceToHost, s),
+                   clean());
+    PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());
+    PPCG_HIP_CLEAN(hipMalloc(&sb.col, sizeof(int) * std::max<int64_t>(sb.stored, 1)), clean());
+    PPCG_HIP_CLEAN(hipMalloc(&sb.val, sizeof(double) * std::max<int64_t>(sb.stored, 1)), clean());
+    k_sell_fill<<<blocks_for((size_t)sb.nchunks * kSellC, 256), 256, 0, s>>>(
+        n, sb.nchunks, rp, ci, val, sb.perm, sb.invperm, sb.cptr, sb.col, sb.val);
+    PPCG_HIP_CLEAN(hipGetLastError(), clean());
+    (void)hipFree(sz);
+    sz = nullptr;
+    *out = sb;
+    return PPCG_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Candidate SpMV configurations are timed on the matrix itself: five timed
+// SpMV executions each (after one warm-up), the same count the paper's
+// performance model uses to measure SpMV speed (Section IV-C).  Choices are
+// cached per coarse matrix signature.
+struct TuneKey {
+    int logn, mean, cv10, maxlen_log;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(logn, mean, cv10, maxlen_log) < std::tie(o.logn, o.mean, o.cv10, o.maxlen_log);
+    }
+};
+struct TuneVal {
+    int fmt, sigma, lanes;
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tune_cache;
+
+ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double tol, int fixed, int maxit,
+                      int stop)
+{
+    PrecData &pd = prec == PREC_F64 ? h->f64 : h->f32;
+    if (!pd.ready) {
+        set_error("precision data not prepared");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    memset(d, 0, sizeof *d);
+    d->n = h->n;
+    d->ntiles = h->ntiles;
+    d->fmt = h->fmt;
+    d->lanes = h->lanes;
+    d->stop = stop;
+    d->maxit = maxit;
+    d->fixed = fixed;
+    d->prec = prec;
+    d->pair = -1;
+    d->tol = tol;
+    d->cptr = h->cptr;
+    d->rp = h->rp;
+    d->col = h->col;
+    d->val = pd.val;
+    d->dinv = pd.dinv;
+    d->x = pd.vec[VX];
+    d->r = pd.vec[VR];
+    d->u = pd.vec[VU];
+    d->w = pd.vec[VW];
+    d->m = pd.vec[VM];
+    d->nv = pd.vec[VN];
+    d->z = pd.vec[VZ];
+    d->q = pd.vec[VQ];
+    d->s = pd.vec[VS];
+    d->p = pd.vec[VP];
+    d->b = pd.vec[VB];
+    d->part = prec == PREC_F64 ? h->part : h->part32;
+    d->st = st;
+    return PPCG_OK;
+}
+
+// Upload a single-system descriptor (all tiles) for direct kernel launches.
+static ppcg_status plain_setup(ppcg_handle *h, double tol, int fixed, int maxit)
+{
+    hipStream_t s = h->stream;
+    if (!h->plain_desc) {
+        PPCG_HIP(hipMalloc(&h->plain_desc, sizeof(SysDesc)));
+        PPCG_HIP(hipMalloc(&h->plain_st, sizeof(SysState)));
+        PPCG_HIP(hipMalloc(&h->plain_tab, sizeof(WorkItem) * h->ntiles));
+        PPCG_HIP(hipMalloc(&h->plain_cnt, sizeof(int)));
+        std::vector<WorkItem> th(h->ntiles);
+        for (int t = 0; t < h->ntiles; ++t)
+            th[t] = {0, t};
+        const int count = h->ntiles;
+        PPCG_HIP(hipMemcpyAsync(h->plain_tab, th.data(), sizeof(WorkItem) * count, hipMemcpyHostToDevice, s));
+        PPCG_HIP(hipMemcpyAsync(h->plain_cnt, &count, sizeof(int), hipMemcpyHostToDevice, s));
+        PPCG_HIP(hipStreamSynchronize(s));  // host sources are about to go out of scope
+    }
+    SysDesc dh;
+    PPCG_TRY(fill_desc(h, PREC_F64, h->plain_st, &dh, tol, fixed, maxit, STOP_REL));
+    PPCG_HIP(hipMemcpyAsync(h->plain_desc, &dh, sizeof dh, hipMemcpyHostToDevice, s));
+    PPCG_HIP(hipMemsetAsync(h->plain_st, 0, sizeof(SysState), s));
+    PPCG_HIP(hipStreamSynchronize(s));
+    return PPCG_OK;
+}
+
+static void plain_free(ppcg_handle *h)
+{
+    if (h->plain_desc) (void)hipFree(h->plain_desc);
+    if (h->plain_st) (void)hipFree(h->plain_st);
+    if (h->plain_tab) (void)hipFree(h->plain_tab);
+    if (h->plain_cnt) (void)hipFree(h->plain_cnt);
+    h->plain_desc = nullptr;
+    h->plain_st = nullptr;
+    h->plain_tab = nullptr;
+    h->plain_cnt = nullptr;
+}
+
+// Time `reps` SpMV launches of the handle's current format (MODE_PLAIN).
+static ppcg_status time_spmv(ppcg_handle *h, int reps, double *ms)
+{
+    hipStream_t s = h->stream;
+    PPCG_TRY(plain_setup(h, 1e-8, 0, 1));
+    k_fill<double><<<blocks_for(h->n, 256), 256, 0, s>>>((size_t)h->n, (double *)h->f64.vec[VX], 1.0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto clean = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    PPCG_HIP_CLEAN(hipEventCreate(&e0), clean());
+    PPCG_HIP_CLEAN(hipEventCreate(&e1), clean());
+    k_spmv<double, MODE_PLAIN><<<h->ntiles, kSpmvThreads, 0, s>>>(h->plain_tab, h->plain_cnt, h->plain_desc, 1);
+    PPCG_HIP_CLEAN(hipEventRecord(e0, s), clean());
+    for (int i = 0; i < reps; ++i)
+        k_spmv<double, MODE_PLAIN><<<h->ntiles, kSpmvThreads, 0, s>>>(h->plain_tab, h->plain_cnt, h->plain_desc,
+                                                                      1);
+    PPCG_HIP_CLEAN(hipEventRecord(e1, s), clean());
+    PPCG_HIP_CLEAN(hipEventSynchronize(e1), clean());
+    float f = 0.f;
+    PPCG_HIP_CLEAN(hipEventElapsedTime(&f, e0, e1), clean());
+    *ms = f / reps;
+    clean();
+    return PPCG_OK;
+}
+
+static void free_matrix(ppcg_handle *h)
+{
+    if (h->cptr) (void)hipFree(h->cptr);
+    if (h->rp) (void)hipFree(h->rp);
+    if (h->col) (void)hipFree(h->col);
+    if (h->val64) (void)hipFree(h->val64);
+    if (h->perm) (void)hipFree(h->perm);
+    if (h->invperm) (void)hipFree(h->invperm);
+    h->cptr = nullptr;
+    h->rp = h->col = h->perm = h->invperm = nullptr;
+    h->val64 = nullptr;
+}
+
+static void adopt_sell(ppcg_handle *h, SellBuild &sb)
+{
+    free_matrix(h);
+    h->fmt = FMT_SELL;
+    h->sigma = sb.sigma;
+    h->lanes = 0;
+    h->nchunks = sb.nchunks;
+    h->nnz_stored = sb.stored;
+    h->cptr = sb.cptr;
+    h->col = sb.col;
+    h->val64 = sb.val;
+    h->perm = sb.perm;
+    h->invperm = sb.invperm;
+    sb = SellBuild();
+}
+
+static ppcg_status adopt_csrv(ppcg_handle *h, int lanes, const int *rp, const int *ci, const double *val)
+{
+    free_matrix(h);
+    h->fmt = FMT_CSRV;
+    h->sigma = 1;
+    h->lanes = lanes;
+    h->nchunks = 0;
+    h->nnz_stored = h->nnz;
+    PPCG_HIP(hipMalloc(&h->rp, sizeof(int) * (h->n + 1)));
+    PPCG_HIP(hipMalloc(&h->col, sizeof(int) * std::max<int64_t>(h->nnz, 1)));
+    PPCG_HIP(hipMalloc(&h->val64, sizeof(double) * std::max<int64_t>(h->nnz, 1)));
+    PPCG_HIP(hipMemcpyAsync(h->rp, rp, sizeof(int) * (h->n + 1), hipMemcpyDeviceToDevice, h->stream));
+    PPCG_HIP(hipMemcpyAsync(h->col, ci, sizeof(int) * h->nnz, hipMemcpyDeviceToDevice, h->stream));
+    PPCG_HIP(hipMemcpyAsync(h->val64, val, sizeof(double) * h->nnz, hipMemcpyDeviceToDevice, h->stream));
+    return PPCG_OK;
+}
+
+// Point the FP64 precision data at the current matrix storage (dinv in
+// stored-row order).
+static ppcg_status bind_f64(ppcg_handle *h, const double *dinv_orig)
+{
+    PrecData &pd = h->f64;
+    pd.prec = PREC_F64;
+    pd.val = h->val64;
+    k_permute_d<<<blocks_for(h->n, 256), 256, 0, h->stream>>>(h->n, h->perm, dinv_orig, h->dinv64);
+    PPCG_HIP(hipGetLastError());
+    pd.dinv = h->dinv64;
+    pd.ready = true;
+    return PPCG_OK;
+}
+
+static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, const double *val, const int *rowlen,
+                                 const double *dinv_orig, const std::vector<int> &rowlen_h)
+{
+    const ppcg_spmv_format want = h->opt.spmv_format;
+    // Row-length statistics.
+    double sum = 0, sum2 = 0;
+    int mx = 0;
+    for (int v : rowlen_h) {
+        sum += v;
+        sum2 += (double)v * v;
+        mx = std::max(mx, v);
+    }
+    const double mean = sum / h->n;
+    const double var = std::max(0.0, sum2 / h->n - mean * mean);
+    const double cv = mean > 0 ? std::sqrt(var) / mean : 0.0;
+    auto pow2_near = [](double v) {
+        int l = 2;
+        while (l < 64 && l < v)
+            l <<= 1;
+        return l;
+    };
+    if (want == PPCG_SPMV_SELL) {
+        int64_t st1 = 0;
+        PPCG_TRY(sell_size(h->stream, h->n, 1, rowlen, &st1));
+        const int sigma = (double)st1 > 1.05 * (double)h->nnz ? kSortWindow : 1;
+        SellBuild sb;
+        PPCG_TRY(build_sell(h->stream, h->n, sigma, rp, ci, val, rowlen, &sb));
+        adopt_sell(h, sb);
+        return bind_f64(h, dinv_orig);
+    }
+    if (want == PPCG_SPMV_CSR_VECTOR) {
+        const int lanes = h->opt.flags ? 0 : pow2_near(mean / 2);
+        PPCG_TRY(adopt_csrv(h, lanes ? lanes : 8, rp, ci, val));
+        return bind_f64(h, dinv_orig);
+    }
+    TuneKey key{(int)std::log2((double)h->n), (int)std::lround(mean), (int)std::lround(10 * cv),
+                (int)std::log2((double)std::max(mx, 1))};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const TuneVal tv = it->second;
+            if (tv.fmt == FMT_SELL) {
+                SellBuild sb;
+                PPCG_TRY(build_sell(h->stream, h->n, tv.sigma, rp, ci, val, rowlen, &sb));
+                adopt_sell(h, sb);
+            } else {
+                PPCG_TRY(adopt_csrv(h, tv.lanes, rp, ci, val));
+            }
+            return bind_f64(h, dinv_orig);
+        }
+    }
+    struct Cand {
+        int fmt, sigma, lanes;
+    };
+    std::vector<Cand> cands;
+    int64_t st1 = 0;
+    PPCG_TRY(sell_size(h->stream, h->n, 1, rowlen, &st1));
+    cands.push_back({FMT_SELL, 1, 0});
+    if ((double)st1 > 1.05 * (double)h->nnz)
+        cands.push_back({FMT_SELL, kSortWindow, 0});
+    if (mean >= 12.0) {
+        const int l = pow2_near(mean / 4);
+        for (int lanes : {l / 2, l, l * 2})
+            if (lanes >= 2 && lanes <= 64)
+                cands.push_back({FMT_CSRV, 1, lanes});
+    }
+    double best = 1e300;
+    Cand bestc = cands[0];
+    for (const Cand &c : cands) {
+        if (c.fmt == FMT_SELL) {
+            SellBuild sb;
+            PPCG_TRY(build_sell(h->stream, h->n, c.sigma, rp, ci, val, rowlen, &sb));
+            adopt_sell(h, sb);
+        } else {
+            PPCG_TRY(adopt_csrv(h, c.lanes, rp, ci, val));
+        }
+        PPCG_TRY(bind_f64(h, dinv_orig));
+        double ms = 0;
+        PPCG_TRY(time_spmv(h, 5, &ms));
+        if (ms < best) {
+            best = ms;
+            bestc = c;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {bestc.fmt, bestc.sigma, bestc.lanes};
+    }
+    const Cand &last = cands.back();
+    if (!(last.fmt == bestc.fmt && last.sigma == bestc.sigma && last.lanes == bestc.lanes)) {
+        if (bestc.fmt == FMT_SELL) {
+            SellBuild sb;
+            PPCG_TRY(build_sell(h->stream, h->n, bestc.sigma, rp, ci, val, rowlen, &sb));
+            adopt_sell(h, sb);
+        } else {
+            PPCG_TRY(adopt_csrv(h, bestc.lanes, rp, ci, val));
+        }
+    }
+    return bind_f64(h, dinv_orig);
+}
+
+// Allocate the FP64 solver vectors and partial sums.
+static ppcg_status alloc_f64_vectors(ppcg_handle *h)
+{
+    const size_t n = (size_t)h->n;
+    const size_t vb = aligned(n * sizeof(double));
+    const size_t pb = aligned((size_t)2 * h->ntiles * kNumPartials * sizeof(double));
+    PPCG_TRY(h->f64.arena.alloc(11 * vb + pb + 2 * 256));
+    for (int k = 0; k < 11; ++k)
+        h->f64.vec[k] = h->f64.arena.take(n * sizeof(double));
+    h->part = (double *)h->f64.arena.take((size_t)2 * h->ntiles * kNumPartials * sizeof(double));
+    return PPCG_OK;
+}
+
+// FP32 copies for the mixed-precision inner solve.
+ppcg_status ensure_f32(ppcg_handle *h)
+{
+    if (h->f32.ready)
+        return PPCG_OK;
+    const size_t n = (size_t)h->n;
+    const size_t vb = aligned(n * sizeof(float));
+    const size_t mb = aligned((size_t)std::max<int64_t>(h->nnz_stored, 1) * sizeof(float));
+    const size_t pb = aligned((size_t)2 * h->ntiles * kNumPartials * sizeof(double));
+    PrecData &pd = h->f32;
+    PPCG_TRY(pd.arena.alloc(12 * vb + mb + pb + 4 * 256));
+    pd.prec = PREC_F32;
+    pd.val = pd.arena.take((size_t)std::max<int64_t>(h->nnz_stored, 1) * sizeof(float));
+    pd.dinv = pd.arena.take(n * sizeof(float));
+    for (int k = 0; k < 11; ++k)
+        pd.vec[k] = pd.arena.take(n * sizeof(float));
+    h->part32 = (double *)pd.arena.take((size_t)2 * h->ntiles * kNumPartials * sizeof(double));
+    k_convert<float, double><<<blocks_for((size_t)h->nnz_stored, 256), 256, 0, h->stream>>>(
+        (size_t)h->nnz_stored, h->val64, (float *)pd.val);
+    k_convert<float, double><<<blocks_for(n, 256), 256, 0, h->stream>>>(n, h->dinv64, (float *)pd.dinv);
+    PPCG_HIP(hipGetLastError());
+    PPCG_HIP(hipStreamSynchronize(h->stream));
+    pd.ready = true;
+    return PPCG_OK;
+}
+
+// ---------------------------------------------------------------- engine
+Engine::~Engine()
+{
+    for (Group *g : {&g64_, &g32_}) {
+        if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->desc_d) (void)hipFree(g->desc_d);
+        if (g->st_d) (void)hipFree(g->st_d);
+        if (g->st_h) (void)hipHostFree(g->st_h);
+        if (g->table_d) (void)hipFree(g->table_d);
+        if (g->count_d) (void)hipFree(g->count_d);
+        if (g->aux_d) (void)hipFree(g->aux_d);
+        if (g->aux_count_d) (void)hipFree(g->aux_count_d);
+        if (g->stage_h) (void)hipHostFree(g->stage_h);
+        if (g->stage_cnt_h) (void)hipHostFree(g->stage_cnt_h);
+    }
+}
+
+ppcg_status Engine::ensure_group(Group &g, int prec, int cap_sys)
+{
+    g.prec = prec;
+    if (g.cap_sys >= cap_sys)
+        return PPCG_OK;
+    if (g.cap_sys > 0) {
+        set_error("engine capacity is fixed once initialised");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    g.cap_sys = cap_sys;
+    PPCG_HIP(hipMalloc(&g.desc_d, sizeof(SysDesc) * cap_sys));
+    PPCG_HIP(hipMalloc(&g.st_d, sizeof(SysState) * cap_sys));
+    PPCG_HIP(hipHostMalloc((void **)&g.st_h, sizeof(SysState) * cap_sys, hipHostMallocDefault));
+    PPCG_HIP(hipMalloc(&g.count_d, sizeof(int)));
+    PPCG_HIP(hipMalloc(&g.aux_count_d, sizeof(int)));
+    PPCG_HIP(hipHostMalloc((void **)&g.stage_cnt_h, sizeof(int) * 2, hipHostMallocDefault));
+    g.desc_h.assign(cap_sys, SysDesc{});
+    g.slot_used.assign(cap_sys, 0);
+    return PPCG_OK;
+}
+
+ppcg_status Engine::init(int cap_sys)
+{
+    PPCG_TRY(ensure_group(g64_, PREC_F64, cap_sys));
+    PPCG_TRY(ensure_group(g32_, PREC_F32, cap_sys));
+    return PPCG_OK;
+}
+
+int Engine::alloc_slot(Group &g)
+{
+    for (int i = 0; i < g.cap_sys; ++i)
+        if (!g.slot_used[i]) {
+            g.slot_used[i] = 1;
+            return i;
+        }
+    return -1;
+}
+
+ppcg_status Engine::upload_desc(Group &g, int slot)
+{
+    PPCG_HIP(hipMemcpyAsync(g.desc_d + slot, &g.desc_h[slot], sizeof(SysDesc), hipMemcpyHostToDevice, stream_));
+    return PPCG_OK;
+}
+
+static ppcg_status grow_table(WorkItem **d, int *cap, int need)
+{
+    if (*cap >= need)
+        return PPCG_OK;
+    int nc = std::max(need, *cap * 2);
+    nc = std::max(nc, 64);
+    if (*d)
+        (void)hipFree(*d);
+    *d = nullptr;
+    PPCG_HIP(hipMalloc(d, sizeof(WorkItem) * nc));
+    *cap = nc;
+    return PPCG_OK;
+}
+
+// Upload a work table through the pinned staging buffer.  The caller has
+// synchronised the stream since the staging buffer was last used.
+static ppcg_status upload_table(hipStream_t s, Group &g, const std::vector<WorkItem> &items, WorkItem *dst,
+                                int *cnt_d, int which)
+{
+    const int n = (int)items.size();
+    if (g.stage_cap < n + 1) {
+        if (g.stage_h)
+            (void)hipHostFree(g.stage_h);
+        g.stage_h = nullptr;
+        g.stage_cap = std::max(2 * n + 1, 256);
+        PPCG_HIP(hipHostMalloc((void **)&g.stage_h, sizeof(WorkItem) * g.stage_cap * 2, hipHostMallocDefault));
+    }
+    WorkItem *st = g.stage_h + (size_t)which * g.stage_cap;
+    if (n)
+        memcpy(st, items.data(), sizeof(WorkItem) * n);
+    g.stage_cnt_h[which] = n;
+    if (n)
+        PPCG_HIP(hipMemcpyAsync(dst, st, sizeof(WorkItem) * n, hipMemcpyHostToDevice, s));
+    PPCG_HIP(hipMemcpyAsync(cnt_d, &g.stage_cnt_h[which], sizeof(int), hipMemcpyHostToDevice, s));
+    return PPCG_OK;
+}
+
+template <typename T>
+static void launch_iter_pair(hipStream_t s, const Group &g, int grid, int remap)
+{
+    k_vma<T><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+    k_spmv<T, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+}
+
+ppcg_status Engine::ensure_table(Group &g)
+{
+    if (!g.table_dirty)
+        return PPCG_OK;
+    PPCG_HIP(hipStreamSynchronize(stream_));  // table_d / staging may still be in use
+    WorkItem *old = g.table_d;
+    PPCG_TRY(grow_table(&g.table_d, &g.table_cap, (int)g.table_h.size()));
+    if (old != g.table_d && g.gexec) {  // graph baked the old pointer
+        (void)hipGraphExecDestroy(g.gexec);
+        (void)hipGraphDestroy(g.graph);
+        g.gexec = nullptr;
+        g.graph = nullptr;
+        g.g_grid = 0;
+    }
+    PPCG_TRY(upload_table(stream_, g, g.table_h, g.table_d, g.count_d, 0));
+    g.table_dirty = false;
+    return PPCG_OK;
+}
+
+ppcg_status Engine::ensure_graph(Group &g, int iters)
+{
+    const int need = (int)g.table_h.size();
+    const bool ok = g.gexec && g.g_iters == iters && g.g_grid >= need && g.g_grid <= std::max(need * 4, 64);
+    if (ok)
+        return PPCG_OK;
+    if (g.gexec) {
+        (void)hipGraphExecDestroy(g.gexec);
+        (void)hipGraphDestroy(g.graph);
+        g.gexec = nullptr;
+        g.graph = nullptr;
+    }
+    const int grid = std::min(g.table_cap, std::max(need, 1));
+    PPCG_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < iters; ++i) {
+        if (g.prec == PREC_F64)
+            launch_iter_pair<double>(stream_, g, grid, remap);
+        else
+            launch_iter_pair<float>(stream_, g, grid, remap);
+    }
+    hipError_t e = hipStreamEndCapture(stream_, &g.graph);
+    if (e != hipSuccess) {
+        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        return PPCG_ERR_DEVICE;
+    }
+    PPCG_HIP(hipGraphInstantiate(&g.gexec, g.graph, nullptr, nullptr, 0));
+    g.g_grid = grid;
+    g.g_iters = iters;
+    return PPCG_OK;
+}
+
+ppcg_status Engine::sync_states(Group &g)
+{
+    PPCG_HIP(hipMemcpyAsync(g.st_h, g.st_d, sizeof(SysState) * g.cap_sys, hipMemcpyDeviceToHost, stream_));
+    return PPCG_OK;
+}
+
+// Run an auxiliary operation over all tiles of the given slots of group g.
+ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what)
+{
+    if (slots.empty())
+        return PPCG_OK;
+    // The staging buffer and aux_d may still be read by earlier enqueued
+    // copies and kernels: drain the stream before reusing them.
+    PPCG_HIP(hipStreamSynchronize(stream_));
+    std::vector<WorkItem> items;
+    for (int sl : slots)
+        for (int t = 0; t < g.desc_h[sl].ntiles; ++t)
+            items.push_back({sl, t});
+    PPCG_TRY(grow_table(&g.aux_d, &g.aux_cap, (int)items.size()));
+    PPCG_TRY(upload_table(stream_, g, items, g.aux_d, g.aux_count_d, 1));
+    const int grid = (int)items.size();
+    hipStream_t s = stream_;
+    if (what == AUX_INIT) {
+        if (g.prec == PREC_F64) {
+            k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+            k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+            k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+        } else {
+            k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+            k_spmv<float, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+            k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+        }
+    } else if (what == AUX_RESID) {
+        if (g.prec == PREC_F64)
+            k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+        else
+            k_spmv<float, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+        k_reduce_resid<<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d);
+    } else if (what == AUX_MIX_START) {
+        k_mix_start<<<grid, 256, 0, s>>>(g.aux_d, g.aux_count_d, g64_.desc_d, g32_.desc_d);
+    } else if (what == AUX_MIX_CORRECT) {
+        k_mix_correct<<<grid, 256, 0, s>>>(g.aux_d, g.aux_count_d, g64_.desc_d, g32_.desc_d);
+    }
+    PPCG_HIP(hipGetLastError());
+    return PPCG_OK;
+}
+
+ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, int *job_id)
+{
+    Job j;
+    j.h = h;
+    j.mixed = mixed;
+    j.tol = tol;
+    j.t_start = now_ms();
+    j.slot64 = alloc_slot(g64_);
+    if (j.slot64 < 0) {
+        set_error("engine has no free slot");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    const ppcg_options &o = h->opt;
+    const int stop = o.stop == PPCG_STOP_PRECOND_ABS ? STOP_ABS : STOP_REL;
+    PPCG_TRY(fill_desc(h, PREC_F64, g64_.st_d + j.slot64, &g64_.desc_h[j.slot64], tol,
+                       mixed ? 0 : o.fixed_iters, o.max_iter, stop));
+    if (mixed) {
+        PPCG_TRY(ensure_f32(h));
+        j.slot32 = alloc_slot(g32_);
+        if (j.slot32 < 0) {
+            g64_.slot_used[j.slot64] = 0;
+            set_error("engine has no free slot");
+            return PPCG_ERR_INVALID_ARG;
+        }
+        double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+        PPCG_TRY(fill_desc(h, PREC_F32, g32_.st_d + j.slot32, &g32_.desc_h[j.slot32], itol, 0, o.max_iter,
+                           STOP_REL));
+        g32_.desc_h[j.slot32].pair = j.slot64;
+        g64_.desc_h[j.slot64].pair = j.slot32;
+        PPCG_TRY(upload_desc(g32_, j.slot32));
+        j.stage = JS_OUTER;
+    } else {
+        j.stage = JS_NEED_INIT;
+    }
+    PPCG_TRY(upload_desc(g64_, j.slot64));
+    // A new solve starts from a clean state (iteration counters at zero).
+    PPCG_HIP(hipMemsetAsync(g64_.st_d + j.slot64, 0, sizeof(SysState), stream_));
+    if (j.slot32 >= 0)
+        PPCG_HIP(hipMemsetAsync(g32_.st_d + j.slot32, 0, sizeof(SysState), stream_));
+    jobs_.push_back(j);
+    *job_id = (int)jobs_.size() - 1;
+    return PPCG_OK;
+}
+
+bool Engine::all_done() const
+{
+    for (const Job &j : jobs_)
+        if (!j.finished)
+            return false;
+    return true;
+}
+
+int Engine::active() const
+{
+    int a = 0;
+    for (const Job &j : jobs_)
+        a += !j.finished;
+    return a;
+}
+
+void Engine::reset()
+{
+    for (int i = 0; i < (int)jobs_.size(); ++i)
+        if (jobs_[i].h)
+            retire(i);
+    jobs_.clear();
+}
+
+void Engine::retire(int id)
+{
+    Job &j = jobs_[id];
+    if (j.slot64 >= 0)
+        g64_.slot_used[j.slot64] = 0;
+    if (j.slot32 >= 0)
+        g32_.slot_used[j.slot32] = 0;
+    j.slot64 = j.slot32 = -1;
+    j.h = nullptr;
+}
+
+static void finish(Job &j, int status, const SysState &st)
+{
+    j.finished = true;
+    j.stage = JS_DONE;
+    j.status = status;
+    j.t_end = now_ms();
+    if (!j.mixed) {
+        j.iters = st.iter;
+        j.bnorm2 = st.bnorm2;
+        const double bn = std::sqrt(st.bnorm2);
+        j.rel_recur = bn > 0 ? std::sqrt(st.rr) / bn : std::sqrt(st.rr);
+        j.precond_norm = std::sqrt(st.uu);
+    }
+}
+
+ppcg_status Engine::step(int graph_iters)
+{
+    // 1. transitions that need a true residual: FP64 jobs that stopped, and
+    //    mixed jobs between inner solves.
+    std::vector<int> resid64, correct64;
+    for (Job &j : jobs_) {
+        if (j.finished)
+            continue;
+        if (j.stage == JS_NEED_FINAL)
+            resid64.push_back(j.slot64);
+        else if (j.stage == JS_OUTER) {
+            if (j.outer > 0)
+                correct64.push_back(j.slot64);
+            resid64.push_back(j.slot64);
+        }
+    }
+    if (!resid64.empty()) {
+        PPCG_TRY(aux_launch(g64_, correct64, AUX_MIX_CORRECT));
+        PPCG_TRY(aux_launch(g64_, resid64, AUX_RESID));
+        PPCG_TRY(sync_states(g64_));
+        PPCG_HIP(hipStreamSynchronize(stream_));
+        std::vector<int> init64, start_mix;
+        for (Job &j : jobs_) {
+            if (j.finished || (j.stage != JS_NEED_FINAL && j.stage != JS_OUTER))
+                continue;
+            const SysState &st = g64_.st_h[j.slot64];
+            const double bn = std::sqrt(st.bnorm2);
+            const double rel = bn > 0 ? std::sqrt(st.tnorm2) / bn : std::sqrt(st.tnorm2);
+            j.rel_true = rel;
+            const ppcg_options &o = j.h->opt;
+            if (j.stage == JS_NEED_FINAL) {
+                const bool tol_mode = o.fixed_iters <= 0;
+                const bool can_restart = tol_mode && j.restarts < o.max_restarts && st.iter < o.max_iter;
+                if (st.status == ST_OK && tol_mode && o.stop == PPCG_STOP_REL_RESID && rel > j.tol) {
+                    if (can_restart) {
+                        ++j.restarts;
+                        j.stage = JS_NEED_INIT;
+                        continue;
+                    }
+                    finish(j, PPCG_STAGNATED, st);
+                } else if (st.status == ST_BREAKDOWN && st.i_start > 0 && can_restart) {
+                    ++j.restarts;
+                    j.stage = JS_NEED_INIT;
+                    continue;
+                } else {
+                    finish(j, st.status, st);
+                }
+            } else {  // mixed outer step
+                j.bnorm2 = st.bnorm2;
+                if (rel <= j.tol) {
+                    j.iters = j.inner_iters;
+                    finish(j, PPCG_OK, st);
+                    j.iters = j.inner_iters;
+                    j.rel_recur = rel;
+                } else if (j.outer >= o.max_outer || j.inner_iters >= o.max_iter || !(rel == rel)) {
+                    finish(j, !(rel == rel) ? PPCG_BREAKDOWN : PPCG_NOT_CONVERGED, st);
+                    j.iters = j.inner_iters;
+                    j.rel_recur = rel;
+                } else {
+                    // inner budget: what is left of max_iter
+                    SysDesc &d32 = g32_.desc_h[j.slot32];
+                    d32.maxit = o.max_iter - j.inner_iters;
+                    PPCG_TRY(upload_desc(g32_, j.slot32));
+                    start_mix.push_back(j.slot64);
+                    j.stage = JS_ITER;
+                    ++j.outer;
+                }
+            }
+        }
+        for (Job &j : jobs_)
+            if (!j.finished && j.stage == JS_NEED_INIT)
+                init64.push_back(j.slot64);
+        if (!start_mix.empty()) {
+            PPCG_TRY(aux_launch(g64_, start_mix, AUX_MIX_START));
+            std::vector<int> s32;
+            for (int sl : start_mix)
+                s32.push_back(g64_.desc_h[sl].pair);
+            PPCG_TRY(aux_launch(g32_, s32, AUX_INIT));
+        }
+        (void)init64;
+    }
+    // 2. initialisations of FP64 jobs.
+    {
+        std::vector<int> init64;
+        for (Job &j : jobs_)
+            if (!j.finished && j.stage == JS_NEED_INIT) {
+                init64.push_back(j.slot64);
+                j.stage = JS_ITER;
+            }
+        PPCG_TRY(aux_launch(g64_, init64, AUX_INIT));
+    }
+    // 3. iteration tables.
+    for (Group *g : {&g64_, &g32_}) {
+        std::vector<WorkItem> items;
+        for (const Job &j : jobs_) {
+            if (j.finished || j.stage != JS_ITER)
+                continue;
+            const bool in_this = (g == &g32_) == (j.mixed != 0);
+            if (!in_this)
+                continue;
+            const int sl = j.mixed ? j.slot32 : j.slot64;
+            for (int t = 0; t < g->desc_h[sl].ntiles; ++t)
+                items.push_back({sl, t});
+        }
+        if (items.size() != g->table_h.size() ||
+            !std::equal(items.begin(), items.end(), g->table_h.begin(),
+                        [](const WorkItem &a, const WorkItem &b) { return a.slot == b.slot && a.tile == b.tile; })) {
+            g->table_h = items;
+            g->table_dirty = true;
+        }
+    }
+    // 4. one graph chunk per non-empty group.
+    bool launched = false;
+    for (Group *g : {&g64_, &g32_}) {
+        if (g->table_h.empty())
+            continue;
+        PPCG_TRY(ensure_table(*g));
+        PPCG_TRY(ensure_graph(*g, graph_iters));
+        PPCG_HIP(hipGraphLaunch(g->gexec, stream_));
+        launched = true;
+    }
+    // 5. poll.
+    PPCG_TRY(sync_states(g64_));
+    PPCG_TRY(sync_states(g32_));
+    PPCG_HIP(hipStreamSynchronize(stream_));
+    (void)launched;
+    for (Job &j : jobs_) {
+        if (j.finished || j.stage != JS_ITER)
+            continue;
+        if (!j.mixed) {
+            const SysState &st = g64_.st_h[j.slot64];
+            if (st.done)
+                j.stage = JS_NEED_FINAL;
+        } else {
+            const SysState &st = g32_.st_h[j.slot32];
+            if (st.done) {
+                j.inner_iters += st.iter;
+                j.precond_norm = std::sqrt(st.uu);
+                j.stage = JS_OUTER;
+            }
+        }
+    }
+    return PPCG_OK;
+}
+
+// Iterations per graph chunk: aim for a few milliseconds of device work.
+int auto_graph_iters(const ppcg_handle *h)
+{
+    if (h->opt.graph_iters > 0)
+        return h->opt.graph_iters;
+    const ByteModel bm = byte_model(h, PREC_F64);
+    const double us = (bm.vma + bm.spmv) / 5.0e6 + 6.0;  // ~5 TB/s plus launch overheads
+    int k = (int)(2000.0 / us);
+    return std::max(8, std::min(k, 128));
+}
+
+// Copy b and x0 into the handle's internal (stored-row order) vectors.
+ppcg_status stage_inputs(ppcg_handle *h, const double *b, const double *x0)
+{
+    hipStream_t s = h->stream;
+    const int n = h->n;
+    double *bi = (double *)h->f64.vec[VB], *xi = (double *)h->f64.vec[VX], *tmp = (double *)h->f64.vec[VN];
+    const unsigned g = blocks_for(n, 256);
+    if (h->opt.vec_mem == PPCG_MEM_HOST) {
+        PPCG_HIP(hipMemcpyAsync(tmp, b, sizeof(double) * n, hipMemcpyHostToDevice, s));
+        k_gather<double, double><<<g, 256, 0, s>>>(n, h->perm, tmp, bi);
+        if (x0) {
+            PPCG_HIP(hipMemcpyAsync(tmp, x0, sizeof(double) * n, hipMemcpyHostToDevice, s));
+            k_gather<double, double><<<g, 256, 0, s>>>(n, h->perm, tmp, xi);
+        }
+    } else {
+        k_gather<double, double><<<g, 256, 0, s>>>(n, h->perm, b, bi);
+        if (x0)
+            k_gather<double, double><<<g, 256, 0, s>>>(n, h->perm, x0, xi);
+    }
+    if (!x0)
+        k_fill<double><<<g, 256, 0, s>>>((size_t)n, xi, 0.0);
+    PPCG_HIP(hipGetLastError());
+    return PPCG_OK;
+}
+
+ppcg_status unstage_x(ppcg_handle *h, double *x)
+{
+    hipStream_t s = h->stream;
+    const int n = h->n;
+    const double *xi = (const double *)h->f64.vec[VX];
+    double *tmp = (double *)h->f64.vec[VN];
+    const unsigned g = blocks_for(n, 256);
+    if (h->opt.vec_mem == PPCG_MEM_HOST) {
+        k_scatter<<<g, 256, 0, s>>>(n, h->perm, xi, tmp);
+        PPCG_HIP(hipMemcpyAsync(x, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    } else {
+        k_scatter<<<g, 256, 0, s>>>(n, h->perm, xi, x);
+    }
+    PPCG_HIP(hipGetLastError());
+    return PPCG_OK;
+}
+
+void fill_info(const ppcg_handle *h, const Job &j, ppcg_info *info)
+{
+    if (!info)
+        return;
+    const size_t sz = info->struct_size == sizeof(ppcg_info) ? sizeof(ppcg_info) : 0;
+    if (!sz)
+        return;
+    memset(info, 0, sizeof *info);
+    info->struct_size = sizeof *info;
+    info->status = (ppcg_status)j.status;
+    info->iters = j.iters;
+    info->outer_iters = j.outer;
+    info->restarts = j.restarts;
+    info->rel_resid_true = j.rel_true;
+    info->rel_resid_recur = j.rel_recur;
+    info->precond_norm = j.precond_norm;
+    info->time_ms = j.t_end - j.t_start;
+    const ByteModel bm = byte_model(h, j.mixed ? PREC_F32 : PREC_F64);
+    info->model_bytes = (bm.vma + bm.spmv) * j.iters;
+}
+
+// Order the internal stream after all work already queued on the caller's
+// stream (the legacy default stream when the caller passed NULL).
+ppcg_status wait_user(ppcg_handle *h)
+{
+    hipEvent_t ev;
+    PPCG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    PPCG_HIP(hipEventRecord(ev, h->user_stream));
+    PPCG_HIP(hipStreamWaitEvent(h->stream, ev, 0));
+    (void)hipEventDestroy(ev);
+    return PPCG_OK;
+}
+
+ppcg_status run_engine(Engine &E, int graph_iters)
+{
+    int guard = 0;
+    while (!E.all_done()) {
+        PPCG_TRY(E.step(graph_iters));
+        if (++guard > 10000000) {
+            set_error("engine made no progress");
+            return PPCG_ERR_DEVICE;
+        }
+    }
+    return PPCG_OK;
+}
+
+}  // namespace ppcg
+
+using namespace ppcg;
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char *ppcg_last_error(void) { return g_err.c_str(); }
+
+const char *ppcg_status_str(ppcg_status s)
+{
+    switch (s) {
+    case PPCG_OK: return "PPCG_OK";
+    case PPCG_NOT_CONVERGED: return "PPCG_NOT_CONVERGED";
+    case PPCG_BREAKDOWN: return "PPCG_BREAKDOWN";
+    case PPCG_STAGNATED: return "PPCG_STAGNATED";
+    case PPCG_ERR_INVALID_ARG: return "PPCG_ERR_INVALID_ARG";
+    case PPCG_ERR_BAD_CSR: return "PPCG_ERR_BAD_CSR";
+    case PPCG_ERR_NOMEM: return "PPCG_ERR_NOMEM";
+    case PPCG_ERR_DEVICE: return "PPCG_ERR_DEVICE";
+    case PPCG_ERR_BUDGET: return "PPCG_ERR_BUDGET";
+    }
+    return "PPCG_UNKNOWN";
+}
+
+ppcg_status ppcg_default_options(ppcg_options *opt)
+{
+    if (!opt) {
+        set_error("opt is NULL");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    memset(opt, 0, sizeof *opt);
+    opt->struct_size = sizeof *opt;
+    opt->tol = 1e-8;
+    opt->max_iter = 10000;
+    opt->fixed_iters = 0;
+    opt->max_restarts = 3;
+    opt->stop = PPCG_STOP_REL_RESID;
+    opt->precision = PPCG_FP64;
+    opt->vec_mem = PPCG_MEM_DEVICE;
+    opt->spmv_format = PPCG_SPMV_AUTO;
+    opt->graph_iters = 0;
+    opt->inner_tol = 0.0;
+    opt->max_outer = 30;
+    opt->flags = 0;
+    return PPCG_OK;
+}
+
+static ppcg_status check_options(const ppcg_options *o)
+{
+    if (!o || o->struct_size != sizeof(ppcg_options)) {
+        set_error("options NULL or struct_size mismatch");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol) || o->max_iter < 0 || o->fixed_iters < 0 ||
+        o->max_restarts < 0 || o->graph_iters < 0 || o->graph_iters > 4096 || !(o->inner_tol >= 0.0) ||
+        o->inner_tol >= 1.0 || o->max_outer < 0 ||
+        (o->stop != PPCG_STOP_REL_RESID && o->stop != PPCG_STOP_PRECOND_ABS) ||
+        (o->precision != PPCG_FP64 && o->precision != PPCG_MIXED_FP32) ||
+        (o->vec_mem != PPCG_MEM_DEVICE && o->vec_mem != PPCG_MEM_HOST) ||
+        (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
+         o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
+        o->flags != 0) {
+        set_error("invalid option value");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    return PPCG_OK;
+}
+
+static void destroy_handle(ppcg_handle *h)
+{
+    if (!h)
+        return;
+    if (h->stream)
+        (void)hipStreamSynchronize(h->stream);
+    delete h->solo;
+    h->solo = nullptr;
+    plain_free(h);
+    free_matrix(h);
+    if (h->dinv64)
+        (void)hipFree(h->dinv64);
+    h->f64.arena.release();
+    h->f32.arena.release();
+    if (h->stream)
+        (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_stream, ppcg_handle **out)
+{
+    clear_error();
+    if (!out) {
+        set_error("out is NULL");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!A || A->struct_size != sizeof(ppcg_csr)) {
+        set_error("A NULL or struct_size mismatch");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    PPCG_TRY(check_options(opt));
+    if (A->n < 1 || A->nnz < A->n || A->nnz >= (int64_t)INT_MAX || !A->row_ptr || !A->col_idx || !A->values ||
+        (A->mem != PPCG_MEM_DEVICE && A->mem != PPCG_MEM_HOST)) {
+        set_error("invalid CSR description (n=%d nnz=%lld)", A->n, (long long)A->nnz);
+        return PPCG_ERR_INVALID_ARG;
+    }
+    const double t0 = now_ms();
+    ppcg_handle *h = new ppcg_handle();
+    h->opt = *opt;
+    h->n = A->n;
+    h->nnz = A->nnz;
+    h->ntiles = (A->n + kTileRows - 1) / kTileRows;
+    h->user_stream = (hipStream_t)hip_stream;
+    int *rp = nullptr, *ci = nullptr, *rowlen = nullptr;
+    double *val = nullptr, *dinv_orig = nullptr;
+    unsigned *err = nullptr;
+    bool own_csr = false;
+    auto fail = [&](ppcg_status s) {
+        if (own_csr) {
+            if (rp) (void)hipFree(rp);
+            if (ci) (void)hipFree(ci);
+            if (val) (void)hipFree(val);
+        }
+        if (rowlen) (void)hipFree(rowlen);
+        if (dinv_orig) (void)hipFree(dinv_orig);
+        if (err) (void)hipFree(err);
+        destroy_handle(h);
+        return s;
+    };
+#define CK(call)                                                                              \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            set_error("%s failed: %s", #call, hipGetErrorString(e_));                         \
+            return fail(e_ == hipErrorOutOfMemory ? PPCG_ERR_NOMEM : PPCG_ERR_DEVICE);        \
+        }                                                                                     \
+    } while (0)
+#define CKS(expr)                   \
+    do {                            \
+        ppcg_status s_ = (expr);    \
+        if (s_ != PPCG_OK)          \
+            return fail(s_);        \
+    } while (0)
+    CK(hipGetDevice(&h->device));
+    CK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    hipStream_t s = h->stream;
+    {
+        hipEvent_t ev;
+        CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        CK(hipEventRecord(ev, h->user_stream));
+        CK(hipStreamWaitEvent(s, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
+    const int n = A->n;
+    const int64_t nnz = A->nnz;
+    if (A->mem == PPCG_MEM_HOST) {
+        own_csr = true;
+        CK(hipMalloc(&rp, sizeof(int) * (n + 1)));
+        CK(hipMalloc(&ci, sizeof(int) * nnz));
+        CK(hipMalloc(&val, sizeof(double) * nnz));
+        CK(hipMemcpyAsync(rp, A->row_ptr, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(ci, A->col_idx, sizeof(int) * nnz, hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(val, A->values, sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+    } else {
+        CKS(check_dev_range(A->row_ptr, sizeof(int) * (n + 1), "row_ptr"));
+        CKS(check_dev_range(A->col_idx, sizeof(int) * nnz, "col_idx"));
+        CKS(check_dev_range(A->values, sizeof(double) * nnz, "values"));
+        rp = (int *)A->row_ptr;
+        ci = (int *)A->col_idx;
+        val = (double *)A->values;
+    }
+    CK(hipMalloc(&rowlen, sizeof(int) * n));
+    CK(hipMalloc(&dinv_orig, sizeof(double) * n));
+    CK(hipMalloc(&h->dinv64, sizeof(double) * n));
+    CK(hipMalloc(&err, sizeof(unsigned) * 2));
+    unsigned err_init[2] = {0u, 0xFFFFFFFFu};
+    CK(hipMemcpyAsync(err, err_init, sizeof err_init, hipMemcpyHostToDevice, s));
+    k_validate<<<blocks_for(n, 256), 256, 0, s>>>(n, nnz, rp, ci, val, dinv_orig, rowlen, err);
+    CK(hipGetLastError());
+    unsigned err_h[2];
+    CK(hipMemcpyAsync(err_h, err, sizeof err_h, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (err_h[0]) {
+        std::string what;
+        const char *names[] = {"row_ptr[0] != 0", "row_ptr[n] != nnz", "row_ptr not monotone / out of range",
+                               "column index out of range", "columns not strictly ascending",
+                               "missing diagonal", "diagonal not positive", "non-finite value"};
+        for (int b = 0; b < 8; ++b)
+            if (err_h[0] & (1u << b)) {
+                if (!what.empty())
+                    what += ", ";
+                what += names[b];
+            }
+        set_error("bad CSR: %s (first row %u)", what.c_str(), err_h[1]);
+        return fail(PPCG_ERR_BAD_CSR);
+    }
+    std::vector<int> rowlen_h(n);
+    CK(hipMemcpy(rowlen_h.data(), rowlen, sizeof(int) * n, hipMemcpyDeviceToHost));
+    CKS(alloc_f64_vectors(h));
+    CKS(choose_format(h, rp, ci, val, rowlen, dinv_orig, rowlen_h));
+    if (opt->precision == PPCG_MIXED_FP32)
+        CKS(ensure_f32(h));
+    CK(hipStreamSynchronize(s));
+    if (own_csr) {
+        (void)hipFree(rp);
+        (void)hipFree(ci);
+        (void)hipFree(val);
+    }
+    (void)hipFree(rowlen);
+    (void)hipFree(dinv_orig);
+    (void)hipFree(err);
+    h->setup_ms = now_ms() - t0;
+    *out = h;
+    return PPCG_OK;
+#undef CK
+#undef CKS
+}
+
+ppcg_status ppcg_set_options(ppcg_handle *h, const ppcg_options *opt)
+{
+    clear_error();
+    if (!h) {
+        set_error("handle is NULL");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    PPCG_TRY(check_options(opt));
+    if (opt->spmv_format != h->opt.spmv_format && opt->spmv_format != PPCG_SPMV_AUTO) {
+        set_error("the SpMV format is fixed at creation");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    ppcg_spmv_format keep = h->opt.spmv_format;
+    h->opt = *opt;
+    h->opt.spmv_format = keep;
+    if (opt->precision == PPCG_MIXED_FP32)
+        PPCG_TRY(ensure_f32(h));
+    return PPCG_OK;
+}
+
+ppcg_status ppcg_destroy(ppcg_handle *h)
+{
+    clear_error();
+    destroy_handle(h);
+    return PPCG_OK;
+}
+
+static ppcg_status check_vec(const ppcg_handle *h, const void *p, const char *what, bool may_null)
+{
+    if (!p) {
+        if (may_null)
+            return PPCG_OK;
+        set_error("%s is NULL", what);
+        return PPCG_ERR_INVALID_ARG;
+    }
+    if (h->opt.vec_mem == PPCG_MEM_DEVICE)
+        return check_dev_range(p, sizeof(double) * (size_t)h->n, what);
+    return PPCG_OK;
+}
+
+ppcg_status ppcg_solve(ppcg_handle *h, const double *b, const double *x0, double *x, ppcg_info *info)
+{
+    clear_error();
+    if (!h) {
+        set_error("handle is NULL");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    if (info && info->struct_size != sizeof(ppcg_info)) {
+        set_error("info struct_size mismatch");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    PPCG_TRY(check_vec(h, b, "b", false));
+    PPCG_TRY(check_vec(h, x0, "x0", true));
+    PPCG_TRY(check_vec(h, x, "x", false));
+    PPCG_HIP(hipSetDevice(h->device));
+    PPCG_TRY(wait_user(h));
+    PPCG_TRY(stage_inputs(h, b, x0));
+    if (!h->solo) {
+        h->solo = new Engine(h->stream);
+        PPCG_TRY(h->solo->init(1));
+    }
+    Engine &E = *h->solo;
+    E.reset();  // the solo engine is reused: one job per solve
+    int id = -1;
+    const int mixed = h->opt.precision == PPCG_MIXED_FP32;
+    PPCG_TRY(E.add(h, mixed, h->opt.tol, nullptr, &id));
+    PPCG_TRY(run_engine(E, auto_graph_iters(h)));
+    PPCG_TRY(unstage_x(h, x));
+    PPCG_HIP(hipStreamSynchronize(h->stream));
+    Job &j = E.job(id);
+    j.t_end = now_ms();
+    fill_info(h, j, info);
+    return (ppcg_status)j.status;
+}
+
+ppcg_status ppcg_solve_batch(int32_t count, ppcg_handle *const *hs, const double *const *b, const double *const *x0,
+                             double *const *x, ppcg_info *infos)
+{
+    clear_error();
+    if (count < 1 || !hs || !b || !x) {
+        set_error("invalid batch arguments");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i]) {
+            set_error("hs[%d] is NULL", i);
+            return PPCG_ERR_INVALID_ARG;
+        }
+        for (int k = 0; k < i; ++k)
+            if (hs[k] == hs[i]) {
+                set_error("handle %d appears twice in the batch", i);
+                return PPCG_ERR_INVALID_ARG;
+            }
+        if (hs[i]->device != hs[0]->device) {
+            set_error("handles on different devices");
+            return PPCG_ERR_INVALID_ARG;
+        }
+        if (infos && infos[i].struct_size != sizeof(ppcg_info)) {
+            set_error("infos[%d] struct_size mismatch", i);
+            return PPCG_ERR_INVALID_ARG;
+        }
+        PPCG_TRY(check_vec(hs[i], b[i], "b[i]", false));
+        PPCG_TRY(check_vec(hs[i], x0 ? x0[i] : nullptr, "x0[i]", true));
+        PPCG_TRY(check_vec(hs[i], x[i], "x[i]", false));
+    }
+    ppcg_handle *h0 = hs[0];
+    PPCG_HIP(hipSetDevice(h0->device));
+    PPCG_TRY(wait_user(h0));
+    hipStream_t s = h0->stream;
+    // All staging runs on the first handle's internal stream.
+    for (int i = 0; i < count; ++i) {
+        hipStream_t keep = hs[i]->stream;
+        hs[i]->stream = s;
+        ppcg_status rc = stage_inputs(hs[i], b[i], x0 ? x0[i] : nullptr);
+        hs[i]->stream = keep;
+        PPCG_TRY(rc);
+    }
+    Engine E(s);
+    PPCG_TRY(E.init(count));
+    int gi = 128;
+    for (int i = 0; i < count; ++i) {
+        int id;
+        const int mixed = hs[i]->opt.precision == PPCG_MIXED_FP32;
+        PPCG_TRY(E.add(hs[i], mixed, hs[i]->opt.tol, nullptr, &id));
+        gi = std::min(gi, auto_graph_iters(hs[i]));
+    }
+    PPCG_TRY(run_engine(E, std::max(gi, 16)));
+    for (int i = 0; i < count; ++i) {
+        hipStream_t keep = hs[i]->stream;
+        hs[i]->stream = s;
+        ppcg_status rc = unstage_x(hs[i], x[i]);
+        hs[i]->stream = keep;
+        PPCG_TRY(rc);
+    }
+    PPCG_HIP(hipStreamSynchronize(s));
+    if (infos)
+        for (int i = 0; i < count; ++i)
+            fill_info(hs[i], E.job(i), &infos[i]);
+    return PPCG_OK;
+}
+
+ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
+{
+    clear_error();
+    if (!h || !mi || mi->struct_size != sizeof(ppcg_matrix_info)) {
+        set_error("invalid arguments");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    memset(mi, 0, sizeof *mi);
+    mi->struct_size = sizeof *mi;
+    mi->n = h->n;
+    mi->nnz = h->nnz;
+    mi->nnz_stored = h->nnz_stored;
+    mi->format = (ppcg_spmv_format)h->fmt;
+    mi->sell_c = kSellC;
+    mi->sell_sigma = h->sigma;
+    mi->lanes_per_row = h->lanes;
+    mi->tile_rows = kTileRows;
+    const ByteModel bm = byte_model(h, h->opt.precision == PPCG_MIXED_FP32 ? PREC_F32 : PREC_F64);
+    mi->bytes_vma = bm.vma;
+    mi->bytes_spmv = bm.spmv;
+    mi->bytes_per_iter = bm.vma + bm.spmv;
+    mi->device_bytes = (double)h->f64.arena.size + (double)h->f32.arena.size +
+                       (double)h->nnz_stored * 12.0 + 8.0 * h->n +
+                       (h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (h->n + 1)) +
+                       (h->perm ? 8.0 * h->n : 0.0);
+    mi->setup_ms = h->setup_ms;
+    return PPCG_OK;
+}
+
+double ppcg_footprint_bytes(int32_t n, int64_t nnz, ppcg_precision precision)
+{
+    if (n < 1 || nnz < n)
+        return 0.0;
+    const double ntiles = (n + kTileRows - 1) / kTileRows;
+    const double stored = 1.10 * (double)nnz;  // padding allowance
+    double b = stored * 12.0 + 8.0 * (n / kSellC + 2) + 8.0 * n /* dinv */ + 8.0 * n /* perm */ +
+               11.0 * 8.0 * n + 2.0 * ntiles * kNumPartials * 8.0 + 12 * 256.0;
+    if (precision == PPCG_MIXED_FP32)
+        b += stored * 4.0 + 12.0 * 4.0 * n + 2.0 * ntiles * kNumPartials * 8.0;
+    return b;
+}
+
+ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, double *ms_vma, double *ms_spmv)
+{
+    clear_error();
+    if (!h || iters < 1 || iters > 100000 || !ms_vma || !ms_spmv) {
+        set_error("invalid arguments");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    PPCG_TRY(check_vec(h, b, "b", false));
+    PPCG_HIP(hipSetDevice(h->device));
+    PPCG_TRY(wait_user(h));
+    PPCG_TRY(stage_inputs(h, b, nullptr));
+    hipStream_t s = h->stream;
+    // Fixed-iteration mode with a count larger than iters: never stops early.
+    PPCG_TRY(plain_setup(h, 0.0, INT_MAX, INT_MAX));
+    std::vector<hipEvent_t> ev(2 * iters + 1, nullptr);
+    auto clean = [&]() {
+        (void)hipStreamSynchronize(s);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    const int grid = h->ntiles;
+    const WorkItem *tab = h->plain_tab;
+    const int *cnt = h->plain_cnt;
+    const SysDesc *dd = h->plain_desc;
+    k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, 1);
+    k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, 1);
+    k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, 1);
+    for (auto &e : ev)
+        PPCG_HIP_CLEAN(hipEventCreate(&e), clean());
+    PPCG_HIP_CLEAN(hipEventRecord(ev[0], s), clean());
+    for (int i = 0; i < iters; ++i) {
+        k_vma<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd, 1);
+        PPCG_HIP_CLEAN(hipEventRecord(ev[2 * i + 1], s), clean());
+        k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, 1);
+        PPCG_HIP_CLEAN(hipEventRecord(ev[2 * i + 2], s), clean());
+    }
+    PPCG_HIP_CLEAN(hipEventSynchronize(ev[2 * iters]), clean());
+    double tv = 0, ts = 0;
+    for (int i = 0; i < iters; ++i) {
+        float a = 0, c = 0;
+        PPCG_HIP_CLEAN(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]), clean());
+        PPCG_HIP_CLEAN(hipEventElapsedTime(&c, ev[2 * i + 1], ev[2 * i + 2]), clean());
+        tv += a;
+        ts += c;
+    }
+    *ms_vma = tv / iters;
+    *ms_spmv = ts / iters;
+    clean();
+    return PPCG_OK;
+}
+
+ppcg_status ppcg_spmv(ppcg_handle *h, const double *x, double *y)
+{
+    clear_error();
+    if (!h) {
+        set_error("handle is NULL");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    PPCG_TRY(check_vec(h, x, "x", false));
+    PPCG_TRY(check_vec(h, y, "y", false));
+    if (x == y) {
+        set_error("x and y must not alias");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    PPCG_HIP(hipSetDevice(h->device));
+    PPCG_TRY(wait_user(h));
+    // stage x into the internal x vector (stored-row order)
+    PPCG_TRY(stage_inputs(h, x, x));
+    PPCG_TRY(plain_setup(h, 1e-8, 0, 1));
+    hipStream_t s = h->stream;
+    k_spmv<double, MODE_PLAIN><<<h->ntiles, kSpmvThreads, 0, s>>>(h->plain_tab, h->plain_cnt, h->plain_desc, 1);
+    PPCG_HIP(hipGetLastError());
+    // result is in the internal nv vector; scatter it out like x
+    const int n = h->n;
+    const unsigned g = blocks_for(n, 256);
+    double *nv = (double *)h->f64.vec[VN], *tmp = (double *)h->f64.vec[VZ];
+    if (h->opt.vec_mem == PPCG_MEM_HOST) {
+        k_scatter<<<g, 256, 0, s>>>(n, h->perm, nv, tmp);
+        PPCG_HIP(hipMemcpyAsync(y, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    } else {
+        k_scatter<<<g, 256, 0, s>>>(n, h->perm, nv, y);
+    }
+    PPCG_HIP(hipStreamSynchronize(s));
+    return PPCG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+// ppcg_setup.hpp -- device kernels that prepare a matrix (ppcg_create).
+//
+// Validation and the Jacobi inverse diagonal (Section V-A: Jacobi
+// preconditioner, CSR input), then conversion of CSR to SELL-C-sigma: rows
+// (optionally sorted by length inside windows of sigma rows) are cut into
+// chunks of C = 64, each chunk padded to its longest row and stored
+// column-major, so that lane l of a wavefront reads entry k of its row at
+// offset k * 64 + l and every load instruction of the wavefront is one
+// contiguous 512-byte (values) or 256-byte (columns) segment.
+#pragma once
+
+#include "ppcg_internal.hpp"
+
+namespace ppcg {
+
+enum CsrErr : unsigned {
+    CSR_E_RP0 = 1u,       // row_ptr[0] != 0
+    CSR_E_RPN = 2u,       // row_ptr[n] != nnz
+    CSR_E_MONO = 4u,      // row_ptr decreasing or out of [0, nnz]
+    CSR_E_COL = 8u,       // column index out of range
+    CSR_E_ORDER = 16u,    // columns not strictly ascending in a row
+    CSR_E_NODIAG = 32u,   // missing diagonal
+    CSR_E_DIAG = 64u,     // diagonal not > 0
+    CSR_E_VAL = 128u      // non-finite value
+};
+
+// err[0]: OR of CsrErr flags, err[1]: first offending row (atomic min).
+__global__ void k_validate(int n, int64_t nnz, const int *__restrict__ rp, const int *__restrict__ ci,
+                           const double *__restrict__ val, double *__restrict__ dinv, int *__restrict__ rowlen,
+                           unsigned *__restrict__ err)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        if (rp[0] != 0)
+            atomicOr(&err[0], CSR_E_RP0);
+        if ((int64_t)rp[n] != nnz)
+            atomicOr(&err[0], CSR_E_RPN);
+    }
+    if (i >= n)
+        return;
+    const int a = rp[i], b = rp[i + 1];
+    if (a < 0 || b < a || (int64_t)b > nnz) {
+        atomicOr(&err[0], CSR_E_MONO);
+        atomicMin(&err[1], (unsigned)i);
+        rowlen[i] = 0;
+        dinv[i] = 0.0;
+        return;
+    }
+    unsigned f = 0;
+    int prev = -1;
+    double dg = 0.0;
+    bool found = false;
+    for (int k = a; k < b; ++k) {
+        const int c = ci[k];
+        const double v = val[k];
+        if (c < 0 || c >= n)
+            f |= CSR_E_COL;
+        else if (c <= prev)
+            f |= CSR_E_ORDER;
+        prev = c;
+        if (!isfinite(v))
+            f |= CSR_E_VAL;
+        if (c == i) {
+            dg = v;
+            found = true;
+        }
+    }
+    if (!found)
+        f |= CSR_E_NODIAG;
+    else if (!(dg > 0.0))
+        f |= CSR_E_DIAG;
+    if (f) {
+        atomicOr(&err[0], f);
+        atomicMin(&err[1], (unsigned)i);
+    }
+    dinv[i] = found && dg > 0.0 ? 1.0 / dg : 0.0;
+    rowlen[i] = b - a;
+}
+
+// Sort the rows of each window of kSortWindow rows by decreasing length
+// (ties by increasing index): perm[p] = original row at sorted position p.
+// One workgroup of kSortWindow / 2 threads per window, bitonic sort in LDS.
+__global__ __launch_bounds__(kSortWindow / 2) void k_sort_window(int n, const int *__restrict__ rowlen,
+                                                                  int *__restrict__ perm)
+{
+    __shared__ unsigned long long key[kSortWindow];
+    const int w0 = blockIdx.x * kSortWindow;
+    for (int j = threadIdx.x; j < kSortWindow; j += blockDim.x) {
+        const int r = w0 + j;
+        key[j] = r < n ? ((unsigned long long)(0xFFFFFFFFu - (unsigned)rowlen[r]) << 32) | (unsigned)j
+                       : ~0ull;
+    }
+    __syncthreads();
+    for (int k = 2; k <= kSortWindow; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < kSortWindow; t += blockDim.x) {
+                const int partner = t ^ j;
+                if (partner > t) {
+                    const bool up = (t & k) == 0;
+                    const unsigned long long a = key[t], b = key[partner];
+                    if ((a > b) == up) {
+                        key[t] = b;
+                        key[partner] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = threadIdx.x; j < kSortWindow; j += blockDim.x) {
+        const int p = w0 + j;
+        if (p < n)
+            perm[p] = w0 + (int)(key[j] & 0xFFFFFFFFull);
+    }
+}
+
+__global__ void k_invert_perm(int n, const int *__restrict__ perm, int *__restrict__ invperm)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n)
+        invperm[perm[p]] = p;
+}
+
+// Entries stored by each chunk: 64 x (longest row of the chunk).
+__global__ void k_chunk_size(int n, int nchunks, const int *__restrict__ perm, const int *__restrict__ rowlen,
+                             int64_t *__restrict__ sz)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nchunks)
+        return;
+    int mx = 0;
+    for (int l = 0; l < kSellC; ++l) {
+        const int p = c * kSellC + l;
+        if (p < n) {
+            const int r = perm ? perm[p] : p;
+            mx = max(mx, rowlen[r]);
+        }
+    }
+    sz[c] = (int64_t)mx * kSellC;
+}
+
+// Exclusive scan of sz[0..m) into out[0..m], single workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_scan(int m, const int64_t *__restrict__ sz, int64_t *__restrict__ out)
+{
+    __shared__ int64_t s[1024];
+    const int t = threadIdx.x;
+    const int per = (m + 1023) / 1024;
+    const int a = min(t * per, m), b = min(a + per, m);
+    int64_t sum = 0;
+    for (int i = a; i < b; ++i)
+        sum += sz[i];
+    s[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t ? s[t - 1] : 0;
+    for (int i = a; i < b; ++i) {
+        out[i] = run;
+        run += sz[i];
+    }
+    if (t == 1023)
+        out[m] = s[1023];
+}
+
+// Fill SELL arrays.  Stored row p (original row perm[p]) keeps its entries
+// in their CSR order; columns are relabelled to sorted positions when the
+// rows are permuted.  Padding entries have value 0 and a valid column (the
+// row's own position, or n-1 for the rows past n of the last chunk).
+__global__ void k_sell_fill(int n, int nchunks, const int *__restrict__ rp, const int *__restrict__ ci,
+                            const double *__restrict__ val, const int *__restrict__ perm,
+                            const int *__restrict__ invperm, const int64_t *__restrict__ cptr,
+                            int *__restrict__ scol, double *__restrict__ sval)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nchunks * kSellC)
+        return;
+    const int c = p / kSellC, l = p % kSellC;
+    const int64_t base = cptr[c];
+    const int len = (int)((cptr[c + 1] - base) / kSellC);
+    int a = 0, L = 0;
+    if (p < n) {
+        const int r = perm ? perm[p] : p;
+        a = rp[r];
+        L = rp[r + 1] - a;
+    }
+    const int pad_col = p < n ? p : n - 1;
+    for (int k = 0; k < len; ++k) {
+        const size_t o = (size_t)base + (size_t)k * kSellC + l;
+        if (k < L) {
+            const int cc = ci[a + k];
+            scol[o] = invperm ? invperm[cc] : cc;
+            sval[o] = val[a + k];
+        } else {
+            scol[o] = pad_col;
+            sval[o] = 0.0;
+        }
+    }
+}
+
+// Permute the inverse diagonal into stored-row order.
+__global__ void k_permute_d(int n, const int *__restrict__ perm, const double *__restrict__ in,
+                            double *__restrict__ out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n)
+        out[p] = in[perm ? perm[p] : p];
+}
+
+template <typename TO, typename TI>
+__global__ void k_convert(size_t m, const TI *__restrict__ in, TO *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m)
+        out[i] = (TO)in[i];
+}
+
+}  // namespace ppcg

@@ -1,0 +1,432 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances.  The fused updates and the SpMV (SELL format) perform the same
+rounded operations in the same order as the oracle, so the SpMV is checked
+bit for bit.  The dot products are reduced in a different (fixed, tree)
+order, so the scalars alpha and beta differ in their last bits and iterates
+drift apart by rounding; for the well-conditioned cases here that drift stays
+below 1e-10 relative after the fixed iteration counts tested, the bound set
+for the FP64 iterates.  Tolerance solves are judged on the true residual and
+on the iteration count (equal to the oracle's within 2).
+"""
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_06176_amd import ppcg
+from paper_2105_06176_amd.ppcg import PPCGError, Server, Solver, solve_batch
+from workloads import (CSR, batch_c4, poisson2d, poisson3d, random_spd, rhs_from_solution, shifted,
+                       stencil27_lognormal, xstar_paper, xstar_uniform)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dev(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def problem(A, seed=1):
+    xs = xstar_uniform(A.n, seed)
+    return rhs_from_solution(A, xs), xs
+
+
+CASES = {
+    "c1_poisson2d_64": lambda: poisson2d(64),
+    "poisson2d_37_ragged": lambda: poisson2d(37),
+    "poisson3d_24": lambda: poisson3d(24),
+    "random_spd_3001": lambda: random_spd(3001, seed=2),
+    "stencil27_12": lambda: stencil27_lognormal(12, seed=3),
+}
+
+
+# ---------------------------------------------------------------- SpMV
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("fmt", ["sell", "csr_vector", "auto"])
+def test_spmv_matches_oracle(name, fmt):
+    A = CASES[name]()
+    S = Solver(A, spmv_format=fmt)
+    x = xstar_uniform(A.n, 7)
+    y = host(S.spmv(dev(x)))
+    y_ora = oracle.spmv(A, x)
+    if S.matrix_info()["format"] == ppcg.SPMV_SELL:
+        assert np.array_equal(y, y_ora), "SELL SpMV must match the oracle bit for bit"
+    else:
+        rowabs = np.abs(A.to_scipy()) @ np.abs(x)
+        assert np.all(np.abs(y - y_ora) <= 4 * np.finfo(float).eps * rowabs)
+
+
+def test_spmv_sorted_sell_is_bitwise():
+    """Random SPD rows vary in length, so SELL sorts rows in windows
+    (sigma > 1); the permuted product must still match bit for bit."""
+    A = random_spd(5000, seed=9)
+    S = Solver(A, spmv_format="sell")
+    mi = S.matrix_info()
+    assert mi["sell_sigma"] > 1
+    assert mi["nnz_stored"] < 1.10 * A.nnz
+    x = xstar_uniform(A.n, 3)
+    assert np.array_equal(host(S.spmv(dev(x))), oracle.spmv(A, x))
+
+
+# ---------------------------------------------------------------- fixed iterates
+
+@pytest.mark.parametrize("name,ks", [("c1_poisson2d_64", (1, 10, 50, 100)), ("poisson2d_37_ragged", (5, 40)),
+                                     ("poisson3d_24", (20, 60)), ("random_spd_3001", (10, 30)),
+                                     ("stencil27_12", (10, 20))])
+@pytest.mark.parametrize("fmt", ["sell", "csr_vector"])
+def test_fixed_iterates_match_oracle(name, ks, fmt):
+    A = CASES[name]()
+    b, _ = problem(A)
+    S = Solver(A, spmv_format=fmt)
+    bd = dev(b)
+    for k in ks:
+        S.set_options(fixed_iters=k)
+        x, info = S.solve(bd)
+        ref = oracle.pipecg(A, b, fixed_iters=k)
+        assert info["status"] == ppcg.OK
+        assert info["iters"] == k == ref.iters
+        assert relerr(host(x), ref.x) <= 1e-10, (k, relerr(host(x), ref.x))
+
+
+def test_solves_are_deterministic():
+    A = random_spd(4000, seed=4)
+    b, _ = problem(A)
+    S = Solver(A, fixed_iters=40)
+    x1, _ = S.solve(dev(b))
+    x2, _ = S.solve(dev(b))
+    assert np.array_equal(host(x1), host(x2))
+
+
+# ---------------------------------------------------------------- tolerance solves
+
+@pytest.mark.parametrize("name,tol", [("c1_poisson2d_64", 1e-8), ("poisson3d_24", 1e-10),
+                                      ("random_spd_3001", 1e-10), ("stencil27_12", 1e-8)])
+def test_tolerance_solve_matches_oracle(name, tol):
+    A = CASES[name]()
+    b, xs = problem(A)
+    S = Solver(A, tol=tol)
+    x, info = S.solve(dev(b))
+    ref = oracle.pipecg(A, b, tol=tol)
+    assert info["status"] == ppcg.OK
+    assert abs(info["iters"] - ref.iters) <= 2
+    assert info["rel_resid_true"] <= tol
+    assert oracle.true_relres(A, b, host(x)) <= tol
+
+
+def test_paper_protocol_absolute_preconditioned_tolerance():
+    """Section VI protocol: x* = 1/sqrt(N), b = A x*, absolute tolerance 1e-5
+    on sqrt((u,u)), at most 10000 iterations."""
+    for A in (poisson2d(64), poisson3d(32)):
+        b = rhs_from_solution(A, xstar_paper(A.n))
+        S = Solver(A, tol=1e-5, stop="abs", max_iter=10000)
+        x, info = S.solve(dev(b))
+        ref = oracle.pipecg(A, b, tol=1e-5, stop=oracle.STOP_ABS, maxit=10000)
+        assert info["status"] == ppcg.OK
+        assert abs(info["iters"] - ref.iters) <= 2
+        assert info["precond_norm"] < 1e-5
+
+
+# ---------------------------------------------------------------- full size 128^3
+
+def _golden_c2():
+    vals, meta = {}, {}
+    with open(os.path.join(GOLDEN, "c2_poisson3d_128.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            p = line.split()
+            if p[0] == "x500":
+                vals[int(p[1])] = float(p[2])
+            else:
+                meta[p[0]] = float(p[1])
+    return vals, meta
+
+
+@pytest.fixture(scope="module")
+def c2():
+    A = poisson3d(128)
+    b, _ = problem(A)
+    return A, b
+
+
+def test_c2_full_size_spmv_bitwise(c2):
+    A, _ = c2
+    S = Solver(A)
+    x = xstar_uniform(A.n, 5)
+    assert np.array_equal(host(S.spmv(dev(x))), oracle.spmv(A, x))
+
+
+def test_c2_full_size_500_iterations_sampled(c2):
+    A, b = c2
+    vals, meta = _golden_c2()
+    S = Solver(A, fixed_iters=500)
+    x, info = S.solve(dev(b))
+    assert info["iters"] == 500
+    xh = host(x)
+    idx = np.array(sorted(vals))
+    ref = np.array([vals[i] for i in idx])
+    assert relerr(xh[idx], ref) <= 1e-10
+    assert abs(np.linalg.norm(xh) - meta["norm_x500"]) <= 1e-10 * meta["norm_x500"]
+
+
+def test_c2_full_size_to_tolerance(c2):
+    A, b = c2
+    _, meta = _golden_c2()
+    S = Solver(A, tol=1e-10)
+    x, info = S.solve(dev(b))
+    assert info["status"] == ppcg.OK
+    assert abs(info["iters"] - int(meta["tol1e-10_iters"])) <= 2
+    assert info["rel_resid_true"] <= 1e-10
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_one_by_one_and_tiny_systems():
+    A = CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+    x, info = Solver(A).solve(dev([2.0]))
+    assert info["iters"] == 1 and host(x)[0] == 0.5
+    D = np.array([[4.0, -1.0, 0.0], [-1.0, 4.0, -1.0], [0.0, -1.0, 4.0]])
+    from scipy.sparse import csr_matrix
+
+    M = csr_matrix(D)
+    A3 = CSR(3, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data)
+    b = np.array([1.0, 2.0, 3.0])
+    x, info = Solver(A3, tol=1e-14).solve(dev(b))
+    assert info["iters"] <= 3
+    assert relerr(host(x), np.linalg.solve(D, b)) <= 1e-14
+
+
+def test_maxit_zero_zero_rhs_and_converged_guess():
+    A = poisson2d(20)
+    b, xs = problem(A)
+    x, info = Solver(A, max_iter=0).solve(dev(b))
+    assert info["status"] == ppcg.NOT_CONVERGED and info["iters"] == 0 and np.all(host(x) == 0)
+    x, info = Solver(A).solve(dev(np.zeros(A.n)))
+    assert info["status"] == ppcg.OK and info["iters"] == 0 and np.all(host(x) == 0)
+    bx = oracle.spmv(A, xs)
+    x, info = Solver(A, tol=1e-12).solve(dev(bx), x0=dev(xs))
+    assert info["iters"] == 0 and np.array_equal(host(x), xs)
+
+
+def test_tol_zero_runs_to_maxit():
+    A = poisson2d(16)
+    b, _ = problem(A)
+    x, info = Solver(A, tol=0.0, max_iter=25).solve(dev(b))
+    ref = oracle.pipecg(A, b, tol=0.0, maxit=25)
+    assert info["status"] == ref.status
+    assert info["iters"] == ref.iters
+
+
+def test_x0_aliases_x_and_nonzero_initial_guess():
+    A = random_spd(2000, seed=5)
+    b, _ = problem(A)
+    g = xstar_uniform(A.n, 11) * 0.5
+    S = Solver(A, fixed_iters=15)
+    xt = dev(g)
+    x, _ = S.solve(dev(b), x0=xt, out=xt)
+    ref = oracle.pipecg(A, b, x0=g, fixed_iters=15)
+    assert relerr(host(x), ref.x) <= 1e-10
+
+
+def test_host_vectors_and_device_csr():
+    import torch
+
+    A = poisson2d(30)
+    b, _ = problem(A)
+    S = Solver(A, fixed_iters=20, vec_mem="host")
+    xh = torch.zeros(A.n, dtype=torch.float64)
+    S.solve(torch.as_tensor(b), out=xh)
+    ref = oracle.pipecg(A, b, fixed_iters=20)
+    assert relerr(xh.numpy(), ref.x) <= 1e-10
+    Ad = (dev(A.rp).to(torch.int32), dev(A.ci).to(torch.int32), dev(A.val))
+    S2 = Solver(Ad, fixed_iters=20)
+    x2, _ = S2.solve(dev(b))
+    assert np.array_equal(host(x2), xh.numpy())
+
+
+def _bad(A, **edit):
+    rp, ci, val = A.rp.copy(), A.ci.copy(), A.val.copy()
+    if "rp" in edit:
+        rp = edit["rp"](rp)
+    if "ci" in edit:
+        ci = edit["ci"](ci)
+    if "val" in edit:
+        val = edit["val"](val)
+    return CSR(A.n, rp, ci, val)
+
+
+@pytest.mark.parametrize("what", ["diag_missing", "diag_negative", "col_range", "col_order", "rp0", "nan"])
+def test_bad_csr_rejected(what):
+    A = poisson2d(6)
+    if what == "diag_missing":
+        # replace row 0's diagonal column by a duplicate-free off-diagonal slot
+        B = _bad(A, ci=lambda c: np.where(np.arange(c.size) == 0, 2, c))
+    elif what == "diag_negative":
+        B = _bad(A, val=lambda v: np.where(v == 4.0, -4.0, v))
+    elif what == "col_range":
+        B = _bad(A, ci=lambda c: np.where(np.arange(c.size) == 5, A.n + 3, c))
+    elif what == "col_order":
+        B = _bad(A, ci=lambda c: np.concatenate([[c[1], c[0]], c[2:]]))
+    elif what == "rp0":
+        B = _bad(A, rp=lambda r: np.concatenate([[1], r[1:]]).astype(np.int32))
+    else:
+        B = _bad(A, val=lambda v: np.where(np.arange(v.size) == 7, np.nan, v))
+    with pytest.raises(PPCGError) as e:
+        Solver(B)
+    assert e.value.status == ppcg.ERR_BAD_CSR
+
+
+def test_indefinite_matrix_breaks_down():
+    D = np.array([[1.0, 2.0], [2.0, 1.0]])
+    A = CSR(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), D.ravel())
+    x, info = Solver(A).solve(dev([1.0, -1.0]))
+    assert info["status"] == ppcg.BREAKDOWN
+
+
+def test_kernel_timing_entry_point():
+    A = poisson3d(48)
+    b, _ = problem(A)
+    tv, ts = Solver(A).time_kernels(dev(b), iters=10)
+    assert tv > 0 and ts > 0
+
+
+# ---------------------------------------------------------------- batching
+
+def _batch_systems():
+    mats = [shifted(poisson2d(s), h) for s, h in [(33, 0.01), (64, 0.2), (17, 0.0), (90, 0.05)]]
+    mats += [random_spd(3001, seed=8), poisson3d(21)]
+    return mats
+
+
+def test_batch_results_bitwise_equal_solo():
+    mats = _batch_systems()
+    bs = [problem(A, seed=20 + i)[0] for i, A in enumerate(mats)]
+    solo = []
+    for A, b in zip(mats, bs):
+        x, info = Solver(A, tol=1e-10).solve(dev(b))
+        solo.append((host(x), info))
+    solvers = [Solver(A, tol=1e-10) for A in mats]
+    xs, infos = solve_batch(solvers, [dev(b) for b in bs])
+    for (xs_, is_), x, info, A, b in zip(solo, xs, infos, mats, bs):
+        assert np.array_equal(host(x), xs_), A.name
+        assert info["iters"] == is_["iters"]
+        assert info["status"] == ppcg.OK
+        assert info["rel_resid_true"] <= 1e-10
+        ref = oracle.pipecg(A, b, tol=1e-10)
+        assert abs(info["iters"] - ref.iters) <= 2
+
+
+def test_batch_c4_subset_against_oracle():
+    spec = [s for s in batch_c4(seed=0)][:12]
+    mats = [shifted(poisson2d(min(side, 96)), sh) for side, sh in spec]
+    bs = [problem(A, seed=100 + i)[0] for i, A in enumerate(mats)]
+    solvers = [Solver(A, tol=1e-10) for A in mats]
+    xs, infos = solve_batch(solvers, [dev(b) for b in bs])
+    for A, b, x, info in zip(mats, bs, xs, infos):
+        assert info["status"] == ppcg.OK
+        assert oracle.true_relres(A, b, host(x)) <= 1e-10
+        ref = oracle.pipecg(A, b, tol=1e-10)
+        assert abs(info["iters"] - ref.iters) <= 2
+
+
+def test_batch_fixed_iterates_match_oracle():
+    mats = _batch_systems()
+    bs = [problem(A, seed=40 + i)[0] for i, A in enumerate(mats)]
+    solvers = [Solver(A, fixed_iters=25) for A in mats]
+    xs, infos = solve_batch(solvers, [dev(b) for b in bs])
+    for A, b, x in zip(mats, bs, xs):
+        assert relerr(host(x), oracle.pipecg(A, b, fixed_iters=25).x) <= 1e-10
+
+
+# ---------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("gen", [lambda: stencil27_lognormal(16, seed=1), lambda: poisson2d(64),
+                                 lambda: random_spd(20000, seed=3)])
+def test_mixed_precision_reaches_fp64_tolerance(gen):
+    A = gen()
+    b, xs = problem(A)
+    S = Solver(A, tol=1e-10, precision="mixed")
+    x, info = S.solve(dev(b))
+    assert info["status"] == ppcg.OK, info
+    assert info["outer_iters"] >= 1
+    assert info["rel_resid_true"] <= 1e-10
+    assert oracle.true_relres(A, b, host(x)) <= 1e-10
+    ref = oracle.pipecg(A, b, tol=1e-10)
+    # both solutions satisfy the same residual bound; their distance is bounded
+    # by the conditioning times the tolerance
+    assert relerr(host(x), ref.x) <= 1e-5
+
+
+# ---------------------------------------------------------------- serving
+
+def _serve_all(srv, reqs, stagger=2):
+    """Submit requests a few at a time between steps; return id -> result."""
+    ids = {}
+    pending = list(reqs)
+    results = {}
+    while pending or len(results) < len(ids):
+        for _ in range(stagger):
+            if pending:
+                key, A, b, tol, prec = pending.pop(0)
+                ids[srv.submit(A, b, tol, prec)] = key
+        srv.step()
+        for rid, key in list(ids.items()):
+            if key in results:
+                continue
+            r = srv.poll(rid)
+            if r is not None:
+                results[key] = r
+    return results
+
+
+def test_server_result_same_alone_and_in_mix():
+    A = poisson3d(20)
+    b, _ = problem(A, 3)
+    alone = _serve_all(Server(), [("R", A, b, 1e-10, "fp64")])["R"]
+    mix = [("m0", random_spd(4000, seed=1), problem(random_spd(4000, seed=1))[0], 1e-8, "fp64"),
+           ("R", A, b, 1e-10, "fp64"),
+           ("m1", poisson2d(50), problem(poisson2d(50))[0], 1e-6, "fp64"),
+           ("m2", stencil27_lognormal(10, seed=2), problem(stencil27_lognormal(10, seed=2))[0], 1e-10, "mixed"),
+           ("m3", poisson2d(120), problem(poisson2d(120))[0], 1e-10, "fp64")]
+    res = _serve_all(Server(), mix, stagger=1)
+    assert np.array_equal(res["R"][0], alone[0])
+    assert res["R"][1]["iters"] == alone[1]["iters"]
+    for key, Am, bm, tol, prec in mix:
+        assert res[key][1]["status"] == ppcg.OK
+        assert oracle.true_relres(Am, bm, res[key][0]) <= tol
+    # the served result equals a direct solve of the same request
+    x, info = Solver(A, tol=1e-10).solve(dev(b))
+    assert np.array_equal(host(x), alone[0])
+
+
+def test_server_refuses_over_budget_and_admits_in_turn():
+    A = poisson2d(100)
+    b, _ = problem(A)
+    fp = ppcg.footprint_bytes(A.n, A.nnz)
+    srv = Server(budget_bytes=1.5 * fp)
+    big = poisson2d(200)
+    with pytest.raises(PPCGError) as e:
+        srv.submit(big, problem(big)[0], 1e-8)
+    assert e.value.status == ppcg.ERR_BUDGET
+    res = _serve_all(srv, [(f"r{i}", A, b, 1e-8, "fp64") for i in range(4)], stagger=4)
+    assert len(res) == 4
+    xs = [res[f"r{i}"][0] for i in range(4)]
+    for x in xs[1:]:
+        assert np.array_equal(x, xs[0])
