@@ -175,8 +175,8 @@ def leg_c3(torch, ppcg, wl):
     bd = torch.as_tensor(b).cuda()
     out = {"workload": "3D 27-point lognormal 160^3 (N=4096000), shift 1e-3, tol 1e-10", "nnz": A.nnz}
     xs = {}
-    for prec in ("fp64", "mixed"):
-        S = ppcg.Solver(A, tol=1e-10, precision=prec, max_iter=20000)
+    for prec in ("fp64", "mixed", "mixed_values"):
+        S = ppcg.Solver(A, tol=1e-10, precision=prec, max_iter=20000, spmv_format="sell")
         S.solve(bd)  # warm-up (graph capture, FP32 copy)
         sync()
         t0 = time.perf_counter()
@@ -189,9 +189,10 @@ def leg_c3(torch, ppcg, wl):
                      "time_s": round(t, 4), "solves_per_s": round(1 / t, 3)}
         log(f"27-pt {prec}: {info}")
         S.close()
-    out["mixed_vs_fp64_solution_rel_diff"] = float(np.linalg.norm(xs["mixed"] - xs["fp64"]) /
-                                                   np.linalg.norm(xs["fp64"]))
-    out["mixed_speedup"] = round(out["fp64"]["time_s"] / out["mixed"]["time_s"], 3)
+    for prec in ("mixed", "mixed_values"):
+        out[prec]["solution_rel_diff_vs_fp64"] = float(np.linalg.norm(xs[prec] - xs["fp64"]) /
+                                                       np.linalg.norm(xs["fp64"]))
+        out[prec]["speedup_vs_fp64"] = round(out["fp64"]["time_s"] / out[prec]["time_s"], 3)
     return out
 
 
@@ -248,7 +249,7 @@ def _serve_requests(wl, n_req, seed=0):
         else:
             A = wl.random_spd(max(64, int(N)), seed=int(rng.integers(1 << 30)))
         b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 2000 + i))
-        prec = "mixed" if tol >= 1e-8 else "fp64"
+        prec = "mixed_values" if tol >= 1e-8 else "fp64"
         reqs.append((A, b, tol, prec))
     return reqs
 
@@ -286,7 +287,7 @@ def leg_c5(ppcg, wl, n_req):
     total, lat = _run_server(ppcg, reqs, np.zeros(n_req))  # saturation: all at t = 0
     sat = n_req / total
     out = {"workload": f"{n_req} requests: 40% 2D 5-pt, 30% 3D 7-pt, 30% random SPD, N log-uniform [1e3,4e6], "
-                       "tol {1e-6,1e-8,1e-10}; FP32-inner+FP64-refinement for tol >= 1e-8",
+                       "tol {1e-6,1e-8,1e-10}; FP32 values + FP64 reliable updates for tol >= 1e-8",
            "saturation_solves_per_s": round(sat, 2)}
     rng = np.random.default_rng(0)
     for frac in (0.5, 0.8):
@@ -309,6 +310,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--legs", default="c1,c3,c4,c5", help="extra legs: c1,c3,c4,c5 or none")
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain device copy of 256 MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this library runs on one GPU; multi-GPU runs are not supported "
@@ -323,6 +326,20 @@ def main():
     ppcg.lib()
     torch.cuda.set_device(0)
     log(f"device: {torch.cuda.get_device_name(0)}")
+    copy_gbs = None
+    if args.copy_calibration:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            c.copy_(a)
+        sync()
+        copy_gbs = 2 * a.numel() * 8 * 10 / (time.perf_counter() - t0) / 1e9
+        log(f"copy calibration: 256 MiB copies at {copy_gbs:.0f} GB/s")
+        del a, c
     c2 = leg_c2(args, torch, ppcg, wl, oracle)
     legs = {}
     wanted = [x for x in args.legs.split(",") if x and x != "none"]
@@ -352,6 +369,8 @@ def main():
         "effective_gbs": round(c2["gbs"], 1), "pct_peak_hbm": round(100 * c2["gbs"] / PEAK_HBM_GBS, 2),
         "roofline": c2["roofline"], "tol_1e-10": c2["tol_run"],
     }
+    if copy_gbs is not None:
+        line["copy_256MiB_gbs"] = round(copy_gbs, 1)
     if "cpu_baseline" in c2:
         line["cpu_baseline"] = c2["cpu_baseline"]
         line["parity_x_k"] = c2["parity_x_k"]

@@ -60,10 +60,16 @@ typedef enum {
 } ppcg_stop;
 
 typedef enum {
-    PPCG_FP64 = 0,       /* every vector, matrix value and scalar in FP64 */
-    PPCG_MIXED_FP32 = 1  /* inner PIPECG with FP32 matrix values and vectors, FP64 dot
-                            products and scalars, inside an FP64 iterative-refinement
-                            loop on the FP64 operator */
+    PPCG_FP64 = 0,        /* every vector, matrix value and scalar in FP64 */
+    PPCG_MIXED_FP32 = 1,  /* inner PIPECG with FP32 matrix values and vectors, FP64 dot
+                             products and scalars, restarted inside an FP64
+                             iterative-refinement loop on the FP64 operator */
+    PPCG_MIXED_FP32_VALUES = 2 /* one PIPECG sequence whose SpMVs read FP32 matrix values
+                             (FP64 vectors, FP64 accumulation, FP64 dots and scalars),
+                             with reliable updates: whenever the residual has dropped by
+                             inner_tol (default 1e-3) the FP64 residual b - A x is
+                             recomputed with the FP64 values and the pipelined
+                             auxiliary vectors are rebuilt from it */
 } ppcg_precision;
 
 typedef enum { PPCG_MEM_DEVICE = 0, PPCG_MEM_HOST = 1 } ppcg_mem;
@@ -105,9 +111,11 @@ typedef struct {
     ppcg_mem vec_mem;        /* where b, x0 and x live (default PPCG_MEM_DEVICE) */
     ppcg_spmv_format spmv_format; /* default PPCG_SPMV_AUTO */
     int32_t graph_iters;     /* iterations per captured HIP graph; 0 = automatic */
-    double inner_tol;        /* mixed precision: relative reduction asked of each inner
-                                solve (0 = automatic) */
-    int32_t max_outer;       /* mixed precision: maximum refinement steps (default 30) */
+    double inner_tol;        /* PPCG_MIXED_FP32: relative reduction asked of each inner
+                                solve; PPCG_MIXED_FP32_VALUES: residual reduction between
+                                reliable updates (0 = automatic) */
+    int32_t max_outer;       /* mixed precision: maximum refinement steps / reliable
+                                updates (default 30) */
     uint32_t flags;          /* reserved, must be 0 */
 } ppcg_options;
 
@@ -117,7 +125,8 @@ typedef struct {
     ppcg_status status;
     int32_t iters;           /* PIPECG iterations (x-updates); total inner iterations in
                                 mixed precision */
-    int32_t outer_iters;     /* refinement steps (mixed precision), else 0 */
+    int32_t outer_iters;     /* refinement steps (PPCG_MIXED_FP32) or reliable updates
+                                (PPCG_MIXED_FP32_VALUES), else 0 */
     int32_t restarts;        /* restarts from x (true residual above tol, or breakdown) */
     double rel_resid_true;   /* ||b - A x||_2 / ||b||_2 in FP64 at exit */
     double rel_resid_recur;  /* sqrt((r,r)) / ||b|| of the recurrence at exit */

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -81,6 +82,7 @@ struct ppcg_handle {
     int *col = nullptr;
     int *perm = nullptr, *invperm = nullptr;
     double *val64 = nullptr;  // FP64 values in the stored format
+    float *val32 = nullptr;   // FP32 copy of the stored values (mixed modes)
     double *dinv64 = nullptr;
     ppcg::DevArena mat_arena;
     ppcg::PrecData f64, f32;
@@ -101,7 +103,8 @@ namespace ppcg {
 // One solve in progress inside an engine.
 struct Job {
     ppcg_handle *h = nullptr;
-    int mixed = 0;          // 1: FP32 inner PIPECG + FP64 refinement
+    int mixed = 0;          // 0 FP64, 1 FP32 inner PIPECG + FP64 refinement,
+                            // 2 FP32 values + reliable updates (MixKind)
     int slot64 = -1;        // slot in the FP64 group (always)
     int slot32 = -1;        // slot in the FP32 group (mixed only)
     int stage = 0;          // JobStage
@@ -115,14 +118,22 @@ struct Job {
     double rel_true = 0.0, rel_recur = 0.0, precond_norm = 0.0;
     double bnorm2 = 0.0;
     int iters = 0;
+    // convergence tracking for choosing graph chunk lengths
+    double last_norm = -1.0;
+    int last_iter = 0;
+    // MIX_VALUES32: residual norm right after the last replacement (-1: unknown)
+    double repl_ref = -1.0;
 };
 
+enum MixKind { MIX_NONE = 0, MIX_INNER32 = 1, MIX_VALUES32 = 2 };
+
 enum JobStage {
-    JS_NEED_INIT = 0,   // FP64: run the initialisation, then iterate
+    JS_NEED_INIT = 0,   // FP64 group: run the initialisation, then iterate
     JS_ITER = 1,        // iterating in the group's table
-    JS_NEED_FINAL = 2,  // FP64: true residual, then restart or finish
-    JS_OUTER = 3,       // mixed: true residual of x, then finish or start an inner solve
-    JS_DONE = 4
+    JS_NEED_FINAL = 2,  // FP64 group: true residual, then restart / replace or finish
+    JS_OUTER = 3,       // MIX_INNER32: true residual of x, then finish or start an inner solve
+    JS_NEED_REPL = 4,   // MIX_VALUES32: residual replacement (reliable update)
+    JS_DONE = 5
 };
 
 // Per-precision set of system slots, work table and captured graph.
@@ -145,9 +156,13 @@ struct Group {
     int stage_cap = 0;
     std::vector<WorkItem> table_h;  // current iteration table
     bool table_dirty = true;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int g_grid = 0, g_iters = 0;
+    // Captured graphs of K iterations (K a power of two), all for grid g_grid.
+    struct CapturedGraph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::map<int, CapturedGraph> graphs;
+    int g_grid = 0;
 };
 
 class Engine {
@@ -168,14 +183,16 @@ class Engine {
     // Release every job and forget them.
     void reset();
     hipStream_t stream() const { return stream_; }
-    int remap = 1;
+    int remap = PPCG_XCD_REMAP;
 
   private:
     ppcg_status ensure_group(Group &g, int prec, int cap_sys);
     ppcg_status upload_desc(Group &g, int slot);
     ppcg_status aux_launch(Group &g, const std::vector<int> &slots, int what);
     ppcg_status ensure_table(Group &g);
-    ppcg_status ensure_graph(Group &g, int iters);
+    ppcg_status ensure_graph(Group &g, int iters, hipGraphExec_t *exec);
+    void drop_graphs(Group &g);
+    int chunk_iters(const Group &g, int max_iters);
     ppcg_status sync_states(Group &g);
     int alloc_slot(Group &g);
     hipStream_t stream_;
@@ -184,7 +201,7 @@ class Engine {
 };
 
 // Aux operations run over a subset of slots.
-enum AuxOp { AUX_INIT = 0, AUX_RESID = 1, AUX_MIX_START = 2, AUX_MIX_CORRECT = 3 };
+enum AuxOp { AUX_INIT = 0, AUX_RESID = 1, AUX_MIX_START = 2, AUX_MIX_CORRECT = 3, AUX_REPL = 4 };
 
 double now_ms();
 int auto_graph_iters(const ppcg_handle *h);
@@ -195,7 +212,8 @@ void fill_info(const ppcg_handle *h, const Job &j, ppcg_info *info);
 ppcg_status wait_user(ppcg_handle *h);
 ppcg_status run_engine(Engine &E, int graph_iters);
 ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double tol, int fixed, int maxit,
-                      int stop);
+                      int stop, int vals32 = 0);
 ppcg_status ensure_f32(ppcg_handle *h);
+ppcg_status ensure_val32(ppcg_handle *h);
 
 }  // namespace ppcg

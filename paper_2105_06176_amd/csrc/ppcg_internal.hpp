@@ -17,14 +17,25 @@ namespace ppcg {
 
 constexpr int kTileRows = 512;     // rows per work item (both kernels)
 constexpr int kVmaThreads = 256;   // fused update kernel: 2 rows per thread
-constexpr int kSpmvThreads = 512;  // SpMV kernel: 8 wavefronts
+constexpr int kSpmvThreads = 512;  // SpMV kernel: 8 wavefronts, one row per lane (SELL)
 constexpr int kSellC = 64;         // SELL chunk height = wavefront width
 constexpr int kSellChunksPerTile = kTileRows / kSellC;
 constexpr int kSortWindow = 1024;  // SELL sigma when sorting is used
 constexpr int kNumPartials = 4;    // (r,u), (w,u), (u,u), (r,r)
+constexpr int kPartStride = 8;     // doubles per tile partial record (replacement uses 6)
+
+// Tile-to-workgroup mapping.  The fused update is a pure stream and runs
+// slightly faster with each XCD owning a contiguous range of tiles; the SpMV
+// measured slightly faster with the plain round-robin mapping.
+#ifndef PPCG_XCD_REMAP
+#define PPCG_XCD_REMAP 1
+#endif
+#ifndef PPCG_XCD_REMAP_SPMV
+#define PPCG_XCD_REMAP_SPMV 0
+#endif
 
 enum Fmt : int { FMT_SELL = 1, FMT_CSRV = 2 };
-enum Prec : int { PREC_F64 = 0, PREC_F32 = 1 };
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_V32 = 2 /* FP32 values, FP64 vectors */ };
 
 // Status codes mirrored from ppcg.h (device code does not include it).
 enum DevStatus : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_STAGNATED = 3 };
@@ -42,6 +53,7 @@ struct alignas(128) SysState {
     double beta;        // beta_i used by the next fused update
     double gamma_prev;  // gamma_{i-1}
     double alpha_prev;  // alpha_{i-1}
+    double gamma_prev2; // gamma_{i-1} as it was before the last scalar update
     double bnorm2;      // (b, b)
     double tnorm2;      // (b - A x, b - A x) from the last true-residual pass
     int iter;           // x-updates so far (all starts)
@@ -52,6 +64,7 @@ struct alignas(128) SysState {
     int gen;            // incremented by every reduction (debug / polling aid)
     int pad[2];
 };
+static_assert(sizeof(SysState) == 128, "SysState is one 128-byte record");
 
 // Per-system descriptor (device-resident copy per engine slot).
 struct SysDesc {
@@ -64,16 +77,17 @@ struct SysDesc {
     int fixed;          // > 0: fixed number of iterations
     int prec;           // Prec of the vectors and values below
     int pair;           // mixed precision: slot of the same system in the other group
-    int pad_;
+    int vals32;         // 1: iteration SpMVs read the FP32 copy of the values (val32)
     double tol;
     const int64_t *cptr;  // SELL chunk offsets [nchunks + 1]
     const int *rp;        // CSR row pointers [n + 1] (CSR-vector format)
     const int *col;       // SELL / CSR column indices
     const void *val;      // matrix values (double or float)
+    const float *val32;   // FP32 copy of the values (vals32 mode)
     const void *dinv;     // inverse diagonal (double or float)
     void *x, *r, *u, *w, *m, *nv, *z, *q, *s, *p;  // solver vectors
     const void *b;        // right-hand side (internal copy)
-    double *part;         // partial sums: 2 slots x ntiles x 4
+    double *part;         // partial sums: 2 slots x ntiles x kPartStride
     SysState *st;
 };
 

@@ -33,12 +33,22 @@ enum SpmvMode : int {
     MODE_INIT1 = 1,  // r = b - A x; u = M^-1 r; partial (b,b); reset the state
     MODE_INIT2 = 2,  // w = A u; m = M^-1 w; partials (r,u),(w,u),(u,u),(r,r); reduce (b,b)
     MODE_RESID = 3,  // r = b - A x; partials (r,r), (b,b)
-    MODE_PLAIN = 4   // nv = A x (timing only)
+    MODE_PLAIN = 4,  // nv = A x (timing only)
+    // Residual replacement (reliable update) against the FP64 operator:
+    MODE_REPL1 = 5,  // r = b - A x (FP64 values); u = M^-1 r
+    MODE_DUAL1 = 6,  // w = A u and s = A p in one pass; m = M^-1 w; q = M^-1 s;
+                     // partials (r,u),(w,u),(u,u),(r,r),(u,s),(p,s)
+    MODE_DUAL2 = 7   // nv = A m and z = A q in one pass; reduce; scalars with the
+                     // exact alpha denominator
 };
 
+constexpr int kReplPartials = 6;
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
 template <typename T> struct Vec2;
-template <> struct Vec2<double> { using type = double2; };
-template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = dvec2; };
+template <> struct Vec2<float> { using type = fvec2; };
 
 // Map the hardware workgroup id to a table position so that each of the 8
 // XCDs (which receive workgroups round-robin) works on a contiguous range of
@@ -87,20 +97,32 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* [NT/64
 
 // Reduce slot `slot` of a system's partials (ntiles x 4) in a fixed order.
 // Every thread of the workgroup must call it; result valid in thread 0.
-template <int NT>
-__device__ __forceinline__ void reduce_partials(const SysDesc &d, int slot, double (&out)[kNumPartials],
-                                                double *lds)
+template <int NT, int NV = kNumPartials>
+__device__ __forceinline__ void reduce_partials(const SysDesc &d, int slot, double (&out)[NV], double *lds)
 {
-    const double *P = d.part + (size_t)slot * d.ntiles * kNumPartials;
+    const double *P = d.part + (size_t)slot * d.ntiles * kPartStride;
 #pragma unroll
-    for (int k = 0; k < kNumPartials; ++k)
+    for (int k = 0; k < NV; ++k)
         out[k] = 0.0;
-    for (int t = threadIdx.x; t < d.ntiles; t += NT) {
+    // Batches of 2 tiles per thread: loads first, then the sums in tile order.
+    for (int t0 = threadIdx.x; t0 < d.ntiles; t0 += 2 * NT) {
+        double v[2][NV];
 #pragma unroll
-        for (int k = 0; k < kNumPartials; ++k)
-            out[k] = out[k] + P[t * kNumPartials + k];
+        for (int j = 0; j < 2; ++j) {
+            const int t = t0 + j * NT;
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                v[j][k] = t < d.ntiles ? P[(size_t)t * kPartStride + k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (t0 + j * NT < d.ntiles) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k)
+                    out[k] = out[k] + v[j][k];
+            }
     }
-    block_sum<NT, kNumPartials>(out, lds);
+    block_sum<NT, NV>(out, lds);
 }
 
 // Scalar recurrences and stopping test, executed by one thread per system
@@ -119,6 +141,7 @@ __device__ inline void scalar_update(const SysDesc &d, SysState *st, const doubl
         st->i_start += 1;
     }
     st->gen += 1;
+    st->gamma_prev2 = st->gamma_prev;
     const double g = v[0], dl = v[1], uu = v[2], rr = v[3];
     st->gamma = g;
     st->delta = dl;
@@ -161,6 +184,56 @@ __device__ inline void scalar_update(const SysDesc &d, SysState *st, const doubl
     st->alpha_prev = alpha;
 }
 
+// Scalars after a residual replacement.  r, u, w, m, n were recomputed from
+// the FP64 residual and s, q, z from the current direction p, so the
+// recurrence for alpha's denominator (p, A p) = delta - beta gamma /
+// alpha_{i-1} no longer holds exactly; it is evaluated directly instead:
+// with p' = u + beta p and A p' = w + beta s, and A symmetric,
+//   (p', A p') = (u, w) + 2 beta (u, s) + beta^2 (p, s).
+// The iteration counters do not move.
+__device__ inline void scalar_update_repl(const SysDesc &d, SysState *st, const double (&v)[kReplPartials])
+{
+    st->gen += 1;
+    const double g = v[0], dl = v[1], uu = v[2], rr = v[3], us = v[4], ps = v[5];
+    st->gamma = g;
+    st->delta = dl;
+    st->uu = uu;
+    st->rr = rr;
+    st->done = 0;
+    st->status = ST_OK;
+    bool conv;
+    if (d.fixed > 0)
+        conv = (st->iter >= d.fixed) || (g == 0.0);
+    else if (d.stop == STOP_ABS)
+        conv = sqrt(uu) < d.tol;
+    else
+        conv = sqrt(rr) <= d.tol * sqrt(st->bnorm2);
+    if (conv) {
+        st->done = 1;
+        return;
+    }
+    if (d.fixed <= 0 && st->iter >= d.maxit) {
+        st->done = 1;
+        st->status = ST_NOT_CONVERGED;
+        return;
+    }
+    double beta = 0.0, denom = dl;
+    if (st->i_start > 0) {
+        beta = g / st->gamma_prev2;
+        denom = dl + 2.0 * beta * us + beta * beta * ps;
+    }
+    const double alpha = g / denom;
+    if (!(g > 0.0) || !(denom > 0.0) || !isfinite(alpha) || !isfinite(beta)) {
+        st->done = 1;
+        st->status = ST_BREAKDOWN;
+        return;
+    }
+    st->alpha = alpha;
+    st->beta = beta;
+    st->gamma_prev = g;
+    st->alpha_prev = alpha;
+}
+
 // ---------------------------------------------------------------------------
 // Fused vector updates + Jacobi + dot-product partials.
 template <typename T>
@@ -181,6 +254,30 @@ __device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T m, T &q, T &w
     acc[1] = acc[1] + wd * ud;
     acc[2] = acc[2] + ud * ud;
     acc[3] = acc[3] + rd * rd;
+}
+
+#ifndef PPCG_VMA_NT
+#define PPCG_VMA_NT 0
+#endif
+
+template <typename V>
+__device__ __forceinline__ V vload(const V *p)
+{
+#if PPCG_VMA_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <typename V>
+__device__ __forceinline__ void vstore(V *p, V v)
+{
+#if PPCG_VMA_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
 }
 
 template <typename T>
@@ -214,22 +311,26 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     const int i = wi.tile * kTileRows + threadIdx.x * 2;
     using V2 = typename Vec2<T>::type;
     if (i + 1 < n) {
-        V2 nv = *(const V2 *)(NV + i), z = *(const V2 *)(Z + i), m = *(const V2 *)(M + i);
-        V2 q = *(const V2 *)(Q + i), w = *(const V2 *)(W + i), s = *(const V2 *)(S + i);
-        V2 u = *(const V2 *)(U + i), p = *(const V2 *)(P + i), x = *(const V2 *)(X + i);
-        V2 r = *(const V2 *)(R + i), di = *(const V2 *)(DI + i);
+        V2 nv = vload((const V2 *)(NV + i)), z = vload((const V2 *)(Z + i)), m = vload((const V2 *)(M + i));
+        V2 q = vload((const V2 *)(Q + i)), w = vload((const V2 *)(W + i)), s = vload((const V2 *)(S + i));
+        V2 u = vload((const V2 *)(U + i)), p = vload((const V2 *)(P + i)), x = vload((const V2 *)(X + i));
+        V2 r = vload((const V2 *)(R + i)), di = vload((const V2 *)(DI + i));
         V2 mo;
-        vma_elem<T>(sa, sb, nv.x, z.x, m.x, q.x, w.x, s.x, u.x, p.x, x.x, r.x, di.x, mo.x, acc);
-        vma_elem<T>(sa, sb, nv.y, z.y, m.y, q.y, w.y, s.y, u.y, p.y, x.y, r.y, di.y, mo.y, acc);
-        *(V2 *)(Z + i) = z;
-        *(V2 *)(Q + i) = q;
-        *(V2 *)(S + i) = s;
-        *(V2 *)(P + i) = p;
-        *(V2 *)(X + i) = x;
-        *(V2 *)(R + i) = r;
-        *(V2 *)(U + i) = u;
-        *(V2 *)(W + i) = w;
-        *(V2 *)(M + i) = mo;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            T zj = z[j], qj = q[j], wj = w[j], sj = s[j], uj = u[j], pj = p[j], xj = x[j], rj = r[j], mj;
+            vma_elem<T>(sa, sb, nv[j], zj, m[j], qj, wj, sj, uj, pj, xj, rj, di[j], mj, acc);
+            z[j] = zj; q[j] = qj; w[j] = wj; s[j] = sj; u[j] = uj; p[j] = pj; x[j] = xj; r[j] = rj; mo[j] = mj;
+        }
+        vstore((V2 *)(Z + i), z);
+        vstore((V2 *)(Q + i), q);
+        vstore((V2 *)(S + i), s);
+        vstore((V2 *)(P + i), p);
+        vstore((V2 *)(X + i), x);
+        vstore((V2 *)(R + i), r);
+        vstore((V2 *)(U + i), u);
+        vstore((V2 *)(W + i), w);
+        vstore((V2 *)(M + i), mo);
     } else if (i < n) {
         T z = Z[i], q = Q[i], w = W[i], s = S[i], u = U[i], p = P[i], x = X[i], r = R[i], mo;
         vma_elem<T>(sa, sb, NV[i], z, M[i], q, w, s, u, p, x, r, DI[i], mo, acc);
@@ -237,7 +338,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     }
     block_sum<kVmaThreads, kNumPartials>(acc, lds);
     if (threadIdx.x == 0) {
-        double *out = d.part + ((size_t)d.ntiles + wi.tile) * kNumPartials;  // slot 1
+        double *out = d.part + ((size_t)d.ntiles + wi.tile) * kPartStride;  // slot 1
 #pragma unroll
         for (int k = 0; k < kNumPartials; ++k)
             out[k] = acc[k];
@@ -247,138 +348,198 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
 // ---------------------------------------------------------------------------
 // SpMV row kernels.
 
-// SELL-C-sigma, C = 64, one lane per row, chunk-major storage: entry k of
-// row (chunk c, lane l) is at cptr[c] + k * 64 + l.  Rows are summed in
-// stored (ascending original column) order.
+#ifndef PPCG_SPMV_NT
+#define PPCG_SPMV_NT 1
+#endif
+
+// Matrix entries are read exactly once per SpMV: load them with the
+// non-temporal hint so they do not evict the reused input-vector lines.
 template <typename T>
-__device__ __forceinline__ T sell_row(const int64_t *__restrict__ cptr, const int *__restrict__ col,
-                                      const T *__restrict__ val, const T *__restrict__ xin, int chunk,
-                                      int lane)
+__device__ __forceinline__ T stream_load(const T *p)
 {
+#if PPCG_SPMV_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+// SELL-C-sigma, C = 64, one lane per row: entry k of the row (chunk c, lane
+// l) is at cptr[c] + k * 64 + l.  NX input vectors share one pass over the
+// matrix (NX = 2 for the replacement steps).  Entries are handled in
+// batches of 8: the column indices and values of a batch are loaded first,
+// then its gathers are issued, so each lane has up to 16 independent loads
+// in flight; the products of every row are still added in stored
+// (ascending original column) order.  VT is the value type, T the vector
+// and accumulation type.
+template <typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const int *__restrict__ col,
+                                         const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
+                                         int lane, T (&acc)[NX])
+{
+    constexpr int B = 8;
     const int64_t base = cptr[chunk];
     const int len = (int)((cptr[chunk + 1] - base) / kSellC);
     const int *c = col + base + lane;
-    const T *v = val + base + lane;
-    T acc = (T)0;
-#pragma unroll 4
-    for (int k = 0; k < len; ++k)
-        acc = acc + v[(size_t)k * kSellC] * xin[c[(size_t)k * kSellC]];
-    return acc;
+    const VT *v = val + base + lane;
+#pragma unroll
+    for (int q = 0; q < NX; ++q)
+        acc[q] = (T)0;
+    for (int k0 = 0; k0 < len; k0 += B) {
+        int cc[B];
+        VT vv[B];
+        // len is the same for every lane of the wavefront (one chunk), so
+        // these guards are uniform branches, not divergence.
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            cc[j] = 0;
+            vv[j] = (VT)0;
+            if (k0 + j < len) {
+                cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
+                vv[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NX; ++q) {
+            T xx[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                xx[j] = k0 + j < len ? xin[q][cc[j]] : (T)0;
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                if (k0 + j < len)
+                    acc[q] = acc[q] + (T)vv[j] * xx[j];
+        }
+    }
 }
 
-// Per-row epilogue of each mode.  Returns nothing; accumulates partials.
-template <typename T, int MODE>
-__device__ __forceinline__ void spmv_epilogue(const SysDesc &d, int i, T y, double (&acc)[kNumPartials])
+// CSR-vector: a group of L lanes per row (L a power of two in [2, 64]); lane
+// k of the group sums entries k, k + L, ... and the group combines its lanes
+// with a butterfly.  Result valid in every lane of the group.
+template <typename VT, typename T, int NX>
+__device__ __forceinline__ void csrv_row(const int *__restrict__ rp, const int *__restrict__ col,
+                                         const VT *__restrict__ val, const T *const (&xin)[NX], int i, int n, int L,
+                                         int l, T (&acc)[NX])
 {
-    if (MODE == MODE_ITER || MODE == MODE_PLAIN) {
-        ((T *)d.nv)[i] = y;
-    } else if (MODE == MODE_INIT1) {
+#pragma unroll
+    for (int q = 0; q < NX; ++q)
+        acc[q] = (T)0;
+    if (i < n) {
+        const int e = rp[i + 1];
+        for (int k = rp[i] + l; k < e; k += L) {
+            const T a = (T)stream_load(val + k);
+            const int cc = stream_load(col + k);
+#pragma unroll
+            for (int q = 0; q < NX; ++q)
+                acc[q] = acc[q] + a * xin[q][cc];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NX; ++q)
+        for (int off = L >> 1; off >= 1; off >>= 1)
+            acc[q] = acc[q] + __shfl_xor(acc[q], off, 64);
+}
+
+// Inputs of each mode.
+template <int MODE> struct SpmvIn { static constexpr int NX = 1; };
+template <> struct SpmvIn<MODE_DUAL1> { static constexpr int NX = 2; };
+template <> struct SpmvIn<MODE_DUAL2> { static constexpr int NX = 2; };
+
+template <typename T, int MODE>
+__device__ __forceinline__ void spmv_inputs(const SysDesc &d, const T *(&x)[SpmvIn<MODE>::NX])
+{
+    if constexpr (MODE == MODE_ITER) {
+        x[0] = (const T *)d.m;
+    } else if constexpr (MODE == MODE_INIT2) {
+        x[0] = (const T *)d.u;
+    } else if constexpr (MODE == MODE_DUAL1) {
+        x[0] = (const T *)d.u;
+        x[1] = (const T *)d.p;
+    } else if constexpr (MODE == MODE_DUAL2) {
+        x[0] = (const T *)d.m;
+        x[1] = (const T *)d.q;
+    } else {  // INIT1, RESID, PLAIN, REPL1
+        x[0] = (const T *)d.x;
+    }
+}
+
+// Modes that form a true residual b - A x always use the FP64 values; the
+// iteration's own products use the FP32 copy in vals32 mode.
+template <int MODE> constexpr bool kTrueOperator = MODE == MODE_INIT1 || MODE == MODE_RESID || MODE == MODE_REPL1;
+
+// Per-row epilogue of each mode; accumulates this row's share of the partials.
+template <typename T, int MODE>
+__device__ __forceinline__ void spmv_epilogue(const SysDesc &d, int i, const T (&y)[SpmvIn<MODE>::NX],
+                                              double (&acc)[kReplPartials])
+{
+    const T *DI = (const T *)d.dinv;
+    if constexpr (MODE == MODE_ITER || MODE == MODE_PLAIN) {
+        ((T *)d.nv)[i] = y[0];
+    } else if constexpr (MODE == MODE_INIT1 || MODE == MODE_REPL1) {
         const T bi = ((const T *)d.b)[i];
-        const T ri = bi - y;
-        const T ui = ((const T *)d.dinv)[i] * ri;
+        const T ri = bi - y[0];
+        const T ui = DI[i] * ri;
         ((T *)d.r)[i] = ri;
         ((T *)d.u)[i] = ui;
+        if constexpr (MODE == MODE_INIT1) {
+            // z, q, s, p enter the first update multiplied by beta = 0: start
+            // them at zero so that stale memory (possibly NaN) cannot leak in.
+            ((T *)d.z)[i] = (T)0;
+            ((T *)d.q)[i] = (T)0;
+            ((T *)d.s)[i] = (T)0;
+            ((T *)d.p)[i] = (T)0;
+        }
         acc[0] = acc[0] + (double)bi * (double)bi;
-    } else if (MODE == MODE_INIT2) {
+    } else if constexpr (MODE == MODE_INIT2) {
         const T ri = ((const T *)d.r)[i];
         const T ui = ((const T *)d.u)[i];
-        const T mi = ((const T *)d.dinv)[i] * y;
-        ((T *)d.w)[i] = y;
+        const T mi = DI[i] * y[0];
+        ((T *)d.w)[i] = y[0];
         ((T *)d.m)[i] = mi;
-        const double rd = (double)ri, ud = (double)ui, wd = (double)y;
+        const double rd = (double)ri, ud = (double)ui, wd = (double)y[0];
         acc[0] = acc[0] + rd * ud;
         acc[1] = acc[1] + wd * ud;
         acc[2] = acc[2] + ud * ud;
         acc[3] = acc[3] + rd * rd;
-    } else if (MODE == MODE_RESID) {
+    } else if constexpr (MODE == MODE_DUAL1) {
+        const T ri = ((const T *)d.r)[i];
+        const T ui = ((const T *)d.u)[i];
+        const T pi = ((const T *)d.p)[i];
+        ((T *)d.w)[i] = y[0];
+        ((T *)d.s)[i] = y[1];
+        ((T *)d.m)[i] = DI[i] * y[0];
+        ((T *)d.q)[i] = DI[i] * y[1];
+        const double rd = (double)ri, ud = (double)ui, wd = (double)y[0], sd = (double)y[1], pd = (double)pi;
+        acc[0] = acc[0] + rd * ud;
+        acc[1] = acc[1] + wd * ud;
+        acc[2] = acc[2] + ud * ud;
+        acc[3] = acc[3] + rd * rd;
+        acc[4] = acc[4] + ud * sd;
+        acc[5] = acc[5] + pd * sd;
+    } else if constexpr (MODE == MODE_DUAL2) {
+        ((T *)d.nv)[i] = y[0];
+        ((T *)d.z)[i] = y[1];
+    } else if constexpr (MODE == MODE_RESID) {
         const T bi = ((const T *)d.b)[i];
-        const T ti = bi - y;
+        const T ti = bi - y[0];
         ((T *)d.r)[i] = ti;
         acc[0] = acc[0] + (double)ti * (double)ti;
         acc[1] = acc[1] + (double)bi * (double)bi;
     }
 }
 
-template <int MODE> struct SpmvIO;
-template <> struct SpmvIO<MODE_ITER> { static __device__ const void *in(const SysDesc &d) { return d.m; } };
-template <> struct SpmvIO<MODE_PLAIN> { static __device__ const void *in(const SysDesc &d) { return d.x; } };
-template <> struct SpmvIO<MODE_INIT1> { static __device__ const void *in(const SysDesc &d) { return d.x; } };
-template <> struct SpmvIO<MODE_INIT2> { static __device__ const void *in(const SysDesc &d) { return d.u; } };
-template <> struct SpmvIO<MODE_RESID> { static __device__ const void *in(const SysDesc &d) { return d.x; } };
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv(const WorkItem *__restrict__ table,
-                                                       const int *__restrict__ count,
-                                                       const SysDesc *__restrict__ descs, int remap)
+// Work of the designated workgroup of a system after its SpMV tile: reduce
+// the partials of the previous launch and update the scalars.  Kept out of
+// line so that its registers do not add to the SpMV's register pressure.
+template <int MODE>
+__device__ __noinline__ void designated_reduce(const SysDesc &d, SysState *st, double *lds)
 {
-    __shared__ double lds[kSpmvThreads / 64 * kNumPartials];
-    const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (pos >= *count)
-        return;
-    const WorkItem wi = table[pos];
-    const SysDesc &d = descs[wi.slot];
-    SysState *st = d.st;
-    if (MODE == MODE_ITER && st->done)
-        return;
-    const T *__restrict__ xin = (const T *)SpmvIO<MODE>::in(d);
-    const T *__restrict__ val = (const T *)d.val;
-    const int n = d.n;
-    double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
-    if (d.fmt == FMT_SELL) {
-        const int lane = threadIdx.x & 63;
-        const int chunk = wi.tile * kSellChunksPerTile + (threadIdx.x >> 6);
-        const int i = chunk * kSellC + lane;
-        if (chunk * kSellC < n) {
-            const T y = sell_row<T>(d.cptr, d.col, val, xin, chunk, lane);
-            if (i < n)
-                spmv_epilogue<T, MODE>(d, i, y, acc);
-        }
+    if constexpr (MODE == MODE_DUAL2) {
+        double v[kReplPartials];
+        reduce_partials<kSpmvThreads, kReplPartials>(d, 1, v, lds);
+        if (threadIdx.x == 0)
+            scalar_update_repl(d, st, v);
     } else {
-        // CSR-vector: groups of L lanes per row, L a power of two in [2, 64];
-        // lane k of a group sums entries k, k + L, ...; the group then
-        // combines its lanes with a butterfly.
-        const int L = d.lanes;
-        const int g = threadIdx.x / L, l = threadIdx.x % L;
-        const int rows_per_pass = kSpmvThreads / L;
-        const int *__restrict__ rp = d.rp;
-        const int *__restrict__ col = d.col;
-        for (int pass = 0; pass < L; ++pass) {
-            const int i = wi.tile * kTileRows + pass * rows_per_pass + g;
-            T a = (T)0;
-            if (i < n) {
-                const int e = rp[i + 1];
-                for (int k = rp[i] + l; k < e; k += L)
-                    a = a + val[k] * xin[col[k]];
-            }
-            for (int off = L >> 1; off >= 1; off >>= 1)
-                a = a + __shfl_xor(a, off, 64);
-            if (l == 0 && i < n)
-                spmv_epilogue<T, MODE>(d, i, a, acc);
-        }
-    }
-    if (MODE == MODE_INIT1 || MODE == MODE_INIT2 || MODE == MODE_RESID) {
-        double v[kNumPartials] = {acc[0], acc[1], acc[2], acc[3]};
-        block_sum<kSpmvThreads, kNumPartials>(v, lds);
-        if (threadIdx.x == 0) {
-            const int slot = (MODE == MODE_INIT2) ? 1 : 0;
-            double *out = d.part + ((size_t)slot * d.ntiles + wi.tile) * kNumPartials;
-#pragma unroll
-            for (int k = 0; k < kNumPartials; ++k)
-                out[k] = v[k];
-        }
-    }
-    if (wi.tile != 0)
-        return;
-    // Designated workgroup of this system.
-    if (MODE == MODE_INIT1) {
-        if (threadIdx.x == 0) {
-            st->phase = 1;
-            st->i_start = 0;
-            st->done = 0;
-            st->status = ST_OK;
-        }
-    } else if (MODE == MODE_INIT2 || MODE == MODE_ITER) {
-        __syncthreads();  // lds reuse
         double v[kNumPartials];
         reduce_partials<kSpmvThreads>(d, MODE == MODE_INIT2 ? 0 : 1, v, lds);
         if (threadIdx.x == 0) {
@@ -387,6 +548,93 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(const WorkItem *__restric
             else
                 scalar_update(d, st, v);
         }
+    }
+}
+
+template <typename VT, typename T, int MODE>
+__device__ __forceinline__ void spmv_tile(const SysDesc &d, const VT *__restrict__ val, const WorkItem wi,
+                                          double (&acc)[kReplPartials])
+{
+    constexpr int NX = SpmvIn<MODE>::NX;
+    const T *xin[NX];
+    spmv_inputs<T, MODE>(d, xin);
+    const int n = d.n;
+    T y[NX];
+    if (d.fmt == FMT_SELL) {
+        static_assert(kTileRows == kSpmvThreads, "SELL path: one row per lane");
+        const int lane = threadIdx.x & 63;
+        const int chunk = wi.tile * kSellChunksPerTile + (threadIdx.x >> 6);
+        const int i = chunk * kSellC + lane;
+        if (chunk * kSellC < n) {
+            sell_row<VT, T, NX>(d.cptr, d.col, val, xin, chunk, lane, y);
+            if (i < n)
+                spmv_epilogue<T, MODE>(d, i, y, acc);
+        }
+    } else {
+        const int L = d.lanes;
+        const int g = threadIdx.x / L, l = threadIdx.x % L;
+        const int rows_per_pass = kSpmvThreads / L;
+        const int passes = kTileRows / rows_per_pass;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int i = wi.tile * kTileRows + pass * rows_per_pass + g;
+            csrv_row<VT, T, NX>(d.rp, d.col, val, xin, i, n, L, l, y);
+            if (l == 0 && i < n)
+                spmv_epilogue<T, MODE>(d, i, y, acc);
+        }
+    }
+}
+
+// Eight waves per SIMD (at most 64 VGPRs): the gathers depend on the column
+// loads, so latency is hidden by the number of waves in flight.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kSpmvThreads, 8) void k_spmv(const WorkItem *__restrict__ table,
+                                                          const int *__restrict__ count,
+                                                          const SysDesc *__restrict__ descs, int remap)
+{
+    __shared__ double lds[kSpmvThreads / 64 * kReplPartials];
+    const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (pos >= *count)
+        return;
+    const WorkItem wi = table[pos];
+    const SysDesc &d = descs[wi.slot];
+    SysState *st = d.st;
+    if (MODE == MODE_ITER && st->done)
+        return;
+    double acc[kReplPartials] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!kTrueOperator<MODE> && d.vals32)
+        spmv_tile<float, T, MODE>(d, d.val32, wi, acc);
+    else
+        spmv_tile<T, T, MODE>(d, (const T *)d.val, wi, acc);
+    constexpr bool kWritesPartials =
+        MODE == MODE_INIT1 || MODE == MODE_INIT2 || MODE == MODE_RESID || MODE == MODE_DUAL1;
+    if constexpr (kWritesPartials) {
+        constexpr int NV = MODE == MODE_DUAL1 ? kReplPartials : kNumPartials;
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            v[k] = acc[k];
+        block_sum<kSpmvThreads, NV>(v, lds);
+        if (threadIdx.x == 0) {
+            const int slot = (MODE == MODE_INIT2 || MODE == MODE_DUAL1) ? 1 : 0;
+            double *out = d.part + ((size_t)slot * d.ntiles + wi.tile) * kPartStride;
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                out[k] = v[k];
+        }
+    }
+    if (wi.tile != 0)
+        return;
+    // Designated workgroup of this system.
+    if constexpr (MODE == MODE_INIT1) {
+        if (threadIdx.x == 0) {
+            st->phase = 1;
+            st->i_start = 0;
+            st->done = 0;
+            st->status = ST_OK;
+        }
+    } else if constexpr (MODE == MODE_INIT2 || MODE == MODE_ITER || MODE == MODE_DUAL2) {
+        __syncthreads();  // lds reuse
+        designated_reduce<MODE>(d, st, lds);
     }
 }
 

@@ -5,6 +5,7 @@
 // Jacobi preconditioner (Section V-A), solving a sparse SPD system given in
 // CSR.  See ppcg_kernels.hpp for the kernels of one iteration.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -126,12 +127,13 @@ struct ByteModel {
 
 static ByteModel byte_model(const ppcg_handle *h, int prec)
 {
-    const double ve = prec == PREC_F64 ? 8.0 : 4.0;
+    const double ve = prec == PREC_F32 ? 4.0 : 8.0;   // vector element
+    const double me = prec == PREC_F64 ? 8.0 : 4.0;   // matrix value
     const double n = h->n;
     ByteModel bm;
     bm.vma = 20.0 * ve * n;
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
-    bm.spmv = (ve + 4.0) * (double)h->nnz + ptr + 2.0 * ve * n;
+    bm.spmv = (me + 4.0) * (double)h->nnz + ptr + 2.0 * ve * n;
     return bm;
 }
 
@@ -245,7 +247,7 @@ static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneVal> g_tune_cache;
 
 ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double tol, int fixed, int maxit,
-                      int stop)
+                      int stop, int vals32)
 {
     PrecData &pd = prec == PREC_F64 ? h->f64 : h->f32;
     if (!pd.ready) {
@@ -267,6 +269,12 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->rp = h->rp;
     d->col = h->col;
     d->val = pd.val;
+    d->val32 = h->val32;
+    d->vals32 = vals32;
+    if (vals32 && !h->val32) {
+        set_error("FP32 values not prepared");
+        return PPCG_ERR_INVALID_ARG;
+    }
     d->dinv = pd.dinv;
     d->x = pd.vec[VX];
     d->r = pd.vec[VR];
@@ -334,11 +342,11 @@ static ppcg_status time_spmv(ppcg_handle *h, int reps, double *ms)
     };
     PPCG_HIP_CLEAN(hipEventCreate(&e0), clean());
     PPCG_HIP_CLEAN(hipEventCreate(&e1), clean());
-    k_spmv<double, MODE_PLAIN><<<h->ntiles, kSpmvThreads, 0, s>>>(h->plain_tab, h->plain_cnt, h->plain_desc, 1);
+    k_spmv<double, MODE_PLAIN><<<h->ntiles, kSpmvThreads, 0, s>>>(h->plain_tab, h->plain_cnt, h->plain_desc, PPCG_XCD_REMAP_SPMV);
     PPCG_HIP_CLEAN(hipEventRecord(e0, s), clean());
     for (int i = 0; i < reps; ++i)
         k_spmv<double, MODE_PLAIN><<<h->ntiles, kSpmvThreads, 0, s>>>(h->plain_tab, h->plain_cnt, h->plain_desc,
-                                                                      1);
+                                                                      PPCG_XCD_REMAP_SPMV);
     PPCG_HIP_CLEAN(hipEventRecord(e1, s), clean());
     PPCG_HIP_CLEAN(hipEventSynchronize(e1), clean());
     float f = 0.f;
@@ -354,11 +362,13 @@ static void free_matrix(ppcg_handle *h)
     if (h->rp) (void)hipFree(h->rp);
     if (h->col) (void)hipFree(h->col);
     if (h->val64) (void)hipFree(h->val64);
+    if (h->val32) (void)hipFree(h->val32);
     if (h->perm) (void)hipFree(h->perm);
     if (h->invperm) (void)hipFree(h->invperm);
     h->cptr = nullptr;
     h->rp = h->col = h->perm = h->invperm = nullptr;
     h->val64 = nullptr;
+    h->val32 = nullptr;
 }
 
 static void adopt_sell(ppcg_handle *h, SellBuild &sb)
@@ -515,33 +525,45 @@ static ppcg_status alloc_f64_vectors(ppcg_handle *h)
 {
     const size_t n = (size_t)h->n;
     const size_t vb = aligned(n * sizeof(double));
-    const size_t pb = aligned((size_t)2 * h->ntiles * kNumPartials * sizeof(double));
+    const size_t pb = aligned((size_t)2 * h->ntiles * kPartStride * sizeof(double));
     PPCG_TRY(h->f64.arena.alloc(11 * vb + pb + 2 * 256));
     for (int k = 0; k < 11; ++k)
         h->f64.vec[k] = h->f64.arena.take(n * sizeof(double));
-    h->part = (double *)h->f64.arena.take((size_t)2 * h->ntiles * kNumPartials * sizeof(double));
+    h->part = (double *)h->f64.arena.take((size_t)2 * h->ntiles * kPartStride * sizeof(double));
     return PPCG_OK;
 }
 
-// FP32 copies for the mixed-precision inner solve.
+// FP32 copy of the stored matrix values (both mixed modes).
+ppcg_status ensure_val32(ppcg_handle *h)
+{
+    if (h->val32)
+        return PPCG_OK;
+    const size_t m = (size_t)std::max<int64_t>(h->nnz_stored, 1);
+    PPCG_HIP(hipMalloc(&h->val32, m * sizeof(float)));
+    k_convert<float, double><<<blocks_for((size_t)h->nnz_stored, 256), 256, 0, h->stream>>>(
+        (size_t)h->nnz_stored, h->val64, h->val32);
+    PPCG_HIP(hipGetLastError());
+    PPCG_HIP(hipStreamSynchronize(h->stream));
+    return PPCG_OK;
+}
+
+// FP32 vectors for the restarted mixed-precision inner solve.
 ppcg_status ensure_f32(ppcg_handle *h)
 {
     if (h->f32.ready)
         return PPCG_OK;
+    PPCG_TRY(ensure_val32(h));
     const size_t n = (size_t)h->n;
     const size_t vb = aligned(n * sizeof(float));
-    const size_t mb = aligned((size_t)std::max<int64_t>(h->nnz_stored, 1) * sizeof(float));
-    const size_t pb = aligned((size_t)2 * h->ntiles * kNumPartials * sizeof(double));
+    const size_t pb = aligned((size_t)2 * h->ntiles * kPartStride * sizeof(double));
     PrecData &pd = h->f32;
-    PPCG_TRY(pd.arena.alloc(12 * vb + mb + pb + 4 * 256));
+    PPCG_TRY(pd.arena.alloc(12 * vb + pb + 4 * 256));
     pd.prec = PREC_F32;
-    pd.val = pd.arena.take((size_t)std::max<int64_t>(h->nnz_stored, 1) * sizeof(float));
+    pd.val = h->val32;
     pd.dinv = pd.arena.take(n * sizeof(float));
     for (int k = 0; k < 11; ++k)
         pd.vec[k] = pd.arena.take(n * sizeof(float));
-    h->part32 = (double *)pd.arena.take((size_t)2 * h->ntiles * kNumPartials * sizeof(double));
-    k_convert<float, double><<<blocks_for((size_t)h->nnz_stored, 256), 256, 0, h->stream>>>(
-        (size_t)h->nnz_stored, h->val64, (float *)pd.val);
+    h->part32 = (double *)pd.arena.take((size_t)2 * h->ntiles * kPartStride * sizeof(double));
     k_convert<float, double><<<blocks_for(n, 256), 256, 0, h->stream>>>(n, h->dinv64, (float *)pd.dinv);
     PPCG_HIP(hipGetLastError());
     PPCG_HIP(hipStreamSynchronize(h->stream));
@@ -553,8 +575,7 @@ ppcg_status ensure_f32(ppcg_handle *h)
 Engine::~Engine()
 {
     for (Group *g : {&g64_, &g32_}) {
-        if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
-        if (g->graph) (void)hipGraphDestroy(g->graph);
+        drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
         if (g->st_d) (void)hipFree(g->st_d);
         if (g->st_h) (void)hipHostFree(g->st_h);
@@ -652,7 +673,7 @@ template <typename T>
 static void launch_iter_pair(hipStream_t s, const Group &g, int grid, int remap)
 {
     k_vma<T><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
-    k_spmv<T, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+    k_spmv<T, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
 }
 
 ppcg_status Engine::ensure_table(Group &g)
@@ -662,31 +683,39 @@ ppcg_status Engine::ensure_table(Group &g)
     PPCG_HIP(hipStreamSynchronize(stream_));  // table_d / staging may still be in use
     WorkItem *old = g.table_d;
     PPCG_TRY(grow_table(&g.table_d, &g.table_cap, (int)g.table_h.size()));
-    if (old != g.table_d && g.gexec) {  // graph baked the old pointer
-        (void)hipGraphExecDestroy(g.gexec);
-        (void)hipGraphDestroy(g.graph);
-        g.gexec = nullptr;
-        g.graph = nullptr;
-        g.g_grid = 0;
-    }
+    if (old != g.table_d)  // graphs baked the old pointer
+        drop_graphs(g);
     PPCG_TRY(upload_table(stream_, g, g.table_h, g.table_d, g.count_d, 0));
     g.table_dirty = false;
     return PPCG_OK;
 }
 
-ppcg_status Engine::ensure_graph(Group &g, int iters)
+void Engine::drop_graphs(Group &g)
 {
-    const int need = (int)g.table_h.size();
-    const bool ok = g.gexec && g.g_iters == iters && g.g_grid >= need && g.g_grid <= std::max(need * 4, 64);
-    if (ok)
-        return PPCG_OK;
-    if (g.gexec) {
-        (void)hipGraphExecDestroy(g.gexec);
-        (void)hipGraphDestroy(g.graph);
-        g.gexec = nullptr;
-        g.graph = nullptr;
+    for (auto &kv : g.graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
-    const int grid = std::min(g.table_cap, std::max(need, 1));
+    g.graphs.clear();
+    g.g_grid = 0;
+}
+
+// Graph of `iters` iterations over the group's table.  The grid is baked
+// into the graph; workgroups past the live table size exit at once, so a
+// graph stays valid while the table shrinks, and graphs are recaptured when
+// the table outgrows the grid or shrinks below a quarter of it.
+ppcg_status Engine::ensure_graph(Group &g, int iters, hipGraphExec_t *exec)
+{
+    const int need = std::max((int)g.table_h.size(), 1);
+    if (g.g_grid < need || g.g_grid > std::max(need * 4, 64))
+        drop_graphs(g);
+    auto it = g.graphs.find(iters);
+    if (it != g.graphs.end()) {
+        *exec = it->second.exec;
+        return PPCG_OK;
+    }
+    const int grid = g.g_grid ? g.g_grid : need;
+    Group::CapturedGraph cg;
     PPCG_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < iters; ++i) {
         if (g.prec == PREC_F64)
@@ -694,15 +723,54 @@ ppcg_status Engine::ensure_graph(Group &g, int iters)
         else
             launch_iter_pair<float>(stream_, g, grid, remap);
     }
-    hipError_t e = hipStreamEndCapture(stream_, &g.graph);
+    hipError_t e = hipStreamEndCapture(stream_, &cg.graph);
     if (e != hipSuccess) {
         set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
         return PPCG_ERR_DEVICE;
     }
-    PPCG_HIP(hipGraphInstantiate(&g.gexec, g.graph, nullptr, nullptr, 0));
+    e = hipGraphInstantiate(&cg.exec, cg.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(cg.graph);
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        return PPCG_ERR_DEVICE;
+    }
     g.g_grid = grid;
-    g.g_iters = iters;
+    g.graphs[iters] = cg;
+    *exec = cg.exec;
     return PPCG_OK;
+}
+
+// Iterations for the next chunk of a group: the most any of its iterating
+// jobs still needs (exact in fixed-iteration mode, predicted from the
+// observed convergence rate otherwise), capped at max_iters and rounded down
+// to a power of two so that few graphs are ever captured.
+int Engine::chunk_iters(const Group &g, int max_iters)
+{
+    int want = 1;
+    for (const Job &j : jobs_) {
+        if (j.finished || j.stage != JS_ITER)
+            continue;
+        const bool in_this = (&g == &g32_) == (j.mixed == MIX_INNER32);
+        if (!in_this)
+            continue;
+        const SysState &st = j.mixed == MIX_INNER32 ? g32_.st_h[j.slot32] : g64_.st_h[j.slot64];
+        const SysDesc &d = j.mixed == MIX_INNER32 ? g32_.desc_h[j.slot32] : g64_.desc_h[j.slot64];
+        int rem = max_iters;
+        if (d.fixed > 0) {
+            rem = d.fixed - (j.last_norm < 0 ? 0 : st.iter);
+        } else if (j.last_norm > 0 && st.iter > j.last_iter) {
+            const double cur = d.stop == STOP_ABS ? std::sqrt(st.uu) : std::sqrt(st.rr);
+            const double target = d.stop == STOP_ABS ? d.tol : d.tol * std::sqrt(st.bnorm2);
+            const double rate = std::pow(cur / j.last_norm, 1.0 / (st.iter - j.last_iter));
+            if (rate > 0.0 && rate < 0.9999 && cur > target && target > 0.0)
+                rem = (int)std::ceil(1.1 * std::log(target / cur) / std::log(rate)) + 1;
+        }
+        want = std::max(want, std::min(rem, max_iters));
+    }
+    int k = 1;
+    while (k * 2 <= want)
+        k *= 2;
+    return k;
 }
 
 ppcg_status Engine::sync_states(Group &g)
@@ -729,20 +797,26 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     hipStream_t s = stream_;
     if (what == AUX_INIT) {
         if (g.prec == PREC_F64) {
-            k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
-            k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
-            k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+            k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+            k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+            k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
         } else {
-            k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
-            k_spmv<float, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
-            k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+            k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+            k_spmv<float, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+            k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
         }
     } else if (what == AUX_RESID) {
         if (g.prec == PREC_F64)
-            k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+            k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
         else
-            k_spmv<float, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, remap);
+            k_spmv<float, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
         k_reduce_resid<<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d);
+    } else if (what == AUX_REPL) {
+        // Reliable update: FP64 residual, then the rebuilt auxiliaries (two
+        // dual-product passes with the iteration's values).
+        k_spmv<double, MODE_REPL1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        k_spmv<double, MODE_DUAL1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        k_spmv<double, MODE_DUAL2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
     } else if (what == AUX_MIX_START) {
         k_mix_start<<<grid, 256, 0, s>>>(g.aux_d, g.aux_count_d, g64_.desc_d, g32_.desc_d);
     } else if (what == AUX_MIX_CORRECT) {
@@ -766,9 +840,11 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
     }
     const ppcg_options &o = h->opt;
     const int stop = o.stop == PPCG_STOP_PRECOND_ABS ? STOP_ABS : STOP_REL;
+    if (mixed == MIX_VALUES32)
+        PPCG_TRY(ensure_val32(h));
     PPCG_TRY(fill_desc(h, PREC_F64, g64_.st_d + j.slot64, &g64_.desc_h[j.slot64], tol,
-                       mixed ? 0 : o.fixed_iters, o.max_iter, stop));
-    if (mixed) {
+                       mixed == MIX_INNER32 ? 0 : o.fixed_iters, o.max_iter, stop, mixed == MIX_VALUES32));
+    if (mixed == MIX_INNER32) {
         PPCG_TRY(ensure_f32(h));
         j.slot32 = alloc_slot(g32_);
         if (j.slot32 < 0) {
@@ -837,7 +913,7 @@ static void finish(Job &j, int status, const SysState &st)
     j.stage = JS_DONE;
     j.status = status;
     j.t_end = now_ms();
-    if (!j.mixed) {
+    if (j.mixed != MIX_INNER32) {
         j.iters = st.iter;
         j.bnorm2 = st.bnorm2;
         const double bn = std::sqrt(st.bnorm2);
@@ -876,7 +952,22 @@ ppcg_status Engine::step(int graph_iters)
             const double rel = bn > 0 ? std::sqrt(st.tnorm2) / bn : std::sqrt(st.tnorm2);
             j.rel_true = rel;
             const ppcg_options &o = j.h->opt;
-            if (j.stage == JS_NEED_FINAL) {
+            if (j.stage == JS_NEED_FINAL && j.mixed == MIX_VALUES32) {
+                // The recurrence follows the FP32-valued operator: a true
+                // residual above tol is fixed by a reliable update, not a restart.
+                const bool tol_mode = o.fixed_iters <= 0;
+                const bool bad = tol_mode && o.stop == PPCG_STOP_REL_RESID ? rel > j.tol : false;
+                const bool can_replace = tol_mode && j.outer < o.max_outer && st.iter < o.max_iter;
+                if ((st.status == ST_OK && bad) || (st.status == ST_BREAKDOWN && st.i_start > 0)) {
+                    if (can_replace) {
+                        j.stage = JS_NEED_REPL;
+                        continue;
+                    }
+                    finish(j, st.status == ST_OK ? PPCG_STAGNATED : st.status, st);
+                } else {
+                    finish(j, st.status, st);
+                }
+            } else if (j.stage == JS_NEED_FINAL) {
                 const bool tol_mode = o.fixed_iters <= 0;
                 const bool can_restart = tol_mode && j.restarts < o.max_restarts && st.iter < o.max_iter;
                 if (st.status == ST_OK && tol_mode && o.stop == PPCG_STOP_REL_RESID && rel > j.tol) {
@@ -921,21 +1012,34 @@ ppcg_status Engine::step(int graph_iters)
         if (!start_mix.empty()) {
             PPCG_TRY(aux_launch(g64_, start_mix, AUX_MIX_START));
             std::vector<int> s32;
-            for (int sl : start_mix)
+            for (int sl : start_mix) {
                 s32.push_back(g64_.desc_h[sl].pair);
+                // every inner solve counts its iterations from zero
+                PPCG_HIP(hipMemsetAsync(g32_.st_d + s32.back(), 0, sizeof(SysState), stream_));
+            }
             PPCG_TRY(aux_launch(g32_, s32, AUX_INIT));
         }
         (void)init64;
     }
-    // 2. initialisations of FP64 jobs.
+    // 2. initialisations and reliable updates of FP64-group jobs.
     {
-        std::vector<int> init64;
-        for (Job &j : jobs_)
-            if (!j.finished && j.stage == JS_NEED_INIT) {
+        std::vector<int> init64, repl64;
+        for (Job &j : jobs_) {
+            if (j.finished)
+                continue;
+            if (j.stage == JS_NEED_INIT) {
                 init64.push_back(j.slot64);
                 j.stage = JS_ITER;
+                j.repl_ref = -1.0;
+            } else if (j.stage == JS_NEED_REPL) {
+                repl64.push_back(j.slot64);
+                j.stage = JS_ITER;
+                j.repl_ref = -1.0;
+                ++j.outer;
             }
+        }
         PPCG_TRY(aux_launch(g64_, init64, AUX_INIT));
+        PPCG_TRY(aux_launch(g64_, repl64, AUX_REPL));
     }
     // 3. iteration tables.
     for (Group *g : {&g64_, &g32_}) {
@@ -943,10 +1047,10 @@ ppcg_status Engine::step(int graph_iters)
         for (const Job &j : jobs_) {
             if (j.finished || j.stage != JS_ITER)
                 continue;
-            const bool in_this = (g == &g32_) == (j.mixed != 0);
+            const bool in_this = (g == &g32_) == (j.mixed == MIX_INNER32);
             if (!in_this)
                 continue;
-            const int sl = j.mixed ? j.slot32 : j.slot64;
+            const int sl = j.mixed == MIX_INNER32 ? j.slot32 : j.slot64;
             for (int t = 0; t < g->desc_h[sl].ntiles; ++t)
                 items.push_back({sl, t});
         }
@@ -958,33 +1062,43 @@ ppcg_status Engine::step(int graph_iters)
         }
     }
     // 4. one graph chunk per non-empty group.
-    bool launched = false;
     for (Group *g : {&g64_, &g32_}) {
         if (g->table_h.empty())
             continue;
         PPCG_TRY(ensure_table(*g));
-        PPCG_TRY(ensure_graph(*g, graph_iters));
-        PPCG_HIP(hipGraphLaunch(g->gexec, stream_));
-        launched = true;
+        hipGraphExec_t exec = nullptr;
+        PPCG_TRY(ensure_graph(*g, chunk_iters(*g, graph_iters), &exec));
+        PPCG_HIP(hipGraphLaunch(exec, stream_));
     }
     // 5. poll.
     PPCG_TRY(sync_states(g64_));
     PPCG_TRY(sync_states(g32_));
     PPCG_HIP(hipStreamSynchronize(stream_));
-    (void)launched;
     for (Job &j : jobs_) {
         if (j.finished || j.stage != JS_ITER)
             continue;
-        if (!j.mixed) {
-            const SysState &st = g64_.st_h[j.slot64];
-            if (st.done)
+        const SysState &st = j.mixed == MIX_INNER32 ? g32_.st_h[j.slot32] : g64_.st_h[j.slot64];
+        const SysDesc &d = j.mixed == MIX_INNER32 ? g32_.desc_h[j.slot32] : g64_.desc_h[j.slot64];
+        if (st.done) {
+            j.last_norm = -1.0;
+            if (j.mixed != MIX_INNER32) {
                 j.stage = JS_NEED_FINAL;
-        } else {
-            const SysState &st = g32_.st_h[j.slot32];
-            if (st.done) {
+            } else {
                 j.inner_iters += st.iter;
                 j.precond_norm = std::sqrt(st.uu);
                 j.stage = JS_OUTER;
+            }
+        } else {
+            j.last_norm = d.stop == STOP_ABS ? std::sqrt(st.uu) : std::sqrt(st.rr);
+            j.last_iter = st.iter;
+            if (j.mixed == MIX_VALUES32) {
+                // reliable update once the residual fell by the replacement factor
+                const double rn = std::sqrt(st.rr);
+                const double f = j.h->opt.inner_tol > 0 ? j.h->opt.inner_tol : 1e-3;
+                if (j.repl_ref < 0)
+                    j.repl_ref = rn;
+                else if (rn < f * j.repl_ref && j.outer < j.h->opt.max_outer)
+                    j.stage = JS_NEED_REPL;
             }
         }
     }
@@ -1061,7 +1175,7 @@ void fill_info(const ppcg_handle *h, const Job &j, ppcg_info *info)
     info->rel_resid_recur = j.rel_recur;
     info->precond_norm = j.precond_norm;
     info->time_ms = j.t_end - j.t_start;
-    const ByteModel bm = byte_model(h, j.mixed ? PREC_F32 : PREC_F64);
+    const ByteModel bm = byte_model(h, j.mixed == MIX_INNER32 ? PREC_F32 : j.mixed == MIX_VALUES32 ? PREC_V32 : PREC_F64);
     info->model_bytes = (bm.vma + bm.spmv) * j.iters;
 }
 
@@ -1149,7 +1263,7 @@ static ppcg_status check_options(const ppcg_options *o)
         o->max_restarts < 0 || o->graph_iters < 0 || o->graph_iters > 4096 || !(o->inner_tol >= 0.0) ||
         o->inner_tol >= 1.0 || o->max_outer < 0 ||
         (o->stop != PPCG_STOP_REL_RESID && o->stop != PPCG_STOP_PRECOND_ABS) ||
-        (o->precision != PPCG_FP64 && o->precision != PPCG_MIXED_FP32) ||
+        (o->precision != PPCG_FP64 && o->precision != PPCG_MIXED_FP32 && o->precision != PPCG_MIXED_FP32_VALUES) ||
         (o->vec_mem != PPCG_MEM_DEVICE && o->vec_mem != PPCG_MEM_HOST) ||
         (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
          o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
@@ -1293,6 +1407,8 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
     CKS(choose_format(h, rp, ci, val, rowlen, dinv_orig, rowlen_h));
     if (opt->precision == PPCG_MIXED_FP32)
         CKS(ensure_f32(h));
+    if (opt->precision == PPCG_MIXED_FP32_VALUES)
+        CKS(ensure_val32(h));
     CK(hipStreamSynchronize(s));
     if (own_csr) {
         (void)hipFree(rp);
@@ -1326,6 +1442,8 @@ ppcg_status ppcg_set_options(ppcg_handle *h, const ppcg_options *opt)
     h->opt.spmv_format = keep;
     if (opt->precision == PPCG_MIXED_FP32)
         PPCG_TRY(ensure_f32(h));
+    if (opt->precision == PPCG_MIXED_FP32_VALUES)
+        PPCG_TRY(ensure_val32(h));
     return PPCG_OK;
 }
 
@@ -1373,7 +1491,7 @@ ppcg_status ppcg_solve(ppcg_handle *h, const double *b, const double *x0, double
     Engine &E = *h->solo;
     E.reset();  // the solo engine is reused: one job per solve
     int id = -1;
-    const int mixed = h->opt.precision == PPCG_MIXED_FP32;
+    const int mixed = h->opt.precision == PPCG_MIXED_FP32 ? MIX_INNER32 : h->opt.precision == PPCG_MIXED_FP32_VALUES ? MIX_VALUES32 : MIX_NONE;
     PPCG_TRY(E.add(h, mixed, h->opt.tol, nullptr, &id));
     PPCG_TRY(run_engine(E, auto_graph_iters(h)));
     PPCG_TRY(unstage_x(h, x));
@@ -1431,7 +1549,7 @@ ppcg_status ppcg_solve_batch(int32_t count, ppcg_handle *const *hs, const double
     int gi = 128;
     for (int i = 0; i < count; ++i) {
         int id;
-        const int mixed = hs[i]->opt.precision == PPCG_MIXED_FP32;
+        const int mixed = hs[i]->opt.precision == PPCG_MIXED_FP32 ? MIX_INNER32 : hs[i]->opt.precision == PPCG_MIXED_FP32_VALUES ? MIX_VALUES32 : MIX_NONE;
         PPCG_TRY(E.add(hs[i], mixed, hs[i]->opt.tol, nullptr, &id));
         gi = std::min(gi, auto_graph_iters(hs[i]));
     }
@@ -1467,7 +1585,8 @@ ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
     mi->sell_sigma = h->sigma;
     mi->lanes_per_row = h->lanes;
     mi->tile_rows = kTileRows;
-    const ByteModel bm = byte_model(h, h->opt.precision == PPCG_MIXED_FP32 ? PREC_F32 : PREC_F64);
+    const ByteModel bm = byte_model(h, h->opt.precision == PPCG_MIXED_FP32 ? PREC_F32
+                                       : h->opt.precision == PPCG_MIXED_FP32_VALUES ? PREC_V32 : PREC_F64);
     mi->bytes_vma = bm.vma;
     mi->bytes_spmv = bm.spmv;
     mi->bytes_per_iter = bm.vma + bm.spmv;
@@ -1486,9 +1605,11 @@ double ppcg_footprint_bytes(int32_t n, int64_t nnz, ppcg_precision precision)
     const double ntiles = (n + kTileRows - 1) / kTileRows;
     const double stored = 1.10 * (double)nnz;  // padding allowance
     double b = stored * 12.0 + 8.0 * (n / kSellC + 2) + 8.0 * n /* dinv */ + 8.0 * n /* perm */ +
-               11.0 * 8.0 * n + 2.0 * ntiles * kNumPartials * 8.0 + 12 * 256.0;
+               11.0 * 8.0 * n + 2.0 * ntiles * kPartStride * 8.0 + 12 * 256.0;
     if (precision == PPCG_MIXED_FP32)
-        b += stored * 4.0 + 12.0 * 4.0 * n + 2.0 * ntiles * kNumPartials * 8.0;
+        b += stored * 4.0 + 12.0 * 4.0 * n + 2.0 * ntiles * kPartStride * 8.0;
+    if (precision == PPCG_MIXED_FP32_VALUES)
+        b += stored * 4.0;
     return b;
 }
 
@@ -1506,7 +1627,7 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     hipStream_t s = h->stream;
     // Fixed-iteration mode with a count larger than iters: never stops early.
     PPCG_TRY(plain_setup(h, 0.0, INT_MAX, INT_MAX));
-    std::vector<hipEvent_t> ev(2 * iters + 1, nullptr);
+    std::vector<hipEvent_t> ev(4 * iters, nullptr);
     auto clean = [&]() {
         (void)hipStreamSynchronize(s);
         for (auto &e : ev)
@@ -1516,24 +1637,26 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     const WorkItem *tab = h->plain_tab;
     const int *cnt = h->plain_cnt;
     const SysDesc *dd = h->plain_desc;
-    k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, 1);
-    k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, 1);
-    k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, 1);
+    k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
+    k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
+    k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
     for (auto &e : ev)
         PPCG_HIP_CLEAN(hipEventCreate(&e), clean());
-    PPCG_HIP_CLEAN(hipEventRecord(ev[0], s), clean());
+    // Events attached to each launch (start/stop of the kernel itself), so
+    // the durations exclude the gaps between launches.
     for (int i = 0; i < iters; ++i) {
-        k_vma<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd, 1);
-        PPCG_HIP_CLEAN(hipEventRecord(ev[2 * i + 1], s), clean());
-        k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, 1);
-        PPCG_HIP_CLEAN(hipEventRecord(ev[2 * i + 2], s), clean());
+        hipExtLaunchKernelGGL(k_vma<double>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0,
+                              tab, cnt, dd, (int)PPCG_XCD_REMAP);
+        hipExtLaunchKernelGGL((k_spmv<double, MODE_ITER>), dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2],
+                              ev[4 * i + 3], 0, tab, cnt, dd, (int)PPCG_XCD_REMAP_SPMV);
     }
-    PPCG_HIP_CLEAN(hipEventSynchronize(ev[2 * iters]), clean());
+    PPCG_HIP_CLEAN(hipGetLastError(), clean());
+    PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());
     double tv = 0, ts = 0;
     for (int i = 0; i < iters; ++i) {
         float a = 0, c = 0;
-        PPCG_HIP_CLEAN(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]), clean());
-        PPCG_HIP_CLEAN(hipEventElapsedTime(&c, ev[2 * i + 1], ev[2 * i + 2]), clean());
+        PPCG_HIP_CLEAN(hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]), clean());
+        PPCG_HIP_CLEAN(hipEventElapsedTime(&c, ev[4 * i + 2], ev[4 * i + 3]), clean());
         tv += a;
         ts += c;
     }
@@ -1562,7 +1685,7 @@ ppcg_status ppcg_spmv(ppcg_handle *h, const double *x, double *y)
     PPCG_TRY(stage_inputs(h, x, x));
     PPCG_TRY(plain_setup(h, 1e-8, 0, 1));
     hipStream_t s = h->stream;
-    k_spmv<double, MODE_PLAIN><<<h->ntiles, kSpmvThreads, 0, s>>>(h->plain_tab, h->plain_cnt, h->plain_desc, 1);
+    k_spmv<double, MODE_PLAIN><<<h->ntiles, kSpmvThreads, 0, s>>>(h->plain_tab, h->plain_cnt, h->plain_desc, PPCG_XCD_REMAP_SPMV);
     PPCG_HIP(hipGetLastError());
     // result is in the internal nv vector; scatter it out like x
     const int n = h->n;

@@ -94,7 +94,10 @@ static ppcg_status admit(ppcg_server *s)
         rc = stage_inputs(r.h, r.b.data(), nullptr);
         r.h->stream = keep;
         PPCG_TRY(rc);
-        PPCG_TRY(s->eng->add(r.h, r.precision == PPCG_MIXED_FP32, r.tol, nullptr, &r.job));
+        const int mixed = r.precision == PPCG_MIXED_FP32          ? MIX_INNER32
+                          : r.precision == PPCG_MIXED_FP32_VALUES ? MIX_VALUES32
+                                                                  : MIX_NONE;
+        PPCG_TRY(s->eng->add(r.h, mixed, r.tol, nullptr, &r.job));
         r.state = 1;
         s->used += r.footprint;
         ++s->active;
@@ -167,7 +170,7 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
     clear_error();
     if (!s || !A || !b || !req_id || A->struct_size != sizeof(ppcg_csr) || A->mem != PPCG_MEM_HOST || A->n < 1 ||
         A->nnz < A->n || !A->row_ptr || !A->col_idx || !A->values || !(tol >= 0.0) ||
-        (precision != PPCG_FP64 && precision != PPCG_MIXED_FP32)) {
+        (precision != PPCG_FP64 && precision != PPCG_MIXED_FP32 && precision != PPCG_MIXED_FP32_VALUES)) {
         set_error("invalid request");
         return PPCG_ERR_INVALID_ARG;
     }

@@ -404,6 +404,8 @@ def test_server_result_same_alone_and_in_mix():
            ("R", A, b, 1e-10, "fp64"),
            ("m1", poisson2d(50), problem(poisson2d(50))[0], 1e-6, "fp64"),
            ("m2", stencil27_lognormal(10, seed=2), problem(stencil27_lognormal(10, seed=2))[0], 1e-10, "mixed"),
+           ("m4", stencil27_lognormal(11, seed=5), problem(stencil27_lognormal(11, seed=5))[0], 1e-10,
+            "mixed_values"),
            ("m3", poisson2d(120), problem(poisson2d(120))[0], 1e-10, "fp64")]
     res = _serve_all(Server(), mix, stagger=1)
     assert np.array_equal(res["R"][0], alone[0])
@@ -430,3 +432,55 @@ def test_server_refuses_over_budget_and_admits_in_turn():
     xs = [res[f"r{i}"][0] for i in range(4)]
     for x in xs[1:]:
         assert np.array_equal(x, xs[0])
+
+
+# ---------------------------------------------------------------- FP32 values + reliable updates
+
+def _round32(A):
+    return CSR(A.n, A.rp, A.ci, A.val.astype(np.float32).astype(np.float64), A.name + "_fp32")
+
+
+@pytest.mark.parametrize("gen", [lambda: stencil27_lognormal(14, seed=2), lambda: random_spd(5000, seed=6)])
+def test_fp32_values_iterates_match_oracle_on_rounded_matrix(gen):
+    """Before the first reliable update the iteration is PIPECG on the
+    FP32-rounded operator (FP64 vectors, FP64 accumulation); with x0 = 0 the
+    initial residual is b either way, so the oracle run on the rounded matrix
+    is the reference."""
+    A = gen()
+    b, _ = problem(A)
+    S = Solver(A, precision="mixed_values", inner_tol=1e-30, spmv_format="sell")
+    for k in (1, 4, 12):
+        S.set_options(precision="mixed_values", fixed_iters=k, inner_tol=1e-30)
+        x, info = S.solve(dev(b))
+        ref = oracle.pipecg(_round32(A), b, fixed_iters=k)
+        assert info["iters"] == k and info["outer_iters"] == 0
+        assert relerr(host(x), ref.x) <= 1e-10, k
+
+
+@pytest.mark.parametrize("gen,factor", [(lambda: stencil27_lognormal(16, seed=1), 1e-3),
+                                        (lambda: stencil27_lognormal(16, seed=1), 0.3),
+                                        (lambda: poisson3d(24), 1e-2),
+                                        (lambda: random_spd(20000, seed=3), 1e-3)])
+def test_fp32_values_reliable_updates_reach_fp64_tolerance(gen, factor):
+    A = gen()
+    b, _ = problem(A)
+    S = Solver(A, tol=1e-10, precision="mixed_values", inner_tol=factor)
+    x, info = S.solve(dev(b))
+    ref = oracle.pipecg(A, b, tol=1e-10)
+    assert info["status"] == ppcg.OK, info
+    assert info["rel_resid_true"] <= 1e-10
+    assert oracle.true_relres(A, b, host(x)) <= 1e-10
+    # one Krylov sequence: the iteration count stays close to the FP64 one
+    assert info["iters"] <= 1.15 * ref.iters + 5, (info["iters"], ref.iters)
+    assert relerr(host(x), ref.x) <= 1e-5
+
+
+def test_fp32_values_batch_bitwise_equals_solo():
+    mats = [stencil27_lognormal(12, seed=4), shifted(poisson2d(70), 0.01), random_spd(4000, seed=2)]
+    bs = [problem(A, seed=60 + i)[0] for i, A in enumerate(mats)]
+    solo = [host(Solver(A, tol=1e-10, precision="mixed_values").solve(dev(b))[0]) for A, b in zip(mats, bs)]
+    solvers = [Solver(A, tol=1e-10, precision="mixed_values") for A in mats]
+    xs, infos = solve_batch(solvers, [dev(b) for b in bs])
+    for x, xs_, info in zip(xs, solo, infos):
+        assert np.array_equal(host(x), xs_)
+        assert info["status"] == ppcg.OK and info["rel_resid_true"] <= 1e-10
