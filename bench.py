@@ -235,6 +235,39 @@ def leg_c4(torch, ppcg, wl, count=256):
             "algorithmic_gbs": round(bytes_total / t_batch / 1e9, 1), "setup_s": round(setup, 2)}
 
 
+def leg_p125(torch, ppcg, wl, side=165):
+    """The paper's 125-point Poisson matrices (Table 2: 4.5M rows at side 165)
+    under its protocol (Section VI): x* = 1/sqrt(N), b = A x*, absolute
+    tolerance 1e-5 on sqrt((u,u)), at most 10000 iterations."""
+    t0 = time.perf_counter()
+    A = wl.poisson125(side)
+    b = wl.rhs_from_solution(A, wl.xstar_paper(A.n))
+    gen_s = time.perf_counter() - t0
+    log(f"125-pt side {side}: N={A.n} nnz={A.nnz} generated in {gen_s:.1f}s")
+    bd = torch.as_tensor(b).cuda()
+    out = {"workload": f"125-point Poisson side {side} (Table 2), paper protocol: x*=1/sqrt(N), "
+                       "absolute tol 1e-5 on sqrt((u,u)), maxit 10000", "n": A.n, "nnz": A.nnz}
+    del b
+    for prec in ("fp64", "mixed_values"):
+        S = ppcg.Solver(A, tol=1e-5, stop="abs", max_iter=10000, precision=prec)
+        mi = S.matrix_info()
+        S.solve(bd)
+        sync()
+        t0 = time.perf_counter()
+        _, info = S.solve(bd)
+        sync()
+        t = time.perf_counter() - t0
+        out[prec] = {"status": info["status"], "iters": info["iters"], "time_s": round(t, 4),
+                     "ms_per_iter": round(t / max(info["iters"], 1) * 1e3, 4),
+                     "algorithmic_gbs": round(mi["bytes_per_iter"] * info["iters"] / t / 1e9, 1),
+                     "precond_norm": info["precond_norm"], "rel_resid_true": info["rel_resid_true"],
+                     "spmv_format": mi["format"], "lanes_per_row": mi["lanes_per_row"],
+                     "setup_ms": round(mi["setup_ms"], 1)}
+        log(f"125-pt {prec}: {out[prec]}")
+        S.close()
+    return out
+
+
 def _serve_requests(wl, n_req, seed=0):
     rng = np.random.default_rng(seed)
     reqs = []
@@ -308,7 +341,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    ap.add_argument("--legs", default="c1,c3,c4,c5", help="extra legs: c1,c3,c4,c5 or none")
+    ap.add_argument("--legs", default="c1,c3,c4,c5,p125", help="extra legs: c1,c3,c4,c5,p125 or none")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 256 MiB (reference for HBM counters)")
@@ -354,6 +387,8 @@ def main():
                 legs[name] = leg_c4(torch, ppcg, wl)
             elif name == "c5":
                 legs[name] = leg_c5(ppcg, wl, args.serve_requests)
+            elif name == "p125":
+                legs[name] = leg_p125(torch, ppcg, wl)
         except Exception as e:  # a failing extra leg must not hide the main line
             legs[name] = {"error": f"{type(e).__name__}: {e}"}
         log(f"leg {name} done in {time.perf_counter() - t0:.1f}s: {legs[name]}")

@@ -105,8 +105,9 @@ struct Job {
     ppcg_handle *h = nullptr;
     int mixed = 0;          // 0 FP64, 1 FP32 inner PIPECG + FP64 refinement,
                             // 2 FP32 values + reliable updates (MixKind)
-    int slot64 = -1;        // slot in the FP64 group (always)
-    int slot32 = -1;        // slot in the FP32 group (mixed only)
+    int slot64 = -1;        // slot in the FP64 group (MIX_NONE, and the outer FP64 steps of MIX_INNER32)
+    int slot32 = -1;        // slot in the FP32-vector group (MIX_INNER32)
+    int slotv = -1;         // slot in the FP32-values group (MIX_VALUES32)
     int stage = 0;          // JobStage
     int restarts = 0;
     int outer = 0;
@@ -193,10 +194,13 @@ class Engine {
     ppcg_status ensure_graph(Group &g, int iters, hipGraphExec_t *exec);
     void drop_graphs(Group &g);
     int chunk_iters(const Group &g, int max_iters);
+    // group and slot where a job iterates
+    Group &pgroup(const Job &j) { return j.mixed == MIX_INNER32 ? g32_ : j.mixed == MIX_VALUES32 ? gv_ : g64_; }
+    int pslot(const Job &j) const { return j.mixed == MIX_INNER32 ? j.slot32 : j.mixed == MIX_VALUES32 ? j.slotv : j.slot64; }
     ppcg_status sync_states(Group &g);
     int alloc_slot(Group &g);
     hipStream_t stream_;
-    Group g64_, g32_;
+    Group g64_, g32_, gv_;
     std::vector<Job> jobs_;
 };
 

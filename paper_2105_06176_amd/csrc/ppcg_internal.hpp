@@ -38,7 +38,13 @@ enum Fmt : int { FMT_SELL = 1, FMT_CSRV = 2 };
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_V32 = 2 /* FP32 values, FP64 vectors */ };
 
 // Status codes mirrored from ppcg.h (device code does not include it).
-enum DevStatus : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_STAGNATED = 3 };
+enum DevStatus : int {
+    ST_OK = 0,
+    ST_NOT_CONVERGED = 1,
+    ST_BREAKDOWN = 2,
+    ST_STAGNATED = 3,
+    ST_REPLACE = 4  // FP32-values mode: paused for a reliable update (not a final status)
+};
 enum StopMode : int { STOP_REL = 0, STOP_ABS = 1 };
 
 // Per-system iteration state.  Lives in device memory, written only by the
@@ -54,6 +60,7 @@ struct alignas(128) SysState {
     double gamma_prev;  // gamma_{i-1}
     double alpha_prev;  // alpha_{i-1}
     double gamma_prev2; // gamma_{i-1} as it was before the last scalar update
+    double repl_ref;    // FP32-values mode: residual norm at the last start / reliable update
     double bnorm2;      // (b, b)
     double tnorm2;      // (b - A x, b - A x) from the last true-residual pass
     int iter;           // x-updates so far (all starts)
@@ -79,6 +86,7 @@ struct SysDesc {
     int pair;           // mixed precision: slot of the same system in the other group
     int vals32;         // 1: iteration SpMVs read the FP32 copy of the values (val32)
     double tol;
+    double repl_factor; // vals32: pause for a reliable update when the residual fell by this factor
     const int64_t *cptr;  // SELL chunk offsets [nchunks + 1]
     const int *rp;        // CSR row pointers [n + 1] (CSR-vector format)
     const int *col;       // SELL / CSR column indices

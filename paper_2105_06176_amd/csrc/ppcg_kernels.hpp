@@ -132,8 +132,19 @@ __device__ __forceinline__ void reduce_partials(const SysDesc &d, int slot, doub
 // alpha_i = gamma_i / (delta - beta_i gamma_i / alpha_{i-1}) (beta = 0 and
 // alpha = gamma / delta on the first iteration of a start), with breakdown
 // when gamma <= 0, the denominator <= 0 or a scalar is not finite.
-__device__ inline void scalar_update(const SysDesc &d, SysState *st, const double (&v)[kNumPartials])
+//
+// FP32-values mode (d.vals32) differs in two ways.  (1) The denominator
+// (p_i, A p_i) is evaluated directly, (p, A p) = delta + 2 beta (u, s_{i-1})
+// + beta^2 (p_{i-1}, s_{i-1}) with A symmetric, from two extra dot products
+// of the fused update (v[4], v[5]): the recurrence form relies on CG
+// orthogonality identities that a residual computed with the FP64 operator
+// does not satisfy for the FP32-valued recurrences.  (2) Once the residual
+// has fallen by d.repl_factor since the last start or reliable update, the
+// system pauses (ST_REPLACE) so the host can run the reliable update.
+template <int NV>
+__device__ inline void scalar_update(const SysDesc &d, SysState *st, const double (&v)[NV])
 {
+    const bool first = st->phase != 0;
     if (st->phase) {
         st->phase = 0;
     } else {
@@ -164,10 +175,25 @@ __device__ inline void scalar_update(const SysDesc &d, SysState *st, const doubl
         st->status = ST_NOT_CONVERGED;
         return;
     }
+    if constexpr (NV >= kReplPartials) {
+        if (d.vals32) {
+            const double rn = sqrt(rr);
+            if (first) {
+                st->repl_ref = rn;
+            } else if (d.repl_factor > 0.0 && rn < d.repl_factor * st->repl_ref) {
+                st->done = 1;
+                st->status = ST_REPLACE;
+                return;
+            }
+        }
+    }
     double beta, denom;
     if (st->i_start > 0) {
         beta = g / st->gamma_prev;
-        denom = dl - beta * g / st->alpha_prev;
+        if constexpr (NV >= kReplPartials)
+            denom = d.vals32 ? dl + 2.0 * beta * v[4] + beta * beta * v[5] : dl - beta * g / st->alpha_prev;
+        else
+            denom = dl - beta * g / st->alpha_prev;
     } else {
         beta = 0.0;
         denom = dl;
@@ -217,10 +243,18 @@ __device__ inline void scalar_update_repl(const SysDesc &d, SysState *st, const 
         st->status = ST_NOT_CONVERGED;
         return;
     }
+    st->repl_ref = sqrt(rr);
     double beta = 0.0, denom = dl;
     if (st->i_start > 0) {
         beta = g / st->gamma_prev2;
         denom = dl + 2.0 * beta * us + beta * beta * ps;
+        if (!(denom > 0.0)) {
+            // The kept direction is no longer usable: restart the direction
+            // (beta = 0) from the replaced residual instead of breaking down.
+            st->i_start = 0;
+            beta = 0.0;
+            denom = dl;
+        }
     }
     const double alpha = g / denom;
     if (!(g > 0.0) || !(denom > 0.0) || !isfinite(alpha) || !isfinite(beta)) {
@@ -236,9 +270,9 @@ __device__ inline void scalar_update_repl(const SysDesc &d, SysState *st, const 
 
 // ---------------------------------------------------------------------------
 // Fused vector updates + Jacobi + dot-product partials.
-template <typename T>
+template <typename T, int NV>
 __device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T m, T &q, T &w, T &s, T &u, T &p, T &x,
-                                         T &r, T dinv, T &m_out, double (&acc)[kNumPartials])
+                                         T &r, T dinv, T &m_out, double (&acc)[NV])
 {
     z = nv + sb * z;
     q = m + sb * q;
@@ -254,6 +288,11 @@ __device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T m, T &q, T &w
     acc[1] = acc[1] + wd * ud;
     acc[2] = acc[2] + ud * ud;
     acc[3] = acc[3] + rd * rd;
+    if constexpr (NV >= kReplPartials) {
+        const double sd = (double)s, pd = (double)p;
+        acc[4] = acc[4] + ud * sd;
+        acc[5] = acc[5] + pd * sd;
+    }
 }
 
 #ifndef PPCG_VMA_NT
@@ -280,12 +319,15 @@ __device__ __forceinline__ void vstore(V *p, V v)
 #endif
 }
 
-template <typename T>
+// EXACT: also emit the partials of (u_{i+1}, s_i) and (p_i, s_i) for the
+// directly evaluated alpha denominator (FP32-values mode).
+template <typename T, bool EXACT = false>
 __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict__ table,
                                                      const int *__restrict__ count,
                                                      const SysDesc *__restrict__ descs, int remap)
 {
-    __shared__ double lds[kVmaThreads / 64 * kNumPartials];
+    constexpr int NV = EXACT ? kReplPartials : kNumPartials;
+    __shared__ double lds[kVmaThreads / 64 * NV];
     const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     if (pos >= *count)
         return;
@@ -301,17 +343,20 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     T *__restrict__ U = (T *)d.u;
     T *__restrict__ W = (T *)d.w;
     T *__restrict__ M = (T *)d.m;
-    const T *__restrict__ NV = (const T *)d.nv;
+    const T *__restrict__ NVv = (const T *)d.nv;
     T *__restrict__ Z = (T *)d.z;
     T *__restrict__ Q = (T *)d.q;
     T *__restrict__ S = (T *)d.s;
     T *__restrict__ P = (T *)d.p;
     const T *__restrict__ DI = (const T *)d.dinv;
-    double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        acc[k] = 0.0;
     const int i = wi.tile * kTileRows + threadIdx.x * 2;
     using V2 = typename Vec2<T>::type;
     if (i + 1 < n) {
-        V2 nv = vload((const V2 *)(NV + i)), z = vload((const V2 *)(Z + i)), m = vload((const V2 *)(M + i));
+        V2 nv = vload((const V2 *)(NVv + i)), z = vload((const V2 *)(Z + i)), m = vload((const V2 *)(M + i));
         V2 q = vload((const V2 *)(Q + i)), w = vload((const V2 *)(W + i)), s = vload((const V2 *)(S + i));
         V2 u = vload((const V2 *)(U + i)), p = vload((const V2 *)(P + i)), x = vload((const V2 *)(X + i));
         V2 r = vload((const V2 *)(R + i)), di = vload((const V2 *)(DI + i));
@@ -319,7 +364,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             T zj = z[j], qj = q[j], wj = w[j], sj = s[j], uj = u[j], pj = p[j], xj = x[j], rj = r[j], mj;
-            vma_elem<T>(sa, sb, nv[j], zj, m[j], qj, wj, sj, uj, pj, xj, rj, di[j], mj, acc);
+            vma_elem<T, NV>(sa, sb, nv[j], zj, m[j], qj, wj, sj, uj, pj, xj, rj, di[j], mj, acc);
             z[j] = zj; q[j] = qj; w[j] = wj; s[j] = sj; u[j] = uj; p[j] = pj; x[j] = xj; r[j] = rj; mo[j] = mj;
         }
         vstore((V2 *)(Z + i), z);
@@ -333,14 +378,14 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
         vstore((V2 *)(M + i), mo);
     } else if (i < n) {
         T z = Z[i], q = Q[i], w = W[i], s = S[i], u = U[i], p = P[i], x = X[i], r = R[i], mo;
-        vma_elem<T>(sa, sb, NV[i], z, M[i], q, w, s, u, p, x, r, DI[i], mo, acc);
+        vma_elem<T, NV>(sa, sb, NVv[i], z, M[i], q, w, s, u, p, x, r, DI[i], mo, acc);
         Z[i] = z; Q[i] = q; S[i] = s; P[i] = p; X[i] = x; R[i] = r; U[i] = u; W[i] = w; M[i] = mo;
     }
-    block_sum<kVmaThreads, kNumPartials>(acc, lds);
+    block_sum<kVmaThreads, NV>(acc, lds);
     if (threadIdx.x == 0) {
         double *out = d.part + ((size_t)d.ntiles + wi.tile) * kPartStride;  // slot 1
 #pragma unroll
-        for (int k = 0; k < kNumPartials; ++k)
+        for (int k = 0; k < NV; ++k)
             out[k] = acc[k];
     }
 }
@@ -539,6 +584,11 @@ __device__ __noinline__ void designated_reduce(const SysDesc &d, SysState *st, d
         reduce_partials<kSpmvThreads, kReplPartials>(d, 1, v, lds);
         if (threadIdx.x == 0)
             scalar_update_repl(d, st, v);
+    } else if (MODE == MODE_ITER && d.vals32) {
+        double v[kReplPartials];
+        reduce_partials<kSpmvThreads, kReplPartials>(d, 1, v, lds);
+        if (threadIdx.x == 0)
+            scalar_update<kReplPartials>(d, st, v);
     } else {
         double v[kNumPartials];
         reduce_partials<kSpmvThreads>(d, MODE == MODE_INIT2 ? 0 : 1, v, lds);
@@ -546,7 +596,7 @@ __device__ __noinline__ void designated_reduce(const SysDesc &d, SysState *st, d
             if (MODE == MODE_INIT2)
                 st->bnorm2 = v[0];
             else
-                scalar_update(d, st, v);
+                scalar_update<kNumPartials>(d, st, v);
         }
     }
 }
@@ -620,6 +670,10 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_spmv(const WorkItem *__rest
 #pragma unroll
             for (int k = 0; k < NV; ++k)
                 out[k] = v[k];
+            if constexpr (MODE == MODE_INIT2) {
+                out[4] = 0.0;  // the direct-denominator terms are unused at a start
+                out[5] = 0.0;
+            }
         }
     }
     if (wi.tile != 0)

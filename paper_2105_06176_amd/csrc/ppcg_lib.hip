@@ -574,7 +574,7 @@ ppcg_status ensure_f32(ppcg_handle *h)
 // ---------------------------------------------------------------- engine
 Engine::~Engine()
 {
-    for (Group *g : {&g64_, &g32_}) {
+    for (Group *g : {&g64_, &g32_, &gv_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
         if (g->st_d) (void)hipFree(g->st_d);
@@ -613,6 +613,7 @@ ppcg_status Engine::init(int cap_sys)
 {
     PPCG_TRY(ensure_group(g64_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(g32_, PREC_F32, cap_sys));
+    PPCG_TRY(ensure_group(gv_, PREC_V32, cap_sys));
     return PPCG_OK;
 }
 
@@ -669,11 +670,21 @@ static ppcg_status upload_table(hipStream_t s, Group &g, const std::vector<WorkI
     return PPCG_OK;
 }
 
-template <typename T>
+// One iteration of a group: the fused update, then the SpMV with the
+// in-launch reduction.  The FP32-values group uses the fused-update variant
+// that also emits the direct-denominator partials.
 static void launch_iter_pair(hipStream_t s, const Group &g, int grid, int remap)
 {
-    k_vma<T><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
-    k_spmv<T, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+    if (g.prec == PREC_F32) {
+        k_vma<float><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+        k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+    } else if (g.prec == PREC_V32) {
+        k_vma<double, true><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+        k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+    } else {
+        k_vma<double><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+        k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+    }
 }
 
 ppcg_status Engine::ensure_table(Group &g)
@@ -717,12 +728,8 @@ ppcg_status Engine::ensure_graph(Group &g, int iters, hipGraphExec_t *exec)
     const int grid = g.g_grid ? g.g_grid : need;
     Group::CapturedGraph cg;
     PPCG_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < iters; ++i) {
-        if (g.prec == PREC_F64)
-            launch_iter_pair<double>(stream_, g, grid, remap);
-        else
-            launch_iter_pair<float>(stream_, g, grid, remap);
-    }
+    for (int i = 0; i < iters; ++i)
+        launch_iter_pair(stream_, g, grid, remap);
     hipError_t e = hipStreamEndCapture(stream_, &cg.graph);
     if (e != hipSuccess) {
         set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
@@ -748,13 +755,10 @@ int Engine::chunk_iters(const Group &g, int max_iters)
 {
     int want = 1;
     for (const Job &j : jobs_) {
-        if (j.finished || j.stage != JS_ITER)
+        if (j.finished || j.stage != JS_ITER || &pgroup(j) != &g)
             continue;
-        const bool in_this = (&g == &g32_) == (j.mixed == MIX_INNER32);
-        if (!in_this)
-            continue;
-        const SysState &st = j.mixed == MIX_INNER32 ? g32_.st_h[j.slot32] : g64_.st_h[j.slot64];
-        const SysDesc &d = j.mixed == MIX_INNER32 ? g32_.desc_h[j.slot32] : g64_.desc_h[j.slot64];
+        const SysState &st = g.st_h[pslot(j)];
+        const SysDesc &d = g.desc_h[pslot(j)];
         int rem = max_iters;
         if (d.fixed > 0) {
             rem = d.fixed - (j.last_norm < 0 ? 0 : st.iter);
@@ -795,32 +799,37 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     PPCG_TRY(upload_table(stream_, g, items, g.aux_d, g.aux_count_d, 1));
     const int grid = (int)items.size();
     hipStream_t s = stream_;
+    const WorkItem *tab = g.aux_d;
+    const int *cnt = g.aux_count_d;
+    const SysDesc *dd = g.desc_d;
+    const int rs = PPCG_XCD_REMAP_SPMV;
+    const bool f32 = g.prec == PREC_F32;
     if (what == AUX_INIT) {
-        if (g.prec == PREC_F64) {
-            k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-            k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-            k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        if (f32) {
+            k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            k_spmv<float, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
         } else {
-            k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-            k_spmv<float, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-            k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+            k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
         }
     } else if (what == AUX_RESID) {
-        if (g.prec == PREC_F64)
-            k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        if (f32)
+            k_spmv<float, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
         else
-            k_spmv<float, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-        k_reduce_resid<<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d);
+            k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        k_reduce_resid<<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_REPL) {
         // Reliable update: FP64 residual, then the rebuilt auxiliaries (two
         // dual-product passes with the iteration's values).
-        k_spmv<double, MODE_REPL1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-        k_spmv<double, MODE_DUAL1><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-        k_spmv<double, MODE_DUAL2><<<grid, kSpmvThreads, 0, s>>>(g.aux_d, g.aux_count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        k_spmv<double, MODE_REPL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        k_spmv<double, MODE_DUAL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        k_spmv<double, MODE_DUAL2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
     } else if (what == AUX_MIX_START) {
-        k_mix_start<<<grid, 256, 0, s>>>(g.aux_d, g.aux_count_d, g64_.desc_d, g32_.desc_d);
+        k_mix_start<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, g32_.desc_d);
     } else if (what == AUX_MIX_CORRECT) {
-        k_mix_correct<<<grid, 256, 0, s>>>(g.aux_d, g.aux_count_d, g64_.desc_d, g32_.desc_d);
+        k_mix_correct<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, g32_.desc_d);
     }
     PPCG_HIP(hipGetLastError());
     return PPCG_OK;
@@ -833,40 +842,69 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
     j.mixed = mixed;
     j.tol = tol;
     j.t_start = now_ms();
-    j.slot64 = alloc_slot(g64_);
-    if (j.slot64 < 0) {
-        set_error("engine has no free slot");
-        return PPCG_ERR_INVALID_ARG;
-    }
     const ppcg_options &o = h->opt;
     const int stop = o.stop == PPCG_STOP_PRECOND_ABS ? STOP_ABS : STOP_REL;
-    if (mixed == MIX_VALUES32)
-        PPCG_TRY(ensure_val32(h));
-    PPCG_TRY(fill_desc(h, PREC_F64, g64_.st_d + j.slot64, &g64_.desc_h[j.slot64], tol,
-                       mixed == MIX_INNER32 ? 0 : o.fixed_iters, o.max_iter, stop, mixed == MIX_VALUES32));
-    if (mixed == MIX_INNER32) {
-        PPCG_TRY(ensure_f32(h));
-        j.slot32 = alloc_slot(g32_);
-        if (j.slot32 < 0) {
-            g64_.slot_used[j.slot64] = 0;
+    auto release = [&]() {
+        if (j.slot64 >= 0) g64_.slot_used[j.slot64] = 0;
+        if (j.slot32 >= 0) g32_.slot_used[j.slot32] = 0;
+        if (j.slotv >= 0) gv_.slot_used[j.slotv] = 0;
+    };
+    auto fail = [&](ppcg_status s) {
+        release();
+        return s;
+    };
+    if (mixed == MIX_VALUES32) {
+        j.slotv = alloc_slot(gv_);
+        if (j.slotv < 0) {
             set_error("engine has no free slot");
             return PPCG_ERR_INVALID_ARG;
         }
-        double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
-        PPCG_TRY(fill_desc(h, PREC_F32, g32_.st_d + j.slot32, &g32_.desc_h[j.slot32], itol, 0, o.max_iter,
-                           STOP_REL));
-        g32_.desc_h[j.slot32].pair = j.slot64;
-        g64_.desc_h[j.slot64].pair = j.slot32;
-        PPCG_TRY(upload_desc(g32_, j.slot32));
-        j.stage = JS_OUTER;
-    } else {
+        ppcg_status rc = ensure_val32(h);
+        if (rc == PPCG_OK)
+            rc = fill_desc(h, PREC_F64, gv_.st_d + j.slotv, &gv_.desc_h[j.slotv], tol, o.fixed_iters, o.max_iter,
+                           stop, 1);
+        if (rc != PPCG_OK)
+            return fail(rc);
+        gv_.desc_h[j.slotv].repl_factor = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+        PPCG_TRY(upload_desc(gv_, j.slotv));
+        PPCG_HIP(hipMemsetAsync(gv_.st_d + j.slotv, 0, sizeof(SysState), stream_));
         j.stage = JS_NEED_INIT;
+    } else {
+        j.slot64 = alloc_slot(g64_);
+        if (j.slot64 < 0) {
+            set_error("engine has no free slot");
+            return PPCG_ERR_INVALID_ARG;
+        }
+        ppcg_status rc = fill_desc(h, PREC_F64, g64_.st_d + j.slot64, &g64_.desc_h[j.slot64], tol,
+                                   mixed == MIX_INNER32 ? 0 : o.fixed_iters, o.max_iter, stop);
+        if (rc != PPCG_OK)
+            return fail(rc);
+        if (mixed == MIX_INNER32) {
+            rc = ensure_f32(h);
+            if (rc != PPCG_OK)
+                return fail(rc);
+            j.slot32 = alloc_slot(g32_);
+            if (j.slot32 < 0) {
+                set_error("engine has no free slot");
+                return fail(PPCG_ERR_INVALID_ARG);
+            }
+            const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+            rc = fill_desc(h, PREC_F32, g32_.st_d + j.slot32, &g32_.desc_h[j.slot32], itol, 0, o.max_iter,
+                           STOP_REL);
+            if (rc != PPCG_OK)
+                return fail(rc);
+            g32_.desc_h[j.slot32].pair = j.slot64;
+            g64_.desc_h[j.slot64].pair = j.slot32;
+            PPCG_TRY(upload_desc(g32_, j.slot32));
+            PPCG_HIP(hipMemsetAsync(g32_.st_d + j.slot32, 0, sizeof(SysState), stream_));
+            j.stage = JS_OUTER;
+        } else {
+            j.stage = JS_NEED_INIT;
+        }
+        PPCG_TRY(upload_desc(g64_, j.slot64));
+        // A new solve starts from a clean state (iteration counters at zero).
+        PPCG_HIP(hipMemsetAsync(g64_.st_d + j.slot64, 0, sizeof(SysState), stream_));
     }
-    PPCG_TRY(upload_desc(g64_, j.slot64));
-    // A new solve starts from a clean state (iteration counters at zero).
-    PPCG_HIP(hipMemsetAsync(g64_.st_d + j.slot64, 0, sizeof(SysState), stream_));
-    if (j.slot32 >= 0)
-        PPCG_HIP(hipMemsetAsync(g32_.st_d + j.slot32, 0, sizeof(SysState), stream_));
     jobs_.push_back(j);
     *job_id = (int)jobs_.size() - 1;
     return PPCG_OK;
@@ -903,7 +941,9 @@ void Engine::retire(int id)
         g64_.slot_used[j.slot64] = 0;
     if (j.slot32 >= 0)
         g32_.slot_used[j.slot32] = 0;
-    j.slot64 = j.slot32 = -1;
+    if (j.slotv >= 0)
+        gv_.slot_used[j.slotv] = 0;
+    j.slot64 = j.slot32 = j.slotv = -1;
     j.h = nullptr;
 }
 
@@ -924,39 +964,41 @@ static void finish(Job &j, int status, const SysState &st)
 
 ppcg_status Engine::step(int graph_iters)
 {
-    // 1. transitions that need a true residual: FP64 jobs that stopped, and
-    //    mixed jobs between inner solves.
-    std::vector<int> resid64, correct64;
+    // 1. Jobs that need a true residual: stopped FP64 / FP32-values jobs, and
+    //    FP32-vector jobs between inner solves (after adding the correction).
+    std::vector<int> resid64, residv, correct64;
     for (Job &j : jobs_) {
         if (j.finished)
             continue;
         if (j.stage == JS_NEED_FINAL)
-            resid64.push_back(j.slot64);
+            (j.mixed == MIX_VALUES32 ? residv : resid64).push_back(pslot(j));
         else if (j.stage == JS_OUTER) {
             if (j.outer > 0)
                 correct64.push_back(j.slot64);
             resid64.push_back(j.slot64);
         }
     }
-    if (!resid64.empty()) {
+    if (!resid64.empty() || !residv.empty()) {
         PPCG_TRY(aux_launch(g64_, correct64, AUX_MIX_CORRECT));
         PPCG_TRY(aux_launch(g64_, resid64, AUX_RESID));
+        PPCG_TRY(aux_launch(gv_, residv, AUX_RESID));
         PPCG_TRY(sync_states(g64_));
+        PPCG_TRY(sync_states(gv_));
         PPCG_HIP(hipStreamSynchronize(stream_));
-        std::vector<int> init64, start_mix;
+        std::vector<int> start_mix;
         for (Job &j : jobs_) {
             if (j.finished || (j.stage != JS_NEED_FINAL && j.stage != JS_OUTER))
                 continue;
-            const SysState &st = g64_.st_h[j.slot64];
+            const SysState &st = j.stage == JS_OUTER ? g64_.st_h[j.slot64] : pgroup(j).st_h[pslot(j)];
             const double bn = std::sqrt(st.bnorm2);
             const double rel = bn > 0 ? std::sqrt(st.tnorm2) / bn : std::sqrt(st.tnorm2);
             j.rel_true = rel;
             const ppcg_options &o = j.h->opt;
+            const bool tol_mode = o.fixed_iters <= 0;
             if (j.stage == JS_NEED_FINAL && j.mixed == MIX_VALUES32) {
-                // The recurrence follows the FP32-valued operator: a true
+                // The recurrences follow the FP32-valued operator: a true
                 // residual above tol is fixed by a reliable update, not a restart.
-                const bool tol_mode = o.fixed_iters <= 0;
-                const bool bad = tol_mode && o.stop == PPCG_STOP_REL_RESID ? rel > j.tol : false;
+                const bool bad = tol_mode && o.stop == PPCG_STOP_REL_RESID && rel > j.tol;
                 const bool can_replace = tol_mode && j.outer < o.max_outer && st.iter < o.max_iter;
                 if ((st.status == ST_OK && bad) || (st.status == ST_BREAKDOWN && st.i_start > 0)) {
                     if (can_replace) {
@@ -968,7 +1010,6 @@ ppcg_status Engine::step(int graph_iters)
                     finish(j, st.status, st);
                 }
             } else if (j.stage == JS_NEED_FINAL) {
-                const bool tol_mode = o.fixed_iters <= 0;
                 const bool can_restart = tol_mode && j.restarts < o.max_restarts && st.iter < o.max_iter;
                 if (st.status == ST_OK && tol_mode && o.stop == PPCG_STOP_REL_RESID && rel > j.tol) {
                     if (can_restart) {
@@ -984,10 +1025,9 @@ ppcg_status Engine::step(int graph_iters)
                 } else {
                     finish(j, st.status, st);
                 }
-            } else {  // mixed outer step
+            } else {  // FP32-vector mixed precision: outer refinement step
                 j.bnorm2 = st.bnorm2;
                 if (rel <= j.tol) {
-                    j.iters = j.inner_iters;
                     finish(j, PPCG_OK, st);
                     j.iters = j.inner_iters;
                     j.rel_recur = rel;
@@ -996,9 +1036,8 @@ ppcg_status Engine::step(int graph_iters)
                     j.iters = j.inner_iters;
                     j.rel_recur = rel;
                 } else {
-                    // inner budget: what is left of max_iter
                     SysDesc &d32 = g32_.desc_h[j.slot32];
-                    d32.maxit = o.max_iter - j.inner_iters;
+                    d32.maxit = o.max_iter - j.inner_iters;  // inner budget: what is left
                     PPCG_TRY(upload_desc(g32_, j.slot32));
                     start_mix.push_back(j.slot64);
                     j.stage = JS_ITER;
@@ -1006,9 +1045,6 @@ ppcg_status Engine::step(int graph_iters)
                 }
             }
         }
-        for (Job &j : jobs_)
-            if (!j.finished && j.stage == JS_NEED_INIT)
-                init64.push_back(j.slot64);
         if (!start_mix.empty()) {
             PPCG_TRY(aux_launch(g64_, start_mix, AUX_MIX_START));
             std::vector<int> s32;
@@ -1019,38 +1055,38 @@ ppcg_status Engine::step(int graph_iters)
             }
             PPCG_TRY(aux_launch(g32_, s32, AUX_INIT));
         }
-        (void)init64;
     }
-    // 2. initialisations and reliable updates of FP64-group jobs.
+    // 2. Initialisations and reliable updates.
     {
-        std::vector<int> init64, repl64;
+        std::vector<int> init64, initv, repl;
         for (Job &j : jobs_) {
             if (j.finished)
                 continue;
             if (j.stage == JS_NEED_INIT) {
-                init64.push_back(j.slot64);
+                (j.mixed == MIX_VALUES32 ? initv : init64).push_back(pslot(j));
                 j.stage = JS_ITER;
-                j.repl_ref = -1.0;
             } else if (j.stage == JS_NEED_REPL) {
-                repl64.push_back(j.slot64);
+                repl.push_back(j.slotv);
                 j.stage = JS_ITER;
-                j.repl_ref = -1.0;
                 ++j.outer;
+                if (j.outer >= j.h->opt.max_outer && gv_.desc_h[j.slotv].repl_factor > 0.0) {
+                    // budget spent: no further pauses, iterate to the end
+                    gv_.desc_h[j.slotv].repl_factor = 0.0;
+                    PPCG_TRY(upload_desc(gv_, j.slotv));
+                }
             }
         }
         PPCG_TRY(aux_launch(g64_, init64, AUX_INIT));
-        PPCG_TRY(aux_launch(g64_, repl64, AUX_REPL));
+        PPCG_TRY(aux_launch(gv_, initv, AUX_INIT));
+        PPCG_TRY(aux_launch(gv_, repl, AUX_REPL));
     }
-    // 3. iteration tables.
-    for (Group *g : {&g64_, &g32_}) {
+    // 3. Iteration tables.
+    for (Group *g : {&g64_, &g32_, &gv_}) {
         std::vector<WorkItem> items;
         for (const Job &j : jobs_) {
-            if (j.finished || j.stage != JS_ITER)
+            if (j.finished || j.stage != JS_ITER || &pgroup(j) != g)
                 continue;
-            const bool in_this = (g == &g32_) == (j.mixed == MIX_INNER32);
-            if (!in_this)
-                continue;
-            const int sl = j.mixed == MIX_INNER32 ? j.slot32 : j.slot64;
+            const int sl = pslot(j);
             for (int t = 0; t < g->desc_h[sl].ntiles; ++t)
                 items.push_back({sl, t});
         }
@@ -1061,8 +1097,8 @@ ppcg_status Engine::step(int graph_iters)
             g->table_dirty = true;
         }
     }
-    // 4. one graph chunk per non-empty group.
-    for (Group *g : {&g64_, &g32_}) {
+    // 4. One graph chunk per non-empty group.
+    for (Group *g : {&g64_, &g32_, &gv_}) {
         if (g->table_h.empty())
             continue;
         PPCG_TRY(ensure_table(*g));
@@ -1070,36 +1106,30 @@ ppcg_status Engine::step(int graph_iters)
         PPCG_TRY(ensure_graph(*g, chunk_iters(*g, graph_iters), &exec));
         PPCG_HIP(hipGraphLaunch(exec, stream_));
     }
-    // 5. poll.
-    PPCG_TRY(sync_states(g64_));
-    PPCG_TRY(sync_states(g32_));
+    // 5. Poll.
+    for (Group *g : {&g64_, &g32_, &gv_})
+        PPCG_TRY(sync_states(*g));
     PPCG_HIP(hipStreamSynchronize(stream_));
     for (Job &j : jobs_) {
         if (j.finished || j.stage != JS_ITER)
             continue;
-        const SysState &st = j.mixed == MIX_INNER32 ? g32_.st_h[j.slot32] : g64_.st_h[j.slot64];
-        const SysDesc &d = j.mixed == MIX_INNER32 ? g32_.desc_h[j.slot32] : g64_.desc_h[j.slot64];
+        const Group &g = pgroup(j);
+        const SysState &st = g.st_h[pslot(j)];
+        const SysDesc &d = g.desc_h[pslot(j)];
         if (st.done) {
             j.last_norm = -1.0;
-            if (j.mixed != MIX_INNER32) {
-                j.stage = JS_NEED_FINAL;
-            } else {
+            if (j.mixed == MIX_INNER32) {
                 j.inner_iters += st.iter;
                 j.precond_norm = std::sqrt(st.uu);
                 j.stage = JS_OUTER;
+            } else if (st.status == ST_REPLACE) {
+                j.stage = JS_NEED_REPL;
+            } else {
+                j.stage = JS_NEED_FINAL;
             }
         } else {
             j.last_norm = d.stop == STOP_ABS ? std::sqrt(st.uu) : std::sqrt(st.rr);
             j.last_iter = st.iter;
-            if (j.mixed == MIX_VALUES32) {
-                // reliable update once the residual fell by the replacement factor
-                const double rn = std::sqrt(st.rr);
-                const double f = j.h->opt.inner_tol > 0 ? j.h->opt.inner_tol : 1e-3;
-                if (j.repl_ref < 0)
-                    j.repl_ref = rn;
-                else if (rn < f * j.repl_ref && j.outer < j.h->opt.max_outer)
-                    j.stage = JS_NEED_REPL;
-            }
         }
     }
     return PPCG_OK;
