@@ -124,6 +124,8 @@ struct Job {
     int last_iter = 0;
     // MIX_VALUES32: residual norm right after the last replacement (-1: unknown)
     double repl_ref = -1.0;
+    // FP64 system small enough for the one-workgroup iteration kernel
+    bool small = false;
 };
 
 enum MixKind { MIX_NONE = 0, MIX_INNER32 = 1, MIX_VALUES32 = 2 };
@@ -195,12 +197,15 @@ class Engine {
     void drop_graphs(Group &g);
     int chunk_iters(const Group &g, int max_iters);
     // group and slot where a job iterates
-    Group &pgroup(const Job &j) { return j.mixed == MIX_INNER32 ? g32_ : j.mixed == MIX_VALUES32 ? gv_ : g64_; }
+    Group &pgroup(const Job &j)
+    {
+        return j.mixed == MIX_INNER32 ? g32_ : j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
+    }
     int pslot(const Job &j) const { return j.mixed == MIX_INNER32 ? j.slot32 : j.mixed == MIX_VALUES32 ? j.slotv : j.slot64; }
     ppcg_status sync_states(Group &g);
     int alloc_slot(Group &g);
     hipStream_t stream_;
-    Group g64_, g32_, gv_;
+    Group g64_, g32_, gv_, gs_;  // FP64, FP32 vectors, FP32 values, small FP64 systems
     std::vector<Job> jobs_;
 };
 

@@ -34,6 +34,12 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 #define PPCG_XCD_REMAP_SPMV 0
 #endif
 
+// Systems with at most this many rows (SELL format, FP64) iterate in the
+// one-workgroup kernel: for them launch latency, not bandwidth, dominates.
+#ifndef PPCG_SMALL_MAX_ROWS
+#define PPCG_SMALL_MAX_ROWS 8192
+#endif
+
 enum Fmt : int { FMT_SELL = 1, FMT_CSRV = 2 };
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_V32 = 2 /* FP32 values, FP64 vectors */ };
 

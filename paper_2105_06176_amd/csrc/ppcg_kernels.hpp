@@ -692,6 +692,65 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_spmv(const WorkItem *__rest
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small systems: one workgroup of kSmallThreads runs up to `iters` whole
+// PIPECG iterations of one system per launch (work item = system), with
+// workgroup barriers between the phases: fused update + partial sums, fixed
+// order reduction and scalar update (thread 0), SpMV.  No per-iteration
+// launches and no grid-wide synchronisation.  SELL format only.
+constexpr int kSmallThreads = 1024;
+
+__global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__restrict__ table,
+                                                              const int *__restrict__ count,
+                                                              const SysDesc *__restrict__ descs, int iters)
+{
+    __shared__ double lds[kSmallThreads / 64 * kNumPartials];
+    if ((int)blockIdx.x >= *count)
+        return;
+    const WorkItem wi = table[blockIdx.x];
+    const SysDesc &d = descs[wi.slot];
+    SysState *st = d.st;
+    const int n = d.n;
+    const int nchunks = (n + kSellC - 1) / kSellC;
+    double *__restrict__ X = (double *)d.x;
+    double *__restrict__ R = (double *)d.r;
+    double *__restrict__ U = (double *)d.u;
+    double *__restrict__ W = (double *)d.w;
+    double *__restrict__ M = (double *)d.m;
+    double *__restrict__ NVv = (double *)d.nv;
+    double *__restrict__ Z = (double *)d.z;
+    double *__restrict__ Q = (double *)d.q;
+    double *__restrict__ S = (double *)d.s;
+    double *__restrict__ P = (double *)d.p;
+    const double *__restrict__ DI = (const double *)d.dinv;
+    const double *__restrict__ val = (const double *)d.val;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int it = 0; it < iters; ++it) {
+        if (st->done)
+            break;  // read after a barrier: uniform across the workgroup
+        const double sa = st->alpha, sb = st->beta;
+        double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = threadIdx.x; i < n; i += kSmallThreads) {
+            double z = Z[i], q = Q[i], w = W[i], s = S[i], u = U[i], p = P[i], x = X[i], r = R[i], mo;
+            vma_elem<double, kNumPartials>(sa, sb, NVv[i], z, M[i], q, w, s, u, p, x, r, DI[i], mo, acc);
+            Z[i] = z; Q[i] = q; W[i] = w; S[i] = s; U[i] = u; P[i] = p; X[i] = x; R[i] = r; M[i] = mo;
+        }
+        block_sum<kSmallThreads, kNumPartials>(acc, lds);
+        if (threadIdx.x == 0)
+            scalar_update<kNumPartials>(d, st, acc);
+        __syncthreads();  // m complete; the new scalars visible
+        const double *const xin[1] = {M};
+        for (int c = wave; c < nchunks; c += kSmallThreads / 64) {
+            double y[1];
+            sell_row<double, double, 1>(d.cptr, d.col, val, xin, c, lane, y);
+            const int i = c * kSellC + lane;
+            if (i < n)
+                NVv[i] = y[0];
+        }
+        __syncthreads();  // n complete before the next update
+    }
+}
+
 // Reduce the true-residual partials of each system (tile-0 workgroups only).
 __global__ __launch_bounds__(kSpmvThreads) void k_reduce_resid(const WorkItem *__restrict__ table,
                                                                const int *__restrict__ count,

@@ -574,7 +574,7 @@ ppcg_status ensure_f32(ppcg_handle *h)
 // ---------------------------------------------------------------- engine
 Engine::~Engine()
 {
-    for (Group *g : {&g64_, &g32_, &gv_}) {
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
         if (g->st_d) (void)hipFree(g->st_d);
@@ -614,6 +614,7 @@ ppcg_status Engine::init(int cap_sys)
     PPCG_TRY(ensure_group(g64_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(g32_, PREC_F32, cap_sys));
     PPCG_TRY(ensure_group(gv_, PREC_V32, cap_sys));
+    PPCG_TRY(ensure_group(gs_, PREC_F64, cap_sys));
     return PPCG_OK;
 }
 
@@ -869,6 +870,22 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
         PPCG_TRY(upload_desc(gv_, j.slotv));
         PPCG_HIP(hipMemsetAsync(gv_.st_d + j.slotv, 0, sizeof(SysState), stream_));
         j.stage = JS_NEED_INIT;
+    } else if (mixed == MIX_NONE && h->fmt == FMT_SELL && h->n <= PPCG_SMALL_MAX_ROWS) {
+        j.small = true;
+        j.slot64 = alloc_slot(gs_);
+        if (j.slot64 < 0) {
+            set_error("engine has no free slot");
+            return PPCG_ERR_INVALID_ARG;
+        }
+        ppcg_status rc = fill_desc(h, PREC_F64, gs_.st_d + j.slot64, &gs_.desc_h[j.slot64], tol, o.fixed_iters,
+                                   o.max_iter, stop);
+        if (rc != PPCG_OK) {
+            gs_.slot_used[j.slot64] = 0;
+            return rc;
+        }
+        PPCG_TRY(upload_desc(gs_, j.slot64));
+        PPCG_HIP(hipMemsetAsync(gs_.st_d + j.slot64, 0, sizeof(SysState), stream_));
+        j.stage = JS_NEED_INIT;
     } else {
         j.slot64 = alloc_slot(g64_);
         if (j.slot64 < 0) {
@@ -938,7 +955,7 @@ void Engine::retire(int id)
 {
     Job &j = jobs_[id];
     if (j.slot64 >= 0)
-        g64_.slot_used[j.slot64] = 0;
+        (j.small ? gs_ : g64_).slot_used[j.slot64] = 0;
     if (j.slot32 >= 0)
         g32_.slot_used[j.slot32] = 0;
     if (j.slotv >= 0)
@@ -962,28 +979,33 @@ static void finish(Job &j, int status, const SysState &st)
     }
 }
 
+// Iterations per launch of the one-workgroup kernel (a few milliseconds).
+constexpr int kSmallChunkIters = 512;
+
 ppcg_status Engine::step(int graph_iters)
 {
     // 1. Jobs that need a true residual: stopped FP64 / FP32-values jobs, and
     //    FP32-vector jobs between inner solves (after adding the correction).
-    std::vector<int> resid64, residv, correct64;
+    std::vector<int> resid64, residv, resids, correct64;
     for (Job &j : jobs_) {
         if (j.finished)
             continue;
         if (j.stage == JS_NEED_FINAL)
-            (j.mixed == MIX_VALUES32 ? residv : resid64).push_back(pslot(j));
+            (j.mixed == MIX_VALUES32 ? residv : j.small ? resids : resid64).push_back(pslot(j));
         else if (j.stage == JS_OUTER) {
             if (j.outer > 0)
                 correct64.push_back(j.slot64);
             resid64.push_back(j.slot64);
         }
     }
-    if (!resid64.empty() || !residv.empty()) {
+    if (!resid64.empty() || !residv.empty() || !resids.empty()) {
         PPCG_TRY(aux_launch(g64_, correct64, AUX_MIX_CORRECT));
         PPCG_TRY(aux_launch(g64_, resid64, AUX_RESID));
         PPCG_TRY(aux_launch(gv_, residv, AUX_RESID));
+        PPCG_TRY(aux_launch(gs_, resids, AUX_RESID));
         PPCG_TRY(sync_states(g64_));
         PPCG_TRY(sync_states(gv_));
+        PPCG_TRY(sync_states(gs_));
         PPCG_HIP(hipStreamSynchronize(stream_));
         std::vector<int> start_mix;
         for (Job &j : jobs_) {
@@ -1058,12 +1080,12 @@ ppcg_status Engine::step(int graph_iters)
     }
     // 2. Initialisations and reliable updates.
     {
-        std::vector<int> init64, initv, repl;
+        std::vector<int> init64, initv, inits, repl;
         for (Job &j : jobs_) {
             if (j.finished)
                 continue;
             if (j.stage == JS_NEED_INIT) {
-                (j.mixed == MIX_VALUES32 ? initv : init64).push_back(pslot(j));
+                (j.mixed == MIX_VALUES32 ? initv : j.small ? inits : init64).push_back(pslot(j));
                 j.stage = JS_ITER;
             } else if (j.stage == JS_NEED_REPL) {
                 repl.push_back(j.slotv);
@@ -1078,16 +1100,18 @@ ppcg_status Engine::step(int graph_iters)
         }
         PPCG_TRY(aux_launch(g64_, init64, AUX_INIT));
         PPCG_TRY(aux_launch(gv_, initv, AUX_INIT));
+        PPCG_TRY(aux_launch(gs_, inits, AUX_INIT));
         PPCG_TRY(aux_launch(gv_, repl, AUX_REPL));
     }
-    // 3. Iteration tables.
-    for (Group *g : {&g64_, &g32_, &gv_}) {
+    // 3. Iteration tables (one work item per system in the small group).
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_}) {
         std::vector<WorkItem> items;
         for (const Job &j : jobs_) {
             if (j.finished || j.stage != JS_ITER || &pgroup(j) != g)
                 continue;
             const int sl = pslot(j);
-            for (int t = 0; t < g->desc_h[sl].ntiles; ++t)
+            const int nt = g == &gs_ ? 1 : g->desc_h[sl].ntiles;
+            for (int t = 0; t < nt; ++t)
                 items.push_back({sl, t});
         }
         if (items.size() != g->table_h.size() ||
@@ -1097,17 +1121,24 @@ ppcg_status Engine::step(int graph_iters)
             g->table_dirty = true;
         }
     }
-    // 4. One graph chunk per non-empty group.
-    for (Group *g : {&g64_, &g32_, &gv_}) {
+    // 4. One graph chunk per non-empty group; the small group runs its
+    //    chunk as a single launch of the one-workgroup kernel.
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_}) {
         if (g->table_h.empty())
             continue;
         PPCG_TRY(ensure_table(*g));
+        if (g == &gs_) {
+            k_small_iter<<<(int)gs_.table_h.size(), kSmallThreads, 0, stream_>>>(
+                gs_.table_d, gs_.count_d, gs_.desc_d, chunk_iters(gs_, kSmallChunkIters));
+            PPCG_HIP(hipGetLastError());
+            continue;
+        }
         hipGraphExec_t exec = nullptr;
         PPCG_TRY(ensure_graph(*g, chunk_iters(*g, graph_iters), &exec));
         PPCG_HIP(hipGraphLaunch(exec, stream_));
     }
     // 5. Poll.
-    for (Group *g : {&g64_, &g32_, &gv_})
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_})
         PPCG_TRY(sync_states(*g));
     PPCG_HIP(hipStreamSynchronize(stream_));
     for (Job &j : jobs_) {
