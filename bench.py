@@ -196,6 +196,48 @@ def leg_c3(torch, ppcg, wl):
     return out
 
 
+def leg_pcg(torch, ppcg, wl, iters=500):
+    """Algorithm 1 (classic PCG) beside Algorithm 2 (PIPECG) on the 128^3
+    7-point problem: fixed-iteration rate, kernel durations against their
+    byte models, and the solve to 1e-10."""
+    A = wl.poisson3d(128)
+    b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
+    bd = torch.as_tensor(b).cuda()
+    out = {"workload": "3D 7-point Poisson 128^3, FP64, fixed iterations and tol 1e-10"}
+    for method in ("pcg", "pipecg"):
+        S = ppcg.Solver(A, fixed_iters=20, method=method)
+        x = torch.empty_like(bd)
+        S.solve(bd, out=x)
+        S.set_options(fixed_iters=iters, method=method)
+        sync()
+        t0 = time.perf_counter()
+        _, info = S.solve(bd, out=x)
+        sync()
+        dt = time.perf_counter() - t0
+        mi = S.matrix_info()
+        ms_vma, ms_spmv = S.time_kernels(bd, iters=100)
+        S.set_options(tol=1e-10, max_iter=10000, method=method)
+        S.solve(bd)
+        sync()
+        t0 = time.perf_counter()
+        _, it = S.solve(bd)
+        sync()
+        ttol = time.perf_counter() - t0
+        out[method] = {"iters_per_s": round(iters / dt, 1), "us_per_iter": round(dt / iters * 1e6, 2),
+                       "bytes_per_iter": mi["bytes_per_iter"],
+                       "effective_gbs": round(mi["bytes_per_iter"] * iters / dt / 1e9, 1),
+                       "update_kernel_us": round(ms_vma * 1e3, 2),
+                       "update_kernel_gbs": round(mi["bytes_vma"] / (ms_vma * 1e-3) / 1e9, 1),
+                       "spmv_kernel_us": round(ms_spmv * 1e3, 2),
+                       "spmv_kernel_gbs": round(mi["bytes_spmv"] / (ms_spmv * 1e-3) / 1e9, 1),
+                       "tol_iters": it["iters"], "tol_status": it["status"],
+                       "tol_rel_resid_true": it["rel_resid_true"], "tol_time_s": round(ttol, 4)}
+        log(f"{method}: {out[method]}")
+        S.close()
+    out["pipecg_over_pcg_time_per_iter"] = round(out["pipecg"]["us_per_iter"] / out["pcg"]["us_per_iter"], 3)
+    return out
+
+
 def leg_c4(torch, ppcg, wl, count=256):
     spec = wl.batch_c4(seed=0, count=count)
     t0 = time.perf_counter()
@@ -341,7 +383,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    ap.add_argument("--legs", default="c1,c3,c4,c5,p125", help="extra legs: c1,c3,c4,c5,p125 or none")
+    ap.add_argument("--legs", default="c1,c3,c4,c5,p125,pcg", help="extra legs: c1,c3,c4,c5,p125,pcg or none")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 256 MiB (reference for HBM counters)")
@@ -383,6 +425,8 @@ def main():
                 legs[name] = leg_c1(torch, ppcg, wl, oracle)
             elif name == "c3":
                 legs[name] = leg_c3(torch, ppcg, wl)
+            elif name == "pcg":
+                legs[name] = leg_pcg(torch, ppcg, wl)
             elif name == "c4":
                 legs[name] = leg_c4(torch, ppcg, wl)
             elif name == "c5":

@@ -72,6 +72,16 @@ typedef enum {
                              auxiliary vectors are rebuilt from it */
 } ppcg_precision;
 
+/* Iteration scheme (ppcg_options.method). */
+typedef enum {
+    PPCG_METHOD_PIPECG = 0, /* Algorithm 2 (Section III-B): one fused vector update with all
+                               dot products, then the SpMV that overlaps their reduction
+                               (default) */
+    PPCG_METHOD_PCG = 1     /* Algorithm 1 (Section III-A): classic PCG, kept for comparison;
+                               two launches per iteration, each ending in a reduction the
+                               next launch waits for.  PPCG_FP64 only */
+} ppcg_method;
+
 typedef enum { PPCG_MEM_DEVICE = 0, PPCG_MEM_HOST = 1 } ppcg_mem;
 
 /* SpMV formats the autotuner chooses from (ppcg_options.spmv_format). */
@@ -116,6 +126,7 @@ typedef struct {
                                 reliable updates (0 = automatic) */
     int32_t max_outer;       /* mixed precision: maximum refinement steps / reliable
                                 updates (default 30) */
+    ppcg_method method;      /* default PPCG_METHOD_PIPECG */
     uint32_t flags;          /* reserved, must be 0 */
 } ppcg_options;
 
@@ -146,9 +157,12 @@ typedef struct {
     int32_t sell_sigma;      /* SELL sorting window (1 = unsorted) */
     int32_t lanes_per_row;   /* CSR-vector group size */
     int32_t tile_rows;       /* rows per workgroup tile */
-    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration (both kernels) */
-    double bytes_vma;        /* algorithmic bytes of one fused VMA+PC+dot launch */
-    double bytes_spmv;       /* algorithmic bytes of one SpMV launch */
+    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration (both kernels) of
+                                the handle's current method (opt.method) */
+    double bytes_vma;        /* algorithmic bytes of one vector-update launch (PIPECG: fused
+                                VMA+PC+dots, 20 vectors; PCG: 8 vectors) */
+    double bytes_spmv;       /* algorithmic bytes of one SpMV launch (matrix plus 2 vectors;
+                                PCG: plus 4, the direction update being fused into it) */
     double device_bytes;     /* device memory held by the handle */
     double setup_ms;         /* time spent in ppcg_create (validation, conversion, tuning) */
 } ppcg_matrix_info;
@@ -211,6 +225,9 @@ double ppcg_footprint_bytes(int32_t n, int64_t nnz, ppcg_precision precision);
  * updates + preconditioner + dot products, and its SpMV) over `iters`
  * iterations on the handle's stream, each launch bracketed by HIP events.
  * Runs the initialisation first, so the vectors hold a real iterate.
+ * With opt.method = PPCG_METHOD_PCG the two kernels of Algorithm 1 are
+ * timed instead (vector updates + preconditioner + dot products; SpMV with
+ * the direction update and (s, p)), each with its closing reduction.
  * ms_vma, ms_spmv: average launch duration in milliseconds (host pointers). */
 ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, double *ms_vma,
                               double *ms_spmv);

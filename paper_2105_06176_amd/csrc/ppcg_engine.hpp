@@ -126,6 +126,8 @@ struct Job {
     double repl_ref = -1.0;
     // FP64 system small enough for the one-workgroup iteration kernel
     bool small = false;
+    // classic PCG (Algorithm 1) instead of PIPECG
+    bool pcg = false;
 };
 
 enum MixKind { MIX_NONE = 0, MIX_INNER32 = 1, MIX_VALUES32 = 2 };
@@ -142,6 +144,7 @@ enum JobStage {
 // Per-precision set of system slots, work table and captured graph.
 struct Group {
     int prec = PREC_F64;
+    bool pcg = false;               // iterates Algorithm 1 (two launches per iteration, PAR alternating)
     int cap_sys = 0;
     SysDesc *desc_d = nullptr;
     SysState *st_d = nullptr;
@@ -199,13 +202,14 @@ class Engine {
     // group and slot where a job iterates
     Group &pgroup(const Job &j)
     {
-        return j.mixed == MIX_INNER32 ? g32_ : j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
+        return j.pcg ? gp_ : j.mixed == MIX_INNER32 ? g32_ : j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
     }
     int pslot(const Job &j) const { return j.mixed == MIX_INNER32 ? j.slot32 : j.mixed == MIX_VALUES32 ? j.slotv : j.slot64; }
     ppcg_status sync_states(Group &g);
     int alloc_slot(Group &g);
     hipStream_t stream_;
     Group g64_, g32_, gv_, gs_;  // FP64, FP32 vectors, FP32 values, small FP64 systems
+    Group gp_;                   // classic PCG (FP64)
     std::vector<Job> jobs_;
 };
 

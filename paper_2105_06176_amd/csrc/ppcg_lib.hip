@@ -23,6 +23,7 @@
 
 #include "ppcg_engine.hpp"
 #include "ppcg_kernels.hpp"
+#include "ppcg_pcg.hpp"
 #include "ppcg_setup.hpp"
 
 namespace ppcg {
@@ -118,9 +119,12 @@ static ppcg_status check_dev_range(const void *p, size_t bytes, const char *what
 }
 
 // ---------------------------------------------------------------- byte model
-// Algorithmic HBM bytes of one iteration: the fused update reads 11 vectors
-// and writes 9; the SpMV reads values and column indices of every stored
-// entry, its row/chunk pointers, the input vector once, and writes one vector.
+// Algorithmic HBM bytes of one iteration.  PIPECG: the fused update reads 11
+// vectors and writes 9; the SpMV reads values and column indices of every
+// stored entry, its row/chunk pointers, the input vector once, and writes one
+// vector.  Classic PCG: the update reads x, p, r, s and the inverse diagonal
+// and writes x, r, u (8 vectors); the SpMV reads u and the previous direction
+// once each and writes the new direction and s (4 vectors) besides the matrix.
 struct ByteModel {
     double vma, spmv;
 };
@@ -130,10 +134,11 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     const double ve = prec == PREC_F32 ? 4.0 : 8.0;   // vector element
     const double me = prec == PREC_F64 ? 8.0 : 4.0;   // matrix value
     const double n = h->n;
+    const bool pcg = h->opt.method == PPCG_METHOD_PCG;
     ByteModel bm;
-    bm.vma = 20.0 * ve * n;
+    bm.vma = (pcg ? 8.0 : 20.0) * ve * n;
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
-    bm.spmv = (me + 4.0) * (double)h->nnz + ptr + 2.0 * ve * n;
+    bm.spmv = (me + 4.0) * (double)h->nnz + ptr + (pcg ? 4.0 : 2.0) * ve * n;
     return bm;
 }
 
@@ -574,7 +579,7 @@ ppcg_status ensure_f32(ppcg_handle *h)
 // ---------------------------------------------------------------- engine
 Engine::~Engine()
 {
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_}) {
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
         if (g->st_d) (void)hipFree(g->st_d);
@@ -615,6 +620,8 @@ ppcg_status Engine::init(int cap_sys)
     PPCG_TRY(ensure_group(g32_, PREC_F32, cap_sys));
     PPCG_TRY(ensure_group(gv_, PREC_V32, cap_sys));
     PPCG_TRY(ensure_group(gs_, PREC_F64, cap_sys));
+    PPCG_TRY(ensure_group(gp_, PREC_F64, cap_sys));
+    gp_.pcg = true;
     return PPCG_OK;
 }
 
@@ -676,7 +683,14 @@ static ppcg_status upload_table(hipStream_t s, Group &g, const std::vector<WorkI
 // that also emits the direct-denominator partials.
 static void launch_iter_pair(hipStream_t s, const Group &g, int grid, int remap)
 {
-    if (g.prec == PREC_F32) {
+    if (g.pcg) {
+        // Two Algorithm 1 iterations: the direction alternates between the
+        // p and z buffers, so a chunk always holds an even number of them.
+        k_pcg_spmv<0><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        k_pcg_vma<0><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+        k_pcg_spmv<1><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        k_pcg_vma<1><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+    } else if (g.prec == PREC_F32) {
         k_vma<float><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
         k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
     } else if (g.prec == PREC_V32) {
@@ -729,7 +743,7 @@ ppcg_status Engine::ensure_graph(Group &g, int iters, hipGraphExec_t *exec)
     const int grid = g.g_grid ? g.g_grid : need;
     Group::CapturedGraph cg;
     PPCG_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < iters; ++i)
+    for (int i = 0; i < (g.pcg ? iters / 2 : iters); ++i)
         launch_iter_pair(stream_, g, grid, remap);
     hipError_t e = hipStreamEndCapture(stream_, &cg.graph);
     if (e != hipSuccess) {
@@ -775,7 +789,7 @@ int Engine::chunk_iters(const Group &g, int max_iters)
     int k = 1;
     while (k * 2 <= want)
         k *= 2;
-    return k;
+    return g.pcg ? std::max(k, 2) : k;
 }
 
 ppcg_status Engine::sync_states(Group &g)
@@ -805,7 +819,10 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     const SysDesc *dd = g.desc_d;
     const int rs = PPCG_XCD_REMAP_SPMV;
     const bool f32 = g.prec == PREC_F32;
-    if (what == AUX_INIT) {
+    if (what == AUX_INIT && g.pcg) {
+        k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        k_pcg_init<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+    } else if (what == AUX_INIT) {
         if (f32) {
             k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
             k_spmv<float, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
@@ -854,7 +871,27 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
         release();
         return s;
     };
-    if (mixed == MIX_VALUES32) {
+    if (o.method == PPCG_METHOD_PCG) {
+        if (mixed != MIX_NONE) {
+            set_error("classic PCG runs in FP64 only");
+            return PPCG_ERR_INVALID_ARG;
+        }
+        j.pcg = true;
+        j.slot64 = alloc_slot(gp_);
+        if (j.slot64 < 0) {
+            set_error("engine has no free slot");
+            return PPCG_ERR_INVALID_ARG;
+        }
+        ppcg_status rc = fill_desc(h, PREC_F64, gp_.st_d + j.slot64, &gp_.desc_h[j.slot64], tol, o.fixed_iters,
+                                   o.max_iter, stop);
+        if (rc != PPCG_OK) {
+            gp_.slot_used[j.slot64] = 0;
+            return rc;
+        }
+        PPCG_TRY(upload_desc(gp_, j.slot64));
+        PPCG_HIP(hipMemsetAsync(gp_.st_d + j.slot64, 0, sizeof(SysState), stream_));
+        j.stage = JS_NEED_INIT;
+    } else if (mixed == MIX_VALUES32) {
         j.slotv = alloc_slot(gv_);
         if (j.slotv < 0) {
             set_error("engine has no free slot");
@@ -955,7 +992,7 @@ void Engine::retire(int id)
 {
     Job &j = jobs_[id];
     if (j.slot64 >= 0)
-        (j.small ? gs_ : g64_).slot_used[j.slot64] = 0;
+        (j.pcg ? gp_ : j.small ? gs_ : g64_).slot_used[j.slot64] = 0;
     if (j.slot32 >= 0)
         g32_.slot_used[j.slot32] = 0;
     if (j.slotv >= 0)
@@ -986,26 +1023,28 @@ ppcg_status Engine::step(int graph_iters)
 {
     // 1. Jobs that need a true residual: stopped FP64 / FP32-values jobs, and
     //    FP32-vector jobs between inner solves (after adding the correction).
-    std::vector<int> resid64, residv, resids, correct64;
+    std::vector<int> resid64, residv, resids, residp, correct64;
     for (Job &j : jobs_) {
         if (j.finished)
             continue;
         if (j.stage == JS_NEED_FINAL)
-            (j.mixed == MIX_VALUES32 ? residv : j.small ? resids : resid64).push_back(pslot(j));
+            (j.pcg ? residp : j.mixed == MIX_VALUES32 ? residv : j.small ? resids : resid64).push_back(pslot(j));
         else if (j.stage == JS_OUTER) {
             if (j.outer > 0)
                 correct64.push_back(j.slot64);
             resid64.push_back(j.slot64);
         }
     }
-    if (!resid64.empty() || !residv.empty() || !resids.empty()) {
+    if (!resid64.empty() || !residv.empty() || !resids.empty() || !residp.empty()) {
         PPCG_TRY(aux_launch(g64_, correct64, AUX_MIX_CORRECT));
         PPCG_TRY(aux_launch(g64_, resid64, AUX_RESID));
         PPCG_TRY(aux_launch(gv_, residv, AUX_RESID));
         PPCG_TRY(aux_launch(gs_, resids, AUX_RESID));
+        PPCG_TRY(aux_launch(gp_, residp, AUX_RESID));
         PPCG_TRY(sync_states(g64_));
         PPCG_TRY(sync_states(gv_));
         PPCG_TRY(sync_states(gs_));
+        PPCG_TRY(sync_states(gp_));
         PPCG_HIP(hipStreamSynchronize(stream_));
         std::vector<int> start_mix;
         for (Job &j : jobs_) {
@@ -1080,12 +1119,12 @@ ppcg_status Engine::step(int graph_iters)
     }
     // 2. Initialisations and reliable updates.
     {
-        std::vector<int> init64, initv, inits, repl;
+        std::vector<int> init64, initv, inits, initp, repl;
         for (Job &j : jobs_) {
             if (j.finished)
                 continue;
             if (j.stage == JS_NEED_INIT) {
-                (j.mixed == MIX_VALUES32 ? initv : j.small ? inits : init64).push_back(pslot(j));
+                (j.pcg ? initp : j.mixed == MIX_VALUES32 ? initv : j.small ? inits : init64).push_back(pslot(j));
                 j.stage = JS_ITER;
             } else if (j.stage == JS_NEED_REPL) {
                 repl.push_back(j.slotv);
@@ -1101,10 +1140,11 @@ ppcg_status Engine::step(int graph_iters)
         PPCG_TRY(aux_launch(g64_, init64, AUX_INIT));
         PPCG_TRY(aux_launch(gv_, initv, AUX_INIT));
         PPCG_TRY(aux_launch(gs_, inits, AUX_INIT));
+        PPCG_TRY(aux_launch(gp_, initp, AUX_INIT));
         PPCG_TRY(aux_launch(gv_, repl, AUX_REPL));
     }
     // 3. Iteration tables (one work item per system in the small group).
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_}) {
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_}) {
         std::vector<WorkItem> items;
         for (const Job &j : jobs_) {
             if (j.finished || j.stage != JS_ITER || &pgroup(j) != g)
@@ -1123,7 +1163,7 @@ ppcg_status Engine::step(int graph_iters)
     }
     // 4. One graph chunk per non-empty group; the small group runs its
     //    chunk as a single launch of the one-workgroup kernel.
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_}) {
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_}) {
         if (g->table_h.empty())
             continue;
         PPCG_TRY(ensure_table(*g));
@@ -1138,7 +1178,7 @@ ppcg_status Engine::step(int graph_iters)
         PPCG_HIP(hipGraphLaunch(exec, stream_));
     }
     // 5. Poll.
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_})
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_})
         PPCG_TRY(sync_states(*g));
     PPCG_HIP(hipStreamSynchronize(stream_));
     for (Job &j : jobs_) {
@@ -1310,6 +1350,7 @@ ppcg_status ppcg_default_options(ppcg_options *opt)
     opt->graph_iters = 0;
     opt->inner_tol = 0.0;
     opt->max_outer = 30;
+    opt->method = PPCG_METHOD_PIPECG;
     opt->flags = 0;
     return PPCG_OK;
 }
@@ -1328,7 +1369,8 @@ static ppcg_status check_options(const ppcg_options *o)
         (o->vec_mem != PPCG_MEM_DEVICE && o->vec_mem != PPCG_MEM_HOST) ||
         (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
          o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
-        o->flags != 0) {
+        (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
+        (o->method == PPCG_METHOD_PCG && o->precision != PPCG_FP64) || o->flags != 0) {
         set_error("invalid option value");
         return PPCG_ERR_INVALID_ARG;
     }
@@ -1698,18 +1740,36 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     const WorkItem *tab = h->plain_tab;
     const int *cnt = h->plain_cnt;
     const SysDesc *dd = h->plain_desc;
+    const bool pcg = h->opt.method == PPCG_METHOD_PCG;
     k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
-    k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
-    k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
+    if (pcg) {
+        k_pcg_init<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+    } else {
+        k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
+        k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
+    }
     for (auto &e : ev)
         PPCG_HIP_CLEAN(hipEventCreate(&e), clean());
     // Events attached to each launch (start/stop of the kernel itself), so
     // the durations exclude the gaps between launches.
     for (int i = 0; i < iters; ++i) {
-        hipExtLaunchKernelGGL(k_vma<double>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0,
-                              tab, cnt, dd, (int)PPCG_XCD_REMAP);
-        hipExtLaunchKernelGGL((k_spmv<double, MODE_ITER>), dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2],
-                              ev[4 * i + 3], 0, tab, cnt, dd, (int)PPCG_XCD_REMAP_SPMV);
+        const int rv = (int)PPCG_XCD_REMAP, rs = (int)PPCG_XCD_REMAP_SPMV;
+        if (pcg && (i & 1) == 0) {
+            hipExtLaunchKernelGGL(k_pcg_spmv<0>, dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2], ev[4 * i + 3],
+                                  0, tab, cnt, dd, rs);
+            hipExtLaunchKernelGGL(k_pcg_vma<0>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0,
+                                  tab, cnt, dd, rv);
+        } else if (pcg) {
+            hipExtLaunchKernelGGL(k_pcg_spmv<1>, dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2], ev[4 * i + 3],
+                                  0, tab, cnt, dd, rs);
+            hipExtLaunchKernelGGL(k_pcg_vma<1>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0,
+                                  tab, cnt, dd, rv);
+        } else {
+            hipExtLaunchKernelGGL(k_vma<double>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0,
+                                  tab, cnt, dd, rv);
+            hipExtLaunchKernelGGL((k_spmv<double, MODE_ITER>), dim3(grid), dim3(kSpmvThreads), 0, s,
+                                  ev[4 * i + 2], ev[4 * i + 3], 0, tab, cnt, dd, rs);
+        }
     }
     PPCG_HIP_CLEAN(hipGetLastError(), clean());
     PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());

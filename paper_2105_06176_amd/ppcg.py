@@ -21,11 +21,13 @@ ERR_INVALID_ARG, ERR_BAD_CSR, ERR_NOMEM, ERR_DEVICE, ERR_BUDGET = -1, -2, -3, -4
 STOP_REL_RESID, STOP_PRECOND_ABS = 0, 1
 FP64, MIXED_FP32, MIXED_FP32_VALUES = 0, 1, 2
 MEM_DEVICE, MEM_HOST = 0, 1
+METHOD_PIPECG, METHOD_PCG = 0, 1
 SPMV_AUTO, SPMV_SELL, SPMV_CSR_VECTOR = 0, 1, 2
 
 _STOP = {"rel": STOP_REL_RESID, "abs": STOP_PRECOND_ABS}
 _PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_values": MIXED_FP32_VALUES}
 _FMT = {"auto": SPMV_AUTO, "sell": SPMV_SELL, "csr_vector": SPMV_CSR_VECTOR}
+_METHOD = {"pipecg": METHOD_PIPECG, "pcg": METHOD_PCG}
 
 
 class Csr(ctypes.Structure):
@@ -39,7 +41,7 @@ class Options(ctypes.Structure):
                 ("fixed_iters", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("stop", ctypes.c_int),
                 ("precision", ctypes.c_int), ("vec_mem", ctypes.c_int), ("spmv_format", ctypes.c_int),
                 ("graph_iters", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("method", ctypes.c_int), ("flags", ctypes.c_uint32)]
 
 
 class Info(ctypes.Structure):
@@ -140,6 +142,8 @@ def make_options(**kw) -> Options:
             v = _PREC.get(v, v)
         elif k == "spmv_format":
             v = _FMT.get(v, v)
+        elif k == "method":
+            v = _METHOD.get(v, v)
         elif k == "vec_mem":
             v = {"device": MEM_DEVICE, "host": MEM_HOST}.get(v, v)
         setattr(o, k, v)
