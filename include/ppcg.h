@@ -77,9 +77,11 @@ typedef enum {
     PPCG_METHOD_PIPECG = 0, /* Algorithm 2 (Section III-B): one fused vector update with all
                                dot products, then the SpMV that overlaps their reduction
                                (default) */
-    PPCG_METHOD_PCG = 1     /* Algorithm 1 (Section III-A): classic PCG, kept for comparison;
-                               two launches per iteration, each ending in a reduction the
-                               next launch waits for.  PPCG_FP64 only */
+    PPCG_METHOD_PCG = 1     /* Algorithm 1 (Section III-A): classic PCG; two launches per
+                               iteration, each ending in a reduction the next launch waits
+                               for.  With PPCG_FP64 or PPCG_MIXED_FP32_VALUES (FP32 values,
+                               reliable updates r = b - A x keeping the direction); not with
+                               PPCG_MIXED_FP32 (ERR_INVALID_ARG) */
 } ppcg_method;
 
 typedef enum { PPCG_MEM_DEVICE = 0, PPCG_MEM_HOST = 1 } ppcg_mem;

@@ -202,14 +202,16 @@ class Engine {
     // group and slot where a job iterates
     Group &pgroup(const Job &j)
     {
-        return j.pcg ? gp_ : j.mixed == MIX_INNER32 ? g32_ : j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
+        if (j.pcg)
+            return j.mixed == MIX_VALUES32 ? gpv_ : gp_;
+        return j.mixed == MIX_INNER32 ? g32_ : j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
     }
     int pslot(const Job &j) const { return j.mixed == MIX_INNER32 ? j.slot32 : j.mixed == MIX_VALUES32 ? j.slotv : j.slot64; }
     ppcg_status sync_states(Group &g);
     int alloc_slot(Group &g);
     hipStream_t stream_;
     Group g64_, g32_, gv_, gs_;  // FP64, FP32 vectors, FP32 values, small FP64 systems
-    Group gp_;                   // classic PCG (FP64)
+    Group gp_, gpv_;             // classic PCG: FP64, FP32 values
     std::vector<Job> jobs_;
 };
 

@@ -579,7 +579,7 @@ ppcg_status ensure_f32(ppcg_handle *h)
 // ---------------------------------------------------------------- engine
 Engine::~Engine()
 {
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_}) {
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
         if (g->st_d) (void)hipFree(g->st_d);
@@ -621,7 +621,8 @@ ppcg_status Engine::init(int cap_sys)
     PPCG_TRY(ensure_group(gv_, PREC_V32, cap_sys));
     PPCG_TRY(ensure_group(gs_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(gp_, PREC_F64, cap_sys));
-    gp_.pcg = true;
+    PPCG_TRY(ensure_group(gpv_, PREC_V32, cap_sys));
+    gp_.pcg = gpv_.pcg = true;
     return PPCG_OK;
 }
 
@@ -821,7 +822,11 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     const bool f32 = g.prec == PREC_F32;
     if (what == AUX_INIT && g.pcg) {
         k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        k_pcg_init<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_restart<PCG_START><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+    } else if (what == AUX_REPL && g.pcg) {
+        // Reliable update of classic PCG: r = b - A64 x, u = M^-1 r; p is kept.
+        k_spmv<double, MODE_REPL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        k_pcg_restart<PCG_REPL><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_INIT) {
         if (f32) {
             k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
@@ -872,24 +877,31 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
         return s;
     };
     if (o.method == PPCG_METHOD_PCG) {
-        if (mixed != MIX_NONE) {
-            set_error("classic PCG runs in FP64 only");
+        if (mixed == MIX_INNER32) {
+            set_error("classic PCG runs in FP64 or with FP32 matrix values only");
             return PPCG_ERR_INVALID_ARG;
         }
         j.pcg = true;
-        j.slot64 = alloc_slot(gp_);
-        if (j.slot64 < 0) {
+        const bool v32 = mixed == MIX_VALUES32;
+        Group &g = v32 ? gpv_ : gp_;
+        int &slot = v32 ? j.slotv : j.slot64;
+        slot = alloc_slot(g);
+        if (slot < 0) {
             set_error("engine has no free slot");
             return PPCG_ERR_INVALID_ARG;
         }
-        ppcg_status rc = fill_desc(h, PREC_F64, gp_.st_d + j.slot64, &gp_.desc_h[j.slot64], tol, o.fixed_iters,
-                                   o.max_iter, stop);
+        ppcg_status rc = v32 ? ensure_val32(h) : PPCG_OK;
+        if (rc == PPCG_OK)
+            rc = fill_desc(h, PREC_F64, g.st_d + slot, &g.desc_h[slot], tol, o.fixed_iters, o.max_iter, stop,
+                           v32 ? 1 : 0);
         if (rc != PPCG_OK) {
-            gp_.slot_used[j.slot64] = 0;
+            g.slot_used[slot] = 0;
             return rc;
         }
-        PPCG_TRY(upload_desc(gp_, j.slot64));
-        PPCG_HIP(hipMemsetAsync(gp_.st_d + j.slot64, 0, sizeof(SysState), stream_));
+        if (v32)
+            g.desc_h[slot].repl_factor = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+        PPCG_TRY(upload_desc(g, slot));
+        PPCG_HIP(hipMemsetAsync(g.st_d + slot, 0, sizeof(SysState), stream_));
         j.stage = JS_NEED_INIT;
     } else if (mixed == MIX_VALUES32) {
         j.slotv = alloc_slot(gv_);
@@ -996,7 +1008,7 @@ void Engine::retire(int id)
     if (j.slot32 >= 0)
         g32_.slot_used[j.slot32] = 0;
     if (j.slotv >= 0)
-        gv_.slot_used[j.slotv] = 0;
+        (j.pcg ? gpv_ : gv_).slot_used[j.slotv] = 0;
     j.slot64 = j.slot32 = j.slotv = -1;
     j.h = nullptr;
 }
@@ -1023,28 +1035,27 @@ ppcg_status Engine::step(int graph_iters)
 {
     // 1. Jobs that need a true residual: stopped FP64 / FP32-values jobs, and
     //    FP32-vector jobs between inner solves (after adding the correction).
-    std::vector<int> resid64, residv, resids, residp, correct64;
+    Group *const groups[] = {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_};
+    std::map<Group *, std::vector<int>> resid;  // slots per group
+    std::vector<int> correct64;
     for (Job &j : jobs_) {
         if (j.finished)
             continue;
         if (j.stage == JS_NEED_FINAL)
-            (j.pcg ? residp : j.mixed == MIX_VALUES32 ? residv : j.small ? resids : resid64).push_back(pslot(j));
+            resid[&pgroup(j)].push_back(pslot(j));
         else if (j.stage == JS_OUTER) {
             if (j.outer > 0)
                 correct64.push_back(j.slot64);
-            resid64.push_back(j.slot64);
+            resid[&g64_].push_back(j.slot64);
         }
     }
-    if (!resid64.empty() || !residv.empty() || !resids.empty() || !residp.empty()) {
+    if (!resid.empty()) {
         PPCG_TRY(aux_launch(g64_, correct64, AUX_MIX_CORRECT));
-        PPCG_TRY(aux_launch(g64_, resid64, AUX_RESID));
-        PPCG_TRY(aux_launch(gv_, residv, AUX_RESID));
-        PPCG_TRY(aux_launch(gs_, resids, AUX_RESID));
-        PPCG_TRY(aux_launch(gp_, residp, AUX_RESID));
-        PPCG_TRY(sync_states(g64_));
-        PPCG_TRY(sync_states(gv_));
-        PPCG_TRY(sync_states(gs_));
-        PPCG_TRY(sync_states(gp_));
+        for (Group *g : groups)
+            if (resid.count(g)) {
+                PPCG_TRY(aux_launch(*g, resid[g], AUX_RESID));
+                PPCG_TRY(sync_states(*g));
+            }
         PPCG_HIP(hipStreamSynchronize(stream_));
         std::vector<int> start_mix;
         for (Job &j : jobs_) {
@@ -1119,32 +1130,34 @@ ppcg_status Engine::step(int graph_iters)
     }
     // 2. Initialisations and reliable updates.
     {
-        std::vector<int> init64, initv, inits, initp, repl;
+        std::map<Group *, std::vector<int>> init, repl;
         for (Job &j : jobs_) {
             if (j.finished)
                 continue;
             if (j.stage == JS_NEED_INIT) {
-                (j.pcg ? initp : j.mixed == MIX_VALUES32 ? initv : j.small ? inits : init64).push_back(pslot(j));
+                init[&pgroup(j)].push_back(pslot(j));
                 j.stage = JS_ITER;
             } else if (j.stage == JS_NEED_REPL) {
-                repl.push_back(j.slotv);
+                Group &g = pgroup(j);
+                repl[&g].push_back(j.slotv);
                 j.stage = JS_ITER;
                 ++j.outer;
-                if (j.outer >= j.h->opt.max_outer && gv_.desc_h[j.slotv].repl_factor > 0.0) {
+                if (j.outer >= j.h->opt.max_outer && g.desc_h[j.slotv].repl_factor > 0.0) {
                     // budget spent: no further pauses, iterate to the end
-                    gv_.desc_h[j.slotv].repl_factor = 0.0;
-                    PPCG_TRY(upload_desc(gv_, j.slotv));
+                    g.desc_h[j.slotv].repl_factor = 0.0;
+                    PPCG_TRY(upload_desc(g, j.slotv));
                 }
             }
         }
-        PPCG_TRY(aux_launch(g64_, init64, AUX_INIT));
-        PPCG_TRY(aux_launch(gv_, initv, AUX_INIT));
-        PPCG_TRY(aux_launch(gs_, inits, AUX_INIT));
-        PPCG_TRY(aux_launch(gp_, initp, AUX_INIT));
-        PPCG_TRY(aux_launch(gv_, repl, AUX_REPL));
+        for (Group *g : groups) {
+            if (init.count(g))
+                PPCG_TRY(aux_launch(*g, init[g], AUX_INIT));
+            if (repl.count(g))
+                PPCG_TRY(aux_launch(*g, repl[g], AUX_REPL));
+        }
     }
     // 3. Iteration tables (one work item per system in the small group).
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_}) {
+    for (Group *g : groups) {
         std::vector<WorkItem> items;
         for (const Job &j : jobs_) {
             if (j.finished || j.stage != JS_ITER || &pgroup(j) != g)
@@ -1163,7 +1176,7 @@ ppcg_status Engine::step(int graph_iters)
     }
     // 4. One graph chunk per non-empty group; the small group runs its
     //    chunk as a single launch of the one-workgroup kernel.
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_}) {
+    for (Group *g : groups) {
         if (g->table_h.empty())
             continue;
         PPCG_TRY(ensure_table(*g));
@@ -1178,7 +1191,7 @@ ppcg_status Engine::step(int graph_iters)
         PPCG_HIP(hipGraphLaunch(exec, stream_));
     }
     // 5. Poll.
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_})
+    for (Group *g : groups)
         PPCG_TRY(sync_states(*g));
     PPCG_HIP(hipStreamSynchronize(stream_));
     for (Job &j : jobs_) {
@@ -1370,7 +1383,7 @@ static ppcg_status check_options(const ppcg_options *o)
         (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
          o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
         (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
-        (o->method == PPCG_METHOD_PCG && o->precision != PPCG_FP64) || o->flags != 0) {
+        (o->method == PPCG_METHOD_PCG && o->precision == PPCG_MIXED_FP32) || o->flags != 0) {
         set_error("invalid option value");
         return PPCG_ERR_INVALID_ARG;
     }
@@ -1743,7 +1756,7 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     const bool pcg = h->opt.method == PPCG_METHOD_PCG;
     k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
     if (pcg) {
-        k_pcg_init<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_restart<PCG_START><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
     } else {
         k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
         k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);

@@ -1,5 +1,6 @@
 // ppcg_pcg.hpp -- classic PCG (Algorithm 1 of Tiwari & Vadhiyar, Section
-// III-A) on the device, for comparison with the pipelined method.
+// III-A) on the device, for comparison with the pipelined method, and as the
+// iteration of the FP32-values mode when selected.
 //
 // One iteration is two launches over the same (system, tile) work table:
 //
@@ -15,6 +16,13 @@
 // Unlike Algorithm 2, each iteration has two reductions that the next launch
 // depends on, so they are done by the last-arriving workgroup.  PAR selects
 // which of p / z holds the previous direction; iterations alternate PAR.
+//
+// FP32-values mode (d.vals32): s = A32 p with FP32 matrix values, FP64
+// vectors and accumulation.  When the recurrence residual has fallen by
+// d.repl_factor since the last start or reliable update, the system pauses
+// (ST_REPLACE); the host then recomputes r = b - A64 x and u = M^-1 r and the
+// iteration continues with the same direction (beta from the replaced
+// residual), the residual-replacement scheme for classic CG.
 #pragma once
 
 #include "ppcg_kernels.hpp"
@@ -24,7 +32,6 @@ namespace ppcg {
 // Last-workgroup reduction: every workgroup publishes its record, then
 // increments the system's ticket; the one that brings it to ntiles reduces
 // all records in tile order.  Returns true (in every thread) for that one.
-template <int NT>
 __device__ __forceinline__ bool arrive_last(const SysDesc &d, SysState *st, int *flag)
 {
     __syncthreads();  // this workgroup's partial record is written (thread 0)
@@ -38,6 +45,82 @@ __device__ __forceinline__ bool arrive_last(const SysDesc &d, SysState *st, int 
     if (last)
         __threadfence();  // acquire: see every other workgroup's record
     return last;
+}
+
+// s = A p for one tile with p = u + beta p_old formed per gathered entry;
+// returns this thread's share of (s, p).
+template <typename VT>
+__device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem wi, const VT *__restrict__ val,
+                                                double beta, const double *__restrict__ U,
+                                                const double *__restrict__ Pold, double *__restrict__ Pnew,
+                                                double *__restrict__ S)
+{
+    const int n = d.n;
+    double acc = 0.0;
+    if (d.fmt == FMT_SELL) {
+        const int lane = threadIdx.x & 63;
+        const int chunk = wi.tile * kSellChunksPerTile + (threadIdx.x >> 6);
+        const int i = chunk * kSellC + lane;
+        if (chunk * kSellC < n) {
+            constexpr int B = 8;
+            const int64_t base = d.cptr[chunk];
+            const int len = (int)((d.cptr[chunk + 1] - base) / kSellC);
+            const int *c = d.col + base + lane;
+            const VT *v = val + base + lane;
+            double y = 0.0;
+            for (int k0 = 0; k0 < len; k0 += B) {
+                int cc[B];
+                double vv[B], xx[B];
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    cc[j] = 0;
+                    vv[j] = 0.0;
+                    if (k0 + j < len) {
+                        cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
+                        vv[j] = (double)stream_load(v + (size_t)(k0 + j) * kSellC);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < B; ++j)
+                    xx[j] = k0 + j < len ? U[cc[j]] + beta * Pold[cc[j]] : 0.0;
+#pragma unroll
+                for (int j = 0; j < B; ++j)
+                    if (k0 + j < len)
+                        y = y + vv[j] * xx[j];
+            }
+            if (i < n) {
+                const double pn = U[i] + beta * Pold[i];
+                Pnew[i] = pn;
+                S[i] = y;
+                acc = acc + y * pn;
+            }
+        }
+    } else {
+        const int L = d.lanes;
+        const int g = threadIdx.x / L, l = threadIdx.x % L;
+        const int rows_per_pass = kSpmvThreads / L;
+        const int passes = kTileRows / rows_per_pass;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int i = wi.tile * kTileRows + pass * rows_per_pass + g;
+            double y = 0.0;
+            if (i < n) {
+                const int e = d.rp[i + 1];
+                for (int k = d.rp[i] + l; k < e; k += L) {
+                    const int cc = stream_load(d.col + k);
+                    y = y + (double)stream_load(val + k) * (U[cc] + beta * Pold[cc]);
+                }
+            }
+            for (int off = L >> 1; off >= 1; off >>= 1)
+                y = y + __shfl_xor(y, off, 64);
+            if (l == 0 && i < n) {
+                const double pn = U[i] + beta * Pold[i];
+                Pnew[i] = pn;
+                S[i] = y;
+                acc = acc + y * pn;
+            }
+        }
+    }
+    return acc;
 }
 
 template <int PAR>
@@ -56,79 +139,19 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__
     if (st->done)
         return;
     const double beta = st->beta;
-    const double *__restrict__ U = (const double *)d.u;
-    const double *__restrict__ Pold = (const double *)(PAR ? d.z : d.p);
-    double *__restrict__ Pnew = (double *)(PAR ? d.p : d.z);
-    double *__restrict__ S = (double *)d.s;
-    const double *__restrict__ val = (const double *)d.val;
-    const int n = d.n;
-    double acc = 0.0;
-    auto row_out = [&](int i, double y) {
-        const double pn = U[i] + beta * Pold[i];
-        Pnew[i] = pn;
-        S[i] = y;
-        acc = acc + y * pn;
-    };
-    if (d.fmt == FMT_SELL) {
-        const int lane = threadIdx.x & 63;
-        const int chunk = wi.tile * kSellChunksPerTile + (threadIdx.x >> 6);
-        const int i = chunk * kSellC + lane;
-        if (chunk * kSellC < n) {
-            constexpr int B = 8;
-            const int64_t base = d.cptr[chunk];
-            const int len = (int)((d.cptr[chunk + 1] - base) / kSellC);
-            const int *c = d.col + base + lane;
-            const double *v = val + base + lane;
-            double y = 0.0;
-            for (int k0 = 0; k0 < len; k0 += B) {
-                int cc[B];
-                double vv[B], xx[B];
-#pragma unroll
-                for (int j = 0; j < B; ++j) {
-                    cc[j] = 0;
-                    vv[j] = 0.0;
-                    if (k0 + j < len) {
-                        cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
-                        vv[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < B; ++j)
-                    xx[j] = k0 + j < len ? U[cc[j]] + beta * Pold[cc[j]] : 0.0;
-#pragma unroll
-                for (int j = 0; j < B; ++j)
-                    if (k0 + j < len)
-                        y = y + vv[j] * xx[j];
-            }
-            if (i < n)
-                row_out(i, y);
-        }
-    } else {
-        const int L = d.lanes;
-        const int g = threadIdx.x / L, l = threadIdx.x % L;
-        const int rows_per_pass = kSpmvThreads / L;
-        const int passes = kTileRows / rows_per_pass;
-        for (int pass = 0; pass < passes; ++pass) {
-            const int i = wi.tile * kTileRows + pass * rows_per_pass + g;
-            double y = 0.0;
-            if (i < n) {
-                const int e = d.rp[i + 1];
-                for (int k = d.rp[i] + l; k < e; k += L) {
-                    const int cc = stream_load(d.col + k);
-                    y = y + stream_load(val + k) * (U[cc] + beta * Pold[cc]);
-                }
-            }
-            for (int off = L >> 1; off >= 1; off >>= 1)
-                y = y + __shfl_xor(y, off, 64);
-            if (l == 0 && i < n)
-                row_out(i, y);
-        }
-    }
-    double v[1] = {acc};
+    const double *U = (const double *)d.u;
+    const double *Pold = (const double *)(PAR ? d.z : d.p);
+    double *Pnew = (double *)(PAR ? d.p : d.z);
+    double *S = (double *)d.s;
+    double v[1];
+    if (d.vals32)
+        v[0] = pcg_spmv_tile<float>(d, wi, d.val32, beta, U, Pold, Pnew, S);
+    else
+        v[0] = pcg_spmv_tile<double>(d, wi, (const double *)d.val, beta, U, Pold, Pnew, S);
     block_sum<kSpmvThreads, 1>(v, lds);
     if (threadIdx.x == 0)
         d.part[(size_t)wi.tile * kPartStride] = v[0];  // slot 0
-    if (!arrive_last<kSpmvThreads>(d, st, &flag))
+    if (!arrive_last(d, st, &flag))
         return;
     double dl[1];
     reduce_partials<kSpmvThreads, 1>(d, 0, dl, lds);
@@ -146,22 +169,28 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__
     }
 }
 
+enum PcgUpdate { PCG_START = 0, PCG_ITER = 1, PCG_REPL = 2 };
+
 // Stopping test at the top of Algorithm 1's loop and beta for the next
-// iteration (thread 0 of the last workgroup, or of the initialisation).
+// iteration (thread 0 of the last workgroup).  PCG_START follows the
+// initialisation (beta = 0); PCG_ITER follows an x-update; PCG_REPL follows a
+// reliable update: the counters stay, and beta = (u', r') / gamma_{i-1} with
+// the replaced residual, the direction being kept.
 __device__ inline void pcg_scalar_update(const SysDesc &d, SysState *st, const double (&v)[kNumPartials],
-                                         bool start)
+                                         int kind)
 {
-    if (!start) {
+    if (kind == PCG_ITER) {
         st->iter += 1;
         st->i_start += 1;
+        st->gamma_prev = st->gamma;
     }
     st->gen += 1;
     const double g = v[0], uu = v[1], rr = v[2];
-    const double gprev = st->gamma;
-    st->gamma_prev = gprev;
     st->gamma = g;
     st->uu = uu;
     st->rr = rr;
+    st->done = 0;
+    st->status = ST_OK;
     bool conv;
     if (d.fixed > 0)
         conv = (st->iter >= d.fixed) || (g == 0.0);
@@ -171,7 +200,6 @@ __device__ inline void pcg_scalar_update(const SysDesc &d, SysState *st, const d
         conv = sqrt(rr) <= d.tol * sqrt(st->bnorm2);
     if (conv) {
         st->done = 1;
-        st->status = ST_OK;
         return;
     }
     if (d.fixed <= 0 && st->iter >= d.maxit) {
@@ -179,7 +207,17 @@ __device__ inline void pcg_scalar_update(const SysDesc &d, SysState *st, const d
         st->status = ST_NOT_CONVERGED;
         return;
     }
-    st->beta = start || st->i_start == 0 ? 0.0 : g / gprev;
+    if (d.vals32) {
+        const double rn = sqrt(rr);
+        if (kind != PCG_ITER) {
+            st->repl_ref = rn;
+        } else if (d.repl_factor > 0.0 && rn < d.repl_factor * st->repl_ref) {
+            st->done = 1;
+            st->status = ST_REPLACE;
+            return;
+        }
+    }
+    st->beta = kind == PCG_START || st->i_start == 0 ? 0.0 : g / st->gamma_prev;
 }
 
 template <int PAR>
@@ -225,21 +263,23 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
         for (int k = 0; k < kNumPartials; ++k)
             out[k] = acc[k];
     }
-    if (!arrive_last<kVmaThreads>(d, st, &flag))
+    if (!arrive_last(d, st, &flag))
         return;
     double v[kNumPartials];
     reduce_partials<kVmaThreads>(d, 1, v, lds);
     if (threadIdx.x == 0) {
         st->ticket = 0;
-        pcg_scalar_update(d, st, v, false);
+        pcg_scalar_update(d, st, v, PCG_ITER);
     }
 }
 
-// Initialisation after MODE_INIT1 (r = b - A x, u = M^-1 r, p = z = 0):
-// gamma0 = (u, r), (u, u), (r, r), (b, b); stopping test at iteration 0.
-__global__ __launch_bounds__(kVmaThreads) void k_pcg_init(const WorkItem *__restrict__ table,
-                                                          const int *__restrict__ count,
-                                                          const SysDesc *__restrict__ descs)
+// After r = b - A x and u = M^-1 r were (re)computed (MODE_INIT1 at a start,
+// MODE_REPL1 at a reliable update): (u, r), (u, u), (r, r), (b, b) and the
+// scalar update of the given kind (PCG_START or PCG_REPL).
+template <int KIND>
+__global__ __launch_bounds__(kVmaThreads) void k_pcg_restart(const WorkItem *__restrict__ table,
+                                                             const int *__restrict__ count,
+                                                             const SysDesc *__restrict__ descs)
 {
     __shared__ double lds[kVmaThreads / 64 * kNumPartials];
     __shared__ int flag;
@@ -268,7 +308,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_init(const WorkItem *__rest
         for (int k = 0; k < kNumPartials; ++k)
             out[k] = acc[k];
     }
-    if (!arrive_last<kVmaThreads>(d, st, &flag))
+    if (!arrive_last(d, st, &flag))
         return;
     double v[kNumPartials];
     reduce_partials<kVmaThreads>(d, 1, v, lds);
@@ -276,7 +316,11 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_init(const WorkItem *__rest
         st->ticket = 0;
         st->bnorm2 = v[3];
         st->phase = 0;
-        pcg_scalar_update(d, st, v, true);
+        // A reliable update after a breakdown restarts the direction (beta = 0)
+        // from the replaced residual: the kept direction is not usable.
+        if (KIND == PCG_REPL && st->status == ST_BREAKDOWN)
+            st->i_start = 0;
+        pcg_scalar_update(d, st, v, KIND);
     }
 }
 

@@ -155,9 +155,70 @@ def test_pcg_edge_cases():
     assert info["status"] == ppcg.BREAKDOWN
 
 
-def test_pcg_rejects_mixed_precision():
+def test_pcg_rejects_fp32_vector_mode():
     with pytest.raises(PPCGError):
-        Solver(poisson2d(8), method="pcg", precision="mixed_values")
+        Solver(poisson2d(8), method="pcg", precision="mixed")
+
+
+# ---------------------------------------------------------------- FP32 matrix values
+
+def _round32(A):
+    return CSR(A.n, A.rp, A.ci, A.val.astype(np.float32).astype(np.float64), A.name + "_fp32")
+
+
+def _diag_fp32_exact(A):
+    """A with its diagonal rounded to FP32, so that the Jacobi preconditioner
+    of A and of its FP32 rounding coincide (still SPD: the change is ~1e-7
+    relative)."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.rp))
+    val = A.val.copy()
+    on = A.ci == rows
+    val[on] = val[on].astype(np.float32).astype(np.float64)
+    return CSR(A.n, A.rp, A.ci, val, A.name)
+
+
+@pytest.mark.parametrize("gen", [lambda: stencil27_lognormal(14, seed=2), lambda: random_spd(5000, seed=6)])
+def test_pcg_fp32_values_iterates_match_oracle_on_rounded_matrix(gen):
+    """Until the first reliable update the iteration is Algorithm 1 on the
+    FP32-rounded operator with FP64 vectors and accumulation; x0 = 0 makes the
+    initial residual b either way, so the oracle on the rounded matrix is the
+    reference."""
+    A = _diag_fp32_exact(gen())
+    b = problem(A)
+    S = Solver(A, method="pcg", precision="mixed_values", inner_tol=1e-30, spmv_format="sell")
+    for k in (1, 4, 13):
+        S.set_options(method="pcg", precision="mixed_values", fixed_iters=k, inner_tol=1e-30)
+        x, info = S.solve(dev(b))
+        ref = oracle.pcg(_round32(A), b, fixed_iters=k)
+        assert info["iters"] == k and info["outer_iters"] == 0
+        assert relerr(host(x), ref.x) <= 1e-10, k
+
+
+@pytest.mark.parametrize("gen,factor", [(lambda: stencil27_lognormal(16, seed=1), 1e-3),
+                                        (lambda: stencil27_lognormal(16, seed=1), 0.3),
+                                        (lambda: poisson3d(24), 1e-2),
+                                        (lambda: random_spd(20000, seed=3), 1e-3)])
+def test_pcg_fp32_values_reliable_updates_reach_fp64_tolerance(gen, factor):
+    A = gen()
+    b = problem(A)
+    x, info = Solver(A, tol=1e-10, method="pcg", precision="mixed_values", inner_tol=factor).solve(dev(b))
+    ref = oracle.pcg(A, b, tol=1e-10)
+    assert info["status"] == ppcg.OK, info
+    assert info["rel_resid_true"] <= 1e-10
+    assert oracle.true_relres(A, b, host(x)) <= 1e-10
+    assert info["iters"] <= 1.15 * ref.iters + 5, (info["iters"], ref.iters)
+    assert relerr(host(x), ref.x) <= 1e-5
+
+
+def test_pcg_fp32_values_batch_bitwise_equals_solo():
+    mats = [stencil27_lognormal(12, seed=4), shifted(poisson2d(70), 0.01), random_spd(4000, seed=2)]
+    bs = [problem(A, seed=70 + i) for i, A in enumerate(mats)]
+    kw = dict(tol=1e-10, method="pcg", precision="mixed_values")
+    solo = [host(Solver(A, **kw).solve(dev(b))[0]) for A, b in zip(mats, bs)]
+    xs, infos = solve_batch([Solver(A, **kw) for A in mats], [dev(b) for b in bs])
+    for x, xs_, info in zip(xs, solo, infos):
+        assert np.array_equal(host(x), xs_)
+        assert info["status"] == ppcg.OK and info["rel_resid_true"] <= 1e-10
 
 
 def test_pcg_batch_bitwise_equals_solo():
