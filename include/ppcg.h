@@ -227,9 +227,10 @@ double ppcg_footprint_bytes(int32_t n, int64_t nnz, ppcg_precision precision);
  * updates + preconditioner + dot products, and its SpMV) over `iters`
  * iterations on the handle's stream, each launch bracketed by HIP events.
  * Runs the initialisation first, so the vectors hold a real iterate.
- * With opt.method = PPCG_METHOD_PCG the two kernels of Algorithm 1 are
- * timed instead (vector updates + preconditioner + dot products; SpMV with
- * the direction update and (s, p)), each with its closing reduction.
+ * With opt.method = PPCG_METHOD_PCG the two streaming kernels of Algorithm 1
+ * are timed instead (vector updates + preconditioner + dot-product partials;
+ * SpMV with the direction update and the (s, p) partials); the per-system
+ * reductions between them run but are not included.
  * ms_vma, ms_spmv: average launch duration in milliseconds (host pointers). */
 ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, double *ms_vma,
                               double *ms_spmv);
@@ -243,6 +244,70 @@ const char *ppcg_status_str(ppcg_status s);
 
 /* Detail message of the last failing call on this thread ("" if none). */
 const char *ppcg_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Row split and 2-D decomposition (Section IV-C, "Performance Modelling" and
+ * "Data Decomposition").  The paper divides A between processing units in
+ * proportion to the speed each shows on the same SpMV, then splits every
+ * unit's entries into those that need only the unit's own piece of the
+ * vector (its SpMV part 1) and those that need elements owned by others
+ * (part 2, after they have been copied in).  Here the units are devices of
+ * a multi-GPU (or host + GPU) run; these calls plan the split and hold one
+ * unit's share with its two-part SpMV.  The exchange between units is not
+ * part of the library.
+ * ------------------------------------------------------------------------- */
+
+/* Rows per unit.  times[k] (> 0, seconds): unit k's time for the same SpMV
+ * over all nnz entries; its speed s_k = nnz / t_k and share r_k = s_k / sum s.
+ * Unit k gets the rows [row_begin[k], row_begin[k+1]); each boundary before
+ * the last is the most leading row count whose non-zeros number at most
+ * nnz * (r_1 + ... + r_k) (equal or slightly fewer, as in the paper, which
+ * has two units); the last unit takes the rest.  row_ptr: host [n + 1];
+ * times: host [parts]; row_begin: host [parts + 1], written.  Host only. */
+ppcg_status ppcg_split_rows(int32_t n, const int32_t *row_ptr, int32_t parts, const double *times,
+                            int32_t *row_begin);
+
+typedef struct ppcg_shard ppcg_shard; /* opaque, owned by the library */
+
+typedef struct {
+    size_t struct_size;      /* sizeof(ppcg_shard_info) */
+    int32_t row_begin;       /* the unit's rows are [row_begin, row_end) */
+    int32_t row_end;
+    int64_t nnz_local;       /* nnz1: entries whose column is also in [row_begin, row_end) */
+    int64_t nnz_remote;      /* nnz2: the other entries */
+    int32_t halo;            /* distinct remote columns = length of the halo vector */
+    int32_t boundary_rows;   /* rows with at least one remote entry */
+    double bytes_part1;      /* algorithmic bytes of part 1 (matrix, input, output) */
+    double bytes_part2;      /* algorithmic bytes of part 2 (matrix, halo, output update) */
+    double halo_bytes;       /* bytes the unit receives per SpMV (8 per halo entry) */
+} ppcg_shard_info;
+
+/* One unit's share of A: rows [row_begin, row_end) of the n x n CSR matrix A
+ * (host or device arrays, read during the call only; A's CSR requirements
+ * apply to these rows, no diagonal is needed).  Part 1 is stored with local
+ * columns (0 .. rows-1); part 2 with columns renumbered to the halo vector,
+ * which lists the distinct remote columns in ascending order.  Work is
+ * ordered on hip_stream.  Errors: ERR_INVALID_ARG (range, pointers),
+ * ERR_BAD_CSR, ERR_NOMEM. */
+ppcg_status ppcg_shard_create(const ppcg_csr *A, int32_t row_begin, int32_t row_end, void *hip_stream,
+                              ppcg_shard **out);
+ppcg_status ppcg_shard_get_info(const ppcg_shard *s, ppcg_shard_info *info);
+/* cols: host [halo], receives the global column of every halo entry. */
+ppcg_status ppcg_shard_halo_columns(const ppcg_shard *s, int32_t *cols);
+/* x_halo[k] = x_global[cols[k]] on the device: the halo a unit would receive
+ * from the others, taken here from a global vector.  Device pointers. */
+ppcg_status ppcg_shard_gather(ppcg_shard *s, const double *x_global, double *x_halo);
+/* y = A_rows x in two parts: parts & 1 writes y = (part 1) x_local, parts & 2
+ * adds (part 2) x_halo to y.  Row i's part-1 and part-2 entries are each
+ * summed in stored column order and the two sums added.  x_local: device
+ * [rows], x_halo: device [halo], y: device [rows], not aliasing x_local. */
+ppcg_status ppcg_shard_spmv(ppcg_shard *s, const double *x_local, const double *x_halo, double *y,
+                            int32_t parts);
+/* Average durations (ms, HIP events attached to each launch) over iters
+ * rounds of part 1, the halo gather from x_global, and part 2. */
+ppcg_status ppcg_shard_time(ppcg_shard *s, const double *x_global, const double *x_local, double *x_halo,
+                            double *y, int32_t iters, double *ms_part1, double *ms_gather, double *ms_part2);
+ppcg_status ppcg_shard_destroy(ppcg_shard *s); /* NULL-safe */
 
 /* ---------------------------------------------------------------------------
  * Serving: a continuous-batching solve server.  Requests are admitted while

@@ -162,6 +162,13 @@ struct Group {
     int stage_cap = 0;
     std::vector<WorkItem> table_h;  // current iteration table
     bool table_dirty = true;
+    // classic PCG groups: one item (slot, 0) per iterating system, for the
+    // per-system reduction kernels
+    WorkItem *sys_d = nullptr;
+    int *sys_count_d = nullptr;
+    int sys_cap = 0;
+    int nsys = 0;
+    int g_sys_grid = 0;
     // Captured graphs of K iterations (K a power of two), all for grid g_grid.
     struct CapturedGraph {
         hipGraph_t graph = nullptr;
@@ -219,6 +226,8 @@ class Engine {
 enum AuxOp { AUX_INIT = 0, AUX_RESID = 1, AUX_MIX_START = 2, AUX_MIX_CORRECT = 3, AUX_REPL = 4 };
 
 double now_ms();
+// NULL, non-device and too-short device buffers are rejected with a message.
+ppcg_status check_dev_range(const void *p, size_t bytes, const char *what);
 int auto_graph_iters(const ppcg_handle *h);
 // Helpers shared by the solver API and the server.
 ppcg_status stage_inputs(ppcg_handle *h, const double *b, const double *x0);

@@ -75,8 +75,7 @@ struct alignas(128) SysState {
     int status;         // DevStatus when done
     int phase;          // 1: the next reduction is the one that ends initialisation
     int gen;            // incremented by every reduction (debug / polling aid)
-    int ticket;         // Algorithm 1 path: arrival counter of the last-workgroup reductions
-    int pad;
+    int pad[2];
 };
 static_assert(sizeof(SysState) == 128, "SysState is one 128-byte record");
 

@@ -89,7 +89,7 @@ static size_t aligned(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Check that [p, p + bytes) lies inside one device allocation of the current
 // device, so that no kernel can fault on a wrong pointer or short buffer.
-static ppcg_status check_dev_range(const void *p, size_t bytes, const char *what)
+ppcg_status check_dev_range(const void *p, size_t bytes, const char *what)
 {
     if (!p) {
         set_error("%s is NULL", what);
@@ -588,6 +588,8 @@ Engine::~Engine()
         if (g->count_d) (void)hipFree(g->count_d);
         if (g->aux_d) (void)hipFree(g->aux_d);
         if (g->aux_count_d) (void)hipFree(g->aux_count_d);
+        if (g->sys_d) (void)hipFree(g->sys_d);
+        if (g->sys_count_d) (void)hipFree(g->sys_count_d);
         if (g->stage_h) (void)hipHostFree(g->stage_h);
         if (g->stage_cnt_h) (void)hipHostFree(g->stage_cnt_h);
     }
@@ -608,7 +610,8 @@ ppcg_status Engine::ensure_group(Group &g, int prec, int cap_sys)
     PPCG_HIP(hipHostMalloc((void **)&g.st_h, sizeof(SysState) * cap_sys, hipHostMallocDefault));
     PPCG_HIP(hipMalloc(&g.count_d, sizeof(int)));
     PPCG_HIP(hipMalloc(&g.aux_count_d, sizeof(int)));
-    PPCG_HIP(hipHostMalloc((void **)&g.stage_cnt_h, sizeof(int) * 2, hipHostMallocDefault));
+    PPCG_HIP(hipMalloc(&g.sys_count_d, sizeof(int)));
+    PPCG_HIP(hipHostMalloc((void **)&g.stage_cnt_h, sizeof(int) * 3, hipHostMallocDefault));
     g.desc_h.assign(cap_sys, SysDesc{});
     g.slot_used.assign(cap_sys, 0);
     return PPCG_OK;
@@ -667,7 +670,8 @@ static ppcg_status upload_table(hipStream_t s, Group &g, const std::vector<WorkI
             (void)hipHostFree(g.stage_h);
         g.stage_h = nullptr;
         g.stage_cap = std::max(2 * n + 1, 256);
-        PPCG_HIP(hipHostMalloc((void **)&g.stage_h, sizeof(WorkItem) * g.stage_cap * 2, hipHostMallocDefault));
+        // three regions: iteration table, aux table, system table
+        PPCG_HIP(hipHostMalloc((void **)&g.stage_h, sizeof(WorkItem) * g.stage_cap * 3, hipHostMallocDefault));
     }
     WorkItem *st = g.stage_h + (size_t)which * g.stage_cap;
     if (n)
@@ -685,12 +689,12 @@ static ppcg_status upload_table(hipStream_t s, Group &g, const std::vector<WorkI
 static void launch_iter_pair(hipStream_t s, const Group &g, int grid, int remap)
 {
     if (g.pcg) {
-        // Two Algorithm 1 iterations: the direction alternates between the
-        // p and z buffers, so a chunk always holds an even number of them.
-        k_pcg_spmv<0><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-        k_pcg_vma<0><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
-        k_pcg_spmv<1><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
-        k_pcg_vma<1><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+        // Algorithm 1: SpMV, alpha, vector updates, stopping test and beta.
+        const int sg = std::max(g.g_sys_grid, 1);
+        k_pcg_spmv<<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        k_pcg_alpha<<<sg, kPcgRedThreads, 0, s>>>(g.sys_d, g.sys_count_d, g.desc_d);
+        k_pcg_vma<<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+        k_pcg_update<PCG_ITER><<<sg, kPcgRedThreads, 0, s>>>(g.sys_d, g.sys_count_d, g.desc_d);
     } else if (g.prec == PREC_F32) {
         k_vma<float><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
         k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
@@ -713,6 +717,18 @@ ppcg_status Engine::ensure_table(Group &g)
     if (old != g.table_d)  // graphs baked the old pointer
         drop_graphs(g);
     PPCG_TRY(upload_table(stream_, g, g.table_h, g.table_d, g.count_d, 0));
+    if (g.pcg) {
+        std::vector<WorkItem> sys;
+        for (const WorkItem &w : g.table_h)
+            if (w.tile == 0)
+                sys.push_back(w);
+        WorkItem *olds = g.sys_d;
+        PPCG_TRY(grow_table(&g.sys_d, &g.sys_cap, (int)sys.size()));
+        if (olds != g.sys_d)
+            drop_graphs(g);
+        PPCG_TRY(upload_table(stream_, g, sys, g.sys_d, g.sys_count_d, 2));
+        g.nsys = (int)sys.size();
+    }
     g.table_dirty = false;
     return PPCG_OK;
 }
@@ -725,6 +741,7 @@ void Engine::drop_graphs(Group &g)
     }
     g.graphs.clear();
     g.g_grid = 0;
+    g.g_sys_grid = 0;
 }
 
 // Graph of `iters` iterations over the group's table.  The grid is baked
@@ -734,7 +751,9 @@ void Engine::drop_graphs(Group &g)
 ppcg_status Engine::ensure_graph(Group &g, int iters, hipGraphExec_t *exec)
 {
     const int need = std::max((int)g.table_h.size(), 1);
-    if (g.g_grid < need || g.g_grid > std::max(need * 4, 64))
+    const int need_sys = std::max(g.nsys, 1);
+    if (g.g_grid < need || g.g_grid > std::max(need * 4, 64) ||
+        (g.pcg && (g.g_sys_grid < need_sys || g.g_sys_grid > std::max(need_sys * 4, 16))))
         drop_graphs(g);
     auto it = g.graphs.find(iters);
     if (it != g.graphs.end()) {
@@ -742,9 +761,11 @@ ppcg_status Engine::ensure_graph(Group &g, int iters, hipGraphExec_t *exec)
         return PPCG_OK;
     }
     const int grid = g.g_grid ? g.g_grid : need;
+    if (g.pcg && !g.g_sys_grid)
+        g.g_sys_grid = need_sys;
     Group::CapturedGraph cg;
     PPCG_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < (g.pcg ? iters / 2 : iters); ++i)
+    for (int i = 0; i < iters; ++i)
         launch_iter_pair(stream_, g, grid, remap);
     hipError_t e = hipStreamEndCapture(stream_, &cg.graph);
     if (e != hipSuccess) {
@@ -790,7 +811,7 @@ int Engine::chunk_iters(const Group &g, int max_iters)
     int k = 1;
     while (k * 2 <= want)
         k *= 2;
-    return g.pcg ? std::max(k, 2) : k;
+    return k;
 }
 
 ppcg_status Engine::sync_states(Group &g)
@@ -822,11 +843,13 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     const bool f32 = g.prec == PREC_F32;
     if (what == AUX_INIT && g.pcg) {
         k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        k_pcg_restart<PCG_START><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_dots<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_update<PCG_START><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_REPL && g.pcg) {
         // Reliable update of classic PCG: r = b - A64 x, u = M^-1 r; p is kept.
         k_spmv<double, MODE_REPL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        k_pcg_restart<PCG_REPL><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_dots<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_update<PCG_REPL><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_INIT) {
         if (f32) {
             k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
@@ -1756,7 +1779,8 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     const bool pcg = h->opt.method == PPCG_METHOD_PCG;
     k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
     if (pcg) {
-        k_pcg_restart<PCG_START><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_dots<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_update<PCG_START><<<1, kPcgRedThreads, 0, s>>>(tab, cnt, dd);  // item 0 is (system, tile 0)
     } else {
         k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
         k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
@@ -1767,16 +1791,15 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     // the durations exclude the gaps between launches.
     for (int i = 0; i < iters; ++i) {
         const int rv = (int)PPCG_XCD_REMAP, rs = (int)PPCG_XCD_REMAP_SPMV;
-        if (pcg && (i & 1) == 0) {
-            hipExtLaunchKernelGGL(k_pcg_spmv<0>, dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2], ev[4 * i + 3],
-                                  0, tab, cnt, dd, rs);
-            hipExtLaunchKernelGGL(k_pcg_vma<0>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0,
-                                  tab, cnt, dd, rv);
-        } else if (pcg) {
-            hipExtLaunchKernelGGL(k_pcg_spmv<1>, dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2], ev[4 * i + 3],
-                                  0, tab, cnt, dd, rs);
-            hipExtLaunchKernelGGL(k_pcg_vma<1>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0,
-                                  tab, cnt, dd, rv);
+        if (pcg) {
+            // the two streaming kernels are timed; the per-system reductions
+            // between them run untimed
+            hipExtLaunchKernelGGL(k_pcg_spmv, dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2], ev[4 * i + 3], 0,
+                                  tab, cnt, dd, rs);
+            k_pcg_alpha<<<1, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
+            hipExtLaunchKernelGGL(k_pcg_vma, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0, tab,
+                                  cnt, dd, rv);
+            k_pcg_update<PCG_ITER><<<1, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
         } else {
             hipExtLaunchKernelGGL(k_vma<double>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0,
                                   tab, cnt, dd, rv);

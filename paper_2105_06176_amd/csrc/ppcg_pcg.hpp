@@ -2,20 +2,24 @@
 // III-A) on the device, for comparison with the pipelined method, and as the
 // iteration of the FP32-values mode when selected.
 //
-// One iteration is two launches over the same (system, tile) work table:
+// One iteration is four launches:
 //
-//   k_pcg_spmv<PAR>  p = u + beta p (formed on the fly for every gathered
-//                    entry, written for the workgroup's own rows into the
-//                    other buffer of a double-buffered pair), s = A p, and
-//                    the partial sums of (s, p); the last workgroup to finish
-//                    (arrival ticket) reduces them and computes alpha.
-//   k_pcg_vma<PAR>   x += alpha p, r -= alpha s, u = M^-1 r and the partial
-//                    sums of (u, r), (u, u), (r, r); the last workgroup
-//                    reduces them, runs the stopping test and computes beta.
+//   k_pcg_spmv      (per tile)   p = u + beta p, formed on the fly for every
+//                                gathered entry and written for the tile's
+//                                own rows into the other buffer of a
+//                                double-buffered pair; s = A p; partial sums
+//                                of (s, p).
+//   k_pcg_alpha     (per system) reduce (s, p) in a fixed order; alpha.
+//   k_pcg_vma       (per tile)   x += alpha p, r -= alpha s, u = M^-1 r;
+//                                partial sums of (u, r), (u, u), (r, r).
+//   k_pcg_update    (per system) reduce them; stopping test; beta.
 //
-// Unlike Algorithm 2, each iteration has two reductions that the next launch
-// depends on, so they are done by the last-arriving workgroup.  PAR selects
-// which of p / z holds the previous direction; iterations alternate PAR.
+// Unlike Algorithm 2, each of the two reductions gates the next launch, so
+// they cannot be hidden behind other work: they run as one-workgroup-per-
+// system kernels between the streaming kernels (no grid-wide fences or
+// atomics).  Which buffer of the pair holds the current direction follows
+// from the iteration counter: the SpMV of the iteration after k x-updates
+// reads buffer k mod 2 (p for even, z for odd) and writes the other.
 //
 // FP32-values mode (d.vals32): s = A32 p with FP32 matrix values, FP64
 // vectors and accumulation.  When the recurrence residual has fallen by
@@ -29,23 +33,11 @@
 
 namespace ppcg {
 
-// Last-workgroup reduction: every workgroup publishes its record, then
-// increments the system's ticket; the one that brings it to ntiles reduces
-// all records in tile order.  Returns true (in every thread) for that one.
-__device__ __forceinline__ bool arrive_last(const SysDesc &d, SysState *st, int *flag)
-{
-    __syncthreads();  // this workgroup's partial record is written (thread 0)
-    if (threadIdx.x == 0) {
-        __threadfence();  // publish the record before arriving
-        const int t = atomicAdd(&st->ticket, 1);
-        *flag = (t == d.ntiles - 1);
-    }
-    __syncthreads();
-    const bool last = *flag != 0;
-    if (last)
-        __threadfence();  // acquire: see every other workgroup's record
-    return last;
-}
+// Threads of the one-workgroup-per-system reduction kernels.
+constexpr int kPcgRedThreads = 1024;
+
+// Direction buffers: the current direction after k x-updates is in pbuf(k).
+__device__ __forceinline__ double *pcg_dir(const SysDesc &d, int k) { return (double *)((k & 1) ? d.z : d.p); }
 
 // s = A p for one tile with p = u + beta p_old formed per gathered entry;
 // returns this thread's share of (s, p).
@@ -123,25 +115,24 @@ __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem
     return acc;
 }
 
-template <int PAR>
 __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__restrict__ table,
                                                               const int *__restrict__ count,
                                                               const SysDesc *__restrict__ descs, int remap)
 {
     __shared__ double lds[kSpmvThreads / 64];
-    __shared__ int flag;
     const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     if (pos >= *count)
         return;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
-    SysState *st = d.st;
+    const SysState *st = d.st;
     if (st->done)
         return;
     const double beta = st->beta;
+    const int k = st->iter;
     const double *U = (const double *)d.u;
-    const double *Pold = (const double *)(PAR ? d.z : d.p);
-    double *Pnew = (double *)(PAR ? d.p : d.z);
+    const double *Pold = pcg_dir(d, k);
+    double *Pnew = pcg_dir(d, k + 1);
     double *S = (double *)d.s;
     double v[1];
     if (d.vals32)
@@ -151,13 +142,27 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__
     block_sum<kSpmvThreads, 1>(v, lds);
     if (threadIdx.x == 0)
         d.part[(size_t)wi.tile * kPartStride] = v[0];  // slot 0
-    if (!arrive_last(d, st, &flag))
+}
+
+// alpha = gamma / (s, p), with breakdown when gamma <= 0, (s, p) <= 0 or a
+// scalar is not finite.  One workgroup per system: the work items name
+// systems (tile 0); items of other tiles exit at once, so a tile table works
+// too.
+__global__ __launch_bounds__(kPcgRedThreads) void k_pcg_alpha(const WorkItem *__restrict__ systab,
+                                                              const int *__restrict__ count,
+                                                              const SysDesc *__restrict__ descs)
+{
+    __shared__ double lds[kPcgRedThreads / 64];
+    if ((int)blockIdx.x >= *count || systab[blockIdx.x].tile != 0)
+        return;
+    const SysDesc &d = descs[systab[blockIdx.x].slot];
+    SysState *st = d.st;
+    if (st->done)
         return;
     double dl[1];
-    reduce_partials<kSpmvThreads, 1>(d, 0, dl, lds);
+    reduce_partials<kPcgRedThreads, 1>(d, 0, dl, lds);
     if (threadIdx.x == 0) {
-        st->ticket = 0;
-        const double g = st->gamma;
+        const double g = st->gamma, beta = st->beta;
         const double alpha = g / dl[0];
         st->delta = dl[0];
         if (!(g > 0.0) || !(dl[0] > 0.0) || !isfinite(alpha) || !isfinite(beta)) {
@@ -172,10 +177,10 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__
 enum PcgUpdate { PCG_START = 0, PCG_ITER = 1, PCG_REPL = 2 };
 
 // Stopping test at the top of Algorithm 1's loop and beta for the next
-// iteration (thread 0 of the last workgroup).  PCG_START follows the
-// initialisation (beta = 0); PCG_ITER follows an x-update; PCG_REPL follows a
-// reliable update: the counters stay, and beta = (u', r') / gamma_{i-1} with
-// the replaced residual, the direction being kept.
+// iteration.  PCG_START follows the initialisation (beta = 0); PCG_ITER
+// follows an x-update; PCG_REPL follows a reliable update: the counters stay,
+// and beta = (u', r') / gamma_{i-1} with the replaced residual, the direction
+// being kept.
 __device__ inline void pcg_scalar_update(const SysDesc &d, SysState *st, const double (&v)[kNumPartials],
                                          int kind)
 {
@@ -220,42 +225,58 @@ __device__ inline void pcg_scalar_update(const SysDesc &d, SysState *st, const d
     st->beta = kind == PCG_START || st->i_start == 0 ? 0.0 : g / st->gamma_prev;
 }
 
-template <int PAR>
 __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restrict__ table,
                                                          const int *__restrict__ count,
                                                          const SysDesc *__restrict__ descs, int remap)
 {
     __shared__ double lds[kVmaThreads / 64 * kNumPartials];
-    __shared__ int flag;
     const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     if (pos >= *count)
         return;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
-    SysState *st = d.st;
+    const SysState *st = d.st;
     if (st->done)
         return;
     const double alpha = st->alpha;
     double *__restrict__ X = (double *)d.x;
     double *__restrict__ R = (double *)d.r;
     double *__restrict__ U = (double *)d.u;
-    const double *__restrict__ P = (const double *)(PAR ? d.p : d.z);
+    const double *__restrict__ P = pcg_dir(d, st->iter + 1);
     const double *__restrict__ S = (const double *)d.s;
     const double *__restrict__ DI = (const double *)d.dinv;
     double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < 2; ++k) {
-        const int i = wi.tile * kTileRows + threadIdx.x * 2 + k;
-        if (i < d.n) {
-            const double x = X[i] + alpha * P[i];
-            const double r = R[i] - alpha * S[i];
-            const double u = DI[i] * r;
-            X[i] = x;
-            R[i] = r;
-            U[i] = u;
-            acc[0] = acc[0] + u * r;
-            acc[1] = acc[1] + u * u;
-            acc[2] = acc[2] + r * r;
+    auto elem = [&](double &x, double &r, double &u, double p, double sv, double di) {
+        x = x + alpha * p;
+        r = r - alpha * sv;
+        u = di * r;
+        acc[0] = acc[0] + u * r;
+        acc[1] = acc[1] + u * u;
+        acc[2] = acc[2] + r * r;
+    };
+    const int i = wi.tile * kTileRows + threadIdx.x * 2;
+    if (i + 1 < d.n) {
+        dvec2 x = vload((const dvec2 *)(X + i)), r = vload((const dvec2 *)(R + i));
+        const dvec2 p = vload((const dvec2 *)(P + i)), sv = vload((const dvec2 *)(S + i));
+        const dvec2 di = vload((const dvec2 *)(DI + i));
+        dvec2 u;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            double xj = x[j], rj = r[j], uj;
+            elem(xj, rj, uj, p[j], sv[j], di[j]);
+            x[j] = xj;
+            r[j] = rj;
+            u[j] = uj;
         }
+        vstore((dvec2 *)(X + i), x);
+        vstore((dvec2 *)(R + i), r);
+        vstore((dvec2 *)(U + i), u);
+    } else if (i < d.n) {
+        double x = X[i], r = R[i], u;
+        elem(x, r, u, P[i], S[i], DI[i]);
+        X[i] = x;
+        R[i] = r;
+        U[i] = u;
     }
     block_sum<kVmaThreads, kNumPartials>(acc, lds);
     if (threadIdx.x == 0) {
@@ -263,32 +284,21 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
         for (int k = 0; k < kNumPartials; ++k)
             out[k] = acc[k];
     }
-    if (!arrive_last(d, st, &flag))
-        return;
-    double v[kNumPartials];
-    reduce_partials<kVmaThreads>(d, 1, v, lds);
-    if (threadIdx.x == 0) {
-        st->ticket = 0;
-        pcg_scalar_update(d, st, v, PCG_ITER);
-    }
 }
 
 // After r = b - A x and u = M^-1 r were (re)computed (MODE_INIT1 at a start,
-// MODE_REPL1 at a reliable update): (u, r), (u, u), (r, r), (b, b) and the
-// scalar update of the given kind (PCG_START or PCG_REPL).
-template <int KIND>
-__global__ __launch_bounds__(kVmaThreads) void k_pcg_restart(const WorkItem *__restrict__ table,
-                                                             const int *__restrict__ count,
-                                                             const SysDesc *__restrict__ descs)
+// MODE_REPL1 at a reliable update): partial sums of (u, r), (u, u), (r, r)
+// and (b, b) per tile, in the layout k_pcg_update reduces.
+__global__ __launch_bounds__(kVmaThreads) void k_pcg_dots(const WorkItem *__restrict__ table,
+                                                          const int *__restrict__ count,
+                                                          const SysDesc *__restrict__ descs)
 {
     __shared__ double lds[kVmaThreads / 64 * kNumPartials];
-    __shared__ int flag;
     const int pos = blockIdx.x;
     if (pos >= *count)
         return;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
-    SysState *st = d.st;
     const double *__restrict__ R = (const double *)d.r;
     const double *__restrict__ U = (const double *)d.u;
     const double *__restrict__ Bv = (const double *)d.b;
@@ -308,14 +318,31 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_restart(const WorkItem *__r
         for (int k = 0; k < kNumPartials; ++k)
             out[k] = acc[k];
     }
-    if (!arrive_last(d, st, &flag))
+}
+
+// Reduce the update's partial sums and run the scalar update of the given
+// kind.  One workgroup per system.  After k_pcg_vma (PCG_ITER) only systems
+// still iterating take part; after k_pcg_dots (PCG_START, PCG_REPL) the
+// system's state is set up again, (b, b) included.
+template <int KIND>
+__global__ __launch_bounds__(kPcgRedThreads) void k_pcg_update(const WorkItem *__restrict__ systab,
+                                                               const int *__restrict__ count,
+                                                               const SysDesc *__restrict__ descs)
+{
+    __shared__ double lds[kPcgRedThreads / 64 * kNumPartials];
+    if ((int)blockIdx.x >= *count || systab[blockIdx.x].tile != 0)
+        return;
+    const SysDesc &d = descs[systab[blockIdx.x].slot];
+    SysState *st = d.st;
+    if (KIND == PCG_ITER && st->done)
         return;
     double v[kNumPartials];
-    reduce_partials<kVmaThreads>(d, 1, v, lds);
+    reduce_partials<kPcgRedThreads>(d, 1, v, lds);
     if (threadIdx.x == 0) {
-        st->ticket = 0;
-        st->bnorm2 = v[3];
-        st->phase = 0;
+        if (KIND != PCG_ITER) {
+            st->bnorm2 = v[3];
+            st->phase = 0;
+        }
         // A reliable update after a breakdown restarts the direction (beta = 0)
         // from the replaced residual: the kept direction is not usable.
         if (KIND == PCG_REPL && st->status == ST_BREAKDOWN)

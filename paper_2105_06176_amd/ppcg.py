@@ -65,10 +65,22 @@ class MatrixInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
 
 
+class ShardInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("row_begin", ctypes.c_int32), ("row_end", ctypes.c_int32),
+                ("nnz_local", ctypes.c_int64), ("nnz_remote", ctypes.c_int64), ("halo", ctypes.c_int32),
+                ("boundary_rows", ctypes.c_int32), ("bytes_part1", ctypes.c_double),
+                ("bytes_part2", ctypes.c_double), ("halo_bytes", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
+
+
 EXPORTS = ["ppcg_default_options", "ppcg_create", "ppcg_set_options", "ppcg_solve", "ppcg_solve_batch",
            "ppcg_spmv",
            "ppcg_get_matrix_info", "ppcg_footprint_bytes", "ppcg_time_kernels", "ppcg_destroy",
-           "ppcg_status_str", "ppcg_last_error", "ppcg_srv_create", "ppcg_srv_submit", "ppcg_srv_step",
+           "ppcg_status_str", "ppcg_last_error", "ppcg_split_rows", "ppcg_shard_create", "ppcg_shard_get_info",
+           "ppcg_shard_halo_columns", "ppcg_shard_gather", "ppcg_shard_spmv", "ppcg_shard_time",
+           "ppcg_shard_destroy", "ppcg_srv_create", "ppcg_srv_submit", "ppcg_srv_step",
            "ppcg_srv_poll", "ppcg_srv_destroy"]
 
 _lib = None
@@ -97,6 +109,15 @@ def lib():
         "ppcg_destroy": ([P], ctypes.c_int),
         "ppcg_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "ppcg_last_error": ([], ctypes.c_char_p),
+        "ppcg_split_rows": ([I32, P, I32, P, P], ctypes.c_int),
+        "ppcg_shard_create": ([ctypes.POINTER(Csr), I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
+        "ppcg_shard_get_info": ([P, ctypes.POINTER(ShardInfo)], ctypes.c_int),
+        "ppcg_shard_halo_columns": ([P, P], ctypes.c_int),
+        "ppcg_shard_gather": ([P, P, P], ctypes.c_int),
+        "ppcg_shard_spmv": ([P, P, P, P, I32], ctypes.c_int),
+        "ppcg_shard_time": ([P, P, P, P, P, I32, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
+                            ctypes.c_int),
+        "ppcg_shard_destroy": ([P], ctypes.c_int),
         "ppcg_srv_create": ([ctypes.POINTER(Options), D, P, ctypes.POINTER(P)], ctypes.c_int),
         "ppcg_srv_submit": ([P, ctypes.POINTER(Csr), P, D, ctypes.c_int, ctypes.POINTER(I64)], ctypes.c_int),
         "ppcg_srv_step": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
@@ -315,6 +336,72 @@ class Server:
     def close(self):
         if getattr(self, "s", None):
             lib().ppcg_srv_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def split_rows(row_ptr, times) -> List[int]:
+    """Row boundaries of the performance-model split (host only, no GPU)."""
+    import numpy as np
+
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    out = np.zeros(len(t) + 1, dtype=np.int32)
+    _check(lib().ppcg_split_rows(int(rp.size - 1), rp.ctypes.data, int(t.size), t.ctypes.data, out.ctypes.data),
+           "ppcg_split_rows")
+    return [int(v) for v in out]
+
+
+class Shard:
+    """One unit's rows of A under the 2-D decomposition (part 1 local columns,
+    part 2 halo columns)."""
+
+    def __init__(self, A, row_begin: int, row_end: int, stream=None):
+        keep: list = []
+        c = _csr_struct(A, keep)
+        s = ctypes.c_void_p()
+        _check(lib().ppcg_shard_create(ctypes.byref(c), int(row_begin), int(row_end), _stream_ptr(stream),
+                                       ctypes.byref(s)), "ppcg_shard_create")
+        self.s = s
+        self.rows = int(row_end - row_begin)
+
+    def info(self) -> dict:
+        i = ShardInfo()
+        i.struct_size = ctypes.sizeof(ShardInfo)
+        _check(lib().ppcg_shard_get_info(self.s, ctypes.byref(i)), "ppcg_shard_get_info")
+        return i.as_dict()
+
+    def halo_columns(self):
+        import numpy as np
+
+        h = self.info()["halo"]
+        cols = np.zeros(max(h, 1), dtype=np.int32)
+        _check(lib().ppcg_shard_halo_columns(self.s, cols.ctypes.data), "ppcg_shard_halo_columns")
+        return cols[:h]
+
+    def gather(self, x_global, x_halo):
+        _check(lib().ppcg_shard_gather(self.s, x_global.data_ptr(), x_halo.data_ptr()), "ppcg_shard_gather")
+
+    def spmv(self, x_local, x_halo, y, parts: int = 3):
+        xh = x_halo.data_ptr() if x_halo is not None else None
+        _check(lib().ppcg_shard_spmv(self.s, x_local.data_ptr(), xh, y.data_ptr(), int(parts)), "ppcg_shard_spmv")
+        return y
+
+    def time(self, x_global, x_local, x_halo, y, iters: int = 50) -> Tuple[float, float, float]:
+        a, g, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().ppcg_shard_time(self.s, x_global.data_ptr(), x_local.data_ptr(), x_halo.data_ptr(),
+                                     y.data_ptr(), int(iters), ctypes.byref(a), ctypes.byref(g), ctypes.byref(c)),
+               "ppcg_shard_time")
+        return a.value, g.value, c.value
+
+    def close(self):
+        if getattr(self, "s", None):
+            lib().ppcg_shard_destroy(self.s)
             self.s = None
 
     def __del__(self):
