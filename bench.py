@@ -240,6 +240,39 @@ def leg_pcg(torch, ppcg, wl, iters=500):
     return out
 
 
+def leg_shard(torch, ppcg, wl, parts=8):
+    """2-D decomposition (Section IV-C) of the 128^3 7-point matrix into
+    equal-speed row slabs: one slab's SpMV part 1 (local columns), halo
+    gather and part 2 (remote columns) on this GPU, beside the unsplit SpMV."""
+    A = wl.poisson3d(128)
+    x = wl.xstar_uniform(A.n, 1)
+    xg = torch.as_tensor(x).cuda()
+    b = ppcg.split_rows(A.rp, [1.0] * parts)
+    k = parts // 2 - 1  # an interior slab: two halo planes
+    lo, hi = b[k], b[k + 1]
+    S = ppcg.Shard(A, lo, hi)
+    info = S.info()
+    xl = xg[lo:hi].contiguous()
+    xh = torch.empty(max(info["halo"], 1), dtype=torch.float64, device="cuda")
+    y = torch.empty(hi - lo, dtype=torch.float64, device="cuda")
+    S.time(xg, xl, xh, y, iters=5)
+    ms1, msg, ms2 = S.time(xg, xl, xh, y, iters=100)
+    full = ppcg.Solver(A, spmv_format="sell")
+    _, ms_spmv = full.time_kernels(xg, iters=50)
+    full.close()
+    S.close()
+    link = 153e9  # bytes/s of one xGMI link (per direction), the exchange a real split would make
+    out = {"workload": f"3D 7-point Poisson 128^3 split into {parts} equal row slabs; slab {k}",
+           "rows": hi - lo, "nnz_local": info["nnz_local"], "nnz_remote": info["nnz_remote"],
+           "halo": info["halo"], "halo_bytes": info["halo_bytes"],
+           "part1_us": round(ms1 * 1e3, 2), "part1_gbs": round(info["bytes_part1"] / (ms1 * 1e-3) / 1e9, 1),
+           "gather_us": round(msg * 1e3, 2), "part2_us": round(ms2 * 1e3, 2),
+           "unsplit_spmv_us_whole_matrix": round(ms_spmv * 1e3, 2),
+           "unsplit_spmv_us_per_slab": round(ms_spmv * 1e3 / parts, 2),
+           "halo_transfer_us_one_xgmi_link": round(info["halo_bytes"] / link * 1e6, 2)}
+    return out
+
+
 def leg_c4(torch, ppcg, wl, count=256):
     spec = wl.batch_c4(seed=0, count=count)
     t0 = time.perf_counter()
@@ -385,14 +418,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    ap.add_argument("--legs", default="c1,c3,c4,c5,p125,pcg", help="extra legs: c1,c3,c4,c5,p125,pcg or none")
+    ap.add_argument("--legs", default="c1,c3,c4,c5,p125,pcg,shard",
+                    help="extra legs: c1,c3,c4,c5,p125,pcg,shard or none")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 256 MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this library runs on one GPU; multi-GPU runs are not supported "
-              "(the sharded design is described in DESIGN.md).", file=sys.stderr)
+              "(only the per-unit row split and shard SpMV exist, measured by the 'shard' leg).", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -429,6 +463,8 @@ def main():
                 legs[name] = leg_c3(torch, ppcg, wl)
             elif name == "pcg":
                 legs[name] = leg_pcg(torch, ppcg, wl)
+            elif name == "shard":
+                legs[name] = leg_shard(torch, ppcg, wl)
             elif name == "c4":
                 legs[name] = leg_c4(torch, ppcg, wl)
             elif name == "c5":

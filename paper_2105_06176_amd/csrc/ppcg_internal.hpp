@@ -37,7 +37,7 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 // Systems with at most this many rows (SELL format, FP64) iterate in the
 // one-workgroup kernel: for them launch latency, not bandwidth, dominates.
 #ifndef PPCG_SMALL_MAX_ROWS
-#define PPCG_SMALL_MAX_ROWS 8192
+#define PPCG_SMALL_MAX_ROWS 4096
 #endif
 
 enum Fmt : int { FMT_SELL = 1, FMT_CSRV = 2 };

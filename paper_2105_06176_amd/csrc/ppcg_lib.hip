@@ -579,6 +579,12 @@ ppcg_status ensure_f32(ppcg_handle *h)
 // ---------------------------------------------------------------- engine
 Engine::~Engine()
 {
+    if (small_stream_) {
+        (void)hipStreamSynchronize(small_stream_);
+        (void)hipStreamDestroy(small_stream_);
+    }
+    if (ev_fork_) (void)hipEventDestroy(ev_fork_);
+    if (ev_join_) (void)hipEventDestroy(ev_join_);
     for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
@@ -619,6 +625,11 @@ ppcg_status Engine::ensure_group(Group &g, int prec, int cap_sys)
 
 ppcg_status Engine::init(int cap_sys)
 {
+    if (!small_stream_) {
+        PPCG_HIP(hipStreamCreateWithFlags(&small_stream_, hipStreamNonBlocking));
+        PPCG_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+        PPCG_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+    }
     PPCG_TRY(ensure_group(g64_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(g32_, PREC_F32, cap_sys));
     PPCG_TRY(ensure_group(gv_, PREC_V32, cap_sys));
@@ -1198,22 +1209,32 @@ ppcg_status Engine::step(int graph_iters)
         }
     }
     // 4. One graph chunk per non-empty group; the small group runs its
-    //    chunk as a single launch of the one-workgroup kernel.
+    //    chunk as a single launch of the one-workgroup kernel on its own
+    //    stream, concurrently with the other groups' graphs.
+    bool small_forked = false;
+    if (!gs_.table_h.empty()) {
+        PPCG_TRY(ensure_table(gs_));
+        // fork: everything enqueued so far (tables, aux work) precedes the
+        // small-system launch; it is joined back before the poll below
+        PPCG_HIP(hipEventRecord(ev_fork_, stream_));
+        PPCG_HIP(hipStreamWaitEvent(small_stream_, ev_fork_, 0));
+        k_small_iter<<<(int)gs_.table_h.size(), kSmallThreads, 0, small_stream_>>>(
+            gs_.table_d, gs_.count_d, gs_.desc_d, chunk_iters(gs_, kSmallChunkIters));
+        PPCG_HIP(hipGetLastError());
+        PPCG_HIP(hipEventRecord(ev_join_, small_stream_));
+        small_forked = true;
+    }
     for (Group *g : groups) {
-        if (g->table_h.empty())
+        if (g == &gs_ || g->table_h.empty())
             continue;
         PPCG_TRY(ensure_table(*g));
-        if (g == &gs_) {
-            k_small_iter<<<(int)gs_.table_h.size(), kSmallThreads, 0, stream_>>>(
-                gs_.table_d, gs_.count_d, gs_.desc_d, chunk_iters(gs_, kSmallChunkIters));
-            PPCG_HIP(hipGetLastError());
-            continue;
-        }
         hipGraphExec_t exec = nullptr;
         PPCG_TRY(ensure_graph(*g, chunk_iters(*g, graph_iters), &exec));
         PPCG_HIP(hipGraphLaunch(exec, stream_));
     }
     // 5. Poll.
+    if (small_forked)
+        PPCG_HIP(hipStreamWaitEvent(stream_, ev_join_, 0));
     for (Group *g : groups)
         PPCG_TRY(sync_states(*g));
     PPCG_HIP(hipStreamSynchronize(stream_));

@@ -6,7 +6,7 @@ bit for bit.  The dot products are reduced in a different (fixed, tree)
 order, so the scalars alpha and beta differ in their last bits and iterates
 drift apart by rounding; for the well-conditioned cases here that drift stays
 below 1e-10 relative after the fixed iteration counts tested, the bound set
-for the FP64 iterates.  Tolerance solves are judged on the true residual and
+for the FP64 iterates.  Tolerance solves are checked on the true residual and
 on the iteration count (equal to the oracle's within 2).
 """
 

@@ -114,3 +114,33 @@ def test_figure_matrix_other_splits_by_hand():
     assert P.decompose(A.rp, A.ci, 0, 3) == (9, 1, [3])
     assert P.decompose(A.rp, A.ci, 3, 5) == (4, 1, [2])
     assert P.decompose(A.rp, A.ci, 0, 5) == (15, 0, [])
+
+
+# ---------------------------------------------------------------- the library's planner (host only)
+
+def test_library_split_rows_matches_reference():
+    from paper_2105_06176_amd import ppcg
+
+    rng = np.random.default_rng(7)
+    mats = [random_spd(2000, seed=1), poisson3d(10), _figure_matrix()[0]]
+    for A in mats:
+        for parts in (1, 2, 3, 5, 8):
+            for _ in range(6):
+                t = rng.uniform(0.05, 3.0, size=parts)
+                assert ppcg.split_rows(A.rp, t) == P.split_rows(A.rp, t), (A.name, parts, t)
+    A, meta = _figure_matrix()
+    assert ppcg.split_rows(A.rp, [1.5, 1.0]) == [0, meta["N_cpu"], 5]
+
+
+def test_library_split_rows_rejects_bad_input():
+    from paper_2105_06176_amd import ppcg
+
+    rp = np.array([0, 2, 4], np.int32)
+    with pytest.raises(ppcg.PPCGError):
+        ppcg.split_rows(rp, [1.0, 0.0])
+    with pytest.raises(ppcg.PPCGError):
+        ppcg.split_rows(rp, [1.0, float("nan")])
+    with pytest.raises(ppcg.PPCGError):
+        ppcg.split_rows(np.array([0, 3, 2], np.int32), [1.0, 1.0])
+    # no non-zeros: the first unit takes every row
+    assert ppcg.split_rows(np.zeros(4, np.int32), [1.0, 2.0]) == [0, 3, 3]
