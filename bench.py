@@ -359,8 +359,7 @@ def _serve_requests(wl, n_req, seed=0):
         else:
             A = wl.random_spd(max(64, int(N)), seed=int(rng.integers(1 << 30)))
         b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 2000 + i))
-        prec = "mixed_values" if tol >= 1e-8 else "fp64"
-        reqs.append((A, b, tol, prec))
+        reqs.append((A, b, tol, "auto"))  # the server picks FP64 or FP32 values per request
     return reqs
 
 
@@ -397,7 +396,8 @@ def leg_c5(ppcg, wl, n_req):
     total, lat = _run_server(ppcg, reqs, np.zeros(n_req))  # saturation: all at t = 0
     sat = n_req / total
     out = {"workload": f"{n_req} requests: 40% 2D 5-pt, 30% 3D 7-pt, 30% random SPD, N log-uniform [1e3,4e6], "
-                       "tol {1e-6,1e-8,1e-10}; FP32 values + FP64 reliable updates for tol >= 1e-8",
+                       "tol {1e-6,1e-8,1e-10}; precision chosen by the server (FP32 values with FP64 "
+                       "reliable updates for >= 65536 rows, else FP64)",
            "saturation_solves_per_s": round(sat, 2)}
     rng = np.random.default_rng(0)
     for frac in (0.5, 0.8):

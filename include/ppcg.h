@@ -64,12 +64,19 @@ typedef enum {
     PPCG_MIXED_FP32 = 1,  /* inner PIPECG with FP32 matrix values and vectors, FP64 dot
                              products and scalars, restarted inside an FP64
                              iterative-refinement loop on the FP64 operator */
-    PPCG_MIXED_FP32_VALUES = 2 /* one PIPECG sequence whose SpMVs read FP32 matrix values
+    PPCG_MIXED_FP32_VALUES = 2, /* one PIPECG sequence whose SpMVs read FP32 matrix values
                              (FP64 vectors, FP64 accumulation, FP64 dots and scalars),
                              with reliable updates: whenever the residual has dropped by
                              inner_tol (default 1e-3) the FP64 residual b - A x is
                              recomputed with the FP64 values and the pipelined
                              auxiliary vectors are rebuilt from it */
+    PPCG_PRECISION_AUTO = 3 /* serving only (ppcg_srv_submit): the server chooses per request by
+                             a byte model of one iteration.  Systems of at least 65536 rows
+                             (bandwidth-bound) run PPCG_MIXED_FP32_VALUES when its bytes per
+                             iteration (8 per stored entry + 176 per row) are at least 5% below
+                             FP64's (12 per entry + 176 per row); others run PPCG_FP64.  A
+                             FP32-values request that ends PPCG_STAGNATED or PPCG_BREAKDOWN is
+                             run again in PPCG_FP64 from its last iterate */
 } ppcg_precision;
 
 /* Iteration scheme (ppcg_options.method). */
@@ -326,9 +333,9 @@ ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *
                             ppcg_server **out);
 
 /* Queue a request.  A: host CSR (copied before returning); b: host [n] FP64,
- * copied; tol: this request's tolerance; precision: PPCG_FP64 or
- * PPCG_MIXED_FP32.  *req_id receives the request's id.  PPCG_ERR_BUDGET when
- * the request could never fit the budget. */
+ * copied; tol: this request's tolerance; precision: any ppcg_precision,
+ * PPCG_PRECISION_AUTO included.  *req_id receives the request's id.
+ * PPCG_ERR_BUDGET when the request could never fit the budget. */
 ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, double tol,
                             ppcg_precision precision, int64_t *req_id);
 

@@ -692,164 +692,6 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_spmv(const WorkItem *__rest
     }
 }
 
-// ---------------------------------------------------------------------------
-// Small systems: one workgroup of kSmallThreads runs up to `iters` whole
-// PIPECG iterations of one system per launch (work item = system).  Thread t
-// owns the rows t, t + kSmallThreads, ... (at most kSmallRowsPerThread) and
-// keeps their z, q, s, p, r, u, w and n in registers for the whole launch;
-// m, the only vector other rows read (the SpMV gathers), lives in LDS.  An
-// iteration touches global memory only for the matrix, the inverse diagonal
-// and x (read-modify-write; all L2-resident at these sizes): fused update, fixed-
-// order workgroup reduction and scalar update (thread 0), workgroup barrier,
-// SpMV from LDS, barrier.  Vectors are loaded at the start and stored at the
-// end of the launch, so the state in HBM is complete between launches.  SELL
-// format only; rows of a wavefront form one SELL chunk, so chunk lengths are
-// uniform across each wavefront.
-constexpr int kSmallThreads = 512;
-constexpr int kSmallRowsPerThread = 8;
-constexpr int kSmallMaxRows = kSmallThreads * kSmallRowsPerThread;
-static_assert(PPCG_SMALL_MAX_ROWS <= kSmallMaxRows, "small systems must fit the register-resident kernel");
-
-__global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__restrict__ table,
-                                                              const int *__restrict__ count,
-                                                              const SysDesc *__restrict__ descs, int iters)
-{
-    constexpr int R = kSmallRowsPerThread;
-    __shared__ double lds[kSmallThreads / 64 * kNumPartials];
-    __shared__ double lm[kSmallMaxRows];  // m
-    __shared__ double scal[2];            // alpha, beta of the next update
-    __shared__ int stop;
-    if ((int)blockIdx.x >= *count)
-        return;
-    const WorkItem wi = table[blockIdx.x];
-    const SysDesc &d = descs[wi.slot];
-    SysState *st = d.st;
-    const int n = d.n;
-    double *__restrict__ X = (double *)d.x;
-    double *__restrict__ Rv = (double *)d.r;
-    double *__restrict__ U = (double *)d.u;
-    double *__restrict__ W = (double *)d.w;
-    double *__restrict__ M = (double *)d.m;
-    double *__restrict__ NVv = (double *)d.nv;
-    double *__restrict__ Z = (double *)d.z;
-    double *__restrict__ Q = (double *)d.q;
-    double *__restrict__ S = (double *)d.s;
-    double *__restrict__ P = (double *)d.p;
-    const double *__restrict__ DI = (const double *)d.dinv;
-    const double *__restrict__ val = (const double *)d.val;
-    const int *__restrict__ col = d.col;
-    const int64_t *__restrict__ cptr = d.cptr;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double z[R], q[R], s[R], p[R], r[R], u[R], w[R], nv[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int i = threadIdx.x + j * kSmallThreads;
-        const bool ok = i < n;
-        z[j] = ok ? Z[i] : 0.0;
-        q[j] = ok ? Q[i] : 0.0;
-        s[j] = ok ? S[i] : 0.0;
-        p[j] = ok ? P[i] : 0.0;
-        r[j] = ok ? Rv[i] : 0.0;
-        u[j] = ok ? U[i] : 0.0;
-        w[j] = ok ? W[i] : 0.0;
-        nv[j] = ok ? NVv[i] : 0.0;
-        if (ok)
-            lm[i] = M[i];
-    }
-    if (threadIdx.x == 0) {
-        stop = st->done;
-        scal[0] = st->alpha;
-        scal[1] = st->beta;
-    }
-    __syncthreads();
-    for (int it = 0; it < iters && !stop; ++it) {
-        const double sa = scal[0], sb = scal[1];
-        double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
-        // all global loads of the update first (one memory latency), then the arithmetic
-        double xg[R], dg[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int i = threadIdx.x + j * kSmallThreads;
-            xg[j] = 0.0;
-            dg[j] = 0.0;
-            if (i < n) {
-                xg[j] = X[i];
-                dg[j] = DI[i];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int i = threadIdx.x + j * kSmallThreads;
-            if (i < n) {
-                double mo;
-                vma_elem<double, kNumPartials>(sa, sb, nv[j], z[j], lm[i], q[j], w[j], s[j], u[j], p[j], xg[j],
-                                               r[j], dg[j], mo, acc);
-                X[i] = xg[j];
-                lm[i] = mo;  // only this thread touches lm[i] until the barrier below
-            }
-        }
-        block_sum<kSmallThreads, kNumPartials>(acc, lds);
-        if (threadIdx.x == 0) {
-            scalar_update<kNumPartials>(d, st, acc);
-            stop = st->done;
-            scal[0] = st->alpha;
-            scal[1] = st->beta;
-        }
-        __syncthreads();  // m complete in LDS; the new scalars visible
-        // SpMV from LDS: the wavefront's chunk for row slot j is wave + j *
-        // (waves per workgroup); entry k of all its chunks is fetched together.
-        // (stored entries of a system with at most kSmallMaxRows rows fit 32 bits)
-        int base[R], len[R], maxlen = 0;
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int c = wave + j * (kSmallThreads / 64);
-            base[j] = 0;
-            len[j] = 0;
-            if (c * kSellC < n) {
-                base[j] = (int)cptr[c] + lane;
-                len[j] = (int)((cptr[c + 1] - cptr[c]) / kSellC);
-            }
-            maxlen = len[j] > maxlen ? len[j] : maxlen;
-            nv[j] = 0.0;
-        }
-        for (int k = 0; k < maxlen; ++k) {
-            // entry k of every row slot: loads first, then the LDS gathers
-            int cv[R];
-            double vv[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                cv[j] = 0;
-                vv[j] = 0.0;
-                if (k < len[j]) {
-                    const size_t o = (size_t)base[j] + (size_t)k * kSellC;
-                    cv[j] = col[o];
-                    vv[j] = val[o];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-                if (k < len[j])
-                    nv[j] = nv[j] + vv[j] * lm[cv[j]];
-        }
-        __syncthreads();  // every gather of m done before the next update rewrites it
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int i = threadIdx.x + j * kSmallThreads;
-        if (i < n) {
-            Z[i] = z[j];
-            Q[i] = q[j];
-            S[i] = s[j];
-            P[i] = p[j];
-            Rv[i] = r[j];
-            U[i] = u[j];
-            W[i] = w[j];
-            NVv[i] = nv[j];
-            M[i] = lm[i];
-        }
-    }
-}
-
 // Reduce the true-residual partials of each system (tile-0 workgroups only).
 __global__ __launch_bounds__(kSpmvThreads) void k_reduce_resid(const WorkItem *__restrict__ table,
                                                                const int *__restrict__ count,

@@ -24,6 +24,7 @@
 #include "ppcg_engine.hpp"
 #include "ppcg_kernels.hpp"
 #include "ppcg_pcg.hpp"
+#include "ppcg_small.hpp"
 #include "ppcg_setup.hpp"
 
 namespace ppcg {

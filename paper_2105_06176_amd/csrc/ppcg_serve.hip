@@ -35,6 +35,7 @@ struct Request {
     double footprint = 0.0;
     double tol = 0.0;
     ppcg_precision precision = PPCG_FP64;
+    bool auto_prec = false;  // chosen by the server; FP32 values fall back to FP64
     int32_t n = 0;
     std::vector<int32_t> rp, ci;
     std::vector<double> val, b, x;
@@ -91,7 +92,8 @@ static ppcg_status admit(ppcg_server *s)
         PPCG_TRY(wait_user(r.h));
         hipStream_t keep = r.h->stream;
         r.h->stream = s->eng->stream();
-        rc = stage_inputs(r.h, r.b.data(), nullptr);
+        // a rerun (automatic precision fallback) starts from the last iterate
+        rc = stage_inputs(r.h, r.b.data(), r.x.empty() ? nullptr : r.x.data());
         r.h->stream = keep;
         PPCG_TRY(rc);
         const int mixed = r.precision == PPCG_MIXED_FP32          ? MIX_INNER32
@@ -101,10 +103,12 @@ static ppcg_status admit(ppcg_server *s)
         r.state = 1;
         s->used += r.footprint;
         ++s->active;
-        // inputs now live on the device
-        std::vector<int32_t>().swap(r.rp);
-        std::vector<int32_t>().swap(r.ci);
-        std::vector<double>().swap(r.val);
+        // inputs now live on the device (kept while a fallback rerun may need them)
+        if (!(r.auto_prec && r.precision == PPCG_MIXED_FP32_VALUES)) {
+            std::vector<int32_t>().swap(r.rp);
+            std::vector<int32_t>().swap(r.ci);
+            std::vector<double>().swap(r.val);
+        }
     }
     return PPCG_OK;
 }
@@ -130,10 +134,23 @@ static ppcg_status retire_finished(ppcg_server *s)
         s->eng->retire(r.job);
         ppcg_destroy(r.h);
         r.h = nullptr;
-        r.state = 2;
         s->used -= r.footprint;
         --s->active;
+        if (r.auto_prec && r.precision == PPCG_MIXED_FP32_VALUES &&
+            (r.info.status == PPCG_STAGNATED || r.info.status == PPCG_BREAKDOWN)) {
+            // FP32 values did not reach the tolerance: run again in FP64 from
+            // the last iterate, ahead of the requests still queued
+            r.precision = PPCG_FP64;
+            r.footprint = ppcg_footprint_bytes(r.n, (int64_t)r.ci.size(), PPCG_FP64);
+            r.state = 0;
+            s->queue.push_front(kv.first);
+            continue;
+        }
+        r.state = 2;
         std::vector<double>().swap(r.b);
+        std::vector<int32_t>().swap(r.rp);
+        std::vector<int32_t>().swap(r.ci);
+        std::vector<double>().swap(r.val);
     }
     return PPCG_OK;
 }
@@ -170,9 +187,18 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
     clear_error();
     if (!s || !A || !b || !req_id || A->struct_size != sizeof(ppcg_csr) || A->mem != PPCG_MEM_HOST || A->n < 1 ||
         A->nnz < A->n || !A->row_ptr || !A->col_idx || !A->values || !(tol >= 0.0) ||
-        (precision != PPCG_FP64 && precision != PPCG_MIXED_FP32 && precision != PPCG_MIXED_FP32_VALUES)) {
+        (precision != PPCG_FP64 && precision != PPCG_MIXED_FP32 && precision != PPCG_MIXED_FP32_VALUES &&
+         precision != PPCG_PRECISION_AUTO)) {
         set_error("invalid request");
         return PPCG_ERR_INVALID_ARG;
+    }
+    const bool auto_prec = precision == PPCG_PRECISION_AUTO;
+    if (auto_prec) {
+        // bytes of one PIPECG iteration: 12 (FP64) or 8 (FP32 values) per
+        // stored entry, plus the 22 FP64 vector streams of a row
+        const double b64 = 12.0 * (double)A->nnz + 176.0 * A->n;
+        const double b32 = 8.0 * (double)A->nnz + 176.0 * A->n;
+        precision = (A->n >= 65536 && b32 <= 0.95 * b64) ? PPCG_MIXED_FP32_VALUES : PPCG_FP64;
     }
     const double fp = ppcg_footprint_bytes(A->n, A->nnz, precision);
     if (fp > s->budget) {
@@ -184,6 +210,7 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
     r.footprint = fp;
     r.tol = tol;
     r.precision = precision;
+    r.auto_prec = auto_prec;
     r.n = A->n;
     r.rp.assign(A->row_ptr, A->row_ptr + A->n + 1);
     r.ci.assign(A->col_idx, A->col_idx + A->nnz);

@@ -19,13 +19,13 @@ LIB_PATH = os.path.join(HERE, "libppcg.so")
 OK, NOT_CONVERGED, BREAKDOWN, STAGNATED = 0, 1, 2, 3
 ERR_INVALID_ARG, ERR_BAD_CSR, ERR_NOMEM, ERR_DEVICE, ERR_BUDGET = -1, -2, -3, -4, -5
 STOP_REL_RESID, STOP_PRECOND_ABS = 0, 1
-FP64, MIXED_FP32, MIXED_FP32_VALUES = 0, 1, 2
+FP64, MIXED_FP32, MIXED_FP32_VALUES, PRECISION_AUTO = 0, 1, 2, 3
 MEM_DEVICE, MEM_HOST = 0, 1
 METHOD_PIPECG, METHOD_PCG = 0, 1
 SPMV_AUTO, SPMV_SELL, SPMV_CSR_VECTOR = 0, 1, 2
 
 _STOP = {"rel": STOP_REL_RESID, "abs": STOP_PRECOND_ABS}
-_PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_values": MIXED_FP32_VALUES}
+_PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_values": MIXED_FP32_VALUES, "auto": PRECISION_AUTO}
 _FMT = {"auto": SPMV_AUTO, "sell": SPMV_SELL, "csr_vector": SPMV_CSR_VECTOR}
 _METHOD = {"pipecg": METHOD_PIPECG, "pcg": METHOD_PCG}
 

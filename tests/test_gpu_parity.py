@@ -434,6 +434,34 @@ def test_server_refuses_over_budget_and_admits_in_turn():
         assert np.array_equal(x, xs[0])
 
 
+def test_server_automatic_precision():
+    """Automatic precision: a large request runs with FP32 values (it makes
+    reliable updates), a small one in FP64; both reach the tolerance."""
+    big, small = poisson3d(48), poisson2d(40)
+    reqs = [("big", big, problem(big)[0], 1e-10, "auto"), ("small", small, problem(small)[0], 1e-10, "auto")]
+    res = _serve_all(Server(), reqs)
+    for key, A, b, tol, _ in reqs:
+        assert res[key][1]["status"] == ppcg.OK
+        assert oracle.true_relres(A, b, res[key][0]) <= tol
+    assert res["big"][1]["outer_iters"] >= 1
+    assert res["small"][1]["outer_iters"] == 0
+
+
+def test_server_automatic_precision_falls_back_to_fp64():
+    """With reliable updates switched off (no pause, no update allowed), the
+    FP32-values run of a matrix whose values FP32 does not represent ends
+    above tol (STAGNATED); the server reruns it in FP64 from its last
+    iterate, which then needs fewer iterations than a solve from zero."""
+    big = stencil27_lognormal(48, seed=1)
+    b = problem(big)[0]
+    res = _serve_all(Server(inner_tol=1e-30, max_outer=0), [("big", big, b, 1e-10, "auto")])
+    x, info = res["big"]
+    assert info["status"] == ppcg.OK
+    assert oracle.true_relres(big, b, x) <= 1e-10
+    assert info["outer_iters"] == 0
+    assert info["iters"] < 0.8 * oracle.pipecg(big, b, tol=1e-10).iters
+
+
 # ---------------------------------------------------------------- FP32 values + reliable updates
 
 def _round32(A):
