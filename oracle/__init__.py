@@ -69,12 +69,15 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(
-            os.path.join(HERE, "ppcg_oracle.c")):
+    # ORACLE_LIB names another build of ppcg_oracle.c; the mutation tests use
+    # it to load copies with a planted mistake in place of the oracle.
+    path = os.environ.get("ORACLE_LIB", _LIB_PATH)
+    if path == _LIB_PATH and (not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(
+            os.path.join(HERE, "ppcg_oracle.c"))):
         from . import build as _b
 
         _b.build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     I = ctypes.c_int
     D = ctypes.c_double
