@@ -36,6 +36,39 @@ namespace ppcg {
 // Threads of the one-workgroup-per-system reduction kernels.
 constexpr int kPcgRedThreads = 1024;
 
+// Fixed-order reduction of NV partials over a system's tiles for the
+// one-workgroup reduction kernels: thread t takes the tiles t, t + NT, ...
+// in index order, with the loads of kPcgRedBatch tiles issued before their
+// sums (one memory latency per batch), then the workgroup tree.
+constexpr int kPcgRedBatch = 4;
+
+template <int NV>
+__device__ __forceinline__ void pcg_reduce(const SysDesc &d, int slot, double (&out)[NV], double *lds)
+{
+    const double *P = d.part + (size_t)slot * d.ntiles * kPartStride;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        out[k] = 0.0;
+    for (int t0 = threadIdx.x; t0 < d.ntiles; t0 += kPcgRedBatch * kPcgRedThreads) {
+        double v[kPcgRedBatch][NV];
+#pragma unroll
+        for (int j = 0; j < kPcgRedBatch; ++j) {
+            const int t = t0 + j * kPcgRedThreads;
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                v[j][k] = t < d.ntiles ? P[(size_t)t * kPartStride + k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kPcgRedBatch; ++j)
+            if (t0 + j * kPcgRedThreads < d.ntiles) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k)
+                    out[k] = out[k] + v[j][k];
+            }
+    }
+    block_sum<kPcgRedThreads, NV>(out, lds);
+}
+
 // Direction buffers: the current direction after k x-updates is in pbuf(k).
 __device__ __forceinline__ double *pcg_dir(const SysDesc &d, int k) { return (double *)((k & 1) ? d.z : d.p); }
 
@@ -160,7 +193,7 @@ __global__ __launch_bounds__(kPcgRedThreads) void k_pcg_alpha(const WorkItem *__
     if (st->done)
         return;
     double dl[1];
-    reduce_partials<kPcgRedThreads, 1>(d, 0, dl, lds);
+    pcg_reduce<1>(d, 0, dl, lds);
     if (threadIdx.x == 0) {
         const double g = st->gamma, beta = st->beta;
         const double alpha = g / dl[0];
@@ -337,7 +370,7 @@ __global__ __launch_bounds__(kPcgRedThreads) void k_pcg_update(const WorkItem *_
     if (KIND == PCG_ITER && st->done)
         return;
     double v[kNumPartials];
-    reduce_partials<kPcgRedThreads>(d, 1, v, lds);
+    pcg_reduce<kNumPartials>(d, 1, v, lds);
     if (threadIdx.x == 0) {
         if (KIND != PCG_ITER) {
             st->bnorm2 = v[3];
