@@ -273,6 +273,31 @@ def leg_shard(torch, ppcg, wl, parts=8):
     return out
 
 
+def leg_hybrid(torch, ppcg, wl, iters=200, threads=8):
+    """Host cores + GPU together (Section IV-C, Hybrid-PIPECG-3) on the 128^3
+    7-point problem: the performance model's split, forced splits, and the
+    rate against the GPU-only solver."""
+    A = wl.poisson3d(128)
+    b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
+    out = {"workload": f"3D 7-point Poisson 128^3, FP64, {iters} fixed iterations, {threads} host threads"}
+    for label, share in (("model", -1.0), ("share_0.02", 0.02), ("share_0", 0.0)):
+        H = ppcg.Hybrid(A, host_threads=threads, cpu_share=share, fixed_iters=20)
+        H.solve(b)
+        H.close()
+        H = ppcg.Hybrid(A, host_threads=threads, cpu_share=share, fixed_iters=iters)
+        t0 = time.perf_counter()
+        x, info = H.solve(b)
+        dt = time.perf_counter() - t0
+        hi = H.info()
+        out[label] = {"iters_per_s": round(iters / dt, 1), "us_per_iter": round(dt / iters * 1e6, 1),
+                      "n_cpu": hi["n_cpu"], "n_gpu": hi["n_gpu"], "t_cpu_spmv_ms": round(hi["t_cpu_spmv_ms"], 3),
+                      "t_gpu_spmv_ms": round(hi["t_gpu_spmv_ms"], 4), "halo_to_cpu": hi["halo_to_cpu"],
+                      "halo_to_gpu": hi["halo_to_gpu"]}
+        log(f"hybrid {label}: {out[label]}")
+        H.close()
+    return out
+
+
 def leg_c4(torch, ppcg, wl, count=256):
     spec = wl.batch_c4(seed=0, count=count)
     t0 = time.perf_counter()
@@ -395,10 +420,27 @@ def leg_c5(ppcg, wl, n_req):
     _run_server(ppcg, reqs[: min(8, n_req)], np.zeros(min(8, n_req)))  # warm-up
     total, lat = _run_server(ppcg, reqs, np.zeros(n_req))  # saturation: all at t = 0
     sat = n_req / total
+    # the same stream with every request in plain FP64, and with FP32 values
+    reqs64 = [(A, b, tol, "fp64") for A, b, tol, _ in reqs]
+    total64, _ = _run_server(ppcg, reqs64, np.zeros(n_req))
+    total32, _ = _run_server(ppcg, [(A, b, tol, "mixed_values") for A, b, tol, _ in reqs], np.zeros(n_req))
+    # plain FP64 PPCG one request after another (a solver per request)
+    t0 = time.perf_counter()
+    import torch
+
+    for A, b, tol, _ in reqs:
+        S = ppcg.Solver(A, tol=tol, vec_mem="host")
+        S.solve(torch.as_tensor(b), out=torch.empty(A.n, dtype=torch.float64))
+        S.close()
+    t_seq = time.perf_counter() - t0
     out = {"workload": f"{n_req} requests: 40% 2D 5-pt, 30% 3D 7-pt, 30% random SPD, N log-uniform [1e3,4e6], "
                        "tol {1e-6,1e-8,1e-10}; precision chosen by the server (FP32 values with FP64 "
                        "reliable updates for >= 65536 rows, else FP64)",
-           "saturation_solves_per_s": round(sat, 2)}
+           "saturation_solves_per_s": round(sat, 2),
+           "saturation_solves_per_s_all_fp64": round(n_req / total64, 2),
+           "saturation_solves_per_s_all_fp32_values": round(n_req / total32, 2),
+           "sequential_fp64_solves_per_s": round(n_req / t_seq, 2),
+           "served_over_sequential_fp64": round(t_seq / total, 3)}
     rng = np.random.default_rng(0)
     for frac in (0.5, 0.8):
         lam = frac * sat
@@ -418,8 +460,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    ap.add_argument("--legs", default="c1,c3,c4,c5,p125,pcg,shard",
-                    help="extra legs: c1,c3,c4,c5,p125,pcg,shard or none")
+    ap.add_argument("--legs", default="c1,c3,c4,c5,p125,pcg,shard,hybrid",
+                    help="extra legs: c1,c3,c4,c5,p125,pcg,shard,hybrid or none")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 256 MiB (reference for HBM counters)")
@@ -465,6 +507,8 @@ def main():
                 legs[name] = leg_pcg(torch, ppcg, wl)
             elif name == "shard":
                 legs[name] = leg_shard(torch, ppcg, wl)
+            elif name == "hybrid":
+                legs[name] = leg_hybrid(torch, ppcg, wl)
             elif name == "c4":
                 legs[name] = leg_c4(torch, ppcg, wl)
             elif name == "c5":

@@ -73,7 +73,7 @@ typedef enum {
     PPCG_PRECISION_AUTO = 3 /* serving only (ppcg_srv_submit): the server chooses per request by
                              a byte model of one iteration.  Systems of at least 65536 rows
                              (bandwidth-bound) run PPCG_MIXED_FP32_VALUES when its bytes per
-                             iteration (8 per stored entry + 176 per row) are at least 5% below
+                             iteration (8 per stored entry + 176 per row) are at least 15% below
                              FP64's (12 per entry + 176 per row); others run PPCG_FP64.  A
                              FP32-values request that ends PPCG_STAGNATED or PPCG_BREAKDOWN is
                              run again in PPCG_FP64 from its last iterate */
@@ -315,6 +315,48 @@ ppcg_status ppcg_shard_spmv(ppcg_shard *s, const double *x_local, const double *
 ppcg_status ppcg_shard_time(ppcg_shard *s, const double *x_global, const double *x_local, double *x_halo,
                             double *y, int32_t iters, double *ms_part1, double *ms_gather, double *ms_part2);
 ppcg_status ppcg_shard_destroy(ppcg_shard *s); /* NULL-safe */
+
+/* ---------------------------------------------------------------------------
+ * Host cores + GPU together (Section IV-C, Hybrid-PIPECG-3).  Setup times five
+ * SpMVs over all of A on the host threads and on the GPU, splits the rows
+ * with the performance model (ppcg_split_rows: rows [0, n_cpu) on the host,
+ * the rest on the GPU) and builds both sides' 2-D decomposition.  Each
+ * iteration of Algorithm 2 then follows the paper's execution flow: the m
+ * entries each side needs from the other move (device <-> pinned host
+ * memory) while both sides update q, s, p, x, r, u and compute SpMV part 1;
+ * part 2 runs once the copy has arrived; then z, w, m and the dot products;
+ * the host adds both sides' partial sums and computes alpha and beta.
+ * ------------------------------------------------------------------------- */
+typedef struct ppcg_hybrid ppcg_hybrid; /* opaque, owned by the library */
+
+typedef struct {
+    size_t struct_size;       /* sizeof(ppcg_hybrid_info) */
+    int32_t n_cpu;            /* rows [0, n_cpu) iterate on the host */
+    int32_t n_gpu;            /* rows [n_cpu, n) iterate on the GPU */
+    int32_t host_threads;
+    double t_cpu_spmv_ms;     /* performance model: one SpMV over all of A on the host threads */
+    double t_gpu_spmv_ms;     /* ... and on the GPU */
+    int64_t nnz_cpu_local;    /* host part 1 / part 2 entries */
+    int64_t nnz_cpu_remote;
+    int64_t nnz_gpu_local;    /* GPU part 1 / part 2 entries */
+    int64_t nnz_gpu_remote;
+    int32_t halo_to_cpu;      /* m entries copied GPU -> host per iteration */
+    int32_t halo_to_gpu;      /* m entries copied host -> GPU per iteration */
+} ppcg_hybrid_info;
+
+/* A: host CSR (read during the call).  opt: PPCG_FP64, PPCG_METHOD_PIPECG,
+ * vec_mem = PPCG_MEM_HOST (b, x0, x are host arrays); tol, max_iter,
+ * fixed_iters, max_restarts and stop as for ppcg_solve.  host_threads: 1..256.
+ * cpu_share < 0: split by the performance model; 0 <= cpu_share <= 1: give
+ * the host that share of the non-zeros instead (same row rule).  Errors:
+ * ERR_INVALID_ARG, ERR_BAD_CSR, ERR_NOMEM, ERR_DEVICE. */
+ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, int32_t host_threads,
+                               double cpu_share, void *hip_stream, ppcg_hybrid **out);
+ppcg_status ppcg_hybrid_get_info(const ppcg_hybrid *hy, ppcg_hybrid_info *info);
+/* b: host [n]; x0: host [n] or NULL (= 0); x: host [n], written; info may be
+ * NULL.  Returns the solve status as ppcg_solve does. */
+ppcg_status ppcg_hybrid_solve(ppcg_hybrid *hy, const double *b, const double *x0, double *x, ppcg_info *info);
+ppcg_status ppcg_hybrid_destroy(ppcg_hybrid *hy); /* NULL-safe */
 
 /* ---------------------------------------------------------------------------
  * Serving: a continuous-batching solve server.  Requests are admitted while

@@ -6,5 +6,5 @@
 
 from .ppcg import (  # noqa: F401
     BREAKDOWN, ERR_BAD_CSR, ERR_BUDGET, ERR_INVALID_ARG, NOT_CONVERGED, OK, STAGNATED,
-    PPCGError, Server, Shard, Solver, footprint_bytes, lib, make_options, solve_batch, split_rows,
+    Hybrid, PPCGError, Server, Shard, Solver, footprint_bytes, lib, make_options, solve_batch, split_rows,
 )

@@ -157,19 +157,26 @@ __global__ void k_shard_gather(int h, const int *__restrict__ cols, const double
 
 }  // namespace
 
-struct ppcg_shard {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int n = 0, lo = 0, hi = 0;
-    int64_t nnz1 = 0, nnz2 = 0;
-    int halo = 0, nb = 0;
-    int nch1 = 0, nch2 = 0;
-    std::vector<int> halo_cols;  // host copy
-    DevArena arena;
-    int64_t *cptr1 = nullptr, *cptr2 = nullptr;
-    int *col1 = nullptr, *col2 = nullptr, *brow = nullptr, *hcols = nullptr;
-    double *val1 = nullptr, *val2 = nullptr;
-};
+#include "ppcg_shard_internal.hpp"
+
+ppcg_status shard_launch(ppcg_shard *s, int which, const double *x_local, const double *x_halo, double *y,
+                         hipEvent_t e0, hipEvent_t e1)
+{
+    const int rows = s->hi - s->lo;
+    const int cpb = kShardThreads / 64;
+    if (which == 1) {
+        const int grid = (s->nch1 + cpb - 1) / cpb;
+        hipExtLaunchKernelGGL(k_shard_part1, dim3(grid), dim3(kShardThreads), 0, s->stream, e0, e1, 0, rows,
+                              (const int64_t *)s->cptr1, (const int *)s->col1, (const double *)s->val1, x_local, y);
+    } else if (s->nb > 0) {
+        const int grid = (s->nch2 + cpb - 1) / cpb;
+        hipExtLaunchKernelGGL(k_shard_part2, dim3(grid), dim3(kShardThreads), 0, s->stream, e0, e1, 0, s->nb,
+                              (const int *)s->brow, (const int64_t *)s->cptr2, (const int *)s->col2,
+                              (const double *)s->val2, x_halo, y);
+    }
+    PPCG_HIP(hipGetLastError());
+    return PPCG_OK;
+}
 
 extern "C" {
 
@@ -391,24 +398,6 @@ ppcg_status ppcg_shard_halo_columns(const ppcg_shard *s, int32_t *cols)
     return PPCG_OK;
 }
 
-static ppcg_status shard_launch(ppcg_shard *s, int which, const double *x_local, const double *x_halo, double *y,
-                                hipEvent_t e0, hipEvent_t e1)
-{
-    const int rows = s->hi - s->lo;
-    const int cpb = kShardThreads / 64;
-    if (which == 1) {
-        const int grid = (s->nch1 + cpb - 1) / cpb;
-        hipExtLaunchKernelGGL(k_shard_part1, dim3(grid), dim3(kShardThreads), 0, s->stream, e0, e1, 0, rows,
-                              (const int64_t *)s->cptr1, (const int *)s->col1, (const double *)s->val1, x_local, y);
-    } else if (s->nb > 0) {
-        const int grid = (s->nch2 + cpb - 1) / cpb;
-        hipExtLaunchKernelGGL(k_shard_part2, dim3(grid), dim3(kShardThreads), 0, s->stream, e0, e1, 0, s->nb,
-                              (const int *)s->brow, (const int64_t *)s->cptr2, (const int *)s->col2,
-                              (const double *)s->val2, x_halo, y);
-    }
-    PPCG_HIP(hipGetLastError());
-    return PPCG_OK;
-}
 
 ppcg_status ppcg_shard_gather(ppcg_shard *s, const double *x_global, double *x_halo)
 {

@@ -75,12 +75,24 @@ class ShardInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
 
 
+class HybridInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("n_cpu", ctypes.c_int32), ("n_gpu", ctypes.c_int32),
+                ("host_threads", ctypes.c_int32), ("t_cpu_spmv_ms", ctypes.c_double),
+                ("t_gpu_spmv_ms", ctypes.c_double), ("nnz_cpu_local", ctypes.c_int64),
+                ("nnz_cpu_remote", ctypes.c_int64), ("nnz_gpu_local", ctypes.c_int64),
+                ("nnz_gpu_remote", ctypes.c_int64), ("halo_to_cpu", ctypes.c_int32), ("halo_to_gpu", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
+
+
 EXPORTS = ["ppcg_default_options", "ppcg_create", "ppcg_set_options", "ppcg_solve", "ppcg_solve_batch",
            "ppcg_spmv",
            "ppcg_get_matrix_info", "ppcg_footprint_bytes", "ppcg_time_kernels", "ppcg_destroy",
            "ppcg_status_str", "ppcg_last_error", "ppcg_split_rows", "ppcg_shard_create", "ppcg_shard_get_info",
            "ppcg_shard_halo_columns", "ppcg_shard_gather", "ppcg_shard_spmv", "ppcg_shard_time",
-           "ppcg_shard_destroy", "ppcg_srv_create", "ppcg_srv_submit", "ppcg_srv_step",
+           "ppcg_shard_destroy", "ppcg_hybrid_create", "ppcg_hybrid_get_info", "ppcg_hybrid_solve",
+           "ppcg_hybrid_destroy", "ppcg_srv_create", "ppcg_srv_submit", "ppcg_srv_step",
            "ppcg_srv_poll", "ppcg_srv_destroy"]
 
 _lib = None
@@ -118,6 +130,11 @@ def lib():
         "ppcg_shard_time": ([P, P, P, P, P, I32, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
                             ctypes.c_int),
         "ppcg_shard_destroy": ([P], ctypes.c_int),
+        "ppcg_hybrid_create": ([ctypes.POINTER(Csr), ctypes.POINTER(Options), I32, D, P, ctypes.POINTER(P)],
+                               ctypes.c_int),
+        "ppcg_hybrid_get_info": ([P, ctypes.POINTER(HybridInfo)], ctypes.c_int),
+        "ppcg_hybrid_solve": ([P, P, P, P, ctypes.POINTER(Info)], ctypes.c_int),
+        "ppcg_hybrid_destroy": ([P], ctypes.c_int),
         "ppcg_srv_create": ([ctypes.POINTER(Options), D, P, ctypes.POINTER(P)], ctypes.c_int),
         "ppcg_srv_submit": ([P, ctypes.POINTER(Csr), P, D, ctypes.c_int, ctypes.POINTER(I64)], ctypes.c_int),
         "ppcg_srv_step": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
@@ -403,6 +420,54 @@ class Shard:
         if getattr(self, "s", None):
             lib().ppcg_shard_destroy(self.s)
             self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hybrid:
+    """Algorithm 2 on host threads and the GPU together (rows split by the
+    performance model, or by a forced share of the non-zeros)."""
+
+    def __init__(self, A, host_threads: int = 4, cpu_share: float = -1.0, stream=None, **options):
+        options.setdefault("vec_mem", "host")
+        self.opt = make_options(**options)
+        keep: list = []
+        c = _csr_struct(A, keep)
+        if c.mem != MEM_HOST:
+            raise ValueError("the host + GPU solver takes host CSR arrays")
+        h = ctypes.c_void_p()
+        _check(lib().ppcg_hybrid_create(ctypes.byref(c), ctypes.byref(self.opt), int(host_threads),
+                                        float(cpu_share), _stream_ptr(stream), ctypes.byref(h)),
+               "ppcg_hybrid_create")
+        self.h = h
+        self.n = int(c.n)
+
+    def info(self) -> dict:
+        i = HybridInfo()
+        i.struct_size = ctypes.sizeof(HybridInfo)
+        _check(lib().ppcg_hybrid_get_info(self.h, ctypes.byref(i)), "ppcg_hybrid_get_info")
+        return i.as_dict()
+
+    def solve(self, b, x0=None):
+        import numpy as np
+
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        xx = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        x = np.empty(self.n, dtype=np.float64)
+        info = Info()
+        info.struct_size = ctypes.sizeof(Info)
+        _check(lib().ppcg_hybrid_solve(self.h, bb.ctypes.data, None if xx is None else xx.ctypes.data,
+                                       x.ctypes.data, ctypes.byref(info)), "ppcg_hybrid_solve")
+        return x, info.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ppcg_hybrid_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -55,6 +55,10 @@ def test_host_side_argument_errors():
     assert L.ppcg_solve(None, None, None, None, None) == ppcg.ERR_INVALID_ARG
     assert L.ppcg_destroy(None) == ppcg.OK
     assert L.ppcg_srv_destroy(None) == ppcg.OK
+    assert L.ppcg_shard_destroy(None) == ppcg.OK
+    assert L.ppcg_hybrid_destroy(None) == ppcg.OK
+    assert L.ppcg_hybrid_create(None, None, 1, -1.0, None, None) == ppcg.ERR_INVALID_ARG
+    assert L.ppcg_shard_create(None, 0, 1, None, None) == ppcg.ERR_INVALID_ARG
     assert L.ppcg_footprint_bytes(0, 0, 0) == 0.0
     assert L.ppcg_footprint_bytes(1000, 5000, 1) > L.ppcg_footprint_bytes(1000, 5000, 0) > 0
 
@@ -67,8 +71,12 @@ LAYOUT_C = r"""
 int main(void) {
   printf("ppcg_csr %zu\nppcg_options %zu\nppcg_info %zu\nppcg_matrix_info %zu\n",
          sizeof(ppcg_csr), sizeof(ppcg_options), sizeof(ppcg_info), sizeof(ppcg_matrix_info));
+  printf("ppcg_shard_info %zu\nppcg_hybrid_info %zu\n", sizeof(ppcg_shard_info), sizeof(ppcg_hybrid_info));
   F(ppcg_csr, nnz) F(ppcg_csr, values) F(ppcg_csr, mem)
-  F(ppcg_options, tol) F(ppcg_options, stop) F(ppcg_options, inner_tol) F(ppcg_options, flags)
+  F(ppcg_options, tol) F(ppcg_options, stop) F(ppcg_options, inner_tol) F(ppcg_options, method)
+  F(ppcg_options, flags)
+  F(ppcg_shard_info, nnz_local) F(ppcg_shard_info, boundary_rows) F(ppcg_shard_info, halo_bytes)
+  F(ppcg_hybrid_info, t_cpu_spmv_ms) F(ppcg_hybrid_info, nnz_gpu_remote) F(ppcg_hybrid_info, halo_to_gpu)
   F(ppcg_info, status) F(ppcg_info, rel_resid_true) F(ppcg_info, model_bytes)
   F(ppcg_matrix_info, nnz_stored) F(ppcg_matrix_info, tile_rows) F(ppcg_matrix_info, setup_ms)
   return 0;
@@ -84,7 +92,8 @@ def test_ctypes_structs_match_c_layout(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     got = dict(line.split() for line in out if line.strip())
     py = {"ppcg_csr": ppcg.Csr, "ppcg_options": ppcg.Options, "ppcg_info": ppcg.Info,
-          "ppcg_matrix_info": ppcg.MatrixInfo}
+          "ppcg_matrix_info": ppcg.MatrixInfo, "ppcg_shard_info": ppcg.ShardInfo,
+          "ppcg_hybrid_info": ppcg.HybridInfo}
     for k, v in got.items():
         if "." in k:
             t, m = k.split(".")

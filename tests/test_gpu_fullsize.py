@@ -1,0 +1,111 @@
+"""Parity at the workloads' full sizes, in the configurations bench.py times:
+the 27-point lognormal stencil at 160^3 (FP64 and FP32 values), the 256-system
+batch, and Table 2's 125-point Poisson matrix at side 165.  Reference values
+the oracle cannot afford at this size inline come from tests/golden (written by
+make_c3_p125_reference.py from the oracle only); the rest is checked through
+properties that hold at any size (true residual recomputed by the oracle,
+SpMV bit for bit)."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_06176_amd import ppcg
+from paper_2105_06176_amd.ppcg import Solver, solve_batch
+from workloads import (batch_c4, poisson125, poisson2d, rhs_from_solution, shifted, stencil27_lognormal,
+                       xstar_paper, xstar_uniform)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dev(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _golden(name, key):
+    vals, meta = {}, {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            p = line.split()
+            if p[0] == key:
+                vals[int(p[1])] = float(p[2])
+            else:
+                meta[p[0]] = float(p[1])
+    return vals, meta
+
+
+def _check_sampled(x, vals, meta, k):
+    idx = np.array(sorted(vals))
+    assert relerr(x[idx], np.array([vals[i] for i in idx])) <= 1e-10
+    assert abs(np.linalg.norm(x) - meta[f"norm_x{k}"]) <= 1e-10 * meta[f"norm_x{k}"]
+
+
+def test_c3_stencil27_160_full_size():
+    A = stencil27_lognormal(160, seed=0, shift=1e-3)
+    b = rhs_from_solution(A, xstar_uniform(A.n, 1))
+    vals, meta = _golden("c3_stencil27_160.txt", "x10")
+    assert (meta["n"], meta["nnz"]) == (A.n, A.nnz)
+    S = Solver(A, fixed_iters=10, spmv_format="sell")
+    xt = xstar_uniform(A.n, 5)
+    assert np.array_equal(host(S.spmv(dev(xt))), oracle.spmv(A, xt))
+    x, info = S.solve(dev(b))
+    assert info["iters"] == 10
+    _check_sampled(host(x), vals, meta, 10)
+    # to 1e-10 in FP64 and with FP32 values: true residuals recomputed by the oracle
+    S.set_options(tol=1e-10, max_iter=20000, spmv_format="sell")
+    x64, i64 = S.solve(dev(b))
+    assert i64["status"] == ppcg.OK and oracle.true_relres(A, b, host(x64)) <= 1e-10
+    S.set_options(tol=1e-10, max_iter=20000, spmv_format="sell", precision="mixed_values")
+    x32, i32 = S.solve(dev(b))
+    assert i32["status"] == ppcg.OK and oracle.true_relres(A, b, host(x32)) <= 1e-10
+    assert i32["iters"] <= 1.15 * i64["iters"] + 5
+
+
+def test_c4_full_batch():
+    spec = batch_c4(seed=0, count=256)
+    mats = [shifted(poisson2d(side), sh) for side, sh in spec]
+    bs = [rhs_from_solution(A, xstar_uniform(A.n, 1000 + i)) for i, A in enumerate(mats)]
+    solvers = [Solver(A, tol=1e-10, spmv_format="sell") for A in mats]
+    xs, infos = solve_batch(solvers, [dev(b) for b in bs])
+    for A, b, x, info in zip(mats, bs, xs, infos):
+        assert info["status"] == ppcg.OK
+        assert oracle.true_relres(A, b, host(x)) <= 1e-10
+    # iteration counts against the oracle on a sample of systems of every size class
+    order = np.argsort([A.n for A in mats])
+    for k in list(order[:3]) + list(order[len(order) // 2: len(order) // 2 + 2]):
+        ref = oracle.pipecg(mats[k], bs[k], tol=1e-10)
+        assert abs(infos[k]["iters"] - ref.iters) <= 2, (mats[k].n, infos[k]["iters"], ref.iters)
+    for S in solvers:
+        S.close()
+
+
+def test_table2_125pt_side165_full_size():
+    A = poisson125(165)
+    b = rhs_from_solution(A, xstar_paper(A.n))
+    vals, meta = _golden("p125_side165.txt", "x5")
+    assert (meta["n"], meta["nnz"]) == (A.n, A.nnz)
+    S = Solver(A, fixed_iters=5)
+    x, info = S.solve(dev(b))
+    assert info["iters"] == 5
+    _check_sampled(host(x), vals, meta, 5)
+    S.set_options(tol=1e-5, stop="abs", max_iter=10000)
+    x, info = S.solve(dev(b))
+    assert info["status"] == ppcg.OK
+    assert abs(info["iters"] - int(meta["abs1e-5_iters"])) <= 2
+    assert info["precond_norm"] < 1e-5
