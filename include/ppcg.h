@@ -117,6 +117,12 @@ typedef struct {
     ppcg_mem mem;            /* where the three arrays live */
 } ppcg_csr;
 
+/* ppcg_options.flags bits (any other bit is ERR_INVALID_ARG). */
+#define PPCG_FLAG_BORROW_INPUTS 1u /* serving (ppcg_srv_create's options): requests reference the
+                                      caller's A and b arrays instead of copying them; they must
+                                      stay valid and unchanged until ppcg_srv_poll reports the
+                                      request ready.  Ignored elsewhere */
+
 /* Solver options; initialise with ppcg_default_options(). */
 typedef struct {
     size_t struct_size;      /* sizeof(ppcg_options) */
@@ -136,7 +142,7 @@ typedef struct {
     int32_t max_outer;       /* mixed precision: maximum refinement steps / reliable
                                 updates (default 30) */
     ppcg_method method;      /* default PPCG_METHOD_PIPECG */
-    uint32_t flags;          /* reserved, must be 0 */
+    uint32_t flags;          /* PPCG_FLAG_* bits, default 0 */
 } ppcg_options;
 
 /* Per-solve report. */
@@ -374,8 +380,10 @@ typedef struct ppcg_server ppcg_server;
 ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *hip_stream,
                             ppcg_server **out);
 
-/* Queue a request.  A: host CSR (copied before returning); b: host [n] FP64,
- * copied; tol: this request's tolerance; precision: any ppcg_precision,
+/* Queue a request.  A: host CSR; b: host [n] FP64; both copied before
+ * returning, or referenced until the request is polled ready when the server
+ * was created with PPCG_FLAG_BORROW_INPUTS.  tol: this request's tolerance;
+ * precision: any ppcg_precision,
  * PPCG_PRECISION_AUTO included.  *req_id receives the request's id.
  * PPCG_ERR_BUDGET when the request could never fit the budget. */
 ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, double tol,

@@ -328,9 +328,13 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
 {
     constexpr int NV = EXACT ? kReplPartials : kNumPartials;
     __shared__ double lds[kVmaThreads / 64 * NV];
-    const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (pos >= *count)
+    // Graphs bake a grid that may exceed the live table: blocks past it exit,
+    // and the XCD-aware order is taken over the live items only, so that
+    // every XCD gets an equal share of them.
+    const int live = *count;
+    if ((int)blockIdx.x >= live)
         return;
+    const int pos = remap ? xcd_remap(blockIdx.x, live) : (int)blockIdx.x;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
     const SysState *st = d.st;
@@ -642,9 +646,13 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_spmv(const WorkItem *__rest
                                                           const SysDesc *__restrict__ descs, int remap)
 {
     __shared__ double lds[kSpmvThreads / 64 * kReplPartials];
-    const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (pos >= *count)
+    // Graphs bake a grid that may exceed the live table: blocks past it exit,
+    // and the XCD-aware order is taken over the live items only, so that
+    // every XCD gets an equal share of them.
+    const int live = *count;
+    if ((int)blockIdx.x >= live)
         return;
+    const int pos = remap ? xcd_remap(blockIdx.x, live) : (int)blockIdx.x;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
     SysState *st = d.st;

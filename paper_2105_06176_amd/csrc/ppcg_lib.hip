@@ -1428,7 +1428,8 @@ static ppcg_status check_options(const ppcg_options *o)
         (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
          o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
         (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
-        (o->method == PPCG_METHOD_PCG && o->precision == PPCG_MIXED_FP32) || o->flags != 0) {
+        (o->method == PPCG_METHOD_PCG && o->precision == PPCG_MIXED_FP32) ||
+        (o->flags & ~PPCG_FLAG_BORROW_INPUTS) != 0) {
         set_error("invalid option value");
         return PPCG_ERR_INVALID_ARG;
     }

@@ -153,9 +153,13 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__
                                                               const SysDesc *__restrict__ descs, int remap)
 {
     __shared__ double lds[kSpmvThreads / 64];
-    const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (pos >= *count)
+    // Graphs bake a grid that may exceed the live table: blocks past it exit,
+    // and the XCD-aware order is taken over the live items only, so that
+    // every XCD gets an equal share of them.
+    const int live = *count;
+    if ((int)blockIdx.x >= live)
         return;
+    const int pos = remap ? xcd_remap(blockIdx.x, live) : (int)blockIdx.x;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
     const SysState *st = d.st;
@@ -263,9 +267,13 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
                                                          const SysDesc *__restrict__ descs, int remap)
 {
     __shared__ double lds[kVmaThreads / 64 * kNumPartials];
-    const int pos = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (pos >= *count)
+    // Graphs bake a grid that may exceed the live table: blocks past it exit,
+    // and the XCD-aware order is taken over the live items only, so that
+    // every XCD gets an equal share of them.
+    const int live = *count;
+    if ((int)blockIdx.x >= live)
         return;
+    const int pos = remap ? xcd_remap(blockIdx.x, live) : (int)blockIdx.x;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
     const SysState *st = d.st;

@@ -37,8 +37,12 @@ struct Request {
     ppcg_precision precision = PPCG_FP64;
     bool auto_prec = false;  // chosen by the server; FP32 values fall back to FP64
     int32_t n = 0;
+    int64_t nnz = 0;
+    // inputs: owned copies, or the caller's arrays (borrowing server)
     std::vector<int32_t> rp, ci;
     std::vector<double> val, b, x;
+    const int32_t *rp_p = nullptr, *ci_p = nullptr;
+    const double *val_p = nullptr, *b_p = nullptr;
     ppcg_handle *h = nullptr;
     int job = -1;
     ppcg_info info{};
@@ -74,10 +78,10 @@ static ppcg_status admit(ppcg_server *s)
         ppcg_csr A{};
         A.struct_size = sizeof A;
         A.n = r.n;
-        A.nnz = (int64_t)r.ci.size();
-        A.row_ptr = r.rp.data();
-        A.col_idx = r.ci.data();
-        A.values = r.val.data();
+        A.nnz = r.nnz;
+        A.row_ptr = r.rp_p;
+        A.col_idx = r.ci_p;
+        A.values = r.val_p;
         A.mem = PPCG_MEM_HOST;
         ppcg_status rc = ppcg_create(&A, &o, s->stream, &r.h);
         if (rc != PPCG_OK) {
@@ -93,7 +97,7 @@ static ppcg_status admit(ppcg_server *s)
         hipStream_t keep = r.h->stream;
         r.h->stream = s->eng->stream();
         // a rerun (automatic precision fallback) starts from the last iterate
-        rc = stage_inputs(r.h, r.b.data(), r.x.empty() ? nullptr : r.x.data());
+        rc = stage_inputs(r.h, r.b_p, r.x.empty() ? nullptr : r.x.data());
         r.h->stream = keep;
         PPCG_TRY(rc);
         const int mixed = r.precision == PPCG_MIXED_FP32          ? MIX_INNER32
@@ -108,6 +112,8 @@ static ppcg_status admit(ppcg_server *s)
             std::vector<int32_t>().swap(r.rp);
             std::vector<int32_t>().swap(r.ci);
             std::vector<double>().swap(r.val);
+            r.rp_p = r.ci_p = nullptr;
+            r.val_p = nullptr;
         }
     }
     return PPCG_OK;
@@ -141,7 +147,7 @@ static ppcg_status retire_finished(ppcg_server *s)
             // FP32 values did not reach the tolerance: run again in FP64 from
             // the last iterate, ahead of the requests still queued
             r.precision = PPCG_FP64;
-            r.footprint = ppcg_footprint_bytes(r.n, (int64_t)r.ci.size(), PPCG_FP64);
+            r.footprint = ppcg_footprint_bytes(r.n, r.nnz, PPCG_FP64);
             r.state = 0;
             s->queue.push_front(kv.first);
             continue;
@@ -214,10 +220,22 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
     r.precision = precision;
     r.auto_prec = auto_prec;
     r.n = A->n;
-    r.rp.assign(A->row_ptr, A->row_ptr + A->n + 1);
-    r.ci.assign(A->col_idx, A->col_idx + A->nnz);
-    r.val.assign(A->values, A->values + A->nnz);
-    r.b.assign(b, b + A->n);
+    r.nnz = A->nnz;
+    if (s->defaults.flags & PPCG_FLAG_BORROW_INPUTS) {
+        r.rp_p = A->row_ptr;
+        r.ci_p = A->col_idx;
+        r.val_p = A->values;
+        r.b_p = b;
+    } else {
+        r.rp.assign(A->row_ptr, A->row_ptr + A->n + 1);
+        r.ci.assign(A->col_idx, A->col_idx + A->nnz);
+        r.val.assign(A->values, A->values + A->nnz);
+        r.b.assign(b, b + A->n);
+        r.rp_p = r.rp.data();
+        r.ci_p = r.ci.data();
+        r.val_p = r.val.data();
+        r.b_p = r.b.data();
+    }
     *req_id = r.id;
     s->queue.push_back(r.id);
     s->reqs.emplace(r.id, std::move(r));

@@ -22,6 +22,7 @@ STOP_REL_RESID, STOP_PRECOND_ABS = 0, 1
 FP64, MIXED_FP32, MIXED_FP32_VALUES, PRECISION_AUTO = 0, 1, 2, 3
 MEM_DEVICE, MEM_HOST = 0, 1
 METHOD_PIPECG, METHOD_PCG = 0, 1
+FLAG_BORROW_INPUTS = 1
 SPMV_AUTO, SPMV_SELL, SPMV_CSR_VECTOR = 0, 1, 2
 
 _STOP = {"rel": STOP_REL_RESID, "abs": STOP_PRECOND_ABS}
@@ -309,13 +310,18 @@ def footprint_bytes(n: int, nnz: int, precision: str = "fp64") -> float:
 class Server:
     """Continuous-batching solve server (ppcg_srv_*)."""
 
-    def __init__(self, budget_bytes: float = 0.0, stream=None, **options):
+    def __init__(self, budget_bytes: float = 0.0, stream=None, borrow: bool = False, **options):
+        """borrow: requests reference the submitted arrays (kept alive here
+        until polled ready) instead of the server copying them."""
+        if borrow:
+            options["flags"] = options.get("flags", 0) | FLAG_BORROW_INPUTS
         self.opt = make_options(**options)
         s = ctypes.c_void_p()
         _check(lib().ppcg_srv_create(ctypes.byref(self.opt), float(budget_bytes), _stream_ptr(stream),
                                      ctypes.byref(s)), "ppcg_srv_create")
         self.s = s
         self._n = {}
+        self._borrowed = {}
 
     def submit(self, A, b, tol: float, precision: str = "fp64") -> int:
         import numpy as np
@@ -329,6 +335,8 @@ class Server:
         _check(lib().ppcg_srv_submit(self.s, ctypes.byref(c), bb.ctypes.data, float(tol), _PREC[precision],
                                      ctypes.byref(rid)), "ppcg_srv_submit")
         self._n[rid.value] = int(c.n)
+        if self.opt.flags & FLAG_BORROW_INPUTS:
+            self._borrowed[rid.value] = (keep, bb)
         return rid.value
 
     def step(self) -> Tuple[int, int]:
@@ -348,6 +356,7 @@ class Server:
         if not ready.value:
             return None
         del self._n[rid]
+        self._borrowed.pop(rid, None)
         return x, info.as_dict()
 
     def close(self):

@@ -434,6 +434,18 @@ def test_server_refuses_over_budget_and_admits_in_turn():
         assert np.array_equal(x, xs[0])
 
 
+def test_server_borrowing_inputs_gives_the_same_results():
+    """A server created with PPCG_FLAG_BORROW_INPUTS reads the caller's
+    arrays instead of copies: same results, bit for bit."""
+    mats = [poisson3d(16), random_spd(3000, seed=4), poisson2d(45)]
+    reqs = [(f"r{i}", A, problem(A, 30 + i)[0], 1e-10, "fp64") for i, A in enumerate(mats)]
+    copied = _serve_all(Server(), reqs)
+    borrowed = _serve_all(Server(borrow=True), reqs)
+    for key, *_ in reqs:
+        assert np.array_equal(copied[key][0], borrowed[key][0])
+        assert copied[key][1]["iters"] == borrowed[key][1]["iters"]
+
+
 def test_server_automatic_precision():
     """Automatic precision: a large request runs with FP32 values (it makes
     reliable updates), a small one in FP64; both reach the tolerance."""
