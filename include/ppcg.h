@@ -73,7 +73,7 @@ typedef enum {
     PPCG_PRECISION_AUTO = 3 /* serving only (ppcg_srv_submit): the server chooses per request by
                              a byte model of one iteration.  Systems of at least 65536 rows
                              (bandwidth-bound) run PPCG_MIXED_FP32_VALUES when its bytes per
-                             iteration (8 per stored entry + 176 per row) are at least 15% below
+                             iteration (8 per stored entry + 176 per row) are at least 5% below
                              FP64's (12 per entry + 176 per row); others run PPCG_FP64.  A
                              FP32-values request that ends PPCG_STAGNATED or PPCG_BREAKDOWN is
                              run again in PPCG_FP64 from its last iterate */

@@ -217,10 +217,14 @@ class Engine {
     ppcg_status sync_states(Group &g);
     int alloc_slot(Group &g);
     hipStream_t stream_;
-    // Small systems iterate on a stream of their own, so their long
-    // one-workgroup launches overlap the other groups' graphs.
-    hipStream_t small_stream_ = nullptr;
-    hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+    // Each group iterates on a stream of its own (forked from stream_ after
+    // the tables and auxiliary work, joined back before the poll), so the
+    // groups' launches overlap: the one-workgroup small-system kernel and the
+    // graphs of groups holding systems of different precision or method.
+    static constexpr int kGroups = 6;
+    hipStream_t gstream_[kGroups] = {};
+    hipEvent_t ev_fork_ = nullptr;
+    hipEvent_t ev_join_[kGroups] = {};
     Group g64_, g32_, gv_, gs_;  // FP64, FP32 vectors, FP32 values, small FP64 systems
     Group gp_, gpv_;             // classic PCG: FP64, FP32 values
     std::vector<Job> jobs_;

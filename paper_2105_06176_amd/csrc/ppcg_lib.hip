@@ -580,12 +580,14 @@ ppcg_status ensure_f32(ppcg_handle *h)
 // ---------------------------------------------------------------- engine
 Engine::~Engine()
 {
-    if (small_stream_) {
-        (void)hipStreamSynchronize(small_stream_);
-        (void)hipStreamDestroy(small_stream_);
+    for (int k = 0; k < kGroups; ++k) {
+        if (gstream_[k]) {
+            (void)hipStreamSynchronize(gstream_[k]);
+            (void)hipStreamDestroy(gstream_[k]);
+        }
+        if (ev_join_[k]) (void)hipEventDestroy(ev_join_[k]);
     }
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
-    if (ev_join_) (void)hipEventDestroy(ev_join_);
     for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
@@ -626,10 +628,12 @@ ppcg_status Engine::ensure_group(Group &g, int prec, int cap_sys)
 
 ppcg_status Engine::init(int cap_sys)
 {
-    if (!small_stream_) {
-        PPCG_HIP(hipStreamCreateWithFlags(&small_stream_, hipStreamNonBlocking));
+    if (!ev_fork_) {
         PPCG_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
-        PPCG_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+        for (int k = 0; k < kGroups; ++k) {
+            PPCG_HIP(hipStreamCreateWithFlags(&gstream_[k], hipStreamNonBlocking));
+            PPCG_HIP(hipEventCreateWithFlags(&ev_join_[k], hipEventDisableTiming));
+        }
     }
     PPCG_TRY(ensure_group(g64_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(g32_, PREC_F32, cap_sys));
@@ -1209,33 +1213,38 @@ ppcg_status Engine::step(int graph_iters)
             g->table_dirty = true;
         }
     }
-    // 4. One graph chunk per non-empty group; the small group runs its
-    //    chunk as a single launch of the one-workgroup kernel on its own
-    //    stream, concurrently with the other groups' graphs.
-    bool small_forked = false;
-    if (!gs_.table_h.empty()) {
-        PPCG_TRY(ensure_table(gs_));
-        // fork: everything enqueued so far (tables, aux work) precedes the
-        // small-system launch; it is joined back before the poll below
-        PPCG_HIP(hipEventRecord(ev_fork_, stream_));
-        PPCG_HIP(hipStreamWaitEvent(small_stream_, ev_fork_, 0));
-        k_small_iter<<<(int)gs_.table_h.size(), kSmallThreads, 0, small_stream_>>>(
-            gs_.table_d, gs_.count_d, gs_.desc_d, chunk_iters(gs_, kSmallChunkIters));
-        PPCG_HIP(hipGetLastError());
-        PPCG_HIP(hipEventRecord(ev_join_, small_stream_));
-        small_forked = true;
-    }
-    for (Group *g : groups) {
-        if (g == &gs_ || g->table_h.empty())
+    // 4. One graph chunk per non-empty group, each on its own stream; the
+    //    small group runs its chunk as a single launch of the one-workgroup
+    //    kernel.  Tables and graphs are prepared on stream_ first.
+    hipGraphExec_t execs[kGroups] = {};
+    int small_iters = 0;
+    for (int k = 0; k < kGroups; ++k) {
+        Group *g = groups[k];
+        if (g->table_h.empty())
             continue;
         PPCG_TRY(ensure_table(*g));
-        hipGraphExec_t exec = nullptr;
-        PPCG_TRY(ensure_graph(*g, chunk_iters(*g, graph_iters), &exec));
-        PPCG_HIP(hipGraphLaunch(exec, stream_));
+        if (g == &gs_)
+            small_iters = chunk_iters(gs_, kSmallChunkIters);
+        else
+            PPCG_TRY(ensure_graph(*g, chunk_iters(*g, graph_iters), &execs[k]));
+    }
+    PPCG_HIP(hipEventRecord(ev_fork_, stream_));
+    for (int k = 0; k < kGroups; ++k) {
+        Group *g = groups[k];
+        if (g->table_h.empty())
+            continue;
+        PPCG_HIP(hipStreamWaitEvent(gstream_[k], ev_fork_, 0));
+        if (g == &gs_) {
+            k_small_iter<<<(int)gs_.table_h.size(), kSmallThreads, 0, gstream_[k]>>>(gs_.table_d, gs_.count_d,
+                                                                                   gs_.desc_d, small_iters);
+            PPCG_HIP(hipGetLastError());
+        } else {
+            PPCG_HIP(hipGraphLaunch(execs[k], gstream_[k]));
+        }
+        PPCG_HIP(hipEventRecord(ev_join_[k], gstream_[k]));
+        PPCG_HIP(hipStreamWaitEvent(stream_, ev_join_[k], 0));
     }
     // 5. Poll.
-    if (small_forked)
-        PPCG_HIP(hipStreamWaitEvent(stream_, ev_join_, 0));
     for (Group *g : groups)
         PPCG_TRY(sync_states(*g));
     PPCG_HIP(hipStreamSynchronize(stream_));

@@ -201,12 +201,11 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
     const bool auto_prec = precision == PPCG_PRECISION_AUTO;
     if (auto_prec) {
         // bytes of one PIPECG iteration: 12 (FP64) or 8 (FP32 values) per
-        // stored entry, plus the 22 FP64 vector streams of a row.  The FP32
-        // copy, the reliable updates and the extra engine group cost about
-        // a tenth of a solve in a mix, so a smaller saving does not pay.
+        // stored entry, plus the 22 FP64 vector streams of a row; below
+        // 65536 rows launch latency, not bytes, sets the time
         const double b64 = 12.0 * (double)A->nnz + 176.0 * A->n;
         const double b32 = 8.0 * (double)A->nnz + 176.0 * A->n;
-        precision = (A->n >= 65536 && b32 <= 0.85 * b64) ? PPCG_MIXED_FP32_VALUES : PPCG_FP64;
+        precision = (A->n >= 65536 && b32 <= 0.95 * b64) ? PPCG_MIXED_FP32_VALUES : PPCG_FP64;
     }
     const double fp = ppcg_footprint_bytes(A->n, A->nnz, precision);
     if (fp > s->budget) {

@@ -449,7 +449,7 @@ def test_server_borrowing_inputs_gives_the_same_results():
 def test_server_automatic_precision():
     """Automatic precision: a large request runs with FP32 values (it makes
     reliable updates), a small one in FP64; both reach the tolerance."""
-    big, small = poisson3d(48), poisson2d(40)
+    big, small = stencil27_lognormal(41, seed=1), poisson2d(40)
     reqs = [("big", big, problem(big)[0], 1e-10, "auto"), ("small", small, problem(small)[0], 1e-10, "auto")]
     res = _serve_all(Server(), reqs)
     for key, A, b, tol, _ in reqs:
