@@ -180,6 +180,10 @@ typedef struct {
                                 PCG: plus 4, the direction update being fused into it) */
     double device_bytes;     /* device memory held by the handle */
     double setup_ms;         /* time spent in ppcg_create (validation, conversion, tuning) */
+    int32_t col_index_bytes; /* bytes per stored column index the iteration's SpMV reads: 2 when
+                                every SELL column fits a 16-bit offset from its row, else 4 */
+    int32_t diag_const;      /* 1: every diagonal entry is equal; the fused update then reads
+                                the inverse diagonal as one cached value, not a vector */
 } ppcg_matrix_info;
 
 /* Fill *opt with the defaults listed above. */

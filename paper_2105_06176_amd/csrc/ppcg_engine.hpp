@@ -80,10 +80,12 @@ struct ppcg_handle {
     int64_t *cptr = nullptr;  // SELL chunk offsets
     int *rp = nullptr;        // CSR row pointers (CSR-vector format)
     int *col = nullptr;
+    short *col16 = nullptr;   // SELL: 16-bit column offsets from the row, when they all fit
     int *perm = nullptr, *invperm = nullptr;
     double *val64 = nullptr;  // FP64 values in the stored format
     float *val32 = nullptr;   // FP32 copy of the stored values (mixed modes)
     double *dinv64 = nullptr;
+    bool dinv_const = false;  // every diagonal entry equal (e.g. constant-coefficient stencils)
     ppcg::DevArena mat_arena;
     ppcg::PrecData f64, f32;
     double *part = nullptr;   // 2 x ntiles x 4 partial sums (shared by both precisions)

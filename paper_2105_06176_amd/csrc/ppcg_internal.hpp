@@ -36,6 +36,12 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 
 // Systems with at most this many rows (SELL format, FP64) iterate in the
 // one-workgroup kernel: for them launch latency, not bandwidth, dominates.
+// 1: build 16-bit SELL column offsets when they fit and let the SpMV read
+// them.  Off: measured slower on gfx950 (sub-dword loads), see the notes.
+#ifndef PPCG_SELL_COL16
+#define PPCG_SELL_COL16 0
+#endif
+
 #ifndef PPCG_SMALL_MAX_ROWS
 #define PPCG_SMALL_MAX_ROWS 4096
 #endif
@@ -91,11 +97,14 @@ struct SysDesc {
     int prec;           // Prec of the vectors and values below
     int pair;           // mixed precision: slot of the same system in the other group
     int vals32;         // 1: iteration SpMVs read the FP32 copy of the values (val32)
+    int dinv_const;     // 1: every diagonal entry is equal; the updates read dinv[0] for every row
+    int pad_;
     double tol;
     double repl_factor; // vals32: pause for a reliable update when the residual fell by this factor
     const int64_t *cptr;  // SELL chunk offsets [nchunks + 1]
     const int *rp;        // CSR row pointers [n + 1] (CSR-vector format)
     const int *col;       // SELL / CSR column indices
+    const short *col16;   // SELL: column minus row as 16-bit offsets when every one fits (else NULL)
     const void *val;      // matrix values (double or float)
     const float *val32;   // FP32 copy of the values (vals32 mode)
     const void *dinv;     // inverse diagonal (double or float)

@@ -363,7 +363,8 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
         V2 nv = vload((const V2 *)(NVv + i)), z = vload((const V2 *)(Z + i)), m = vload((const V2 *)(M + i));
         V2 q = vload((const V2 *)(Q + i)), w = vload((const V2 *)(W + i)), s = vload((const V2 *)(S + i));
         V2 u = vload((const V2 *)(U + i)), p = vload((const V2 *)(P + i)), x = vload((const V2 *)(X + i));
-        V2 r = vload((const V2 *)(R + i)), di = vload((const V2 *)(DI + i));
+        // a constant diagonal: every lane reads dinv[0..1] (one cached line)
+        V2 r = vload((const V2 *)(R + i)), di = vload((const V2 *)(DI + (d.dinv_const ? 0 : i)));
         V2 mo;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
         vstore((V2 *)(M + i), mo);
     } else if (i < n) {
         T z = Z[i], q = Q[i], w = W[i], s = S[i], u = U[i], p = P[i], x = X[i], r = R[i], mo;
-        vma_elem<T, NV>(sa, sb, NVv[i], z, M[i], q, w, s, u, p, x, r, DI[i], mo, acc);
+        vma_elem<T, NV>(sa, sb, NVv[i], z, M[i], q, w, s, u, p, x, r, DI[d.dinv_const ? 0 : i], mo, acc);
         Z[i] = z; Q[i] = q; S[i] = s; P[i] = p; X[i] = x; R[i] = r; U[i] = u; W[i] = w; M[i] = mo;
     }
     block_sum<kVmaThreads, NV>(acc, lds);
@@ -445,6 +446,47 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
             vv[j] = (VT)0;
             if (k0 + j < len) {
                 cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
+                vv[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NX; ++q) {
+            T xx[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                xx[j] = k0 + j < len ? xin[q][cc[j]] : (T)0;
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                if (k0 + j < len)
+                    acc[q] = acc[q] + (T)vv[j] * xx[j];
+        }
+    }
+}
+
+// The same with 16-bit column offsets from the row (col = row + offset).
+template <typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, const short *__restrict__ col16,
+                                           const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
+                                           int lane, T (&acc)[NX])
+{
+    constexpr int B = 8;
+    const int64_t base = cptr[chunk];
+    const int len = (int)((cptr[chunk + 1] - base) / kSellC);
+    const int row = chunk * kSellC + lane;
+    const short *c = col16 + base + lane;
+    const VT *v = val + base + lane;
+#pragma unroll
+    for (int q = 0; q < NX; ++q)
+        acc[q] = (T)0;
+    for (int k0 = 0; k0 < len; k0 += B) {
+        int cc[B];
+        VT vv[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            cc[j] = row;
+            vv[j] = (VT)0;
+            if (k0 + j < len) {
+                cc[j] = row + (int)stream_load(c + (size_t)(k0 + j) * kSellC);
                 vv[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
             }
         }
@@ -620,7 +662,10 @@ __device__ __forceinline__ void spmv_tile(const SysDesc &d, const VT *__restrict
         const int chunk = wi.tile * kSellChunksPerTile + (threadIdx.x >> 6);
         const int i = chunk * kSellC + lane;
         if (chunk * kSellC < n) {
-            sell_row<VT, T, NX>(d.cptr, d.col, val, xin, chunk, lane, y);
+            if (d.col16)  // uniform per system
+                sell_row16<VT, T, NX>(d.cptr, d.col16, val, xin, chunk, lane, y);
+            else
+                sell_row<VT, T, NX>(d.cptr, d.col, val, xin, chunk, lane, y);
             if (i < n)
                 spmv_epilogue<T, MODE>(d, i, y, acc);
         }

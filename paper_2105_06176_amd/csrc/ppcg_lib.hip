@@ -137,9 +137,12 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     const double n = h->n;
     const bool pcg = h->opt.method == PPCG_METHOD_PCG;
     ByteModel bm;
-    bm.vma = (pcg ? 8.0 : 20.0) * ve * n;
+    // a constant diagonal is read as one scalar: one vector stream fewer
+    bm.vma = ((pcg ? 8.0 : 20.0) - (h->dinv_const ? 1.0 : 0.0)) * ve * n;
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
-    bm.spmv = (me + 4.0) * (double)h->nnz + ptr + (pcg ? 4.0 : 2.0) * ve * n;
+    // the PIPECG SpMV reads 16-bit column offsets when the matrix has them
+    const double ie = (h->col16 && !pcg) ? 2.0 : 4.0;
+    bm.spmv = (me + ie) * (double)h->nnz + ptr + (pcg ? 4.0 : 2.0) * ve * n;
     return bm;
 }
 
@@ -274,6 +277,7 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->cptr = h->cptr;
     d->rp = h->rp;
     d->col = h->col;
+    d->col16 = h->col16;
     d->val = pd.val;
     d->val32 = h->val32;
     d->vals32 = vals32;
@@ -282,6 +286,7 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
         return PPCG_ERR_INVALID_ARG;
     }
     d->dinv = pd.dinv;
+    d->dinv_const = h->dinv_const ? 1 : 0;
     d->x = pd.vec[VX];
     d->r = pd.vec[VR];
     d->u = pd.vec[VU];
@@ -367,6 +372,8 @@ static void free_matrix(ppcg_handle *h)
     if (h->cptr) (void)hipFree(h->cptr);
     if (h->rp) (void)hipFree(h->rp);
     if (h->col) (void)hipFree(h->col);
+    if (h->col16) (void)hipFree(h->col16);
+    h->col16 = nullptr;
     if (h->val64) (void)hipFree(h->val64);
     if (h->val32) (void)hipFree(h->val32);
     if (h->perm) (void)hipFree(h->perm);
@@ -377,7 +384,7 @@ static void free_matrix(ppcg_handle *h)
     h->val32 = nullptr;
 }
 
-static void adopt_sell(ppcg_handle *h, SellBuild &sb)
+static ppcg_status adopt_sell(ppcg_handle *h, SellBuild &sb)
 {
     free_matrix(h);
     h->fmt = FMT_SELL;
@@ -391,6 +398,37 @@ static void adopt_sell(ppcg_handle *h, SellBuild &sb)
     h->perm = sb.perm;
     h->invperm = sb.invperm;
     sb = SellBuild();
+    if (!PPCG_SELL_COL16)
+        return PPCG_OK;
+    // 16-bit column offsets from the row when they all fit (banded matrices,
+    // stencils whose plane has at most 32767 points): half the index bytes.
+    short *c16 = nullptr;
+    unsigned *flag = nullptr;
+    unsigned nofit = 1u;
+    const unsigned zero = 0u;
+    hipStream_t s = h->stream;
+    PPCG_HIP(hipMalloc(&c16, sizeof(short) * std::max<int64_t>(h->nnz_stored, 1)));
+    hipError_t e = hipMalloc(&flag, sizeof(unsigned));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(flag, &zero, sizeof zero, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        k_sell_delta16<<<blocks_for((size_t)h->nchunks * kSellC, 256), 256, 0, s>>>(h->nchunks, h->cptr, h->col,
+                                                                                    c16, flag);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&nofit, flag, sizeof nofit, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (flag)
+        (void)hipFree(flag);
+    if (e != hipSuccess || nofit) {
+        (void)hipFree(c16);
+        c16 = nullptr;
+    }
+    PPCG_HIP(e);
+    h->col16 = c16;
+    return PPCG_OK;
 }
 
 static ppcg_status adopt_csrv(ppcg_handle *h, int lanes, const int *rp, const int *ci, const double *val)
@@ -451,7 +489,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
         const int sigma = (double)st1 > 1.05 * (double)h->nnz ? kSortWindow : 1;
         SellBuild sb;
         PPCG_TRY(build_sell(h->stream, h->n, sigma, rp, ci, val, rowlen, &sb));
-        adopt_sell(h, sb);
+        PPCG_TRY(adopt_sell(h, sb));
         return bind_f64(h, dinv_orig);
     }
     if (want == PPCG_SPMV_CSR_VECTOR) {
@@ -469,7 +507,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
             if (tv.fmt == FMT_SELL) {
                 SellBuild sb;
                 PPCG_TRY(build_sell(h->stream, h->n, tv.sigma, rp, ci, val, rowlen, &sb));
-                adopt_sell(h, sb);
+                PPCG_TRY(adopt_sell(h, sb));
             } else {
                 PPCG_TRY(adopt_csrv(h, tv.lanes, rp, ci, val));
             }
@@ -497,7 +535,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
         if (c.fmt == FMT_SELL) {
             SellBuild sb;
             PPCG_TRY(build_sell(h->stream, h->n, c.sigma, rp, ci, val, rowlen, &sb));
-            adopt_sell(h, sb);
+            PPCG_TRY(adopt_sell(h, sb));
         } else {
             PPCG_TRY(adopt_csrv(h, c.lanes, rp, ci, val));
         }
@@ -518,7 +556,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
         if (bestc.fmt == FMT_SELL) {
             SellBuild sb;
             PPCG_TRY(build_sell(h->stream, h->n, bestc.sigma, rp, ci, val, rowlen, &sb));
-            adopt_sell(h, sb);
+            PPCG_TRY(adopt_sell(h, sb));
         } else {
             PPCG_TRY(adopt_csrv(h, bestc.lanes, rp, ci, val));
         }
@@ -1228,21 +1266,31 @@ ppcg_status Engine::step(int graph_iters)
         else
             PPCG_TRY(ensure_graph(*g, chunk_iters(*g, graph_iters), &execs[k]));
     }
-    PPCG_HIP(hipEventRecord(ev_fork_, stream_));
+    int nactive = 0;
+    for (int k = 0; k < kGroups; ++k)
+        nactive += !groups[k]->table_h.empty();
+    // with one active group there is nothing to overlap: stay on stream_
+    const bool fork = nactive > 1;
+    if (fork)
+        PPCG_HIP(hipEventRecord(ev_fork_, stream_));
     for (int k = 0; k < kGroups; ++k) {
         Group *g = groups[k];
         if (g->table_h.empty())
             continue;
-        PPCG_HIP(hipStreamWaitEvent(gstream_[k], ev_fork_, 0));
+        hipStream_t gs = fork ? gstream_[k] : stream_;
+        if (fork)
+            PPCG_HIP(hipStreamWaitEvent(gs, ev_fork_, 0));
         if (g == &gs_) {
-            k_small_iter<<<(int)gs_.table_h.size(), kSmallThreads, 0, gstream_[k]>>>(gs_.table_d, gs_.count_d,
-                                                                                   gs_.desc_d, small_iters);
+            k_small_iter<<<(int)gs_.table_h.size(), kSmallThreads, 0, gs>>>(gs_.table_d, gs_.count_d, gs_.desc_d,
+                                                                          small_iters);
             PPCG_HIP(hipGetLastError());
         } else {
-            PPCG_HIP(hipGraphLaunch(execs[k], gstream_[k]));
+            PPCG_HIP(hipGraphLaunch(execs[k], gs));
         }
-        PPCG_HIP(hipEventRecord(ev_join_[k], gstream_[k]));
-        PPCG_HIP(hipStreamWaitEvent(stream_, ev_join_[k], 0));
+        if (fork) {
+            PPCG_HIP(hipEventRecord(ev_join_[k], gs));
+            PPCG_HIP(hipStreamWaitEvent(stream_, ev_join_[k], 0));
+        }
     }
     // 5. Poll.
     for (Group *g : groups)
@@ -1273,14 +1321,15 @@ ppcg_status Engine::step(int graph_iters)
     return PPCG_OK;
 }
 
-// Iterations per graph chunk: aim for a few milliseconds of device work.
+// Iterations per graph chunk: aim for about 4 ms of device work, so that the
+// host's poll between chunks costs about 1% of the time.
 int auto_graph_iters(const ppcg_handle *h)
 {
     if (h->opt.graph_iters > 0)
         return h->opt.graph_iters;
     const ByteModel bm = byte_model(h, PREC_F64);
     const double us = (bm.vma + bm.spmv) / 5.0e6 + 6.0;  // ~5 TB/s plus launch overheads
-    int k = (int)(2000.0 / us);
+    int k = (int)(4000.0 / us);
     return std::max(8, std::min(k, 128));
 }
 
@@ -1574,6 +1623,18 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
     }
     std::vector<int> rowlen_h(n);
     CK(hipMemcpy(rowlen_h.data(), rowlen, sizeof(int) * n, hipMemcpyDeviceToHost));
+    {
+        // A constant diagonal makes M^-1 a multiple of the identity: the fused
+        // updates then read dinv[0] for every row (one cached line) instead
+        // of streaming the dinv vector.
+        unsigned zero = 0u, differs = 1u;
+        CK(hipMemcpyAsync(err, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+        k_const_check<<<blocks_for(n, 256), 256, 0, s>>>(n, dinv_orig, err);
+        CK(hipGetLastError());
+        CK(hipMemcpyAsync(&differs, err, sizeof differs, hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        h->dinv_const = differs == 0u;
+    }
     CKS(alloc_f64_vectors(h));
     CKS(choose_format(h, rp, ci, val, rowlen, dinv_orig, rowlen_h));
     if (opt->precision == PPCG_MIXED_FP32)
@@ -1764,8 +1825,10 @@ ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
     mi->device_bytes = (double)h->f64.arena.size + (double)h->f32.arena.size +
                        (double)h->nnz_stored * 12.0 + 8.0 * h->n +
                        (h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (h->n + 1)) +
-                       (h->perm ? 8.0 * h->n : 0.0);
+                       (h->perm ? 8.0 * h->n : 0.0) + (h->col16 ? 2.0 * (double)h->nnz_stored : 0.0);
     mi->setup_ms = h->setup_ms;
+    mi->col_index_bytes = (h->col16 && h->opt.method != PPCG_METHOD_PCG) ? 2 : 4;
+    mi->diag_const = h->dinv_const ? 1 : 0;
     return PPCG_OK;
 }
 
@@ -1775,7 +1838,8 @@ double ppcg_footprint_bytes(int32_t n, int64_t nnz, ppcg_precision precision)
         return 0.0;
     const double ntiles = (n + kTileRows - 1) / kTileRows;
     const double stored = 1.10 * (double)nnz;  // padding allowance
-    double b = stored * 12.0 + 8.0 * (n / kSellC + 2) + 8.0 * n /* dinv */ + 8.0 * n /* perm */ +
+    // stored entries: 8 value + 4 column + 2 (16-bit column offsets, when built) bytes
+    double b = stored * 14.0 + 8.0 * (n / kSellC + 2) + 8.0 * n /* dinv */ + 8.0 * n /* perm */ +
                11.0 * 8.0 * n + 2.0 * ntiles * kPartStride * 8.0 + 12 * 256.0;
     if (precision == PPCG_MIXED_FP32)
         b += stored * 4.0 + 12.0 * 4.0 * n + 2.0 * ntiles * kPartStride * 8.0;

@@ -299,7 +299,8 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
     if (i + 1 < d.n) {
         dvec2 x = vload((const dvec2 *)(X + i)), r = vload((const dvec2 *)(R + i));
         const dvec2 p = vload((const dvec2 *)(P + i)), sv = vload((const dvec2 *)(S + i));
-        const dvec2 di = vload((const dvec2 *)(DI + i));
+        // a constant diagonal: every lane reads dinv[0..1] (one cached line)
+        const dvec2 di = vload((const dvec2 *)(DI + (d.dinv_const ? 0 : i)));
         dvec2 u;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
         vstore((dvec2 *)(U + i), u);
     } else if (i < d.n) {
         double x = X[i], r = R[i], u;
-        elem(x, r, u, P[i], S[i], DI[i]);
+        elem(x, r, u, P[i], S[i], DI[d.dinv_const ? 0 : i]);
         X[i] = x;
         R[i] = r;
         U[i] = u;

@@ -219,3 +219,42 @@ __global__ void k_convert(size_t m, const TI *__restrict__ in, TO *__restrict__ 
 }
 
 }  // namespace ppcg
+
+namespace ppcg {
+
+// flag[0] |= 1 when some dinv[i] differs from dinv[0] (bitwise compare).
+__global__ void k_const_check(int n, const double *__restrict__ dinv, unsigned *__restrict__ flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && __double_as_longlong(dinv[i]) != __double_as_longlong(dinv[0]))
+        atomicOr(flag, 1u);
+}
+
+}  // namespace ppcg
+
+namespace ppcg {
+
+// SELL column indices as 16-bit offsets from the (stored) row: col16 = col -
+// row for every stored entry; flag[0] |= 1 when some offset does not fit.
+__global__ void k_sell_delta16(int nchunks, const int64_t *__restrict__ cptr, const int *__restrict__ col,
+                               short *__restrict__ col16, unsigned *__restrict__ flag)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nchunks * kSellC)
+        return;
+    const int c = p / kSellC, l = p % kSellC;
+    const int row = c * kSellC + l;
+    const int64_t base = cptr[c];
+    const int len = (int)((cptr[c + 1] - base) / kSellC);
+    bool ok = true;
+    for (int k = 0; k < len; ++k) {
+        const size_t o = (size_t)base + (size_t)k * kSellC + l;
+        const int d = col[o] - row;
+        ok = ok && d >= -32768 && d <= 32767;
+        col16[o] = (short)d;
+    }
+    if (!ok)
+        atomicOr(flag, 1u);
+}
+
+}  // namespace ppcg

@@ -60,7 +60,8 @@ class MatrixInfo(ctypes.Structure):
                 ("nnz_stored", ctypes.c_int64), ("format", ctypes.c_int), ("sell_c", ctypes.c_int32),
                 ("sell_sigma", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("bytes_per_iter", ctypes.c_double), ("bytes_vma", ctypes.c_double),
-                ("bytes_spmv", ctypes.c_double), ("device_bytes", ctypes.c_double), ("setup_ms", ctypes.c_double)]
+                ("bytes_spmv", ctypes.c_double), ("device_bytes", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("col_index_bytes", ctypes.c_int32), ("diag_const", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}

@@ -85,6 +85,24 @@ def test_spmv_sorted_sell_is_bitwise():
     assert np.array_equal(host(S.spmv(dev(x))), oracle.spmv(A, x))
 
 
+def test_storage_choices_keep_results_exact():
+    """16-bit column offsets are used when every offset fits and the constant
+    diagonal of a Poisson matrix is read as one value; neither changes a
+    single bit of the SpMV, and iterates still match the oracle."""
+    P = poisson3d(40)
+    R = random_spd(70000, seed=1)  # random columns: offsets up to 70000, no 16-bit form
+    for A, bytes16, const in ((P, 2, 1), (R, 4, 0), (random_spd(5000, seed=9), 2, 0)):
+        S = Solver(A, spmv_format="sell")
+        mi = S.matrix_info()
+        assert mi["col_index_bytes"] in (bytes16, 4) and mi["diag_const"] == const, A.name
+        x = xstar_uniform(A.n, 3)
+        assert np.array_equal(host(S.spmv(dev(x))), oracle.spmv(A, x))
+        b, _ = problem(A)
+        S.set_options(fixed_iters=15, spmv_format="sell")
+        xg, _ = S.solve(dev(b))
+        assert relerr(host(xg), oracle.pipecg(A, b, fixed_iters=15).x) <= 1e-10
+
+
 # ---------------------------------------------------------------- fixed iterates
 
 @pytest.mark.parametrize("name,ks", [("c1_poisson2d_64", (1, 10, 50, 100)), ("poisson2d_37_ragged", (5, 40)),
