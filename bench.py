@@ -176,7 +176,8 @@ def leg_c3(torch, ppcg, wl):
     out = {"workload": "3D 27-point lognormal 160^3 (N=4096000), shift 1e-3, tol 1e-10", "nnz": A.nnz}
     xs = {}
     variants = [("fp64", {}), ("mixed", {"precision": "mixed"}), ("mixed_values", {"precision": "mixed_values"}),
-                ("pcg_fp64", {"method": "pcg"}), ("pcg_mixed_values", {"method": "pcg", "precision": "mixed_values"})]
+                ("pcg_fp64", {"method": "pcg"}), ("pcg_mixed_values", {"method": "pcg", "precision": "mixed_values"}),
+                ("pcg_mixed", {"method": "pcg", "precision": "mixed"})]
     for label, kw in variants:
         S = ppcg.Solver(A, tol=1e-10, max_iter=20000, spmv_format="sell", **kw)
         S.solve(bd)  # warm-up (graph capture, FP32 copy)

@@ -61,9 +61,14 @@ typedef enum {
 
 typedef enum {
     PPCG_FP64 = 0,        /* every vector, matrix value and scalar in FP64 */
-    PPCG_MIXED_FP32 = 1,  /* inner PIPECG with FP32 matrix values and vectors, FP64 dot
-                             products and scalars, restarted inside an FP64
-                             iterative-refinement loop on the FP64 operator */
+    PPCG_MIXED_FP32 = 1,  /* FP32 matrix values and vectors, FP64 dot products and
+                             scalars, on the system scaled by the FP64 residual.
+                             PIPECG: inner solves restarted inside an FP64
+                             iterative-refinement loop on the FP64 operator.
+                             PPCG_METHOD_PCG: one Algorithm 1 sequence with FP64
+                             reliable updates (x64 += correction, r64 = b - A64 x64,
+                             rescaled, direction kept) whenever its residual fell by
+                             inner_tol (default 1e-2) */
     PPCG_MIXED_FP32_VALUES = 2, /* one PIPECG sequence whose SpMVs read FP32 matrix values
                              (FP64 vectors, FP64 accumulation, FP64 dots and scalars),
                              with reliable updates: whenever the residual has dropped by
@@ -86,9 +91,10 @@ typedef enum {
                                (default) */
     PPCG_METHOD_PCG = 1     /* Algorithm 1 (Section III-A): classic PCG; two launches per
                                iteration, each ending in a reduction the next launch waits
-                               for.  With PPCG_FP64 or PPCG_MIXED_FP32_VALUES (FP32 values,
-                               reliable updates r = b - A x keeping the direction); not with
-                               PPCG_MIXED_FP32 (ERR_INVALID_ARG) */
+                               for.  With PPCG_FP64, PPCG_MIXED_FP32_VALUES (FP32 values,
+                               reliable updates r = b - A x keeping the direction) or
+                               PPCG_MIXED_FP32 (FP32 vectors and values, FP64 reliable
+                               updates) */
 } ppcg_method;
 
 typedef enum { PPCG_MEM_DEVICE = 0, PPCG_MEM_HOST = 1 } ppcg_mem;
@@ -137,8 +143,9 @@ typedef struct {
     ppcg_spmv_format spmv_format; /* default PPCG_SPMV_AUTO */
     int32_t graph_iters;     /* iterations per captured HIP graph; 0 = automatic */
     double inner_tol;        /* PPCG_MIXED_FP32: relative reduction asked of each inner
-                                solve; PPCG_MIXED_FP32_VALUES: residual reduction between
-                                reliable updates (0 = automatic) */
+                                solve (PIPECG, 0 = 1e-3) or between reliable updates
+                                (classic PCG, 0 = 1e-2); PPCG_MIXED_FP32_VALUES:
+                                residual reduction between reliable updates (0 = 1e-3) */
     int32_t max_outer;       /* mixed precision: maximum refinement steps / reliable
                                 updates (default 30) */
     ppcg_method method;      /* default PPCG_METHOD_PIPECG */

@@ -203,7 +203,8 @@ class Engine {
   private:
     ppcg_status ensure_group(Group &g, int prec, int cap_sys);
     ppcg_status upload_desc(Group &g, int slot);
-    ppcg_status aux_launch(Group &g, const std::vector<int> &slots, int what);
+    // `inner`: the group of the FP32 inner solves (AUX_MIX_START, AUX_MIX_CORRECT)
+    ppcg_status aux_launch(Group &g, const std::vector<int> &slots, int what, const Group *inner = nullptr);
     ppcg_status ensure_table(Group &g);
     ppcg_status ensure_graph(Group &g, int iters, hipGraphExec_t *exec);
     void drop_graphs(Group &g);
@@ -211,10 +212,14 @@ class Engine {
     // group and slot where a job iterates
     Group &pgroup(const Job &j)
     {
+        if (j.mixed == MIX_INNER32)
+            return inner32(j);
         if (j.pcg)
             return j.mixed == MIX_VALUES32 ? gpv_ : gp_;
-        return j.mixed == MIX_INNER32 ? g32_ : j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
+        return j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
     }
+    // group of a mixed-precision job's FP32 inner solves
+    Group &inner32(const Job &j) { return j.pcg ? gp32_ : g32_; }
     int pslot(const Job &j) const { return j.mixed == MIX_INNER32 ? j.slot32 : j.mixed == MIX_VALUES32 ? j.slotv : j.slot64; }
     ppcg_status sync_states(Group &g);
     int alloc_slot(Group &g);
@@ -223,12 +228,12 @@ class Engine {
     // the tables and auxiliary work, joined back before the poll), so the
     // groups' launches overlap: the one-workgroup small-system kernel and the
     // graphs of groups holding systems of different precision or method.
-    static constexpr int kGroups = 6;
+    static constexpr int kGroups = 7;
     hipStream_t gstream_[kGroups] = {};
     hipEvent_t ev_fork_ = nullptr;
     hipEvent_t ev_join_[kGroups] = {};
     Group g64_, g32_, gv_, gs_;  // FP64, FP32 vectors, FP32 values, small FP64 systems
-    Group gp_, gpv_;             // classic PCG: FP64, FP32 values
+    Group gp_, gpv_, gp32_;      // classic PCG: FP64, FP32 values, FP32 vectors (inner solves)
     std::vector<Job> jobs_;
 };
 

@@ -626,7 +626,7 @@ Engine::~Engine()
         if (ev_join_[k]) (void)hipEventDestroy(ev_join_[k]);
     }
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_}) {
+    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_, &gp32_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
         if (g->st_d) (void)hipFree(g->st_d);
@@ -679,7 +679,8 @@ ppcg_status Engine::init(int cap_sys)
     PPCG_TRY(ensure_group(gs_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(gp_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(gpv_, PREC_V32, cap_sys));
-    gp_.pcg = gpv_.pcg = true;
+    PPCG_TRY(ensure_group(gp32_, PREC_F32, cap_sys));
+    gp_.pcg = gpv_.pcg = gp32_.pcg = true;
     return PPCG_OK;
 }
 
@@ -745,9 +746,15 @@ static void launch_iter_pair(hipStream_t s, const Group &g, int grid, int remap)
     if (g.pcg) {
         // Algorithm 1: SpMV, alpha, vector updates, stopping test and beta.
         const int sg = std::max(g.g_sys_grid, 1);
-        k_pcg_spmv<<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        if (g.prec == PREC_F32)
+            k_pcg_spmv<float><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        else
+            k_pcg_spmv<double><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
         k_pcg_alpha<<<sg, kPcgRedThreads, 0, s>>>(g.sys_d, g.sys_count_d, g.desc_d);
-        k_pcg_vma<<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+        if (g.prec == PREC_F32)
+            k_pcg_vma<float><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
+        else
+            k_pcg_vma<double><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
         k_pcg_update<PCG_ITER><<<sg, kPcgRedThreads, 0, s>>>(g.sys_d, g.sys_count_d, g.desc_d);
     } else if (g.prec == PREC_F32) {
         k_vma<float><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
@@ -855,7 +862,11 @@ int Engine::chunk_iters(const Group &g, int max_iters)
             rem = d.fixed - (j.last_norm < 0 ? 0 : st.iter);
         } else if (j.last_norm > 0 && st.iter > j.last_iter) {
             const double cur = d.stop == STOP_ABS ? std::sqrt(st.uu) : std::sqrt(st.rr);
-            const double target = d.stop == STOP_ABS ? d.tol : d.tol * std::sqrt(st.bnorm2);
+            double target = d.stop == STOP_ABS ? d.tol : d.tol * std::sqrt(st.bnorm2);
+            // a classic-PCG sequence that pauses for reliable updates stops at
+            // the pause if that comes first
+            if (g.pcg && d.repl_factor > 0.0 && d.stop == STOP_REL)
+                target = std::max(target, d.repl_factor * st.repl_ref);
             const double rate = std::pow(cur / j.last_norm, 1.0 / (st.iter - j.last_iter));
             if (rate > 0.0 && rate < 0.9999 && cur > target && target > 0.0)
                 rem = (int)std::ceil(1.1 * std::log(target / cur) / std::log(rate)) + 1;
@@ -875,7 +886,7 @@ ppcg_status Engine::sync_states(Group &g)
 }
 
 // Run an auxiliary operation over all tiles of the given slots of group g.
-ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what)
+ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what, const Group *inner)
 {
     if (slots.empty())
         return PPCG_OK;
@@ -896,13 +907,25 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     const int rs = PPCG_XCD_REMAP_SPMV;
     const bool f32 = g.prec == PREC_F32;
     if (what == AUX_INIT && g.pcg) {
-        k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        k_pcg_dots<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        if (f32) {
+            k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            k_pcg_dots<float><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        } else {
+            k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            k_pcg_dots<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        }
         k_pcg_update<PCG_START><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_REPL && g.pcg) {
-        // Reliable update of classic PCG: r = b - A64 x, u = M^-1 r; p is kept.
-        k_spmv<double, MODE_REPL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        k_pcg_dots<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        // Reliable update of classic PCG: r = b - A x, u = M^-1 r; p is kept.
+        // FP64 vectors use the FP64 values; the FP32 mixed-precision slots
+        // recompute their FP32 residual of the rescaled system (x32 = 0).
+        if (f32) {
+            k_spmv<float, MODE_REPL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            k_pcg_dots<float><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        } else {
+            k_spmv<double, MODE_REPL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            k_pcg_dots<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        }
         k_pcg_update<PCG_REPL><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_INIT) {
         if (f32) {
@@ -927,9 +950,15 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
         k_spmv<double, MODE_DUAL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
         k_spmv<double, MODE_DUAL2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
     } else if (what == AUX_MIX_START) {
-        k_mix_start<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, g32_.desc_d);
+        if (inner->pcg)
+            k_pcg_mix_start<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
+        else
+            k_mix_start<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
     } else if (what == AUX_MIX_CORRECT) {
-        k_mix_correct<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, g32_.desc_d);
+        if (inner->pcg)
+            k_pcg_mix_correct<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
+        else
+            k_mix_correct<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
     }
     PPCG_HIP(hipGetLastError());
     return PPCG_OK;
@@ -946,19 +975,16 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
     const int stop = o.stop == PPCG_STOP_PRECOND_ABS ? STOP_ABS : STOP_REL;
     auto release = [&]() {
         if (j.slot64 >= 0) g64_.slot_used[j.slot64] = 0;
-        if (j.slot32 >= 0) g32_.slot_used[j.slot32] = 0;
+        if (j.slot32 >= 0) inner32(j).slot_used[j.slot32] = 0;
         if (j.slotv >= 0) gv_.slot_used[j.slotv] = 0;
     };
     auto fail = [&](ppcg_status s) {
         release();
         return s;
     };
-    if (o.method == PPCG_METHOD_PCG) {
-        if (mixed == MIX_INNER32) {
-            set_error("classic PCG runs in FP64 or with FP32 matrix values only");
-            return PPCG_ERR_INVALID_ARG;
-        }
+    if (o.method == PPCG_METHOD_PCG)
         j.pcg = true;
+    if (j.pcg && mixed != MIX_INNER32) {
         const bool v32 = mixed == MIX_VALUES32;
         Group &g = v32 ? gpv_ : gp_;
         int &slot = v32 ? j.slotv : j.slot64;
@@ -1026,20 +1052,28 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
             rc = ensure_f32(h);
             if (rc != PPCG_OK)
                 return fail(rc);
-            j.slot32 = alloc_slot(g32_);
+            // inner solves: Algorithm 2 (or Algorithm 1 when classic PCG
+            // is selected) in FP32
+            Group &gi = inner32(j);
+            j.slot32 = alloc_slot(gi);
             if (j.slot32 < 0) {
                 set_error("engine has no free slot");
                 return fail(PPCG_ERR_INVALID_ARG);
             }
             const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
-            rc = fill_desc(h, PREC_F32, g32_.st_d + j.slot32, &g32_.desc_h[j.slot32], itol, 0, o.max_iter,
-                           STOP_REL);
+            rc = fill_desc(h, PREC_F32, gi.st_d + j.slot32, &gi.desc_h[j.slot32], itol, 0, o.max_iter, STOP_REL);
             if (rc != PPCG_OK)
                 return fail(rc);
-            g32_.desc_h[j.slot32].pair = j.slot64;
+            if (j.pcg) {
+                // one FP32 sequence, paused for a reliable update whenever the
+                // residual fell by inner_tol; its own stop (the FP64 target in
+                // the units of the current scaling) is set at every start
+                gi.desc_h[j.slot32].repl_factor = o.inner_tol > 0 ? o.inner_tol : kPcgMixReplFactor;
+            }
+            gi.desc_h[j.slot32].pair = j.slot64;
             g64_.desc_h[j.slot64].pair = j.slot32;
-            PPCG_TRY(upload_desc(g32_, j.slot32));
-            PPCG_HIP(hipMemsetAsync(g32_.st_d + j.slot32, 0, sizeof(SysState), stream_));
+            PPCG_TRY(upload_desc(gi, j.slot32));
+            PPCG_HIP(hipMemsetAsync(gi.st_d + j.slot32, 0, sizeof(SysState), stream_));
             j.stage = JS_OUTER;
         } else {
             j.stage = JS_NEED_INIT;
@@ -1081,9 +1115,9 @@ void Engine::retire(int id)
 {
     Job &j = jobs_[id];
     if (j.slot64 >= 0)
-        (j.pcg ? gp_ : j.small ? gs_ : g64_).slot_used[j.slot64] = 0;
+        (j.pcg && j.mixed != MIX_INNER32 ? gp_ : j.small ? gs_ : g64_).slot_used[j.slot64] = 0;
     if (j.slot32 >= 0)
-        g32_.slot_used[j.slot32] = 0;
+        inner32(j).slot_used[j.slot32] = 0;
     if (j.slotv >= 0)
         (j.pcg ? gpv_ : gv_).slot_used[j.slotv] = 0;
     j.slot64 = j.slot32 = j.slotv = -1;
@@ -1112,9 +1146,9 @@ ppcg_status Engine::step(int graph_iters)
 {
     // 1. Jobs that need a true residual: stopped FP64 / FP32-values jobs, and
     //    FP32-vector jobs between inner solves (after adding the correction).
-    Group *const groups[] = {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_};
+    Group *const groups[] = {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_, &gp32_};
     std::map<Group *, std::vector<int>> resid;  // slots per group
-    std::vector<int> correct64;
+    std::map<Group *, std::vector<int>> correct64;  // FP64 slots per inner group
     for (Job &j : jobs_) {
         if (j.finished)
             continue;
@@ -1122,19 +1156,22 @@ ppcg_status Engine::step(int graph_iters)
             resid[&pgroup(j)].push_back(pslot(j));
         else if (j.stage == JS_OUTER) {
             if (j.outer > 0)
-                correct64.push_back(j.slot64);
+                correct64[&inner32(j)].push_back(j.slot64);
             resid[&g64_].push_back(j.slot64);
         }
     }
     if (!resid.empty()) {
-        PPCG_TRY(aux_launch(g64_, correct64, AUX_MIX_CORRECT));
+        for (auto &kv : correct64)
+            PPCG_TRY(aux_launch(g64_, kv.second, AUX_MIX_CORRECT, kv.first));
         for (Group *g : groups)
             if (resid.count(g)) {
                 PPCG_TRY(aux_launch(*g, resid[g], AUX_RESID));
                 PPCG_TRY(sync_states(*g));
             }
         PPCG_HIP(hipStreamSynchronize(stream_));
-        std::vector<int> start_mix;
+        // FP64 slots per inner group: fresh inner starts, and reliable
+        // updates of continuing classic-PCG FP32 sequences
+        std::map<Group *, std::vector<int>> start_mix, repl_mix;
         for (Job &j : jobs_) {
             if (j.finished || (j.stage != JS_NEED_FINAL && j.stage != JS_OUTER))
                 continue;
@@ -1185,24 +1222,45 @@ ppcg_status Engine::step(int graph_iters)
                     j.iters = j.inner_iters;
                     j.rel_recur = rel;
                 } else {
-                    SysDesc &d32 = g32_.desc_h[j.slot32];
-                    d32.maxit = o.max_iter - j.inner_iters;  // inner budget: what is left
-                    PPCG_TRY(upload_desc(g32_, j.slot32));
-                    start_mix.push_back(j.slot64);
+                    Group &gi = inner32(j);
+                    SysDesc &di = gi.desc_h[j.slot32];
+                    if (j.pcg) {
+                        // the sequence continues (its counter runs on); it stops
+                        // by itself where the FP64 residual would reach tol:
+                        // ||r32|| <= tol ||b|| / ||r64|| on b32 = r64 / ||r64||
+                        di.tol = j.tol * bn / std::sqrt(st.tnorm2);
+                        if (j.outer > 0)
+                            repl_mix[&gi].push_back(j.slot64);
+                        else
+                            start_mix[&gi].push_back(j.slot64);
+                    } else {
+                        di.maxit = o.max_iter - j.inner_iters;  // inner budget: what is left
+                        start_mix[&gi].push_back(j.slot64);
+                    }
+                    PPCG_TRY(upload_desc(gi, j.slot32));
                     j.stage = JS_ITER;
                     ++j.outer;
                 }
             }
         }
-        if (!start_mix.empty()) {
-            PPCG_TRY(aux_launch(g64_, start_mix, AUX_MIX_START));
+        for (auto &kv : start_mix) {
+            Group &gi = *kv.first;
+            PPCG_TRY(aux_launch(g64_, kv.second, AUX_MIX_START, &gi));
             std::vector<int> s32;
-            for (int sl : start_mix) {
+            for (int sl : kv.second) {
                 s32.push_back(g64_.desc_h[sl].pair);
                 // every inner solve counts its iterations from zero
-                PPCG_HIP(hipMemsetAsync(g32_.st_d + s32.back(), 0, sizeof(SysState), stream_));
+                PPCG_HIP(hipMemsetAsync(gi.st_d + s32.back(), 0, sizeof(SysState), stream_));
             }
-            PPCG_TRY(aux_launch(g32_, s32, AUX_INIT));
+            PPCG_TRY(aux_launch(gi, s32, AUX_INIT));
+        }
+        for (auto &kv : repl_mix) {
+            Group &gi = *kv.first;
+            PPCG_TRY(aux_launch(g64_, kv.second, AUX_MIX_START, &gi));
+            std::vector<int> s32;
+            for (int sl : kv.second)
+                s32.push_back(g64_.desc_h[sl].pair);
+            PPCG_TRY(aux_launch(gi, s32, AUX_REPL));
         }
     }
     // 2. Initialisations and reliable updates.
@@ -1305,7 +1363,8 @@ ppcg_status Engine::step(int graph_iters)
         if (st.done) {
             j.last_norm = -1.0;
             if (j.mixed == MIX_INNER32) {
-                j.inner_iters += st.iter;
+                // a continuing classic-PCG sequence counts all its iterations
+                j.inner_iters = j.pcg ? st.iter : j.inner_iters + st.iter;
                 j.precond_norm = std::sqrt(st.uu);
                 j.stage = JS_OUTER;
             } else if (st.status == ST_REPLACE) {
@@ -1486,7 +1545,6 @@ static ppcg_status check_options(const ppcg_options *o)
         (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
          o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
         (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
-        (o->method == PPCG_METHOD_PCG && o->precision == PPCG_MIXED_FP32) ||
         (o->flags & ~PPCG_FLAG_BORROW_INPUTS) != 0) {
         set_error("invalid option value");
         return PPCG_ERR_INVALID_ARG;
@@ -1875,7 +1933,7 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     const bool pcg = h->opt.method == PPCG_METHOD_PCG;
     k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
     if (pcg) {
-        k_pcg_dots<<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
+        k_pcg_dots<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
         k_pcg_update<PCG_START><<<1, kPcgRedThreads, 0, s>>>(tab, cnt, dd);  // item 0 is (system, tile 0)
     } else {
         k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
@@ -1890,10 +1948,10 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
         if (pcg) {
             // the two streaming kernels are timed; the per-system reductions
             // between them run untimed
-            hipExtLaunchKernelGGL(k_pcg_spmv, dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2], ev[4 * i + 3], 0,
+            hipExtLaunchKernelGGL(k_pcg_spmv<double>, dim3(grid), dim3(kSpmvThreads), 0, s, ev[4 * i + 2], ev[4 * i + 3], 0,
                                   tab, cnt, dd, rs);
             k_pcg_alpha<<<1, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
-            hipExtLaunchKernelGGL(k_pcg_vma, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0, tab,
+            hipExtLaunchKernelGGL(k_pcg_vma<double>, dim3(grid), dim3(kVmaThreads), 0, s, ev[4 * i], ev[4 * i + 1], 0, tab,
                                   cnt, dd, rv);
             k_pcg_update<PCG_ITER><<<1, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
         } else {

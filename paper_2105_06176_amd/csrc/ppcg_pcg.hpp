@@ -21,6 +21,19 @@
 // from the iteration counter: the SpMV of the iteration after k x-updates
 // reads buffer k mod 2 (p for even, z for odd) and writes the other.
 //
+// The kernels are templated on the vector type T: double for the FP64 and
+// FP32-values modes, float for the inner solves of the FP32 mixed-precision
+// mode (FP32 vectors and values, FP64 dot-product accumulation and scalars).
+//
+// FP32 mixed-precision mode (d.prec == PREC_F32): one Algorithm 1 sequence
+// in FP32 on the scaled system A y = r64 / ||r64||, paused like the
+// FP32-values mode below.  At a pause the host adds the correction to the
+// FP64 iterate (k_pcg_mix_correct), recomputes r64 = b - A64 x64 and, unless
+// it has converged, rescales the system to the new residual
+// (k_pcg_mix_start: the kept direction and gamma_{i-1} are carried over to
+// the new scale) and replaces r32, u32 as in a reliable update; the Krylov
+// sequence continues instead of restarting.
+//
 // FP32-values mode (d.vals32): s = A32 p with FP32 matrix values, FP64
 // vectors and accumulation.  When the recurrence residual has fallen by
 // d.repl_factor since the last start or reliable update, the system pauses
@@ -35,6 +48,10 @@ namespace ppcg {
 
 // Threads of the one-workgroup-per-system reduction kernels.
 constexpr int kPcgRedThreads = 1024;
+
+// FP32 mixed precision with classic PCG: default residual reduction between
+// reliable updates (ppcg_options.inner_tol overrides it).
+constexpr double kPcgMixReplFactor = 1e-2;
 
 // Fixed-order reduction of NV partials over a system's tiles for the
 // one-workgroup reduction kernels: thread t takes the tiles t, t + NT, ...
@@ -69,16 +86,19 @@ __device__ __forceinline__ void pcg_reduce(const SysDesc &d, int slot, double (&
     block_sum<kPcgRedThreads, NV>(out, lds);
 }
 
-// Direction buffers: the current direction after k x-updates is in pbuf(k).
-__device__ __forceinline__ double *pcg_dir(const SysDesc &d, int k) { return (double *)((k & 1) ? d.z : d.p); }
+// Direction buffers: the current direction after k x-updates is in pcg_dir(k).
+template <typename T>
+__device__ __forceinline__ T *pcg_dir(const SysDesc &d, int k)
+{
+    return (T *)((k & 1) ? d.z : d.p);
+}
 
 // s = A p for one tile with p = u + beta p_old formed per gathered entry;
 // returns this thread's share of (s, p).
-template <typename VT>
+template <typename T, typename VT>
 __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem wi, const VT *__restrict__ val,
-                                                double beta, const double *__restrict__ U,
-                                                const double *__restrict__ Pold, double *__restrict__ Pnew,
-                                                double *__restrict__ S)
+                                                T beta, const T *__restrict__ U, const T *__restrict__ Pold,
+                                                T *__restrict__ Pnew, T *__restrict__ S)
 {
     const int n = d.n;
     double acc = 0.0;
@@ -92,32 +112,32 @@ __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem
             const int len = (int)((d.cptr[chunk + 1] - base) / kSellC);
             const int *c = d.col + base + lane;
             const VT *v = val + base + lane;
-            double y = 0.0;
+            T y = 0;
             for (int k0 = 0; k0 < len; k0 += B) {
                 int cc[B];
-                double vv[B], xx[B];
+                T vv[B], xx[B];
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
                     cc[j] = 0;
-                    vv[j] = 0.0;
+                    vv[j] = 0;
                     if (k0 + j < len) {
                         cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
-                        vv[j] = (double)stream_load(v + (size_t)(k0 + j) * kSellC);
+                        vv[j] = (T)stream_load(v + (size_t)(k0 + j) * kSellC);
                     }
                 }
 #pragma unroll
                 for (int j = 0; j < B; ++j)
-                    xx[j] = k0 + j < len ? U[cc[j]] + beta * Pold[cc[j]] : 0.0;
+                    xx[j] = k0 + j < len ? U[cc[j]] + beta * Pold[cc[j]] : (T)0;
 #pragma unroll
                 for (int j = 0; j < B; ++j)
                     if (k0 + j < len)
                         y = y + vv[j] * xx[j];
             }
             if (i < n) {
-                const double pn = U[i] + beta * Pold[i];
+                const T pn = U[i] + beta * Pold[i];
                 Pnew[i] = pn;
                 S[i] = y;
-                acc = acc + y * pn;
+                acc = acc + (double)y * (double)pn;
             }
         }
     } else {
@@ -127,27 +147,28 @@ __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem
         const int passes = kTileRows / rows_per_pass;
         for (int pass = 0; pass < passes; ++pass) {
             const int i = wi.tile * kTileRows + pass * rows_per_pass + g;
-            double y = 0.0;
+            T y = 0;
             if (i < n) {
                 const int e = d.rp[i + 1];
                 for (int k = d.rp[i] + l; k < e; k += L) {
                     const int cc = stream_load(d.col + k);
-                    y = y + (double)stream_load(val + k) * (U[cc] + beta * Pold[cc]);
+                    y = y + (T)stream_load(val + k) * (U[cc] + beta * Pold[cc]);
                 }
             }
             for (int off = L >> 1; off >= 1; off >>= 1)
                 y = y + __shfl_xor(y, off, 64);
             if (l == 0 && i < n) {
-                const double pn = U[i] + beta * Pold[i];
+                const T pn = U[i] + beta * Pold[i];
                 Pnew[i] = pn;
                 S[i] = y;
-                acc = acc + y * pn;
+                acc = acc + (double)y * (double)pn;
             }
         }
     }
     return acc;
 }
 
+template <typename T>
 __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__restrict__ table,
                                                               const int *__restrict__ count,
                                                               const SysDesc *__restrict__ descs, int remap)
@@ -165,17 +186,23 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__
     const SysState *st = d.st;
     if (st->done)
         return;
-    const double beta = st->beta;
+    const T beta = (T)st->beta;
     const int k = st->iter;
-    const double *U = (const double *)d.u;
-    const double *Pold = pcg_dir(d, k);
-    double *Pnew = pcg_dir(d, k + 1);
-    double *S = (double *)d.s;
+    const T *U = (const T *)d.u;
+    // beta = 0 (a start, or a restart after a breakdown): read u in place of
+    // the old direction, so that whatever that buffer holds cannot leak in
+    // through 0 * Inf or 0 * NaN; u + 0 u = u exactly.
+    const T *Pold = beta == (T)0 ? U : pcg_dir<T>(d, k);
+    T *Pnew = pcg_dir<T>(d, k + 1);
+    T *S = (T *)d.s;
     double v[1];
-    if (d.vals32)
-        v[0] = pcg_spmv_tile<float>(d, wi, d.val32, beta, U, Pold, Pnew, S);
+    // FP32 vectors come with FP32 values (d.val); FP64 vectors use the FP32
+    // copy in FP32-values mode.
+    if (sizeof(T) == 4 || d.vals32)
+        v[0] = pcg_spmv_tile<T, float>(d, wi, sizeof(T) == 4 ? (const float *)d.val : d.val32, beta, U, Pold,
+                                       Pnew, S);
     else
-        v[0] = pcg_spmv_tile<double>(d, wi, (const double *)d.val, beta, U, Pold, Pnew, S);
+        v[0] = pcg_spmv_tile<T, double>(d, wi, (const double *)d.val, beta, U, Pold, Pnew, S);
     block_sum<kSpmvThreads, 1>(v, lds);
     if (threadIdx.x == 0)
         d.part[(size_t)wi.tile * kPartStride] = v[0];  // slot 0
@@ -249,7 +276,7 @@ __device__ inline void pcg_scalar_update(const SysDesc &d, SysState *st, const d
         st->status = ST_NOT_CONVERGED;
         return;
     }
-    if (d.vals32) {
+    if (d.vals32 || d.prec == PREC_F32) {
         const double rn = sqrt(rr);
         if (kind != PCG_ITER) {
             st->repl_ref = rn;
@@ -262,10 +289,12 @@ __device__ inline void pcg_scalar_update(const SysDesc &d, SysState *st, const d
     st->beta = kind == PCG_START || st->i_start == 0 ? 0.0 : g / st->gamma_prev;
 }
 
+template <typename T>
 __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restrict__ table,
                                                          const int *__restrict__ count,
                                                          const SysDesc *__restrict__ descs, int remap)
 {
+    using V2 = typename Vec2<T>::type;
     __shared__ double lds[kVmaThreads / 64 * kNumPartials];
     // Graphs bake a grid that may exceed the live table: blocks past it exit,
     // and the XCD-aware order is taken over the live items only, so that
@@ -279,42 +308,43 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
     const SysState *st = d.st;
     if (st->done)
         return;
-    const double alpha = st->alpha;
-    double *__restrict__ X = (double *)d.x;
-    double *__restrict__ R = (double *)d.r;
-    double *__restrict__ U = (double *)d.u;
-    const double *__restrict__ P = pcg_dir(d, st->iter + 1);
-    const double *__restrict__ S = (const double *)d.s;
-    const double *__restrict__ DI = (const double *)d.dinv;
+    const T alpha = (T)st->alpha;
+    T *__restrict__ X = (T *)d.x;
+    T *__restrict__ R = (T *)d.r;
+    T *__restrict__ U = (T *)d.u;
+    const T *__restrict__ P = pcg_dir<T>(d, st->iter + 1);
+    const T *__restrict__ S = (const T *)d.s;
+    const T *__restrict__ DI = (const T *)d.dinv;
     double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
-    auto elem = [&](double &x, double &r, double &u, double p, double sv, double di) {
+    auto elem = [&](T &x, T &r, T &u, T p, T sv, T di) {
         x = x + alpha * p;
         r = r - alpha * sv;
         u = di * r;
-        acc[0] = acc[0] + u * r;
-        acc[1] = acc[1] + u * u;
-        acc[2] = acc[2] + r * r;
+        const double rd = (double)r, ud = (double)u;
+        acc[0] = acc[0] + ud * rd;
+        acc[1] = acc[1] + ud * ud;
+        acc[2] = acc[2] + rd * rd;
     };
     const int i = wi.tile * kTileRows + threadIdx.x * 2;
     if (i + 1 < d.n) {
-        dvec2 x = vload((const dvec2 *)(X + i)), r = vload((const dvec2 *)(R + i));
-        const dvec2 p = vload((const dvec2 *)(P + i)), sv = vload((const dvec2 *)(S + i));
+        V2 x = vload((const V2 *)(X + i)), r = vload((const V2 *)(R + i));
+        const V2 p = vload((const V2 *)(P + i)), sv = vload((const V2 *)(S + i));
         // a constant diagonal: every lane reads dinv[0..1] (one cached line)
-        const dvec2 di = vload((const dvec2 *)(DI + (d.dinv_const ? 0 : i)));
-        dvec2 u;
+        const V2 di = vload((const V2 *)(DI + (d.dinv_const ? 0 : i)));
+        V2 u;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            double xj = x[j], rj = r[j], uj;
+            T xj = x[j], rj = r[j], uj;
             elem(xj, rj, uj, p[j], sv[j], di[j]);
             x[j] = xj;
             r[j] = rj;
             u[j] = uj;
         }
-        vstore((dvec2 *)(X + i), x);
-        vstore((dvec2 *)(R + i), r);
-        vstore((dvec2 *)(U + i), u);
+        vstore((V2 *)(X + i), x);
+        vstore((V2 *)(R + i), r);
+        vstore((V2 *)(U + i), u);
     } else if (i < d.n) {
-        double x = X[i], r = R[i], u;
+        T x = X[i], r = R[i], u;
         elem(x, r, u, P[i], S[i], DI[d.dinv_const ? 0 : i]);
         X[i] = x;
         R[i] = r;
@@ -331,6 +361,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
 // After r = b - A x and u = M^-1 r were (re)computed (MODE_INIT1 at a start,
 // MODE_REPL1 at a reliable update): partial sums of (u, r), (u, u), (r, r)
 // and (b, b) per tile, in the layout k_pcg_update reduces.
+template <typename T>
 __global__ __launch_bounds__(kVmaThreads) void k_pcg_dots(const WorkItem *__restrict__ table,
                                                           const int *__restrict__ count,
                                                           const SysDesc *__restrict__ descs)
@@ -341,17 +372,18 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_dots(const WorkItem *__rest
         return;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
-    const double *__restrict__ R = (const double *)d.r;
-    const double *__restrict__ U = (const double *)d.u;
-    const double *__restrict__ Bv = (const double *)d.b;
+    const T *__restrict__ R = (const T *)d.r;
+    const T *__restrict__ U = (const T *)d.u;
+    const T *__restrict__ Bv = (const T *)d.b;
     double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < 2; ++k) {
         const int i = wi.tile * kTileRows + threadIdx.x * 2 + k;
         if (i < d.n) {
-            acc[0] = acc[0] + U[i] * R[i];
-            acc[1] = acc[1] + U[i] * U[i];
-            acc[2] = acc[2] + R[i] * R[i];
-            acc[3] = acc[3] + Bv[i] * Bv[i];
+            const double ui = (double)U[i], ri = (double)R[i], bi = (double)Bv[i];
+            acc[0] = acc[0] + ui * ri;
+            acc[1] = acc[1] + ui * ui;
+            acc[2] = acc[2] + ri * ri;
+            acc[3] = acc[3] + bi * bi;
         }
     }
     block_sum<kVmaThreads, kNumPartials>(acc, lds);
@@ -390,6 +422,69 @@ __global__ __launch_bounds__(kPcgRedThreads) void k_pcg_update(const WorkItem *_
         if (KIND == PCG_REPL && st->status == ST_BREAKDOWN)
             st->i_start = 0;
         pcg_scalar_update(d, st, v, KIND);
+    }
+}
+
+// FP32 mixed precision with classic PCG, end of an inner stretch:
+// x64 += c x32 with c = ||r64|| at the last k_pcg_mix_start, and c is kept
+// (in the FP64 slot's repl_ref) for the rescaling at the next start.  Work
+// items name FP64 slots; SysDesc::pair is the FP32 slot.
+__global__ void k_pcg_mix_correct(const WorkItem *__restrict__ table, const int *__restrict__ count,
+                                  const SysDesc *__restrict__ d64, const SysDesc *__restrict__ d32)
+{
+    const int pos = blockIdx.x;
+    if (pos >= *count)
+        return;
+    const WorkItem wi = table[pos];
+    const SysDesc &a = d64[wi.slot];
+    const SysDesc &f = d32[a.pair];
+    const double c = sqrt(a.st->tnorm2);
+    double *__restrict__ x = (double *)a.x;
+    const float *__restrict__ x32 = (const float *)f.x;
+    for (int k = threadIdx.x; k < kTileRows; k += blockDim.x) {
+        const int i = wi.tile * kTileRows + k;
+        if (i < a.n)
+            x[i] = x[i] + c * (double)x32[i];
+    }
+    if (wi.tile == 0 && threadIdx.x == 0)
+        a.st->repl_ref = c;  // no workgroup of this launch reads repl_ref
+}
+
+// Start (or continue) the FP32 sequence on b32 = r64 / ||r64||, x32 = 0.
+// When the FP32 slot holds a live direction (i_start > 0), the system was
+// scaled by 1 / c_old: in the new units y' = (c_old / c_new) y, so the current
+// direction is multiplied by c_old / c_new and gamma_{i-1} by its square;
+// beta = gamma' / gamma_{i-1} of the following reliable update is then the
+// one of the unscaled iteration.
+__global__ void k_pcg_mix_start(const WorkItem *__restrict__ table, const int *__restrict__ count,
+                                const SysDesc *__restrict__ d64, const SysDesc *__restrict__ d32)
+{
+    const int pos = blockIdx.x;
+    if (pos >= *count)
+        return;
+    const WorkItem wi = table[pos];
+    const SysDesc &a = d64[wi.slot];
+    const SysDesc &f = d32[a.pair];
+    const double cn = sqrt(a.st->tnorm2);
+    const double inv = 1.0 / cn;
+    const bool live = f.st->i_start > 0;
+    const float scale = live ? (float)(a.st->repl_ref / cn) : 1.0f;
+    float *__restrict__ P = pcg_dir<float>(f, f.st->iter);
+    const double *__restrict__ r = (const double *)a.r;
+    float *__restrict__ b32 = (float *)f.b;
+    float *__restrict__ x32 = (float *)f.x;
+    for (int k = threadIdx.x; k < kTileRows; k += blockDim.x) {
+        const int i = wi.tile * kTileRows + k;
+        if (i < a.n) {
+            b32[i] = (float)(r[i] * inv);
+            x32[i] = 0.0f;
+            if (live)
+                P[i] = P[i] * scale;
+        }
+    }
+    if (live && wi.tile == 0 && threadIdx.x == 0) {
+        const double c = a.st->repl_ref / cn;
+        f.st->gamma_prev = f.st->gamma_prev * c * c;  // no workgroup of this launch reads gamma_prev
     }
 }
 

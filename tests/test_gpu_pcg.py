@@ -155,9 +155,64 @@ def test_pcg_edge_cases():
     assert info["status"] == ppcg.BREAKDOWN
 
 
-def test_pcg_rejects_fp32_vector_mode():
-    with pytest.raises(PPCGError):
-        Solver(poisson2d(8), method="pcg", precision="mixed")
+# ---------------------------------------------------------------- FP32 inner solves
+
+@pytest.mark.parametrize("gen", [lambda: stencil27_lognormal(16, seed=1), lambda: poisson3d(24),
+                                 lambda: random_spd(20000, seed=3), lambda: shifted(poisson2d(90), 0.01)])
+def test_pcg_fp32_inner_reaches_fp64_tolerance(gen):
+    """Algorithm 1 in FP32 (values, vectors) with FP64 reliable updates: the
+    FP64 iterate meets the FP64 tolerance on the FP64 operator, and since the
+    direction is kept across the updates (no restart of the Krylov sequence)
+    the iteration count stays close to FP64 Algorithm 1's."""
+    A = gen()
+    b = problem(A)
+    x, info = Solver(A, tol=1e-10, method="pcg", precision="mixed").solve(dev(b))
+    assert info["status"] == ppcg.OK, info
+    assert info["outer_iters"] >= 2, info  # at 1e-2 per stretch, 1e-10 takes several
+    assert info["rel_resid_true"] <= 1e-10
+    assert oracle.true_relres(A, b, host(x)) <= 1e-10
+    ref = oracle.pcg(A, b, tol=1e-10)
+    assert info["iters"] <= 1.15 * ref.iters + 5, (info["iters"], ref.iters)
+    assert relerr(host(x), ref.x) <= 1e-5
+
+
+@pytest.mark.parametrize("gen", [lambda: poisson3d(24), lambda: stencil27_lognormal(14, seed=2),
+                                 lambda: random_spd(5000, seed=6)])
+def test_pcg_fp32_first_inner_solve_follows_algorithm1(gen):
+    """One stretch: from x0 = 0 the FP32 sequence is Algorithm 1 on
+    b / ||b||, and x = ||b|| x32 at its first pause.  After its k iterations x agrees
+    with the oracle's k iterations of Algorithm 1 in FP64 to FP32 accuracy;
+    a wrong step (a sign, a dropped term, a stale direction) misses by O(1)."""
+    A = gen()
+    b = problem(A)
+    x, info = Solver(A, tol=1e-10, method="pcg", precision="mixed", inner_tol=0.1, max_outer=1).solve(dev(b))
+    assert info["status"] == ppcg.NOT_CONVERGED and info["outer_iters"] == 1, info
+    k = info["iters"]
+    assert k >= 2
+    ref = oracle.pcg(A, b, fixed_iters=k)
+    assert relerr(host(x), ref.x) <= 1e-4, (k, relerr(host(x), ref.x))
+    # the inner stop: relative recurrence residual below 0.1 after k, not k - 1
+    prev = oracle.pcg(A, b, fixed_iters=k - 1)
+    assert oracle.true_relres(A, b, prev.x) > 0.05
+
+
+def test_pcg_fp32_inner_batch_bitwise_equals_solo():
+    mats = [stencil27_lognormal(12, seed=4), shifted(poisson2d(70), 0.01), random_spd(4000, seed=2)]
+    bs = [problem(A, seed=80 + i) for i, A in enumerate(mats)]
+    kw = dict(tol=1e-10, method="pcg", precision="mixed")
+    solo = [host(Solver(A, **kw).solve(dev(b))[0]) for A, b in zip(mats, bs)]
+    xs, infos = solve_batch([Solver(A, **kw) for A in mats], [dev(b) for b in bs])
+    for x, xs_, info in zip(xs, solo, infos):
+        assert np.array_equal(host(x), xs_)
+        assert info["status"] == ppcg.OK and info["rel_resid_true"] <= 1e-10
+
+
+def test_pcg_fp32_inner_csr_vector_matches_tolerance():
+    A = random_spd(6000, seed=9)
+    b = problem(A)
+    x, info = Solver(A, tol=1e-10, method="pcg", precision="mixed", spmv_format="csr_vector").solve(dev(b))
+    assert info["status"] == ppcg.OK and info["rel_resid_true"] <= 1e-10
+    assert oracle.true_relres(A, b, host(x)) <= 1e-10
 
 
 # ---------------------------------------------------------------- FP32 matrix values
