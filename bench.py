@@ -435,8 +435,9 @@ def leg_c5(ppcg, wl, n_req):
         S.close()
     t_seq = time.perf_counter() - t0
     out = {"workload": f"{n_req} requests: 40% 2D 5-pt, 30% 3D 7-pt, 30% random SPD, N log-uniform [1e3,4e6], "
-                       "tol {1e-6,1e-8,1e-10}; precision chosen by the server (FP32 values with FP64 "
-                       "reliable updates for >= 65536 rows, else FP64)",
+                       "tol {1e-6,1e-8,1e-10}; precision chosen by the server (FP32 classic PCG with FP64 "
+                       "reliable updates for >= 262144 rows, FP32 values with FP64 reliable updates "
+                       "for >= 65536 rows, else FP64)",
            "saturation_solves_per_s": round(sat, 2),
            "saturation_solves_per_s_all_fp64": round(n_req / total64, 2),
            "saturation_solves_per_s_all_fp32_values": round(n_req / total32, 2),

@@ -76,12 +76,18 @@ typedef enum {
                              recomputed with the FP64 values and the pipelined
                              auxiliary vectors are rebuilt from it */
     PPCG_PRECISION_AUTO = 3 /* serving only (ppcg_srv_submit): the server chooses per request by
-                             a byte model of one iteration.  Systems of at least 65536 rows
-                             (bandwidth-bound) run PPCG_MIXED_FP32_VALUES when its bytes per
-                             iteration (8 per stored entry + 176 per row) are at least 5% below
-                             FP64's (12 per entry + 176 per row); others run PPCG_FP64.  A
-                             FP32-values request that ends PPCG_STAGNATED or PPCG_BREAKDOWN is
-                             run again in PPCG_FP64 from its last iterate */
+                             a byte model of one iteration; FP64 PIPECG moves 12 bytes per
+                             stored entry + 176 per row.  Systems of at least 262144 rows run
+                             PPCG_MIXED_FP32 with PPCG_METHOD_PCG (8 per entry + 48 per row)
+                             when that is at most 70% of FP64's bytes: enough to pay for its
+                             two extra launches per iteration.  Systems of at least 65536 rows
+                             run PPCG_MIXED_FP32_VALUES (8 per entry + 176 per row) when that
+                             is at least 5% below FP64's.  Below 65536 rows launch latency,
+                             not bytes, sets the time: PPCG_FP64.  A request run in reduced
+                             precision that ends PPCG_STAGNATED, PPCG_BREAKDOWN, or
+                             PPCG_NOT_CONVERGED with its refinement budget (max_outer) spent is
+                             run again in PPCG_FP64 with the server's method from its last
+                             iterate.  ppcg_info reports the precision and method used */
 } ppcg_precision;
 
 /* Iteration scheme (ppcg_options.method). */
@@ -166,6 +172,9 @@ typedef struct {
     double precond_norm;     /* sqrt((u,u)) at exit */
     double time_ms;          /* wall time of the solve on its stream */
     double model_bytes;      /* algorithmic HBM bytes moved by the iterations */
+    ppcg_precision precision;/* precision the solve ran in (the server's choice for
+                                PPCG_PRECISION_AUTO; PPCG_FP64 after an automatic rerun) */
+    ppcg_method method;      /* iteration scheme the solve ran with */
 } ppcg_info;
 
 /* Static description of a handle's matrix as the library stores it. */

@@ -1453,6 +1453,8 @@ void fill_info(const ppcg_handle *h, const Job &j, ppcg_info *info)
     info->time_ms = j.t_end - j.t_start;
     const ByteModel bm = byte_model(h, j.mixed == MIX_INNER32 ? PREC_F32 : j.mixed == MIX_VALUES32 ? PREC_V32 : PREC_F64);
     info->model_bytes = (bm.vma + bm.spmv) * j.iters;
+    info->precision = h->opt.precision;
+    info->method = h->opt.method;
 }
 
 // Order the internal stream after all work already queued on the caller's

@@ -28,6 +28,9 @@ namespace {
 
 constexpr int kServerSlots = 1024;
 constexpr int kServeGraphIters = 32;
+// automatic precision: smallest systems given reduced precision
+constexpr int kAutoValues32Rows = 65536;
+constexpr int kAutoPcg32Rows = 262144;
 
 struct Request {
     int64_t id = 0;
@@ -35,7 +38,8 @@ struct Request {
     double footprint = 0.0;
     double tol = 0.0;
     ppcg_precision precision = PPCG_FP64;
-    bool auto_prec = false;  // chosen by the server; FP32 values fall back to FP64
+    ppcg_method method = PPCG_METHOD_PIPECG;
+    bool auto_prec = false;  // chosen by the server; reduced precision falls back to FP64
     int32_t n = 0;
     int64_t nnz = 0;
     // inputs: owned copies, or the caller's arrays (borrowing server)
@@ -73,6 +77,7 @@ static ppcg_status admit(ppcg_server *s)
         ppcg_options o = s->defaults;
         o.tol = r.tol;
         o.precision = r.precision;
+        o.method = r.method;
         o.vec_mem = PPCG_MEM_HOST;
         o.fixed_iters = 0;
         ppcg_csr A{};
@@ -108,7 +113,7 @@ static ppcg_status admit(ppcg_server *s)
         s->used += r.footprint;
         ++s->active;
         // inputs now live on the device (kept while a fallback rerun may need them)
-        if (!(r.auto_prec && r.precision == PPCG_MIXED_FP32_VALUES)) {
+        if (!(r.auto_prec && r.precision != PPCG_FP64)) {
             std::vector<int32_t>().swap(r.rp);
             std::vector<int32_t>().swap(r.ci);
             std::vector<double>().swap(r.val);
@@ -142,11 +147,14 @@ static ppcg_status retire_finished(ppcg_server *s)
         r.h = nullptr;
         s->used -= r.footprint;
         --s->active;
-        if (r.auto_prec && r.precision == PPCG_MIXED_FP32_VALUES &&
-            (r.info.status == PPCG_STAGNATED || r.info.status == PPCG_BREAKDOWN)) {
-            // FP32 values did not reach the tolerance: run again in FP64 from
-            // the last iterate, ahead of the requests still queued
+        const bool budget_spent =
+            r.info.status == PPCG_NOT_CONVERGED && r.info.outer_iters >= s->defaults.max_outer;
+        if (r.auto_prec && r.precision != PPCG_FP64 &&
+            (r.info.status == PPCG_STAGNATED || r.info.status == PPCG_BREAKDOWN || budget_spent)) {
+            // reduced precision did not reach the tolerance: run again in
+            // FP64 from the last iterate, ahead of the requests still queued
             r.precision = PPCG_FP64;
+            r.method = s->defaults.method;
             r.footprint = ppcg_footprint_bytes(r.n, r.nnz, PPCG_FP64);
             r.state = 0;
             s->queue.push_front(kv.first);
@@ -199,13 +207,25 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
         return PPCG_ERR_INVALID_ARG;
     }
     const bool auto_prec = precision == PPCG_PRECISION_AUTO;
+    ppcg_method method = s->defaults.method;
     if (auto_prec) {
-        // bytes of one PIPECG iteration: 12 (FP64) or 8 (FP32 values) per
-        // stored entry, plus the 22 FP64 vector streams of a row; below
+        // bytes of one iteration: FP64 PIPECG 12 per stored entry plus 22
+        // FP64 vector streams per row; FP32 values 8 per entry; classic PCG
+        // in FP32 8 per entry plus 12 FP32 vector streams per row, with two
+        // more launches per iteration (one-workgroup reductions), so it is
+        // taken only where the bytes saved clearly outweigh them; below
         // 65536 rows launch latency, not bytes, sets the time
         const double b64 = 12.0 * (double)A->nnz + 176.0 * A->n;
-        const double b32 = 8.0 * (double)A->nnz + 176.0 * A->n;
-        precision = (A->n >= 65536 && b32 <= 0.95 * b64) ? PPCG_MIXED_FP32_VALUES : PPCG_FP64;
+        const double bv32 = 8.0 * (double)A->nnz + 176.0 * A->n;
+        const double bp32 = 8.0 * (double)A->nnz + 48.0 * A->n;
+        if (A->n >= kAutoPcg32Rows && bp32 <= 0.7 * b64) {
+            precision = PPCG_MIXED_FP32;
+            method = PPCG_METHOD_PCG;
+        } else if (A->n >= kAutoValues32Rows && bv32 <= 0.95 * b64) {
+            precision = PPCG_MIXED_FP32_VALUES;
+        } else {
+            precision = PPCG_FP64;
+        }
     }
     const double fp = ppcg_footprint_bytes(A->n, A->nnz, precision);
     if (fp > s->budget) {
@@ -217,6 +237,7 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
     r.footprint = fp;
     r.tol = tol;
     r.precision = precision;
+    r.method = method;
     r.auto_prec = auto_prec;
     r.n = A->n;
     r.nnz = A->nnz;

@@ -49,7 +49,8 @@ class Info(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("status", ctypes.c_int), ("iters", ctypes.c_int32),
                 ("outer_iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("rel_resid_true", ctypes.c_double), ("rel_resid_recur", ctypes.c_double),
-                ("precond_norm", ctypes.c_double), ("time_ms", ctypes.c_double), ("model_bytes", ctypes.c_double)]
+                ("precond_norm", ctypes.c_double), ("time_ms", ctypes.c_double), ("model_bytes", ctypes.c_double),
+                ("precision", ctypes.c_int), ("method", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}

@@ -78,6 +78,7 @@ int main(void) {
   F(ppcg_shard_info, nnz_local) F(ppcg_shard_info, boundary_rows) F(ppcg_shard_info, halo_bytes)
   F(ppcg_hybrid_info, t_cpu_spmv_ms) F(ppcg_hybrid_info, nnz_gpu_remote) F(ppcg_hybrid_info, halo_to_gpu)
   F(ppcg_info, status) F(ppcg_info, rel_resid_true) F(ppcg_info, model_bytes)
+  F(ppcg_info, precision) F(ppcg_info, method)
   F(ppcg_matrix_info, nnz_stored) F(ppcg_matrix_info, tile_rows) F(ppcg_matrix_info, setup_ms)
   F(ppcg_matrix_info, col_index_bytes) F(ppcg_matrix_info, diag_const)
   return 0;

@@ -475,6 +475,21 @@ def test_server_automatic_precision():
         assert oracle.true_relres(A, b, res[key][0]) <= tol
     assert res["big"][1]["outer_iters"] >= 1
     assert res["small"][1]["outer_iters"] == 0
+    assert res["big"][1]["precision"] == ppcg.MIXED_FP32_VALUES
+    assert res["small"][1]["precision"] == ppcg.FP64
+    assert res["big"][1]["method"] == res["small"][1]["method"] == ppcg.METHOD_PIPECG
+
+
+def test_server_automatic_precision_takes_fp32_pcg_for_large_systems():
+    """At 262144 rows and more the server runs classic PCG in FP32 (values and
+    vectors) with FP64 reliable updates; it reaches the FP64 tolerance."""
+    big = poisson3d(64)
+    b = problem(big)[0]
+    x, info = _serve_all(Server(), [("big", big, b, 1e-10, "auto")])["big"]
+    assert info["status"] == ppcg.OK, info
+    assert info["precision"] == ppcg.MIXED_FP32 and info["method"] == ppcg.METHOD_PCG
+    assert info["outer_iters"] >= 2
+    assert oracle.true_relres(big, b, x) <= 1e-10
 
 
 def test_server_automatic_precision_falls_back_to_fp64():
@@ -489,7 +504,21 @@ def test_server_automatic_precision_falls_back_to_fp64():
     assert info["status"] == ppcg.OK
     assert oracle.true_relres(big, b, x) <= 1e-10
     assert info["outer_iters"] == 0
+    assert info["precision"] == ppcg.FP64 and info["method"] == ppcg.METHOD_PIPECG
     assert info["iters"] < 0.8 * oracle.pipecg(big, b, tol=1e-10).iters
+
+
+def test_server_automatic_fp32_pcg_falls_back_to_fp64_when_budget_spent():
+    """One reliable-update stretch allowed (max_outer 1, pause at 0.1): the
+    FP32 classic-PCG run ends NOT_CONVERGED with its refinement budget spent,
+    and the server reruns the request in FP64 PIPECG from its last iterate."""
+    big = poisson3d(64)
+    b = problem(big)[0]
+    x, info = _serve_all(Server(inner_tol=0.1, max_outer=1), [("big", big, b, 1e-10, "auto")])["big"]
+    assert info["status"] == ppcg.OK, info
+    assert info["precision"] == ppcg.FP64 and info["method"] == ppcg.METHOD_PIPECG
+    assert oracle.true_relres(big, b, x) <= 1e-10
+    assert info["iters"] < oracle.pipecg(big, b, tol=1e-10).iters
 
 
 # ---------------------------------------------------------------- FP32 values + reliable updates
