@@ -270,10 +270,17 @@ __device__ inline void scalar_update_repl(const SysDesc &d, SysState *st, const 
 
 // ---------------------------------------------------------------------------
 // Fused vector updates + Jacobi + dot-product partials.
+//
+// m_i = M^-1 w_i is not read back: every writer of w (the initialisation, a
+// reliable update, this kernel) stores m = dinv * w beside it, so the old m
+// is recomputed from the old w and dinv, both read here anyway.  The product
+// is the same rounded operation on the same operands, so the result is
+// bitwise the stored value, and one vector stream fewer is read.
 template <typename T, int NV>
-__device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T m, T &q, T &w, T &s, T &u, T &p, T &x,
-                                         T &r, T dinv, T &m_out, double (&acc)[NV])
+__device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T &q, T &w, T &s, T &u, T &p, T &x, T &r,
+                                         T dinv, T &m_out, double (&acc)[NV])
 {
+    const T m = dinv * w;
     z = nv + sb * z;
     q = m + sb * q;
     s = w + sb * s;
@@ -360,7 +367,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     const int i = wi.tile * kTileRows + threadIdx.x * 2;
     using V2 = typename Vec2<T>::type;
     if (i + 1 < n) {
-        V2 nv = vload((const V2 *)(NVv + i)), z = vload((const V2 *)(Z + i)), m = vload((const V2 *)(M + i));
+        V2 nv = vload((const V2 *)(NVv + i)), z = vload((const V2 *)(Z + i));
         V2 q = vload((const V2 *)(Q + i)), w = vload((const V2 *)(W + i)), s = vload((const V2 *)(S + i));
         V2 u = vload((const V2 *)(U + i)), p = vload((const V2 *)(P + i)), x = vload((const V2 *)(X + i));
         // a constant diagonal: every lane reads dinv[0..1] (one cached line)
@@ -369,7 +376,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             T zj = z[j], qj = q[j], wj = w[j], sj = s[j], uj = u[j], pj = p[j], xj = x[j], rj = r[j], mj;
-            vma_elem<T, NV>(sa, sb, nv[j], zj, m[j], qj, wj, sj, uj, pj, xj, rj, di[j], mj, acc);
+            vma_elem<T, NV>(sa, sb, nv[j], zj, qj, wj, sj, uj, pj, xj, rj, di[j], mj, acc);
             z[j] = zj; q[j] = qj; w[j] = wj; s[j] = sj; u[j] = uj; p[j] = pj; x[j] = xj; r[j] = rj; mo[j] = mj;
         }
         vstore((V2 *)(Z + i), z);
@@ -383,7 +390,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
         vstore((V2 *)(M + i), mo);
     } else if (i < n) {
         T z = Z[i], q = Q[i], w = W[i], s = S[i], u = U[i], p = P[i], x = X[i], r = R[i], mo;
-        vma_elem<T, NV>(sa, sb, NVv[i], z, M[i], q, w, s, u, p, x, r, DI[d.dinv_const ? 0 : i], mo, acc);
+        vma_elem<T, NV>(sa, sb, NVv[i], z, q, w, s, u, p, x, r, DI[d.dinv_const ? 0 : i], mo, acc);
         Z[i] = z; Q[i] = q; S[i] = s; P[i] = p; X[i] = x; R[i] = r; U[i] = u; W[i] = w; M[i] = mo;
     }
     block_sum<kVmaThreads, NV>(acc, lds);

@@ -97,8 +97,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
             const int i = threadIdx.x + j * kSmallThreads;
             if (i < n) {
                 double mo;
-                vma_elem<double, kNumPartials>(sa, sb, nv[j], z[j], lm[i], q[j], w[j], s[j], u[j], p[j], xg[j],
-                                               r[j], dg[j], mo, acc);
+                vma_elem<double, kNumPartials>(sa, sb, nv[j], z[j], q[j], w[j], s[j], u[j], p[j], xg[j], r[j],
+                                               dg[j], mo, acc);
                 X[i] = xg[j];
                 lm[i] = mo;  // only this thread touches lm[i] until the barrier below
             }
