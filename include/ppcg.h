@@ -191,7 +191,7 @@ typedef struct {
     double bytes_per_iter;   /* algorithmic HBM bytes of one iteration (both kernels) of
                                 the handle's current method (opt.method) */
     double bytes_vma;        /* algorithmic bytes of one vector-update launch (PIPECG: fused
-                                VMA+PC+dots, 19 vectors; PCG: 8 vectors; one fewer when
+                                VMA+PC+dots, 15 vectors; PCG: 8 vectors; one fewer when
                                 diag_const) */
     double bytes_spmv;       /* algorithmic bytes of one SpMV launch (matrix plus 2 vectors;
                                 PCG: plus 4, the direction update being fused into it) */

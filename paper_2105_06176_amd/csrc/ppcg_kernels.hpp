@@ -271,26 +271,33 @@ __device__ inline void scalar_update_repl(const SysDesc &d, SysState *st, const 
 // ---------------------------------------------------------------------------
 // Fused vector updates + Jacobi + dot-product partials.
 //
-// m_i = M^-1 w_i is not read back: every writer of w (the initialisation, a
-// reliable update, this kernel) stores m = dinv * w beside it, so the old m
-// is recomputed from the old w and dinv, both read here anyway.  The product
-// is the same rounded operation on the same operands, so the result is
-// bitwise the stored value, and one vector stream fewer is read.
+// With the Jacobi preconditioner M^-1 is a diagonal scaling, so three of
+// Algorithm 2's preconditioned vectors are the scaled unpreconditioned ones
+// at every step: m_i = M^-1 w_i, u_i = M^-1 r_i and q_i = M^-1 s_i.  (Each
+// holds after the initialisation, where q_0 = m_0 and s_0 = w_0, and is kept
+// by the updates: q_i = m_i + beta q_{i-1} = M^-1 (w_i + beta s_{i-1}), and
+// u_{i+1} = u_i - alpha q_i = M^-1 (r_i - alpha s_i).)  The kernel therefore
+// forms u from r with the inverse diagonal instead of carrying u and q as
+// vectors of their own: neither is read and q is never stored, four vector
+// streams fewer.  m, which the SpMV gathers, is still stored.  Every writer
+// of r (the initialisation, a reliable update, this kernel) also writes
+// u = dinv * r, so the u read back elsewhere is the same rounded product.
+// In exact arithmetic the iterates are Algorithm 2's; in floating point the
+// two recurrences for u and q are replaced by the exact scaling.
 template <typename T, int NV>
-__device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T &q, T &w, T &s, T &u, T &p, T &x, T &r,
-                                         T dinv, T &m_out, double (&acc)[NV])
+__device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T &w, T &s, T &p, T &x, T &r, T dinv,
+                                         T &u_out, T &m_out, double (&acc)[NV])
 {
-    const T m = dinv * w;
+    const T u = dinv * r;  // u_i
     z = nv + sb * z;
-    q = m + sb * q;
     s = w + sb * s;
     p = u + sb * p;
     x = x + sa * p;
     r = r - sa * s;
-    u = u - sa * q;
     w = w - sa * z;
-    m_out = dinv * w;
-    const double rd = (double)r, ud = (double)u, wd = (double)w;
+    u_out = dinv * r;  // u_{i+1}
+    m_out = dinv * w;  // m_{i+1}
+    const double rd = (double)r, ud = (double)u_out, wd = (double)w;
     acc[0] = acc[0] + rd * ud;
     acc[1] = acc[1] + wd * ud;
     acc[2] = acc[2] + ud * ud;
@@ -351,12 +358,10 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     const int n = d.n;
     T *__restrict__ X = (T *)d.x;
     T *__restrict__ R = (T *)d.r;
-    T *__restrict__ U = (T *)d.u;
     T *__restrict__ W = (T *)d.w;
     T *__restrict__ M = (T *)d.m;
     const T *__restrict__ NVv = (const T *)d.nv;
     T *__restrict__ Z = (T *)d.z;
-    T *__restrict__ Q = (T *)d.q;
     T *__restrict__ S = (T *)d.s;
     T *__restrict__ P = (T *)d.p;
     const T *__restrict__ DI = (const T *)d.dinv;
@@ -367,31 +372,28 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     const int i = wi.tile * kTileRows + threadIdx.x * 2;
     using V2 = typename Vec2<T>::type;
     if (i + 1 < n) {
-        V2 nv = vload((const V2 *)(NVv + i)), z = vload((const V2 *)(Z + i));
-        V2 q = vload((const V2 *)(Q + i)), w = vload((const V2 *)(W + i)), s = vload((const V2 *)(S + i));
-        V2 u = vload((const V2 *)(U + i)), p = vload((const V2 *)(P + i)), x = vload((const V2 *)(X + i));
+        V2 nv = vload((const V2 *)(NVv + i)), z = vload((const V2 *)(Z + i)), w = vload((const V2 *)(W + i));
+        V2 s = vload((const V2 *)(S + i)), p = vload((const V2 *)(P + i)), x = vload((const V2 *)(X + i));
         // a constant diagonal: every lane reads dinv[0..1] (one cached line)
         V2 r = vload((const V2 *)(R + i)), di = vload((const V2 *)(DI + (d.dinv_const ? 0 : i)));
         V2 mo;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            T zj = z[j], qj = q[j], wj = w[j], sj = s[j], uj = u[j], pj = p[j], xj = x[j], rj = r[j], mj;
-            vma_elem<T, NV>(sa, sb, nv[j], zj, qj, wj, sj, uj, pj, xj, rj, di[j], mj, acc);
-            z[j] = zj; q[j] = qj; w[j] = wj; s[j] = sj; u[j] = uj; p[j] = pj; x[j] = xj; r[j] = rj; mo[j] = mj;
+            T zj = z[j], wj = w[j], sj = s[j], pj = p[j], xj = x[j], rj = r[j], uj, mj;
+            vma_elem<T, NV>(sa, sb, nv[j], zj, wj, sj, pj, xj, rj, di[j], uj, mj, acc);
+            z[j] = zj; w[j] = wj; s[j] = sj; p[j] = pj; x[j] = xj; r[j] = rj; mo[j] = mj;
         }
         vstore((V2 *)(Z + i), z);
-        vstore((V2 *)(Q + i), q);
         vstore((V2 *)(S + i), s);
         vstore((V2 *)(P + i), p);
         vstore((V2 *)(X + i), x);
         vstore((V2 *)(R + i), r);
-        vstore((V2 *)(U + i), u);
         vstore((V2 *)(W + i), w);
         vstore((V2 *)(M + i), mo);
     } else if (i < n) {
-        T z = Z[i], q = Q[i], w = W[i], s = S[i], u = U[i], p = P[i], x = X[i], r = R[i], mo;
-        vma_elem<T, NV>(sa, sb, NVv[i], z, q, w, s, u, p, x, r, DI[d.dinv_const ? 0 : i], mo, acc);
-        Z[i] = z; Q[i] = q; S[i] = s; P[i] = p; X[i] = x; R[i] = r; U[i] = u; W[i] = w; M[i] = mo;
+        T z = Z[i], w = W[i], s = S[i], p = P[i], x = X[i], r = R[i], u, mo;
+        vma_elem<T, NV>(sa, sb, NVv[i], z, w, s, p, x, r, DI[d.dinv_const ? 0 : i], u, mo, acc);
+        Z[i] = z; S[i] = s; P[i] = p; X[i] = x; R[i] = r; W[i] = w; M[i] = mo;
     }
     block_sum<kVmaThreads, NV>(acc, lds);
     if (threadIdx.x == 0) {

@@ -120,9 +120,10 @@ ppcg_status check_dev_range(const void *p, size_t bytes, const char *what)
 }
 
 // ---------------------------------------------------------------- byte model
-// Algorithmic HBM bytes of one iteration.  PIPECG: the fused update reads 10
-// vectors (n z q w s u p x r dinv; m is recomputed from w) and writes 9 (z q
-// s p x r u w m); the SpMV reads values and column indices of every
+// Algorithmic HBM bytes of one iteration.  PIPECG: the fused update reads 8
+// vectors (n z w s p x r dinv; u and q are scalings of r and s by the inverse
+// diagonal, formed in registers) and writes 7 (z s p x r w m); the SpMV reads
+// values and column indices of every
 // stored entry, its row/chunk pointers, the input vector once, and writes one
 // vector.  Classic PCG: the update reads x, p, r, s and the inverse diagonal
 // and writes x, r, u (8 vectors); the SpMV reads u and the previous direction
@@ -139,7 +140,7 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     const bool pcg = h->opt.method == PPCG_METHOD_PCG;
     ByteModel bm;
     // a constant diagonal is read as one scalar: one vector stream fewer
-    bm.vma = ((pcg ? 8.0 : 19.0) - (h->dinv_const ? 1.0 : 0.0)) * ve * n;
+    bm.vma = ((pcg ? 8.0 : 15.0) - (h->dinv_const ? 1.0 : 0.0)) * ve * n;
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
     // the PIPECG SpMV reads 16-bit column offsets when the matrix has them
     const double ie = (h->col16 && !pcg) ? 2.0 : 4.0;

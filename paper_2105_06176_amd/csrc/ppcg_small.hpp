@@ -47,7 +47,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
     double *__restrict__ M = (double *)d.m;
     double *__restrict__ NVv = (double *)d.nv;
     double *__restrict__ Z = (double *)d.z;
-    double *__restrict__ Q = (double *)d.q;
     double *__restrict__ S = (double *)d.s;
     double *__restrict__ P = (double *)d.p;
     const double *__restrict__ DI = (const double *)d.dinv;
@@ -55,17 +54,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
     const int *__restrict__ col = d.col;
     const int64_t *__restrict__ cptr = d.cptr;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double z[R], q[R], s[R], p[R], r[R], u[R], w[R], nv[R];
+    // u and q are scalings of r and s by the inverse diagonal (see vma_elem):
+    // u is formed from r, q never
+    double z[R], s[R], p[R], r[R], u[R], w[R], nv[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int i = threadIdx.x + j * kSmallThreads;
         const bool ok = i < n;
         z[j] = ok ? Z[i] : 0.0;
-        q[j] = ok ? Q[i] : 0.0;
         s[j] = ok ? S[i] : 0.0;
         p[j] = ok ? P[i] : 0.0;
         r[j] = ok ? Rv[i] : 0.0;
-        u[j] = ok ? U[i] : 0.0;
+        u[j] = ok ? U[i] : 0.0;  // written back unchanged if no iteration runs
         w[j] = ok ? W[i] : 0.0;
         nv[j] = ok ? NVv[i] : 0.0;
         if (ok)
@@ -97,8 +97,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
             const int i = threadIdx.x + j * kSmallThreads;
             if (i < n) {
                 double mo;
-                vma_elem<double, kNumPartials>(sa, sb, nv[j], z[j], q[j], w[j], s[j], u[j], p[j], xg[j], r[j],
-                                               dg[j], mo, acc);
+                vma_elem<double, kNumPartials>(sa, sb, nv[j], z[j], w[j], s[j], p[j], xg[j], r[j], dg[j], u[j], mo,
+                                               acc);
                 X[i] = xg[j];
                 lm[i] = mo;  // only this thread touches lm[i] until the barrier below
             }
@@ -153,7 +153,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
         const int i = threadIdx.x + j * kSmallThreads;
         if (i < n) {
             Z[i] = z[j];
-            Q[i] = q[j];
             S[i] = s[j];
             P[i] = p[j];
             Rv[i] = r[j];
