@@ -62,13 +62,13 @@ typedef enum {
 typedef enum {
     PPCG_FP64 = 0,        /* every vector, matrix value and scalar in FP64 */
     PPCG_MIXED_FP32 = 1,  /* FP32 matrix values and vectors, FP64 dot products and
-                             scalars, on the system scaled by the FP64 residual.
-                             PIPECG: inner solves restarted inside an FP64
-                             iterative-refinement loop on the FP64 operator.
-                             PPCG_METHOD_PCG: one Algorithm 1 sequence with FP64
-                             reliable updates (x64 += correction, r64 = b - A64 x64,
-                             rescaled, direction kept) whenever its residual fell by
-                             inner_tol (default 1e-2) */
+                             scalars: one Algorithm 1 sequence on the system scaled by
+                             the FP64 residual, with FP64 reliable updates (x64 +=
+                             correction, r64 = b - A64 x64, rescaled, direction kept)
+                             whenever its residual fell by inner_tol (default 1e-2).
+                             Always Algorithm 1, whatever ppcg_options.method says:
+                             Algorithm 2's auxiliary recurrences (w, z, s) do not
+                             survive FP32 storage.  ppcg_info.method reports it */
     PPCG_MIXED_FP32_VALUES = 2, /* one PIPECG sequence whose SpMVs read FP32 matrix values
                              (FP64 vectors, FP64 accumulation, FP64 dots and scalars),
                              with reliable updates: whenever the residual has dropped by
@@ -77,11 +77,11 @@ typedef enum {
                              auxiliary vectors are rebuilt from it */
     PPCG_PRECISION_AUTO = 3 /* serving only (ppcg_srv_submit): the server chooses per request by
                              a byte model of one iteration; FP64 PIPECG moves 12 bytes per
-                             stored entry + 176 per row.  Systems of at least 262144 rows run
-                             PPCG_MIXED_FP32 with PPCG_METHOD_PCG (8 per entry + 48 per row)
-                             when that is at most 70% of FP64's bytes: enough to pay for its
-                             two extra launches per iteration.  Systems of at least 65536 rows
-                             run PPCG_MIXED_FP32_VALUES (8 per entry + 176 per row) when that
+                             stored entry + 136 per row.  Systems of at least 262144 rows run
+                             PPCG_MIXED_FP32 (Algorithm 1, 8 per entry + 48 per row) when
+                             that is at most 70% of FP64's bytes: enough to pay for its two
+                             extra launches per iteration.  Systems of at least 65536 rows
+                             run PPCG_MIXED_FP32_VALUES (8 per entry + 136 per row) when that
                              is at least 5% below FP64's.  Below 65536 rows launch latency,
                              not bytes, sets the time: PPCG_FP64.  A request run in reduced
                              precision that ends PPCG_STAGNATED, PPCG_BREAKDOWN, or
@@ -98,9 +98,8 @@ typedef enum {
     PPCG_METHOD_PCG = 1     /* Algorithm 1 (Section III-A): classic PCG; two launches per
                                iteration, each ending in a reduction the next launch waits
                                for.  With PPCG_FP64, PPCG_MIXED_FP32_VALUES (FP32 values,
-                               reliable updates r = b - A x keeping the direction) or
-                               PPCG_MIXED_FP32 (FP32 vectors and values, FP64 reliable
-                               updates) */
+                               reliable updates r = b - A x keeping the direction).
+                               PPCG_MIXED_FP32 always runs Algorithm 1 */
 } ppcg_method;
 
 typedef enum { PPCG_MEM_DEVICE = 0, PPCG_MEM_HOST = 1 } ppcg_mem;
@@ -134,6 +133,10 @@ typedef struct {
                                       caller's A and b arrays instead of copying them; they must
                                       stay valid and unchanged until ppcg_srv_poll reports the
                                       request ready.  Ignored elsewhere */
+#define PPCG_FLAG_SELL_COL16 2u    /* SELL: read 16-bit column offsets from the row whenever all
+                                      fit, without timing them against 32-bit columns (by default
+                                      both are timed at create time and the faster is kept) */
+#define PPCG_FLAG_SELL_COL32 4u    /* SELL: always read 32-bit columns (not with SELL_COL16) */
 
 /* Solver options; initialise with ppcg_default_options(). */
 typedef struct {
@@ -148,10 +151,9 @@ typedef struct {
     ppcg_mem vec_mem;        /* where b, x0 and x live (default PPCG_MEM_DEVICE) */
     ppcg_spmv_format spmv_format; /* default PPCG_SPMV_AUTO */
     int32_t graph_iters;     /* iterations per captured HIP graph; 0 = automatic */
-    double inner_tol;        /* PPCG_MIXED_FP32: relative reduction asked of each inner
-                                solve (PIPECG, 0 = 1e-3) or between reliable updates
-                                (classic PCG, 0 = 1e-2); PPCG_MIXED_FP32_VALUES:
-                                residual reduction between reliable updates (0 = 1e-3) */
+    double inner_tol;        /* residual reduction between reliable updates:
+                                PPCG_MIXED_FP32 (0 = 1e-2), PPCG_MIXED_FP32_VALUES
+                                (0 = 1e-3) */
     int32_t max_outer;       /* mixed precision: maximum refinement steps / reliable
                                 updates (default 30) */
     ppcg_method method;      /* default PPCG_METHOD_PIPECG */

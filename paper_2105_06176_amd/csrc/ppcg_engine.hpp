@@ -89,7 +89,7 @@ struct ppcg_handle {
     ppcg::DevArena mat_arena;
     ppcg::PrecData f64, f32;
     double *part = nullptr;   // 2 x ntiles x 4 partial sums (shared by both precisions)
-    double *part32 = nullptr; // partials of the FP32 inner solve
+    double *part32 = nullptr; // partials of the FP32-vector sequence
     double setup_ms = 0.0;
     ppcg::Engine *solo = nullptr;  // cached single-system engine
     // Single-system launch description for direct kernel calls (SpMV,
@@ -108,7 +108,7 @@ struct Job {
     int mixed = 0;          // 0 FP64, 1 FP32 inner PIPECG + FP64 refinement,
                             // 2 FP32 values + reliable updates (MixKind)
     int slot64 = -1;        // slot in the FP64 group (MIX_NONE, and the outer FP64 steps of MIX_INNER32)
-    int slot32 = -1;        // slot in the FP32-vector group (MIX_INNER32)
+    int slot32 = -1;        // slot in the FP32-vector classic-PCG group (MIX_INNER32)
     int slotv = -1;         // slot in the FP32-values group (MIX_VALUES32)
     int stage = 0;          // JobStage
     int restarts = 0;
@@ -138,7 +138,7 @@ enum JobStage {
     JS_NEED_INIT = 0,   // FP64 group: run the initialisation, then iterate
     JS_ITER = 1,        // iterating in the group's table
     JS_NEED_FINAL = 2,  // FP64 group: true residual, then restart / replace or finish
-    JS_OUTER = 3,       // MIX_INNER32: true residual of x, then finish or start an inner solve
+    JS_OUTER = 3,       // MIX_INNER32: true residual of x, then finish, or start / continue the FP32 sequence
     JS_NEED_REPL = 4,   // MIX_VALUES32: residual replacement (reliable update)
     JS_DONE = 5
 };
@@ -203,7 +203,7 @@ class Engine {
   private:
     ppcg_status ensure_group(Group &g, int prec, int cap_sys);
     ppcg_status upload_desc(Group &g, int slot);
-    // `inner`: the group of the FP32 inner solves (AUX_MIX_START, AUX_MIX_CORRECT)
+    // `inner`: the group of the FP32 sequences (AUX_MIX_START, AUX_MIX_CORRECT)
     ppcg_status aux_launch(Group &g, const std::vector<int> &slots, int what, const Group *inner = nullptr);
     ppcg_status ensure_table(Group &g);
     ppcg_status ensure_graph(Group &g, int iters, hipGraphExec_t *exec);
@@ -213,13 +213,11 @@ class Engine {
     Group &pgroup(const Job &j)
     {
         if (j.mixed == MIX_INNER32)
-            return inner32(j);
+            return gp32_;
         if (j.pcg)
             return j.mixed == MIX_VALUES32 ? gpv_ : gp_;
         return j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
     }
-    // group of a mixed-precision job's FP32 inner solves
-    Group &inner32(const Job &j) { return j.pcg ? gp32_ : g32_; }
     int pslot(const Job &j) const { return j.mixed == MIX_INNER32 ? j.slot32 : j.mixed == MIX_VALUES32 ? j.slotv : j.slot64; }
     ppcg_status sync_states(Group &g);
     int alloc_slot(Group &g);
@@ -228,12 +226,12 @@ class Engine {
     // the tables and auxiliary work, joined back before the poll), so the
     // groups' launches overlap: the one-workgroup small-system kernel and the
     // graphs of groups holding systems of different precision or method.
-    static constexpr int kGroups = 7;
+    static constexpr int kGroups = 6;
     hipStream_t gstream_[kGroups] = {};
     hipEvent_t ev_fork_ = nullptr;
     hipEvent_t ev_join_[kGroups] = {};
-    Group g64_, g32_, gv_, gs_;  // FP64, FP32 vectors, FP32 values, small FP64 systems
-    Group gp_, gpv_, gp32_;      // classic PCG: FP64, FP32 values, FP32 vectors (inner solves)
+    Group g64_, gv_, gs_;   // FP64 (and the FP64 steps of FP32-vector jobs), FP32 values, small systems
+    Group gp_, gpv_, gp32_; // classic PCG: FP64, FP32 values, FP32 vectors
     std::vector<Job> jobs_;
 };
 

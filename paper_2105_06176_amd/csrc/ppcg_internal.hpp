@@ -34,14 +34,15 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 #define PPCG_XCD_REMAP_SPMV 0
 #endif
 
-// Systems with at most this many rows (SELL format, FP64) iterate in the
-// one-workgroup kernel: for them launch latency, not bandwidth, dominates.
-// 1: build 16-bit SELL column offsets when they fit and let the SpMV read
-// them.  Off: measured slower on gfx950 (sub-dword loads), see the notes.
+// 1: for SELL matrices whose column offsets from the row fit 16 bits, time
+// the SpMV with 16-bit offsets against 32-bit columns at setup and keep the
+// faster (0: 32-bit columns only).
 #ifndef PPCG_SELL_COL16
-#define PPCG_SELL_COL16 0
+#define PPCG_SELL_COL16 1
 #endif
 
+// Systems with at most this many rows (SELL format, FP64) iterate in the
+// one-workgroup kernel: for them launch latency, not bandwidth, dominates.
 #ifndef PPCG_SMALL_MAX_ROWS
 #define PPCG_SMALL_MAX_ROWS 4096
 #endif

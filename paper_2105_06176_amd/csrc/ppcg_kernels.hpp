@@ -472,7 +472,35 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
     }
 }
 
-// The same with 16-bit column offsets from the row (col = row + offset).
+// Column indices of entries k0 .. k0 + B - 1 of one SELL row from 16-bit
+// offsets stored in pairs (see k_sell_delta16): entries 2j and 2j + 1 of the
+// lane come in one dword, the last entry of an odd-length chunk as one short.
+// base: the chunk's first slot, len: its padded length (uniform over the
+// wavefront, so the guards are uniform branches), row: the stored row.
+// Entries past len get the row itself (a valid index, never used).
+template <int B>
+__device__ __forceinline__ void sell_cols16(const short *__restrict__ col16, int64_t base, int len, int k0, int lane,
+                                            int row, int (&cc)[B])
+{
+    static_assert(B % 2 == 0, "batches hold whole pairs");
+    const int paired = len & ~1;
+    const unsigned *cp = (const unsigned *)(col16 + base) + lane;   // pair j at cp[j * 64]
+#pragma unroll
+    for (int t = 0; t < B / 2; ++t) {
+        const int k = k0 + 2 * t;
+        cc[2 * t] = row;
+        cc[2 * t + 1] = row;
+        if (k + 1 < len) {
+            const unsigned pr = stream_load(cp + (size_t)(k >> 1) * kSellC);
+            cc[2 * t] = row + (int)(short)(pr & 0xffffu);
+            cc[2 * t + 1] = row + ((int)pr >> 16);
+        } else if (k < len) {
+            cc[2 * t] = row + (int)stream_load(col16 + base + (size_t)paired * kSellC + lane);
+        }
+    }
+}
+
+// sell_row with 16-bit column offsets from the row.
 template <typename VT, typename T, int NX>
 __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, const short *__restrict__ col16,
                                            const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
@@ -482,7 +510,6 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
     const int64_t base = cptr[chunk];
     const int len = (int)((cptr[chunk + 1] - base) / kSellC);
     const int row = chunk * kSellC + lane;
-    const short *c = col16 + base + lane;
     const VT *v = val + base + lane;
 #pragma unroll
     for (int q = 0; q < NX; ++q)
@@ -490,14 +517,12 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
     for (int k0 = 0; k0 < len; k0 += B) {
         int cc[B];
         VT vv[B];
+        sell_cols16<B>(col16, base, len, k0, lane, row, cc);
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-            cc[j] = row;
             vv[j] = (VT)0;
-            if (k0 + j < len) {
-                cc[j] = row + (int)stream_load(c + (size_t)(k0 + j) * kSellC);
+            if (k0 + j < len)
                 vv[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
-            }
         }
 #pragma unroll
         for (int q = 0; q < NX; ++q) {
@@ -772,50 +797,6 @@ __global__ __launch_bounds__(kSpmvThreads) void k_reduce_resid(const WorkItem *_
     if (threadIdx.x == 0) {
         d.st->tnorm2 = v[0];
         d.st->bnorm2 = v[1];
-    }
-}
-
-// Mixed precision, start of an inner solve: b32 = r64 / ||r64||, x32 = 0.
-// Work items name FP64 slots; SysDesc::pair is the FP32 slot of the system.
-__global__ void k_mix_start(const WorkItem *__restrict__ table, const int *__restrict__ count,
-                            const SysDesc *__restrict__ d64, const SysDesc *__restrict__ d32)
-{
-    const int pos = blockIdx.x;
-    if (pos >= *count)
-        return;
-    const WorkItem wi = table[pos];
-    const SysDesc &a = d64[wi.slot];
-    const SysDesc &f = d32[a.pair];
-    const double inv = 1.0 / sqrt(a.st->tnorm2);
-    const double *__restrict__ r = (const double *)a.r;
-    float *__restrict__ b32 = (float *)f.b;
-    float *__restrict__ x32 = (float *)f.x;
-    for (int k = threadIdx.x; k < kTileRows; k += blockDim.x) {
-        const int i = wi.tile * kTileRows + k;
-        if (i < a.n) {
-            b32[i] = (float)(r[i] * inv);
-            x32[i] = 0.0f;
-        }
-    }
-}
-
-// Mixed precision, end of an inner solve: x64 += ||r64|| * x32.
-__global__ void k_mix_correct(const WorkItem *__restrict__ table, const int *__restrict__ count,
-                              const SysDesc *__restrict__ d64, const SysDesc *__restrict__ d32)
-{
-    const int pos = blockIdx.x;
-    if (pos >= *count)
-        return;
-    const WorkItem wi = table[pos];
-    const SysDesc &a = d64[wi.slot];
-    const SysDesc &f = d32[a.pair];
-    const double rn = sqrt(a.st->tnorm2);
-    double *__restrict__ x = (double *)a.x;
-    const float *__restrict__ x32 = (const float *)f.x;
-    for (int k = threadIdx.x; k < kTileRows; k += blockDim.x) {
-        const int i = wi.tile * kTileRows + k;
-        if (i < a.n)
-            x[i] = x[i] + rn * (double)x32[i];
     }
 }
 

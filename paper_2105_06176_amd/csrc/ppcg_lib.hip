@@ -137,13 +137,15 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     const double ve = prec == PREC_F32 ? 4.0 : 8.0;   // vector element
     const double me = prec == PREC_F64 ? 8.0 : 4.0;   // matrix value
     const double n = h->n;
-    const bool pcg = h->opt.method == PPCG_METHOD_PCG;
+    // FP32 vectors always iterate with Algorithm 1
+    const bool pcg = h->opt.method == PPCG_METHOD_PCG || prec == PREC_F32;
     ByteModel bm;
     // a constant diagonal is read as one scalar: one vector stream fewer
     bm.vma = ((pcg ? 8.0 : 15.0) - (h->dinv_const ? 1.0 : 0.0)) * ve * n;
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
-    // the PIPECG SpMV reads 16-bit column offsets when the matrix has them
-    const double ie = (h->col16 && !pcg) ? 2.0 : 4.0;
+    // the SpMVs read 16-bit column offsets when the matrix has them (not the
+    // classic-PCG SpMV with FP32 values and FP64 vectors)
+    const double ie = (h->col16 && !(pcg && prec == PREC_V32)) ? 2.0 : 4.0;
     bm.spmv = (me + ie) * (double)h->nnz + ptr + (pcg ? 4.0 : 2.0) * ve * n;
     return bm;
 }
@@ -253,6 +255,7 @@ struct TuneKey {
 };
 struct TuneVal {
     int fmt, sigma, lanes;
+    int col16;  // SELL: 1 when the 16-bit column offsets timed faster
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneVal> g_tune_cache;
@@ -400,10 +403,15 @@ static ppcg_status adopt_sell(ppcg_handle *h, SellBuild &sb)
     h->perm = sb.perm;
     h->invperm = sb.invperm;
     sb = SellBuild();
-    if (!PPCG_SELL_COL16)
-        return PPCG_OK;
-    // 16-bit column offsets from the row when they all fit (banded matrices,
-    // stencils whose plane has at most 32767 points): half the index bytes.
+    return PPCG_OK;
+}
+
+// 16-bit column offsets from the row, when every one fits (banded matrices,
+// stencils whose plane has at most 32767 points): half the index bytes.
+// Sets *built; a matrix whose offsets do not fit keeps its 32-bit columns.
+static ppcg_status build_col16(ppcg_handle *h, bool *built)
+{
+    *built = false;
     short *c16 = nullptr;
     unsigned *flag = nullptr;
     unsigned nofit = 1u;
@@ -430,6 +438,50 @@ static ppcg_status adopt_sell(ppcg_handle *h, SellBuild &sb)
     }
     PPCG_HIP(e);
     h->col16 = c16;
+    *built = c16 != nullptr;
+    return PPCG_OK;
+}
+
+static void drop_col16(ppcg_handle *h)
+{
+    if (h->col16)
+        (void)hipFree(h->col16);
+    h->col16 = nullptr;
+}
+
+static ppcg_status time_spmv(ppcg_handle *h, int reps, double *ms);
+
+// SELL: whether the SpMVs read 16-bit column offsets.  They halve the index
+// bytes but cost an unpack per entry pair and a sub-dword load for an odd
+// tail; on gfx950 that wins for long rows (27-point stencils) and loses for
+// short ones (7-point), so both are timed on the matrix (five SpMVs each,
+// after a warm-up) and the faster is kept.  `known` >= 0 replays a cached
+// decision; PPCG_FLAG_SELL_COL16 / _COL32 force the choice.  Off entirely
+// when PPCG_SELL_COL16 is 0.
+static ppcg_status tune_col16(ppcg_handle *h, int known, int *chosen)
+{
+    *chosen = 0;
+    if (h->opt.flags & PPCG_FLAG_SELL_COL16)
+        known = 1;
+    else if (h->opt.flags & PPCG_FLAG_SELL_COL32)
+        known = 0;
+    if (!PPCG_SELL_COL16 || h->fmt != FMT_SELL || known == 0)
+        return PPCG_OK;
+    double t32 = 0.0, t16 = 0.0;
+    if (known < 0)
+        PPCG_TRY(time_spmv(h, 5, &t32));
+    bool built = false;
+    PPCG_TRY(build_col16(h, &built));
+    if (!built)
+        return PPCG_OK;
+    if (known < 0) {
+        PPCG_TRY(time_spmv(h, 5, &t16));
+        if (!(t16 < 0.99 * t32)) {
+            drop_col16(h);
+            return PPCG_OK;
+        }
+    }
+    *chosen = 1;
     return PPCG_OK;
 }
 
@@ -468,6 +520,8 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
                                  const double *dinv_orig, const std::vector<int> &rowlen_h)
 {
     const ppcg_spmv_format want = h->opt.spmv_format;
+    // a forced 16-bit column choice is not a timing result: not cached
+    const bool forced16 = (h->opt.flags & (PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32)) != 0;
     // Row-length statistics.
     double sum = 0, sum2 = 0;
     int mx = 0;
@@ -492,11 +546,12 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
         SellBuild sb;
         PPCG_TRY(build_sell(h->stream, h->n, sigma, rp, ci, val, rowlen, &sb));
         PPCG_TRY(adopt_sell(h, sb));
-        return bind_f64(h, dinv_orig);
+        PPCG_TRY(bind_f64(h, dinv_orig));
+        int c16 = 0;
+        return tune_col16(h, -1, &c16);
     }
     if (want == PPCG_SPMV_CSR_VECTOR) {
-        const int lanes = h->opt.flags ? 0 : pow2_near(mean / 2);
-        PPCG_TRY(adopt_csrv(h, lanes ? lanes : 8, rp, ci, val));
+        PPCG_TRY(adopt_csrv(h, pow2_near(mean / 2), rp, ci, val));
         return bind_f64(h, dinv_orig);
     }
     TuneKey key{(int)std::log2((double)h->n), (int)std::lround(mean), (int)std::lround(10 * cv),
@@ -513,7 +568,12 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
             } else {
                 PPCG_TRY(adopt_csrv(h, tv.lanes, rp, ci, val));
             }
-            return bind_f64(h, dinv_orig);
+            PPCG_TRY(bind_f64(h, dinv_orig));
+            int c16 = 0;
+            PPCG_TRY(tune_col16(h, tv.col16, &c16));
+            if (tv.col16 < 0 && !forced16)
+                it->second.col16 = c16;  // timed now (the entry came from a forced choice)
+            return PPCG_OK;
         }
     }
     struct Cand {
@@ -549,10 +609,6 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
             bestc = c;
         }
     }
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = {bestc.fmt, bestc.sigma, bestc.lanes};
-    }
     const Cand &last = cands.back();
     if (!(last.fmt == bestc.fmt && last.sigma == bestc.sigma && last.lanes == bestc.lanes)) {
         if (bestc.fmt == FMT_SELL) {
@@ -563,7 +619,14 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
             PPCG_TRY(adopt_csrv(h, bestc.lanes, rp, ci, val));
         }
     }
-    return bind_f64(h, dinv_orig);
+    PPCG_TRY(bind_f64(h, dinv_orig));
+    int c16 = 0;
+    PPCG_TRY(tune_col16(h, -1, &c16));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {bestc.fmt, bestc.sigma, bestc.lanes, forced16 ? -1 : c16};
+    }
+    return PPCG_OK;
 }
 
 // Allocate the FP64 solver vectors and partial sums.
@@ -593,7 +656,7 @@ ppcg_status ensure_val32(ppcg_handle *h)
     return PPCG_OK;
 }
 
-// FP32 vectors for the restarted mixed-precision inner solve.
+// FP32 vectors and values for the FP32 mixed-precision sequence.
 ppcg_status ensure_f32(ppcg_handle *h)
 {
     if (h->f32.ready)
@@ -628,7 +691,7 @@ Engine::~Engine()
         if (ev_join_[k]) (void)hipEventDestroy(ev_join_[k]);
     }
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
-    for (Group *g : {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_, &gp32_}) {
+    for (Group *g : {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)hipFree(g->desc_d);
         if (g->st_d) (void)hipFree(g->st_d);
@@ -676,7 +739,6 @@ ppcg_status Engine::init(int cap_sys)
         }
     }
     PPCG_TRY(ensure_group(g64_, PREC_F64, cap_sys));
-    PPCG_TRY(ensure_group(g32_, PREC_F32, cap_sys));
     PPCG_TRY(ensure_group(gv_, PREC_V32, cap_sys));
     PPCG_TRY(ensure_group(gs_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(gp_, PREC_F64, cap_sys));
@@ -758,9 +820,6 @@ static void launch_iter_pair(hipStream_t s, const Group &g, int grid, int remap)
         else
             k_pcg_vma<double><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
         k_pcg_update<PCG_ITER><<<sg, kPcgRedThreads, 0, s>>>(g.sys_d, g.sys_count_d, g.desc_d);
-    } else if (g.prec == PREC_F32) {
-        k_vma<float><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
-        k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
     } else if (g.prec == PREC_V32) {
         k_vma<double, true><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
         k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
@@ -930,20 +989,11 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
         }
         k_pcg_update<PCG_REPL><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_INIT) {
-        if (f32) {
-            k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-            k_spmv<float, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-            k_spmv<float, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        } else {
-            k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-            k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-            k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        }
+        k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
     } else if (what == AUX_RESID) {
-        if (f32)
-            k_spmv<float, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        else
-            k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
         k_reduce_resid<<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_REPL) {
         // Reliable update: FP64 residual, then the rebuilt auxiliaries (two
@@ -952,15 +1002,9 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
         k_spmv<double, MODE_DUAL1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
         k_spmv<double, MODE_DUAL2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
     } else if (what == AUX_MIX_START) {
-        if (inner->pcg)
-            k_pcg_mix_start<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
-        else
-            k_mix_start<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
+        k_pcg_mix_start<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
     } else if (what == AUX_MIX_CORRECT) {
-        if (inner->pcg)
-            k_pcg_mix_correct<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
-        else
-            k_mix_correct<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
+        k_pcg_mix_correct<<<grid, 256, 0, s>>>(tab, cnt, g64_.desc_d, inner->desc_d);
     }
     PPCG_HIP(hipGetLastError());
     return PPCG_OK;
@@ -977,14 +1021,17 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
     const int stop = o.stop == PPCG_STOP_PRECOND_ABS ? STOP_ABS : STOP_REL;
     auto release = [&]() {
         if (j.slot64 >= 0) g64_.slot_used[j.slot64] = 0;
-        if (j.slot32 >= 0) inner32(j).slot_used[j.slot32] = 0;
+        if (j.slot32 >= 0) gp32_.slot_used[j.slot32] = 0;
         if (j.slotv >= 0) gv_.slot_used[j.slotv] = 0;
     };
     auto fail = [&](ppcg_status s) {
         release();
         return s;
     };
-    if (o.method == PPCG_METHOD_PCG)
+    // FP32 vectors always iterate with Algorithm 1: the pipelined method's
+    // auxiliary recurrences (w, z, s) drift away from A u, A q, A p within a
+    // few dozen FP32 iterations, even with the other vectors recomputed
+    if (o.method == PPCG_METHOD_PCG || mixed == MIX_INNER32)
         j.pcg = true;
     if (j.pcg && mixed != MIX_INNER32) {
         const bool v32 = mixed == MIX_VALUES32;
@@ -1054,24 +1101,20 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
             rc = ensure_f32(h);
             if (rc != PPCG_OK)
                 return fail(rc);
-            // inner solves: Algorithm 2 (or Algorithm 1 when classic PCG
-            // is selected) in FP32
-            Group &gi = inner32(j);
+            // the FP32 sequence (Algorithm 1)
+            Group &gi = gp32_;
             j.slot32 = alloc_slot(gi);
             if (j.slot32 < 0) {
                 set_error("engine has no free slot");
                 return fail(PPCG_ERR_INVALID_ARG);
             }
-            const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
-            rc = fill_desc(h, PREC_F32, gi.st_d + j.slot32, &gi.desc_h[j.slot32], itol, 0, o.max_iter, STOP_REL);
+            // its own stop (the FP64 target in the units of the current
+            // scaling) is set at every start; it pauses for a reliable update
+            // whenever its residual fell by inner_tol
+            rc = fill_desc(h, PREC_F32, gi.st_d + j.slot32, &gi.desc_h[j.slot32], tol, 0, o.max_iter, STOP_REL);
             if (rc != PPCG_OK)
                 return fail(rc);
-            if (j.pcg) {
-                // one FP32 sequence, paused for a reliable update whenever the
-                // residual fell by inner_tol; its own stop (the FP64 target in
-                // the units of the current scaling) is set at every start
-                gi.desc_h[j.slot32].repl_factor = o.inner_tol > 0 ? o.inner_tol : kPcgMixReplFactor;
-            }
+            gi.desc_h[j.slot32].repl_factor = o.inner_tol > 0 ? o.inner_tol : kPcgMixReplFactor;
             gi.desc_h[j.slot32].pair = j.slot64;
             g64_.desc_h[j.slot64].pair = j.slot32;
             PPCG_TRY(upload_desc(gi, j.slot32));
@@ -1119,7 +1162,7 @@ void Engine::retire(int id)
     if (j.slot64 >= 0)
         (j.pcg && j.mixed != MIX_INNER32 ? gp_ : j.small ? gs_ : g64_).slot_used[j.slot64] = 0;
     if (j.slot32 >= 0)
-        inner32(j).slot_used[j.slot32] = 0;
+        gp32_.slot_used[j.slot32] = 0;
     if (j.slotv >= 0)
         (j.pcg ? gpv_ : gv_).slot_used[j.slotv] = 0;
     j.slot64 = j.slot32 = j.slotv = -1;
@@ -1147,10 +1190,10 @@ constexpr int kSmallChunkIters = 512;
 ppcg_status Engine::step(int graph_iters)
 {
     // 1. Jobs that need a true residual: stopped FP64 / FP32-values jobs, and
-    //    FP32-vector jobs between inner solves (after adding the correction).
-    Group *const groups[] = {&g64_, &g32_, &gv_, &gs_, &gp_, &gpv_, &gp32_};
+    //    FP32-vector jobs at a pause of their sequence (after adding the correction).
+    Group *const groups[] = {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_};
     std::map<Group *, std::vector<int>> resid;  // slots per group
-    std::map<Group *, std::vector<int>> correct64;  // FP64 slots per inner group
+    std::vector<int> correct64;                 // FP64 slots of FP32-vector jobs
     for (Job &j : jobs_) {
         if (j.finished)
             continue;
@@ -1158,22 +1201,21 @@ ppcg_status Engine::step(int graph_iters)
             resid[&pgroup(j)].push_back(pslot(j));
         else if (j.stage == JS_OUTER) {
             if (j.outer > 0)
-                correct64[&inner32(j)].push_back(j.slot64);
+                correct64.push_back(j.slot64);
             resid[&g64_].push_back(j.slot64);
         }
     }
     if (!resid.empty()) {
-        for (auto &kv : correct64)
-            PPCG_TRY(aux_launch(g64_, kv.second, AUX_MIX_CORRECT, kv.first));
+        PPCG_TRY(aux_launch(g64_, correct64, AUX_MIX_CORRECT, &gp32_));
         for (Group *g : groups)
             if (resid.count(g)) {
                 PPCG_TRY(aux_launch(*g, resid[g], AUX_RESID));
                 PPCG_TRY(sync_states(*g));
             }
         PPCG_HIP(hipStreamSynchronize(stream_));
-        // FP64 slots per inner group: fresh inner starts, and reliable
-        // updates of continuing classic-PCG FP32 sequences
-        std::map<Group *, std::vector<int>> start_mix, repl_mix;
+        // FP64 slots of FP32-vector jobs: sequences to start, and sequences
+        // that continue after a reliable update
+        std::vector<int> start_mix, repl_mix;
         for (Job &j : jobs_) {
             if (j.finished || (j.stage != JS_NEED_FINAL && j.stage != JS_OUTER))
                 continue;
@@ -1224,45 +1266,28 @@ ppcg_status Engine::step(int graph_iters)
                     j.iters = j.inner_iters;
                     j.rel_recur = rel;
                 } else {
-                    Group &gi = inner32(j);
-                    SysDesc &di = gi.desc_h[j.slot32];
-                    if (j.pcg) {
-                        // the sequence continues (its counter runs on); it stops
-                        // by itself where the FP64 residual would reach tol:
-                        // ||r32|| <= tol ||b|| / ||r64|| on b32 = r64 / ||r64||
-                        di.tol = j.tol * bn / std::sqrt(st.tnorm2);
-                        if (j.outer > 0)
-                            repl_mix[&gi].push_back(j.slot64);
-                        else
-                            start_mix[&gi].push_back(j.slot64);
-                    } else {
-                        di.maxit = o.max_iter - j.inner_iters;  // inner budget: what is left
-                        start_mix[&gi].push_back(j.slot64);
-                    }
-                    PPCG_TRY(upload_desc(gi, j.slot32));
+                    // the sequence continues (its counter runs on); it stops
+                    // by itself where the FP64 residual would reach tol:
+                    // ||r32|| <= tol ||b|| / ||r64|| on b32 = r64 / ||r64||
+                    gp32_.desc_h[j.slot32].tol = j.tol * bn / std::sqrt(st.tnorm2);
+                    (j.outer > 0 ? repl_mix : start_mix).push_back(j.slot64);
+                    PPCG_TRY(upload_desc(gp32_, j.slot32));
                     j.stage = JS_ITER;
                     ++j.outer;
                 }
             }
         }
-        for (auto &kv : start_mix) {
-            Group &gi = *kv.first;
-            PPCG_TRY(aux_launch(g64_, kv.second, AUX_MIX_START, &gi));
+        // the slot state was cleared when the job was added, so a first
+        // start finds no live direction to rescale
+        for (int pass = 0; pass < 2; ++pass) {
+            const std::vector<int> &sl64 = pass == 0 ? start_mix : repl_mix;
+            if (sl64.empty())
+                continue;
+            PPCG_TRY(aux_launch(g64_, sl64, AUX_MIX_START, &gp32_));
             std::vector<int> s32;
-            for (int sl : kv.second) {
+            for (int sl : sl64)
                 s32.push_back(g64_.desc_h[sl].pair);
-                // every inner solve counts its iterations from zero
-                PPCG_HIP(hipMemsetAsync(gi.st_d + s32.back(), 0, sizeof(SysState), stream_));
-            }
-            PPCG_TRY(aux_launch(gi, s32, AUX_INIT));
-        }
-        for (auto &kv : repl_mix) {
-            Group &gi = *kv.first;
-            PPCG_TRY(aux_launch(g64_, kv.second, AUX_MIX_START, &gi));
-            std::vector<int> s32;
-            for (int sl : kv.second)
-                s32.push_back(g64_.desc_h[sl].pair);
-            PPCG_TRY(aux_launch(gi, s32, AUX_REPL));
+            PPCG_TRY(aux_launch(gp32_, s32, pass == 0 ? AUX_INIT : AUX_REPL));
         }
     }
     // 2. Initialisations and reliable updates.
@@ -1365,8 +1390,7 @@ ppcg_status Engine::step(int graph_iters)
         if (st.done) {
             j.last_norm = -1.0;
             if (j.mixed == MIX_INNER32) {
-                // a continuing classic-PCG sequence counts all its iterations
-                j.inner_iters = j.pcg ? st.iter : j.inner_iters + st.iter;
+                j.inner_iters = st.iter;  // the sequence's counter runs across reliable updates
                 j.precond_norm = std::sqrt(st.uu);
                 j.stage = JS_OUTER;
             } else if (st.status == ST_REPLACE) {
@@ -1456,7 +1480,7 @@ void fill_info(const ppcg_handle *h, const Job &j, ppcg_info *info)
     const ByteModel bm = byte_model(h, j.mixed == MIX_INNER32 ? PREC_F32 : j.mixed == MIX_VALUES32 ? PREC_V32 : PREC_F64);
     info->model_bytes = (bm.vma + bm.spmv) * j.iters;
     info->precision = h->opt.precision;
-    info->method = h->opt.method;
+    info->method = j.pcg ? PPCG_METHOD_PCG : PPCG_METHOD_PIPECG;
 }
 
 // Order the internal stream after all work already queued on the caller's
@@ -1549,7 +1573,8 @@ static ppcg_status check_options(const ppcg_options *o)
         (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
          o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
         (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
-        (o->flags & ~PPCG_FLAG_BORROW_INPUTS) != 0) {
+        (o->flags & ~(PPCG_FLAG_BORROW_INPUTS | PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32)) != 0 ||
+        ((o->flags & PPCG_FLAG_SELL_COL16) && (o->flags & PPCG_FLAG_SELL_COL32))) {
         set_error("invalid option value");
         return PPCG_ERR_INVALID_ARG;
     }
@@ -1889,7 +1914,8 @@ ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
                        (h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (h->n + 1)) +
                        (h->perm ? 8.0 * h->n : 0.0) + (h->col16 ? 2.0 * (double)h->nnz_stored : 0.0);
     mi->setup_ms = h->setup_ms;
-    mi->col_index_bytes = (h->col16 && h->opt.method != PPCG_METHOD_PCG) ? 2 : 4;
+    mi->col_index_bytes =
+        (h->col16 && !(h->opt.method == PPCG_METHOD_PCG && h->opt.precision == PPCG_MIXED_FP32_VALUES)) ? 2 : 4;
     mi->diag_const = h->dinv_const ? 1 : 0;
     return PPCG_OK;
 }

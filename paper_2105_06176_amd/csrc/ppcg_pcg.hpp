@@ -22,8 +22,9 @@
 // reads buffer k mod 2 (p for even, z for odd) and writes the other.
 //
 // The kernels are templated on the vector type T: double for the FP64 and
-// FP32-values modes, float for the inner solves of the FP32 mixed-precision
-// mode (FP32 vectors and values, FP64 dot-product accumulation and scalars).
+// FP32-values modes, float for the FP32 mixed-precision mode (FP32 vectors
+// and values, FP64 dot-product accumulation and scalars), which always
+// iterates with Algorithm 1.
 //
 // FP32 mixed-precision mode (d.prec == PREC_F32): one Algorithm 1 sequence
 // in FP32 on the scaled system A y = r64 / ||r64||, paused like the
@@ -93,6 +94,51 @@ __device__ __forceinline__ T *pcg_dir(const SysDesc &d, int k)
     return (T *)((k & 1) ? d.z : d.p);
 }
 
+// One SELL row of s = A p with p = u + beta p_old formed per gathered entry.
+// C16: 16-bit column offsets (the SELL pair layout) instead of 32-bit columns.
+template <bool C16, typename T, typename VT>
+__device__ __forceinline__ T pcg_sell_row(const SysDesc &d, const VT *__restrict__ val, int chunk, int lane,
+                                          T beta, const T *__restrict__ U, const T *__restrict__ Pold)
+{
+    constexpr int B = 8;
+    const int64_t base = d.cptr[chunk];
+    const int len = (int)((d.cptr[chunk + 1] - base) / kSellC);
+    const int *c = d.col + base + lane;
+    const VT *v = val + base + lane;
+    T y = 0;
+    for (int k0 = 0; k0 < len; k0 += B) {
+        int cc[B];
+        T vv[B], xx[B];
+        if constexpr (C16) {
+            sell_cols16<B>(d.col16, base, len, k0, lane, chunk * kSellC + lane, cc);
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                vv[j] = 0;
+                if (k0 + j < len)
+                    vv[j] = (T)stream_load(v + (size_t)(k0 + j) * kSellC);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                cc[j] = 0;
+                vv[j] = 0;
+                if (k0 + j < len) {
+                    cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
+                    vv[j] = (T)stream_load(v + (size_t)(k0 + j) * kSellC);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+            xx[j] = k0 + j < len ? U[cc[j]] + beta * Pold[cc[j]] : (T)0;
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+            if (k0 + j < len)
+                y = y + vv[j] * xx[j];
+    }
+    return y;
+}
+
 // s = A p for one tile with p = u + beta p_old formed per gathered entry;
 // returns this thread's share of (s, p).
 template <typename T, typename VT>
@@ -107,32 +153,11 @@ __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem
         const int chunk = wi.tile * kSellChunksPerTile + (threadIdx.x >> 6);
         const int i = chunk * kSellC + lane;
         if (chunk * kSellC < n) {
-            constexpr int B = 8;
-            const int64_t base = d.cptr[chunk];
-            const int len = (int)((d.cptr[chunk + 1] - base) / kSellC);
-            const int *c = d.col + base + lane;
-            const VT *v = val + base + lane;
-            T y = 0;
-            for (int k0 = 0; k0 < len; k0 += B) {
-                int cc[B];
-                T vv[B], xx[B];
-#pragma unroll
-                for (int j = 0; j < B; ++j) {
-                    cc[j] = 0;
-                    vv[j] = 0;
-                    if (k0 + j < len) {
-                        cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
-                        vv[j] = (T)stream_load(v + (size_t)(k0 + j) * kSellC);
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < B; ++j)
-                    xx[j] = k0 + j < len ? U[cc[j]] + beta * Pold[cc[j]] : (T)0;
-#pragma unroll
-                for (int j = 0; j < B; ++j)
-                    if (k0 + j < len)
-                        y = y + vv[j] * xx[j];
-            }
+            // 16-bit columns measured slower for FP32 values with FP64
+            // vectors (27-point case, 263 vs 242 ms), so that mix reads 32-bit ones
+            const bool c16 = d.col16 && !(sizeof(T) == 8 && sizeof(VT) == 4);
+            const T y = c16 ? pcg_sell_row<true>(d, val, chunk, lane, beta, U, Pold)
+                            : pcg_sell_row<false>(d, val, chunk, lane, beta, U, Pold);
             if (i < n) {
                 const T pn = U[i] + beta * Pold[i];
                 Pnew[i] = pn;

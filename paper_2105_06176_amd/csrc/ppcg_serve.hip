@@ -209,17 +209,17 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
     const bool auto_prec = precision == PPCG_PRECISION_AUTO;
     ppcg_method method = s->defaults.method;
     if (auto_prec) {
-        // bytes of one iteration: FP64 PIPECG 12 per stored entry plus 22
+        // bytes of one iteration: FP64 PIPECG 12 per stored entry plus 17
         // FP64 vector streams per row; FP32 values 8 per entry; classic PCG
         // in FP32 8 per entry plus 12 FP32 vector streams per row, with two
         // more launches per iteration (one-workgroup reductions), so it is
         // taken only where the bytes saved clearly outweigh them; below
         // 65536 rows launch latency, not bytes, sets the time
-        const double b64 = 12.0 * (double)A->nnz + 176.0 * A->n;
-        const double bv32 = 8.0 * (double)A->nnz + 176.0 * A->n;
+        const double b64 = 12.0 * (double)A->nnz + 136.0 * A->n;
+        const double bv32 = 8.0 * (double)A->nnz + 136.0 * A->n;
         const double bp32 = 8.0 * (double)A->nnz + 48.0 * A->n;
         if (A->n >= kAutoPcg32Rows && bp32 <= 0.7 * b64) {
-            precision = PPCG_MIXED_FP32;
+            precision = PPCG_MIXED_FP32;  // always Algorithm 1
             method = PPCG_METHOD_PCG;
         } else if (A->n >= kAutoValues32Rows && bv32 <= 0.95 * b64) {
             precision = PPCG_MIXED_FP32_VALUES;

@@ -234,8 +234,13 @@ __global__ void k_const_check(int n, const double *__restrict__ dinv, unsigned *
 
 namespace ppcg {
 
-// SELL column indices as 16-bit offsets from the (stored) row: col16 = col -
-// row for every stored entry; flag[0] |= 1 when some offset does not fit.
+// SELL column indices as 16-bit offsets from the (stored) row, d = col - row,
+// laid out so that a lane reads two of its entries with one dword load: in a
+// chunk of padded length len (base = cptr[c], in 16-bit units), entries 2j
+// and 2j + 1 of lane l sit at base + 128 j + 2 l and base + 128 j + 2 l + 1;
+// when len is odd the last entry sits at base + 128 (len / 2) + l.  A chunk
+// still takes 64 len slots, and base is a multiple of 64, so the pair dwords
+// are aligned.  flag[0] |= 1 when some offset does not fit 16 bits.
 __global__ void k_sell_delta16(int nchunks, const int64_t *__restrict__ cptr, const int *__restrict__ col,
                                short *__restrict__ col16, unsigned *__restrict__ flag)
 {
@@ -246,12 +251,15 @@ __global__ void k_sell_delta16(int nchunks, const int64_t *__restrict__ cptr, co
     const int row = c * kSellC + l;
     const int64_t base = cptr[c];
     const int len = (int)((cptr[c + 1] - base) / kSellC);
+    const int paired = len & ~1;
     bool ok = true;
     for (int k = 0; k < len; ++k) {
         const size_t o = (size_t)base + (size_t)k * kSellC + l;
         const int d = col[o] - row;
         ok = ok && d >= -32768 && d <= 32767;
-        col16[o] = (short)d;
+        const size_t dst = k < paired ? (size_t)base + (size_t)(k >> 1) * (2 * kSellC) + 2 * l + (k & 1)
+                                      : (size_t)base + (size_t)paired * kSellC + l;
+        col16[dst] = (short)d;
     }
     if (!ok)
         atomicOr(flag, 1u);

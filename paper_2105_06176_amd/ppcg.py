@@ -22,7 +22,7 @@ STOP_REL_RESID, STOP_PRECOND_ABS = 0, 1
 FP64, MIXED_FP32, MIXED_FP32_VALUES, PRECISION_AUTO = 0, 1, 2, 3
 MEM_DEVICE, MEM_HOST = 0, 1
 METHOD_PIPECG, METHOD_PCG = 0, 1
-FLAG_BORROW_INPUTS = 1
+FLAG_BORROW_INPUTS, FLAG_SELL_COL16, FLAG_SELL_COL32 = 1, 2, 4
 SPMV_AUTO, SPMV_SELL, SPMV_CSR_VECTOR = 0, 1, 2
 
 _STOP = {"rel": STOP_REL_RESID, "abs": STOP_PRECOND_ABS}

@@ -85,16 +85,26 @@ def test_spmv_sorted_sell_is_bitwise():
     assert np.array_equal(host(S.spmv(dev(x))), oracle.spmv(A, x))
 
 
-def test_storage_choices_keep_results_exact():
-    """16-bit column offsets are used when every offset fits and the constant
-    diagonal of a Poisson matrix is read as one value; neither changes a
-    single bit of the SpMV, and iterates still match the oracle."""
+@pytest.mark.parametrize("flags,expect16", [(ppcg.FLAG_SELL_COL16, True), (ppcg.FLAG_SELL_COL32, False),
+                                            (0, None)])
+def test_storage_choices_keep_results_exact(flags, expect16):
+    """16-bit column offsets are used when every offset fits (forced, refused,
+    or timed against 32-bit columns) and the constant diagonal of a Poisson
+    matrix is read as one value; neither changes a single bit of the SpMV,
+    and iterates still match the oracle.  The 27-point rows (odd length 27)
+    and the ragged random rows exercise the odd-tail entry of the paired
+    16-bit layout."""
     P = poisson3d(40)
     R = random_spd(70000, seed=1)  # random columns: offsets up to 70000, no 16-bit form
-    for A, bytes16, const in ((P, 2, 1), (R, 4, 0), (random_spd(5000, seed=9), 2, 0)):
-        S = Solver(A, spmv_format="sell")
+    for A, fits, const in ((P, True, 1), (R, False, 0), (random_spd(5000, seed=9), True, 0),
+                           (stencil27_lognormal(20, seed=3), True, 0)):
+        S = Solver(A, spmv_format="sell", flags=flags)
         mi = S.matrix_info()
-        assert mi["col_index_bytes"] in (bytes16, 4) and mi["diag_const"] == const, A.name
+        if expect16 is None or not fits:
+            assert mi["col_index_bytes"] in ((2, 4) if fits else (4,)), A.name
+        else:
+            assert mi["col_index_bytes"] == (2 if expect16 else 4), A.name
+        assert mi["diag_const"] == const, A.name
         x = xstar_uniform(A.n, 3)
         assert np.array_equal(host(S.spmv(dev(x))), oracle.spmv(A, x))
         b, _ = problem(A)
@@ -378,11 +388,14 @@ def test_batch_fixed_iterates_match_oracle():
 @pytest.mark.parametrize("gen", [lambda: stencil27_lognormal(16, seed=1), lambda: poisson2d(64),
                                  lambda: random_spd(20000, seed=3)])
 def test_mixed_precision_reaches_fp64_tolerance(gen):
+    """FP32 vectors and values with the default method: the library iterates
+    with Algorithm 1 (reported in the info) and reaches the FP64 tolerance."""
     A = gen()
     b, xs = problem(A)
     S = Solver(A, tol=1e-10, precision="mixed")
     x, info = S.solve(dev(b))
     assert info["status"] == ppcg.OK, info
+    assert info["method"] == ppcg.METHOD_PCG and info["precision"] == ppcg.MIXED_FP32
     assert info["outer_iters"] >= 1
     assert info["rel_resid_true"] <= 1e-10
     assert oracle.true_relres(A, b, host(x)) <= 1e-10
