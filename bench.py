@@ -276,27 +276,51 @@ def leg_shard(torch, ppcg, wl, parts=8):
 
 
 def leg_hybrid(torch, ppcg, wl, iters=200, threads=8):
-    """Host cores + GPU together (Section IV-C, Hybrid-PIPECG-3) on the 128^3
-    7-point problem: the performance model's split, forced splits, and the
-    rate against the GPU-only solver."""
-    A = wl.poisson3d(128)
-    b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
-    out = {"workload": f"3D 7-point Poisson 128^3, FP64, {iters} fixed iterations, {threads} host threads"}
-    for label, share in (("model", -1.0), ("share_0.02", 0.02), ("share_0", 0.0)):
-        H = ppcg.Hybrid(A, host_threads=threads, cpu_share=share, fixed_iters=20)
+    """Host cores + GPU together (Section IV) on the 128^3 7-point problem:
+    Hybrid-PIPECG-3 with the performance model's split and forced splits,
+    Hybrid-PIPECG-1 and -2 (task parallel, every row on the GPU), and, on a
+    32^3 problem where the paper found the task-parallel schemes best, all
+    three beside the GPU-only solver."""
+
+    def run(A, b, label, dst, **kw):
+        H = ppcg.Hybrid(A, host_threads=threads, fixed_iters=20, **kw)
         H.solve(b)
         H.close()
-        H = ppcg.Hybrid(A, host_threads=threads, cpu_share=share, fixed_iters=iters)
+        H = ppcg.Hybrid(A, host_threads=threads, fixed_iters=iters, **kw)
         t0 = time.perf_counter()
         x, info = H.solve(b)
         dt = time.perf_counter() - t0
         hi = H.info()
-        out[label] = {"iters_per_s": round(iters / dt, 1), "us_per_iter": round(dt / iters * 1e6, 1),
-                      "n_cpu": hi["n_cpu"], "n_gpu": hi["n_gpu"], "t_cpu_spmv_ms": round(hi["t_cpu_spmv_ms"], 3),
-                      "t_gpu_spmv_ms": round(hi["t_gpu_spmv_ms"], 4), "halo_to_cpu": hi["halo_to_cpu"],
-                      "halo_to_gpu": hi["halo_to_gpu"]}
-        log(f"hybrid {label}: {out[label]}")
+        dst[label] = {"iters_per_s": round(iters / dt, 1), "us_per_iter": round(dt / iters * 1e6, 1),
+                      "scheme": hi["scheme"], "n_cpu": hi["n_cpu"], "n_gpu": hi["n_gpu"],
+                      "t_cpu_spmv_ms": round(hi["t_cpu_spmv_ms"], 3), "t_gpu_spmv_ms": round(hi["t_gpu_spmv_ms"], 4),
+                      "copy_bytes_per_iter": hi["copy_bytes_per_iter"]}
+        log(f"hybrid {label}: {dst[label]}")
         H.close()
+
+    A = wl.poisson3d(128)
+    b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
+    out = {"workload": f"3D 7-point Poisson 128^3 (and 32^3), FP64, {iters} fixed iterations, {threads} host threads"}
+    for label, share in (("model", -1.0), ("share_0.02", 0.02), ("share_0", 0.0)):
+        run(A, b, label, out, cpu_share=share)
+    for scheme in (1, 2):
+        run(A, b, f"scheme{scheme}", out, scheme=scheme)
+    A = wl.poisson3d(32)
+    b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
+    small = {}
+    for scheme in (1, 2, 3):
+        run(A, b, f"scheme{scheme}", small, scheme=scheme)
+    S = ppcg.Solver(A, fixed_iters=iters)
+    bd = torch.as_tensor(b).cuda()
+    S.solve(bd)
+    sync()
+    t0 = time.perf_counter()
+    S.solve(bd)
+    sync()
+    dt = time.perf_counter() - t0
+    small["gpu_engine"] = {"iters_per_s": round(iters / dt, 1), "us_per_iter": round(dt / iters * 1e6, 1)}
+    S.close()
+    out["poisson3d_32"] = small
     return out
 
 

@@ -346,17 +346,33 @@ ppcg_status ppcg_shard_time(ppcg_shard *s, const double *x_global, const double 
 ppcg_status ppcg_shard_destroy(ppcg_shard *s); /* NULL-safe */
 
 /* ---------------------------------------------------------------------------
- * Host cores + GPU together (Section IV-C, Hybrid-PIPECG-3).  Setup times five
- * SpMVs over all of A on the host threads and on the GPU, splits the rows
- * with the performance model (ppcg_split_rows: rows [0, n_cpu) on the host,
- * the rest on the GPU) and builds both sides' 2-D decomposition.  Each
- * iteration of Algorithm 2 then follows the paper's execution flow: the m
- * entries each side needs from the other move (device <-> pinned host
+ * Host cores + GPU together (Section IV): Algorithm 2 in one of the paper's
+ * three execution schemes.  Alpha and beta are always computed on the host.
+ *
+ * PPCG_HYBRID_3 (Section IV-C, data parallel).  Setup times five SpMVs over
+ * all of A on the host threads and on the GPU, splits the rows with the
+ * performance model (ppcg_split_rows: rows [0, n_cpu) on the host, the rest
+ * on the GPU) and builds both sides' 2-D decomposition.  Each iteration: the
+ * m entries each side needs from the other move (device <-> pinned host
  * memory) while both sides update q, s, p, x, r, u and compute SpMV part 1;
  * part 2 runs once the copy has arrived; then z, w, m and the dot products;
- * the host adds both sides' partial sums and computes alpha and beta.
+ * the host adds both sides' partial sums.
+ *
+ * PPCG_HYBRID_1 and PPCG_HYBRID_2 (Sections IV-A, IV-B, task parallel): every
+ * row lives on the GPU, which runs all vector updates, the preconditioner and
+ * the SpMV.  Hybrid-1 copies w, r and u to pinned host memory after the
+ * updates, overlapping the GPU's preconditioner and SpMV, and host threads
+ * form gamma, delta and the norms from them.  Hybrid-2 copies only n: the host
+ * keeps full-length copies of z, q, s, r, u, w, m and repeats their updates,
+ * q, s, r, u and gamma while n is in flight, then z, w, m and delta.
  * ------------------------------------------------------------------------- */
 typedef struct ppcg_hybrid ppcg_hybrid; /* opaque, owned by the library */
+
+typedef enum {
+    PPCG_HYBRID_1 = 1, /* task parallel: w, r, u copied each iteration, dot products on the host */
+    PPCG_HYBRID_2 = 2, /* task parallel: n copied each iteration, host repeats the updates */
+    PPCG_HYBRID_3 = 3  /* data parallel: performance-model row split, 2-D decomposition */
+} ppcg_hybrid_scheme;
 
 typedef struct {
     size_t struct_size;       /* sizeof(ppcg_hybrid_info) */
@@ -369,18 +385,22 @@ typedef struct {
     int64_t nnz_cpu_remote;
     int64_t nnz_gpu_local;    /* GPU part 1 / part 2 entries */
     int64_t nnz_gpu_remote;
-    int32_t halo_to_cpu;      /* m entries copied GPU -> host per iteration */
-    int32_t halo_to_gpu;      /* m entries copied host -> GPU per iteration */
+    int32_t halo_to_cpu;      /* m entries copied GPU -> host per iteration (Hybrid-3) */
+    int32_t halo_to_gpu;      /* m entries copied host -> GPU per iteration (Hybrid-3) */
+    ppcg_hybrid_scheme scheme;
+    double copy_bytes_per_iter; /* device <-> host bytes per iteration (both directions) */
 } ppcg_hybrid_info;
 
 /* A: host CSR (read during the call).  opt: PPCG_FP64, PPCG_METHOD_PIPECG,
  * vec_mem = PPCG_MEM_HOST (b, x0, x are host arrays); tol, max_iter,
- * fixed_iters, max_restarts and stop as for ppcg_solve.  host_threads: 1..256.
- * cpu_share < 0: split by the performance model; 0 <= cpu_share <= 1: give
- * the host that share of the non-zeros instead (same row rule).  Errors:
- * ERR_INVALID_ARG, ERR_BAD_CSR, ERR_NOMEM, ERR_DEVICE. */
-ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, int32_t host_threads,
-                               double cpu_share, void *hip_stream, ppcg_hybrid **out);
+ * fixed_iters, max_restarts and stop as for ppcg_solve.  scheme: one of
+ * ppcg_hybrid_scheme.  host_threads: 1..256.  Hybrid-3: cpu_share < 0 splits
+ * by the performance model; 0 <= cpu_share <= 1 gives the host that share of
+ * the non-zeros instead (same row rule).  Hybrid-1/2: cpu_share must be < 0
+ * (every row is on the GPU).  Errors: ERR_INVALID_ARG, ERR_BAD_CSR,
+ * ERR_NOMEM, ERR_DEVICE. */
+ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, ppcg_hybrid_scheme scheme,
+                               int32_t host_threads, double cpu_share, void *hip_stream, ppcg_hybrid **out);
 ppcg_status ppcg_hybrid_get_info(const ppcg_hybrid *hy, ppcg_hybrid_info *info);
 /* b: host [n]; x0: host [n] or NULL (= 0); x: host [n], written; info may be
  * NULL.  Returns the solve status as ppcg_solve does. */

@@ -1,6 +1,9 @@
-// ppcg_hybrid.hip -- Algorithm 2 run by host cores and the GPU together, the
-// data-parallel scheme of Tiwari & Vadhiyar's Hybrid-PIPECG-3 (Section IV-C).
+// ppcg_hybrid.hip -- Algorithm 2 run by host cores and the GPU together, in
+// the three execution schemes of Tiwari & Vadhiyar (Section IV).  Most of this
+// file is the data-parallel Hybrid-PIPECG-3 (Section IV-C); the task-parallel
+// Hybrid-PIPECG-1 and -2 (Sections IV-A, IV-B) are solve_task below.
 //
+// Hybrid-PIPECG-3.
 // Setup: both sides time five SpMVs over all of A; the performance model
 // splits the rows (ppcg_split_rows): rows [0, ncpu) go to the host, the rest
 // to the GPU.  Each side's entries are split into part 1 (columns it owns)
@@ -302,6 +305,7 @@ struct HostCsr {
 
 struct ppcg_hybrid {
     int device = 0;
+    int scheme = PPCG_HYBRID_3;
     hipStream_t stream = nullptr;
     ppcg_options opt{};
     int n = 0, ncpu = 0, ngpu = 0;
@@ -327,6 +331,13 @@ struct ppcg_hybrid {
     double *pin_to_dev = nullptr;     // host-owned entries for the GPU [gs->halo]
     double *pin_red = nullptr;        // GPU scalars [4]
     hipEvent_t ev_halo = nullptr;
+    // Hybrid-1 / -2 (every row on the GPU): the copy stream, its events, the
+    // pinned copies (Hybrid-1: w, r, u; Hybrid-2: n) and Hybrid-2's host
+    // vectors
+    hipStream_t cstream = nullptr;
+    hipEvent_t ev_upd = nullptr, ev_copy = nullptr;
+    double *pin_vec = nullptr;
+    std::vector<int> full_lo;         // per host thread: first row of [0, n)
 };
 
 namespace {
@@ -402,6 +413,271 @@ double host_dot_rows(const ppcg_hybrid *hy, const std::vector<double> &a, const 
     return s;
 }
 
+// ||b - A x|| over all rows: host rows from hy->x and hy->bh, GPU rows from
+// hy->dx and hy->db (synchronous).
+ppcg_status hybrid_resid_norm(ppcg_hybrid *hy, const double *xh_rows, double *t2_out)
+{
+    const int nc = hy->ncpu, ng = hy->ngpu;
+    std::vector<double> yh(nc);
+    PPCG_TRY(hybrid_spmv(hy, xh_rows, hy->dx, yh.data(), hy->dy));
+    double t2 = 0.0;
+    for (int k = 0; k < nc; ++k) {
+        const double d = hy->bh[k] - yh[k];
+        t2 = t2 + d * d;
+    }
+    std::vector<double> yg(ng), bg(ng);
+    if (ng > 0) {
+        PPCG_HIP(hipMemcpy(yg.data(), hy->dy, sizeof(double) * ng, hipMemcpyDeviceToHost));
+        PPCG_HIP(hipMemcpy(bg.data(), hy->db, sizeof(double) * ng, hipMemcpyDeviceToHost));
+    }
+    for (int k = 0; k < ng; ++k) {
+        const double d = bg[k] - yg[k];
+        t2 = t2 + d * d;
+    }
+    *t2_out = t2;
+    return PPCG_OK;
+}
+
+// Hybrid-PIPECG-1 and -2 (Sections IV-A, IV-B): every row on the GPU.  The GPU
+// stream runs, per iteration, the updates of q, s, p, x, r, u
+// (k_h3_update1), of z, w, m with the n of the previous SpMV (k_h3_update2),
+// then the SpMV n = A m for the next iteration.  The copy stream moves, after
+// the updates, w, r, u (Hybrid-1) or, after the SpMV, n (Hybrid-2) to pinned
+// host memory; the host computes the dot products and alpha and beta.
+// Hybrid-2's host repeats the updates of q, s, r, u (and gamma, the norms)
+// while n is in flight, then z, w, m (and delta) once it has arrived; its
+// copies are bitwise the GPU's (same operations, same order).  Two n buffers
+// alternate so that the copy of one overlaps the SpMV writing the other: the
+// host waits for a copy before it lets the GPU run the iteration after.
+ppcg_status solve_task(ppcg_hybrid *hy, const double *b, const double *x0, double *x, ppcg_info *info)
+{
+    const auto t_begin = std::chrono::steady_clock::now();
+    const int n = hy->n;
+    const int T = hy->pool->size();
+    const std::vector<int> &lo = hy->full_lo;
+    hipStream_t st = hy->stream, cs = hy->cstream;
+    const ppcg_options &o = hy->opt;
+    const int g1 = (n + kH3Threads - 1) / kH3Threads;
+    const bool h2 = hy->scheme == PPCG_HYBRID_2;
+    double *nbuf[2] = {hy->dn, hy->dy};  // dy is free during the iterations
+    double *pin_w = hy->pin_vec, *pin_r = hy->pin_vec + (h2 ? 0 : n), *pin_u = hy->pin_vec + (h2 ? 0 : 2 * (size_t)n);
+    double *pin_n = hy->pin_vec;
+    std::vector<double> pt(T), pt4(4 * T);
+    PPCG_HIP(hipMemcpyAsync(hy->db, b, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    if (x0)
+        PPCG_HIP(hipMemcpyAsync(hy->dx, x0, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    else
+        PPCG_HIP(hipMemsetAsync(hy->dx, 0, sizeof(double) * n, st));
+    hy->pool->run([&](int t) {
+        double a = 0.0;
+        for (int i = lo[t]; i < lo[t + 1]; ++i)
+            a = a + b[i] * b[i];
+        pt[t] = a;
+    });
+    double bb = 0.0;
+    for (int t = 0; t < T; ++t)
+        bb = bb + pt[t];
+    const double bnorm = std::sqrt(bb);
+    // gamma = (r,u), (u,u), (r,r), delta = (w,u) over all rows, threads in order
+    auto host_dots = [&](const double *r, const double *u, const double *w, double *g) {
+        hy->pool->run([&](int t) {
+            double a[4] = {0, 0, 0, 0};
+            for (int i = lo[t]; i < lo[t + 1]; ++i) {
+                a[0] = a[0] + r[i] * u[i];
+                a[1] = a[1] + u[i] * u[i];
+                a[2] = a[2] + r[i] * r[i];
+                a[3] = a[3] + w[i] * u[i];
+            }
+            for (int k = 0; k < 4; ++k)
+                pt4[4 * t + k] = a[k];
+        });
+        for (int k = 0; k < 4; ++k) {
+            g[k] = 0.0;
+            for (int t = 0; t < T; ++t)
+                g[k] = g[k] + pt4[4 * t + k];
+        }
+    };
+    int it = 0, restarts = 0, status = PPCG_OK;
+    double gamma = 0, delta = 0, uu = 0, rr = 0, alpha_prev = 0, gamma_prev = 0, beta = 0;
+    auto converged = [&]() {
+        if (o.stop == PPCG_STOP_PRECOND_ABS)
+            return std::sqrt(uu) < o.tol;
+        return std::sqrt(rr) <= o.tol * bnorm;
+    };
+    for (;;) {
+        // Algorithm 2 initialisation on the GPU; n0 = A m0 into nbuf[0]
+        PPCG_TRY(hybrid_spmv(hy, nullptr, hy->dx, nullptr, hy->dy));
+        k_h3_init1<<<(n + 255) / 256, 256, 0, st>>>(n, hy->db, hy->dy, hy->ddinv, hy->dr, hy->du, hy->dz, hy->dq,
+                                                    hy->ds, hy->dp);
+        PPCG_TRY(hybrid_spmv(hy, nullptr, hy->du, nullptr, hy->dw));
+        k_h3_init2<<<g1, kH3Threads, 0, st>>>(n, hy->dr, hy->du, hy->dw, hy->ddinv, hy->dm, hy->dpart);
+        PPCG_TRY(shard_launch(hy->gs, 1, hy->dm, hy->dhalo, nbuf[0], nullptr, nullptr));
+        double g[4];
+        if (h2) {
+            // the host's copies: r, u, w, m; z = q = s = 0; and n0 in flight
+            PPCG_HIP(hipMemcpyAsync(hy->r.data(), hy->dr, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+            PPCG_HIP(hipMemcpyAsync(hy->u.data(), hy->du, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+            PPCG_HIP(hipMemcpyAsync(hy->w.data(), hy->dw, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+            PPCG_HIP(hipMemcpyAsync(hy->m.data(), hy->dm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+            PPCG_HIP(hipEventRecord(hy->ev_upd, st));
+            PPCG_HIP(hipStreamWaitEvent(cs, hy->ev_upd, 0));
+            PPCG_HIP(hipMemcpyAsync(pin_n, nbuf[0], sizeof(double) * n, hipMemcpyDeviceToHost, cs));
+            PPCG_HIP(hipEventRecord(hy->ev_copy, cs));
+            PPCG_HIP(hipStreamSynchronize(st));
+            std::fill(hy->z.begin(), hy->z.end(), 0.0);
+            std::fill(hy->q.begin(), hy->q.end(), 0.0);
+            std::fill(hy->s.begin(), hy->s.end(), 0.0);
+            host_dots(hy->r.data(), hy->u.data(), hy->w.data(), g);
+        } else {
+            PPCG_HIP(hipMemcpyAsync(pin_w, hy->dw, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+            PPCG_HIP(hipMemcpyAsync(pin_r, hy->dr, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+            PPCG_HIP(hipMemcpyAsync(pin_u, hy->du, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+            PPCG_HIP(hipStreamSynchronize(st));
+            host_dots(pin_r, pin_u, pin_w, g);
+        }
+        gamma = g[0];
+        uu = g[1];
+        rr = g[2];
+        delta = g[3];
+        int i;
+        for (i = 0;; ++i) {
+            if (o.fixed_iters > 0) {
+                if (it >= o.fixed_iters || gamma == 0.0) {
+                    status = PPCG_OK;
+                    break;
+                }
+            } else {
+                if (converged()) {
+                    status = PPCG_OK;
+                    break;
+                }
+                if (it >= o.max_iter) {
+                    status = PPCG_NOT_CONVERGED;
+                    break;
+                }
+            }
+            double denom;
+            if (i > 0) {
+                beta = gamma / gamma_prev;
+                denom = delta - beta * gamma / alpha_prev;
+            } else {
+                beta = 0.0;
+                denom = delta;
+            }
+            const double alpha = gamma / denom;
+            if (!(gamma > 0.0) || !(denom > 0.0) || !std::isfinite(alpha) || !std::isfinite(beta)) {
+                status = PPCG_BREAKDOWN;
+                break;
+            }
+            double *ncur = nbuf[i & 1], *nnext = nbuf[(i + 1) & 1];
+            // GPU: the vector updates of this iteration, then the next n
+            k_h3_update1<<<g1, kH3Threads, 0, st>>>(n, alpha, beta, hy->dm, hy->dq, hy->dw, hy->ds, hy->du, hy->dp,
+                                                    hy->dx, hy->dr, hy->dpart);
+            k_h3_update2<<<g1, kH3Threads, 0, st>>>(n, alpha, beta, ncur, hy->dz, hy->dw, hy->dm, hy->ddinv,
+                                                    hy->du, hy->dpart);
+            PPCG_HIP(hipGetLastError());
+            if (!h2) {
+                // Hybrid-1: w, r, u move while the GPU runs the SpMV
+                PPCG_HIP(hipEventRecord(hy->ev_upd, st));
+                PPCG_HIP(hipStreamWaitEvent(cs, hy->ev_upd, 0));
+                PPCG_HIP(hipMemcpyAsync(pin_w, hy->dw, sizeof(double) * n, hipMemcpyDeviceToHost, cs));
+                PPCG_HIP(hipMemcpyAsync(pin_r, hy->dr, sizeof(double) * n, hipMemcpyDeviceToHost, cs));
+                PPCG_HIP(hipMemcpyAsync(pin_u, hy->du, sizeof(double) * n, hipMemcpyDeviceToHost, cs));
+                PPCG_HIP(hipEventRecord(hy->ev_copy, cs));
+                PPCG_TRY(shard_launch(hy->gs, 1, hy->dm, hy->dhalo, nnext, nullptr, nullptr));
+                PPCG_HIP(hipEventSynchronize(hy->ev_copy));
+                host_dots(pin_r, pin_u, pin_w, g);
+            } else {
+                // Hybrid-2: the host repeats the updates; the copy of this
+                // iteration's n (enqueued after the previous SpMV) is waited
+                // for only before z, w, m
+                PPCG_TRY(shard_launch(hy->gs, 1, hy->dm, hy->dhalo, nnext, nullptr, nullptr));
+                hy->pool->run([&](int t) {
+                    double a0 = 0, a1 = 0, a2 = 0;
+                    for (int k = lo[t]; k < lo[t + 1]; ++k) {
+                        hy->q[k] = hy->m[k] + beta * hy->q[k];
+                        hy->s[k] = hy->w[k] + beta * hy->s[k];
+                        hy->r[k] = hy->r[k] - alpha * hy->s[k];
+                        hy->u[k] = hy->u[k] - alpha * hy->q[k];
+                        a0 = a0 + hy->r[k] * hy->u[k];
+                        a1 = a1 + hy->u[k] * hy->u[k];
+                        a2 = a2 + hy->r[k] * hy->r[k];
+                    }
+                    pt4[4 * t + 0] = a0;
+                    pt4[4 * t + 1] = a1;
+                    pt4[4 * t + 2] = a2;
+                });
+                PPCG_HIP(hipEventSynchronize(hy->ev_copy));
+                hy->pool->run([&](int t) {
+                    double a3 = 0.0;
+                    for (int k = lo[t]; k < lo[t + 1]; ++k) {
+                        hy->z[k] = pin_n[k] + beta * hy->z[k];
+                        hy->w[k] = hy->w[k] - alpha * hy->z[k];
+                        hy->m[k] = hy->dinv_h[k] * hy->w[k];
+                        a3 = a3 + hy->w[k] * hy->u[k];
+                    }
+                    pt4[4 * t + 3] = a3;
+                });
+                for (int k = 0; k < 4; ++k) {
+                    g[k] = 0.0;
+                    for (int t = 0; t < T; ++t)
+                        g[k] = g[k] + pt4[4 * t + k];
+                }
+                // the next n moves once its SpMV is done (the host has read
+                // pin_n, so it may be overwritten)
+                PPCG_HIP(hipEventRecord(hy->ev_upd, st));
+                PPCG_HIP(hipStreamWaitEvent(cs, hy->ev_upd, 0));
+                PPCG_HIP(hipMemcpyAsync(pin_n, nnext, sizeof(double) * n, hipMemcpyDeviceToHost, cs));
+                PPCG_HIP(hipEventRecord(hy->ev_copy, cs));
+            }
+            gamma_prev = gamma;
+            alpha_prev = alpha;
+            gamma = g[0];
+            uu = g[1];
+            rr = g[2];
+            delta = g[3];
+            ++it;
+        }
+        // nothing of this sequence may still read or write the buffers
+        PPCG_HIP(hipStreamSynchronize(cs));
+        PPCG_HIP(hipStreamSynchronize(st));
+        if (status == PPCG_BREAKDOWN && o.fixed_iters <= 0 && i > 0 && restarts < o.max_restarts &&
+            it < o.max_iter) {
+            ++restarts;
+            continue;
+        }
+        if (status == PPCG_OK && o.fixed_iters <= 0 && o.stop == PPCG_STOP_REL_RESID) {
+            double t2 = 0.0;
+            PPCG_TRY(hybrid_resid_norm(hy, nullptr, &t2));
+            const double rel = bnorm > 0 ? std::sqrt(t2) / bnorm : std::sqrt(t2);
+            if (rel > o.tol) {
+                if (restarts < o.max_restarts && it < o.max_iter) {
+                    ++restarts;
+                    continue;
+                }
+                status = PPCG_STAGNATED;
+            }
+        }
+        break;
+    }
+    PPCG_HIP(hipMemcpy(x, hy->dx, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (info) {
+        memset((char *)info + sizeof(size_t), 0, sizeof(ppcg_info) - sizeof(size_t));
+        info->status = (ppcg_status)status;
+        info->iters = it;
+        info->restarts = restarts;
+        info->rel_resid_recur = bnorm > 0 ? std::sqrt(rr) / bnorm : std::sqrt(rr);
+        info->precond_norm = std::sqrt(uu);
+        info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
+        double t2 = 0.0;
+        PPCG_TRY(hybrid_resid_norm(hy, nullptr, &t2));
+        info->rel_resid_true = bnorm > 0 ? std::sqrt(t2) / bnorm : std::sqrt(t2);
+        info->precision = PPCG_FP64;
+        info->method = PPCG_METHOD_PIPECG;
+    }
+    return (ppcg_status)status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -420,20 +696,29 @@ ppcg_status ppcg_hybrid_destroy(ppcg_hybrid *hy)
     if (hy->pin_to_dev) (void)hipHostFree(hy->pin_to_dev);
     if (hy->pin_red) (void)hipHostFree(hy->pin_red);
     if (hy->ev_halo) (void)hipEventDestroy(hy->ev_halo);
+    if (hy->cstream) {
+        (void)hipStreamSynchronize(hy->cstream);
+        (void)hipStreamDestroy(hy->cstream);
+    }
+    if (hy->ev_upd) (void)hipEventDestroy(hy->ev_upd);
+    if (hy->ev_copy) (void)hipEventDestroy(hy->ev_copy);
+    if (hy->pin_vec) (void)hipHostFree(hy->pin_vec);
     delete hy;
     return PPCG_OK;
 }
 
-ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, int32_t host_threads, double cpu_share,
-                               void *hip_stream, ppcg_hybrid **out)
+ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, ppcg_hybrid_scheme scheme,
+                               int32_t host_threads, double cpu_share, void *hip_stream, ppcg_hybrid **out)
 {
     clear_error();
+    const bool task = scheme == PPCG_HYBRID_1 || scheme == PPCG_HYBRID_2;
     if (!out || !A || !opt || A->struct_size != sizeof(ppcg_csr) || opt->struct_size != sizeof(ppcg_options) ||
         A->mem != PPCG_MEM_HOST || A->n < 1 || A->nnz < A->n || A->nnz >= INT32_MAX || !A->row_ptr ||
         !A->col_idx || !A->values || host_threads < 1 || host_threads > 256 || !(cpu_share <= 1.0) ||
         !std::isfinite(cpu_share) || opt->precision != PPCG_FP64 || opt->method != PPCG_METHOD_PIPECG ||
-        opt->vec_mem != PPCG_MEM_HOST) {
-        set_error("invalid arguments (host CSR, FP64 PIPECG, host vectors, 1..256 threads, cpu_share <= 1)");
+        opt->vec_mem != PPCG_MEM_HOST || !(task || scheme == PPCG_HYBRID_3) || (task && cpu_share >= 0.0)) {
+        set_error("invalid arguments (host CSR, FP64 PIPECG, host vectors, a scheme of ppcg_hybrid_scheme, "
+                  "1..256 threads, cpu_share <= 1 for Hybrid-3 and < 0 for Hybrid-1/2)");
         return PPCG_ERR_INVALID_ARG;
     }
     *out = nullptr;
@@ -474,9 +759,10 @@ ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, int32
     hy->stream = (hipStream_t)hip_stream;
     hy->opt = *opt;
     hy->n = n;
+    hy->scheme = scheme;
     hy->pool.reset(new HostPool(host_threads));
-    // Performance model: five SpMVs over all of A on each side.
-    {
+    // Performance model (Hybrid-3): five SpMVs over all of A on each side.
+    if (!task) {
         ppcg_shard *full = nullptr;
         PPCG_TRY(ppcg_shard_create(A, 0, n, hip_stream, &full));
         std::unique_ptr<ppcg_shard, ppcg_status (*)(ppcg_shard *)> guard(full, ppcg_shard_destroy);
@@ -508,9 +794,12 @@ ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, int32
             });
         hy->t_cpu = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / 5.0;
     }
-    // Row split: the model's, or a forced share of the non-zeros.
+    // Row split: the model's, or a forced share of the non-zeros; the
+    // task-parallel schemes keep every row on the GPU.
     int32_t bounds[3];
-    if (cpu_share < 0.0) {
+    if (task) {
+        bounds[1] = 0;
+    } else if (cpu_share < 0.0) {
         const double times[2] = {hy->t_cpu, hy->t_gpu};
         PPCG_TRY(ppcg_split_rows(n, rp, 2, times, bounds));
     } else if (cpu_share == 0.0) {
@@ -587,6 +876,23 @@ ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, int32
                            hipHostMallocDefault));
     PPCG_HIP(hipHostMalloc((void **)&hy->pin_red, sizeof(double) * 4, hipHostMallocDefault));
     PPCG_HIP(hipEventCreateWithFlags(&hy->ev_halo, hipEventDisableTiming));
+    if (task) {
+        // host thread ranges over all rows, the copy stream (default
+        // priority) and the pinned vectors: w, r, u (Hybrid-1) or n (Hybrid-2)
+        hy->full_lo.resize(T + 1);
+        for (int t = 0; t <= T; ++t)
+            hy->full_lo[t] = (int)((int64_t)n * t / T);
+        PPCG_HIP(hipStreamCreateWithFlags(&hy->cstream, hipStreamNonBlocking));
+        PPCG_HIP(hipEventCreateWithFlags(&hy->ev_upd, hipEventDisableTiming));
+        PPCG_HIP(hipEventCreateWithFlags(&hy->ev_copy, hipEventDisableTiming));
+        const int nvec = scheme == PPCG_HYBRID_1 ? 3 : 1;
+        PPCG_HIP(hipHostMalloc((void **)&hy->pin_vec, sizeof(double) * (size_t)nvec * n, hipHostMallocDefault));
+        if (scheme == PPCG_HYBRID_2) {
+            hy->dinv_h = dinv;
+            for (auto *v : {&hy->r, &hy->u, &hy->w, &hy->m, &hy->z, &hy->q, &hy->s})
+                v->assign(n, 0.0);
+        }
+    }
     *out = hy.release();
     return PPCG_OK;
 }
@@ -609,6 +915,10 @@ ppcg_status ppcg_hybrid_get_info(const ppcg_hybrid *hy, ppcg_hybrid_info *info)
     info->nnz_gpu_remote = hy->gs ? hy->gs->nnz2 : 0;
     info->halo_to_cpu = (int32_t)hy->hcols.size();
     info->halo_to_gpu = hy->gs ? hy->gs->halo : 0;
+    info->scheme = (ppcg_hybrid_scheme)hy->scheme;
+    info->copy_bytes_per_iter = hy->scheme == PPCG_HYBRID_1   ? 3.0 * 8.0 * hy->n
+                                : hy->scheme == PPCG_HYBRID_2 ? 8.0 * hy->n
+                                                              : 8.0 * (info->halo_to_cpu + info->halo_to_gpu);
     return PPCG_OK;
 }
 
@@ -620,6 +930,8 @@ ppcg_status ppcg_hybrid_solve(ppcg_hybrid *hy, const double *b, const double *x0
         return PPCG_ERR_INVALID_ARG;
     }
     PPCG_HIP(hipSetDevice(hy->device));
+    if (hy->scheme != PPCG_HYBRID_3)
+        return solve_task(hy, b, x0, x, info);
     const auto t_begin = std::chrono::steady_clock::now();
     const int nc = hy->ncpu, ng = hy->ngpu, hc = (int)hy->hcols.size();
     const int T = hy->pool->size();

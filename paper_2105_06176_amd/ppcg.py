@@ -83,7 +83,8 @@ class HybridInfo(ctypes.Structure):
                 ("host_threads", ctypes.c_int32), ("t_cpu_spmv_ms", ctypes.c_double),
                 ("t_gpu_spmv_ms", ctypes.c_double), ("nnz_cpu_local", ctypes.c_int64),
                 ("nnz_cpu_remote", ctypes.c_int64), ("nnz_gpu_local", ctypes.c_int64),
-                ("nnz_gpu_remote", ctypes.c_int64), ("halo_to_cpu", ctypes.c_int32), ("halo_to_gpu", ctypes.c_int32)]
+                ("nnz_gpu_remote", ctypes.c_int64), ("halo_to_cpu", ctypes.c_int32), ("halo_to_gpu", ctypes.c_int32),
+                ("scheme", ctypes.c_int), ("copy_bytes_per_iter", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
@@ -133,8 +134,8 @@ def lib():
         "ppcg_shard_time": ([P, P, P, P, P, I32, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
                             ctypes.c_int),
         "ppcg_shard_destroy": ([P], ctypes.c_int),
-        "ppcg_hybrid_create": ([ctypes.POINTER(Csr), ctypes.POINTER(Options), I32, D, P, ctypes.POINTER(P)],
-                               ctypes.c_int),
+        "ppcg_hybrid_create": ([ctypes.POINTER(Csr), ctypes.POINTER(Options), ctypes.c_int, I32, D, P,
+                                ctypes.POINTER(P)], ctypes.c_int),
         "ppcg_hybrid_get_info": ([P, ctypes.POINTER(HybridInfo)], ctypes.c_int),
         "ppcg_hybrid_solve": ([P, P, P, P, ctypes.POINTER(Info)], ctypes.c_int),
         "ppcg_hybrid_destroy": ([P], ctypes.c_int),
@@ -440,10 +441,13 @@ class Shard:
 
 
 class Hybrid:
-    """Algorithm 2 on host threads and the GPU together (rows split by the
-    performance model, or by a forced share of the non-zeros)."""
+    """Algorithm 2 on host threads and the GPU together.  scheme 3 (default):
+    rows split by the performance model, or by a forced share of the
+    non-zeros; schemes 1 and 2: every row on the GPU, dot products (and for 2
+    the vector updates) repeated on the host."""
 
-    def __init__(self, A, host_threads: int = 4, cpu_share: float = -1.0, stream=None, **options):
+    def __init__(self, A, host_threads: int = 4, cpu_share: float = -1.0, stream=None, scheme: int = 3,
+                 **options):
         options.setdefault("vec_mem", "host")
         self.opt = make_options(**options)
         keep: list = []
@@ -451,7 +455,7 @@ class Hybrid:
         if c.mem != MEM_HOST:
             raise ValueError("the host + GPU solver takes host CSR arrays")
         h = ctypes.c_void_p()
-        _check(lib().ppcg_hybrid_create(ctypes.byref(c), ctypes.byref(self.opt), int(host_threads),
+        _check(lib().ppcg_hybrid_create(ctypes.byref(c), ctypes.byref(self.opt), int(scheme), int(host_threads),
                                         float(cpu_share), _stream_ptr(stream), ctypes.byref(h)),
                "ppcg_hybrid_create")
         self.h = h

@@ -57,7 +57,7 @@ def test_host_side_argument_errors():
     assert L.ppcg_srv_destroy(None) == ppcg.OK
     assert L.ppcg_shard_destroy(None) == ppcg.OK
     assert L.ppcg_hybrid_destroy(None) == ppcg.OK
-    assert L.ppcg_hybrid_create(None, None, 1, -1.0, None, None) == ppcg.ERR_INVALID_ARG
+    assert L.ppcg_hybrid_create(None, None, 3, 1, -1.0, None, None) == ppcg.ERR_INVALID_ARG
     assert L.ppcg_shard_create(None, 0, 1, None, None) == ppcg.ERR_INVALID_ARG
     assert L.ppcg_footprint_bytes(0, 0, 0) == 0.0
     assert L.ppcg_footprint_bytes(1000, 5000, 1) > L.ppcg_footprint_bytes(1000, 5000, 0) > 0
@@ -77,6 +77,7 @@ int main(void) {
   F(ppcg_options, flags)
   F(ppcg_shard_info, nnz_local) F(ppcg_shard_info, boundary_rows) F(ppcg_shard_info, halo_bytes)
   F(ppcg_hybrid_info, t_cpu_spmv_ms) F(ppcg_hybrid_info, nnz_gpu_remote) F(ppcg_hybrid_info, halo_to_gpu)
+  F(ppcg_hybrid_info, scheme) F(ppcg_hybrid_info, copy_bytes_per_iter)
   F(ppcg_info, status) F(ppcg_info, rel_resid_true) F(ppcg_info, model_bytes)
   F(ppcg_info, precision) F(ppcg_info, method)
   F(ppcg_matrix_info, nnz_stored) F(ppcg_matrix_info, tile_rows) F(ppcg_matrix_info, setup_ms)

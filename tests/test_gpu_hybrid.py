@@ -97,6 +97,59 @@ def test_hybrid_paper_protocol():
     assert info["precond_norm"] < 1e-5
 
 
+# ---------------------------------------------------------------- task-parallel schemes
+
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_task_schemes_fixed_iterates_match_oracle(scheme, name):
+    """Hybrid-1 (w, r, u copied, dots on the host) and Hybrid-2 (n copied, the
+    host repeats the updates of z, q, s, r, u, w, m): the GPU runs every
+    update and the SpMV with Algorithm 2's arithmetic, the host sums the dot
+    products in a fixed thread order, so iterates match the oracle to 1e-10."""
+    A = CASES[name]()
+    b = problem(A)
+    for k in (1, 7, 30):
+        H = Hybrid(A, host_threads=3, scheme=scheme, fixed_iters=k)
+        i = H.info()
+        assert i["scheme"] == scheme and i["n_cpu"] == 0 and i["n_gpu"] == A.n
+        assert i["copy_bytes_per_iter"] == (3 if scheme == 1 else 1) * 8.0 * A.n
+        x, info = H.solve(b)
+        ref = oracle.pipecg(A, b, fixed_iters=k)
+        assert info["status"] == ppcg.OK and info["iters"] == k == ref.iters
+        assert relerr(x, ref.x) <= 1e-10, (k, relerr(x, ref.x))
+        H.close()
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_task_schemes_tolerance_solve_and_initial_guess(scheme):
+    A = poisson3d(24)
+    b = problem(A)
+    x, info = Hybrid(A, host_threads=4, scheme=scheme, tol=1e-10).solve(b)
+    ref = oracle.pipecg(A, b, tol=1e-10)
+    assert info["status"] == ppcg.OK and abs(info["iters"] - ref.iters) <= 2
+    assert info["rel_resid_true"] <= 1e-10 and oracle.true_relres(A, b, x) <= 1e-10
+    x0 = xstar_uniform(A.n, 9)
+    x, info = Hybrid(A, host_threads=2, scheme=scheme, fixed_iters=20).solve(b, x0)
+    assert relerr(x, oracle.pipecg(A, b, x0=x0, fixed_iters=20).x) <= 1e-10
+    # the paper's absolute stop on the preconditioned residual
+    P = poisson3d(20)
+    bp = rhs_from_solution(P, xstar_paper(P.n))
+    x, info = Hybrid(P, host_threads=2, scheme=scheme, tol=1e-5, stop="abs", max_iter=10000).solve(bp)
+    refp = oracle.pipecg(P, bp, tol=1e-5, stop=oracle.STOP_ABS, maxit=10000)
+    assert info["status"] == ppcg.OK and abs(info["iters"] - refp.iters) <= 2
+
+
+def test_task_schemes_agree_with_each_other():
+    """Both task schemes form the same iteration on the GPU; Hybrid-2's host
+    copies are the GPU's bit for bit and its dot products are summed as
+    Hybrid-1 sums the copied vectors', so the two give the same x."""
+    A = stencil27_lognormal(14, seed=5)
+    b = problem(A)
+    x1, i1 = Hybrid(A, host_threads=3, scheme=1, fixed_iters=40).solve(b)
+    x2, i2 = Hybrid(A, host_threads=3, scheme=2, fixed_iters=40).solve(b)
+    assert np.array_equal(x1, x2)
+
+
 def test_hybrid_rejects_unsupported_options():
     A = poisson2d(8)
     with pytest.raises(PPCGError):
@@ -105,3 +158,7 @@ def test_hybrid_rejects_unsupported_options():
         Hybrid(A, vec_mem="device")
     with pytest.raises(PPCGError):
         Hybrid(A, cpu_share=1.5)
+    with pytest.raises(PPCGError):
+        Hybrid(A, scheme=1, cpu_share=0.5)  # every row is on the GPU in the task schemes
+    with pytest.raises(PPCGError):
+        Hybrid(A, scheme=4)
