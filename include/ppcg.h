@@ -135,7 +135,8 @@ typedef struct {
                                       request ready.  Ignored elsewhere */
 #define PPCG_FLAG_SELL_COL16 2u    /* SELL: read 16-bit column offsets from the row whenever all
                                       fit, without timing them against 32-bit columns (by default
-                                      both are timed at create time and the faster is kept) */
+                                      both are timed at create time and the faster is kept).
+                                      Read by ppcg_create only, like the format itself */
 #define PPCG_FLAG_SELL_COL32 4u    /* SELL: always read 32-bit columns (not with SELL_COL16) */
 
 /* Solver options; initialise with ppcg_default_options(). */

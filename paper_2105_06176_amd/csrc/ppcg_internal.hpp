@@ -41,6 +41,16 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 #define PPCG_SELL_COL16 1
 #endif
 
+// SELL SpMV: entries per lane whose column and value loads are issued
+// together before their gathers (even: the 16-bit layout reads pairs).
+#ifndef PPCG_SELL_BATCH
+#define PPCG_SELL_BATCH 8
+#endif
+// Waves per SIMD the SpMV is compiled for (8: at most 64 VGPRs).
+#ifndef PPCG_SPMV_WAVES
+#define PPCG_SPMV_WAVES 8
+#endif
+
 // Systems with at most this many rows (SELL format, FP64) iterate in the
 // one-workgroup kernel: for them launch latency, not bandwidth, dominates.
 #ifndef PPCG_SMALL_MAX_ROWS

@@ -436,7 +436,7 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
                                          const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
                                          int lane, T (&acc)[NX])
 {
-    constexpr int B = 8;
+    constexpr int B = PPCG_SELL_BATCH;
     const int64_t base = cptr[chunk];
     const int len = (int)((cptr[chunk + 1] - base) / kSellC);
     const int *c = col + base + lane;
@@ -506,7 +506,7 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
                                            const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
                                            int lane, T (&acc)[NX])
 {
-    constexpr int B = 8;
+    constexpr int B = PPCG_SELL_BATCH;
     const int64_t base = cptr[chunk];
     const int len = (int)((cptr[chunk + 1] - base) / kSellC);
     const int row = chunk * kSellC + lane;
@@ -720,7 +720,7 @@ __device__ __forceinline__ void spmv_tile(const SysDesc &d, const VT *__restrict
 // Eight waves per SIMD (at most 64 VGPRs): the gathers depend on the column
 // loads, so latency is hidden by the number of waves in flight.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kSpmvThreads, 8) void k_spmv(const WorkItem *__restrict__ table,
+__global__ __launch_bounds__(kSpmvThreads, PPCG_SPMV_WAVES) void k_spmv(const WorkItem *__restrict__ table,
                                                           const int *__restrict__ count,
                                                           const SysDesc *__restrict__ descs, int remap)
 {

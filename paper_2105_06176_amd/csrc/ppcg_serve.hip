@@ -29,8 +29,14 @@ namespace {
 constexpr int kServerSlots = 1024;
 constexpr int kServeGraphIters = 32;
 // automatic precision: smallest systems given reduced precision
-constexpr int kAutoValues32Rows = 65536;
-constexpr int kAutoPcg32Rows = 262144;
+#ifndef PPCG_AUTO_VALUES32_ROWS
+#define PPCG_AUTO_VALUES32_ROWS 65536
+#endif
+#ifndef PPCG_AUTO_PCG32_ROWS
+#define PPCG_AUTO_PCG32_ROWS 262144
+#endif
+constexpr int kAutoValues32Rows = PPCG_AUTO_VALUES32_ROWS;
+constexpr int kAutoPcg32Rows = PPCG_AUTO_PCG32_ROWS;
 
 struct Request {
     int64_t id = 0;
