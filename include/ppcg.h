@@ -194,8 +194,9 @@ typedef struct {
     double bytes_per_iter;   /* algorithmic HBM bytes of one iteration (both kernels) of
                                 the handle's current method (opt.method) */
     double bytes_vma;        /* algorithmic bytes of one vector-update launch (PIPECG: fused
-                                VMA+PC+dots, 15 vectors; PCG: 8 vectors; one fewer when
-                                diag_const) */
+                                VMA+PC+dots, 14 vectors on average, x being read and
+                                written every other launch; PCG: 8 vectors; one fewer
+                                when diag_const) */
     double bytes_spmv;       /* algorithmic bytes of one SpMV launch (matrix plus 2 vectors;
                                 PCG: plus 4, the direction update being fused into it) */
     double device_bytes;     /* device memory held by the handle */

@@ -86,13 +86,13 @@ struct alignas(128) SysState {
     double repl_ref;    // FP32-values mode: residual norm at the last start / reliable update
     double bnorm2;      // (b, b)
     double tnorm2;      // (b - A x, b - A x) from the last true-residual pass
+    double alpha_x;     // alpha of the x-update the fused update deferred (x_pending)
     int iter;           // x-updates so far (all starts)
     int i_start;        // x-updates in the current start
     int done;           // 1: stop iterating
     int status;         // DevStatus when done
     int phase;          // 1: the next reduction is the one that ends initialisation
-    int gen;            // incremented by every reduction (debug / polling aid)
-    int pad[2];
+    int x_pending;      // 1: x still lacks alpha_x * p (the fused update defers every other x-update)
 };
 static_assert(sizeof(SysState) == 128, "SysState is one 128-byte record");
 

@@ -151,7 +151,6 @@ __device__ inline void scalar_update(const SysDesc &d, SysState *st, const doubl
         st->iter += 1;
         st->i_start += 1;
     }
-    st->gen += 1;
     st->gamma_prev2 = st->gamma_prev;
     const double g = v[0], dl = v[1], uu = v[2], rr = v[3];
     st->gamma = g;
@@ -219,7 +218,6 @@ __device__ inline void scalar_update(const SysDesc &d, SysState *st, const doubl
 // The iteration counters do not move.
 __device__ inline void scalar_update_repl(const SysDesc &d, SysState *st, const double (&v)[kReplPartials])
 {
-    st->gen += 1;
     const double g = v[0], dl = v[1], uu = v[2], rr = v[3], us = v[4], ps = v[5];
     st->gamma = g;
     st->delta = dl;
@@ -284,15 +282,19 @@ __device__ inline void scalar_update_repl(const SysDesc &d, SysState *st, const 
 // u = dinv * r, so the u read back elsewhere is the same rounded product.
 // In exact arithmetic the iterates are Algorithm 2's; in floating point the
 // two recurrences for u and q are replaced by the exact scaling.
+//
+// x is not needed by the iteration itself, so its update x += alpha p is
+// left to the caller: k_vma defers every other one and applies two at once
+// (x + alpha_{i-1} p_{i-1}, then + alpha_i p_i: the same two rounded
+// operations as one at a time), so x is read and written every other launch.
 template <typename T, int NV>
-__device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T &w, T &s, T &p, T &x, T &r, T dinv,
-                                         T &u_out, T &m_out, double (&acc)[NV])
+__device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T &w, T &s, T &p, T &r, T dinv, T &u_out,
+                                         T &m_out, double (&acc)[NV])
 {
     const T u = dinv * r;  // u_i
     z = nv + sb * z;
     s = w + sb * s;
     p = u + sb * p;
-    x = x + sa * p;
     r = r - sa * s;
     w = w - sa * z;
     u_out = dinv * r;  // u_{i+1}
@@ -355,6 +357,10 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     if (st->done)
         return;
     const T sa = (T)st->alpha, sb = (T)st->beta;
+    // x_pending: x still lacks alpha_{i-1} p_{i-1}; apply it with this
+    // iteration's term.  Otherwise defer this iteration's term (x untouched).
+    const bool xp = st->x_pending != 0;
+    const T ax = (T)st->alpha_x;
     const int n = d.n;
     T *__restrict__ X = (T *)d.x;
     T *__restrict__ R = (T *)d.r;
@@ -373,27 +379,41 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     using V2 = typename Vec2<T>::type;
     if (i + 1 < n) {
         V2 nv = vload((const V2 *)(NVv + i)), z = vload((const V2 *)(Z + i)), w = vload((const V2 *)(W + i));
-        V2 s = vload((const V2 *)(S + i)), p = vload((const V2 *)(P + i)), x = vload((const V2 *)(X + i));
+        V2 s = vload((const V2 *)(S + i)), p = vload((const V2 *)(P + i));
         // a constant diagonal: every lane reads dinv[0..1] (one cached line)
         V2 r = vload((const V2 *)(R + i)), di = vload((const V2 *)(DI + (d.dinv_const ? 0 : i)));
+        V2 x;
+        if (xp)
+            x = vload((const V2 *)(X + i));
         V2 mo;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            T zj = z[j], wj = w[j], sj = s[j], pj = p[j], xj = x[j], rj = r[j], uj, mj;
-            vma_elem<T, NV>(sa, sb, nv[j], zj, wj, sj, pj, xj, rj, di[j], uj, mj, acc);
-            z[j] = zj; w[j] = wj; s[j] = sj; p[j] = pj; x[j] = xj; r[j] = rj; mo[j] = mj;
+            const T pold = p[j];
+            T zj = z[j], wj = w[j], sj = s[j], pj = p[j], rj = r[j], uj, mj;
+            vma_elem<T, NV>(sa, sb, nv[j], zj, wj, sj, pj, rj, di[j], uj, mj, acc);
+            z[j] = zj; w[j] = wj; s[j] = sj; p[j] = pj; r[j] = rj; mo[j] = mj;
+            if (xp) {
+                const T x1 = x[j] + ax * pold;
+                x[j] = x1 + sa * pj;
+            }
         }
         vstore((V2 *)(Z + i), z);
         vstore((V2 *)(S + i), s);
         vstore((V2 *)(P + i), p);
-        vstore((V2 *)(X + i), x);
+        if (xp)
+            vstore((V2 *)(X + i), x);
         vstore((V2 *)(R + i), r);
         vstore((V2 *)(W + i), w);
         vstore((V2 *)(M + i), mo);
     } else if (i < n) {
-        T z = Z[i], w = W[i], s = S[i], p = P[i], x = X[i], r = R[i], u, mo;
-        vma_elem<T, NV>(sa, sb, NVv[i], z, w, s, p, x, r, DI[d.dinv_const ? 0 : i], u, mo, acc);
-        Z[i] = z; S[i] = s; P[i] = p; X[i] = x; R[i] = r; W[i] = w; M[i] = mo;
+        T z = Z[i], w = W[i], s = S[i], p = P[i], r = R[i], u, mo;
+        const T pold = p;
+        vma_elem<T, NV>(sa, sb, NVv[i], z, w, s, p, r, DI[d.dinv_const ? 0 : i], u, mo, acc);
+        Z[i] = z; S[i] = s; P[i] = p; R[i] = r; W[i] = w; M[i] = mo;
+        if (xp) {
+            const T x1 = X[i] + ax * pold;
+            X[i] = x1 + sa * p;
+        }
     }
     block_sum<kVmaThreads, NV>(acc, lds);
     if (threadIdx.x == 0) {
@@ -659,6 +679,15 @@ __device__ __forceinline__ void spmv_epilogue(const SysDesc &d, int i, const T (
 template <int MODE>
 __device__ __noinline__ void designated_reduce(const SysDesc &d, SysState *st, double *lds)
 {
+    // After a fused update (not the ITER pass that ends the initialisation):
+    // it either deferred its x-update (alpha of this iteration kept) or
+    // applied the deferred one with its own.
+    auto note_x = [&]() {
+        if (!st->phase) {
+            st->alpha_x = st->alpha;
+            st->x_pending ^= 1;
+        }
+    };
     if constexpr (MODE == MODE_DUAL2) {
         double v[kReplPartials];
         reduce_partials<kSpmvThreads, kReplPartials>(d, 1, v, lds);
@@ -667,16 +696,20 @@ __device__ __noinline__ void designated_reduce(const SysDesc &d, SysState *st, d
     } else if (MODE == MODE_ITER && d.vals32) {
         double v[kReplPartials];
         reduce_partials<kSpmvThreads, kReplPartials>(d, 1, v, lds);
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
+            note_x();
             scalar_update<kReplPartials>(d, st, v);
+        }
     } else {
         double v[kNumPartials];
         reduce_partials<kSpmvThreads>(d, MODE == MODE_INIT2 ? 0 : 1, v, lds);
         if (threadIdx.x == 0) {
-            if (MODE == MODE_INIT2)
+            if (MODE == MODE_INIT2) {
                 st->bnorm2 = v[0];
-            else
+            } else {
+                note_x();
                 scalar_update<kNumPartials>(d, st, v);
+            }
         }
     }
 }
@@ -772,6 +805,7 @@ __global__ __launch_bounds__(kSpmvThreads, PPCG_SPMV_WAVES) void k_spmv(const Wo
             st->i_start = 0;
             st->done = 0;
             st->status = ST_OK;
+            st->x_pending = 0;  // a start reads a complete x (k_x_fixup ran before)
         }
     } else if constexpr (MODE == MODE_INIT2 || MODE == MODE_ITER || MODE == MODE_DUAL2) {
         __syncthreads();  // lds reuse
@@ -798,6 +832,43 @@ __global__ __launch_bounds__(kSpmvThreads) void k_reduce_resid(const WorkItem *_
         d.st->tnorm2 = v[0];
         d.st->bnorm2 = v[1];
     }
+}
+
+// Deferred x-updates (see vma_elem): for the systems whose last x-update is
+// still pending, x += alpha_x p (p is still that iteration's direction).
+// Run before anything reads x; k_x_settle then clears the flag, in a launch
+// of its own so that no workgroup of this one can see it cleared early.
+template <typename T>
+__global__ void k_x_fixup(const WorkItem *__restrict__ table, const int *__restrict__ count,
+                          const SysDesc *__restrict__ descs)
+{
+    const int pos = blockIdx.x;
+    if (pos >= *count)
+        return;
+    const WorkItem wi = table[pos];
+    const SysDesc &d = descs[wi.slot];
+    const SysState *st = d.st;
+    if (!st->x_pending)
+        return;
+    const T a = (T)st->alpha_x;
+    T *__restrict__ X = (T *)d.x;
+    const T *__restrict__ P = (const T *)d.p;
+    for (int k = threadIdx.x; k < kTileRows; k += blockDim.x) {
+        const int i = wi.tile * kTileRows + k;
+        if (i < d.n)
+            X[i] = X[i] + a * P[i];
+    }
+}
+
+__global__ void k_x_settle(const WorkItem *__restrict__ table, const int *__restrict__ count,
+                           const SysDesc *__restrict__ descs)
+{
+    const int pos = blockIdx.x;
+    if (pos >= *count)
+        return;
+    const WorkItem wi = table[pos];
+    if (wi.tile == 0 && threadIdx.x == 0)
+        descs[wi.slot].st->x_pending = 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -120,10 +120,11 @@ ppcg_status check_dev_range(const void *p, size_t bytes, const char *what)
 }
 
 // ---------------------------------------------------------------- byte model
-// Algorithmic HBM bytes of one iteration.  PIPECG: the fused update reads 8
-// vectors (n z w s p x r dinv; u and q are scalings of r and s by the inverse
-// diagonal, formed in registers) and writes 7 (z s p x r w m); the SpMV reads
-// values and column indices of every
+// Algorithmic HBM bytes of one iteration.  PIPECG: the fused update reads 7
+// vectors (n z w s p r dinv; u and q are scalings of r and s by the inverse
+// diagonal, formed in registers) and writes 6 (z s p r w m), plus x read and
+// written every other launch (two x-updates at once): 14 on average; the
+// SpMV reads values and column indices of every
 // stored entry, its row/chunk pointers, the input vector once, and writes one
 // vector.  Classic PCG: the update reads x, p, r, s and the inverse diagonal
 // and writes x, r, u (8 vectors); the SpMV reads u and the previous direction
@@ -141,7 +142,7 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     const bool pcg = h->opt.method == PPCG_METHOD_PCG || prec == PREC_F32;
     ByteModel bm;
     // a constant diagonal is read as one scalar: one vector stream fewer
-    bm.vma = ((pcg ? 8.0 : 15.0) - (h->dinv_const ? 1.0 : 0.0)) * ve * n;
+    bm.vma = ((pcg ? 8.0 : 14.0) - (h->dinv_const ? 1.0 : 0.0)) * ve * n;
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
     // the SpMVs read 16-bit column offsets when the matrix has them (not the
     // classic-PCG SpMV with FP32 values and FP64 vectors)
@@ -967,6 +968,12 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     const SysDesc *dd = g.desc_d;
     const int rs = PPCG_XCD_REMAP_SPMV;
     const bool f32 = g.prec == PREC_F32;
+    // the fused update of Algorithm 2 defers every other x-update: complete
+    // x before anything reads it (a no-op for systems with nothing pending)
+    if (!g.pcg && &g != &gs_ && (what == AUX_RESID || what == AUX_REPL || what == AUX_INIT)) {
+        k_x_fixup<double><<<grid, 256, 0, s>>>(tab, cnt, dd);
+        k_x_settle<<<grid, 64, 0, s>>>(tab, cnt, dd);
+    }
     if (what == AUX_INIT && g.pcg) {
         if (f32) {
             k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);

@@ -278,7 +278,6 @@ __device__ inline void pcg_scalar_update(const SysDesc &d, SysState *st, const d
         st->i_start += 1;
         st->gamma_prev = st->gamma;
     }
-    st->gen += 1;
     const double g = v[0], uu = v[1], rr = v[2];
     st->gamma = g;
     st->uu = uu;

@@ -97,9 +97,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
             const int i = threadIdx.x + j * kSmallThreads;
             if (i < n) {
                 double mo;
-                vma_elem<double, kNumPartials>(sa, sb, nv[j], z[j], w[j], s[j], p[j], xg[j], r[j], dg[j], u[j], mo,
-                                               acc);
-                X[i] = xg[j];
+                vma_elem<double, kNumPartials>(sa, sb, nv[j], z[j], w[j], s[j], p[j], r[j], dg[j], u[j], mo, acc);
+                X[i] = xg[j] + sa * p[j];  // this kernel updates x every iteration
                 lm[i] = mo;  // only this thread touches lm[i] until the barrier below
             }
         }
