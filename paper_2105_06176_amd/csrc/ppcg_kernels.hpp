@@ -50,6 +50,26 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = dvec2; };
 template <> struct Vec2<float> { using type = fvec2; };
 
+// The vectors and matrix arrays reach the kernels as generic pointers (from
+// the system descriptor), for which the compiler emits flat loads and
+// stores.  Every such buffer is device or pinned host memory, never LDS or
+// scratch, so the hot kernels cast them to the global address space and get
+// global_load / global_store: no aperture check, and no share of the counter
+// that scalar loads and LDS accesses wait on.
+#ifndef PPCG_GLOBAL_AS
+#define PPCG_GLOBAL_AS 1
+#endif
+#if PPCG_GLOBAL_AS
+#define PPCG_AS1 __attribute__((address_space(1)))
+#else
+#define PPCG_AS1
+#endif
+template <typename T>
+__device__ __forceinline__ PPCG_AS1 T *as_global(T *p)
+{
+    return (PPCG_AS1 T *)p;
+}
+
 // Map the hardware workgroup id to a table position so that each of the 8
 // XCDs (which receive workgroups round-robin) works on a contiguous range of
 // tiles: neighbouring rows then share an L2, which serves the SpMV gathers.
@@ -100,7 +120,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* [NT/64
 template <int NT, int NV = kNumPartials>
 __device__ __forceinline__ void reduce_partials(const SysDesc &d, int slot, double (&out)[NV], double *lds)
 {
-    const double *P = d.part + (size_t)slot * d.ntiles * kPartStride;
+    const PPCG_AS1 double *P = as_global(d.part + (size_t)slot * d.ntiles * kPartStride);
 #pragma unroll
     for (int k = 0; k < NV; ++k)
         out[k] = 0.0;
@@ -316,7 +336,7 @@ __device__ __forceinline__ void vma_elem(T sa, T sb, T nv, T &z, T &w, T &s, T &
 #endif
 
 template <typename V>
-__device__ __forceinline__ V vload(const V *p)
+__device__ __forceinline__ V vload(const PPCG_AS1 V *p)
 {
 #if PPCG_VMA_NT
     return __builtin_nontemporal_load(p);
@@ -326,7 +346,7 @@ __device__ __forceinline__ V vload(const V *p)
 }
 
 template <typename V>
-__device__ __forceinline__ void vstore(V *p, V v)
+__device__ __forceinline__ void vstore(PPCG_AS1 V *p, V v)
 {
 #if PPCG_VMA_NT
     __builtin_nontemporal_store(v, p);
@@ -362,15 +382,15 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     const bool xp = st->x_pending != 0;
     const T ax = (T)st->alpha_x;
     const int n = d.n;
-    T *__restrict__ X = (T *)d.x;
-    T *__restrict__ R = (T *)d.r;
-    T *__restrict__ W = (T *)d.w;
-    T *__restrict__ M = (T *)d.m;
-    const T *__restrict__ NVv = (const T *)d.nv;
-    T *__restrict__ Z = (T *)d.z;
-    T *__restrict__ S = (T *)d.s;
-    T *__restrict__ P = (T *)d.p;
-    const T *__restrict__ DI = (const T *)d.dinv;
+    PPCG_AS1 T *__restrict__ X = as_global((T *)d.x);
+    PPCG_AS1 T *__restrict__ R = as_global((T *)d.r);
+    PPCG_AS1 T *__restrict__ W = as_global((T *)d.w);
+    PPCG_AS1 T *__restrict__ M = as_global((T *)d.m);
+    const PPCG_AS1 T *__restrict__ NVv = as_global((const T *)d.nv);
+    PPCG_AS1 T *__restrict__ Z = as_global((T *)d.z);
+    PPCG_AS1 T *__restrict__ S = as_global((T *)d.s);
+    PPCG_AS1 T *__restrict__ P = as_global((T *)d.p);
+    const PPCG_AS1 T *__restrict__ DI = as_global((const T *)d.dinv);
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k)
@@ -378,13 +398,14 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
     const int i = wi.tile * kTileRows + threadIdx.x * 2;
     using V2 = typename Vec2<T>::type;
     if (i + 1 < n) {
-        V2 nv = vload((const V2 *)(NVv + i)), z = vload((const V2 *)(Z + i)), w = vload((const V2 *)(W + i));
-        V2 s = vload((const V2 *)(S + i)), p = vload((const V2 *)(P + i));
+        using CV2 = const PPCG_AS1 V2;
+        V2 nv = vload((CV2 *)(NVv + i)), z = vload((CV2 *)(Z + i)), w = vload((CV2 *)(W + i));
+        V2 s = vload((CV2 *)(S + i)), p = vload((CV2 *)(P + i));
         // a constant diagonal: every lane reads dinv[0..1] (one cached line)
-        V2 r = vload((const V2 *)(R + i)), di = vload((const V2 *)(DI + (d.dinv_const ? 0 : i)));
+        V2 r = vload((CV2 *)(R + i)), di = vload((CV2 *)(DI + (d.dinv_const ? 0 : i)));
         V2 x;
         if (xp)
-            x = vload((const V2 *)(X + i));
+            x = vload((CV2 *)(X + i));
         V2 mo;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -397,14 +418,15 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
                 x[j] = x1 + sa * pj;
             }
         }
-        vstore((V2 *)(Z + i), z);
-        vstore((V2 *)(S + i), s);
-        vstore((V2 *)(P + i), p);
+        using GV2 = PPCG_AS1 V2;
+        vstore((GV2 *)(Z + i), z);
+        vstore((GV2 *)(S + i), s);
+        vstore((GV2 *)(P + i), p);
         if (xp)
-            vstore((V2 *)(X + i), x);
-        vstore((V2 *)(R + i), r);
-        vstore((V2 *)(W + i), w);
-        vstore((V2 *)(M + i), mo);
+            vstore((GV2 *)(X + i), x);
+        vstore((GV2 *)(R + i), r);
+        vstore((GV2 *)(W + i), w);
+        vstore((GV2 *)(M + i), mo);
     } else if (i < n) {
         T z = Z[i], w = W[i], s = S[i], p = P[i], r = R[i], u, mo;
         const T pold = p;
@@ -434,7 +456,7 @@ __global__ __launch_bounds__(kVmaThreads) void k_vma(const WorkItem *__restrict_
 // Matrix entries are read exactly once per SpMV: load them with the
 // non-temporal hint so they do not evict the reused input-vector lines.
 template <typename T>
-__device__ __forceinline__ T stream_load(const T *p)
+__device__ __forceinline__ T stream_load(const PPCG_AS1 T *p)
 {
 #if PPCG_SPMV_NT
     return __builtin_nontemporal_load(p);
@@ -457,13 +479,16 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
                                          int lane, T (&acc)[NX])
 {
     constexpr int B = PPCG_SELL_BATCH;
-    const int64_t base = cptr[chunk];
-    const int len = (int)((cptr[chunk + 1] - base) / kSellC);
-    const int *c = col + base + lane;
-    const VT *v = val + base + lane;
+    const int64_t base = as_global(cptr)[chunk];
+    const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
+    const PPCG_AS1 int *c = as_global(col + base + lane);
+    const PPCG_AS1 VT *v = as_global(val + base + lane);
+    const PPCG_AS1 T *xg[NX];
 #pragma unroll
-    for (int q = 0; q < NX; ++q)
+    for (int q = 0; q < NX; ++q) {
         acc[q] = (T)0;
+        xg[q] = as_global(xin[q]);
+    }
     for (int k0 = 0; k0 < len; k0 += B) {
         int cc[B];
         VT vv[B];
@@ -483,7 +508,7 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
             T xx[B];
 #pragma unroll
             for (int j = 0; j < B; ++j)
-                xx[j] = k0 + j < len ? xin[q][cc[j]] : (T)0;
+                xx[j] = k0 + j < len ? xg[q][cc[j]] : (T)0;
 #pragma unroll
             for (int j = 0; j < B; ++j)
                 if (k0 + j < len)
@@ -504,7 +529,7 @@ __device__ __forceinline__ void sell_cols16(const short *__restrict__ col16, int
 {
     static_assert(B % 2 == 0, "batches hold whole pairs");
     const int paired = len & ~1;
-    const unsigned *cp = (const unsigned *)(col16 + base) + lane;   // pair j at cp[j * 64]
+    const PPCG_AS1 unsigned *cp = as_global((const unsigned *)(col16 + base) + lane);  // pair j at cp[j * 64]
 #pragma unroll
     for (int t = 0; t < B / 2; ++t) {
         const int k = k0 + 2 * t;
@@ -515,7 +540,7 @@ __device__ __forceinline__ void sell_cols16(const short *__restrict__ col16, int
             cc[2 * t] = row + (int)(short)(pr & 0xffffu);
             cc[2 * t + 1] = row + ((int)pr >> 16);
         } else if (k < len) {
-            cc[2 * t] = row + (int)stream_load(col16 + base + (size_t)paired * kSellC + lane);
+            cc[2 * t] = row + (int)stream_load(as_global(col16 + base + (size_t)paired * kSellC + lane));
         }
     }
 }
@@ -527,13 +552,16 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
                                            int lane, T (&acc)[NX])
 {
     constexpr int B = PPCG_SELL_BATCH;
-    const int64_t base = cptr[chunk];
-    const int len = (int)((cptr[chunk + 1] - base) / kSellC);
+    const int64_t base = as_global(cptr)[chunk];
+    const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
     const int row = chunk * kSellC + lane;
-    const VT *v = val + base + lane;
+    const PPCG_AS1 VT *v = as_global(val + base + lane);
+    const PPCG_AS1 T *xg[NX];
 #pragma unroll
-    for (int q = 0; q < NX; ++q)
+    for (int q = 0; q < NX; ++q) {
         acc[q] = (T)0;
+        xg[q] = as_global(xin[q]);
+    }
     for (int k0 = 0; k0 < len; k0 += B) {
         int cc[B];
         VT vv[B];
@@ -549,7 +577,7 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
             T xx[B];
 #pragma unroll
             for (int j = 0; j < B; ++j)
-                xx[j] = k0 + j < len ? xin[q][cc[j]] : (T)0;
+                xx[j] = k0 + j < len ? xg[q][cc[j]] : (T)0;
 #pragma unroll
             for (int j = 0; j < B; ++j)
                 if (k0 + j < len)
@@ -570,13 +598,13 @@ __device__ __forceinline__ void csrv_row(const int *__restrict__ rp, const int *
     for (int q = 0; q < NX; ++q)
         acc[q] = (T)0;
     if (i < n) {
-        const int e = rp[i + 1];
-        for (int k = rp[i] + l; k < e; k += L) {
-            const T a = (T)stream_load(val + k);
-            const int cc = stream_load(col + k);
+        const int e = as_global(rp)[i + 1];
+        for (int k = as_global(rp)[i] + l; k < e; k += L) {
+            const T a = (T)stream_load(as_global(val + k));
+            const int cc = stream_load(as_global(col + k));
 #pragma unroll
             for (int q = 0; q < NX; ++q)
-                acc[q] = acc[q] + a * xin[q][cc];
+                acc[q] = acc[q] + a * as_global(xin[q])[cc];
         }
     }
 #pragma unroll
@@ -617,43 +645,43 @@ template <typename T, int MODE>
 __device__ __forceinline__ void spmv_epilogue(const SysDesc &d, int i, const T (&y)[SpmvIn<MODE>::NX],
                                               double (&acc)[kReplPartials])
 {
-    const T *DI = (const T *)d.dinv;
+    const PPCG_AS1 T *DI = as_global((const T *)d.dinv);
     if constexpr (MODE == MODE_ITER || MODE == MODE_PLAIN) {
-        ((T *)d.nv)[i] = y[0];
+        as_global((T *)d.nv)[i] = y[0];
     } else if constexpr (MODE == MODE_INIT1 || MODE == MODE_REPL1) {
-        const T bi = ((const T *)d.b)[i];
+        const T bi = as_global((const T *)d.b)[i];
         const T ri = bi - y[0];
         const T ui = DI[i] * ri;
-        ((T *)d.r)[i] = ri;
-        ((T *)d.u)[i] = ui;
+        as_global((T *)d.r)[i] = ri;
+        as_global((T *)d.u)[i] = ui;
         if constexpr (MODE == MODE_INIT1) {
             // z, q, s, p enter the first update multiplied by beta = 0: start
             // them at zero so that stale memory (possibly NaN) cannot leak in.
-            ((T *)d.z)[i] = (T)0;
-            ((T *)d.q)[i] = (T)0;
-            ((T *)d.s)[i] = (T)0;
-            ((T *)d.p)[i] = (T)0;
+            as_global((T *)d.z)[i] = (T)0;
+            as_global((T *)d.q)[i] = (T)0;
+            as_global((T *)d.s)[i] = (T)0;
+            as_global((T *)d.p)[i] = (T)0;
         }
         acc[0] = acc[0] + (double)bi * (double)bi;
     } else if constexpr (MODE == MODE_INIT2) {
-        const T ri = ((const T *)d.r)[i];
-        const T ui = ((const T *)d.u)[i];
+        const T ri = as_global((const T *)d.r)[i];
+        const T ui = as_global((const T *)d.u)[i];
         const T mi = DI[i] * y[0];
-        ((T *)d.w)[i] = y[0];
-        ((T *)d.m)[i] = mi;
+        as_global((T *)d.w)[i] = y[0];
+        as_global((T *)d.m)[i] = mi;
         const double rd = (double)ri, ud = (double)ui, wd = (double)y[0];
         acc[0] = acc[0] + rd * ud;
         acc[1] = acc[1] + wd * ud;
         acc[2] = acc[2] + ud * ud;
         acc[3] = acc[3] + rd * rd;
     } else if constexpr (MODE == MODE_DUAL1) {
-        const T ri = ((const T *)d.r)[i];
-        const T ui = ((const T *)d.u)[i];
-        const T pi = ((const T *)d.p)[i];
-        ((T *)d.w)[i] = y[0];
-        ((T *)d.s)[i] = y[1];
-        ((T *)d.m)[i] = DI[i] * y[0];
-        ((T *)d.q)[i] = DI[i] * y[1];
+        const T ri = as_global((const T *)d.r)[i];
+        const T ui = as_global((const T *)d.u)[i];
+        const T pi = as_global((const T *)d.p)[i];
+        as_global((T *)d.w)[i] = y[0];
+        as_global((T *)d.s)[i] = y[1];
+        as_global((T *)d.m)[i] = DI[i] * y[0];
+        as_global((T *)d.q)[i] = DI[i] * y[1];
         const double rd = (double)ri, ud = (double)ui, wd = (double)y[0], sd = (double)y[1], pd = (double)pi;
         acc[0] = acc[0] + rd * ud;
         acc[1] = acc[1] + wd * ud;
@@ -662,12 +690,12 @@ __device__ __forceinline__ void spmv_epilogue(const SysDesc &d, int i, const T (
         acc[4] = acc[4] + ud * sd;
         acc[5] = acc[5] + pd * sd;
     } else if constexpr (MODE == MODE_DUAL2) {
-        ((T *)d.nv)[i] = y[0];
-        ((T *)d.z)[i] = y[1];
+        as_global((T *)d.nv)[i] = y[0];
+        as_global((T *)d.z)[i] = y[1];
     } else if constexpr (MODE == MODE_RESID) {
-        const T bi = ((const T *)d.b)[i];
+        const T bi = as_global((const T *)d.b)[i];
         const T ti = bi - y[0];
-        ((T *)d.r)[i] = ti;
+        as_global((T *)d.r)[i] = ti;
         acc[0] = acc[0] + (double)ti * (double)ti;
         acc[1] = acc[1] + (double)bi * (double)bi;
     }
@@ -851,8 +879,8 @@ __global__ void k_x_fixup(const WorkItem *__restrict__ table, const int *__restr
     if (!st->x_pending)
         return;
     const T a = (T)st->alpha_x;
-    T *__restrict__ X = (T *)d.x;
-    const T *__restrict__ P = (const T *)d.p;
+    PPCG_AS1 T *__restrict__ X = as_global((T *)d.x);
+    const PPCG_AS1 T *__restrict__ P = as_global((const T *)d.p);
     for (int k = threadIdx.x; k < kTileRows; k += blockDim.x) {
         const int i = wi.tile * kTileRows + k;
         if (i < d.n)

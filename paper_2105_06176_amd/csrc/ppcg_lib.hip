@@ -455,10 +455,13 @@ static ppcg_status time_spmv(ppcg_handle *h, int reps, double *ms);
 // SELL: whether the SpMVs read 16-bit column offsets.  They halve the index
 // bytes but cost an unpack per entry pair and a sub-dword load for an odd
 // tail; on gfx950 that wins for long rows (27-point stencils) and loses for
-// short ones (7-point), so both are timed on the matrix (five SpMVs each,
-// after a warm-up) and the faster is kept.  `known` >= 0 replays a cached
-// decision; PPCG_FLAG_SELL_COL16 / _COL32 force the choice.  Off entirely
-// when PPCG_SELL_COL16 is 0.
+// short ones (7-point), so both are timed on the matrix and the faster is
+// kept.  The two layouts are timed twice in alternation (five SpMVs each
+// time, after a warm-up) and the best of each pair compared; 16-bit offsets
+// must win by 2 %, so that timing noise cannot pick them for a matrix where
+// they are slower.  `known` >= 0 replays a cached decision;
+// PPCG_FLAG_SELL_COL16 / _COL32 force the choice.  Off entirely when
+// PPCG_SELL_COL16 is 0.
 static ppcg_status tune_col16(ppcg_handle *h, int known, int *chosen)
 {
     *chosen = 0;
@@ -468,16 +471,24 @@ static ppcg_status tune_col16(ppcg_handle *h, int known, int *chosen)
         known = 0;
     if (!PPCG_SELL_COL16 || h->fmt != FMT_SELL || known == 0)
         return PPCG_OK;
-    double t32 = 0.0, t16 = 0.0;
-    if (known < 0)
-        PPCG_TRY(time_spmv(h, 5, &t32));
     bool built = false;
     PPCG_TRY(build_col16(h, &built));
     if (!built)
         return PPCG_OK;
     if (known < 0) {
-        PPCG_TRY(time_spmv(h, 5, &t16));
-        if (!(t16 < 0.99 * t32)) {
+        short *c16 = h->col16;
+        double t32 = 1e300, t16 = 1e300;
+        for (int round = 0; round < 2; ++round) {
+            double t = 0.0;
+            h->col16 = nullptr;  // the SpMV reads the 32-bit columns
+            ppcg_status rc = time_spmv(h, 5, &t);
+            h->col16 = c16;
+            PPCG_TRY(rc);
+            t32 = std::min(t32, t);
+            PPCG_TRY(time_spmv(h, 5, &t));
+            t16 = std::min(t16, t);
+        }
+        if (!(t16 < 0.98 * t32)) {
             drop_col16(h);
             return PPCG_OK;
         }

@@ -63,7 +63,7 @@ constexpr int kPcgRedBatch = 4;
 template <int NV>
 __device__ __forceinline__ void pcg_reduce(const SysDesc &d, int slot, double (&out)[NV], double *lds)
 {
-    const double *P = d.part + (size_t)slot * d.ntiles * kPartStride;
+    const PPCG_AS1 double *P = as_global(d.part + (size_t)slot * d.ntiles * kPartStride);
 #pragma unroll
     for (int k = 0; k < NV; ++k)
         out[k] = 0.0;
@@ -98,13 +98,14 @@ __device__ __forceinline__ T *pcg_dir(const SysDesc &d, int k)
 // C16: 16-bit column offsets (the SELL pair layout) instead of 32-bit columns.
 template <bool C16, typename T, typename VT>
 __device__ __forceinline__ T pcg_sell_row(const SysDesc &d, const VT *__restrict__ val, int chunk, int lane,
-                                          T beta, const T *__restrict__ U, const T *__restrict__ Pold)
+                                          T beta, const PPCG_AS1 T *__restrict__ U,
+                                          const PPCG_AS1 T *__restrict__ Pold)
 {
     constexpr int B = 8;
-    const int64_t base = d.cptr[chunk];
-    const int len = (int)((d.cptr[chunk + 1] - base) / kSellC);
-    const int *c = d.col + base + lane;
-    const VT *v = val + base + lane;
+    const int64_t base = as_global(d.cptr)[chunk];
+    const int len = (int)((as_global(d.cptr)[chunk + 1] - base) / kSellC);
+    const PPCG_AS1 int *c = as_global(d.col + base + lane);
+    const PPCG_AS1 VT *v = as_global(val + base + lane);
     T y = 0;
     for (int k0 = 0; k0 < len; k0 += B) {
         int cc[B];
@@ -143,8 +144,9 @@ __device__ __forceinline__ T pcg_sell_row(const SysDesc &d, const VT *__restrict
 // returns this thread's share of (s, p).
 template <typename T, typename VT>
 __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem wi, const VT *__restrict__ val,
-                                                T beta, const T *__restrict__ U, const T *__restrict__ Pold,
-                                                T *__restrict__ Pnew, T *__restrict__ S)
+                                                T beta, const PPCG_AS1 T *__restrict__ U,
+                                                const PPCG_AS1 T *__restrict__ Pold, PPCG_AS1 T *__restrict__ Pnew,
+                                                PPCG_AS1 T *__restrict__ S)
 {
     const int n = d.n;
     double acc = 0.0;
@@ -174,10 +176,10 @@ __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem
             const int i = wi.tile * kTileRows + pass * rows_per_pass + g;
             T y = 0;
             if (i < n) {
-                const int e = d.rp[i + 1];
-                for (int k = d.rp[i] + l; k < e; k += L) {
-                    const int cc = stream_load(d.col + k);
-                    y = y + (T)stream_load(val + k) * (U[cc] + beta * Pold[cc]);
+                const int e = as_global(d.rp)[i + 1];
+                for (int k = as_global(d.rp)[i] + l; k < e; k += L) {
+                    const int cc = stream_load(as_global(d.col + k));
+                    y = y + (T)stream_load(as_global(val + k)) * (U[cc] + beta * Pold[cc]);
                 }
             }
             for (int off = L >> 1; off >= 1; off >>= 1)
@@ -213,13 +215,13 @@ __global__ __launch_bounds__(kSpmvThreads, 8) void k_pcg_spmv(const WorkItem *__
         return;
     const T beta = (T)st->beta;
     const int k = st->iter;
-    const T *U = (const T *)d.u;
+    const PPCG_AS1 T *U = as_global((const T *)d.u);
     // beta = 0 (a start, or a restart after a breakdown): read u in place of
     // the old direction, so that whatever that buffer holds cannot leak in
     // through 0 * Inf or 0 * NaN; u + 0 u = u exactly.
-    const T *Pold = beta == (T)0 ? U : pcg_dir<T>(d, k);
-    T *Pnew = pcg_dir<T>(d, k + 1);
-    T *S = (T *)d.s;
+    const PPCG_AS1 T *Pold = beta == (T)0 ? U : as_global((const T *)pcg_dir<T>(d, k));
+    PPCG_AS1 T *Pnew = as_global(pcg_dir<T>(d, k + 1));
+    PPCG_AS1 T *S = as_global((T *)d.s);
     double v[1];
     // FP32 vectors come with FP32 values (d.val); FP64 vectors use the FP32
     // copy in FP32-values mode.
@@ -333,12 +335,12 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
     if (st->done)
         return;
     const T alpha = (T)st->alpha;
-    T *__restrict__ X = (T *)d.x;
-    T *__restrict__ R = (T *)d.r;
-    T *__restrict__ U = (T *)d.u;
-    const T *__restrict__ P = pcg_dir<T>(d, st->iter + 1);
-    const T *__restrict__ S = (const T *)d.s;
-    const T *__restrict__ DI = (const T *)d.dinv;
+    PPCG_AS1 T *__restrict__ X = as_global((T *)d.x);
+    PPCG_AS1 T *__restrict__ R = as_global((T *)d.r);
+    PPCG_AS1 T *__restrict__ U = as_global((T *)d.u);
+    const PPCG_AS1 T *__restrict__ P = as_global((const T *)pcg_dir<T>(d, st->iter + 1));
+    const PPCG_AS1 T *__restrict__ S = as_global((const T *)d.s);
+    const PPCG_AS1 T *__restrict__ DI = as_global((const T *)d.dinv);
     double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
     auto elem = [&](T &x, T &r, T &u, T p, T sv, T di) {
         x = x + alpha * p;
@@ -351,10 +353,12 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
     };
     const int i = wi.tile * kTileRows + threadIdx.x * 2;
     if (i + 1 < d.n) {
-        V2 x = vload((const V2 *)(X + i)), r = vload((const V2 *)(R + i));
-        const V2 p = vload((const V2 *)(P + i)), sv = vload((const V2 *)(S + i));
+        using CV2 = const PPCG_AS1 V2;
+        using GV2 = PPCG_AS1 V2;
+        V2 x = vload((CV2 *)(X + i)), r = vload((CV2 *)(R + i));
+        const V2 p = vload((CV2 *)(P + i)), sv = vload((CV2 *)(S + i));
         // a constant diagonal: every lane reads dinv[0..1] (one cached line)
-        const V2 di = vload((const V2 *)(DI + (d.dinv_const ? 0 : i)));
+        const V2 di = vload((CV2 *)(DI + (d.dinv_const ? 0 : i)));
         V2 u;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -364,9 +368,9 @@ __global__ __launch_bounds__(kVmaThreads) void k_pcg_vma(const WorkItem *__restr
             r[j] = rj;
             u[j] = uj;
         }
-        vstore((V2 *)(X + i), x);
-        vstore((V2 *)(R + i), r);
-        vstore((V2 *)(U + i), u);
+        vstore((GV2 *)(X + i), x);
+        vstore((GV2 *)(R + i), r);
+        vstore((GV2 *)(U + i), u);
     } else if (i < d.n) {
         T x = X[i], r = R[i], u;
         elem(x, r, u, P[i], S[i], DI[d.dinv_const ? 0 : i]);
