@@ -37,10 +37,15 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank space removed, so a
+    comment edit does not invalidate the stored counter figures."""
     h = hashlib.sha256()
     for f in ("ppcg_kernels.hpp", "ppcg_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2105_06176_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2105_06176_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -3,11 +3,14 @@
 // The iteration of Algorithm 2 (Tiwari & Vadhiyar, Section III-B) runs as two
 // launches over a table of (system, tile) work items:
 //
-//   k_vma   the eight vector recurrences z, q, s, p, x, r, u, w, the Jacobi
+//   k_vma   the vector recurrences of z, s, p, x, r, w, the Jacobi
 //           preconditioner m = M^-1 w and the partial sums of (r,u), (w,u),
 //           (u,u), (r,r), all in one pass over the vectors (Section V-B:
-//           fused VMAs with the preconditioner folded in).  Each workgroup
-//           writes one partial per dot product.
+//           fused VMAs with the preconditioner folded in).  With a diagonal
+//           M, u = M^-1 r and q = M^-1 s are formed from r and s instead of
+//           being carried as vectors, and x-updates are applied two at a
+//           time (see vma_elem).  Each workgroup writes one partial per dot
+//           product.
 //   k_spmv  n = A m (the SpMV), plus, in the designated workgroup of each
 //           system (its tile 0), the fixed-order reduction of that system's
 //           partials and the scalar recurrences: beta, alpha, the stopping
