@@ -589,6 +589,64 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
     }
 }
 
+// sell_row16 software-pipelined across batches: the gathers of batch k are
+// issued before the column and value loads of batch k + 1, so the wait for
+// the gathers leaves the next batch's loads in flight.  Same products, same
+// order of the sums.
+template <typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_row16_pipe(const int64_t *__restrict__ cptr, const short *__restrict__ col16,
+                                                const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
+                                                int lane, T (&acc)[NX])
+{
+    constexpr int B = PPCG_SELL_PIPE_BATCH;  // two batches in flight: smaller than the plain batch
+    const int64_t base = as_global(cptr)[chunk];
+    const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
+    const int row = chunk * kSellC + lane;
+    const PPCG_AS1 VT *v = as_global(val + base + lane);
+    const PPCG_AS1 T *xg[NX];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+        acc[q] = (T)0;
+        xg[q] = as_global(xin[q]);
+    }
+    int cc[B];
+    VT vv[B];
+    auto load_batch = [&](int k0, int (&c)[B], VT (&w)[B]) {
+        sell_cols16<B>(col16, base, len, k0, lane, row, c);
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            w[j] = (VT)0;
+            if (k0 + j < len)
+                w[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
+        }
+    };
+    if (len > 0)
+        load_batch(0, cc, vv);
+    for (int k0 = 0; k0 < len; k0 += B) {
+        T xx[NX][B];
+#pragma unroll
+        for (int q = 0; q < NX; ++q)
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                xx[q][j] = k0 + j < len ? xg[q][cc[j]] : (T)0;
+        int cn[B];
+        VT vn[B];
+        if (k0 + B < len)
+            load_batch(k0 + B, cn, vn);
+#pragma unroll
+        for (int q = 0; q < NX; ++q)
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                if (k0 + j < len)
+                    acc[q] = acc[q] + (T)vv[j] * xx[q][j];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            cc[j] = cn[j];
+            vv[j] = vn[j];
+        }
+    }
+}
+
 // CSR-vector: a group of L lanes per row (L a power of two in [2, 64]); lane
 // k of the group sums entries k, k + L, ... and the group combines its lanes
 // with a butterfly.  Result valid in every lane of the group.
@@ -761,7 +819,11 @@ __device__ __forceinline__ void spmv_tile(const SysDesc &d, const VT *__restrict
         const int i = chunk * kSellC + lane;
         if (chunk * kSellC < n) {
             if (d.col16)  // uniform per system
+#if PPCG_SELL_PIPE
+                sell_row16_pipe<VT, T, NX>(d.cptr, d.col16, val, xin, chunk, lane, y);
+#else
                 sell_row16<VT, T, NX>(d.cptr, d.col16, val, xin, chunk, lane, y);
+#endif
             else
                 sell_row<VT, T, NX>(d.cptr, d.col, val, xin, chunk, lane, y);
             if (i < n)
