@@ -410,13 +410,18 @@ ppcg_status ppcg_hybrid_solve(ppcg_hybrid *hy, const double *b, const double *x0
 ppcg_status ppcg_hybrid_destroy(ppcg_hybrid *hy); /* NULL-safe */
 
 /* ---------------------------------------------------------------------------
- * Serving: a continuous-batching solve server.  Requests are admitted while
- * the sum of their device footprints (ppcg_footprint_bytes) stays within the
- * budget; admitted requests join the batched iteration at the next graph
- * boundary and leave it when they finish, so requests that arrive while
- * others run overlap with them on the device.  Each request's arithmetic is
- * independent of the others in the mix: its result is bitwise identical to
- * a solo ppcg_solve of the same request with the same options.
+ * Serving: a continuous-batching solve server.  A thread owned by the
+ * server prepares queued requests first-come first-served (matrix copied to
+ * the device, validated and laid out, right-hand side staged) while the sum
+ * of the device footprints (ppcg_footprint_bytes) of the requests it holds
+ * stays within the budget, and releases the memory of retired ones; both
+ * overlap with the iterations of the active requests.  Prepared requests
+ * join the batched iteration at the next graph boundary and leave it when
+ * they finish, so requests that arrive while others run overlap with them on
+ * the device.  Each request's arithmetic is independent of the others in the
+ * mix: its result is bitwise identical to a solo ppcg_solve of the same
+ * request with the same options.  The calls on one server must not overlap
+ * (one calling thread at a time).
  * ------------------------------------------------------------------------- */
 typedef struct ppcg_server ppcg_server;
 
@@ -434,9 +439,12 @@ ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *
 ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, double tol,
                             ppcg_precision precision, int64_t *req_id);
 
-/* Advance the server: admit queued requests that fit, run one graph chunk of
- * iterations over every active request, retire finished ones.  *active and
- * *queued (may be NULL) receive the counts after the step. */
+/* Advance the server: admit the prepared requests, run one graph chunk of
+ * iterations over every active request, retire finished ones.  With no
+ * active request it first waits until a queued request is prepared (or has
+ * failed on its own).  *active and *queued (may be NULL) receive the counts
+ * after the step; queued counts the requests not yet admitted.  A device
+ * error met while preparing a request is returned by the next step. */
 ppcg_status ppcg_srv_step(ppcg_server *s, int32_t *active, int32_t *queued);
 
 /* Fetch a finished request.  Returns PPCG_NOT_CONVERGED with *ready = 0 when

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <map>
 #include <string>
+#include <mutex>
+#include <shared_mutex>
 #include <vector>
 
 #include "../../include/ppcg.h"
@@ -36,6 +38,23 @@ void clear_error();
         if (s_ < 0)                           \
             return s_;                        \
     } while (0)
+
+// ---------------------------------------------------------------- releases
+// Releasing device or pinned host memory synchronizes the whole device, and
+// a device synchronization while another thread captures a graph invalidates
+// that capture.  Every release in the library therefore holds this lock
+// shared, and a graph capture holds it exclusively.
+std::shared_mutex &release_mu();
+inline hipError_t dev_free(void *p)
+{
+    std::shared_lock<std::shared_mutex> lk(release_mu());
+    return hipFree(p);
+}
+inline hipError_t host_free(void *p)
+{
+    std::shared_lock<std::shared_mutex> lk(release_mu());
+    return hipHostFree(p);
+}
 
 // ---------------------------------------------------------------- device buffers
 // A single device allocation cut into 256-byte aligned pieces.

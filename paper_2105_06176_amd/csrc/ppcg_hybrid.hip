@@ -692,9 +692,9 @@ ppcg_status ppcg_hybrid_destroy(ppcg_hybrid *hy)
     if (hy->gs)
         ppcg_shard_destroy(hy->gs);
     hy->arena.release();
-    if (hy->pin_to_host) (void)hipHostFree(hy->pin_to_host);
-    if (hy->pin_to_dev) (void)hipHostFree(hy->pin_to_dev);
-    if (hy->pin_red) (void)hipHostFree(hy->pin_red);
+    if (hy->pin_to_host) (void)host_free(hy->pin_to_host);
+    if (hy->pin_to_dev) (void)host_free(hy->pin_to_dev);
+    if (hy->pin_red) (void)host_free(hy->pin_red);
     if (hy->ev_halo) (void)hipEventDestroy(hy->ev_halo);
     if (hy->cstream) {
         (void)hipStreamSynchronize(hy->cstream);
@@ -702,7 +702,7 @@ ppcg_status ppcg_hybrid_destroy(ppcg_hybrid *hy)
     }
     if (hy->ev_upd) (void)hipEventDestroy(hy->ev_upd);
     if (hy->ev_copy) (void)hipEventDestroy(hy->ev_copy);
-    if (hy->pin_vec) (void)hipHostFree(hy->pin_vec);
+    if (hy->pin_vec) (void)host_free(hy->pin_vec);
     delete hy;
     return PPCG_OK;
 }
@@ -774,8 +774,8 @@ ppcg_status ppcg_hybrid_create(const ppcg_csr *A, const ppcg_options *opt, ppcg_
         double ms1 = 0.0, msg = 0.0, ms2 = 0.0;
         ppcg_status rc = e == hipSuccess ? ppcg_shard_time(full, dxv, dxv, dxv, dyv, 5, &ms1, &msg, &ms2)
                                          : PPCG_ERR_DEVICE;
-        (void)hipFree(dxv);
-        (void)hipFree(dyv);
+        (void)dev_free(dxv);
+        (void)dev_free(dyv);
         PPCG_TRY(rc);
         hy->t_gpu = ms1 * 1e-3;
         const int T = hy->pool->size();

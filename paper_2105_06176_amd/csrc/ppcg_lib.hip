@@ -32,6 +32,12 @@ namespace ppcg {
 // ---------------------------------------------------------------- errors
 static thread_local std::string g_err;
 
+std::shared_mutex &release_mu()
+{
+    static std::shared_mutex m;
+    return m;
+}
+
 void set_error(const char *fmt, ...)
 {
     char buf[1024];
@@ -81,7 +87,7 @@ void *DevArena::take(size_t bytes)
 void DevArena::release()
 {
     if (base)
-        (void)hipFree(base);
+        (void)dev_free(base);
     base = nullptr;
     size = used = 0;
 }
@@ -162,11 +168,11 @@ struct SellBuild {
     int *perm = nullptr, *invperm = nullptr;
     void free_all()
     {
-        if (cptr) (void)hipFree(cptr);
-        if (col) (void)hipFree(col);
-        if (val) (void)hipFree(val);
-        if (perm) (void)hipFree(perm);
-        if (invperm) (void)hipFree(invperm);
+        if (cptr) (void)dev_free(cptr);
+        if (col) (void)dev_free(col);
+        if (val) (void)dev_free(val);
+        if (perm) (void)dev_free(perm);
+        if (invperm) (void)dev_free(invperm);
         *this = SellBuild();
     }
 };
@@ -189,9 +195,9 @@ static ppcg_status sell_size(hipStream_t s, int n, int sigma, const int *rowlen,
     int *perm = nullptr;
     int64_t *sz = nullptr, *cp = nullptr;
     auto clean = [&]() {
-        if (perm) (void)hipFree(perm);
-        if (sz) (void)hipFree(sz);
-        if (cp) (void)hipFree(cp);
+        if (perm) (void)dev_free(perm);
+        if (sz) (void)dev_free(sz);
+        if (cp) (void)dev_free(cp);
     };
     PPCG_HIP_CLEAN(hipMalloc(&sz, sizeof(int64_t) * nchunks), clean());
     PPCG_HIP_CLEAN(hipMalloc(&cp, sizeof(int64_t) * (nchunks + 1)), clean());
@@ -215,7 +221,7 @@ static ppcg_status build_sell(hipStream_t s, int n, int sigma, const int *rp, co
     sb.nchunks = (n + kSellC - 1) / kSellC;
     int64_t *sz = nullptr;
     auto clean = [&]() {
-        if (sz) (void)hipFree(sz);
+        if (sz) (void)dev_free(sz);
         sb.free_all();
     };
     PPCG_HIP_CLEAN(hipMalloc(&sz, sizeof(int64_t) * sb.nchunks), clean());
@@ -236,7 +242,7 @@ static ppcg_status build_sell(hipStream_t s, int n, int sigma, const int *rp, co
     k_sell_fill<<<blocks_for((size_t)sb.nchunks * kSellC, 256), 256, 0, s>>>(
         n, sb.nchunks, rp, ci, val, sb.perm, sb.invperm, sb.cptr, sb.col, sb.val);
     PPCG_HIP_CLEAN(hipGetLastError(), clean());
-    (void)hipFree(sz);
+    (void)dev_free(sz);
     sz = nullptr;
     *out = sb;
     return PPCG_OK;
@@ -336,10 +342,10 @@ static ppcg_status plain_setup(ppcg_handle *h, double tol, int fixed, int maxit)
 
 static void plain_free(ppcg_handle *h)
 {
-    if (h->plain_desc) (void)hipFree(h->plain_desc);
-    if (h->plain_st) (void)hipFree(h->plain_st);
-    if (h->plain_tab) (void)hipFree(h->plain_tab);
-    if (h->plain_cnt) (void)hipFree(h->plain_cnt);
+    if (h->plain_desc) (void)dev_free(h->plain_desc);
+    if (h->plain_st) (void)dev_free(h->plain_st);
+    if (h->plain_tab) (void)dev_free(h->plain_tab);
+    if (h->plain_cnt) (void)dev_free(h->plain_cnt);
     h->plain_desc = nullptr;
     h->plain_st = nullptr;
     h->plain_tab = nullptr;
@@ -375,15 +381,15 @@ static ppcg_status time_spmv(ppcg_handle *h, int reps, double *ms)
 
 static void free_matrix(ppcg_handle *h)
 {
-    if (h->cptr) (void)hipFree(h->cptr);
-    if (h->rp) (void)hipFree(h->rp);
-    if (h->col) (void)hipFree(h->col);
-    if (h->col16) (void)hipFree(h->col16);
+    if (h->cptr) (void)dev_free(h->cptr);
+    if (h->rp) (void)dev_free(h->rp);
+    if (h->col) (void)dev_free(h->col);
+    if (h->col16) (void)dev_free(h->col16);
     h->col16 = nullptr;
-    if (h->val64) (void)hipFree(h->val64);
-    if (h->val32) (void)hipFree(h->val32);
-    if (h->perm) (void)hipFree(h->perm);
-    if (h->invperm) (void)hipFree(h->invperm);
+    if (h->val64) (void)dev_free(h->val64);
+    if (h->val32) (void)dev_free(h->val32);
+    if (h->perm) (void)dev_free(h->perm);
+    if (h->invperm) (void)dev_free(h->invperm);
     h->cptr = nullptr;
     h->rp = h->col = h->perm = h->invperm = nullptr;
     h->val64 = nullptr;
@@ -432,9 +438,9 @@ static ppcg_status build_col16(ppcg_handle *h, bool *built)
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (flag)
-        (void)hipFree(flag);
+        (void)dev_free(flag);
     if (e != hipSuccess || nofit) {
-        (void)hipFree(c16);
+        (void)dev_free(c16);
         c16 = nullptr;
     }
     PPCG_HIP(e);
@@ -446,7 +452,7 @@ static ppcg_status build_col16(ppcg_handle *h, bool *built)
 static void drop_col16(ppcg_handle *h)
 {
     if (h->col16)
-        (void)hipFree(h->col16);
+        (void)dev_free(h->col16);
     h->col16 = nullptr;
 }
 
@@ -705,17 +711,17 @@ Engine::~Engine()
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
     for (Group *g : {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_}) {
         drop_graphs(*g);
-        if (g->desc_d) (void)hipFree(g->desc_d);
-        if (g->st_d) (void)hipFree(g->st_d);
-        if (g->st_h) (void)hipHostFree(g->st_h);
-        if (g->table_d) (void)hipFree(g->table_d);
-        if (g->count_d) (void)hipFree(g->count_d);
-        if (g->aux_d) (void)hipFree(g->aux_d);
-        if (g->aux_count_d) (void)hipFree(g->aux_count_d);
-        if (g->sys_d) (void)hipFree(g->sys_d);
-        if (g->sys_count_d) (void)hipFree(g->sys_count_d);
-        if (g->stage_h) (void)hipHostFree(g->stage_h);
-        if (g->stage_cnt_h) (void)hipHostFree(g->stage_cnt_h);
+        if (g->desc_d) (void)dev_free(g->desc_d);
+        if (g->st_d) (void)dev_free(g->st_d);
+        if (g->st_h) (void)host_free(g->st_h);
+        if (g->table_d) (void)dev_free(g->table_d);
+        if (g->count_d) (void)dev_free(g->count_d);
+        if (g->aux_d) (void)dev_free(g->aux_d);
+        if (g->aux_count_d) (void)dev_free(g->aux_count_d);
+        if (g->sys_d) (void)dev_free(g->sys_d);
+        if (g->sys_count_d) (void)dev_free(g->sys_count_d);
+        if (g->stage_h) (void)host_free(g->stage_h);
+        if (g->stage_cnt_h) (void)host_free(g->stage_cnt_h);
     }
 }
 
@@ -783,7 +789,7 @@ static ppcg_status grow_table(WorkItem **d, int *cap, int need)
     int nc = std::max(need, *cap * 2);
     nc = std::max(nc, 64);
     if (*d)
-        (void)hipFree(*d);
+        (void)dev_free(*d);
     *d = nullptr;
     PPCG_HIP(hipMalloc(d, sizeof(WorkItem) * nc));
     *cap = nc;
@@ -798,7 +804,7 @@ static ppcg_status upload_table(hipStream_t s, Group &g, const std::vector<WorkI
     const int n = (int)items.size();
     if (g.stage_cap < n + 1) {
         if (g.stage_h)
-            (void)hipHostFree(g.stage_h);
+            (void)host_free(g.stage_h);
         g.stage_h = nullptr;
         g.stage_cap = std::max(2 * n + 1, 256);
         // three regions: iteration table, aux table, system table
@@ -897,6 +903,7 @@ ppcg_status Engine::ensure_graph(Group &g, int iters, hipGraphExec_t *exec)
     const int grid = g.g_grid ? g.g_grid : need;
     if (g.pcg && !g.g_sys_grid)
         g.g_sys_grid = need_sys;
+    std::unique_lock<std::shared_mutex> no_release(release_mu());
     Group::CapturedGraph cg;
     PPCG_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < iters; ++i)
@@ -1610,7 +1617,7 @@ static void destroy_handle(ppcg_handle *h)
     plain_free(h);
     free_matrix(h);
     if (h->dinv64)
-        (void)hipFree(h->dinv64);
+        (void)dev_free(h->dinv64);
     h->f64.arena.release();
     h->f32.arena.release();
     if (h->stream)
@@ -1649,13 +1656,13 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
     bool own_csr = false;
     auto fail = [&](ppcg_status s) {
         if (own_csr) {
-            if (rp) (void)hipFree(rp);
-            if (ci) (void)hipFree(ci);
-            if (val) (void)hipFree(val);
+            if (rp) (void)dev_free(rp);
+            if (ci) (void)dev_free(ci);
+            if (val) (void)dev_free(val);
         }
-        if (rowlen) (void)hipFree(rowlen);
-        if (dinv_orig) (void)hipFree(dinv_orig);
-        if (err) (void)hipFree(err);
+        if (rowlen) (void)dev_free(rowlen);
+        if (dinv_orig) (void)dev_free(dinv_orig);
+        if (err) (void)dev_free(err);
         destroy_handle(h);
         return s;
     };
@@ -1727,7 +1734,10 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
         return fail(PPCG_ERR_BAD_CSR);
     }
     std::vector<int> rowlen_h(n);
-    CK(hipMemcpy(rowlen_h.data(), rowlen, sizeof(int) * n, hipMemcpyDeviceToHost));
+    // on the handle's stream: a copy on the null stream synchronizes with the
+    // device and would invalidate a graph capture under way in another thread
+    CK(hipMemcpyAsync(rowlen_h.data(), rowlen, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
     {
         // A constant diagonal makes M^-1 a multiple of the identity: the fused
         // updates then read dinv[0] for every row (one cached line) instead
@@ -1748,13 +1758,13 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
         CKS(ensure_val32(h));
     CK(hipStreamSynchronize(s));
     if (own_csr) {
-        (void)hipFree(rp);
-        (void)hipFree(ci);
-        (void)hipFree(val);
+        (void)dev_free(rp);
+        (void)dev_free(ci);
+        (void)dev_free(val);
     }
-    (void)hipFree(rowlen);
-    (void)hipFree(dinv_orig);
-    (void)hipFree(err);
+    (void)dev_free(rowlen);
+    (void)dev_free(dinv_orig);
+    (void)dev_free(err);
     h->setup_ms = now_ms() - t0;
     *out = h;
     return PPCG_OK;

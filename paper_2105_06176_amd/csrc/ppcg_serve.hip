@@ -1,23 +1,33 @@
 // ppcg_serve.hip -- continuous-batching solve server (ppcg_srv_* in ppcg.h).
 //
-// Requests queue on the host.  Each scheduling step admits queued requests
-// first-come first-served while the sum of their device footprints stays
-// within the budget (and the engine has free slots), then runs one graph
-// chunk of PIPECG iterations over every active request through the shared
-// batched engine, and retires requests that finished: their solution is
-// copied back to the host and their device memory released.  Requests that
-// arrive while others are on the device therefore join the batched launches
-// at the next chunk boundary and overlap with them.  A request's arithmetic
-// is independent of the mix: it owns its tiles, partial sums and scalars.
+// Requests queue on the host.  A preparation thread owned by the server
+// takes them first-come first-served while the sum of the device footprints
+// of the requests it holds (in preparation, prepared, or on the device) stays
+// within the budget, and prepares each one on a stream of its own: the
+// matrix is copied to the device, validated and laid out (ppcg_create) and
+// the right-hand side staged.  Each scheduling step admits the prepared
+// requests in the same order into the shared batched engine, runs one graph
+// chunk of PIPECG iterations over every active request, and retires the
+// requests that finished: their solution is copied back to the host, and the
+// preparation thread releases their device memory.  Preparation and release
+// therefore overlap with the iterations of the requests already on the
+// device (releasing memory synchronizes the device), and requests that arrive
+// while others iterate join the batched launches at the next chunk
+// boundary.  A request's arithmetic is independent of the mix: it owns its
+// tiles, partial sums and scalars.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "ppcg_engine.hpp"
@@ -38,9 +48,11 @@ constexpr int kServeGraphIters = 32;
 constexpr int kAutoValues32Rows = PPCG_AUTO_VALUES32_ROWS;
 constexpr int kAutoPcg32Rows = PPCG_AUTO_PCG32_ROWS;
 
+enum ReqState { RQ_QUEUED, RQ_PREPARING, RQ_PREPARED, RQ_ACTIVE, RQ_DONE };
+
 struct Request {
     int64_t id = 0;
-    int state = 0;  // 0 queued, 1 active, 2 finished
+    ReqState state = RQ_QUEUED;
     double footprint = 0.0;
     double tol = 0.0;
     ppcg_precision precision = PPCG_FP64;
@@ -56,67 +68,168 @@ struct Request {
     ppcg_handle *h = nullptr;
     int job = -1;
     ppcg_info info{};
-    ppcg_status create_status = PPCG_OK;
 };
 
 }  // namespace
 
+// Ownership: the preparation thread alone touches a request in state
+// RQ_PREPARING; the calling thread alone touches one in RQ_PREPARED or
+// RQ_ACTIVE.  The map, both queues, the counters and every state change are
+// guarded by `mu`.
 struct ppcg_server {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // the engine's stream
+    hipStream_t prep_stream = nullptr;  // orders each preparation (its handle has a stream of its own)
+    int device = 0;
     ppcg_options defaults{};
     double budget = 0.0;
-    double used = 0.0;
     int64_t next_id = 1;
     std::unique_ptr<Engine> eng;
+    std::mutex mu;
+    std::condition_variable prep_cv;   // wakes the preparation thread
+    std::condition_variable ready_cv;  // wakes a step that waits for a prepared request
     std::map<int64_t, Request> reqs;
-    std::deque<int64_t> queue;
+    std::deque<int64_t> queue;  // awaiting preparation, first come first served
+    std::deque<int64_t> ready;  // prepared, awaiting admission, in the same order
+    // handles of retired requests with their footprints, released by the
+    // preparation thread (a release synchronizes the device)
+    std::vector<std::pair<ppcg_handle *, double>> retired;
+    double used = 0.0;          // footprints of the handles in preparation, prepared, active or retired
+    int preparing = 0;
     int active = 0;
+    bool stop = false;
+    ppcg_status prep_rc = PPCG_OK;  // a device error met while preparing, reported by the next step
+    std::string prep_msg;
+    std::thread prep;
 };
 
-static ppcg_status admit(ppcg_server *s)
+// The preparation thread may take the first queued request: within the slot
+// count, and within the budget unless nothing else holds device memory.
+static bool can_prepare(const ppcg_server *s)
 {
-    while (!s->queue.empty() && s->active < kServerSlots) {
-        Request &r = s->reqs[s->queue.front()];
-        if (s->used + r.footprint > s->budget && s->active > 0)
-            break;  // wait for memory to free up (first come, first served)
-        s->queue.pop_front();
-        ppcg_options o = s->defaults;
-        o.tol = r.tol;
-        o.precision = r.precision;
-        o.method = r.method;
-        o.vec_mem = PPCG_MEM_HOST;
-        o.fixed_iters = 0;
-        ppcg_csr A{};
-        A.struct_size = sizeof A;
-        A.n = r.n;
-        A.nnz = r.nnz;
-        A.row_ptr = r.rp_p;
-        A.col_idx = r.ci_p;
-        A.values = r.val_p;
-        A.mem = PPCG_MEM_HOST;
-        ppcg_status rc = ppcg_create(&A, &o, s->stream, &r.h);
-        if (rc != PPCG_OK) {
-            // The request fails on its own; the server keeps going.
-            r.state = 2;
-            r.create_status = rc;
-            memset(&r.info, 0, sizeof r.info);
-            r.info.struct_size = sizeof r.info;
-            r.info.status = rc;
+    if (s->stop || s->prep_rc != PPCG_OK || s->queue.empty())
+        return false;
+    const int held = s->active + (int)s->ready.size() + s->preparing;
+    if (held >= kServerSlots)
+        return false;
+    const Request &r = s->reqs.at(s->queue.front());
+    return held == 0 || s->used + r.footprint <= s->budget;
+}
+
+// Copy the request's matrix and right-hand side to the device (runs on the
+// preparation thread, unlocked).  A request whose matrix ppcg_create refuses
+// fails on its own; a device error is returned.
+static ppcg_status prepare(ppcg_server *s, Request &r)
+{
+    ppcg_options o = s->defaults;
+    o.tol = r.tol;
+    o.precision = r.precision;
+    o.method = r.method;
+    o.vec_mem = PPCG_MEM_HOST;
+    o.fixed_iters = 0;
+    ppcg_csr A{};
+    A.struct_size = sizeof A;
+    A.n = r.n;
+    A.nnz = r.nnz;
+    A.row_ptr = r.rp_p;
+    A.col_idx = r.ci_p;
+    A.values = r.val_p;
+    A.mem = PPCG_MEM_HOST;
+    ppcg_status rc = ppcg_create(&A, &o, s->prep_stream, &r.h);
+    if (rc != PPCG_OK) {
+        r.h = nullptr;
+        memset(&r.info, 0, sizeof r.info);
+        r.info.struct_size = sizeof r.info;
+        r.info.status = rc;
+        return PPCG_OK;
+    }
+    // a rerun (automatic precision fallback) starts from the last iterate
+    rc = stage_inputs(r.h, r.b_p, r.x.empty() ? nullptr : r.x.data());
+    if (rc == PPCG_OK && hipStreamSynchronize(r.h->stream) != hipSuccess) {
+        set_error("staging the right-hand side failed");
+        rc = PPCG_ERR_DEVICE;
+    }
+    if (rc != PPCG_OK) {
+        ppcg_destroy(r.h);
+        r.h = nullptr;
+    }
+    return rc;
+}
+
+static void prep_loop(ppcg_server *s)
+{
+    const bool dev_ok = hipSetDevice(s->device) == hipSuccess;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (!dev_ok) {
+        s->prep_rc = PPCG_ERR_DEVICE;
+        s->prep_msg = "hipSetDevice failed on the preparation thread";
+        s->ready_cv.notify_all();
+        return;
+    }
+    for (;;) {
+        s->prep_cv.wait(lk, [s] { return s->stop || !s->retired.empty() || can_prepare(s); });
+        if (!s->retired.empty()) {
+            std::vector<std::pair<ppcg_handle *, double>> done;
+            done.swap(s->retired);
+            lk.unlock();
+            for (auto &e : done)
+                ppcg_destroy(e.first);
+            lk.lock();
+            for (auto &e : done)
+                s->used -= e.second;
             continue;
         }
-        PPCG_TRY(wait_user(r.h));
-        hipStream_t keep = r.h->stream;
-        r.h->stream = s->eng->stream();
-        // a rerun (automatic precision fallback) starts from the last iterate
-        rc = stage_inputs(r.h, r.b_p, r.x.empty() ? nullptr : r.x.data());
-        r.h->stream = keep;
-        PPCG_TRY(rc);
+        if (s->stop)
+            return;
+        const int64_t id = s->queue.front();
+        s->queue.pop_front();
+        Request &r = s->reqs.at(id);  // map nodes stay put while others come and go
+        r.state = RQ_PREPARING;
+        s->used += r.footprint;
+        ++s->preparing;
+        lk.unlock();
+        const ppcg_status rc = prepare(s, r);
+        std::string msg = rc == PPCG_OK ? std::string() : std::string(ppcg_last_error());
+        lk.lock();
+        --s->preparing;
+        if (r.h) {
+            r.state = RQ_PREPARED;
+            s->ready.push_back(id);
+        } else {
+            s->used -= r.footprint;
+            r.state = RQ_DONE;
+            if (rc != PPCG_OK) {
+                r.info.struct_size = sizeof r.info;
+                r.info.status = rc;
+                s->prep_rc = rc;
+                s->prep_msg = msg;
+            }
+        }
+        s->ready_cv.notify_all();
+    }
+}
+
+// Admit the prepared requests (calling thread, under `mu`).
+static ppcg_status admit(ppcg_server *s)
+{
+    while (!s->ready.empty()) {
+        Request &r = s->reqs.at(s->ready.front());
+        s->ready.pop_front();
         const int mixed = r.precision == PPCG_MIXED_FP32          ? MIX_INNER32
                           : r.precision == PPCG_MIXED_FP32_VALUES ? MIX_VALUES32
                                                                   : MIX_NONE;
-        PPCG_TRY(s->eng->add(r.h, mixed, r.tol, nullptr, &r.job));
-        r.state = 1;
-        s->used += r.footprint;
+        ppcg_status rc = s->eng->add(r.h, mixed, r.tol, nullptr, &r.job);
+        if (rc != PPCG_OK) {
+            ppcg_destroy(r.h);
+            r.h = nullptr;
+            s->used -= r.footprint;
+            r.state = RQ_DONE;
+            memset(&r.info, 0, sizeof r.info);
+            r.info.struct_size = sizeof r.info;
+            r.info.status = rc;
+            s->prep_cv.notify_one();
+            return rc;
+        }
+        r.state = RQ_ACTIVE;
         ++s->active;
         // inputs now live on the device (kept while a fallback rerun may need them)
         if (!(r.auto_prec && r.precision != PPCG_FP64)) {
@@ -130,11 +243,12 @@ static ppcg_status admit(ppcg_server *s)
     return PPCG_OK;
 }
 
+// Retire the requests whose job finished (calling thread, under `mu`).
 static ppcg_status retire_finished(ppcg_server *s)
 {
     for (auto &kv : s->reqs) {
         Request &r = kv.second;
-        if (r.state != 1)
+        if (r.state != RQ_ACTIVE)
             continue;
         Job &j = s->eng->job(r.job);
         if (!j.finished)
@@ -149,30 +263,38 @@ static ppcg_status retire_finished(ppcg_server *s)
         r.info.struct_size = sizeof r.info;
         fill_info(r.h, j, &r.info);
         s->eng->retire(r.job);
-        ppcg_destroy(r.h);
+        s->retired.emplace_back(r.h, r.footprint);  // its memory counts until released
         r.h = nullptr;
-        s->used -= r.footprint;
         --s->active;
+        s->prep_cv.notify_one();
         const bool budget_spent =
             r.info.status == PPCG_NOT_CONVERGED && r.info.outer_iters >= s->defaults.max_outer;
         if (r.auto_prec && r.precision != PPCG_FP64 &&
             (r.info.status == PPCG_STAGNATED || r.info.status == PPCG_BREAKDOWN || budget_spent)) {
             // reduced precision did not reach the tolerance: run again in
-            // FP64 from the last iterate, ahead of the requests still queued
+            // FP64 from the last iterate, ahead of the requests not yet prepared
             r.precision = PPCG_FP64;
             r.method = s->defaults.method;
             r.footprint = ppcg_footprint_bytes(r.n, r.nnz, PPCG_FP64);
-            r.state = 0;
+            r.state = RQ_QUEUED;
             s->queue.push_front(kv.first);
             continue;
         }
-        r.state = 2;
+        r.state = RQ_DONE;
         std::vector<double>().swap(r.b);
         std::vector<int32_t>().swap(r.rp);
         std::vector<int32_t>().swap(r.ci);
         std::vector<double>().swap(r.val);
     }
     return PPCG_OK;
+}
+
+static ppcg_status take_prep_error(ppcg_server *s)
+{
+    if (s->prep_rc == PPCG_OK)
+        return PPCG_OK;
+    set_error("request preparation: %s", s->prep_msg.c_str());
+    return s->prep_rc;
 }
 
 extern "C" {
@@ -193,10 +315,30 @@ ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *
         budget_bytes = 0.8 * (double)fr;
     }
     s->budget = budget_bytes;
+    PPCG_HIP(hipGetDevice(&s->device));
     PPCG_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
-    (void)hip_stream;  // requests are ordered on the server's own stream
+    (void)hip_stream;  // requests are ordered on the server's own streams
     s->eng.reset(new Engine(s->stream));
-    PPCG_TRY(s->eng->init(kServerSlots));
+    ppcg_status rc = s->eng->init(kServerSlots);
+    if (rc == PPCG_OK && hipStreamCreateWithFlags(&s->prep_stream, hipStreamNonBlocking) != hipSuccess) {
+        set_error("creating the preparation stream failed");
+        rc = PPCG_ERR_DEVICE;
+    }
+    if (rc == PPCG_OK) {
+        try {
+            s->prep = std::thread(prep_loop, s.get());
+        } catch (...) {
+            set_error("starting the preparation thread failed");
+            rc = PPCG_ERR_NOMEM;
+        }
+    }
+    if (rc != PPCG_OK) {
+        s->eng.reset();
+        if (s->prep_stream)
+            (void)hipStreamDestroy(s->prep_stream);
+        (void)hipStreamDestroy(s->stream);
+        return rc;
+    }
     *out = s.release();
     return PPCG_OK;
 }
@@ -239,6 +381,7 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
         return PPCG_ERR_BUDGET;
     }
     Request r;
+    std::unique_lock<std::mutex> lk(s->mu);
     r.id = s->next_id++;
     r.footprint = fp;
     r.tol = tol;
@@ -265,6 +408,8 @@ ppcg_status ppcg_srv_submit(ppcg_server *s, const ppcg_csr *A, const double *b, 
     *req_id = r.id;
     s->queue.push_back(r.id);
     s->reqs.emplace(r.id, std::move(r));
+    lk.unlock();
+    s->prep_cv.notify_one();
     return PPCG_OK;
 }
 
@@ -275,15 +420,26 @@ ppcg_status ppcg_srv_step(ppcg_server *s, int32_t *active, int32_t *queued)
         set_error("server is NULL");
         return PPCG_ERR_INVALID_ARG;
     }
+    std::unique_lock<std::mutex> lk(s->mu);
+    PPCG_TRY(take_prep_error(s));
+    // with nothing on the device, wait for the next prepared request
+    if (s->active == 0)
+        s->ready_cv.wait(lk, [s] {
+            return !s->ready.empty() || s->prep_rc != PPCG_OK || (s->preparing == 0 && s->queue.empty());
+        });
+    PPCG_TRY(take_prep_error(s));
     PPCG_TRY(admit(s));
     if (s->active > 0) {
+        // the engine and the active requests belong to this thread
+        lk.unlock();
         PPCG_TRY(s->eng->step(kServeGraphIters));
+        lk.lock();
         PPCG_TRY(retire_finished(s));
     }
     if (active)
         *active = s->active;
     if (queued)
-        *queued = (int32_t)s->queue.size();
+        *queued = (int32_t)(s->queue.size() + s->ready.size()) + s->preparing;
     return PPCG_OK;
 }
 
@@ -294,13 +450,14 @@ ppcg_status ppcg_srv_poll(ppcg_server *s, int64_t req_id, int32_t *ready, double
         set_error("invalid arguments");
         return PPCG_ERR_INVALID_ARG;
     }
+    std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->reqs.find(req_id);
     if (it == s->reqs.end()) {
         set_error("unknown request id %lld", (long long)req_id);
         return PPCG_ERR_INVALID_ARG;
     }
     Request &r = it->second;
-    if (r.state != 2) {
+    if (r.state != RQ_DONE) {
         *ready = 0;
         return PPCG_NOT_CONVERGED;
     }
@@ -319,12 +476,23 @@ ppcg_status ppcg_srv_destroy(ppcg_server *s)
     clear_error();
     if (!s)
         return PPCG_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->prep_cv.notify_all();
+    if (s->prep.joinable())
+        s->prep.join();  // a preparation under way completes first
     if (s->stream)
         (void)hipStreamSynchronize(s->stream);
     for (auto &kv : s->reqs)
         if (kv.second.h)
             ppcg_destroy(kv.second.h);
+    for (auto &e : s->retired)
+        ppcg_destroy(e.first);
     s->eng.reset();
+    if (s->prep_stream)
+        (void)hipStreamDestroy(s->prep_stream);
     if (s->stream)
         (void)hipStreamDestroy(s->stream);
     delete s;

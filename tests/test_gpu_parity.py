@@ -465,6 +465,37 @@ def test_server_refuses_over_budget_and_admits_in_turn():
         assert np.array_equal(x, xs[0])
 
 
+def test_server_bad_request_fails_alone():
+    """A request whose matrix fails validation (a negative diagonal entry)
+    ends with ERR_BAD_CSR on its own; the requests before and after it are
+    prepared, solved and returned as if it were not there."""
+    good = poisson2d(40)
+    bad = CSR(good.n, good.rp, good.ci, good.val.copy(), "bad")
+    d = [k for i in range(bad.n) for k in range(bad.rp[i], bad.rp[i + 1]) if bad.ci[k] == i]
+    bad.val[d[7]] = -1.0
+    b = problem(good)[0]
+    alone = _serve_all(Server(), [("g", good, b, 1e-10, "fp64")])["g"]
+    srv = Server()
+    ids = [srv.submit(good, b, 1e-10), srv.submit(bad, b, 1e-10), srv.submit(good, b, 1e-10)]
+    done = {}
+    while len(done) < 3:
+        srv.step()
+        for rid in ids:
+            if rid in done:
+                continue
+            try:
+                r = srv.poll(rid)
+            except PPCGError as e:
+                r = e.status
+            if r is not None:
+                done[rid] = r
+    assert done[ids[1]] == ppcg.ERR_BAD_CSR
+    for rid in (ids[0], ids[2]):
+        assert done[rid][1]["status"] == ppcg.OK
+        assert np.array_equal(done[rid][0], alone[0])
+    srv.close()
+
+
 def test_server_borrowing_inputs_gives_the_same_results():
     """A server created with PPCG_FLAG_BORROW_INPUTS reads the caller's
     arrays instead of copies: same results, bit for bit."""
