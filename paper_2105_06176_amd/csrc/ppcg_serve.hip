@@ -48,7 +48,7 @@ constexpr int kServeGraphIters = 32;
 constexpr int kAutoValues32Rows = PPCG_AUTO_VALUES32_ROWS;
 constexpr int kAutoPcg32Rows = PPCG_AUTO_PCG32_ROWS;
 
-enum ReqState { RQ_QUEUED, RQ_PREPARING, RQ_PREPARED, RQ_ACTIVE, RQ_DONE };
+enum ReqState { RQ_QUEUED, RQ_PREPARING, RQ_PREPARED, RQ_ACTIVE, RQ_FINISHING, RQ_DONE };
 
 struct Request {
     int64_t id = 0;
@@ -73,8 +73,9 @@ struct Request {
 }  // namespace
 
 // Ownership: the preparation thread alone touches a request in state
-// RQ_PREPARING; the calling thread alone touches one in RQ_PREPARED or
-// RQ_ACTIVE.  The map, both queues, the counters and every state change are
+// RQ_PREPARING or RQ_FINISHING; the calling thread alone touches one in
+// RQ_PREPARED or RQ_ACTIVE.  The map, the queues, the counters and every
+// state change are
 // guarded by `mu`.
 struct ppcg_server {
     hipStream_t stream = nullptr;       // the engine's stream
@@ -90,9 +91,17 @@ struct ppcg_server {
     std::map<int64_t, Request> reqs;
     std::deque<int64_t> queue;  // awaiting preparation, first come first served
     std::deque<int64_t> ready;  // prepared, awaiting admission, in the same order
-    // handles of retired requests with their footprints, released by the
-    // preparation thread (a release synchronizes the device)
-    std::vector<std::pair<ppcg_handle *, double>> retired;
+    // Retired requests: the preparation thread copies the solution out and
+    // releases the handle (a release synchronizes the device), then marks
+    // the request ready to poll, or queues it again for an FP64 rerun.
+    struct Retired {
+        int64_t id;
+        ppcg_handle *h;
+        double footprint;
+        bool rerun;
+    };
+    std::vector<Retired> retired;
+    int finishing = 0;          // retired requests not yet ready to poll
     double used = 0.0;          // footprints of the handles in preparation, prepared, active or retired
     int preparing = 0;
     int active = 0;
@@ -168,14 +177,52 @@ static void prep_loop(ppcg_server *s)
     for (;;) {
         s->prep_cv.wait(lk, [s] { return s->stop || !s->retired.empty() || can_prepare(s); });
         if (!s->retired.empty()) {
-            std::vector<std::pair<ppcg_handle *, double>> done;
-            done.swap(s->retired);
+            std::vector<ppcg_server::Retired> batch;
+            batch.swap(s->retired);
+            std::vector<Request *> rs;
+            for (auto &e : batch)
+                rs.push_back(&s->reqs.at(e.id));
             lk.unlock();
-            for (auto &e : done)
-                ppcg_destroy(e.first);
+            ppcg_status rc = PPCG_OK;
+            for (size_t k = 0; k < batch.size(); ++k) {
+                Request &r = *rs[k];
+                if (rc == PPCG_OK) {
+                    r.x.assign(r.n, 0.0);
+                    rc = unstage_x(batch[k].h, r.x.data());
+                    if (rc == PPCG_OK && hipStreamSynchronize(batch[k].h->stream) != hipSuccess) {
+                        set_error("copying the solution out failed");
+                        rc = PPCG_ERR_DEVICE;
+                    }
+                }
+                ppcg_destroy(batch[k].h);
+            }
+            std::string msg = rc == PPCG_OK ? std::string() : std::string(ppcg_last_error());
             lk.lock();
-            for (auto &e : done)
-                s->used -= e.second;
+            for (size_t k = 0; k < batch.size(); ++k) {
+                Request &r = *rs[k];
+                s->used -= batch[k].footprint;
+                --s->finishing;
+                if (batch[k].rerun && rc == PPCG_OK) {
+                    // reduced precision did not reach the tolerance: run again
+                    // in FP64 from the last iterate, ahead of the requests not
+                    // yet prepared
+                    r.state = RQ_QUEUED;
+                    s->queue.push_front(batch[k].id);
+                    continue;
+                }
+                r.state = RQ_DONE;
+                if (rc != PPCG_OK)
+                    r.info.status = rc;
+                std::vector<double>().swap(r.b);
+                std::vector<int32_t>().swap(r.rp);
+                std::vector<int32_t>().swap(r.ci);
+                std::vector<double>().swap(r.val);
+            }
+            if (rc != PPCG_OK) {
+                s->prep_rc = rc;
+                s->prep_msg = msg;
+            }
+            s->ready_cv.notify_all();
             continue;
         }
         if (s->stop)
@@ -243,7 +290,8 @@ static ppcg_status admit(ppcg_server *s)
     return PPCG_OK;
 }
 
-// Retire the requests whose job finished (calling thread, under `mu`).
+// Retire the requests whose job finished (calling thread, under `mu`); the
+// preparation thread copies their solutions out.
 static ppcg_status retire_finished(ppcg_server *s)
 {
     for (auto &kv : s->reqs) {
@@ -253,38 +301,29 @@ static ppcg_status retire_finished(ppcg_server *s)
         Job &j = s->eng->job(r.job);
         if (!j.finished)
             continue;
-        r.x.assign(r.n, 0.0);
-        hipStream_t keep = r.h->stream;
-        r.h->stream = s->eng->stream();
-        ppcg_status rc = unstage_x(r.h, r.x.data());
-        r.h->stream = keep;
-        PPCG_TRY(rc);
-        PPCG_HIP(hipStreamSynchronize(s->eng->stream()));
         r.info.struct_size = sizeof r.info;
         fill_info(r.h, j, &r.info);
         s->eng->retire(r.job);
-        s->retired.emplace_back(r.h, r.footprint);  // its memory counts until released
-        r.h = nullptr;
-        --s->active;
-        s->prep_cv.notify_one();
         const bool budget_spent =
             r.info.status == PPCG_NOT_CONVERGED && r.info.outer_iters >= s->defaults.max_outer;
-        if (r.auto_prec && r.precision != PPCG_FP64 &&
-            (r.info.status == PPCG_STAGNATED || r.info.status == PPCG_BREAKDOWN || budget_spent)) {
-            // reduced precision did not reach the tolerance: run again in
-            // FP64 from the last iterate, ahead of the requests not yet prepared
+        const bool rerun = r.auto_prec && r.precision != PPCG_FP64 &&
+                           (r.info.status == PPCG_STAGNATED || r.info.status == PPCG_BREAKDOWN || budget_spent);
+        // the memory counts until it is released
+        s->retired.push_back({kv.first, r.h, r.footprint, rerun});
+        r.h = nullptr;
+        r.state = RQ_FINISHING;
+        --s->active;
+        ++s->finishing;
+        if (rerun) {
             r.precision = PPCG_FP64;
             r.method = s->defaults.method;
             r.footprint = ppcg_footprint_bytes(r.n, r.nnz, PPCG_FP64);
-            r.state = RQ_QUEUED;
-            s->queue.push_front(kv.first);
-            continue;
         }
-        r.state = RQ_DONE;
-        std::vector<double>().swap(r.b);
-        std::vector<int32_t>().swap(r.rp);
-        std::vector<int32_t>().swap(r.ci);
-        std::vector<double>().swap(r.val);
+    }
+    if (!s->retired.empty()) {
+        // the engine's last chunk must be complete before another stream reads x
+        PPCG_HIP(hipStreamSynchronize(s->eng->stream()));
+        s->prep_cv.notify_one();
     }
     return PPCG_OK;
 }
@@ -425,7 +464,8 @@ ppcg_status ppcg_srv_step(ppcg_server *s, int32_t *active, int32_t *queued)
     // with nothing on the device, wait for the next prepared request
     if (s->active == 0)
         s->ready_cv.wait(lk, [s] {
-            return !s->ready.empty() || s->prep_rc != PPCG_OK || (s->preparing == 0 && s->queue.empty());
+            return !s->ready.empty() || s->prep_rc != PPCG_OK ||
+                   (s->preparing == 0 && s->queue.empty() && s->finishing == 0);
         });
     PPCG_TRY(take_prep_error(s));
     PPCG_TRY(admit(s));
@@ -437,7 +477,7 @@ ppcg_status ppcg_srv_step(ppcg_server *s, int32_t *active, int32_t *queued)
         PPCG_TRY(retire_finished(s));
     }
     if (active)
-        *active = s->active;
+        *active = s->active + s->finishing;
     if (queued)
         *queued = (int32_t)(s->queue.size() + s->ready.size()) + s->preparing;
     return PPCG_OK;
@@ -489,7 +529,7 @@ ppcg_status ppcg_srv_destroy(ppcg_server *s)
         if (kv.second.h)
             ppcg_destroy(kv.second.h);
     for (auto &e : s->retired)
-        ppcg_destroy(e.first);
+        ppcg_destroy(e.h);
     s->eng.reset();
     if (s->prep_stream)
         (void)hipStreamDestroy(s->prep_stream);
