@@ -37,7 +37,12 @@ using namespace ppcg;
 namespace {
 
 constexpr int kServerSlots = 1024;
-constexpr int kServeGraphIters = 32;
+// iterations per graph chunk (a power of two): requests finish, and new ones
+// join, at chunk boundaries
+#ifndef PPCG_SERVE_GRAPH_ITERS
+#define PPCG_SERVE_GRAPH_ITERS 8
+#endif
+constexpr int kServeGraphIters = PPCG_SERVE_GRAPH_ITERS;
 // automatic precision: smallest systems given reduced precision
 #ifndef PPCG_AUTO_VALUES32_ROWS
 #define PPCG_AUTO_VALUES32_ROWS 65536
