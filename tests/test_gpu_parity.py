@@ -496,6 +496,35 @@ def test_server_bad_request_fails_alone():
     srv.close()
 
 
+def test_server_many_requests_match_direct_solves():
+    """48 requests of mixed kinds and sizes (small-system kernel, batched
+    tiles, several tolerances) arrive in bursts between steps, so that
+    preparation, admission, retirement and the copy-out interleave: every
+    served solution equals a direct solve of the same request bit for bit."""
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(48):
+        k = i % 3
+        if k == 0:
+            A = poisson2d(int(rng.integers(8, 80)))
+        elif k == 1:
+            A = poisson3d(int(rng.integers(5, 24)))
+        else:
+            A = random_spd(int(rng.integers(300, 20000)), seed=int(rng.integers(1 << 20)))
+        tol = float(rng.choice([1e-6, 1e-8, 1e-10]))
+        reqs.append((f"q{i}", A, problem(A, 100 + i)[0], tol, "fp64"))
+    res = _serve_all(Server(), reqs, stagger=5)
+    assert len(res) == len(reqs)
+    for key, A, b, tol, _ in reqs:
+        xs, info = res[key]
+        assert info["status"] == ppcg.OK, (key, info)
+        S = Solver(A, tol=tol)
+        xd, infod = S.solve(dev(b))
+        S.close()
+        assert np.array_equal(xs, host(xd)), key
+        assert info["iters"] == infod["iters"], key
+
+
 def test_server_borrowing_inputs_gives_the_same_results():
     """A server created with PPCG_FLAG_BORROW_INPUTS reads the caller's
     arrays instead of copies: same results, bit for bit."""
