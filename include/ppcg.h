@@ -138,6 +138,15 @@ typedef struct {
                                       both are timed at create time and the faster is kept).
                                       Read by ppcg_create only, like the format itself */
 #define PPCG_FLAG_SELL_COL32 4u    /* SELL: always read 32-bit columns (not with SELL_COL16) */
+#define PPCG_FLAG_SELL_VALUE_TABLE 8u /* SELL: when the matrix has at most 256 distinct values (the
+                                         padding's 0.0 included), the PIPECG SpMV with FP64
+                                         values reads a one-byte index per stored entry into a
+                                         table of them, without timing it against the 8-byte
+                                         values (by default both are timed at create time and the
+                                         faster is kept).  Exact: the same values multiply.  Read
+                                         by ppcg_create only */
+#define PPCG_FLAG_SELL_FULL_VALUES 16u /* SELL: never build the value table (not with
+                                          SELL_VALUE_TABLE) */
 
 /* Solver options; initialise with ppcg_default_options(). */
 typedef struct {
@@ -205,6 +214,9 @@ typedef struct {
                                 every SELL column fits a 16-bit offset from its row, else 4 */
     int32_t diag_const;      /* 1: every diagonal entry is equal; the fused update then reads
                                 the inverse diagonal as one cached value, not a vector */
+    int32_t value_bytes;     /* bytes per stored value the iteration's SpMV reads: 1 with the
+                                value table (FP64 PIPECG), 4 with FP32 values, else 8 */
+    int32_t distinct_values; /* entries of the value table (0 when there is none) */
 } ppcg_matrix_info;
 
 /* Fill *opt with the defaults listed above. */

@@ -100,6 +100,9 @@ struct ppcg_handle {
     int *rp = nullptr;        // CSR row pointers (CSR-vector format)
     int *col = nullptr;
     short *col16 = nullptr;   // SELL: 16-bit column offsets from the row, when they all fit
+    unsigned char *vidx = nullptr;  // SELL: one-byte index of each stored value in vtab
+    double *vtab = nullptr;   // the distinct values (ascending bit patterns) when vidx is set
+    int nvtab = 0;
     int *perm = nullptr, *invperm = nullptr;
     double *val64 = nullptr;  // FP64 values in the stored format
     float *val32 = nullptr;   // FP32 copy of the stored values (mixed modes)

@@ -37,6 +37,9 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 // 1: for SELL matrices whose column offsets from the row fit 16 bits, time
 // the SpMV with 16-bit offsets against 32-bit columns at setup and keep the
 // faster (0: 32-bit columns only).
+#ifndef PPCG_SELL_VTAB
+#define PPCG_SELL_VTAB 1  // one-byte value indices into a table of distinct values, when timed faster
+#endif
 #ifndef PPCG_SELL_COL16
 #define PPCG_SELL_COL16 1
 #endif
@@ -105,6 +108,9 @@ struct alignas(128) SysState {
 static_assert(sizeof(SysState) == 128, "SysState is one 128-byte record");
 
 // Per-system descriptor (device-resident copy per engine slot).
+// Largest value table: a one-byte index per stored entry.
+constexpr int kMaxValueTable = 256;
+
 struct SysDesc {
     int n;
     int ntiles;
@@ -117,13 +123,15 @@ struct SysDesc {
     int pair;           // mixed precision: slot of the same system in the other group
     int vals32;         // 1: iteration SpMVs read the FP32 copy of the values (val32)
     int dinv_const;     // 1: every diagonal entry is equal; the updates read dinv[0] for every row
-    int pad_;
+    int nvtab;          // entries of vtab (when vidx is set)
     double tol;
     double repl_factor; // vals32: pause for a reliable update when the residual fell by this factor
     const int64_t *cptr;  // SELL chunk offsets [nchunks + 1]
     const int *rp;        // CSR row pointers [n + 1] (CSR-vector format)
     const int *col;       // SELL / CSR column indices
     const short *col16;   // SELL: column minus row as 16-bit offsets when every one fits (else NULL)
+    const unsigned char *vidx;  // SELL, FP64 values: index of each stored value in vtab (else NULL)
+    const double *vtab;   // the matrix's distinct values (at most kMaxValueTable), ascending bit patterns
     const void *val;      // matrix values (double or float)
     const float *val32;   // FP32 copy of the values (vals32 mode)
     const void *dinv;     // inverse diagonal (double or float)

@@ -27,6 +27,8 @@
 // and, for a single system, identical run to run and alone or batched.
 #pragma once
 
+#include <type_traits>
+
 #include "ppcg_internal.hpp"
 
 namespace ppcg {
@@ -468,6 +470,20 @@ __device__ __forceinline__ T stream_load(const PPCG_AS1 T *p)
 #endif
 }
 
+// Value of the stored SELL entry at offset o from the lane's first slot: the
+// value itself, or (VI, FP64 values) the entry of the value table `tab` (in
+// LDS) named by its one-byte index.  The table holds the matrix's distinct
+// values exactly, so both give the same number.
+template <bool VI, typename VT>
+__device__ __forceinline__ VT sell_value(const PPCG_AS1 VT *v, const PPCG_AS1 unsigned char *vi, const double *tab,
+                                         size_t o)
+{
+    if constexpr (VI)
+        return (VT)tab[stream_load(vi + o)];
+    else
+        return stream_load(v + o);
+}
+
 // SELL-C-sigma, C = 64, one lane per row: entry k of the row (chunk c, lane
 // l) is at cptr[c] + k * 64 + l.  NX input vectors share one pass over the
 // matrix (NX = 2 for the replacement steps).  Entries are handled in
@@ -476,16 +492,18 @@ __device__ __forceinline__ T stream_load(const PPCG_AS1 T *p)
 // in flight; the products of every row are still added in stored
 // (ascending original column) order.  VT is the value type, T the vector
 // and accumulation type.
-template <typename VT, typename T, int NX>
+template <typename VT, typename T, int NX, bool VI = false>
 __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const int *__restrict__ col,
                                          const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
-                                         int lane, T (&acc)[NX])
+                                         int lane, T (&acc)[NX], const unsigned char *__restrict__ vidx = nullptr,
+                                         const double *tab = nullptr)
 {
     constexpr int B = PPCG_SELL_BATCH;
     const int64_t base = as_global(cptr)[chunk];
     const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
     const PPCG_AS1 int *c = as_global(col + base + lane);
-    const PPCG_AS1 VT *v = as_global(val + base + lane);
+    const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
+    const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
     const PPCG_AS1 T *xg[NX];
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
@@ -503,7 +521,7 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
             vv[j] = (VT)0;
             if (k0 + j < len) {
                 cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
-                vv[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
+                vv[j] = sell_value<VI>(v, vi, tab, (size_t)(k0 + j) * kSellC);
             }
         }
 #pragma unroll
@@ -549,16 +567,18 @@ __device__ __forceinline__ void sell_cols16(const short *__restrict__ col16, int
 }
 
 // sell_row with 16-bit column offsets from the row.
-template <typename VT, typename T, int NX>
+template <typename VT, typename T, int NX, bool VI = false>
 __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, const short *__restrict__ col16,
                                            const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
-                                           int lane, T (&acc)[NX])
+                                           int lane, T (&acc)[NX], const unsigned char *__restrict__ vidx = nullptr,
+                                           const double *tab = nullptr)
 {
     constexpr int B = PPCG_SELL_BATCH;
     const int64_t base = as_global(cptr)[chunk];
     const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
     const int row = chunk * kSellC + lane;
-    const PPCG_AS1 VT *v = as_global(val + base + lane);
+    const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
+    const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
     const PPCG_AS1 T *xg[NX];
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
@@ -573,7 +593,7 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
         for (int j = 0; j < B; ++j) {
             vv[j] = (VT)0;
             if (k0 + j < len)
-                vv[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
+                vv[j] = sell_value<VI>(v, vi, tab, (size_t)(k0 + j) * kSellC);
         }
 #pragma unroll
         for (int q = 0; q < NX; ++q) {
@@ -593,16 +613,19 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
 // issued before the column and value loads of batch k + 1, so the wait for
 // the gathers leaves the next batch's loads in flight.  Same products, same
 // order of the sums.
-template <typename VT, typename T, int NX>
+template <typename VT, typename T, int NX, bool VI = false>
 __device__ __forceinline__ void sell_row16_pipe(const int64_t *__restrict__ cptr, const short *__restrict__ col16,
                                                 const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
-                                                int lane, T (&acc)[NX])
+                                                int lane, T (&acc)[NX],
+                                                const unsigned char *__restrict__ vidx = nullptr,
+                                                const double *tab = nullptr)
 {
     constexpr int B = PPCG_SELL_PIPE_BATCH;  // two batches in flight: smaller than the plain batch
     const int64_t base = as_global(cptr)[chunk];
     const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
     const int row = chunk * kSellC + lane;
-    const PPCG_AS1 VT *v = as_global(val + base + lane);
+    const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
+    const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
     const PPCG_AS1 T *xg[NX];
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
@@ -617,7 +640,7 @@ __device__ __forceinline__ void sell_row16_pipe(const int64_t *__restrict__ cptr
         for (int j = 0; j < B; ++j) {
             w[j] = (VT)0;
             if (k0 + j < len)
-                w[j] = stream_load(v + (size_t)(k0 + j) * kSellC);
+                w[j] = sell_value<VI>(v, vi, tab, (size_t)(k0 + j) * kSellC);
         }
     };
     if (len > 0)
@@ -803,9 +826,11 @@ __device__ __noinline__ void designated_reduce(const SysDesc &d, SysState *st, d
     }
 }
 
+// tab: the system's value table in LDS when it reads one-byte value indices
+// (FP64 values only), else NULL.
 template <typename VT, typename T, int MODE>
 __device__ __forceinline__ void spmv_tile(const SysDesc &d, const VT *__restrict__ val, const WorkItem wi,
-                                          double (&acc)[kReplPartials])
+                                          double (&acc)[kReplPartials], const double *tab = nullptr)
 {
     constexpr int NX = SpmvIn<MODE>::NX;
     const T *xin[NX];
@@ -818,14 +843,31 @@ __device__ __forceinline__ void spmv_tile(const SysDesc &d, const VT *__restrict
         const int chunk = wi.tile * kSellChunksPerTile + (threadIdx.x >> 6);
         const int i = chunk * kSellC + lane;
         if (chunk * kSellC < n) {
-            if (d.col16)  // uniform per system
+            // both choices are uniform per system
+            bool done = false;
+            if constexpr (std::is_same<VT, double>::value && NX == 1) {
+                if (tab) {
+                    if (d.col16)
 #if PPCG_SELL_PIPE
-                sell_row16_pipe<VT, T, NX>(d.cptr, d.col16, val, xin, chunk, lane, y);
+                        sell_row16_pipe<VT, T, NX, true>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab);
 #else
-                sell_row16<VT, T, NX>(d.cptr, d.col16, val, xin, chunk, lane, y);
+                        sell_row16<VT, T, NX, true>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab);
 #endif
-            else
-                sell_row<VT, T, NX>(d.cptr, d.col, val, xin, chunk, lane, y);
+                    else
+                        sell_row<VT, T, NX, true>(d.cptr, d.col, val, xin, chunk, lane, y, d.vidx, tab);
+                    done = true;
+                }
+            }
+            if (!done) {
+                if (d.col16)
+#if PPCG_SELL_PIPE
+                    sell_row16_pipe<VT, T, NX>(d.cptr, d.col16, val, xin, chunk, lane, y);
+#else
+                    sell_row16<VT, T, NX>(d.cptr, d.col16, val, xin, chunk, lane, y);
+#endif
+                else
+                    sell_row<VT, T, NX>(d.cptr, d.col, val, xin, chunk, lane, y);
+            }
             if (i < n)
                 spmv_epilogue<T, MODE>(d, i, y, acc);
         }
@@ -864,10 +906,19 @@ __global__ __launch_bounds__(kSpmvThreads, PPCG_SPMV_WAVES) void k_spmv(const Wo
     if (MODE == MODE_ITER && st->done)
         return;
     double acc[kReplPartials] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (!kTrueOperator<MODE> && d.vals32)
+    if (!kTrueOperator<MODE> && d.vals32) {
         spmv_tile<float, T, MODE>(d, d.val32, wi, acc);
-    else
+    } else if (std::is_same<T, double>::value && SpmvIn<MODE>::NX == 1 && d.vidx && d.fmt == FMT_SELL) {
+        // the value table, once per workgroup (one work item: uniform); the
+        // two-vector SpMVs of the reliable updates read the values
+        __shared__ double vtab[kMaxValueTable];
+        for (int t = threadIdx.x; t < d.nvtab; t += kSpmvThreads)
+            vtab[t] = d.vtab[t];
+        __syncthreads();
+        spmv_tile<T, T, MODE>(d, (const T *)d.val, wi, acc, vtab);
+    } else {
         spmv_tile<T, T, MODE>(d, (const T *)d.val, wi, acc);
+    }
     constexpr bool kWritesPartials =
         MODE == MODE_INIT1 || MODE == MODE_INIT2 || MODE == MODE_RESID || MODE == MODE_DUAL1;
     if constexpr (kWritesPartials) {

@@ -142,7 +142,10 @@ struct ByteModel {
 static ByteModel byte_model(const ppcg_handle *h, int prec)
 {
     const double ve = prec == PREC_F32 ? 4.0 : 8.0;   // vector element
-    const double me = prec == PREC_F64 ? 8.0 : 4.0;   // matrix value
+    const bool pcg0 = h->opt.method == PPCG_METHOD_PCG || prec == PREC_F32;
+    // matrix value: FP64, or a one-byte index into the value table (the
+    // PIPECG SpMV with FP64 values), or FP32
+    const double me = prec == PREC_F64 ? (h->vidx && !pcg0 ? 1.0 : 8.0) : 4.0;
     const double n = h->n;
     // FP32 vectors always iterate with Algorithm 1
     const bool pcg = h->opt.method == PPCG_METHOD_PCG || prec == PREC_F32;
@@ -290,6 +293,9 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->rp = h->rp;
     d->col = h->col;
     d->col16 = h->col16;
+    d->vidx = h->vidx;
+    d->vtab = h->vtab;
+    d->nvtab = h->nvtab;
     d->val = pd.val;
     d->val32 = h->val32;
     d->vals32 = vals32;
@@ -386,6 +392,11 @@ static void free_matrix(ppcg_handle *h)
     if (h->col) (void)dev_free(h->col);
     if (h->col16) (void)dev_free(h->col16);
     h->col16 = nullptr;
+    if (h->vidx) (void)dev_free(h->vidx);
+    if (h->vtab) (void)dev_free(h->vtab);
+    h->vidx = nullptr;
+    h->vtab = nullptr;
+    h->nvtab = 0;
     if (h->val64) (void)dev_free(h->val64);
     if (h->val32) (void)dev_free(h->val32);
     if (h->perm) (void)dev_free(h->perm);
@@ -500,6 +511,172 @@ static ppcg_status tune_col16(ppcg_handle *h, int known, int *chosen)
         }
     }
     *chosen = 1;
+    return PPCG_OK;
+}
+
+// The matrix's distinct values as ascending bit patterns, +0.0 (the SELL
+// padding) included, when there are at most kMaxValueTable of them (*fits).
+// The scan stops at the first value past that count, so a matrix with many
+// values costs little.  Values come from the host CSR array when there is
+// one, else in chunks from the device CSR array.
+static ppcg_status distinct_values(const ppcg_handle *h, const double *val_host, const double *val_dev,
+                                   std::vector<uint64_t> *keys, bool *fits)
+{
+    constexpr int kSlots = 4 * kMaxValueTable;  // open addressing, load at most 1/4
+    std::vector<uint64_t> slot(kSlots, 0);
+    std::vector<char> used(kSlots, 0);
+    int count = 0;
+    uint64_t last = 0;
+    bool have_last = false;
+    auto add = [&](uint64_t k) {
+        if (have_last && k == last)
+            return true;
+        last = k;
+        have_last = true;
+        unsigned p = (unsigned)((k * 0x9E3779B97F4A7C15ull) >> 54);  // 10 bits
+        while (used[p]) {
+            if (slot[p] == k)
+                return true;
+            p = (p + 1) & (kSlots - 1);
+        }
+        if (count == kMaxValueTable)
+            return false;
+        used[p] = 1;
+        slot[p] = k;
+        ++count;
+        return true;
+    };
+    auto scan = [&](const double *v, int64_t m) {
+        for (int64_t i = 0; i < m; ++i) {
+            uint64_t k;
+            memcpy(&k, v + i, sizeof k);
+            if (!add(k))
+                return false;
+        }
+        return true;
+    };
+    *fits = false;
+    const double zero = 0.0;
+    if (!scan(&zero, 1))
+        return PPCG_OK;
+    if (val_host) {
+        if (!scan(val_host, h->nnz))
+            return PPCG_OK;
+    } else {
+        constexpr int64_t kChunk = 1 << 20;
+        std::vector<double> buf((size_t)std::min<int64_t>(h->nnz, kChunk));
+        for (int64_t off = 0; off < h->nnz; off += kChunk) {
+            const int64_t m = std::min(kChunk, h->nnz - off);
+            PPCG_HIP(hipMemcpyAsync(buf.data(), val_dev + off, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
+            PPCG_HIP(hipStreamSynchronize(h->stream));
+            if (!scan(buf.data(), m))
+                return PPCG_OK;
+        }
+    }
+    keys->clear();
+    for (int p = 0; p < kSlots; ++p)
+        if (used[p])
+            keys->push_back(slot[p]);
+    std::sort(keys->begin(), keys->end());
+    *fits = true;
+    return PPCG_OK;
+}
+
+// Build the one-byte value indices of the stored SELL values and the table.
+static ppcg_status build_vtab(ppcg_handle *h, const std::vector<uint64_t> &keys)
+{
+    hipStream_t s = h->stream;
+    const int nt = (int)keys.size();
+    unsigned char *vi = nullptr;
+    double *tab = nullptr;
+    unsigned *flag = nullptr;
+    unsigned zero = 0u, bad = 0u;
+    hipError_t e = hipMalloc(&vi, (size_t)std::max<int64_t>(h->nnz_stored, 1));
+    if (e == hipSuccess)
+        e = hipMalloc(&tab, sizeof(double) * nt);
+    if (e == hipSuccess)
+        e = hipMalloc(&flag, sizeof(unsigned));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tab, keys.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(flag, &zero, sizeof zero, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && h->nnz_stored > 0) {
+        k_sell_vidx<<<blocks_for((size_t)h->nnz_stored, 256), 256, 0, s>>>(
+            h->nnz_stored, h->val64, (const unsigned long long *)tab, nt, vi, flag);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (flag)
+        (void)dev_free(flag);
+    if (e != hipSuccess || bad) {
+        if (vi) (void)dev_free(vi);
+        if (tab) (void)dev_free(tab);
+        vi = nullptr;
+        tab = nullptr;
+    }
+    PPCG_HIP(e);
+    h->vidx = vi;
+    h->vtab = tab;
+    h->nvtab = vi ? nt : 0;
+    return PPCG_OK;
+}
+
+static void drop_vtab(ppcg_handle *h)
+{
+    if (h->vidx) (void)dev_free(h->vidx);
+    if (h->vtab) (void)dev_free(h->vtab);
+    h->vidx = nullptr;
+    h->vtab = nullptr;
+    h->nvtab = 0;
+}
+
+// SELL: whether the FP64 SpMVs read a one-byte index per stored entry into a
+// table of the matrix's distinct values instead of the 8-byte value, when
+// there are at most 256 of them (index-and-value compression, as in CSR-VI:
+// Kourtis, Goumas and Koziris, 2008).  Exact: the table holds the values
+// themselves, so the products are the same.  Constant-coefficient stencils
+// have two or three values; most assembled matrices have too many, and the
+// scan gives up early.  Both layouts are timed like the column layouts
+// (alternated), and the table is kept when the SpMV time it saves is at
+// least 5 % of an iteration (the SpMV plus the fused update, whose time is
+// estimated from its bytes at 6.5 TB/s): it costs a scan and a byte per
+// entry at setup, so a gain within run-to-run noise is not taken.  The short
+// rows of a 7-point stencil are bound by the latency of the column load and
+// the gather that depends on it: halving their bytes saved 2-3 % of the
+// SpMV, about 1 % of an iteration.  The 125-point rows' SpMV ran 1.45x
+// faster.  PPCG_FLAG_SELL_VALUE_TABLE / _FULL_VALUES force the choice, and
+// PPCG_SELL_VTAB = 0 switches it off.
+static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const double *val_dev)
+{
+    const unsigned fl = h->opt.flags;
+    if (!PPCG_SELL_VTAB || h->fmt != FMT_SELL || (fl & PPCG_FLAG_SELL_FULL_VALUES))
+        return PPCG_OK;
+    std::vector<uint64_t> keys;
+    bool fits = false;
+    PPCG_TRY(distinct_values(h, val_host, val_dev, &keys, &fits));
+    if (!fits)
+        return PPCG_OK;
+    PPCG_TRY(build_vtab(h, keys));
+    if (!h->vidx || (fl & PPCG_FLAG_SELL_VALUE_TABLE))
+        return PPCG_OK;
+    unsigned char *vi = h->vidx;
+    double tf = 1e300, tv = 1e300;
+    for (int round = 0; round < 2; ++round) {
+        double t = 0.0;
+        h->vidx = nullptr;  // the SpMV reads the values
+        ppcg_status rc = time_spmv(h, 5, &t);
+        h->vidx = vi;
+        PPCG_TRY(rc);
+        tf = std::min(tf, t);
+        PPCG_TRY(time_spmv(h, 5, &t));
+        tv = std::min(tv, t);
+    }
+    const double t_update_ms = byte_model(h, PREC_F64).vma / 6.5e12 * 1e3;
+    if (!(tf - tv >= 0.05 * (tf + t_update_ms)))
+        drop_vtab(h);
     return PPCG_OK;
 }
 
@@ -1598,8 +1775,10 @@ static ppcg_status check_options(const ppcg_options *o)
         (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
          o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
         (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
-        (o->flags & ~(PPCG_FLAG_BORROW_INPUTS | PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32)) != 0 ||
-        ((o->flags & PPCG_FLAG_SELL_COL16) && (o->flags & PPCG_FLAG_SELL_COL32))) {
+        (o->flags & ~(PPCG_FLAG_BORROW_INPUTS | PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32 |
+                      PPCG_FLAG_SELL_VALUE_TABLE | PPCG_FLAG_SELL_FULL_VALUES)) != 0 ||
+        ((o->flags & PPCG_FLAG_SELL_COL16) && (o->flags & PPCG_FLAG_SELL_COL32)) ||
+        ((o->flags & PPCG_FLAG_SELL_VALUE_TABLE) && (o->flags & PPCG_FLAG_SELL_FULL_VALUES))) {
         set_error("invalid option value");
         return PPCG_ERR_INVALID_ARG;
     }
@@ -1752,6 +1931,7 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
     }
     CKS(alloc_f64_vectors(h));
     CKS(choose_format(h, rp, ci, val, rowlen, dinv_orig, rowlen_h));
+    CKS(tune_vtab(h, A->mem == PPCG_MEM_HOST ? A->values : nullptr, val));
     if (opt->precision == PPCG_MIXED_FP32)
         CKS(ensure_f32(h));
     if (opt->precision == PPCG_MIXED_FP32_VALUES)
@@ -1940,11 +2120,17 @@ ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
     mi->device_bytes = (double)h->f64.arena.size + (double)h->f32.arena.size +
                        (double)h->nnz_stored * 12.0 + 8.0 * h->n +
                        (h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (h->n + 1)) +
-                       (h->perm ? 8.0 * h->n : 0.0) + (h->col16 ? 2.0 * (double)h->nnz_stored : 0.0);
+                       (h->perm ? 8.0 * h->n : 0.0) + (h->col16 ? 2.0 * (double)h->nnz_stored : 0.0) +
+                       (h->vidx ? (double)h->nnz_stored + 8.0 * h->nvtab : 0.0);
     mi->setup_ms = h->setup_ms;
     mi->col_index_bytes =
         (h->col16 && !(h->opt.method == PPCG_METHOD_PCG && h->opt.precision == PPCG_MIXED_FP32_VALUES)) ? 2 : 4;
     mi->diag_const = h->dinv_const ? 1 : 0;
+    const bool pcg = h->opt.method == PPCG_METHOD_PCG || h->opt.precision == PPCG_MIXED_FP32;
+    mi->value_bytes = h->opt.precision == PPCG_MIXED_FP32 || h->opt.precision == PPCG_MIXED_FP32_VALUES ? 4
+                      : (h->vidx && !pcg)                                                              ? 1
+                                                                                                       : 8;
+    mi->distinct_values = h->nvtab;
     return PPCG_OK;
 }
 
@@ -1954,8 +2140,9 @@ double ppcg_footprint_bytes(int32_t n, int64_t nnz, ppcg_precision precision)
         return 0.0;
     const double ntiles = (n + kTileRows - 1) / kTileRows;
     const double stored = 1.10 * (double)nnz;  // padding allowance
-    // stored entries: 8 value + 4 column + 2 (16-bit column offsets, when built) bytes
-    double b = stored * 14.0 + 8.0 * (n / kSellC + 2) + 8.0 * n /* dinv */ + 8.0 * n /* perm */ +
+    // stored entries: 8 value + 4 column + 2 (16-bit column offsets, when
+    // built) + 1 (value index, when built) bytes
+    double b = stored * 15.0 + 8.0 * (n / kSellC + 2) + 8.0 * n /* dinv */ + 8.0 * n /* perm */ +
                11.0 * 8.0 * n + 2.0 * ntiles * kPartStride * 8.0 + 12 * 256.0;
     if (precision == PPCG_MIXED_FP32)
         b += stored * 4.0 + 12.0 * 4.0 * n + 2.0 * ntiles * kPartStride * 8.0;

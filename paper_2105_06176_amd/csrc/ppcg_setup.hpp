@@ -265,4 +265,35 @@ __global__ void k_sell_delta16(int nchunks, const int64_t *__restrict__ cptr, co
         atomicOr(flag, 1u);
 }
 
+// One-byte value indices: vidx[e] = the position of the stored value val[e]
+// in tab, the matrix's distinct values as ascending unsigned 64-bit bit
+// patterns (ntab in [1, kMaxValueTable]), found by binary search.  A value
+// missing from the table sets flag[0] |= 1 (and index 0); the caller then
+// drops the indices.
+__global__ void k_sell_vidx(int64_t stored, const double *__restrict__ val, const unsigned long long *__restrict__ tab,
+                            int ntab, unsigned char *__restrict__ vidx, unsigned *__restrict__ flag)
+{
+    __shared__ unsigned long long t[kMaxValueTable];
+    for (int k = threadIdx.x; k < ntab; k += blockDim.x)
+        t[k] = tab[k];
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= stored)
+        return;
+    const unsigned long long key = (unsigned long long)__double_as_longlong(val[e]);
+    int lo = 0, hi = ntab - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (t[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (t[lo] != key) {
+        atomicOr(flag, 1u);
+        lo = 0;
+    }
+    vidx[e] = (unsigned char)lo;
+}
+
 }  // namespace ppcg

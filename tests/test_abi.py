@@ -31,6 +31,16 @@ def test_library_loads_and_exports_every_symbol():
         assert hasattr(L, name), name
 
 
+def test_header_flag_values_match_the_binding():
+    src = open(HEADER).read()
+    flags = dict(re.findall(r"#define PPCG_FLAG_([A-Z0-9_]+) (\d+)u", src))
+    assert flags and set(flags) == {k[5:] for k in dir(ppcg) if k.startswith("FLAG_")}
+    for name, v in flags.items():
+        assert getattr(ppcg, "FLAG_" + name) == int(v), name
+    bits = [int(v) for v in flags.values()]
+    assert len(set(bits)) == len(bits) and all(b & (b - 1) == 0 for b in bits)
+
+
 def test_default_options_and_status_strings():
     o = ppcg.make_options()
     assert o.struct_size == ctypes.sizeof(ppcg.Options)
@@ -82,6 +92,7 @@ int main(void) {
   F(ppcg_info, precision) F(ppcg_info, method)
   F(ppcg_matrix_info, nnz_stored) F(ppcg_matrix_info, tile_rows) F(ppcg_matrix_info, setup_ms)
   F(ppcg_matrix_info, col_index_bytes) F(ppcg_matrix_info, diag_const)
+  F(ppcg_matrix_info, value_bytes) F(ppcg_matrix_info, distinct_values)
   return 0;
 }
 """

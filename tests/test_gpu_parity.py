@@ -113,6 +113,66 @@ def test_storage_choices_keep_results_exact(flags, expect16):
         assert relerr(host(xg), oracle.pipecg(A, b, fixed_iters=15).x) <= 1e-10
 
 
+@pytest.mark.parametrize("col_flag", [ppcg.FLAG_SELL_COL16, ppcg.FLAG_SELL_COL32])
+def test_value_table_is_exact(col_flag):
+    """A constant-coefficient stencil stores three values (6, -1 and the
+    padding's 0).  With the value table forced, the PIPECG SpMV reads one-byte
+    indices into it; the SpMV output, the solve to 1e-10 and its iteration
+    count are bitwise those of the 8-byte values, with either column layout,
+    for host and for device CSR input (the scan then copies the values in
+    chunks)."""
+    import torch
+
+    A = poisson3d(40)
+    b, _ = problem(A)
+    x = xstar_uniform(A.n, 3)
+    dev_csr = (torch.as_tensor(A.rp).cuda(), torch.as_tensor(A.ci).cuda(), torch.as_tensor(A.val).cuda())
+    res = {}
+    for label, src, vflag in (("on", A, ppcg.FLAG_SELL_VALUE_TABLE), ("on_dev", dev_csr, ppcg.FLAG_SELL_VALUE_TABLE),
+                              ("off", A, ppcg.FLAG_SELL_FULL_VALUES)):
+        S = Solver(src, spmv_format="sell", flags=col_flag | vflag, tol=1e-10)
+        mi = S.matrix_info()
+        y = host(S.spmv(dev(x)))
+        xs, info = S.solve(dev(b))
+        res[label] = (y, host(xs), info["iters"], mi)
+        S.close()
+    for label in ("on", "on_dev"):
+        assert res[label][3]["value_bytes"] == 1 and res[label][3]["distinct_values"] == 3, label
+    assert res["off"][3]["value_bytes"] == 8 and res["off"][3]["distinct_values"] == 0
+    assert res["on"][3]["bytes_spmv"] < res["off"][3]["bytes_spmv"]
+    assert np.array_equal(res["off"][0], oracle.spmv(A, x))
+    for label in ("on", "on_dev"):
+        assert np.array_equal(res[label][0], res["off"][0]), label
+        assert np.array_equal(res[label][1], res["off"][1]), label
+        assert res[label][2] == res["off"][2], label
+
+
+def _tridiag_values(n, k):
+    """SPD tridiagonal matrix with k distinct off-diagonal values (and the
+    diagonal 4): k + 2 distinct stored values with the SELL padding."""
+    import scipy.sparse as sp
+
+    off = -1.0 - (np.arange(n - 1) % k) * 2.0 ** -10
+    M = sp.diags([off, np.full(n, 4.0), off], [-1, 0, 1], format="csr")
+    M.sort_indices()
+    return CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64), f"tri{k}")
+
+
+def test_value_table_holds_at_most_256_values():
+    """254 off-diagonal values + 4 + the padding's 0 = 256 fit the one-byte
+    table; one more value and the matrix keeps its 8-byte values.  Either way
+    the SpMV equals the oracle's bit for bit."""
+    for k, fits in ((254, True), (255, False)):
+        A = _tridiag_values(6000, k)
+        S = Solver(A, spmv_format="sell", flags=ppcg.FLAG_SELL_VALUE_TABLE)
+        mi = S.matrix_info()
+        assert mi["distinct_values"] == (256 if fits else 0), k
+        assert mi["value_bytes"] == (1 if fits else 8), k
+        x = xstar_uniform(A.n, 4)
+        assert np.array_equal(host(S.spmv(dev(x))), oracle.spmv(A, x)), k
+        S.close()
+
+
 # ---------------------------------------------------------------- fixed iterates
 
 @pytest.mark.parametrize("name,ks", [("c1_poisson2d_64", (1, 10, 50, 100)), ("poisson2d_37_ragged", (5, 40)),
