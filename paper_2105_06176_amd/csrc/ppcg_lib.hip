@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -16,8 +17,10 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -514,22 +517,18 @@ static ppcg_status tune_col16(ppcg_handle *h, int known, int *chosen)
     return PPCG_OK;
 }
 
-// The matrix's distinct values as ascending bit patterns, +0.0 (the SELL
-// padding) included, when there are at most kMaxValueTable of them (*fits).
-// The scan stops at the first value past that count, so a matrix with many
-// values costs little.  Values come from the host CSR array when there is
-// one, else in chunks from the device CSR array.
-static ppcg_status distinct_values(const ppcg_handle *h, const double *val_host, const double *val_dev,
-                                   std::vector<uint64_t> *keys, bool *fits)
-{
-    constexpr int kSlots = 4 * kMaxValueTable;  // open addressing, load at most 1/4
-    std::vector<uint64_t> slot(kSlots, 0);
-    std::vector<char> used(kSlots, 0);
+// A set of at most kMaxValueTable 64-bit keys (open addressing, load at
+// most 1/4); add() fails when a new key would exceed that count.
+struct ValueSet {
+    static constexpr int kSlots = 4 * kMaxValueTable;
+    uint64_t slot[kSlots];
+    bool used[kSlots] = {};
     int count = 0;
     uint64_t last = 0;
     bool have_last = false;
-    auto add = [&](uint64_t k) {
-        if (have_last && k == last)
+    bool add(uint64_t k)
+    {
+        if (have_last && k == last)  // runs of equal values are common
             return true;
         last = k;
         have_last = true;
@@ -541,27 +540,66 @@ static ppcg_status distinct_values(const ppcg_handle *h, const double *val_host,
         }
         if (count == kMaxValueTable)
             return false;
-        used[p] = 1;
+        used[p] = true;
         slot[p] = k;
         ++count;
         return true;
-    };
-    auto scan = [&](const double *v, int64_t m) {
+    }
+    // false as soon as a value does not fit (or *stop is raised)
+    bool scan(const double *v, int64_t m, const std::atomic<bool> *stop = nullptr)
+    {
         for (int64_t i = 0; i < m; ++i) {
+            if (stop && (i & 0xffff) == 0 && stop->load(std::memory_order_relaxed))
+                return false;
             uint64_t k;
             memcpy(&k, v + i, sizeof k);
             if (!add(k))
                 return false;
         }
         return true;
-    };
+    }
+};
+
+// The matrix's distinct values as ascending bit patterns, +0.0 (the SELL
+// padding) included, when there are at most kMaxValueTable of them (*fits).
+// A scan stops at the first value past that count, so a matrix with many
+// values costs little.  Host CSR values are scanned by up to 8 threads, each
+// over its own range, and their sets merged; device values are copied in
+// chunks and scanned in turn.
+static ppcg_status distinct_values(const ppcg_handle *h, const double *val_host, const double *val_dev,
+                                   std::vector<uint64_t> *keys, bool *fits)
+{
     *fits = false;
-    const double zero = 0.0;
-    if (!scan(&zero, 1))
+    auto merged = std::make_unique<ValueSet>();
+    if (!merged->add(0))  // +0.0
         return PPCG_OK;
     if (val_host) {
-        if (!scan(val_host, h->nnz))
-            return PPCG_OK;
+        const int64_t nnz = h->nnz;
+        const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(8, nnz / (1 << 20)));
+        std::vector<std::unique_ptr<ValueSet>> sets;
+        for (int t = 0; t < nt; ++t)
+            sets.push_back(std::make_unique<ValueSet>());
+        std::vector<char> ok(nt, 1);
+        std::atomic<bool> stop(false);
+        auto work = [&](int t) {
+            const int64_t lo = nnz * t / nt, hi = nnz * (t + 1) / nt;
+            ok[t] = sets[t]->scan(val_host + lo, hi - lo, &stop);
+            if (!ok[t])
+                stop.store(true);
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nt; ++t)
+            th.emplace_back(work, t);
+        work(0);
+        for (auto &x : th)
+            x.join();
+        for (int t = 0; t < nt; ++t) {
+            if (!ok[t])
+                return PPCG_OK;
+            for (int p = 0; p < ValueSet::kSlots; ++p)
+                if (sets[t]->used[p] && !merged->add(sets[t]->slot[p]))
+                    return PPCG_OK;
+        }
     } else {
         constexpr int64_t kChunk = 1 << 20;
         std::vector<double> buf((size_t)std::min<int64_t>(h->nnz, kChunk));
@@ -569,14 +607,14 @@ static ppcg_status distinct_values(const ppcg_handle *h, const double *val_host,
             const int64_t m = std::min(kChunk, h->nnz - off);
             PPCG_HIP(hipMemcpyAsync(buf.data(), val_dev + off, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
             PPCG_HIP(hipStreamSynchronize(h->stream));
-            if (!scan(buf.data(), m))
+            if (!merged->scan(buf.data(), m))
                 return PPCG_OK;
         }
     }
     keys->clear();
-    for (int p = 0; p < kSlots; ++p)
-        if (used[p])
-            keys->push_back(slot[p]);
+    for (int p = 0; p < ValueSet::kSlots; ++p)
+        if (merged->used[p])
+            keys->push_back(merged->slot[p]);
     std::sort(keys->begin(), keys->end());
     *fits = true;
     return PPCG_OK;
