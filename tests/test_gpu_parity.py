@@ -158,12 +158,14 @@ def _tridiag_values(n, k):
     return CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64), f"tri{k}")
 
 
-def test_value_table_holds_at_most_256_values():
+@pytest.mark.parametrize("n", [6000, 1_200_000])
+def test_value_table_holds_at_most_256_values(n):
     """254 off-diagonal values + 4 + the padding's 0 = 256 fit the one-byte
     table; one more value and the matrix keeps its 8-byte values.  Either way
-    the SpMV equals the oracle's bit for bit."""
+    the SpMV equals the oracle's bit for bit.  At 1.2M rows (3.6M values) the
+    scan runs on several host threads whose value sets are merged."""
     for k, fits in ((254, True), (255, False)):
-        A = _tridiag_values(6000, k)
+        A = _tridiag_values(n, k)
         S = Solver(A, spmv_format="sell", flags=ppcg.FLAG_SELL_VALUE_TABLE)
         mi = S.matrix_info()
         assert mi["distinct_values"] == (256 if fits else 0), k
