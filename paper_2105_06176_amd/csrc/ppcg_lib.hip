@@ -645,8 +645,10 @@ static ppcg_status build_vtab(ppcg_handle *h, const std::vector<uint64_t> &keys)
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s);
+    // always: the copies above read and write host memory of this frame
+    const hipError_t es = hipStreamSynchronize(s);
     if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
+        e = es;
     if (flag)
         (void)dev_free(flag);
     if (e != hipSuccess || bad) {
