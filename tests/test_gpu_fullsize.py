@@ -95,12 +95,25 @@ def test_c4_full_batch():
         S.close()
 
 
-def test_table2_125pt_side165_full_size():
+@pytest.fixture(scope="module")
+def p125():
     A = poisson125(165)
-    b = rhs_from_solution(A, xstar_paper(A.n))
+    return A, rhs_from_solution(A, xstar_paper(A.n))
+
+
+@pytest.mark.parametrize("vflag", [ppcg.FLAG_SELL_VALUE_TABLE, ppcg.FLAG_SELL_FULL_VALUES])
+def test_table2_125pt_side165_full_size(p125, vflag):
+    """Table 2's matrix at full size with its three distinct values read
+    through the one-byte table (as the autotuner picks it) and as 8-byte
+    values: the SpMV equals the oracle's bit for bit, and x_5 and the
+    iteration count under the paper's protocol match the stored values."""
+    A, b = p125
     vals, meta = _golden("p125_side165.txt", "x5")
     assert (meta["n"], meta["nnz"]) == (A.n, A.nnz)
-    S = Solver(A, fixed_iters=5)
+    S = Solver(A, fixed_iters=5, flags=vflag)
+    assert S.matrix_info()["value_bytes"] == (1 if vflag == ppcg.FLAG_SELL_VALUE_TABLE else 8)
+    xs = xstar_uniform(A.n, 5)
+    assert np.array_equal(host(S.spmv(dev(xs))), oracle.spmv(A, xs))
     x, info = S.solve(dev(b))
     assert info["iters"] == 5
     _check_sampled(host(x), vals, meta, 5)
@@ -109,3 +122,4 @@ def test_table2_125pt_side165_full_size():
     assert info["status"] == ppcg.OK
     assert abs(info["iters"] - int(meta["abs1e-5_iters"])) <= 2
     assert info["precond_norm"] < 1e-5
+    S.close()

@@ -256,17 +256,24 @@ def c2():
     return A, b
 
 
-def test_c2_full_size_spmv_bitwise(c2):
+# the storage bench.py pins for this matrix, and the autotuner's own choice
+C2_STORAGE = {"bench": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES),
+              "auto": {}}
+
+
+@pytest.mark.parametrize("storage", sorted(C2_STORAGE))
+def test_c2_full_size_spmv_bitwise(c2, storage):
     A, _ = c2
-    S = Solver(A)
+    S = Solver(A, **C2_STORAGE[storage])
     x = xstar_uniform(A.n, 5)
     assert np.array_equal(host(S.spmv(dev(x))), oracle.spmv(A, x))
 
 
-def test_c2_full_size_500_iterations_sampled(c2):
+@pytest.mark.parametrize("storage", sorted(C2_STORAGE))
+def test_c2_full_size_500_iterations_sampled(c2, storage):
     A, b = c2
     vals, meta = _golden_c2()
-    S = Solver(A, fixed_iters=500)
+    S = Solver(A, fixed_iters=500, **C2_STORAGE[storage])
     x, info = S.solve(dev(b))
     assert info["iters"] == 500
     xh = host(x)
@@ -276,10 +283,11 @@ def test_c2_full_size_500_iterations_sampled(c2):
     assert abs(np.linalg.norm(xh) - meta["norm_x500"]) <= 1e-10 * meta["norm_x500"]
 
 
-def test_c2_full_size_to_tolerance(c2):
+@pytest.mark.parametrize("storage", sorted(C2_STORAGE))
+def test_c2_full_size_to_tolerance(c2, storage):
     A, b = c2
     _, meta = _golden_c2()
-    S = Solver(A, tol=1e-10)
+    S = Solver(A, tol=1e-10, **C2_STORAGE[storage])
     x, info = S.solve(dev(b))
     assert info["status"] == ppcg.OK
     assert abs(info["iters"] - int(meta["tol1e-10_iters"])) <= 2
