@@ -411,7 +411,13 @@ def leg_p125(torch, ppcg, wl, side=165):
     return out
 
 
-def _serve_requests(wl, n_req, seed=0):
+def _serve_requests(wl, n_req, seed=0, pool=0):
+    """n_req requests; with pool > 0, drawn uniformly from pool distinct ones
+    (same kind, size and tolerance distribution, far less host memory)."""
+    if pool and pool < n_req:
+        base = _serve_requests(wl, pool, seed)
+        pick = np.random.default_rng(seed + 1).integers(pool, size=n_req)
+        return [base[k] for k in pick]
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(n_req):
@@ -429,12 +435,16 @@ def _serve_requests(wl, n_req, seed=0):
     return reqs
 
 
-def _run_server(ppcg, reqs, arrivals):
+def _run_server(ppcg, reqs, arrivals, depth=None):
+    """Serve reqs arriving at the given times; returns the total time and the
+    latencies.  depth (a dict), when given, receives the mean and largest
+    queued and active counts seen after the steps."""
     srv = ppcg.Server(borrow=True)  # requests reference the generated arrays (no host copy)
     t0 = time.perf_counter()
     i = 0
     pending = {}
     lat = []
+    qs, acts = [], []
     while i < len(reqs) or pending:
         now = time.perf_counter() - t0
         while i < len(reqs) and arrivals[i] <= now:
@@ -443,6 +453,8 @@ def _run_server(ppcg, reqs, arrivals):
             i += 1
         if pending:
             active, queued = srv.step()
+            qs.append(queued)
+            acts.append(active)
             # poll only when some request finished and is not yet fetched
             if len(pending) > active + queued:
                 for rid in list(pending):
@@ -453,22 +465,30 @@ def _run_server(ppcg, reqs, arrivals):
             time.sleep(max(0.0, min(0.01, arrivals[i] - now)))
     total = time.perf_counter() - t0
     srv.close()
+    if depth is not None and qs:
+        depth.update({"queue_mean": round(float(np.mean(qs)), 1), "queue_max": int(max(qs)),
+                      "active_mean": round(float(np.mean(acts)), 1), "active_max": int(max(acts))})
     return total, np.array(lat)
 
 
-def leg_c5(ppcg, wl, n_req):
+def leg_c5(ppcg, wl, n_req, loads=(0.5, 0.8), pool=0):
     t0 = time.perf_counter()
-    reqs = _serve_requests(wl, n_req)
-    log(f"serving: {n_req} requests generated in {time.perf_counter() - t0:.1f}s")
-    # warm-up over the whole stream: every variant below then finds the SpMV
-    # autotuner's choices cached for the stream's matrix signatures
-    _run_server(ppcg, reqs, np.zeros(n_req))
-    total, lat = _run_server(ppcg, reqs, np.zeros(n_req))  # saturation: all at t = 0
+    reqs = _serve_requests(wl, n_req, pool=pool)
+    log(f"serving: {n_req} requests ({pool or n_req} distinct) generated in {time.perf_counter() - t0:.1f}s")
+    # warm-up over the stream's distinct requests: every variant below then
+    # finds the SpMV autotuner's choices cached for its matrix signatures
+    uniq = list({id(r[0]): r for r in reqs}.values())
+    _run_server(ppcg, uniq, np.zeros(len(uniq)))
+    sat_depth = {}
+    total, lat = _run_server(ppcg, reqs, np.zeros(n_req), sat_depth)  # saturation: all at t = 0
     sat = n_req / total
+    log(f"serving at saturation: {sat:.2f} solves/s, {sat_depth}")
     # the same stream with every request in plain FP64, and with FP32 values
     reqs64 = [(A, b, tol, "fp64") for A, b, tol, _ in reqs]
     total64, _ = _run_server(ppcg, reqs64, np.zeros(n_req))
+    log(f"serving, every request in FP64: {n_req / total64:.2f} solves/s")
     total32, _ = _run_server(ppcg, [(A, b, tol, "mixed_values") for A, b, tol, _ in reqs], np.zeros(n_req))
+    log(f"serving, every request with FP32 values: {n_req / total32:.2f} solves/s")
     # plain FP64 PPCG one request after another (a solver per request)
     t0 = time.perf_counter()
     import torch
@@ -478,7 +498,9 @@ def leg_c5(ppcg, wl, n_req):
         S.solve(torch.as_tensor(b), out=torch.empty(A.n, dtype=torch.float64))
         S.close()
     t_seq = time.perf_counter() - t0
-    out = {"workload": f"{n_req} requests: 40% 2D 5-pt, 30% 3D 7-pt, 30% random SPD, N log-uniform [1e3,4e6], "
+    log(f"sequential FP64 solves: {n_req / t_seq:.2f} solves/s")
+    out = {"workload": f"{n_req} requests ({pool or n_req} distinct): 40% 2D 5-pt, 30% 3D 7-pt, 30% random SPD, "
+                       "N log-uniform [1e3,4e6], "
                        "tol {1e-6,1e-8,1e-10}; precision chosen by the server (FP32 classic PCG with FP64 "
                        "reliable updates for >= 262144 rows, FP32 values with FP64 reliable updates "
                        "for >= 65536 rows, else FP64)",
@@ -486,15 +508,16 @@ def leg_c5(ppcg, wl, n_req):
            "saturation_solves_per_s_all_fp64": round(n_req / total64, 2),
            "saturation_solves_per_s_all_fp32_values": round(n_req / total32, 2),
            "sequential_fp64_solves_per_s": round(n_req / t_seq, 2),
-           "served_over_sequential_fp64": round(t_seq / total, 3)}
+           "served_over_sequential_fp64": round(t_seq / total, 3), "saturation_depth": sat_depth}
     rng = np.random.default_rng(0)
-    for frac in (0.5, 0.8):
+    for frac in loads:
         lam = frac * sat
         arr = np.cumsum(rng.exponential(1 / lam, size=n_req))
-        total, lat = _run_server(ppcg, reqs, arr)
+        depth = {}
+        total, lat = _run_server(ppcg, reqs, arr, depth)
         out[f"load_{frac}"] = {"rate_per_s": round(lam, 2), "solves_per_s": round(n_req / total, 2),
                                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-                               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)}
+                               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2), **depth}
         log(f"serving at {frac} x saturation: {out[f'load_{frac}']}")
     return out
 
@@ -509,6 +532,10 @@ def main():
     ap.add_argument("--legs", default="c1,c3,c4,c5,p125,pcg,shard,hybrid",
                     help="extra legs: c1,c3,c4,c5,p125,pcg,shard,hybrid or none")
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-pool", type=int, default=0,
+                    help="draw the serving requests from this many distinct ones (0: all distinct)")
+    ap.add_argument("--serve-loads", default="0.5,0.8",
+                    help="arrival rates as fractions of the measured saturation rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 256 MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -558,7 +585,8 @@ def main():
             elif name == "c4":
                 legs[name] = leg_c4(torch, ppcg, wl)
             elif name == "c5":
-                legs[name] = leg_c5(ppcg, wl, args.serve_requests)
+                legs[name] = leg_c5(ppcg, wl, args.serve_requests,
+                                    tuple(float(v) for v in args.serve_loads.split(",") if v), args.serve_pool)
             elif name == "p125":
                 legs[name] = leg_p125(torch, ppcg, wl)
         except Exception as e:  # a failing extra leg must not hide the main line

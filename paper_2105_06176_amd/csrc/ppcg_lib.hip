@@ -13,12 +13,14 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -272,6 +274,11 @@ struct TuneVal {
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneVal> g_tune_cache;
+// Signatures being tuned: one thread tunes a signature at a time, and
+// the others wait for its choice, so every handle of a signature gets the
+// same layout (the layout decides the summation order of the results).
+static std::set<TuneKey> g_tuning;
+static std::condition_variable g_tune_cv;
 
 ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double tol, int fixed, int maxit,
                       int stop, int vals32)
@@ -791,26 +798,49 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
     }
     TuneKey key{(int)std::log2((double)h->n), (int)std::lround(mean), (int)std::lround(10 * cv),
                 (int)std::log2((double)std::max(mx, 1))};
+    TuneVal tv{};
+    bool hit = false;
     {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
+        std::unique_lock<std::mutex> lk(g_tune_mu);
+        g_tune_cv.wait(lk, [&] { return !g_tuning.count(key); });
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            const TuneVal tv = it->second;
-            if (tv.fmt == FMT_SELL) {
-                SellBuild sb;
-                PPCG_TRY(build_sell(h->stream, h->n, tv.sigma, rp, ci, val, rowlen, &sb));
-                PPCG_TRY(adopt_sell(h, sb));
-            } else {
-                PPCG_TRY(adopt_csrv(h, tv.lanes, rp, ci, val));
-            }
-            PPCG_TRY(bind_f64(h, dinv_orig));
-            int c16 = 0;
-            PPCG_TRY(tune_col16(h, tv.col16, &c16));
-            if (tv.col16 < 0 && !forced16)
-                it->second.col16 = c16;  // timed now (the entry came from a forced choice)
-            return PPCG_OK;
+            tv = it->second;
+            hit = true;
+        } else {
+            g_tuning.insert(key);  // this thread tunes the signature
         }
     }
+    if (hit) {
+        if (tv.fmt == FMT_SELL) {
+            SellBuild sb;
+            PPCG_TRY(build_sell(h->stream, h->n, tv.sigma, rp, ci, val, rowlen, &sb));
+            PPCG_TRY(adopt_sell(h, sb));
+        } else {
+            PPCG_TRY(adopt_csrv(h, tv.lanes, rp, ci, val));
+        }
+        PPCG_TRY(bind_f64(h, dinv_orig));
+        int c16 = 0;
+        PPCG_TRY(tune_col16(h, tv.col16, &c16));
+        if (tv.col16 < 0 && !forced16) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key].col16 = c16;  // timed now (the entry came from a forced choice)
+        }
+        return PPCG_OK;
+    }
+    // on every return below (the choice stored first on success), the
+    // signature is released to the threads waiting for it
+    struct Release {
+        TuneKey k;
+        ~Release()
+        {
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_tuning.erase(k);
+            }
+            g_tune_cv.notify_all();
+        }
+    } release{key};
     struct Cand {
         int fmt, sigma, lanes;
     };

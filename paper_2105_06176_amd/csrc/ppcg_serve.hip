@@ -43,6 +43,13 @@ constexpr int kServerSlots = 1024;
 #define PPCG_SERVE_GRAPH_ITERS 8
 #endif
 constexpr int kServeGraphIters = PPCG_SERVE_GRAPH_ITERS;
+// preparation threads: requests are prepared concurrently (copy, validation,
+// layout and staging), taken first come first served, admitted as they
+// become ready
+#ifndef PPCG_SERVE_PREP_THREADS
+#define PPCG_SERVE_PREP_THREADS 2
+#endif
+constexpr int kPrepThreads = PPCG_SERVE_PREP_THREADS;
 // automatic precision: smallest systems given reduced precision
 #ifndef PPCG_AUTO_VALUES32_ROWS
 #define PPCG_AUTO_VALUES32_ROWS 65536
@@ -113,7 +120,7 @@ struct ppcg_server {
     bool stop = false;
     ppcg_status prep_rc = PPCG_OK;  // a device error met while preparing, reported by the next step
     std::string prep_msg;
-    std::thread prep;
+    std::vector<std::thread> prep;
 };
 
 // The preparation thread may take the first queued request: within the slot
@@ -370,13 +377,21 @@ ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *
     }
     if (rc == PPCG_OK) {
         try {
-            s->prep = std::thread(prep_loop, s.get());
+            for (int t = 0; t < kPrepThreads; ++t)
+                s->prep.emplace_back(prep_loop, s.get());
         } catch (...) {
             set_error("starting the preparation thread failed");
             rc = PPCG_ERR_NOMEM;
         }
     }
     if (rc != PPCG_OK) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->prep_cv.notify_all();
+        for (std::thread &t : s->prep)
+            t.join();
         s->eng.reset();
         if (s->prep_stream)
             (void)hipStreamDestroy(s->prep_stream);
@@ -526,8 +541,8 @@ ppcg_status ppcg_srv_destroy(ppcg_server *s)
         s->stop = true;
     }
     s->prep_cv.notify_all();
-    if (s->prep.joinable())
-        s->prep.join();  // a preparation under way completes first
+    for (std::thread &t : s->prep)
+        t.join();  // a preparation under way completes first
     if (s->stream)
         (void)hipStreamSynchronize(s->stream);
     for (auto &kv : s->reqs)
