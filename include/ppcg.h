@@ -422,9 +422,10 @@ ppcg_status ppcg_hybrid_solve(ppcg_hybrid *hy, const double *b, const double *x0
 ppcg_status ppcg_hybrid_destroy(ppcg_hybrid *hy); /* NULL-safe */
 
 /* ---------------------------------------------------------------------------
- * Serving: a continuous-batching solve server.  A thread owned by the
- * server prepares queued requests first-come first-served (matrix copied to
- * the device, validated and laid out, right-hand side staged) while the sum
+ * Serving: a continuous-batching solve server.  Two threads owned by the
+ * server prepare queued requests, taken first-come first-served (matrix
+ * copied to the device, validated and laid out, right-hand side staged),
+ * and hand them over as they become ready, while the sum
  * of the device footprints (ppcg_footprint_bytes) of the requests it holds
  * stays within the budget, and releases the memory of retired ones; both
  * overlap with the iterations of the active requests.  Prepared requests

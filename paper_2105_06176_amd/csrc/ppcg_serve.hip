@@ -1,15 +1,16 @@
 // ppcg_serve.hip -- continuous-batching solve server (ppcg_srv_* in ppcg.h).
 //
-// Requests queue on the host.  A preparation thread owned by the server
-// takes them first-come first-served while the sum of the device footprints
-// of the requests it holds (in preparation, prepared, or on the device) stays
-// within the budget, and prepares each one on a stream of its own: the
+// Requests queue on the host.  Preparation threads owned by the server take
+// them first-come first-served while the sum of the device footprints of the
+// requests the server holds (in preparation, prepared, or on the device)
+// stays within the budget, and prepare each one on a stream of its own: the
 // matrix is copied to the device, validated and laid out (ppcg_create) and
 // the right-hand side staged.  Each scheduling step admits the prepared
-// requests in the same order into the shared batched engine, runs one graph
-// chunk of PIPECG iterations over every active request, and retires the
-// requests that finished: their solution is copied back to the host, and the
-// preparation thread releases their device memory.  Preparation and release
+// requests, in the order they became ready, into the shared batched engine,
+// runs one graph chunk of PIPECG iterations over every active request, and
+// retires the requests that finished: a preparation thread copies their
+// solutions back to the host and releases their device memory.  Preparation
+// and release
 // therefore overlap with the iterations of the requests already on the
 // device (releasing memory synchronizes the device), and requests that arrive
 // while others iterate join the batched launches at the next chunk
@@ -84,11 +85,10 @@ struct Request {
 
 }  // namespace
 
-// Ownership: the preparation thread alone touches a request in state
-// RQ_PREPARING or RQ_FINISHING; the calling thread alone touches one in
+// Ownership: the preparation thread that took a request alone touches it in
+// state RQ_PREPARING or RQ_FINISHING; the calling thread alone touches one in
 // RQ_PREPARED or RQ_ACTIVE.  The map, the queues, the counters and every
-// state change are
-// guarded by `mu`.
+// state change are guarded by `mu`.
 struct ppcg_server {
     hipStream_t stream = nullptr;       // the engine's stream
     hipStream_t prep_stream = nullptr;  // orders each preparation (its handle has a stream of its own)
