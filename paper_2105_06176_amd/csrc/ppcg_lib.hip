@@ -694,12 +694,30 @@ static void drop_vtab(ppcg_handle *h)
 // rows of a 7-point stencil are bound by the latency of the column load and
 // the gather that depends on it: halving their bytes saved 2-3 % of the
 // SpMV, about 1 % of an iteration.  The 125-point rows' SpMV ran 1.45x
-// faster.  PPCG_FLAG_SELL_VALUE_TABLE / _FULL_VALUES force the choice, and
-// PPCG_SELL_VTAB = 0 switches it off.
+// faster.  The decision is cached per (rows, mean row length) signature: a
+// matrix of a signature whose table lost is not scanned, one whose table
+// won keeps its table when it has one, untimed.  PPCG_FLAG_SELL_VALUE_TABLE /
+// _FULL_VALUES force the choice, and PPCG_SELL_VTAB = 0 switches it off.
+// Timed value-table decisions by (log2 of the row count, mean stored row
+// length): a signature whose table lost is not scanned again.
+static std::map<std::pair<int, int>, bool> g_vtab_kept;
+
 static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const double *val_dev)
 {
     const unsigned fl = h->opt.flags;
     if (!PPCG_SELL_VTAB || h->fmt != FMT_SELL || (fl & PPCG_FLAG_SELL_FULL_VALUES))
+        return PPCG_OK;
+    const std::pair<int, int> sig((int)std::log2((double)h->n), (int)std::lround((double)h->nnz_stored / h->n));
+    bool known = false, kept = false;
+    if (!(fl & PPCG_FLAG_SELL_VALUE_TABLE)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_vtab_kept.find(sig);
+        if (it != g_vtab_kept.end()) {
+            known = true;
+            kept = it->second;
+        }
+    }
+    if (known && !kept)
         return PPCG_OK;
     std::vector<uint64_t> keys;
     bool fits = false;
@@ -707,7 +725,7 @@ static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const doubl
     if (!fits)
         return PPCG_OK;
     PPCG_TRY(build_vtab(h, keys));
-    if (!h->vidx || (fl & PPCG_FLAG_SELL_VALUE_TABLE))
+    if (!h->vidx || (fl & PPCG_FLAG_SELL_VALUE_TABLE) || known)
         return PPCG_OK;
     unsigned char *vi = h->vidx;
     double tf = 1e300, tv = 1e300;
@@ -722,8 +740,11 @@ static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const doubl
         tv = std::min(tv, t);
     }
     const double t_update_ms = byte_model(h, PREC_F64).vma / 6.5e12 * 1e3;
-    if (!(tf - tv >= 0.05 * (tf + t_update_ms)))
+    const bool keep = tf - tv >= 0.05 * (tf + t_update_ms);
+    if (!keep)
         drop_vtab(h);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_vtab_kept[sig] = keep;
     return PPCG_OK;
 }
 
