@@ -21,7 +21,10 @@
  *   - Work is ordered on the HIP stream given at creation (NULL = the
  *     default stream).  A call returns once its outputs are final.
  *   - Handles are not thread-safe; one handle may be used by one thread at
- *     a time and takes part in at most one solve at a time.
+ *     a time and takes part in at most one solve at a time.  Different
+ *     handles (and servers) may be used from different threads at once: the
+ *     autotuner's choices and the library's memory releases are shared
+ *     safely, and results do not depend on what other threads run.
  *   - Sizes: n >= 1 rows, nnz < 2^31.  Row pointers and column indices are
  *     int32, values float64.
  */
