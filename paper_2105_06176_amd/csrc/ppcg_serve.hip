@@ -123,8 +123,9 @@ struct ppcg_server {
     std::vector<std::thread> prep;
 };
 
-// The preparation thread may take the first queued request: within the slot
-// count, and within the budget unless nothing else holds device memory.
+// A preparation thread may take the first queued request: within the slot
+// count, and within the budget unless nothing else holds device memory (a
+// retired request holds its memory until it is released).
 static bool can_prepare(const ppcg_server *s)
 {
     if (s->stop || s->prep_rc != PPCG_OK || s->queue.empty())
@@ -133,7 +134,7 @@ static bool can_prepare(const ppcg_server *s)
     if (held >= kServerSlots)
         return false;
     const Request &r = s->reqs.at(s->queue.front());
-    return held == 0 || s->used + r.footprint <= s->budget;
+    return (held == 0 && s->finishing == 0) || s->used + r.footprint <= s->budget;
 }
 
 // Copy the request's matrix and right-hand side to the device (runs on the
@@ -235,6 +236,7 @@ static void prep_loop(ppcg_server *s)
                 s->prep_msg = msg;
             }
             s->ready_cv.notify_all();
+            s->prep_cv.notify_all();  // memory released: another thread may prepare
             continue;
         }
         if (s->stop)
