@@ -528,9 +528,20 @@ def test_server_refuses_over_budget_and_admits_in_turn():
     with pytest.raises(PPCGError) as e:
         srv.submit(big, problem(big)[0], 1e-8)
     assert e.value.status == ppcg.ERR_BUDGET
-    res = _serve_all(srv, [(f"r{i}", A, b, 1e-8, "fp64") for i in range(4)], stagger=4)
-    assert len(res) == 4
-    xs = [res[f"r{i}"][0] for i in range(4)]
+    # all four queued at once; the budget holds one at a time, also while a
+    # finished one is still being copied out and released (counted as active)
+    ids = [srv.submit(A, b, 1e-8) for _ in range(4)]
+    xs, most = {}, 0
+    while len(xs) < 4:
+        active, queued = srv.step()
+        most = max(most, active)
+        for rid in ids:
+            if rid not in xs:
+                r = srv.poll(rid)
+                if r is not None:
+                    xs[rid] = r[0]
+    assert most == 1
+    xs = list(xs.values())
     for x in xs[1:]:
         assert np.array_equal(x, xs[0])
 
