@@ -98,12 +98,12 @@ struct ppcg_server {
     int64_t next_id = 1;
     std::unique_ptr<Engine> eng;
     std::mutex mu;
-    std::condition_variable prep_cv;   // wakes the preparation thread
+    std::condition_variable prep_cv;   // wakes the preparation threads
     std::condition_variable ready_cv;  // wakes a step that waits for a prepared request
     std::map<int64_t, Request> reqs;
     std::deque<int64_t> queue;  // awaiting preparation, first come first served
-    std::deque<int64_t> ready;  // prepared, awaiting admission, in the same order
-    // Retired requests: the preparation thread copies the solution out and
+    std::deque<int64_t> ready;  // prepared, awaiting admission, in the order they became ready
+    // Retired requests: a preparation thread copies the solution out and
     // releases the handle (a release synchronizes the device), then marks
     // the request ready to poll, or queues it again for an FP64 rerun.
     struct Retired {
@@ -183,7 +183,7 @@ static void prep_loop(ppcg_server *s)
     std::unique_lock<std::mutex> lk(s->mu);
     if (!dev_ok) {
         s->prep_rc = PPCG_ERR_DEVICE;
-        s->prep_msg = "hipSetDevice failed on the preparation thread";
+        s->prep_msg = "hipSetDevice failed on a preparation thread";
         s->ready_cv.notify_all();
         return;
     }
