@@ -137,7 +137,7 @@ static bool can_prepare(const ppcg_server *s)
     return (held == 0 && s->finishing == 0) || s->used + r.footprint <= s->budget;
 }
 
-// Copy the request's matrix and right-hand side to the device (runs on the
+// Copy the request's matrix and right-hand side to the device (runs on a
 // preparation thread, unlocked).  A request whose matrix ppcg_create refuses
 // fails on its own; a device error is returned.
 static ppcg_status prepare(ppcg_server *s, Request &r)
