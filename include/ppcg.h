@@ -441,8 +441,10 @@ ppcg_status ppcg_hybrid_destroy(ppcg_hybrid *hy); /* NULL-safe */
  * ------------------------------------------------------------------------- */
 typedef struct ppcg_server ppcg_server;
 
-/* Create a server on hip_stream with a device-memory budget in bytes
- * (0 = 80% of the free device memory).  opt supplies defaults for requests. */
+/* Create a server on the current device with a device-memory budget in
+ * bytes (0 = 80% of the free device memory).  opt supplies defaults for
+ * requests.  hip_stream is not used: the server orders its work on streams
+ * of its own, and results reach the caller only through ppcg_srv_poll. */
 ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *hip_stream,
                             ppcg_server **out);
 
