@@ -253,9 +253,11 @@ ppcg_status ppcg_solve(ppcg_handle *h, const double *b, const double *x0, double
  * PIPECG iteration of all unconverged systems runs as one fused-update launch
  * and one SpMV launch over a table of (system, row tile) work items, captured
  * in HIP graphs; converged systems leave the table between graph launches.
- * hs: [count] distinct handles (same device and stream as hs[0]); b, x0, x:
- * [count] arrays of per-system pointers as in ppcg_solve (x0[i] or x0 itself
- * may be NULL).  infos: [count] or NULL.  Returns PPCG_OK when the batch ran;
+ * hs: [count] distinct handles on one device; their streams may differ: the
+ * batch waits for the work queued on every handle's stream before it reads
+ * b[i] and x0[i], and returns once x[i] is written.  b, x0, x: [count] arrays
+ * of per-system pointers as in ppcg_solve (x0[i] or x0 itself may be NULL).
+ * infos: [count] or NULL.  Returns PPCG_OK when the batch ran;
  * per-system outcomes are in infos[i].status.  Each system's result is
  * bitwise identical to solving it alone with ppcg_solve. */
 ppcg_status ppcg_solve_batch(int32_t count, ppcg_handle *const *hs, const double *const *b,
@@ -443,10 +445,9 @@ typedef struct ppcg_server ppcg_server;
 
 /* Create a server on the current device with a device-memory budget in
  * bytes (0 = 80% of the free device memory).  opt supplies defaults for
- * requests.  hip_stream is not used: the server orders its work on streams
- * of its own, and results reach the caller only through ppcg_srv_poll. */
-ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *hip_stream,
-                            ppcg_server **out);
+ * requests.  The server takes no stream: its inputs and results are host
+ * arrays, and it orders its device work on streams of its own. */
+ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, ppcg_server **out);
 
 /* Queue a request.  A: host CSR; b: host [n] FP64; both copied before
  * returning, or referenced until the request is polled ready when the server

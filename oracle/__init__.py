@@ -10,7 +10,9 @@ Functions and the passages they follow (Tiwari & Vadhiyar, arXiv 2105.06176):
 
 * ``spmv``      - sparse matrix-vector product with A in CSR (Section V-A).
 * ``jacobi``    - inverse diagonal of A, the Jacobi preconditioner (Section V-A).
-* ``dot``       - sequential FP64 dot product.
+* ``dot``       - FP64 dot product, summed left to right, or with Neumaier's
+                  compensated summation (``dots="comp"``; every solver takes
+                  the same switch for all of its dot products).
 * ``pcg``       - Algorithm 1, PCG (Section III-A).
 * ``pipecg``    - Algorithm 2, PIPECG (Section III-B).
 * ``true_relres`` - ||b - A x|| / ||b||.
@@ -85,6 +87,8 @@ def _load():
     lib.ora_spmv.restype = None
     lib.ora_dot.argtypes = [I, P, P]
     lib.ora_dot.restype = D
+    lib.ora_set_dot_mode.argtypes = [I]
+    lib.ora_set_dot_mode.restype = None
     lib.ora_jacobi.argtypes = [I, P, P, P, P]
     lib.ora_jacobi.restype = I
     lib.ora_true_relres.argtypes = [I, P, P, P, P, P]
@@ -117,11 +121,18 @@ def spmv(A, x: np.ndarray) -> np.ndarray:
     return y
 
 
-def dot(a: np.ndarray, b: np.ndarray) -> float:
+_DOT_MODES = {"seq": 0, "comp": 1}
+
+
+def dot(a: np.ndarray, b: np.ndarray, dots: str = "seq") -> float:
     lib = _load()
     a = np.ascontiguousarray(a, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64)
-    return lib.ora_dot(a.size, _p(a), _p(b))
+    lib.ora_set_dot_mode(_DOT_MODES[dots])
+    try:
+        return lib.ora_dot(a.size, _p(a), _p(b))
+    finally:
+        lib.ora_set_dot_mode(0)
 
 
 def jacobi(A) -> np.ndarray:
@@ -146,8 +157,9 @@ _SCALAR_NAMES = ("gamma", "delta", "uu", "rr", "alpha_prev", "gamma_prev", "beta
 
 
 def _run(which: str, A, b, x0=None, tol=1e-8, maxit=10000, fixed_iters=0, stop=STOP_REL,
-         max_restarts=3, history=False, state=False) -> Result:
+         max_restarts=3, history=False, state=False, dots="seq") -> Result:
     lib = _load()
+    mode = _DOT_MODES[dots]
     rp, ci, val = _csr(A)
     n = A.n
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -159,10 +171,14 @@ def _run(which: str, A, b, x0=None, tol=1e-8, maxit=10000, fixed_iters=0, stop=S
     st = np.zeros(10 * n + 7) if state else None
     args = [n, _p(rp), _p(ci), _p(val), _p(b), _p(x0a), _p(x), float(tol), int(maxit), int(fixed_iters),
             int(stop), int(max_restarts), ctypes.byref(info), _p(hist), hist_len]
-    if which == "pcg":
-        lib.ora_pcg(*args)
-    else:
-        lib.ora_pipecg(*args, _p(st))
+    lib.ora_set_dot_mode(mode)
+    try:
+        if which == "pcg":
+            lib.ora_pcg(*args)
+        else:
+            lib.ora_pipecg(*args, _p(st))
+    finally:
+        lib.ora_set_dot_mode(0)
     res = Result(x, info.iters, info.restarts, info.status, info.rel_true, info.rel_recur,
                  info.precond_norm, info.bnorm)
     if history:

@@ -12,7 +12,8 @@
  *                    each row summed left to right in stored column order.
  *   - ora_jacobi   : the Jacobi preconditioner M = diag(A) (Section V-A),
  *                    stored as dinv_i = 1 / a_ii and applied as dinv (.) v.
- *   - ora_dot      : sequential left-to-right FP64 sum of products.
+ *   - ora_dot      : FP64 sum of products, left to right (default) or with
+ *                    Neumaier's compensated summation (ora_set_dot_mode).
  *   - ora_pcg      : Algorithm 1 (PCG, Section III-A).
  *   - ora_pipecg   : Algorithm 2 (PIPECG, Section III-B), with the squared
  *                    residual norm rho = (r, r) computed beside gamma, delta
@@ -75,9 +76,33 @@ void ora_spmv(int n, const int *rp, const int *ci, const double *v, const double
     }
 }
 
+/* How ora_dot sums its products: ORA_DOT_SEQ (the default) left to right;
+ * ORA_DOT_COMP with Neumaier's compensated summation, which keeps the
+ * rounding error of every addition in a second accumulator.  The paper
+ * leaves the order of the dot products to its BLAS library, so both are
+ * admissible roundings of the same definition; comparing the iterates of the
+ * two measures how far any reordering of the sums moves them. */
+enum { ORA_DOT_SEQ = 0, ORA_DOT_COMP = 1 };
+static int g_dot_mode = ORA_DOT_SEQ;
+
+void ora_set_dot_mode(int mode) { g_dot_mode = mode == ORA_DOT_COMP ? ORA_DOT_COMP : ORA_DOT_SEQ; }
+
 double ora_dot(int n, const double *a, const double *b)
 {
     double acc = 0.0;
+    if (g_dot_mode == ORA_DOT_COMP) {
+        double comp = 0.0; /* sum of the rounding errors of the additions */
+        for (int i = 0; i < n; ++i) {
+            double prod = a[i] * b[i];
+            double t = acc + prod;
+            if (fabs(acc) >= fabs(prod))
+                comp = comp + ((acc - t) + prod);
+            else
+                comp = comp + ((prod - t) + acc);
+            acc = t;
+        }
+        return acc + comp;
+    }
     for (int i = 0; i < n; ++i) {
         double prod = a[i] * b[i];
         acc = acc + prod;

@@ -114,6 +114,7 @@ struct ppcg_handle {
     double *part32 = nullptr; // partials of the FP32-vector sequence
     double setup_ms = 0.0;
     ppcg::Engine *solo = nullptr;  // cached single-system engine
+    hipEvent_t ev_user = nullptr;  // recorded on user_stream for the internal stream to wait on
     // Single-system launch description for direct kernel calls (SpMV,
     // kernel timing, autotuning): descriptor, state, table of all tiles.
     ppcg::SysDesc *plain_desc = nullptr;
@@ -143,9 +144,13 @@ struct Job {
     double rel_true = 0.0, rel_recur = 0.0, precond_norm = 0.0;
     double bnorm2 = 0.0;
     int iters = 0;
-    // convergence tracking for choosing graph chunk lengths
+    // convergence tracking for choosing graph chunk lengths: the stopping
+    // quantity and iteration count at the last poll of the current start
+    // (last_norm < 0: not polled yet), and the mean reduction factor per
+    // iteration between the last two polls (< 0: unknown)
     double last_norm = -1.0;
     int last_iter = 0;
+    double rate = -1.0;
     // MIX_VALUES32: residual norm right after the last replacement (-1: unknown)
     double repl_ref = -1.0;
     // FP64 system small enough for the one-workgroup iteration kernel
@@ -257,9 +262,49 @@ class Engine {
     std::vector<Job> jobs_;
 };
 
+// What follows a stopped FP64 sequence (Algorithm 2, or 1 with FP64 values)
+// once its true residual rel = ||b - A x|| / ||b|| is known: restart from x
+// when the recurrence met a relative tolerance the true residual misses, or
+// after a breakdown past the first iteration of a start (the recurrences
+// lost near the attainable accuracy), while restarts and iterations remain;
+// a missed tolerance with no restart left is STAGNATED; anything else ends
+// with the sequence's own status.
+enum FinalAction { FINAL_DONE = 0, FINAL_RESTART = 1, FINAL_STAGNATED = 2 };
+inline FinalAction final_action(const ppcg_options &o, const SysState &st, int restarts, double rel, double tol)
+{
+    const bool tol_mode = o.fixed_iters <= 0;
+    const bool can_restart = tol_mode && restarts < o.max_restarts && st.iter < o.max_iter;
+    if (st.status == ST_OK && tol_mode && o.stop == PPCG_STOP_REL_RESID && rel > tol)
+        return can_restart ? FINAL_RESTART : FINAL_STAGNATED;
+    if (st.status == ST_BREAKDOWN && st.i_start > 0 && can_restart)
+        return FINAL_RESTART;
+    return FINAL_DONE;
+}
+
 // Aux operations run over a subset of slots.
 enum AuxOp { AUX_INIT = 0, AUX_RESID = 1, AUX_MIX_START = 2, AUX_MIX_CORRECT = 3, AUX_REPL = 4 };
 
+// Launch sequences of FP64 Algorithm 2 over a work table (grid = table
+// size), shared by the engine and ppcg_solve_noalloc:
+//   launch_x_complete   add the deferred x-update, if any, then clear it;
+//   launch_pipecg_init  the initialisation: r0 = b - A x, u0, w0, m0, n0 and
+//                       the reduction that yields the first alpha and beta;
+//   launch_pipecg_iter  one iteration (fused update, SpMV with reduction);
+//   launch_true_resid   ||b - A x||^2 and ||b||^2 into the state record.
+void launch_x_complete(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
+void launch_pipecg_init(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
+void launch_pipecg_iter(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int remap);
+void launch_true_resid(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
+
+// Iterations a running system still needs: exact in fixed-iteration mode,
+// else predicted from st (the last poll) and the reduction factor per
+// iteration observed between the last two polls (rate < 0: unknown, then
+// max_iters); polled: st belongs to the current start.  At least 1, at most
+// max_iters.
+int iters_needed(const SysDesc &d, const SysState &st, double rate, bool polled, int max_iters, bool pcg);
+// After a poll of a running system: update the reduction factor per
+// iteration since the previous poll, and remember this poll's norm and count.
+void note_progress(const SysDesc &d, const SysState &st, double *last_norm, int *last_iter, double *rate);
 double now_ms();
 // NULL, non-device and too-short device buffers are rejected with a message.
 ppcg_status check_dev_range(const void *p, size_t bytes, const char *what);

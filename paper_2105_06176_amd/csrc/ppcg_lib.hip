@@ -1088,6 +1088,34 @@ static ppcg_status upload_table(hipStream_t s, Group &g, const std::vector<WorkI
     return PPCG_OK;
 }
 
+// Launch sequences of FP64 Algorithm 2 over a work table, shared by the
+// engine and ppcg_solve_noalloc.
+void launch_x_complete(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid)
+{
+    k_x_fixup<double><<<grid, 256, 0, s>>>(tab, cnt, dd);
+    k_x_settle<<<grid, 64, 0, s>>>(tab, cnt, dd);
+}
+
+void launch_pipecg_init(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid)
+{
+    const int rs = PPCG_XCD_REMAP_SPMV;
+    k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+    k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+    k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+}
+
+void launch_pipecg_iter(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int remap)
+{
+    k_vma<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd, remap);
+    k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
+}
+
+void launch_true_resid(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid)
+{
+    k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
+    k_reduce_resid<<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd);
+}
+
 // One iteration of a group: the fused update, then the SpMV with the
 // in-launch reduction.  The FP32-values group uses the fused-update variant
 // that also emits the direct-denominator partials.
@@ -1110,8 +1138,7 @@ static void launch_iter_pair(hipStream_t s, const Group &g, int grid, int remap)
         k_vma<double, true><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
         k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
     } else {
-        k_vma<double><<<grid, kVmaThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, remap);
-        k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(g.table_d, g.count_d, g.desc_d, PPCG_XCD_REMAP_SPMV);
+        launch_pipecg_iter(s, g.table_d, g.count_d, g.desc_d, grid, remap);
     }
 }
 
@@ -1197,29 +1224,41 @@ ppcg_status Engine::ensure_graph(Group &g, int iters, hipGraphExec_t *exec)
 // jobs still needs (exact in fixed-iteration mode, predicted from the
 // observed convergence rate otherwise), capped at max_iters and rounded down
 // to a power of two so that few graphs are ever captured.
+int iters_needed(const SysDesc &d, const SysState &st, double rate, bool polled, int max_iters, bool pcg)
+{
+    int rem = max_iters;
+    if (d.fixed > 0) {
+        rem = d.fixed - (polled ? st.iter : 0);
+    } else if (polled && rate > 0.0 && rate < 0.9999) {
+        const double cur = d.stop == STOP_ABS ? std::sqrt(st.uu) : std::sqrt(st.rr);
+        double target = d.stop == STOP_ABS ? d.tol : d.tol * std::sqrt(st.bnorm2);
+        // a classic-PCG sequence that pauses for reliable updates stops at
+        // the pause if that comes first
+        if (pcg && d.repl_factor > 0.0 && d.stop == STOP_REL)
+            target = std::max(target, d.repl_factor * st.repl_ref);
+        if (cur > target && target > 0.0)
+            rem = (int)std::ceil(1.1 * std::log(target / cur) / std::log(rate)) + 1;
+    }
+    return std::max(1, std::min(rem, max_iters));
+}
+
+void note_progress(const SysDesc &d, const SysState &st, double *last_norm, int *last_iter, double *rate)
+{
+    const double cur = d.stop == STOP_ABS ? std::sqrt(st.uu) : std::sqrt(st.rr);
+    if (*last_norm > 0 && st.iter > *last_iter)
+        *rate = std::pow(cur / *last_norm, 1.0 / (st.iter - *last_iter));
+    *last_norm = cur;
+    *last_iter = st.iter;
+}
+
 int Engine::chunk_iters(const Group &g, int max_iters)
 {
     int want = 1;
     for (const Job &j : jobs_) {
         if (j.finished || j.stage != JS_ITER || &pgroup(j) != &g)
             continue;
-        const SysState &st = g.st_h[pslot(j)];
-        const SysDesc &d = g.desc_h[pslot(j)];
-        int rem = max_iters;
-        if (d.fixed > 0) {
-            rem = d.fixed - (j.last_norm < 0 ? 0 : st.iter);
-        } else if (j.last_norm > 0 && st.iter > j.last_iter) {
-            const double cur = d.stop == STOP_ABS ? std::sqrt(st.uu) : std::sqrt(st.rr);
-            double target = d.stop == STOP_ABS ? d.tol : d.tol * std::sqrt(st.bnorm2);
-            // a classic-PCG sequence that pauses for reliable updates stops at
-            // the pause if that comes first
-            if (g.pcg && d.repl_factor > 0.0 && d.stop == STOP_REL)
-                target = std::max(target, d.repl_factor * st.repl_ref);
-            const double rate = std::pow(cur / j.last_norm, 1.0 / (st.iter - j.last_iter));
-            if (rate > 0.0 && rate < 0.9999 && cur > target && target > 0.0)
-                rem = (int)std::ceil(1.1 * std::log(target / cur) / std::log(rate)) + 1;
-        }
-        want = std::max(want, std::min(rem, max_iters));
+        want = std::max(want, iters_needed(g.desc_h[pslot(j)], g.st_h[pslot(j)], j.rate, j.last_norm >= 0,
+                                           max_iters, g.pcg));
     }
     int k = 1;
     while (k * 2 <= want)
@@ -1256,10 +1295,8 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     const bool f32 = g.prec == PREC_F32;
     // the fused update of Algorithm 2 defers every other x-update: complete
     // x before anything reads it (a no-op for systems with nothing pending)
-    if (!g.pcg && &g != &gs_ && (what == AUX_RESID || what == AUX_REPL || what == AUX_INIT)) {
-        k_x_fixup<double><<<grid, 256, 0, s>>>(tab, cnt, dd);
-        k_x_settle<<<grid, 64, 0, s>>>(tab, cnt, dd);
-    }
+    if (!g.pcg && &g != &gs_ && (what == AUX_RESID || what == AUX_REPL || what == AUX_INIT))
+        launch_x_complete(s, tab, cnt, dd, grid);
     if (what == AUX_INIT && g.pcg) {
         if (f32) {
             k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
@@ -1282,12 +1319,9 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
         }
         k_pcg_update<PCG_REPL><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_INIT) {
-        k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+        launch_pipecg_init(s, tab, cnt, dd, grid);
     } else if (what == AUX_RESID) {
-        k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
-        k_reduce_resid<<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd);
+        launch_true_resid(s, tab, cnt, dd, grid);
     } else if (what == AUX_REPL) {
         // Reliable update: FP64 residual, then the rebuilt auxiliaries (two
         // dual-product passes with the iteration's values).
@@ -1533,21 +1567,13 @@ ppcg_status Engine::step(int graph_iters)
                     finish(j, st.status, st);
                 }
             } else if (j.stage == JS_NEED_FINAL) {
-                const bool can_restart = tol_mode && j.restarts < o.max_restarts && st.iter < o.max_iter;
-                if (st.status == ST_OK && tol_mode && o.stop == PPCG_STOP_REL_RESID && rel > j.tol) {
-                    if (can_restart) {
-                        ++j.restarts;
-                        j.stage = JS_NEED_INIT;
-                        continue;
-                    }
-                    finish(j, PPCG_STAGNATED, st);
-                } else if (st.status == ST_BREAKDOWN && st.i_start > 0 && can_restart) {
+                const FinalAction act = final_action(o, st, j.restarts, rel, j.tol);
+                if (act == FINAL_RESTART) {
                     ++j.restarts;
                     j.stage = JS_NEED_INIT;
                     continue;
-                } else {
-                    finish(j, st.status, st);
                 }
+                finish(j, act == FINAL_STAGNATED ? PPCG_STAGNATED : st.status, st);
             } else {  // FP32-vector mixed precision: outer refinement step
                 j.bnorm2 = st.bnorm2;
                 if (rel <= j.tol) {
@@ -1682,6 +1708,7 @@ ppcg_status Engine::step(int graph_iters)
         const SysDesc &d = g.desc_h[pslot(j)];
         if (st.done) {
             j.last_norm = -1.0;
+            j.rate = -1.0;
             if (j.mixed == MIX_INNER32) {
                 j.inner_iters = st.iter;  // the sequence's counter runs across reliable updates
                 j.precond_norm = std::sqrt(st.uu);
@@ -1692,8 +1719,7 @@ ppcg_status Engine::step(int graph_iters)
                 j.stage = JS_NEED_FINAL;
             }
         } else {
-            j.last_norm = d.stop == STOP_ABS ? std::sqrt(st.uu) : std::sqrt(st.rr);
-            j.last_iter = st.iter;
+            note_progress(d, st, &j.last_norm, &j.last_iter, &j.rate);
         }
     }
     return PPCG_OK;
@@ -1780,11 +1806,8 @@ void fill_info(const ppcg_handle *h, const Job &j, ppcg_info *info)
 // stream (the legacy default stream when the caller passed NULL).
 ppcg_status wait_user(ppcg_handle *h)
 {
-    hipEvent_t ev;
-    PPCG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    PPCG_HIP(hipEventRecord(ev, h->user_stream));
-    PPCG_HIP(hipStreamWaitEvent(h->stream, ev, 0));
-    (void)hipEventDestroy(ev);
+    PPCG_HIP(hipEventRecord(h->ev_user, h->user_stream));
+    PPCG_HIP(hipStreamWaitEvent(h->stream, h->ev_user, 0));
     return PPCG_OK;
 }
 
@@ -1890,6 +1913,8 @@ static void destroy_handle(ppcg_handle *h)
         (void)dev_free(h->dinv64);
     h->f64.arena.release();
     h->f32.arena.release();
+    if (h->ev_user)
+        (void)hipEventDestroy(h->ev_user);
     if (h->stream)
         (void)hipStreamDestroy(h->stream);
     delete h;
@@ -1952,14 +1977,10 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
     } while (0)
     CK(hipGetDevice(&h->device));
     CK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    CK(hipEventCreateWithFlags(&h->ev_user, hipEventDisableTiming));
     hipStream_t s = h->stream;
-    {
-        hipEvent_t ev;
-        CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        CK(hipEventRecord(ev, h->user_stream));
-        CK(hipStreamWaitEvent(s, ev, 0));
-        (void)hipEventDestroy(ev);
-    }
+    CK(hipEventRecord(h->ev_user, h->user_stream));
+    CK(hipStreamWaitEvent(s, h->ev_user, 0));
     const int n = A->n;
     const int64_t nnz = A->nnz;
     if (A->mem == PPCG_MEM_HOST) {
@@ -2152,8 +2173,22 @@ ppcg_status ppcg_solve_batch(int32_t count, ppcg_handle *const *hs, const double
     }
     ppcg_handle *h0 = hs[0];
     PPCG_HIP(hipSetDevice(h0->device));
-    PPCG_TRY(wait_user(h0));
     hipStream_t s = h0->stream;
+    // b[i] and x0[i] may come from work queued on any handle's stream: the
+    // batch waits for every distinct one before it stages the inputs.
+    {
+        std::vector<hipStream_t> seen;
+        for (int i = 0; i < count; ++i) {
+            if (std::find(seen.begin(), seen.end(), hs[i]->user_stream) != seen.end())
+                continue;
+            seen.push_back(hs[i]->user_stream);
+            hipStream_t keep = hs[i]->stream;
+            hs[i]->stream = s;
+            ppcg_status rc = wait_user(hs[i]);
+            hs[i]->stream = keep;
+            PPCG_TRY(rc);
+        }
+    }
     // All staging runs on the first handle's internal stream.
     for (int i = 0; i < count; ++i) {
         hipStream_t keep = hs[i]->stream;

@@ -352,7 +352,7 @@ static ppcg_status take_prep_error(ppcg_server *s)
 
 extern "C" {
 
-ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *hip_stream, ppcg_server **out)
+ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, ppcg_server **out)
 {
     clear_error();
     if (!out || !opt || opt->struct_size != sizeof(ppcg_options) || !(budget_bytes >= 0.0)) {
@@ -370,7 +370,6 @@ ppcg_status ppcg_srv_create(const ppcg_options *opt, double budget_bytes, void *
     s->budget = budget_bytes;
     PPCG_HIP(hipGetDevice(&s->device));
     PPCG_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
-    (void)hip_stream;  // requests are ordered on the server's own streams
     s->eng.reset(new Engine(s->stream));
     ppcg_status rc = s->eng->init(kServerSlots);
     if (rc == PPCG_OK && hipStreamCreateWithFlags(&s->prep_stream, hipStreamNonBlocking) != hipSuccess) {

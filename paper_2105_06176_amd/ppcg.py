@@ -141,7 +141,7 @@ def lib():
         "ppcg_hybrid_get_info": ([P, ctypes.POINTER(HybridInfo)], ctypes.c_int),
         "ppcg_hybrid_solve": ([P, P, P, P, ctypes.POINTER(Info)], ctypes.c_int),
         "ppcg_hybrid_destroy": ([P], ctypes.c_int),
-        "ppcg_srv_create": ([ctypes.POINTER(Options), D, P, ctypes.POINTER(P)], ctypes.c_int),
+        "ppcg_srv_create": ([ctypes.POINTER(Options), D, ctypes.POINTER(P)], ctypes.c_int),
         "ppcg_srv_submit": ([P, ctypes.POINTER(Csr), P, D, ctypes.c_int, ctypes.POINTER(I64)], ctypes.c_int),
         "ppcg_srv_step": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
         "ppcg_srv_poll": ([P, I64, ctypes.POINTER(I32), P, ctypes.POINTER(Info)], ctypes.c_int),
@@ -315,15 +315,15 @@ def footprint_bytes(n: int, nnz: int, precision: str = "fp64") -> float:
 class Server:
     """Continuous-batching solve server (ppcg_srv_*)."""
 
-    def __init__(self, budget_bytes: float = 0.0, stream=None, borrow: bool = False, **options):
+    def __init__(self, budget_bytes: float = 0.0, borrow: bool = False, **options):
         """borrow: requests reference the submitted arrays (kept alive here
         until polled ready) instead of the server copying them."""
         if borrow:
             options["flags"] = options.get("flags", 0) | FLAG_BORROW_INPUTS
         self.opt = make_options(**options)
         s = ctypes.c_void_p()
-        _check(lib().ppcg_srv_create(ctypes.byref(self.opt), float(budget_bytes), _stream_ptr(stream),
-                                     ctypes.byref(s)), "ppcg_srv_create")
+        _check(lib().ppcg_srv_create(ctypes.byref(self.opt), float(budget_bytes), ctypes.byref(s)),
+               "ppcg_srv_create")
         self.s = s
         self._n = {}
         self._borrowed = {}

@@ -20,7 +20,11 @@ SRC = os.path.join(ROOT, "oracle", "ppcg_oracle.c")
 # (name, original text, mutated text, which occurrence of the original: 0-based)
 MUTANTS = [
     ("spmv reads x at the row index", "double prod = v[k] * x[ci[k]];", "double prod = v[k] * x[i];", 0),
-    ("dot product squares its first operand", "double prod = a[i] * b[i];", "double prod = a[i] * a[i];", 0),
+    ("compensated dot squares its first operand", "double prod = a[i] * b[i];", "double prod = a[i] * a[i];", 0),
+    ("dot product squares its first operand", "double prod = a[i] * b[i];", "double prod = a[i] * a[i];", 1),
+    ("compensated dot drops its correction", "return acc + comp;", "return acc;", 0),
+    ("compensated dot takes the wrong branch's error", "comp = comp + ((acc - t) + prod);",
+     "comp = comp + ((prod - t) + acc);", 0),
     ("Jacobi applies a_ii instead of its inverse", "dinv[i] = 1.0 / d;", "dinv[i] = d;", 0),
     ("stopping test uses the preconditioned residual", "return sqrt(rr) <= tol * bnorm;",
      "return sqrt(uu) <= tol * bnorm;", 0),

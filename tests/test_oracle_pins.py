@@ -199,9 +199,10 @@ def test_jacobi_symmetric_scaling_identity(solver):
 
 # ---------------------------------------------------------------- exact arithmetic pins
 
+@pytest.mark.parametrize("dots", ["seq", "comp"])
 @pytest.mark.parametrize("seed", range(5))
 @pytest.mark.parametrize("solver", [oracle.pcg, oracle.pipecg])
-def test_iterates_match_exact_galerkin(seed, solver):
+def test_iterates_match_exact_galerkin(seed, solver, dots):
     n = 4 + seed % 4
     A = tiny_spd(n, seed)
     D = A.dense()
@@ -209,8 +210,39 @@ def test_iterates_match_exact_galerkin(seed, solver):
     b[0] = 7.0
     for k in range(1, n + 1):
         exact = galerkin_iterate(D, b, k)
-        got = solver(A, b, fixed_iters=k).x
+        got = solver(A, b, fixed_iters=k, dots=dots).x
         assert relerr(got, exact) <= 1e-11, (k, relerr(got, exact))
+
+
+# ---------------------------------------------------------------- dot products
+
+def test_compensated_dot_recovers_cancelled_terms():
+    """1 + 1e100 + 1 - 1e100 = 2: summed left to right the two ones are lost
+    (0); the compensated sum keeps them."""
+    a = np.array([1.0, 1e100, 1.0, -1e100])
+    assert oracle.dot(a, np.ones(4)) == 0.0
+    assert oracle.dot(a, np.ones(4), dots="comp") == 2.0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dot_error_bounds_against_exact_sum(seed):
+    """Products of small integers times powers of two are exact in FP64, so
+    the exact dot product is a rational sum.  Left to right the error is at
+    most (n-1) eps sum|a_i b_i| (the textbook bound); compensated (Neumaier)
+    it is at most eps |sum| + 2 n eps^2 sum|a_i b_i|."""
+    rng = np.random.default_rng(seed)
+    n = 2000
+    a = rng.integers(-2 ** 20, 2 ** 20, size=n) * np.exp2(rng.integers(-40, 40, size=n))
+    b = rng.integers(-2 ** 20, 2 ** 20, size=n) * np.exp2(rng.integers(-40, 40, size=n))
+    exact = sum(Fraction(float(x)) * Fraction(float(y)) for x, y in zip(a, b))
+    mag = float(sum(abs(Fraction(float(x)) * Fraction(float(y))) for x, y in zip(a, b)))
+    eps = np.finfo(float).eps / 2
+    seq = oracle.dot(a, b)
+    comp = oracle.dot(a, b, dots="comp")
+    assert abs(Fraction(seq) - exact) <= (n - 1) * eps * mag
+    assert abs(Fraction(comp) - exact) <= eps * abs(float(exact)) + 2 * n * eps * eps * mag
+    # the bound is far tighter than the sequential one: the sums differ
+    assert abs(Fraction(comp) - exact) <= abs(Fraction(seq) - exact)
 
 
 @pytest.mark.parametrize("seed", range(5))
