@@ -263,6 +263,32 @@ ppcg_status ppcg_solve(ppcg_handle *h, const double *b, const double *x0, double
 ppcg_status ppcg_solve_batch(int32_t count, ppcg_handle *const *hs, const double *const *b,
                              const double *const *x0, double *const *x, ppcg_info *infos);
 
+/* ppcg_solve without a handle and without allocating, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Solves A x = b with Algorithm 2, FP64,
+ * Jacobi, on the caller's CSR arrays in device memory (A->mem must be
+ * PPCG_MEM_DEVICE; the CSR requirements of ppcg_csr apply and are checked on
+ * the device), with the CSR-vector SpMV; b, x0 (NULL = 0; may equal x) and x
+ * are device [n] FP64 arrays, x 16-byte aligned; opt: PPCG_FP64,
+ * PPCG_METHOD_PIPECG, vec_mem PPCG_MEM_DEVICE, spmv_format AUTO or
+ * CSR_VECTOR; tol, max_iter, fixed_iters, max_restarts and stop as for
+ * ppcg_solve.  Work is ordered on hip_stream (NULL = default stream); the call
+ * returns once x and info are final.
+ * Memory: every buffer the kernels need besides the caller's (nine solver
+ * vectors, the inverse diagonal, partial sums, work table, state) lives in
+ * one static device array of about 40 MiB that each device holds from the
+ * library's first use of it until the process ends; the call makes no
+ * allocation (no hipMalloc, hipHostMalloc or graph).  Limit: n <= 524288
+ * rows; larger n is PPCG_ERR_INVALID_ARG.  The array is shared by all calls
+ * on one device and keeps the last call's contents: calls on one device are
+ * serialized by a lock inside the library; concurrent calls on one device
+ * from different processes would race.
+ * Result: bitwise equal to ppcg_solve on a handle created from the same
+ * arrays with spmv_format = PPCG_SPMV_CSR_VECTOR and the same options.
+ * Errors as for ppcg_create and ppcg_solve; argument errors leave x untouched. */
+ppcg_status ppcg_solve_noalloc(const ppcg_csr *A, const ppcg_options *opt, const double *b, const double *x0,
+                               double *x, ppcg_info *info, void *hip_stream);
+
 /* y = A x with the handle's SpMV kernel (Algorithm 2's SpMV step, A in the
  * stored format chosen at creation).  x, y: [n] FP64 in opt.vec_mem memory,
  * caller-owned, must not alias.  Each row is summed in the CSR column order

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libppcg.so")
-SOURCES = ["ppcg_lib.hip", "ppcg_serve.hip", "ppcg_shard.hip", "ppcg_hybrid.hip"]
+SOURCES = ["ppcg_lib.hip", "ppcg_serve.hip", "ppcg_shard.hip", "ppcg_hybrid.hip", "ppcg_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -295,6 +295,14 @@ void launch_x_complete(hipStream_t s, const WorkItem *tab, const int *cnt, const
 void launch_pipecg_init(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
 void launch_pipecg_iter(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int remap);
 void launch_true_resid(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
+// CSR validation (ppcg_create's checks): dinv = 1 / diag, rowlen, and in
+// err[0] the OR of the error flags, err[1] the first offending row (err must
+// hold {0, 0xFFFFFFFF} before the launch); set_csr_error names the flags.
+void launch_validate(hipStream_t s, int n, int64_t nnz, const int *rp, const int *ci, const double *val,
+                     double *dinv, int *rowlen, unsigned *err);
+void set_csr_error(const unsigned (&err)[2]);
+ppcg_status check_options(const ppcg_options *o);
+int csrv_default_lanes(double mean_row_length);
 
 // Iterations a running system still needs: exact in fixed-iteration mode,
 // else predicted from st (the last poll) and the reduction factor per

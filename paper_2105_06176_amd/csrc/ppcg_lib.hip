@@ -779,6 +779,16 @@ static ppcg_status bind_f64(ppcg_handle *h, const double *dinv_orig)
     return PPCG_OK;
 }
 
+// Lanes per row of the CSR-vector format when it is forced (no timing): the
+// power of two in [2, 64] nearest above half the mean row length.
+int csrv_default_lanes(double mean)
+{
+    int l = 2;
+    while (l < 64 && l < mean / 2)
+        l <<= 1;
+    return l;
+}
+
 static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, const double *val, const int *rowlen,
                                  const double *dinv_orig, const std::vector<int> &rowlen_h)
 {
@@ -814,7 +824,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
         return tune_col16(h, -1, &c16);
     }
     if (want == PPCG_SPMV_CSR_VECTOR) {
-        PPCG_TRY(adopt_csrv(h, pow2_near(mean / 2), rp, ci, val));
+        PPCG_TRY(adopt_csrv(h, csrv_default_lanes(mean), rp, ci, val));
         return bind_f64(h, dinv_orig);
     }
     TuneKey key{(int)std::log2((double)h->n), (int)std::lround(mean), (int)std::lround(10 * cv),
@@ -1114,6 +1124,27 @@ void launch_true_resid(hipStream_t s, const WorkItem *tab, const int *cnt, const
 {
     k_spmv<double, MODE_RESID><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
     k_reduce_resid<<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd);
+}
+
+void launch_validate(hipStream_t s, int n, int64_t nnz, const int *rp, const int *ci, const double *val,
+                     double *dinv, int *rowlen, unsigned *err)
+{
+    k_validate<<<blocks_for(n, 256), 256, 0, s>>>(n, nnz, rp, ci, val, dinv, rowlen, err);
+}
+
+void set_csr_error(const unsigned (&err)[2])
+{
+    std::string what;
+    const char *names[] = {"row_ptr[0] != 0", "row_ptr[n] != nnz", "row_ptr not monotone / out of range",
+                           "column index out of range", "columns not strictly ascending",
+                           "missing diagonal", "diagonal not positive", "non-finite value"};
+    for (int b = 0; b < 8; ++b)
+        if (err[0] & (1u << b)) {
+            if (!what.empty())
+                what += ", ";
+            what += names[b];
+        }
+    set_error("bad CSR: %s (first row %u)", what.c_str(), err[1]);
 }
 
 // One iteration of a group: the fused update, then the SpMV with the
@@ -1824,6 +1855,31 @@ ppcg_status run_engine(Engine &E, int graph_iters)
     return PPCG_OK;
 }
 
+ppcg_status check_options(const ppcg_options *o)
+{
+    if (!o || o->struct_size != sizeof(ppcg_options)) {
+        set_error("options NULL or struct_size mismatch");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol) || o->max_iter < 0 || o->fixed_iters < 0 ||
+        o->max_restarts < 0 || o->graph_iters < 0 || o->graph_iters > 4096 || !(o->inner_tol >= 0.0) ||
+        o->inner_tol >= 1.0 || o->max_outer < 0 ||
+        (o->stop != PPCG_STOP_REL_RESID && o->stop != PPCG_STOP_PRECOND_ABS) ||
+        (o->precision != PPCG_FP64 && o->precision != PPCG_MIXED_FP32 && o->precision != PPCG_MIXED_FP32_VALUES) ||
+        (o->vec_mem != PPCG_MEM_DEVICE && o->vec_mem != PPCG_MEM_HOST) ||
+        (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
+         o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
+        (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
+        (o->flags & ~(PPCG_FLAG_BORROW_INPUTS | PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32 |
+                      PPCG_FLAG_SELL_VALUE_TABLE | PPCG_FLAG_SELL_FULL_VALUES)) != 0 ||
+        ((o->flags & PPCG_FLAG_SELL_COL16) && (o->flags & PPCG_FLAG_SELL_COL32)) ||
+        ((o->flags & PPCG_FLAG_SELL_VALUE_TABLE) && (o->flags & PPCG_FLAG_SELL_FULL_VALUES))) {
+        set_error("invalid option value");
+        return PPCG_ERR_INVALID_ARG;
+    }
+    return PPCG_OK;
+}
+
 }  // namespace ppcg
 
 using namespace ppcg;
@@ -1874,30 +1930,6 @@ ppcg_status ppcg_default_options(ppcg_options *opt)
     return PPCG_OK;
 }
 
-static ppcg_status check_options(const ppcg_options *o)
-{
-    if (!o || o->struct_size != sizeof(ppcg_options)) {
-        set_error("options NULL or struct_size mismatch");
-        return PPCG_ERR_INVALID_ARG;
-    }
-    if (!(o->tol >= 0.0) || !std::isfinite(o->tol) || o->max_iter < 0 || o->fixed_iters < 0 ||
-        o->max_restarts < 0 || o->graph_iters < 0 || o->graph_iters > 4096 || !(o->inner_tol >= 0.0) ||
-        o->inner_tol >= 1.0 || o->max_outer < 0 ||
-        (o->stop != PPCG_STOP_REL_RESID && o->stop != PPCG_STOP_PRECOND_ABS) ||
-        (o->precision != PPCG_FP64 && o->precision != PPCG_MIXED_FP32 && o->precision != PPCG_MIXED_FP32_VALUES) ||
-        (o->vec_mem != PPCG_MEM_DEVICE && o->vec_mem != PPCG_MEM_HOST) ||
-        (o->spmv_format != PPCG_SPMV_AUTO && o->spmv_format != PPCG_SPMV_SELL &&
-         o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
-        (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
-        (o->flags & ~(PPCG_FLAG_BORROW_INPUTS | PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32 |
-                      PPCG_FLAG_SELL_VALUE_TABLE | PPCG_FLAG_SELL_FULL_VALUES)) != 0 ||
-        ((o->flags & PPCG_FLAG_SELL_COL16) && (o->flags & PPCG_FLAG_SELL_COL32)) ||
-        ((o->flags & PPCG_FLAG_SELL_VALUE_TABLE) && (o->flags & PPCG_FLAG_SELL_FULL_VALUES))) {
-        set_error("invalid option value");
-        return PPCG_ERR_INVALID_ARG;
-    }
-    return PPCG_OK;
-}
 
 static void destroy_handle(ppcg_handle *h)
 {
@@ -2011,17 +2043,7 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
     CK(hipMemcpyAsync(err_h, err, sizeof err_h, hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     if (err_h[0]) {
-        std::string what;
-        const char *names[] = {"row_ptr[0] != 0", "row_ptr[n] != nnz", "row_ptr not monotone / out of range",
-                               "column index out of range", "columns not strictly ascending",
-                               "missing diagonal", "diagonal not positive", "non-finite value"};
-        for (int b = 0; b < 8; ++b)
-            if (err_h[0] & (1u << b)) {
-                if (!what.empty())
-                    what += ", ";
-                what += names[b];
-            }
-        set_error("bad CSR: %s (first row %u)", what.c_str(), err_h[1]);
+        set_csr_error(err_h);
         return fail(PPCG_ERR_BAD_CSR);
     }
     std::vector<int> rowlen_h(n);

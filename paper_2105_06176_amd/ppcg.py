@@ -99,7 +99,7 @@ EXPORTS = ["ppcg_default_options", "ppcg_create", "ppcg_set_options", "ppcg_solv
            "ppcg_shard_halo_columns", "ppcg_shard_gather", "ppcg_shard_spmv", "ppcg_shard_time",
            "ppcg_shard_destroy", "ppcg_hybrid_create", "ppcg_hybrid_get_info", "ppcg_hybrid_solve",
            "ppcg_hybrid_destroy", "ppcg_srv_create", "ppcg_srv_submit", "ppcg_srv_step",
-           "ppcg_srv_poll", "ppcg_srv_destroy"]
+           "ppcg_srv_poll", "ppcg_srv_destroy", "ppcg_solve_noalloc"]
 
 _lib = None
 
@@ -146,6 +146,8 @@ def lib():
         "ppcg_srv_step": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
         "ppcg_srv_poll": ([P, I64, ctypes.POINTER(I32), P, ctypes.POINTER(Info)], ctypes.c_int),
         "ppcg_srv_destroy": ([P], ctypes.c_int),
+        "ppcg_solve_noalloc": ([ctypes.POINTER(Csr), ctypes.POINTER(Options), P, P, P, ctypes.POINTER(Info), P],
+                               ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -306,6 +308,25 @@ def solve_batch(solvers: Sequence[Solver], bs: Sequence, x0s: Optional[Sequence]
         infos[i].struct_size = ctypes.sizeof(Info)
     _check(lib().ppcg_solve_batch(n, hs, bp, x0p, xp, infos), "ppcg_solve_batch")
     return xs, [infos[i].as_dict() for i in range(n)]
+
+
+def solve_noalloc(A, b, x0=None, out=None, stream=None, **options) -> Tuple[object, dict]:
+    """ppcg_solve_noalloc: A is a tuple of CUDA tensors (row_ptr int32,
+    col_idx int32, values float64); b, x0, out float64 CUDA tensors.  The
+    library allocates nothing; out (allocated here when not given) receives x."""
+    import torch
+
+    keep: list = []
+    c = _csr_struct(A, keep)
+    n = int(c.n)
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+    opt = make_options(**options)
+    info = Info()
+    info.struct_size = ctypes.sizeof(Info)
+    st = lib().ppcg_solve_noalloc(ctypes.byref(c), ctypes.byref(opt), _vec_ptr(b, n, "b"), _vec_ptr(x0, n, "x0"),
+                                  _vec_ptr(x, n, "x"), ctypes.byref(info), _stream_ptr(stream))
+    _check(st, "ppcg_solve_noalloc")
+    return x, info.as_dict()
 
 
 def footprint_bytes(n: int, nnz: int, precision: str = "fp64") -> float:
