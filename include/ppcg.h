@@ -150,6 +150,16 @@ typedef struct {
                                          by ppcg_create only */
 #define PPCG_FLAG_SELL_FULL_VALUES 16u /* SELL: never build the value table (not with
                                           SELL_VALUE_TABLE) */
+#define PPCG_FLAG_ITER_FUSED 32u   /* FP64 PIPECG on SELL storage: one launch per iteration (the
+                                      SpMV, the reduction of the previous dot products with the
+                                      scalar recurrences, and the fused vector updates with n kept
+                                      in registers), without timing it against the two-launch form
+                                      (by default, for systems above 4096 rows, both are timed at
+                                      create time and the faster is kept).  The dot products are
+                                      associated over 2048-row tiles instead of 512-row ones, so
+                                      results differ from the two-launch form by rounding.  Read by
+                                      ppcg_create only */
+#define PPCG_FLAG_ITER_TWO_LAUNCH 64u /* always two launches per iteration (not with ITER_FUSED) */
 
 /* Solver options; initialise with ppcg_default_options(). */
 typedef struct {
@@ -220,6 +230,10 @@ typedef struct {
     int32_t value_bytes;     /* bytes per stored value the iteration's SpMV reads: 1 with the
                                 value table (FP64 PIPECG), 4 with FP32 values, else 8 */
     int32_t distinct_values; /* entries of the value table (0 when there is none) */
+    int32_t iter_launches;   /* launches per iteration of the handle's current method and
+                                precision: 1 for FP64 PIPECG in the single-launch form
+                                (bytes_per_iter then omits n's write and read, 16 bytes per
+                                row), else 2 */
 } ppcg_matrix_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -307,6 +321,9 @@ double ppcg_footprint_bytes(int32_t n, int64_t nnz, ppcg_precision precision);
 /* Measure the two kernels of the iteration (Algorithm 2's fused vector
  * updates + preconditioner + dot products, and its SpMV) over `iters`
  * iterations on the handle's stream, each launch bracketed by HIP events.
+ * A handle in the single-launch form (ppcg_matrix_info.iter_launches = 1 with
+ * PPCG_FP64 PIPECG) times its one kernel: *ms_vma receives its average
+ * duration and *ms_spmv 0.
  * Runs the initialisation first, so the vectors hold a real iterate.
  * With opt.method = PPCG_METHOD_PCG the two streaming kernels of Algorithm 1
  * are timed instead (vector updates + preconditioner + dot-product partials;

@@ -78,6 +78,10 @@ struct PrecData {
 
 enum VecIdx { VX = 0, VR, VU, VW, VM, VN, VZ, VQ, VS, VP, VB };
 
+// How an FP64 PIPECG iteration is launched: the fused update and the SpMV as
+// two launches (ppcg_kernels.hpp), or one launch (ppcg_fused.hpp).
+enum IterForm { FORM_TWO = 0, FORM_FUSED = 1 };
+
 class Engine;
 
 }  // namespace ppcg
@@ -121,6 +125,14 @@ struct ppcg_handle {
     ppcg::SysState *plain_st = nullptr;
     ppcg::WorkItem *plain_tab = nullptr;
     int *plain_cnt = nullptr;
+    // Iteration form of FP64 PIPECG (IterForm): two launches per iteration or
+    // the single-launch form, chosen at create time; the single-launch form's
+    // buffers (state and partial-sum slots, second m buffer).
+    int form = 0;
+    ppcg::SysState *frec = nullptr;
+    double *fpart = nullptr;
+    double *m1 = nullptr;
+    ppcg::DevArena fused_arena;
 };
 
 namespace ppcg {
@@ -157,6 +169,8 @@ struct Job {
     bool small = false;
     // classic PCG (Algorithm 1) instead of PIPECG
     bool pcg = false;
+    // FP64 PIPECG in the single-launch form
+    bool fused = false;
 };
 
 enum MixKind { MIX_NONE = 0, MIX_INNER32 = 1, MIX_VALUES32 = 2 };
@@ -174,6 +188,7 @@ enum JobStage {
 struct Group {
     int prec = PREC_F64;
     bool pcg = false;               // iterates Algorithm 1 (two launches per iteration, PAR alternating)
+    bool fused = false;             // FP64 PIPECG, one launch per iteration (work items are fused tiles)
     int cap_sys = 0;
     SysDesc *desc_d = nullptr;
     SysState *st_d = nullptr;
@@ -243,7 +258,7 @@ class Engine {
             return gp32_;
         if (j.pcg)
             return j.mixed == MIX_VALUES32 ? gpv_ : gp_;
-        return j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : g64_;
+        return j.mixed == MIX_VALUES32 ? gv_ : j.small ? gs_ : j.fused ? gf_ : g64_;
     }
     int pslot(const Job &j) const { return j.mixed == MIX_INNER32 ? j.slot32 : j.mixed == MIX_VALUES32 ? j.slotv : j.slot64; }
     ppcg_status sync_states(Group &g);
@@ -253,11 +268,12 @@ class Engine {
     // the tables and auxiliary work, joined back before the poll), so the
     // groups' launches overlap: the one-workgroup small-system kernel and the
     // graphs of groups holding systems of different precision or method.
-    static constexpr int kGroups = 6;
+    static constexpr int kGroups = 7;
     hipStream_t gstream_[kGroups] = {};
     hipEvent_t ev_fork_ = nullptr;
     hipEvent_t ev_join_[kGroups] = {};
     Group g64_, gv_, gs_;   // FP64 (and the FP64 steps of FP32-vector jobs), FP32 values, small systems
+    Group gf_;              // FP64 PIPECG in the single-launch form
     Group gp_, gpv_, gp32_; // classic PCG: FP64, FP32 values, FP32 vectors
     std::vector<Job> jobs_;
 };
@@ -294,6 +310,15 @@ enum AuxOp { AUX_INIT = 0, AUX_RESID = 1, AUX_MIX_START = 2, AUX_MIX_CORRECT = 3
 void launch_x_complete(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
 void launch_pipecg_init(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
 void launch_pipecg_iter(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int remap);
+// The initialisation of the single-launch form: r0, u0, w0, m0 and the
+// partials of the first dot products (its first launch computes n0 and the
+// first alpha and beta itself).
+void launch_pipecg_init_fused(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
+// K launches of the single-launch form over a table of fused tiles (K even),
+// preceded by k_fused_begin.
+void launch_fused_chunk(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int iters);
+// Allocate the single-launch form's buffers of a handle (once).
+ppcg_status ensure_fused(ppcg_handle *h);
 void launch_true_resid(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
 // CSR validation (ppcg_create's checks): dinv = 1 / diag, rowlen, and in
 // err[0] the OR of the error flags, err[1] the first offending row (err must

@@ -1,0 +1,231 @@
+// ppcg_fused.hpp -- the PIPECG iteration of Algorithm 2 (Tiwari & Vadhiyar,
+// Section III-B) as ONE launch per iteration.
+//
+// The two-launch form (ppcg_kernels.hpp) writes n = A m in the SpMV launch
+// and reads it back in the next fused update.  Here each workgroup owns a
+// tile of kFusedRows rows and, in one launch:
+//
+//   1. reduces, in one fixed order, the per-tile partial sums of (r,u),
+//      (w,u), (u,u), (r,r) that the previous launch wrote, and runs the scalar
+//      recurrences (the stopping test, beta, alpha, breakdown) itself: every
+//      workgroup reads the same partials in the same order and so obtains
+//      bit-identical scalars, with no grid-wide synchronisation;
+//   2. for each of its rows (SELL-64, one lane per row, kFusedRowsPerThread
+//      rows per thread) computes n = A m_i into a register and applies the
+//      fused vector updates of Section V-B with it, forming
+//      m_{i+1} = M^-1 w_{i+1};
+//   3. writes its own partial sums.
+//
+// The kernel boundary is the only synchronisation.  Everything another
+// workgroup of the same launch may still read is double buffered by the
+// launch's parity `par`: m (read by the SpMV gathers of every tile), the
+// partial sums and the scalar state record.  Launch j of a captured chunk
+// has par = j & 1 and chunks have an even number of launches, so a running
+// system always starts a chunk with m in buffer 0 (the handle's m vector)
+// and its latest partials and state in slot 0; k_fused_begin, the first
+// node of every chunk, copies the canonical state record into slot 0 and,
+// right after an initialisation, folds the initialisation's 512-row
+// partials into the fused tiles' partials.
+//
+// Per iteration this saves the n round trip (16 bytes per row) and one
+// launch.  The cost is the partial-sum reduction every workgroup repeats:
+// 32 bytes per tile, read from the L2 (1,024 tiles at 2^21 rows: 32 KB per
+// workgroup).
+//
+// The arithmetic of one row is that of the two-launch form (same SpMV order,
+// same update formulas, x-updates paired in the same way); only the
+// association of the dot products differs (2,048-row tiles), so results are
+// deterministic, identical alone and batched, but not bitwise equal to the
+// two-launch form.
+#pragma once
+
+#include "ppcg_kernels.hpp"
+
+namespace ppcg {
+
+// Waves per SIMD the kernel is compiled for: 4 lets it keep its 74 VGPRs
+// (6 waves per SIMD in practice); forcing 8 spills and was 14 % slower.
+#ifndef PPCG_FUSED_WAVES
+#define PPCG_FUSED_WAVES 4
+#endif
+// XCD-aware tile order (each XCD a contiguous range of tiles): 1.7 % faster
+// on the 128^3 7-point system.
+#ifndef PPCG_FUSED_REMAP
+#define PPCG_FUSED_REMAP 1
+#endif
+
+struct FusedScalars {
+    double alpha, beta, alpha_x;
+    int go, x_pending;
+};
+
+// SpMV of one SELL chunk row (n = A m) with the handle's storage variant.
+__device__ __forceinline__ double fused_row(const SysDesc &d, const double *min, int chunk, int lane,
+                                            const double *tab)
+{
+    const double *xin[1] = {min};
+    double y[1];
+    const double *val = (const double *)d.val;
+    if (tab) {
+        if (d.col16)
+#if PPCG_SELL_PIPE
+            sell_row16_pipe<double, double, 1, true>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab);
+#else
+            sell_row16<double, double, 1, true>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab);
+#endif
+        else
+            sell_row<double, double, 1, true>(d.cptr, d.col, val, xin, chunk, lane, y, d.vidx, tab);
+    } else {
+        if (d.col16)
+#if PPCG_SELL_PIPE
+            sell_row16_pipe<double, double, 1>(d.cptr, d.col16, val, xin, chunk, lane, y);
+#else
+            sell_row16<double, double, 1>(d.cptr, d.col16, val, xin, chunk, lane, y);
+#endif
+        else
+            sell_row<double, double, 1>(d.cptr, d.col, val, xin, chunk, lane, y);
+    }
+    return y[0];
+}
+
+__global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const WorkItem *__restrict__ table,
+                                                                           const int *__restrict__ count,
+                                                                           const SysDesc *__restrict__ descs,
+                                                                           int remap, int par)
+{
+    constexpr int R = kFusedRowsPerThread;
+    __shared__ double lds[kFusedThreads / 64 * kNumPartials];
+    __shared__ double vtab[kMaxValueTable];
+    __shared__ FusedScalars sc;
+    const int live = *count;
+    if ((int)blockIdx.x >= live)
+        return;
+    const int pos = remap ? xcd_remap(blockIdx.x, live) : (int)blockIdx.x;
+    const WorkItem wi = table[pos];
+    const SysDesc &d = descs[wi.slot];
+    const SysState *rin = d.frec + par;
+    if (rin->done)
+        return;
+    const int n = d.n;
+    const double *min = (const double *)(par ? d.m1 : d.m);
+    double *mout = (double *)(par ? d.m : d.m1);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row0 = wi.tile * kFusedRows;
+    const double *tab = nullptr;
+    if (d.vidx) {
+        for (int t = tid; t < d.nvtab; t += kFusedThreads)
+            vtab[t] = d.vtab[t];
+        __syncthreads();
+        tab = vtab;
+    }
+    // 1. The previous launch's partials, all tiles of the system, in tile
+    // order per thread, then the fixed workgroup tree; the scalar recurrences.
+    {
+        const PPCG_AS1 dvec2 *P = (const PPCG_AS1 dvec2 *)as_global(d.fpart + (size_t)par * d.nftiles * 4);
+        double v[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = tid; t < d.nftiles; t += kFusedThreads) {
+            const dvec2 a = P[2 * t], b = P[2 * t + 1];
+            v[0] = v[0] + a[0];
+            v[1] = v[1] + a[1];
+            v[2] = v[2] + b[0];
+            v[3] = v[3] + b[1];
+        }
+        block_sum<kFusedThreads, kNumPartials>(v, lds);
+        if (tid == 0) {
+            SysState loc = *rin;
+            // the update of the previous launch deferred or applied an x-update
+            if (!loc.phase) {
+                loc.alpha_x = loc.alpha;
+                loc.x_pending ^= 1;
+            }
+            scalar_update<kNumPartials>(d, &loc, v);
+            sc.alpha = loc.alpha;
+            sc.beta = loc.beta;
+            sc.alpha_x = loc.alpha_x;
+            sc.x_pending = loc.x_pending;
+            sc.go = !loc.done;
+            if (wi.tile == 0) {
+                d.frec[par ^ 1] = loc;
+                *d.st = loc;
+            }
+        }
+        __syncthreads();
+    }
+    if (!sc.go)
+        return;
+    // 2. Per row of this thread (row0 + k * kFusedThreads + tid): n = A m_i
+    // into a register, then the fused update with it.
+    const double sa = sc.alpha, sb = sc.beta, ax = sc.alpha_x;
+    const bool xp = sc.x_pending != 0;
+    PPCG_AS1 double *__restrict__ X = as_global((double *)d.x);
+    PPCG_AS1 double *__restrict__ Rv = as_global((double *)d.r);
+    PPCG_AS1 double *__restrict__ W = as_global((double *)d.w);
+    PPCG_AS1 double *__restrict__ M = as_global(mout);
+    PPCG_AS1 double *__restrict__ Z = as_global((double *)d.z);
+    PPCG_AS1 double *__restrict__ S = as_global((double *)d.s);
+    PPCG_AS1 double *__restrict__ P = as_global((double *)d.p);
+    const PPCG_AS1 double *__restrict__ DI = as_global((const double *)d.dinv);
+    double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int k = 0; k < R; ++k) {
+        const int chunk = (row0 + k * kFusedThreads) / kSellC + wave;
+        if (chunk * kSellC >= n)
+            break;  // uniform per wavefront: no later chunk of this thread exists either
+        const int i = chunk * kSellC + lane;
+        const double nv = fused_row(d, min, chunk, lane, tab);
+        if (i < n) {
+            double z = Z[i], w = W[i], s = S[i], p = P[i], r = Rv[i], u, mo;
+            const double di = DI[d.dinv_const ? 0 : i];
+            const double xo = xp ? X[i] : 0.0;
+            const double pold = p;
+            vma_elem<double, kNumPartials>(sa, sb, nv, z, w, s, p, r, di, u, mo, acc);
+            Z[i] = z;
+            S[i] = s;
+            P[i] = p;
+            Rv[i] = r;
+            W[i] = w;
+            M[i] = mo;
+            if (xp) {
+                const double x1 = xo + ax * pold;
+                X[i] = x1 + sa * p;
+            }
+        }
+    }
+    block_sum<kFusedThreads, kNumPartials>(acc, lds);
+    if (tid == 0) {
+        PPCG_AS1 dvec2 *out = (PPCG_AS1 dvec2 *)as_global(d.fpart + ((size_t)(par ^ 1) * d.nftiles + wi.tile) * 4);
+        out[0] = dvec2{acc[0], acc[1]};
+        out[1] = dvec2{acc[2], acc[3]};
+    }
+}
+
+// First node of every chunk of fused launches (one workgroup per fused
+// tile): the canonical state record into slot 0, and after an
+// initialisation (phase 1) the initialisation's partials, one record per
+// 512-row tile, summed in tile order into one record per fused tile (slot 0).
+__global__ void k_fused_begin(const WorkItem *__restrict__ table, const int *__restrict__ count,
+                              const SysDesc *__restrict__ descs)
+{
+    const int pos = blockIdx.x;
+    if (pos >= *count)
+        return;
+    const WorkItem wi = table[pos];
+    const SysDesc &d = descs[wi.slot];
+    const SysState *st = d.st;
+    if (st->done)
+        return;
+    const int k = threadIdx.x;
+    if (st->phase && k < kNumPartials) {
+        constexpr int per = kFusedRows / kTileRows;
+        const int t0 = wi.tile * per, t1 = min(t0 + per, d.ntiles);
+        const double *src = d.part + (size_t)d.ntiles * kPartStride;  // slot 1
+        double a = src[(size_t)t0 * kPartStride + k];
+        for (int t = t0 + 1; t < t1; ++t)
+            a = a + src[(size_t)t * kPartStride + k];
+        d.fpart[(size_t)wi.tile * 4 + k] = a;
+    }
+    if (wi.tile == 0 && k == 0)
+        d.frec[0] = *st;
+}
+
+}  // namespace ppcg

@@ -23,6 +23,13 @@ constexpr int kSellChunksPerTile = kTileRows / kSellC;
 constexpr int kSortWindow = 1024;  // SELL sigma when sorting is used
 constexpr int kNumPartials = 4;    // (r,u), (w,u), (u,u), (r,r)
 constexpr int kPartStride = 8;     // doubles per tile partial record (replacement uses 6)
+// The single-launch iteration (ppcg_fused.hpp): tiles of kFusedRows rows,
+// kFusedRowsPerThread rows per thread.
+constexpr int kFusedThreads = 512;
+constexpr int kFusedRowsPerThread = 4;
+constexpr int kFusedRows = kFusedThreads * kFusedRowsPerThread;
+static_assert(kFusedRows % kTileRows == 0, "fused tiles are whole 512-row tiles");
+static_assert(kFusedThreads % kSellC == 0, "each wavefront of a fused tile reads whole SELL chunks");
 
 // Tile-to-workgroup mapping.  The fused update is a pure stream and runs
 // slightly faster with each XCD owning a contiguous range of tiles; the SpMV
@@ -139,6 +146,11 @@ struct SysDesc {
     const void *b;        // right-hand side (internal copy)
     double *part;         // partial sums: 2 slots x ntiles x kPartStride
     SysState *st;
+    // single-launch iteration (ppcg_fused.hpp); unused by the two-launch form
+    int nftiles;          // tiles of kFusedRows rows
+    SysState *frec;       // scalar state, 2 slots (launch parity)
+    double *fpart;        // partial sums, 2 slots x nftiles x 4
+    void *m1;             // second m buffer (m is read by every tile's gathers while being rewritten)
 };
 
 struct WorkItem {

@@ -484,6 +484,17 @@ __device__ __forceinline__ VT sell_value(const PPCG_AS1 VT *v, const PPCG_AS1 un
         return stream_load(v + o);
 }
 
+// First stored slot and padded length of a SELL chunk.  A chunk is one
+// wavefront's rows, so `chunk` is the same in every lane: taking it from the
+// first lane puts both values in scalar registers and makes every guard on
+// the chunk length a uniform branch.
+__device__ __forceinline__ void sell_extent(const int64_t *__restrict__ cptr, int chunk, int64_t &base, int &len)
+{
+    const int c = __builtin_amdgcn_readfirstlane(chunk);
+    base = as_global(cptr)[c];
+    len = (int)((as_global(cptr)[c + 1] - base) / kSellC);
+}
+
 // SELL-C-sigma, C = 64, one lane per row: entry k of the row (chunk c, lane
 // l) is at cptr[c] + k * 64 + l.  NX input vectors share one pass over the
 // matrix (NX = 2 for the replacement steps).  Entries are handled in
@@ -499,8 +510,9 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
                                          const double *tab = nullptr)
 {
     constexpr int B = PPCG_SELL_BATCH;
-    const int64_t base = as_global(cptr)[chunk];
-    const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
+    int64_t base;
+    int len;
+    sell_extent(cptr, chunk, base, len);
     const PPCG_AS1 int *c = as_global(col + base + lane);
     const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
     const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
@@ -574,8 +586,9 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
                                            const double *tab = nullptr)
 {
     constexpr int B = PPCG_SELL_BATCH;
-    const int64_t base = as_global(cptr)[chunk];
-    const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
+    int64_t base;
+    int len;
+    sell_extent(cptr, chunk, base, len);
     const int row = chunk * kSellC + lane;
     const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
     const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
@@ -621,8 +634,9 @@ __device__ __forceinline__ void sell_row16_pipe(const int64_t *__restrict__ cptr
                                                 const double *tab = nullptr)
 {
     constexpr int B = PPCG_SELL_PIPE_BATCH;  // two batches in flight: smaller than the plain batch
-    const int64_t base = as_global(cptr)[chunk];
-    const int len = (int)((as_global(cptr)[chunk + 1] - base) / kSellC);
+    int64_t base;
+    int len;
+    sell_extent(cptr, chunk, base, len);
     const int row = chunk * kSellC + lane;
     const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
     const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;

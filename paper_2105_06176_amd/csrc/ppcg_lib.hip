@@ -31,6 +31,7 @@
 #include "ppcg_pcg.hpp"
 #include "ppcg_small.hpp"
 #include "ppcg_setup.hpp"
+#include "ppcg_fused.hpp"
 
 namespace ppcg {
 
@@ -162,6 +163,12 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     // classic-PCG SpMV with FP32 values and FP64 vectors)
     const double ie = (h->col16 && !(pcg && prec == PREC_V32)) ? 2.0 : 4.0;
     bm.spmv = (me + ie) * (double)h->nnz + ptr + (pcg ? 4.0 : 2.0) * ve * n;
+    // the single-launch form keeps n in registers: neither written by the
+    // SpMV nor read by the update
+    if (h->form == FORM_FUSED && prec == PREC_F64 && !pcg) {
+        bm.vma -= ve * n;
+        bm.spmv -= ve * n;
+    }
     return bm;
 }
 
@@ -328,6 +335,23 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->b = pd.vec[VB];
     d->part = prec == PREC_F64 ? h->part : h->part32;
     d->st = st;
+    d->nftiles = (h->n + kFusedRows - 1) / kFusedRows;
+    d->frec = h->frec;
+    d->fpart = h->fpart;
+    d->m1 = h->m1;
+    return PPCG_OK;
+}
+
+ppcg_status ensure_fused(ppcg_handle *h)
+{
+    if (h->frec)
+        return PPCG_OK;
+    const size_t nft = (size_t)(h->n + kFusedRows - 1) / kFusedRows;
+    const size_t pb = 2 * nft * 4 * sizeof(double), vb = (size_t)h->n * sizeof(double);
+    PPCG_TRY(h->fused_arena.alloc(2 * sizeof(SysState) + pb + vb + 3 * 256));
+    h->frec = (SysState *)h->fused_arena.take(2 * sizeof(SysState));
+    h->fpart = (double *)h->fused_arena.take(pb);
+    h->m1 = (double *)h->fused_arena.take(vb);
     return PPCG_OK;
 }
 
@@ -339,13 +363,13 @@ static ppcg_status plain_setup(ppcg_handle *h, double tol, int fixed, int maxit)
         PPCG_HIP(hipMalloc(&h->plain_desc, sizeof(SysDesc)));
         PPCG_HIP(hipMalloc(&h->plain_st, sizeof(SysState)));
         PPCG_HIP(hipMalloc(&h->plain_tab, sizeof(WorkItem) * h->ntiles));
-        PPCG_HIP(hipMalloc(&h->plain_cnt, sizeof(int)));
+        PPCG_HIP(hipMalloc(&h->plain_cnt, sizeof(int) * 2));  // [1]: fused tiles
         std::vector<WorkItem> th(h->ntiles);
         for (int t = 0; t < h->ntiles; ++t)
             th[t] = {0, t};
-        const int count = h->ntiles;
-        PPCG_HIP(hipMemcpyAsync(h->plain_tab, th.data(), sizeof(WorkItem) * count, hipMemcpyHostToDevice, s));
-        PPCG_HIP(hipMemcpyAsync(h->plain_cnt, &count, sizeof(int), hipMemcpyHostToDevice, s));
+        const int count[2] = {h->ntiles, (h->n + kFusedRows - 1) / kFusedRows};
+        PPCG_HIP(hipMemcpyAsync(h->plain_tab, th.data(), sizeof(WorkItem) * count[0], hipMemcpyHostToDevice, s));
+        PPCG_HIP(hipMemcpyAsync(h->plain_cnt, count, sizeof count, hipMemcpyHostToDevice, s));
         PPCG_HIP(hipStreamSynchronize(s));  // host sources are about to go out of scope
     }
     SysDesc dh;
@@ -748,6 +772,143 @@ static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const doubl
     return PPCG_OK;
 }
 
+// ---------------------------------------------------------------- iteration form
+// Time kIters iterations of each form of FP64 PIPECG on the handle's stored
+// matrix, after their initialisations, from b = 1 and x0 = 0 in fixed-
+// iteration mode.  *ms_two and *ms_fused: milliseconds per iteration (launch
+// gaps included, kernels launched directly); *valid is false when a
+// sequence stopped early (the timing would not be an iteration's).
+static ppcg_status time_forms(ppcg_handle *h, double *ms_two, double *ms_fused, bool *valid)
+{
+    constexpr int kIters = 16;
+    hipStream_t s = h->stream;
+    PPCG_TRY(plain_setup(h, 0.0, INT_MAX, INT_MAX));
+    const int n = h->n, grid = h->ntiles, fgrid = (n + kFusedRows - 1) / kFusedRows;
+    const WorkItem *tab = h->plain_tab;
+    const int *cnt = h->plain_cnt;
+    const SysDesc *dd = h->plain_desc;
+    hipEvent_t ev[4] = {};
+    auto clean = [&]() {
+        (void)hipStreamSynchronize(s);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto &e : ev)
+        PPCG_HIP_CLEAN(hipEventCreate(&e), clean());
+    *valid = true;
+    float best[2] = {1e30f, 1e30f};
+    for (int round = 0; round < 2; ++round) {
+        for (int form = 0; form < 2; ++form) {
+            k_fill<double><<<blocks_for(n, 256), 256, 0, s>>>((size_t)n, (double *)h->f64.vec[VB], 1.0);
+            k_fill<double><<<blocks_for(n, 256), 256, 0, s>>>((size_t)n, (double *)h->f64.vec[VX], 0.0);
+            if (form == 0) {
+                launch_pipecg_init(s, tab, cnt, dd, grid);
+                PPCG_HIP_CLEAN(hipEventRecord(ev[0], s), clean());
+                for (int i = 0; i < kIters; ++i)
+                    launch_pipecg_iter(s, tab, cnt, dd, grid, PPCG_XCD_REMAP);
+                PPCG_HIP_CLEAN(hipEventRecord(ev[1], s), clean());
+            } else {
+                launch_pipecg_init_fused(s, tab, cnt, dd, grid);
+                k_fused_begin<<<fgrid, 64, 0, s>>>(tab, cnt + 1, dd);
+                // the first launch ends the initialisation (no update)
+                k_fused<<<fgrid, kFusedThreads, 0, s>>>(tab, cnt + 1, dd, PPCG_FUSED_REMAP, 0);
+                PPCG_HIP_CLEAN(hipEventRecord(ev[2], s), clean());
+                for (int i = 1; i <= kIters; ++i)
+                    k_fused<<<fgrid, kFusedThreads, 0, s>>>(tab, cnt + 1, dd, PPCG_FUSED_REMAP, i & 1);
+                PPCG_HIP_CLEAN(hipEventRecord(ev[3], s), clean());
+            }
+            PPCG_HIP_CLEAN(hipGetLastError(), clean());
+            SysState st;
+            PPCG_HIP_CLEAN(hipMemcpyAsync(&st, h->plain_st, sizeof st, hipMemcpyDeviceToHost, s), clean());
+            PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());
+            if (st.done)
+                *valid = false;
+            float ms = 0.f;
+            PPCG_HIP_CLEAN(hipEventElapsedTime(&ms, ev[2 * form], ev[2 * form + 1]), clean());
+            best[form] = std::min(best[form], ms);
+        }
+    }
+    *ms_two = best[0] / kIters;
+    *ms_fused = best[1] / kIters;
+    clean();
+    return PPCG_OK;
+}
+
+// Decisions per (rows on a log scale, stored entries per row, 16-bit columns,
+// value table, sorted rows): 1 = single-launch form.  One thread times a
+// signature at a time, so concurrent creates get the same form (and the same
+// arithmetic).
+static std::map<std::tuple<int, int, int, int, int>, int> g_form_cache;
+static std::set<std::tuple<int, int, int, int, int>> g_form_tuning;
+
+static void drop_fused(ppcg_handle *h)
+{
+    h->fused_arena.release();
+    h->frec = nullptr;
+    h->fpart = nullptr;
+    h->m1 = nullptr;
+}
+
+// Choose the iteration form of FP64 PIPECG for the stored matrix (SELL only):
+// forced by PPCG_FLAG_ITER_FUSED / PPCG_FLAG_ITER_TWO_LAUNCH, else the two
+// launches for systems the one-workgroup kernel takes, else the faster of
+// the two forms timed on this matrix.
+static ppcg_status tune_form(ppcg_handle *h)
+{
+    h->form = FORM_TWO;
+    const uint32_t f = h->opt.flags;
+    if ((f & PPCG_FLAG_ITER_TWO_LAUNCH) || h->fmt != FMT_SELL)
+        return PPCG_OK;
+    if (f & PPCG_FLAG_ITER_FUSED) {
+        PPCG_TRY(ensure_fused(h));
+        h->form = FORM_FUSED;
+        return PPCG_OK;
+    }
+    if (h->n <= PPCG_SMALL_MAX_ROWS)
+        return PPCG_OK;
+    const auto key = std::make_tuple((int)std::log2((double)h->n),
+                                     (int)std::lround((double)h->nnz_stored / h->n), h->col16 ? 1 : 0,
+                                     h->vidx ? 1 : 0, h->sigma > 1 ? 1 : 0);
+    {
+        std::unique_lock<std::mutex> lk(g_tune_mu);
+        g_tune_cv.wait(lk, [&] { return !g_form_tuning.count(key); });
+        auto it = g_form_cache.find(key);
+        if (it != g_form_cache.end()) {
+            lk.unlock();
+            if (it->second == FORM_FUSED) {
+                PPCG_TRY(ensure_fused(h));
+                h->form = FORM_FUSED;
+            }
+            return PPCG_OK;
+        }
+        g_form_tuning.insert(key);
+    }
+    struct Release {
+        std::tuple<int, int, int, int, int> k;
+        ~Release()
+        {
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_form_tuning.erase(k);
+            }
+            g_tune_cv.notify_all();
+        }
+    } release{key};
+    PPCG_TRY(ensure_fused(h));
+    double t2 = 0, tf = 0;
+    bool valid = false;
+    PPCG_TRY(time_forms(h, &t2, &tf, &valid));
+    const int form = valid && tf < t2 ? FORM_FUSED : FORM_TWO;
+    if (form == FORM_FUSED)
+        h->form = FORM_FUSED;
+    else
+        drop_fused(h);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (valid)
+        g_form_cache[key] = form;
+    return PPCG_OK;
+}
+
 static ppcg_status adopt_csrv(ppcg_handle *h, int lanes, const int *rp, const int *ci, const double *val)
 {
     free_matrix(h);
@@ -987,7 +1148,7 @@ Engine::~Engine()
         if (ev_join_[k]) (void)hipEventDestroy(ev_join_[k]);
     }
     if (ev_fork_) (void)hipEventDestroy(ev_fork_);
-    for (Group *g : {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_}) {
+    for (Group *g : {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_, &gf_}) {
         drop_graphs(*g);
         if (g->desc_d) (void)dev_free(g->desc_d);
         if (g->st_d) (void)dev_free(g->st_d);
@@ -1040,7 +1201,9 @@ ppcg_status Engine::init(int cap_sys)
     PPCG_TRY(ensure_group(gp_, PREC_F64, cap_sys));
     PPCG_TRY(ensure_group(gpv_, PREC_V32, cap_sys));
     PPCG_TRY(ensure_group(gp32_, PREC_F32, cap_sys));
+    PPCG_TRY(ensure_group(gf_, PREC_F64, cap_sys));
     gp_.pcg = gpv_.pcg = gp32_.pcg = true;
+    gf_.fused = true;
     return PPCG_OK;
 }
 
@@ -1118,6 +1281,20 @@ void launch_pipecg_iter(hipStream_t s, const WorkItem *tab, const int *cnt, cons
 {
     k_vma<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd, remap);
     k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
+}
+
+void launch_pipecg_init_fused(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid)
+{
+    const int rs = PPCG_XCD_REMAP_SPMV;
+    k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+    k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+}
+
+void launch_fused_chunk(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int iters)
+{
+    k_fused_begin<<<grid, 64, 0, s>>>(tab, cnt, dd);
+    for (int i = 0; i < iters; ++i)
+        k_fused<<<grid, kFusedThreads, 0, s>>>(tab, cnt, dd, PPCG_FUSED_REMAP, i & 1);
 }
 
 void launch_true_resid(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid)
@@ -1232,8 +1409,11 @@ ppcg_status Engine::ensure_graph(Group &g, int iters, hipGraphExec_t *exec)
     std::unique_lock<std::shared_mutex> no_release(release_mu());
     Group::CapturedGraph cg;
     PPCG_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < iters; ++i)
-        launch_iter_pair(stream_, g, grid, remap);
+    if (g.fused)
+        launch_fused_chunk(stream_, g.table_d, g.count_d, g.desc_d, grid, iters);
+    else
+        for (int i = 0; i < iters; ++i)
+            launch_iter_pair(stream_, g, grid, remap);
     hipError_t e = hipStreamEndCapture(stream_, &cg.graph);
     if (e != hipSuccess) {
         set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
@@ -1291,6 +1471,11 @@ int Engine::chunk_iters(const Group &g, int max_iters)
         want = std::max(want, iters_needed(g.desc_h[pslot(j)], g.st_h[pslot(j)], j.rate, j.last_norm >= 0,
                                            max_iters, g.pcg));
     }
+    // The single-launch form: its first launch after an initialisation does
+    // no update, so k updates take k + 1 launches, and chunks hold an even
+    // number of launches (the parity of m, partials and state returns to 0).
+    if (g.fused)
+        want = std::max(2, std::min(want + 1, std::max(max_iters, 2)));
     int k = 1;
     while (k * 2 <= want)
         k *= 2;
@@ -1349,6 +1534,8 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
             k_pcg_dots<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
         }
         k_pcg_update<PCG_REPL><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
+    } else if (what == AUX_INIT && g.fused) {
+        launch_pipecg_init_fused(s, tab, cnt, dd, grid);
     } else if (what == AUX_INIT) {
         launch_pipecg_init(s, tab, cnt, dd, grid);
     } else if (what == AUX_RESID) {
@@ -1428,6 +1615,22 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
         gv_.desc_h[j.slotv].repl_factor = o.inner_tol > 0 ? o.inner_tol : 1e-3;
         PPCG_TRY(upload_desc(gv_, j.slotv));
         PPCG_HIP(hipMemsetAsync(gv_.st_d + j.slotv, 0, sizeof(SysState), stream_));
+        j.stage = JS_NEED_INIT;
+    } else if (mixed == MIX_NONE && h->form == FORM_FUSED && h->frec && h->fmt == FMT_SELL) {
+        j.fused = true;
+        j.slot64 = alloc_slot(gf_);
+        if (j.slot64 < 0) {
+            set_error("engine has no free slot");
+            return PPCG_ERR_INVALID_ARG;
+        }
+        ppcg_status rc = fill_desc(h, PREC_F64, gf_.st_d + j.slot64, &gf_.desc_h[j.slot64], tol, o.fixed_iters,
+                                   o.max_iter, stop);
+        if (rc != PPCG_OK) {
+            gf_.slot_used[j.slot64] = 0;
+            return rc;
+        }
+        PPCG_TRY(upload_desc(gf_, j.slot64));
+        PPCG_HIP(hipMemsetAsync(gf_.st_d + j.slot64, 0, sizeof(SysState), stream_));
         j.stage = JS_NEED_INIT;
     } else if (mixed == MIX_NONE && h->fmt == FMT_SELL && h->n <= PPCG_SMALL_MAX_ROWS) {
         j.small = true;
@@ -1518,7 +1721,7 @@ void Engine::retire(int id)
 {
     Job &j = jobs_[id];
     if (j.slot64 >= 0)
-        (j.pcg && j.mixed != MIX_INNER32 ? gp_ : j.small ? gs_ : g64_).slot_used[j.slot64] = 0;
+        (j.pcg && j.mixed != MIX_INNER32 ? gp_ : j.small ? gs_ : j.fused ? gf_ : g64_).slot_used[j.slot64] = 0;
     if (j.slot32 >= 0)
         gp32_.slot_used[j.slot32] = 0;
     if (j.slotv >= 0)
@@ -1549,7 +1752,7 @@ ppcg_status Engine::step(int graph_iters)
 {
     // 1. Jobs that need a true residual: stopped FP64 / FP32-values jobs, and
     //    FP32-vector jobs at a pause of their sequence (after adding the correction).
-    Group *const groups[] = {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_};
+    Group *const groups[] = {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_, &gf_};
     std::map<Group *, std::vector<int>> resid;  // slots per group
     std::vector<int> correct64;                 // FP64 slots of FP32-vector jobs
     for (Job &j : jobs_) {
@@ -1675,7 +1878,7 @@ ppcg_status Engine::step(int graph_iters)
             if (j.finished || j.stage != JS_ITER || &pgroup(j) != g)
                 continue;
             const int sl = pslot(j);
-            const int nt = g == &gs_ ? 1 : g->desc_h[sl].ntiles;
+            const int nt = g == &gs_ ? 1 : g->fused ? g->desc_h[sl].nftiles : g->desc_h[sl].ntiles;
             for (int t = 0; t < nt; ++t)
                 items.push_back({sl, t});
         }
@@ -1871,7 +2074,9 @@ ppcg_status check_options(const ppcg_options *o)
          o->spmv_format != PPCG_SPMV_CSR_VECTOR) ||
         (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
         (o->flags & ~(PPCG_FLAG_BORROW_INPUTS | PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32 |
-                      PPCG_FLAG_SELL_VALUE_TABLE | PPCG_FLAG_SELL_FULL_VALUES)) != 0 ||
+                      PPCG_FLAG_SELL_VALUE_TABLE | PPCG_FLAG_SELL_FULL_VALUES | PPCG_FLAG_ITER_FUSED |
+                      PPCG_FLAG_ITER_TWO_LAUNCH)) != 0 ||
+        ((o->flags & PPCG_FLAG_ITER_FUSED) && (o->flags & PPCG_FLAG_ITER_TWO_LAUNCH)) ||
         ((o->flags & PPCG_FLAG_SELL_COL16) && (o->flags & PPCG_FLAG_SELL_COL32)) ||
         ((o->flags & PPCG_FLAG_SELL_VALUE_TABLE) && (o->flags & PPCG_FLAG_SELL_FULL_VALUES))) {
         set_error("invalid option value");
@@ -1945,6 +2150,7 @@ static void destroy_handle(ppcg_handle *h)
         (void)dev_free(h->dinv64);
     h->f64.arena.release();
     h->f32.arena.release();
+    h->fused_arena.release();
     if (h->ev_user)
         (void)hipEventDestroy(h->ev_user);
     if (h->stream)
@@ -2066,6 +2272,7 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
     CKS(alloc_f64_vectors(h));
     CKS(choose_format(h, rp, ci, val, rowlen, dinv_orig, rowlen_h));
     CKS(tune_vtab(h, A->mem == PPCG_MEM_HOST ? A->values : nullptr, val));
+    CKS(tune_form(h));
     if (opt->precision == PPCG_MIXED_FP32)
         CKS(ensure_f32(h));
     if (opt->precision == PPCG_MIXED_FP32_VALUES)
@@ -2279,6 +2486,7 @@ ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
                       : (h->vidx && !pcg)                                                              ? 1
                                                                                                        : 8;
     mi->distinct_values = h->nvtab;
+    mi->iter_launches = (h->form == FORM_FUSED && !pcg && h->opt.precision == PPCG_FP64) ? 1 : 2;
     return PPCG_OK;
 }
 
@@ -2324,6 +2532,31 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     const int *cnt = h->plain_cnt;
     const SysDesc *dd = h->plain_desc;
     const bool pcg = h->opt.method == PPCG_METHOD_PCG;
+    if (!pcg && h->form == FORM_FUSED) {
+        // the single-launch form: its one kernel, after the initialisation
+        // and the launch that ends it
+        const int fgrid = (h->n + kFusedRows - 1) / kFusedRows;
+        launch_pipecg_init_fused(s, tab, cnt, dd, grid);
+        k_fused_begin<<<fgrid, 64, 0, s>>>(tab, cnt + 1, dd);
+        k_fused<<<fgrid, kFusedThreads, 0, s>>>(tab, cnt + 1, dd, PPCG_FUSED_REMAP, 0);
+        for (auto &e : ev)
+            PPCG_HIP_CLEAN(hipEventCreate(&e), clean());
+        for (int i = 1; i <= iters; ++i)
+            hipExtLaunchKernelGGL(k_fused, dim3(fgrid), dim3(kFusedThreads), 0, s, ev[4 * (i - 1)],
+                                  ev[4 * (i - 1) + 1], 0, tab, cnt + 1, dd, (int)PPCG_FUSED_REMAP, i & 1);
+        PPCG_HIP_CLEAN(hipGetLastError(), clean());
+        PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());
+        double tf = 0;
+        for (int i = 0; i < iters; ++i) {
+            float a = 0;
+            PPCG_HIP_CLEAN(hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]), clean());
+            tf += a;
+        }
+        *ms_vma = tf / iters;
+        *ms_spmv = 0.0;
+        clean();
+        return PPCG_OK;
+    }
     k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
     if (pcg) {
         k_pcg_dots<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);

@@ -24,6 +24,7 @@ MEM_DEVICE, MEM_HOST = 0, 1
 METHOD_PIPECG, METHOD_PCG = 0, 1
 FLAG_BORROW_INPUTS, FLAG_SELL_COL16, FLAG_SELL_COL32 = 1, 2, 4
 FLAG_SELL_VALUE_TABLE, FLAG_SELL_FULL_VALUES = 8, 16
+FLAG_ITER_FUSED, FLAG_ITER_TWO_LAUNCH = 32, 64
 SPMV_AUTO, SPMV_SELL, SPMV_CSR_VECTOR = 0, 1, 2
 
 _STOP = {"rel": STOP_REL_RESID, "abs": STOP_PRECOND_ABS}
@@ -64,7 +65,8 @@ class MatrixInfo(ctypes.Structure):
                 ("bytes_per_iter", ctypes.c_double), ("bytes_vma", ctypes.c_double),
                 ("bytes_spmv", ctypes.c_double), ("device_bytes", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("col_index_bytes", ctypes.c_int32), ("diag_const", ctypes.c_int32),
-                ("value_bytes", ctypes.c_int32), ("distinct_values", ctypes.c_int32)]
+                ("value_bytes", ctypes.c_int32), ("distinct_values", ctypes.c_int32),
+                ("iter_launches", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}

@@ -256,8 +256,12 @@ def c2():
     return A, b
 
 
-# the storage bench.py pins for this matrix, and the autotuner's own choice
-C2_STORAGE = {"bench": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES),
+# the storage and iteration form bench.py pins for this matrix, the same
+# storage with two launches per iteration, and the autotuner's own choice
+C2_STORAGE = {"bench": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES |
+                            ppcg.FLAG_ITER_FUSED),
+              "two_launch": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES |
+                                 ppcg.FLAG_ITER_TWO_LAUNCH),
               "auto": {}}
 
 
