@@ -40,7 +40,7 @@ def kernel_source_hash():
     """Hash of the kernel sources with comments and blank space removed, so a
     comment edit does not invalidate the stored counter figures."""
     h = hashlib.sha256()
-    for f in ("ppcg_kernels.hpp", "ppcg_internal.hpp"):
+    for f in ("ppcg_kernels.hpp", "ppcg_internal.hpp", "ppcg_fused.hpp"):
         with open(os.path.join(ROOT, "paper_2105_06176_amd", "csrc", f), encoding="utf-8") as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -82,48 +82,102 @@ def sync():
     torch.cuda.synchronize()
 
 
+# The 128^3 storage the autotuner picks in plain runs, pinned so that the
+# counter runs (kernels serialized, where timing-based choices can flip)
+# measure the kernels timed here: SELL, 32-bit columns, 8-byte values, and the
+# single-launch iteration.
+C2_FLAGS_NAMES = ("FLAG_SELL_COL32", "FLAG_SELL_FULL_VALUES", "FLAG_ITER_FUSED")
+
+
+def survey_bytes_per_iter(n, nnz, fused):
+    """The byte model of one PIPECG iteration before any reformulation: CSR
+    matrix (8-byte values, 4-byte columns, 4-byte row pointers) and 22 FP64
+    vector streams (two launches: the update reads n z q s p x r u w m dinv and
+    writes z q s p x r u w m, the SpMV reads m and writes n), or 20 when one
+    launch keeps n in registers."""
+    return 12.0 * nnz + 4.0 * (n + 1) + 8.0 * (20 if fused else 22) * n
+
+
 def leg_c2(args, torch, ppcg, wl, oracle):
     A = wl.poisson3d(128)
     b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
     bd = torch.as_tensor(b).cuda()
-    # The storage is pinned to what the autotuner picks for this matrix in
-    # plain runs (SELL, 32-bit columns, 8-byte values): under counter
-    # collection the kernels are serialized and timing-based choices can
-    # flip, and the profiled runs must measure the kernels timed here.
-    S = ppcg.Solver(A, fixed_iters=max(args.warmup, 1), spmv_format="sell",
-                    flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES)
+    flags = 0
+    for name in C2_FLAGS_NAMES:
+        flags |= getattr(ppcg, name)
+    K = args.steps
+    S = ppcg.Solver(A, fixed_iters=K, spmv_format="sell", flags=flags)
     mi = S.matrix_info()
+    fused = mi["iter_launches"] == 1
     log(f"128^3: format={mi['format']} sigma={mi['sell_sigma']} stored={mi['nnz_stored']} "
-        f"col_bytes={mi['col_index_bytes']} value_bytes={mi['value_bytes']} setup={mi['setup_ms']:.1f}ms")
+        f"col_bytes={mi['col_index_bytes']} value_bytes={mi['value_bytes']} launches/iter={mi['iter_launches']} "
+        f"setup={mi['setup_ms']:.1f}ms")
     x = torch.empty_like(bd)
-    if args.warmup > 0:
+    # warm-up: W iterations as solves of the timed length, so the timed solve
+    # replays graphs captured here (no capture inside the timed region)
+    for _ in range(max(1, math.ceil(args.warmup / K))):
         S.solve(bd, out=x)
-    S.set_options(fixed_iters=args.steps)
     sync()
     t0 = time.perf_counter()
     _, info = S.solve(bd, out=x)
     sync()
     dt = time.perf_counter() - t0
-    assert info["iters"] == args.steps, info
-    ips = args.steps / dt
+    assert info["iters"] == K, info
+    ips = K / dt
     gbs = mi["bytes_per_iter"] * ips / 1e9
-    log(f"128^3 fixed {args.steps}: {dt * 1e3:.2f} ms, {ips:.0f} it/s, {gbs:.0f} GB/s")
-    # kernel durations (HIP events around each launch on the library's stream)
-    ms_vma, ms_spmv = S.time_kernels(bd, iters=100)
-    log(f"kernel avg: vma {ms_vma * 1e3:.2f} us, spmv {ms_spmv * 1e3:.2f} us")
-    dom = "vma" if ms_vma >= ms_spmv else "spmv"
-    bytes_dom = mi["bytes_vma"] if dom == "vma" else mi["bytes_spmv"]
-    ms_dom = ms_vma if dom == "vma" else ms_spmv
+    log(f"128^3 fixed {K}: {dt * 1e3:.2f} ms, {ips:.0f} it/s, {gbs:.0f} GB/s")
+
+    # steady state: the difference of two solve lengths cancels the per-solve
+    # initialisation (2-3 SpMVs), the final true residual and the host polls
+    def best_time(k, reps=3):
+        S.set_options(fixed_iters=k)
+        S.solve(bd, out=x)
+        ts = []
+        for _ in range(reps):
+            sync()
+            t = time.perf_counter()
+            S.solve(bd, out=x)
+            sync()
+            ts.append(time.perf_counter() - t)
+        return min(ts)
+
+    k1, k2 = 20, 520
+    t1, t2 = best_time(k1), best_time(k2)
+    steady = (t2 - t1) / (k2 - k1)
+    overhead = t1 - k1 * steady
+    sb = survey_bytes_per_iter(A.n, A.nnz, fused)
+    steady_res = {"us_per_iter": round(steady * 1e6, 3), "iters_per_s": round(1 / steady, 1),
+                  "effective_gbs": round(mi["bytes_per_iter"] / steady / 1e9, 1),
+                  "pct_peak_hbm": round(100 * mi["bytes_per_iter"] / steady / 1e9 / PEAK_HBM_GBS, 2),
+                  "effective_gbs_survey_bytes": round(sb / steady / 1e9, 1),
+                  "per_solve_init_finalize_ms": round(overhead * 1e3, 4),
+                  "method": f"(t({k2}) - t({k1})) / {k2 - k1}, best of 3 solves each"}
+    log(f"128^3 steady: {steady_res}")
+    # kernel durations (HIP events attached to each launch on the library's stream)
+    ms_a, ms_b = S.time_kernels(bd, iters=100)
+    if fused:
+        kname, bytes_dom, ms_dom = "k_fused", mi["bytes_per_iter"], ms_a
+        other = {}
+    else:
+        dom = "vma" if ms_a >= ms_b else "spmv"
+        bytes_dom = mi["bytes_vma"] if dom == "vma" else mi["bytes_spmv"]
+        ms_dom = ms_a if dom == "vma" else ms_b
+        kname = "k_vma<double>" if dom == "vma" else "k_spmv<double,MODE_ITER>"
+        ms_o = ms_b if dom == "vma" else ms_a
+        other = {"other_kernel_us": round(ms_o * 1e3, 3),
+                 "other_kernel_gbs": round((mi["bytes_spmv"] if dom == "vma" else mi["bytes_vma"]) /
+                                           (ms_o * 1e-3) / 1e9, 1)}
+    log(f"kernel avg: {kname} {ms_dom * 1e3:.2f} us")
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
-    kname = "k_vma<double>" if dom == "vma" else "k_spmv<double,MODE_ITER>"
+    traffic = measured_traffic(kname, "poisson3d_128")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(kname, "poisson3d_128"),
-            "kernel": kname, "bytes_per_launch": bytes_dom, "avg_launch_us": round(ms_dom * 1e3, 3),
-            "other_kernel_us": round((ms_spmv if dom == "vma" else ms_vma) * 1e3, 3),
-            "other_kernel_gbs": round((mi["bytes_spmv"] if dom == "vma" else mi["bytes_vma"]) /
-                                      ((ms_spmv if dom == "vma" else ms_vma) * 1e-3) / 1e9, 1)}
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "traffic_source": "profiles/traffic.json (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE of this kernel "
+                              "source)" if traffic else None,
+            "kernel": kname, "bytes_per_launch": bytes_dom, "avg_launch_us": round(ms_dom * 1e3, 3), **other}
     # tolerance run (after the fixed iterations; untimed in the main value)
     S.set_options(tol=1e-10, max_iter=10000)
+    S.solve(bd)
     sync()
     t0 = time.perf_counter()
     xt, it = S.solve(bd)
@@ -132,24 +186,36 @@ def leg_c2(args, torch, ppcg, wl, oracle):
     tol_run = {"iters": it["iters"], "status": it["status"], "rel_resid_true": it["rel_resid_true"],
                "time_s": round(ttol, 4), "restarts": it["restarts"]}
     log(f"128^3 to 1e-10: {it['iters']} iters, true rel resid {it['rel_resid_true']:.2e}, {ttol * 1e3:.1f} ms")
-    res = {"ips": ips, "dt": dt, "gbs": gbs, "mi": mi, "roofline": roof, "tol_run": tol_run}
+    res = {"ips": ips, "dt": dt, "gbs": gbs, "mi": mi, "roofline": roof, "tol_run": tol_run, "steady": steady_res,
+           "bytes_survey": sb, "fused": fused}
     if args.cpu_baseline:
         k = args.cpu_iters
         t0 = time.perf_counter()
         ref = oracle.pipecg(A, b, fixed_iters=k)
         tc = time.perf_counter() - t0
         ncpu, model = cpu_info()
+        # the paper's CPU baseline: PIPECG with OpenMP and merged loops, on
+        # the host's cores (at most 16: the GPU's share of the host)
+        th = min(oracle.omp_default_threads(), 16)
+        ko = 5 * k
+        t0 = time.perf_counter()
+        xo, sto, ito = oracle.pipecg_openmp(A, b, fixed_iters=ko, threads=th)
+        to = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": round(k / tc, 3), "unit": "iters/s", "cores": 1, "kind": "oracle",
                                "sample": f"FP64 C oracle (single thread), PIPECG {k} fixed iterations of the "
                                          f"128^3 7-point problem incl. its initialisation, {tc:.1f} s",
-                               "host_cpus": ncpu, "host_cpu_model": model}
+                               "host_cpus": ncpu, "host_cpu_model": model,
+                               "openmp": {"value": round(ito / to, 3), "unit": "iters/s", "cores": th,
+                                          "kind": "PIPECG-OpenMP (the paper's CPU baseline: merged update loops)",
+                                          "sample": f"{ito} fixed iterations of the same problem incl. its "
+                                                    f"initialisation, {to:.1f} s, {th} threads"}}
         # parity of the timed configuration on the same sample
         S.set_options(fixed_iters=k)
         xg, _ = S.solve(bd)
         res["parity_x_k"] = {"k": k, "rel_diff_vs_oracle": float(np.linalg.norm(xg.cpu().numpy() - ref.x) /
                                                                   np.linalg.norm(ref.x))}
-        log(f"oracle {k} iters: {tc:.1f}s ({k / tc:.2f} it/s); GPU/oracle x_{k} rel diff "
-            f"{res['parity_x_k']['rel_diff_vs_oracle']:.2e}")
+        log(f"oracle {k} iters: {tc:.1f}s ({k / tc:.2f} it/s); OpenMP {th} threads {ito / to:.1f} it/s; "
+            f"GPU/oracle x_{k} rel diff {res['parity_x_k']['rel_diff_vs_oracle']:.2e}")
     S.close()
     return res
 
@@ -411,6 +477,62 @@ def leg_p125(torch, ppcg, wl, side=165):
     return out
 
 
+def leg_rspd(torch, ppcg, wl, oracle, iters=200, shapes=("rspd_4.1M", "offshore", "serena")):
+    """Random sparse SPD matrices (uniform random columns, values U[-1,0),
+    diagonally dominant by 1e-2): N = 4.1M at ~17 entries per row, and
+    stand-ins with the N and nnz/N of Table 1's offshore and Serena matrices
+    (Section VI-A; the matrices themselves are not used).  Fixed-iteration
+    PIPECG rate with the autotuned storage and iteration form, algorithmic
+    GB/s, the SpMV's fraction of the HBM peak, and the full-size SpMV
+    against the oracle bit for bit."""
+    cases = {"rspd_4.1M": (4_096_000, 8, 0), "offshore": (259_789, 8, 1), "serena": (1_391_349, 23, 2),
+             "queen": (4_147_110, 39, 3)}
+    out = {"workload": f"random SPD (R14 generator), PIPECG FP64, {iters} fixed iterations, autotuned storage"}
+    for name in shapes:
+        n, draws, seed = cases[name]
+        t0 = time.perf_counter()
+        A = wl.random_spd(n, seed=seed, draws=draws)
+        gen_s = time.perf_counter() - t0
+        b = wl.rhs_from_solution(A, wl.xstar_uniform(A.n, 1))
+        bd = torch.as_tensor(b).cuda()
+        S = ppcg.Solver(A, fixed_iters=iters)
+        mi = S.matrix_info()
+        x = torch.empty_like(bd)
+        S.solve(bd, out=x)
+        sync()
+        t0 = time.perf_counter()
+        S.solve(bd, out=x)
+        sync()
+        dt = time.perf_counter() - t0
+        # the SpMV alone (two-launch kernels on the same storage) and the
+        # iteration's kernels as the handle runs them
+        xs = wl.xstar_uniform(A.n, 5)
+        exact = bool(np.array_equal(S.spmv(torch.as_tensor(xs).cuda()).cpu().numpy(), oracle.spmv(A, xs)))
+        T = ppcg.Solver(A, flags=ppcg.FLAG_ITER_TWO_LAUNCH)
+        ms_vma, ms_spmv = T.time_kernels(bd, iters=30)
+        mt = T.matrix_info()
+        T.close()
+        ms_a, _ = S.time_kernels(bd, iters=30)
+        spmv_gbs = mt["bytes_spmv"] / (ms_spmv * 1e-3) / 1e9
+        out[name] = {"n": A.n, "nnz": A.nnz, "nnz_per_row": round(A.nnz / A.n, 2), "generated_s": round(gen_s, 1),
+                     "iters_per_s": round(iters / dt, 1), "us_per_iter": round(dt / iters * 1e6, 2),
+                     "bytes_per_iter": mi["bytes_per_iter"],
+                     "effective_gbs": round(mi["bytes_per_iter"] * iters / dt / 1e9, 1),
+                     "launches_per_iter": mi["iter_launches"], "spmv_format": mi["format"],
+                     "sell_sigma": mi["sell_sigma"], "lanes_per_row": mi["lanes_per_row"],
+                     "nnz_stored": mi["nnz_stored"], "col_index_bytes": mi["col_index_bytes"],
+                     "setup_ms": round(mi["setup_ms"], 1),
+                     "spmv_kernel_us": round(ms_spmv * 1e3, 2), "spmv_kernel_gbs": round(spmv_gbs, 1),
+                     "spmv_frac_of_peak": round(spmv_gbs / PEAK_HBM_GBS, 4),
+                     "update_kernel_us": round(ms_vma * 1e3, 2),
+                     "iteration_kernel_us": round(ms_a * 1e3, 2) if mi["iter_launches"] == 1 else None,
+                     "spmv_bitwise_vs_oracle": exact}
+        log(f"random SPD {name}: {out[name]}")
+        S.close()
+        del A, b, bd, x
+    return out
+
+
 def _serve_requests(wl, n_req, seed=0, pool=0):
     """n_req requests; with pool > 0, drawn uniformly from pool distinct ones
     (same kind, size and tolerance distribution, far less host memory)."""
@@ -529,8 +651,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    ap.add_argument("--legs", default="c1,c3,c4,c5,p125,pcg,shard,hybrid",
-                    help="extra legs: c1,c3,c4,c5,p125,pcg,shard,hybrid or none")
+    ap.add_argument("--legs", default="c1,c3,c4,c5,p125,rspd,pcg,shard,hybrid",
+                    help="extra legs: c1,c3,c4,c5,p125,rspd,rspd_queen,pcg,shard,hybrid or none")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-pool", type=int, default=0,
                     help="draw the serving requests from this many distinct ones (0: all distinct)")
@@ -589,6 +711,10 @@ def main():
                                     tuple(float(v) for v in args.serve_loads.split(",") if v), args.serve_pool)
             elif name == "p125":
                 legs[name] = leg_p125(torch, ppcg, wl)
+            elif name == "rspd":
+                legs[name] = leg_rspd(torch, ppcg, wl, oracle)
+            elif name == "rspd_queen":
+                legs[name] = leg_rspd(torch, ppcg, wl, oracle, shapes=("queen",))
         except Exception as e:  # a failing extra leg must not hide the main line
             legs[name] = {"error": f"{type(e).__name__}: {e}"}
         log(f"leg {name} done in {time.perf_counter() - t0:.1f}s: {legs[name]}")
@@ -598,12 +724,14 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(c2["dt"] / args.steps * 1e3, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "PIPECG, 3D 7-point Poisson 128^3 (N=2097152, nnz=14581760), Jacobi, "
-                               "x*~U[-1,1] seed 1, b=A x*, x0=0, fixed iterations, FP64",
+                               "x*~U[-1,1] seed 1, b=A x*, x0=0, one solve of --steps fixed iterations, FP64",
                    "n": mi["n"], "nnz": mi["nnz"], "spmv_format": mi["format"], "sell_sigma": mi["sell_sigma"],
                    "nnz_stored": mi["nnz_stored"], "col_index_bytes": mi["col_index_bytes"],
-                   "value_bytes": mi["value_bytes"], "bytes_per_iter": mi["bytes_per_iter"]},
+                   "value_bytes": mi["value_bytes"], "launches_per_iter": mi["iter_launches"],
+                   "bytes_per_iter": mi["bytes_per_iter"], "bytes_per_iter_survey_model": c2["bytes_survey"]},
         "effective_gbs": round(c2["gbs"], 1), "pct_peak_hbm": round(100 * c2["gbs"] / PEAK_HBM_GBS, 2),
-        "roofline": c2["roofline"], "tol_1e-10": c2["tol_run"],
+        "effective_gbs_survey_bytes": round(c2["bytes_survey"] * c2["ips"] / 1e9, 1),
+        "steady_state": c2["steady"], "roofline": c2["roofline"], "tol_1e-10": c2["tol_run"],
     }
     if copy_gbs is not None:
         line["copy_256MiB_gbs"] = round(copy_gbs, 1)

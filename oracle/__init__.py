@@ -200,3 +200,46 @@ def pcg(A, b, **kw) -> Result:
 def pipecg(A, b, **kw) -> Result:
     """Algorithm 2 (PIPECG) with the Jacobi preconditioner, FP64."""
     return _run("pipecg", A, b, **kw)
+
+
+# ---------------------------------------------------------------- PIPECG-OpenMP
+# The paper's CPU baseline (Sections V-A and V-B): Algorithm 2 on host threads
+# with the vector-update loops merged.  A timing build, not the checker: its
+# reductions are summed per thread, so it agrees with ``pipecg`` to rounding.
+_OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
+_omp = None
+
+
+def _load_omp():
+    global _omp
+    if _omp is None:
+        if not os.path.exists(_OMP_PATH):
+            raise RuntimeError(f"{_OMP_PATH} is missing: run oracle/build.py")
+        L = ctypes.CDLL(_OMP_PATH)
+        P = ctypes.c_void_p
+        L.omp_pipecg.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.omp_pipecg.restype = ctypes.c_int
+        L.omp_default_threads.argtypes = []
+        L.omp_default_threads.restype = ctypes.c_int
+        _omp = L
+    return _omp
+
+
+def omp_default_threads() -> int:
+    return int(_load_omp().omp_default_threads())
+
+
+def pipecg_openmp(A, b, x0=None, tol=1e-8, maxit=10000, fixed_iters=0, stop=STOP_REL, threads=None):
+    """PIPECG-OpenMP: returns (x, status, iterations)."""
+    L = _load_omp()
+    rp, ci, val = _csr(A)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64)
+    it = ctypes.c_int(0)
+    th = int(threads) if threads else int(L.omp_default_threads())
+    st = L.omp_pipecg(A.n, _p(rp), _p(ci), _p(val), _p(b), _p(x), float(tol), int(maxit), int(fixed_iters),
+                      int(stop), th, ctypes.byref(it))
+    if st < 0:
+        raise ValueError("bad input to PIPECG-OpenMP")
+    return x, st, it.value

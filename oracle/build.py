@@ -7,11 +7,19 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ppcg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+OMP_SRC = os.path.join(HERE, "ppcg_omp.c")
+OMP_LIB = os.path.join(HERE, "liboracle_omp.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            "-o", LIB, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    # the paper's CPU baseline (PIPECG-OpenMP), a timing build
+    cmd = ["gcc", "-std=c99", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", OMP_LIB, OMP_SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
