@@ -33,7 +33,8 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# PPCG_ORACLE_LIB selects another build of the oracle (the tests' sanitized build)
+_LIB_PATH = os.environ.get("PPCG_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 _lib = None
 
 OK, NOT_CONVERGED, BREAKDOWN, STAGNATED, BAD_INPUT = 0, 1, 2, 3, -1

@@ -26,6 +26,18 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(out: str, verbose: bool = False) -> str:
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer (CPU
+    tests only): any out-of-bounds access or undefined operation aborts."""
+    cmd = ["gcc", "-std=c99", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", out, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

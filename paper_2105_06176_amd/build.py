@@ -29,15 +29,15 @@ def _compile(src: str, build_dir: str, extra) -> str:
     return obj
 
 
-def build(verbose: bool = False, extra_flags=(), out: str = LIB) -> str:
-    """Compile and link the library; extra_flags (e.g. -D tuning macros) and
-    out allow side builds of variants."""
+def build(verbose: bool = False, extra_flags=(), out: str = LIB, link_flags=()) -> str:
+    """Compile and link the library; extra_flags (e.g. -D tuning macros),
+    link_flags and out allow side builds of variants."""
     build_dir = BUILD if out == LIB else os.path.splitext(out)[0] + "_build"
     os.makedirs(build_dir, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(len(SOURCES)) as ex:
         objs = list(ex.map(lambda src: _compile(src, build_dir, list(extra_flags)), SOURCES))
     tmp = out + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_flags, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -129,6 +129,7 @@ struct ppcg_handle {
     // the single-launch form, chosen at create time; the single-launch form's
     // buffers (state and partial-sum slots, second m buffer).
     int form = 0;
+    bool x0_zero = false;  // the last staged initial guess was zero (no x0 given)
     ppcg::SysState *frec = nullptr;
     double *fpart = nullptr;
     double *m1 = nullptr;
@@ -171,6 +172,13 @@ struct Job {
     bool pcg = false;
     // FP64 PIPECG in the single-launch form
     bool fused = false;
+    // the initialisation has run once (a later one is a restart from x)
+    bool started = false;
+    // the initial guess is zero: the first initialisation needs no SpMV
+    bool x0_zero = false;
+    // fixed-iteration job whose remaining iterations were all launched in
+    // this step, with its true residual enqueued behind them
+    bool expect_done = false;
 };
 
 enum MixKind { MIX_NONE = 0, MIX_INNER32 = 1, MIX_VALUES32 = 2 };
@@ -201,6 +209,8 @@ struct Group {
     WorkItem *aux_d = nullptr;
     int *aux_count_d = nullptr;
     int aux_cap = 0;
+    std::vector<WorkItem> aux_h;    // items last uploaded to aux_d (an unchanged table is not re-sent)
+    std::vector<SysDesc> desc_up;   // descriptors last uploaded to desc_d
     WorkItem *stage_h = nullptr;    // pinned staging for table uploads
     int *stage_cnt_h = nullptr;
     int stage_cap = 0;
@@ -251,6 +261,12 @@ class Engine {
     ppcg_status ensure_graph(Group &g, int iters, hipGraphExec_t *exec);
     void drop_graphs(Group &g);
     int chunk_iters(const Group &g, int max_iters);
+    // Graph lengths to launch back to back for group g before the next
+    // poll: one chunk, or, when every iterating job of the group runs a
+    // fixed number of iterations, as many chunks as cover them (at most
+    // kFixedChunksPerPoll): such jobs need no poll to decide how long to run.
+    // *covers: the chunks run every fixed-iteration job of the group to its end.
+    std::vector<int> chunk_plan(const Group &g, int max_iters, bool *covers);
     // group and slot where a job iterates
     Group &pgroup(const Job &j)
     {
@@ -298,7 +314,21 @@ inline FinalAction final_action(const ppcg_options &o, const SysState &st, int r
 }
 
 // Aux operations run over a subset of slots.
-enum AuxOp { AUX_INIT = 0, AUX_RESID = 1, AUX_MIX_START = 2, AUX_MIX_CORRECT = 3, AUX_REPL = 4 };
+// AUX_START: the first initialisation of a job (x holds the staged initial
+// guess, nothing deferred); AUX_INIT: a restart from the current x.
+// AUX_START0: a first start from x0 = 0 (r0 = b without a pass over A).
+enum AuxOp {
+    AUX_INIT = 0,
+    AUX_RESID = 1,
+    AUX_MIX_START = 2,
+    AUX_MIX_CORRECT = 3,
+    AUX_REPL = 4,
+    AUX_START = 5,
+    AUX_START0 = 6
+};
+
+// Graph chunks a step may launch back to back for fixed-iteration jobs.
+constexpr int kFixedChunksPerPoll = 16;
 
 // Launch sequences of FP64 Algorithm 2 over a work table (grid = table
 // size), shared by the engine and ppcg_solve_noalloc:
@@ -308,12 +338,14 @@ enum AuxOp { AUX_INIT = 0, AUX_RESID = 1, AUX_MIX_START = 2, AUX_MIX_CORRECT = 3
 //   launch_pipecg_iter  one iteration (fused update, SpMV with reduction);
 //   launch_true_resid   ||b - A x||^2 and ||b||^2 into the state record.
 void launch_x_complete(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
-void launch_pipecg_init(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
+void launch_pipecg_init(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid,
+                        bool x_zero = false);
 void launch_pipecg_iter(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int remap);
 // The initialisation of the single-launch form: r0, u0, w0, m0 and the
 // partials of the first dot products (its first launch computes n0 and the
 // first alpha and beta itself).
-void launch_pipecg_init_fused(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
+void launch_pipecg_init_fused(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid,
+                              bool x_zero = false);
 // K launches of the single-launch form over a table of fused tiles (K even),
 // preceded by k_fused_begin.
 void launch_fused_chunk(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int iters);

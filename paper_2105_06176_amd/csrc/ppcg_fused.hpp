@@ -56,7 +56,7 @@ namespace ppcg {
 
 struct FusedScalars {
     double alpha, beta, alpha_x;
-    int go, x_pending;
+    int go, x_pending, x_finish;
 };
 
 // SpMV of one SELL chunk row (n = A m) with the handle's storage variant.
@@ -104,8 +104,16 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
     const SysState *rin = d.frec + par;
-    if (rin->done)
+    if (rin->done) {
+        // The launch that stopped the system published its record in this
+        // launch's slot only.  Copy it into the other slot, so that the
+        // launch after this one also sees it: otherwise that launch would
+        // redo the stopping step from the older record (and apply the final
+        // x-update a second time).  Nothing in this launch reads the other slot.
+        if (wi.tile == 0 && threadIdx.x == 0)
+            d.frec[par ^ 1] = *rin;
         return;
+    }
     const int n = d.n;
     const double *min = (const double *)(par ? d.m1 : d.m);
     double *mout = (double *)(par ? d.m : d.m1);
@@ -144,6 +152,11 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
             sc.alpha_x = loc.alpha_x;
             sc.x_pending = loc.x_pending;
             sc.go = !loc.done;
+            // a stopping system gets its deferred x-update in this launch,
+            // so that x is complete when the host reads the state
+            sc.x_finish = loc.done && loc.x_pending;
+            if (sc.x_finish)
+                loc.x_pending = 0;
             if (wi.tile == 0) {
                 d.frec[par ^ 1] = loc;
                 *d.st = loc;
@@ -151,8 +164,19 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
         }
         __syncthreads();
     }
-    if (!sc.go)
+    if (!sc.go) {
+        if (sc.x_finish) {
+            const double a = sc.alpha_x;
+            PPCG_AS1 double *__restrict__ X = as_global((double *)d.x);
+            const PPCG_AS1 double *__restrict__ P = as_global((const double *)d.p);
+            for (int k = 0; k < R; ++k) {
+                const int i = row0 + k * kFusedThreads + tid;
+                if (i < n)
+                    X[i] = X[i] + a * P[i];
+            }
+        }
         return;
+    }
     // 2. Per row of this thread (row0 + k * kFusedThreads + tid): n = A m_i
     // into a register, then the fused update with it.
     const double sa = sc.alpha, sb = sc.beta, ax = sc.alpha_x;

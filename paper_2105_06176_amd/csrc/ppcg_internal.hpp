@@ -25,8 +25,14 @@ constexpr int kNumPartials = 4;    // (r,u), (w,u), (u,u), (r,r)
 constexpr int kPartStride = 8;     // doubles per tile partial record (replacement uses 6)
 // The single-launch iteration (ppcg_fused.hpp): tiles of kFusedRows rows,
 // kFusedRowsPerThread rows per thread.
-constexpr int kFusedThreads = 512;
-constexpr int kFusedRowsPerThread = 4;
+#ifndef PPCG_FUSED_THREADS
+#define PPCG_FUSED_THREADS 512
+#endif
+#ifndef PPCG_FUSED_ROWS_PER_THREAD
+#define PPCG_FUSED_ROWS_PER_THREAD 4
+#endif
+constexpr int kFusedThreads = PPCG_FUSED_THREADS;
+constexpr int kFusedRowsPerThread = PPCG_FUSED_ROWS_PER_THREAD;
 constexpr int kFusedRows = kFusedThreads * kFusedRowsPerThread;
 static_assert(kFusedRows % kTileRows == 0, "fused tiles are whole 512-row tiles");
 static_assert(kFusedThreads % kSellC == 0, "each wavefront of a fused tile reads whole SELL chunks");

@@ -43,8 +43,10 @@ enum SpmvMode : int {
     MODE_REPL1 = 5,  // r = b - A x (FP64 values); u = M^-1 r
     MODE_DUAL1 = 6,  // w = A u and s = A p in one pass; m = M^-1 w; q = M^-1 s;
                      // partials (r,u),(w,u),(u,u),(r,r),(u,s),(p,s)
-    MODE_DUAL2 = 7   // nv = A m and z = A q in one pass; reduce; scalars with the
+    MODE_DUAL2 = 7,  // nv = A m and z = A q in one pass; reduce; scalars with the
                      // exact alpha denominator
+    MODE_INIT0 = 8   // MODE_INIT1 for x = 0 (r = b exactly: A 0 sums to +0 in every
+                     // row), without the pass over the matrix
 };
 
 constexpr int kReplPartials = 6;
@@ -736,7 +738,8 @@ __device__ __forceinline__ void spmv_inputs(const SysDesc &d, const T *(&x)[Spmv
 
 // Modes that form a true residual b - A x always use the FP64 values; the
 // iteration's own products use the FP32 copy in vals32 mode.
-template <int MODE> constexpr bool kTrueOperator = MODE == MODE_INIT1 || MODE == MODE_RESID || MODE == MODE_REPL1;
+template <int MODE> constexpr bool kTrueOperator =
+    MODE == MODE_INIT1 || MODE == MODE_INIT0 || MODE == MODE_RESID || MODE == MODE_REPL1;
 
 // Per-row epilogue of each mode; accumulates this row's share of the partials.
 template <typename T, int MODE>
@@ -746,13 +749,13 @@ __device__ __forceinline__ void spmv_epilogue(const SysDesc &d, int i, const T (
     const PPCG_AS1 T *DI = as_global((const T *)d.dinv);
     if constexpr (MODE == MODE_ITER || MODE == MODE_PLAIN) {
         as_global((T *)d.nv)[i] = y[0];
-    } else if constexpr (MODE == MODE_INIT1 || MODE == MODE_REPL1) {
+    } else if constexpr (MODE == MODE_INIT1 || MODE == MODE_INIT0 || MODE == MODE_REPL1) {
         const T bi = as_global((const T *)d.b)[i];
         const T ri = bi - y[0];
         const T ui = DI[i] * ri;
         as_global((T *)d.r)[i] = ri;
         as_global((T *)d.u)[i] = ui;
-        if constexpr (MODE == MODE_INIT1) {
+        if constexpr (MODE == MODE_INIT1 || MODE == MODE_INIT0) {
             // z, q, s, p enter the first update multiplied by beta = 0: start
             // them at zero so that stale memory (possibly NaN) cannot leak in.
             as_global((T *)d.z)[i] = (T)0;
@@ -851,6 +854,27 @@ __device__ __forceinline__ void spmv_tile(const SysDesc &d, const VT *__restrict
     spmv_inputs<T, MODE>(d, xin);
     const int n = d.n;
     T y[NX];
+    if constexpr (MODE == MODE_INIT0) {
+        // A x with x = 0 is +0 in every row: the epilogues run on the rows
+        // and in the order of the format's SpMV (the same partial sums)
+        y[0] = (T)0;
+        if (d.fmt == FMT_SELL) {
+            const int chunk = wi.tile * kSellChunksPerTile + (threadIdx.x >> 6);
+            const int i = chunk * kSellC + (threadIdx.x & 63);
+            if (chunk * kSellC < n && i < n)
+                spmv_epilogue<T, MODE>(d, i, y, acc);
+        } else {
+            const int L = d.lanes;
+            const int g = threadIdx.x / L, l = threadIdx.x % L;
+            const int rows_per_pass = kSpmvThreads / L;
+            for (int pass = 0; pass < kTileRows / rows_per_pass; ++pass) {
+                const int i = wi.tile * kTileRows + pass * rows_per_pass + g;
+                if (l == 0 && i < n)
+                    spmv_epilogue<T, MODE>(d, i, y, acc);
+            }
+        }
+        return;
+    }
     if (d.fmt == FMT_SELL) {
         static_assert(kTileRows == kSpmvThreads, "SELL path: one row per lane");
         const int lane = threadIdx.x & 63;
@@ -934,7 +958,7 @@ __global__ __launch_bounds__(kSpmvThreads, PPCG_SPMV_WAVES) void k_spmv(const Wo
         spmv_tile<T, T, MODE>(d, (const T *)d.val, wi, acc);
     }
     constexpr bool kWritesPartials =
-        MODE == MODE_INIT1 || MODE == MODE_INIT2 || MODE == MODE_RESID || MODE == MODE_DUAL1;
+        MODE == MODE_INIT1 || MODE == MODE_INIT0 || MODE == MODE_INIT2 || MODE == MODE_RESID || MODE == MODE_DUAL1;
     if constexpr (kWritesPartials) {
         constexpr int NV = MODE == MODE_DUAL1 ? kReplPartials : kNumPartials;
         double v[NV];
@@ -957,7 +981,7 @@ __global__ __launch_bounds__(kSpmvThreads, PPCG_SPMV_WAVES) void k_spmv(const Wo
     if (wi.tile != 0)
         return;
     // Designated workgroup of this system.
-    if constexpr (MODE == MODE_INIT1) {
+    if constexpr (MODE == MODE_INIT1 || MODE == MODE_INIT0) {
         if (threadIdx.x == 0) {
             st->phase = 1;
             st->i_start = 0;

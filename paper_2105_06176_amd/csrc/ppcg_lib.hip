@@ -218,7 +218,7 @@ static ppcg_status sell_size(hipStream_t s, int n, int sigma, const int *rowlen,
     PPCG_HIP_CLEAN(hipMalloc(&cp, sizeof(int64_t) * (nchunks + 1)), clean());
     if (sigma > 1) {
         PPCG_HIP_CLEAN(hipMalloc(&perm, sizeof(int) * n), clean());
-        k_sort_window<<<blocks_for(n, kSortWindow), kSortWindow / 2, 0, s>>>(n, rowlen, perm);
+        launch_sort_window(s, n, sigma, rowlen, perm);
     }
     k_chunk_size<<<blocks_for(nchunks, 256), 256, 0, s>>>(n, nchunks, perm, rowlen, sz);
     k_scan<<<1, 1024, 0, s>>>(nchunks, sz, cp);
@@ -244,7 +244,7 @@ static ppcg_status build_sell(hipStream_t s, int n, int sigma, const int *rp, co
     if (sigma > 1) {
         PPCG_HIP_CLEAN(hipMalloc(&sb.perm, sizeof(int) * n), clean());
         PPCG_HIP_CLEAN(hipMalloc(&sb.invperm, sizeof(int) * n), clean());
-        k_sort_window<<<blocks_for(n, kSortWindow), kSortWindow / 2, 0, s>>>(n, rowlen, sb.perm);
+        launch_sort_window(s, n, sigma, rowlen, sb.perm);
         k_invert_perm<<<blocks_for(n, 256), 256, 0, s>>>(n, sb.perm, sb.invperm);
     }
     k_chunk_size<<<blocks_for(sb.nchunks, 256), 256, 0, s>>>(n, sb.nchunks, sb.perm, rowlen, sz);
@@ -1040,11 +1040,17 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
     int64_t st1 = 0;
     PPCG_TRY(sell_size(h->stream, h->n, 1, rowlen, &st1));
     cands.push_back({FMT_SELL, 1, 0});
-    if ((double)st1 > 1.05 * (double)h->nnz)
-        cands.push_back({FMT_SELL, kSortWindow, 0});
-    if (mean >= 12.0) {
+    // rows sorted by length inside windows of sigma rows, when unsorted
+    // chunks pad by more than 1 %: every window size is timed
+    if ((double)st1 > 1.01 * (double)h->nnz)
+        for (int w : kSortWindows)
+            if (w < h->n)
+                cands.push_back({FMT_SELL, w, 0});
+    // CSR-vector with groups of 2 .. 64 lanes around a quarter of the mean
+    // row length
+    if (mean >= 8.0) {
         const int l = pow2_near(mean / 4);
-        for (int lanes : {l / 2, l, l * 2})
+        for (int lanes : {l / 4, l / 2, l, l * 2, l * 4})
             if (lanes >= 2 && lanes <= 64)
                 cands.push_back({FMT_CSRV, 1, lanes});
     }
@@ -1183,6 +1189,10 @@ ppcg_status Engine::ensure_group(Group &g, int prec, int cap_sys)
     PPCG_HIP(hipHostMalloc((void **)&g.stage_cnt_h, sizeof(int) * 3, hipHostMallocDefault));
     g.desc_h.assign(cap_sys, SysDesc{});
     g.slot_used.assign(cap_sys, 0);
+    // never equal to a filled descriptor (n >= 1), so the first upload happens
+    SysDesc none;
+    memset(&none, 0, sizeof none);
+    g.desc_up.assign(cap_sys, none);
     return PPCG_OK;
 }
 
@@ -1219,7 +1229,12 @@ int Engine::alloc_slot(Group &g)
 
 ppcg_status Engine::upload_desc(Group &g, int slot)
 {
+    // descriptors are built from a zeroed record (padding included), so an
+    // unchanged one compares equal byte for byte and is not sent again
+    if (memcmp(&g.desc_up[slot], &g.desc_h[slot], sizeof(SysDesc)) == 0)
+        return PPCG_OK;
     PPCG_HIP(hipMemcpyAsync(g.desc_d + slot, &g.desc_h[slot], sizeof(SysDesc), hipMemcpyHostToDevice, stream_));
+    g.desc_up[slot] = g.desc_h[slot];
     return PPCG_OK;
 }
 
@@ -1269,10 +1284,13 @@ void launch_x_complete(hipStream_t s, const WorkItem *tab, const int *cnt, const
     k_x_settle<<<grid, 64, 0, s>>>(tab, cnt, dd);
 }
 
-void launch_pipecg_init(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid)
+void launch_pipecg_init(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, bool x_zero)
 {
     const int rs = PPCG_XCD_REMAP_SPMV;
-    k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+    if (x_zero)
+        k_spmv<double, MODE_INIT0><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+    else
+        k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
     k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
     k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
 }
@@ -1283,10 +1301,14 @@ void launch_pipecg_iter(hipStream_t s, const WorkItem *tab, const int *cnt, cons
     k_spmv<double, MODE_ITER><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, PPCG_XCD_REMAP_SPMV);
 }
 
-void launch_pipecg_init_fused(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid)
+void launch_pipecg_init_fused(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid,
+                              bool x_zero)
 {
     const int rs = PPCG_XCD_REMAP_SPMV;
-    k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+    if (x_zero)
+        k_spmv<double, MODE_INIT0><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+    else
+        k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
     k_spmv<double, MODE_INIT2><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
 }
 
@@ -1482,6 +1504,45 @@ int Engine::chunk_iters(const Group &g, int max_iters)
     return k;
 }
 
+std::vector<int> Engine::chunk_plan(const Group &g, int max_iters, bool *covers)
+{
+    *covers = false;
+    bool all_fixed = true;
+    int want = 1;
+    for (const Job &j : jobs_) {
+        if (j.finished || j.stage != JS_ITER || &pgroup(j) != &g)
+            continue;
+        const SysDesc &d = g.desc_h[pslot(j)];
+        if (d.fixed <= 0 || d.repl_factor > 0.0)
+            all_fixed = false;
+        want = std::max(want, iters_needed(d, g.st_h[pslot(j)], j.rate, j.last_norm >= 0, INT_MAX / 4, g.pcg));
+    }
+    if (!all_fixed || g.pcg)
+        return {chunk_iters(g, max_iters)};
+    int cap = 1;
+    while (cap * 2 <= max_iters)
+        cap *= 2;
+    if (g.fused) {
+        // k updates take k + 1 launches, an even number per chunk
+        want += 1;
+        want += want & 1;
+        cap = std::max(cap, 2);
+    }
+    int left = std::min(want, kFixedChunksPerPoll * cap);
+    *covers = left == want;
+    std::vector<int> plan;
+    while (left > 0) {
+        int c = 1;
+        while (c * 2 <= left && c * 2 <= cap)
+            c *= 2;
+        if (g.fused && c < 2)
+            c = 2;
+        plan.push_back(c);
+        left -= c;
+    }
+    return plan;
+}
+
 ppcg_status Engine::sync_states(Group &g)
 {
     PPCG_HIP(hipMemcpyAsync(g.st_h, g.st_d, sizeof(SysState) * g.cap_sys, hipMemcpyDeviceToHost, stream_));
@@ -1493,15 +1554,23 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
 {
     if (slots.empty())
         return PPCG_OK;
-    // The staging buffer and aux_d may still be read by earlier enqueued
-    // copies and kernels: drain the stream before reusing them.
-    PPCG_HIP(hipStreamSynchronize(stream_));
     std::vector<WorkItem> items;
     for (int sl : slots)
         for (int t = 0; t < g.desc_h[sl].ntiles; ++t)
             items.push_back({sl, t});
-    PPCG_TRY(grow_table(&g.aux_d, &g.aux_cap, (int)items.size()));
-    PPCG_TRY(upload_table(stream_, g, items, g.aux_d, g.aux_count_d, 1));
+    const bool same = items.size() == g.aux_h.size() &&
+                      std::equal(items.begin(), items.end(), g.aux_h.begin(),
+                                 [](const WorkItem &a, const WorkItem &b) { return a.slot == b.slot && a.tile == b.tile; });
+    if (!same) {
+        // The staging buffer and aux_d may still be read by earlier enqueued
+        // copies and kernels: drain the stream before reusing them.
+        PPCG_HIP(hipStreamSynchronize(stream_));
+        WorkItem *old = g.aux_d;
+        PPCG_TRY(grow_table(&g.aux_d, &g.aux_cap, (int)items.size()));
+        (void)old;
+        PPCG_TRY(upload_table(stream_, g, items, g.aux_d, g.aux_count_d, 1));
+        g.aux_h = items;
+    }
     const int grid = (int)items.size();
     hipStream_t s = stream_;
     const WorkItem *tab = g.aux_d;
@@ -1511,14 +1580,22 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
     const bool f32 = g.prec == PREC_F32;
     // the fused update of Algorithm 2 defers every other x-update: complete
     // x before anything reads it (a no-op for systems with nothing pending)
-    if (!g.pcg && &g != &gs_ && (what == AUX_RESID || what == AUX_REPL || what == AUX_INIT))
+    // (the single-launch form applies a deferred x-update in the launch that
+    // stops the system, so its x is always complete here)
+    if (!g.pcg && !g.fused && &g != &gs_ && (what == AUX_RESID || what == AUX_REPL || what == AUX_INIT))
         launch_x_complete(s, tab, cnt, dd, grid);
+    const bool x_zero = what == AUX_START0;
+    if (what == AUX_START || what == AUX_START0)  // a first start: nothing deferred, x complete
+        what = AUX_INIT;
     if (what == AUX_INIT && g.pcg) {
         if (f32) {
             k_spmv<float, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
             k_pcg_dots<float><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
         } else {
-            k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            if (x_zero)
+                k_spmv<double, MODE_INIT0><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
+            else
+                k_spmv<double, MODE_INIT1><<<grid, kSpmvThreads, 0, s>>>(tab, cnt, dd, rs);
             k_pcg_dots<double><<<grid, kVmaThreads, 0, s>>>(tab, cnt, dd);
         }
         k_pcg_update<PCG_START><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
@@ -1535,9 +1612,9 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
         }
         k_pcg_update<PCG_REPL><<<grid, kPcgRedThreads, 0, s>>>(tab, cnt, dd);
     } else if (what == AUX_INIT && g.fused) {
-        launch_pipecg_init_fused(s, tab, cnt, dd, grid);
+        launch_pipecg_init_fused(s, tab, cnt, dd, grid, x_zero);
     } else if (what == AUX_INIT) {
-        launch_pipecg_init(s, tab, cnt, dd, grid);
+        launch_pipecg_init(s, tab, cnt, dd, grid, x_zero);
     } else if (what == AUX_RESID) {
         launch_true_resid(s, tab, cnt, dd, grid);
     } else if (what == AUX_REPL) {
@@ -1561,6 +1638,7 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
     j.h = h;
     j.mixed = mixed;
     j.tol = tol;
+    j.x0_zero = h->x0_zero;
     j.t_start = now_ms();
     const ppcg_options &o = h->opt;
     const int stop = o.stop == PPCG_STOP_PRECOND_ABS ? STOP_ABS : STOP_REL;
@@ -1845,12 +1923,13 @@ ppcg_status Engine::step(int graph_iters)
     }
     // 2. Initialisations and reliable updates.
     {
-        std::map<Group *, std::vector<int>> init, repl;
+        std::map<Group *, std::vector<int>> init, start, start0, repl;
         for (Job &j : jobs_) {
             if (j.finished)
                 continue;
             if (j.stage == JS_NEED_INIT) {
-                init[&pgroup(j)].push_back(pslot(j));
+                (j.started ? init : j.x0_zero ? start0 : start)[&pgroup(j)].push_back(pslot(j));
+                j.started = true;
                 j.stage = JS_ITER;
             } else if (j.stage == JS_NEED_REPL) {
                 Group &g = pgroup(j);
@@ -1865,6 +1944,10 @@ ppcg_status Engine::step(int graph_iters)
             }
         }
         for (Group *g : groups) {
+            if (start.count(g))
+                PPCG_TRY(aux_launch(*g, start[g], AUX_START));
+            if (start0.count(g))
+                PPCG_TRY(aux_launch(*g, start0[g], AUX_START0));
             if (init.count(g))
                 PPCG_TRY(aux_launch(*g, init[g], AUX_INIT));
             if (repl.count(g))
@@ -1892,17 +1975,26 @@ ppcg_status Engine::step(int graph_iters)
     // 4. One graph chunk per non-empty group, each on its own stream; the
     //    small group runs its chunk as a single launch of the one-workgroup
     //    kernel.  Tables and graphs are prepared on stream_ first.
-    hipGraphExec_t execs[kGroups] = {};
+    std::vector<hipGraphExec_t> execs[kGroups];
     int small_iters = 0;
+    std::vector<Group *> finals;  // groups whose fixed-iteration jobs all end in this step
     for (int k = 0; k < kGroups; ++k) {
         Group *g = groups[k];
         if (g->table_h.empty())
             continue;
         PPCG_TRY(ensure_table(*g));
-        if (g == &gs_)
+        if (g == &gs_) {
             small_iters = chunk_iters(gs_, kSmallChunkIters);
-        else
-            PPCG_TRY(ensure_graph(*g, chunk_iters(*g, graph_iters), &execs[k]));
+        } else {
+            bool covers = false;
+            for (int len : chunk_plan(*g, graph_iters, &covers)) {
+                hipGraphExec_t e = nullptr;
+                PPCG_TRY(ensure_graph(*g, len, &e));
+                execs[k].push_back(e);
+            }
+            if (covers && !g->pcg)
+                finals.push_back(g);
+        }
     }
     int nactive = 0;
     for (int k = 0; k < kGroups; ++k)
@@ -1923,16 +2015,29 @@ ppcg_status Engine::step(int graph_iters)
                                                                           small_iters);
             PPCG_HIP(hipGetLastError());
         } else {
-            PPCG_HIP(hipGraphLaunch(execs[k], gs));
+            for (hipGraphExec_t e : execs[k])
+                PPCG_HIP(hipGraphLaunch(e, gs));
         }
         if (fork) {
             PPCG_HIP(hipEventRecord(ev_join_[k], gs));
             PPCG_HIP(hipStreamWaitEvent(stream_, ev_join_[k], 0));
         }
     }
-    // 5. Poll.
+    // Fixed-iteration jobs whose last iteration was just launched: their
+    // true residual follows at once (no poll in between).
+    for (Group *g : finals) {
+        std::vector<int> slots;
+        for (Job &j : jobs_)
+            if (!j.finished && j.stage == JS_ITER && &pgroup(j) == g) {
+                slots.push_back(pslot(j));
+                j.expect_done = true;
+            }
+        PPCG_TRY(aux_launch(*g, slots, AUX_RESID));
+    }
+    // 5. Poll the groups that iterated.
     for (Group *g : groups)
-        PPCG_TRY(sync_states(*g));
+        if (!g->table_h.empty())
+            PPCG_TRY(sync_states(*g));
     PPCG_HIP(hipStreamSynchronize(stream_));
     for (Job &j : jobs_) {
         if (j.finished || j.stage != JS_ITER)
@@ -1940,6 +2045,18 @@ ppcg_status Engine::step(int graph_iters)
         const Group &g = pgroup(j);
         const SysState &st = g.st_h[pslot(j)];
         const SysDesc &d = g.desc_h[pslot(j)];
+        if (j.expect_done) {
+            j.expect_done = false;
+            if (!st.done) {
+                set_error("a fixed-iteration system did not stop after its last launch");
+                return PPCG_ERR_DEVICE;
+            }
+            const double bn = std::sqrt(st.bnorm2);
+            j.rel_true = bn > 0 ? std::sqrt(st.tnorm2) / bn : std::sqrt(st.tnorm2);
+            const FinalAction act = final_action(j.h->opt, st, j.restarts, j.rel_true, j.tol);
+            finish(j, act == FINAL_STAGNATED ? PPCG_STAGNATED : st.status, st);
+            continue;
+        }
         if (st.done) {
             j.last_norm = -1.0;
             j.rate = -1.0;
@@ -1974,6 +2091,7 @@ int auto_graph_iters(const ppcg_handle *h)
 // Copy b and x0 into the handle's internal (stored-row order) vectors.
 ppcg_status stage_inputs(ppcg_handle *h, const double *b, const double *x0)
 {
+    h->x0_zero = x0 == nullptr;
     hipStream_t s = h->stream;
     const int n = h->n;
     double *bi = (double *)h->f64.vec[VB], *xi = (double *)h->f64.vec[VX], *tmp = (double *)h->f64.vec[VN];

@@ -187,7 +187,8 @@ ppcg_status na_solve(const ppcg_csr *A, const ppcg_options *o, const double *b, 
         // a start (the first, or a restart from x with x completed first)
         if (restarts > 0)
             launch_x_complete(s, table, count, desc, ntiles);
-        launch_pipecg_init(s, table, count, desc, ntiles);
+        // a first start from x0 = 0 needs no pass over A for r0 = b
+        launch_pipecg_init(s, table, count, desc, ntiles, restarts == 0 && !x0);
         PPCG_HIP(hipGetLastError());
         double last_norm = -1.0, rate = -1.0;
         int last_iter = 0;

@@ -77,23 +77,24 @@ __global__ void k_validate(int n, int64_t nnz, const int *__restrict__ rp, const
     rowlen[i] = b - a;
 }
 
-// Sort the rows of each window of kSortWindow rows by decreasing length
-// (ties by increasing index): perm[p] = original row at sorted position p.
-// One workgroup of kSortWindow / 2 threads per window, bitonic sort in LDS.
-__global__ __launch_bounds__(kSortWindow / 2) void k_sort_window(int n, const int *__restrict__ rowlen,
-                                                                  int *__restrict__ perm)
+// Sort the rows of each window of W rows by decreasing length (ties by
+// increasing index): perm[p] = original row at sorted position p.  One
+// workgroup per window, bitonic sort of W keys in LDS.
+template <int W>
+__global__ __launch_bounds__(W / 2 < 512 ? W / 2 : 512) void k_sort_window(int n, const int *__restrict__ rowlen,
+                                                                           int *__restrict__ perm)
 {
-    __shared__ unsigned long long key[kSortWindow];
-    const int w0 = blockIdx.x * kSortWindow;
-    for (int j = threadIdx.x; j < kSortWindow; j += blockDim.x) {
+    __shared__ unsigned long long key[W];
+    const int w0 = blockIdx.x * W;
+    for (int j = threadIdx.x; j < W; j += blockDim.x) {
         const int r = w0 + j;
         key[j] = r < n ? ((unsigned long long)(0xFFFFFFFFu - (unsigned)rowlen[r]) << 32) | (unsigned)j
                        : ~0ull;
     }
     __syncthreads();
-    for (int k = 2; k <= kSortWindow; k <<= 1) {
+    for (int k = 2; k <= W; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < kSortWindow; t += blockDim.x) {
+            for (int t = threadIdx.x; t < W; t += blockDim.x) {
                 const int partner = t ^ j;
                 if (partner > t) {
                     const bool up = (t & k) == 0;
@@ -107,11 +108,26 @@ __global__ __launch_bounds__(kSortWindow / 2) void k_sort_window(int n, const in
             __syncthreads();
         }
     }
-    for (int j = threadIdx.x; j < kSortWindow; j += blockDim.x) {
+    for (int j = threadIdx.x; j < W; j += blockDim.x) {
         const int p = w0 + j;
         if (p < n)
             perm[p] = w0 + (int)(key[j] & 0xFFFFFFFFull);
     }
+}
+
+// Sorting windows the autotuner tries (sigma of SELL-C-sigma).
+constexpr int kSortWindows[] = {128, 1024, 4096};
+
+// perm for windows of sigma rows (one of kSortWindows).
+inline void launch_sort_window(hipStream_t s, int n, int sigma, const int *rowlen, int *perm)
+{
+    auto grid = [&](int w) { return (unsigned)((n + w - 1) / w); };
+    if (sigma == 128)
+        k_sort_window<128><<<grid(128), 64, 0, s>>>(n, rowlen, perm);
+    else if (sigma == 4096)
+        k_sort_window<4096><<<grid(4096), 512, 0, s>>>(n, rowlen, perm);
+    else
+        k_sort_window<1024><<<grid(1024), 512, 0, s>>>(n, rowlen, perm);
 }
 
 __global__ void k_invert_perm(int n, const int *__restrict__ perm, int *__restrict__ invperm)

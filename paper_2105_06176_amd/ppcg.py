@@ -13,7 +13,8 @@ import os
 from typing import List, Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libppcg.so")
+# PPCG_LIB selects another build of the library (the tests' sanitized side build)
+LIB_PATH = os.environ.get("PPCG_LIB") or os.path.join(HERE, "libppcg.so")
 
 # ppcg_status
 OK, NOT_CONVERGED, BREAKDOWN, STAGNATED = 0, 1, 2, 3
