@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <cstdarg>
+#include <functional>
 #include <cstdio>
 #include <map>
 #include <string>
@@ -251,6 +252,11 @@ class Engine {
     void reset();
     hipStream_t stream() const { return stream_; }
     int remap = PPCG_XCD_REMAP;
+    // Work to enqueue on the engine's stream right behind the true residual
+    // of fixed-iteration jobs whose last iteration was launched in the same
+    // step (a solo solve copies x out there, saving a host round trip); it
+    // runs for such jobs only, and before the step's poll.
+    std::function<ppcg_status()> after_fixed_final;
 
   private:
     ppcg_status ensure_group(Group &g, int prec, int cap_sys);
@@ -351,6 +357,8 @@ void launch_pipecg_init_fused(hipStream_t s, const WorkItem *tab, const int *cnt
 void launch_fused_chunk(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int iters);
 // Allocate the single-launch form's buffers of a handle (once).
 ppcg_status ensure_fused(ppcg_handle *h);
+// Fused tiles of a handle's system (fused_tile_rows rows each).
+int fused_tiles(const ppcg_handle *h);
 void launch_true_resid(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
 // CSR validation (ppcg_create's checks): dinv = 1 / diag, rowlen, and in
 // err[0] the OR of the error flags, err[1] the first offending row (err must

@@ -3,15 +3,17 @@
 //
 // The two-launch form (ppcg_kernels.hpp) writes n = A m in the SpMV launch
 // and reads it back in the next fused update.  Here each workgroup owns a
-// tile of kFusedRows rows and, in one launch:
+// tile of frows rows (512 to 2,048, fused_tile_rows: as many rows per
+// thread as keep the tile count near 1,024) and, in one launch:
 //
 //   1. reduces, in one fixed order, the per-tile partial sums of (r,u),
 //      (w,u), (u,u), (r,r) that the previous launch wrote, and runs the scalar
 //      recurrences (the stopping test, beta, alpha, breakdown) itself: every
 //      workgroup reads the same partials in the same order and so obtains
 //      bit-identical scalars, with no grid-wide synchronisation;
-//   2. for each of its rows (SELL-64, one lane per row, kFusedRowsPerThread
-//      rows per thread) computes n = A m_i into a register and applies the
+//   2. for each of its rows (SELL-64, one lane per row, up to
+//      kFusedRowsPerThread rows per thread) computes n = A m_i into a
+//      register and applies the
 //      fused vector updates of Section V-B with it, forming
 //      m_{i+1} = M^-1 w_{i+1};
 //   3. writes its own partial sums.
@@ -34,7 +36,7 @@
 //
 // The arithmetic of one row is that of the two-launch form (same SpMV order,
 // same update formulas, x-updates paired in the same way); only the
-// association of the dot products differs (2,048-row tiles), so results are
+// association of the dot products differs (over the fused tiles), so results are
 // deterministic, identical alone and batched, but not bitwise equal to the
 // two-launch form.
 #pragma once
@@ -93,7 +95,6 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
                                                                            const SysDesc *__restrict__ descs,
                                                                            int remap, int par)
 {
-    constexpr int R = kFusedRowsPerThread;
     __shared__ double lds[kFusedThreads / 64 * kNumPartials];
     __shared__ double vtab[kMaxValueTable];
     __shared__ FusedScalars sc;
@@ -103,6 +104,7 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     const int pos = remap ? xcd_remap(blockIdx.x, live) : (int)blockIdx.x;
     const WorkItem wi = table[pos];
     const SysDesc &d = descs[wi.slot];
+    const int R = d.frows / kFusedThreads;  // rows per thread, 1 .. kFusedRowsPerThread
     const SysState *rin = d.frec + par;
     if (rin->done) {
         // The launch that stopped the system published its record in this
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     const double *min = (const double *)(par ? d.m1 : d.m);
     double *mout = (double *)(par ? d.m : d.m1);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row0 = wi.tile * kFusedRows;
+    const int row0 = wi.tile * d.frows;
     const double *tab = nullptr;
     if (d.vidx) {
         for (int t = tid; t < d.nvtab; t += kFusedThreads)
@@ -240,7 +242,7 @@ __global__ void k_fused_begin(const WorkItem *__restrict__ table, const int *__r
         return;
     const int k = threadIdx.x;
     if (st->phase && k < kNumPartials) {
-        constexpr int per = kFusedRows / kTileRows;
+        const int per = d.frows / kTileRows;
         const int t0 = wi.tile * per, t1 = min(t0 + per, d.ntiles);
         const double *src = d.part + (size_t)d.ntiles * kPartStride;  // slot 1
         double a = src[(size_t)t0 * kPartStride + k];

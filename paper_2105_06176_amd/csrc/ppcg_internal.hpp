@@ -32,9 +32,19 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 #define PPCG_FUSED_ROWS_PER_THREAD 4
 #endif
 constexpr int kFusedThreads = PPCG_FUSED_THREADS;
-constexpr int kFusedRowsPerThread = PPCG_FUSED_ROWS_PER_THREAD;
-constexpr int kFusedRows = kFusedThreads * kFusedRowsPerThread;
-static_assert(kFusedRows % kTileRows == 0, "fused tiles are whole 512-row tiles");
+constexpr int kFusedRowsPerThread = PPCG_FUSED_ROWS_PER_THREAD;  // at most
+constexpr int kFusedRows = kFusedThreads * kFusedRowsPerThread;    // at most
+static_assert(kFusedThreads == kTileRows, "a fused tile is a whole number of 512-row tiles");
+
+// Rows per fused tile for a system of n rows: as few rows per thread as keep
+// the tile count near 1,024 (every workgroup re-reads one partial-sum record
+// per tile), so that small systems still spread over many workgroups.
+__host__ __device__ inline int fused_tile_rows(int n)
+{
+    int r = (n + 1024 * kFusedThreads - 1) / (1024 * kFusedThreads);
+    r = r < 1 ? 1 : r > kFusedRowsPerThread ? kFusedRowsPerThread : r;
+    return r * kFusedThreads;
+}
 static_assert(kFusedThreads % kSellC == 0, "each wavefront of a fused tile reads whole SELL chunks");
 
 // Tile-to-workgroup mapping.  The fused update is a pure stream and runs
@@ -153,7 +163,8 @@ struct SysDesc {
     double *part;         // partial sums: 2 slots x ntiles x kPartStride
     SysState *st;
     // single-launch iteration (ppcg_fused.hpp); unused by the two-launch form
-    int nftiles;          // tiles of kFusedRows rows
+    int nftiles;          // fused tiles (of frows rows)
+    int frows;            // rows per fused tile (fused_tile_rows(n))
     SysState *frec;       // scalar state, 2 slots (launch parity)
     double *fpart;        // partial sums, 2 slots x nftiles x 4
     void *m1;             // second m buffer (m is read by every tile's gathers while being rewritten)

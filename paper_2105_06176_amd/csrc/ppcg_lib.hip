@@ -335,18 +335,25 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->b = pd.vec[VB];
     d->part = prec == PREC_F64 ? h->part : h->part32;
     d->st = st;
-    d->nftiles = (h->n + kFusedRows - 1) / kFusedRows;
+    d->frows = fused_tile_rows(h->n);
+    d->nftiles = (h->n + d->frows - 1) / d->frows;
     d->frec = h->frec;
     d->fpart = h->fpart;
     d->m1 = h->m1;
     return PPCG_OK;
 }
 
+int fused_tiles(const ppcg_handle *h)
+{
+    const int fr = fused_tile_rows(h->n);
+    return (h->n + fr - 1) / fr;
+}
+
 ppcg_status ensure_fused(ppcg_handle *h)
 {
     if (h->frec)
         return PPCG_OK;
-    const size_t nft = (size_t)(h->n + kFusedRows - 1) / kFusedRows;
+    const size_t nft = (size_t)fused_tiles(h);
     const size_t pb = 2 * nft * 4 * sizeof(double), vb = (size_t)h->n * sizeof(double);
     PPCG_TRY(h->fused_arena.alloc(2 * sizeof(SysState) + pb + vb + 3 * 256));
     h->frec = (SysState *)h->fused_arena.take(2 * sizeof(SysState));
@@ -367,7 +374,7 @@ static ppcg_status plain_setup(ppcg_handle *h, double tol, int fixed, int maxit)
         std::vector<WorkItem> th(h->ntiles);
         for (int t = 0; t < h->ntiles; ++t)
             th[t] = {0, t};
-        const int count[2] = {h->ntiles, (h->n + kFusedRows - 1) / kFusedRows};
+        const int count[2] = {h->ntiles, fused_tiles(h)};
         PPCG_HIP(hipMemcpyAsync(h->plain_tab, th.data(), sizeof(WorkItem) * count[0], hipMemcpyHostToDevice, s));
         PPCG_HIP(hipMemcpyAsync(h->plain_cnt, count, sizeof count, hipMemcpyHostToDevice, s));
         PPCG_HIP(hipStreamSynchronize(s));  // host sources are about to go out of scope
@@ -783,7 +790,7 @@ static ppcg_status time_forms(ppcg_handle *h, double *ms_two, double *ms_fused, 
     constexpr int kIters = 16;
     hipStream_t s = h->stream;
     PPCG_TRY(plain_setup(h, 0.0, INT_MAX, INT_MAX));
-    const int n = h->n, grid = h->ntiles, fgrid = (n + kFusedRows - 1) / kFusedRows;
+    const int n = h->n, grid = h->ntiles, fgrid = fused_tiles(h);
     const WorkItem *tab = h->plain_tab;
     const int *cnt = h->plain_cnt;
     const SysDesc *dd = h->plain_desc;
@@ -2034,6 +2041,8 @@ ppcg_status Engine::step(int graph_iters)
             }
         PPCG_TRY(aux_launch(*g, slots, AUX_RESID));
     }
+    if (!finals.empty() && after_fixed_final)
+        PPCG_TRY(after_fixed_final());
     // 5. Poll the groups that iterated.
     for (Group *g : groups)
         if (!g->table_h.empty())
@@ -2479,8 +2488,18 @@ ppcg_status ppcg_solve(ppcg_handle *h, const double *b, const double *x0, double
     int id = -1;
     const int mixed = h->opt.precision == PPCG_MIXED_FP32 ? MIX_INNER32 : h->opt.precision == PPCG_MIXED_FP32_VALUES ? MIX_VALUES32 : MIX_NONE;
     PPCG_TRY(E.add(h, mixed, h->opt.tol, nullptr, &id));
-    PPCG_TRY(run_engine(E, auto_graph_iters(h)));
-    PPCG_TRY(unstage_x(h, x));
+    // a fixed-iteration solve copies x out behind its true residual, before
+    // the engine's last poll; otherwise after the engine has finished
+    bool unstaged = false;
+    E.after_fixed_final = [&]() -> ppcg_status {
+        unstaged = true;
+        return unstage_x(h, x);
+    };
+    ppcg_status rc = run_engine(E, auto_graph_iters(h));
+    E.after_fixed_final = nullptr;
+    PPCG_TRY(rc);
+    if (!unstaged)
+        PPCG_TRY(unstage_x(h, x));
     PPCG_HIP(hipStreamSynchronize(h->stream));
     Job &j = E.job(id);
     j.t_end = now_ms();
@@ -2653,7 +2672,7 @@ ppcg_status ppcg_time_kernels(ppcg_handle *h, const double *b, int32_t iters, do
     if (!pcg && h->form == FORM_FUSED) {
         // the single-launch form: its one kernel, after the initialisation
         // and the launch that ends it
-        const int fgrid = (h->n + kFusedRows - 1) / kFusedRows;
+        const int fgrid = fused_tiles(h);
         launch_pipecg_init_fused(s, tab, cnt, dd, grid);
         k_fused_begin<<<fgrid, 64, 0, s>>>(tab, cnt + 1, dd);
         k_fused<<<fgrid, kFusedThreads, 0, s>>>(tab, cnt + 1, dd, PPCG_FUSED_REMAP, 0);

@@ -8,7 +8,7 @@ operations as the two-launch form (SpMV in stored column order, the same
 update formulas); only the association of the dot products differs, so
 fixed iterates are held to the 1e-10 bar against the oracle, tolerance
 solves to the oracle's iteration count within 2 and a true residual at or
-below tol.  Cases span several 2,048-row tiles with a ragged last tile, the
+below tol.  Cases span several fused tiles (512 to 2,048 rows) with a ragged last tile, the
 value table, 16- and 32-bit columns, sorted rows, and the paths that end a
 solve (restart, stagnation, breakdown).
 """
@@ -51,13 +51,13 @@ def problem(A, seed=1):
 CASES = {
     # (generator, fixed iteration counts, extra create options)
     "c1_poisson2d_64": (lambda: poisson2d(64), (1, 10, 50, 100), {}),
-    "poisson2d_100_ragged": (lambda: poisson2d(100), (3, 40, 120), {}),      # 10,000 rows: 4 tiles + 1,808
+    "poisson2d_100_ragged": (lambda: poisson2d(100), (3, 40, 120), {}),      # 10,000 rows: 19 tiles + 272
     "poisson3d_40": (lambda: poisson3d(40), (25, 100), {}),
     "stencil27_20_col16": (lambda: stencil27_lognormal(20, seed=3), (10, 20), {"flags": ppcg.FLAG_SELL_COL16}),
     "stencil27_20_col32": (lambda: stencil27_lognormal(20, seed=3), (10, 20), {"flags": ppcg.FLAG_SELL_COL32}),
     "random_spd_30001_sorted": (lambda: random_spd(30001, seed=5), (5, 30), {}),
     "poisson125_12_vtab": (lambda: poisson125(12), (5, 15), {"flags": ppcg.FLAG_SELL_VALUE_TABLE}),
-    "tile_and_68_rows": (lambda: shifted(poisson2d(46), 0.1), (1, 7, 30), {}),  # 2,116 rows
+    "tile_and_68_rows": (lambda: shifted(poisson2d(46), 0.1), (1, 7, 30), {}),  # 2,116 rows: 4 tiles + 68
 }
 
 

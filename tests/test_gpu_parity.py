@@ -405,8 +405,11 @@ def test_indefinite_matrix_breaks_down():
 def test_kernel_timing_entry_point():
     A = poisson3d(48)
     b, _ = problem(A)
-    tv, ts = Solver(A).time_kernels(dev(b), iters=10)
-    assert tv > 0 and ts > 0
+    for flags in (ppcg.FLAG_ITER_TWO_LAUNCH, 0):
+        S = Solver(A, flags=flags)
+        tv, ts = S.time_kernels(dev(b), iters=10)
+        # the single-launch form reports its one kernel in the first figure
+        assert tv > 0 and (ts > 0 if S.matrix_info()["iter_launches"] == 2 else ts == 0.0)
 
 
 # ---------------------------------------------------------------- batching
