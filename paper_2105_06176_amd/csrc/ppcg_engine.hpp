@@ -84,6 +84,8 @@ enum VecIdx { VX = 0, VR, VU, VW, VM, VN, VZ, VQ, VS, VP, VB };
 enum IterForm { FORM_TWO = 0, FORM_FUSED = 1 };
 
 class Engine;
+struct BatchCtx;
+struct StageItem;
 
 }  // namespace ppcg
 
@@ -119,6 +121,7 @@ struct ppcg_handle {
     double *part32 = nullptr; // partials of the FP32-vector sequence
     double setup_ms = 0.0;
     ppcg::Engine *solo = nullptr;  // cached single-system engine
+    ppcg::BatchCtx *batch = nullptr;  // cached engine of batches led by this handle
     hipEvent_t ev_user = nullptr;  // recorded on user_stream for the internal stream to wait on
     // Single-system launch description for direct kernel calls (SpMV,
     // kernel timing, autotuning): descriptor, state, table of all tiles.
@@ -212,6 +215,10 @@ struct Group {
     int aux_cap = 0;
     std::vector<WorkItem> aux_h;    // items last uploaded to aux_d (an unchanged table is not re-sent)
     std::vector<SysDesc> desc_up;   // descriptors last uploaded to desc_d
+    // Uploads and state clears requested since the last flush (sent as one
+    // copy / clear per run of consecutive slots)
+    std::vector<char> desc_pending, st_pending;
+    SysDesc *desc_stage_h = nullptr;  // pinned staging of descriptor uploads
     WorkItem *stage_h = nullptr;    // pinned staging for table uploads
     int *stage_cnt_h = nullptr;
     int stage_cap = 0;
@@ -260,7 +267,13 @@ class Engine {
 
   private:
     ppcg_status ensure_group(Group &g, int prec, int cap_sys);
+    // Queue the upload of a slot's descriptor (skipped when unchanged) and
+    // the clearing of its state; flush_uploads() sends what is queued, in
+    // one copy and one clear per run of consecutive slots, ahead of any
+    // launch that reads them.
     ppcg_status upload_desc(Group &g, int slot);
+    void clear_state(Group &g, int slot) { g.st_pending[slot] = 1; }
+    ppcg_status flush_uploads();
     // `inner`: the group of the FP32 sequences (AUX_MIX_START, AUX_MIX_CORRECT)
     ppcg_status aux_launch(Group &g, const std::vector<int> &slots, int what, const Group *inner = nullptr);
     ppcg_status ensure_table(Group &g);
@@ -293,11 +306,25 @@ class Engine {
     static constexpr int kGroups = 7;
     hipStream_t gstream_[kGroups] = {};
     hipEvent_t ev_fork_ = nullptr;
+    hipEvent_t ev_desc_ = nullptr;  // the last flush's descriptor copies (staging reuse)
+    bool desc_copy_queued_ = false;
     hipEvent_t ev_join_[kGroups] = {};
     Group g64_, gv_, gs_;   // FP64 (and the FP64 steps of FP32-vector jobs), FP32 values, small systems
     Group gf_;              // FP64 PIPECG in the single-launch form
     Group gp_, gpv_, gp32_; // classic PCG: FP64, FP32 values, FP32 vectors
     std::vector<Job> jobs_;
+};
+
+// What ppcg_solve_batch keeps on the batch's first handle between calls:
+// the engine (its buffers, streams and captured graphs serve the next batch
+// of at most `cap` systems led by the same handle) and the item table of
+// the batched staging kernel (inputs in, solutions out).
+struct BatchCtx {
+    Engine *E = nullptr;
+    int cap = 0;
+    StageItem *items_d = nullptr;  // 3 x cap items: two per system in, one out
+    StageItem *items_h = nullptr;  // pinned staging of the same
+    ~BatchCtx();
 };
 
 // What follows a stopped FP64 sequence (Algorithm 2, or 1 with FP64 values)

@@ -1082,4 +1082,36 @@ __global__ void k_fill(size_t n, T *__restrict__ out, T v)
         out[i] = v;
 }
 
+// One vector move of a batched solve's staging (perm may be null):
+// STAGE_GATHER dst[i] = src[perm[i]], STAGE_ZERO dst[i] = 0,
+// STAGE_SCATTER dst[perm[i]] = src[i].
+enum StageOp : int { STAGE_GATHER = 0, STAGE_ZERO = 1, STAGE_SCATTER = 2 };
+struct StageItem {
+    const int *perm;
+    const double *src;
+    double *dst;
+    int n;
+    int op;
+};
+
+// All moves of a batch in one launch: grid.y strides over the items,
+// grid.x (with a grid stride) over each item's rows.
+__global__ void k_stage_batch(const StageItem *__restrict__ items, int count)
+{
+    for (int it = blockIdx.y; it < count; it += gridDim.y) {
+        const StageItem s = items[it];
+        const int stride = gridDim.x * blockDim.x;
+        if (s.op == STAGE_GATHER) {
+            for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride)
+                s.dst[i] = s.src[s.perm ? s.perm[i] : i];
+        } else if (s.op == STAGE_ZERO) {
+            for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride)
+                s.dst[i] = 0.0;
+        } else {
+            for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride)
+                s.dst[s.perm ? s.perm[i] : i] = s.src[i];
+        }
+    }
+}
+
 }  // namespace ppcg

@@ -1174,7 +1174,16 @@ Engine::~Engine()
         if (g->sys_count_d) (void)dev_free(g->sys_count_d);
         if (g->stage_h) (void)host_free(g->stage_h);
         if (g->stage_cnt_h) (void)host_free(g->stage_cnt_h);
+        if (g->desc_stage_h) (void)host_free(g->desc_stage_h);
     }
+    if (ev_desc_) (void)hipEventDestroy(ev_desc_);
+}
+
+BatchCtx::~BatchCtx()
+{
+    delete E;
+    if (items_d) (void)dev_free(items_d);
+    if (items_h) (void)host_free(items_h);
 }
 
 ppcg_status Engine::ensure_group(Group &g, int prec, int cap_sys)
@@ -1194,8 +1203,11 @@ ppcg_status Engine::ensure_group(Group &g, int prec, int cap_sys)
     PPCG_HIP(hipMalloc(&g.aux_count_d, sizeof(int)));
     PPCG_HIP(hipMalloc(&g.sys_count_d, sizeof(int)));
     PPCG_HIP(hipHostMalloc((void **)&g.stage_cnt_h, sizeof(int) * 3, hipHostMallocDefault));
+    PPCG_HIP(hipHostMalloc((void **)&g.desc_stage_h, sizeof(SysDesc) * cap_sys, hipHostMallocDefault));
     g.desc_h.assign(cap_sys, SysDesc{});
     g.slot_used.assign(cap_sys, 0);
+    g.desc_pending.assign(cap_sys, 0);
+    g.st_pending.assign(cap_sys, 0);
     // never equal to a filled descriptor (n >= 1), so the first upload happens
     SysDesc none;
     memset(&none, 0, sizeof none);
@@ -1207,6 +1219,7 @@ ppcg_status Engine::init(int cap_sys)
 {
     if (!ev_fork_) {
         PPCG_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+        PPCG_HIP(hipEventCreateWithFlags(&ev_desc_, hipEventDisableTiming));
         for (int k = 0; k < kGroups; ++k) {
             PPCG_HIP(hipStreamCreateWithFlags(&gstream_[k], hipStreamNonBlocking));
             PPCG_HIP(hipEventCreateWithFlags(&ev_join_[k], hipEventDisableTiming));
@@ -1240,8 +1253,54 @@ ppcg_status Engine::upload_desc(Group &g, int slot)
     // unchanged one compares equal byte for byte and is not sent again
     if (memcmp(&g.desc_up[slot], &g.desc_h[slot], sizeof(SysDesc)) == 0)
         return PPCG_OK;
-    PPCG_HIP(hipMemcpyAsync(g.desc_d + slot, &g.desc_h[slot], sizeof(SysDesc), hipMemcpyHostToDevice, stream_));
+    g.desc_pending[slot] = 1;
     g.desc_up[slot] = g.desc_h[slot];
+    return PPCG_OK;
+}
+
+// Send the queued descriptor uploads (through the group's pinned staging,
+// one copy per run of consecutive slots) and state clears.  Adding a batch
+// of systems thus costs a few transfers instead of two per system.
+ppcg_status Engine::flush_uploads()
+{
+    Group *const groups[] = {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_, &gf_};
+    bool copies = false;
+    for (Group *g : groups) {
+        for (int a = 0; a < g->cap_sys;) {
+            if (!g->desc_pending[a]) {
+                ++a;
+                continue;
+            }
+            int b = a;
+            while (b < g->cap_sys && g->desc_pending[b])
+                g->desc_pending[b++] = 0;
+            if (!copies && desc_copy_queued_) {
+                // the staging may still feed the previous flush's copies
+                PPCG_HIP(hipEventSynchronize(ev_desc_));
+                desc_copy_queued_ = false;
+            }
+            copies = true;
+            memcpy(g->desc_stage_h + a, &g->desc_h[a], sizeof(SysDesc) * (b - a));
+            PPCG_HIP(hipMemcpyAsync(g->desc_d + a, g->desc_stage_h + a, sizeof(SysDesc) * (b - a),
+                                    hipMemcpyHostToDevice, stream_));
+            a = b;
+        }
+        for (int a = 0; a < g->cap_sys;) {
+            if (!g->st_pending[a]) {
+                ++a;
+                continue;
+            }
+            int b = a;
+            while (b < g->cap_sys && g->st_pending[b])
+                g->st_pending[b++] = 0;
+            PPCG_HIP(hipMemsetAsync(g->st_d + a, 0, sizeof(SysState) * (b - a), stream_));
+            a = b;
+        }
+    }
+    if (copies) {
+        PPCG_HIP(hipEventRecord(ev_desc_, stream_));
+        desc_copy_queued_ = true;
+    }
     return PPCG_OK;
 }
 
@@ -1561,6 +1620,7 @@ ppcg_status Engine::aux_launch(Group &g, const std::vector<int> &slots, int what
 {
     if (slots.empty())
         return PPCG_OK;
+    PPCG_TRY(flush_uploads());
     std::vector<WorkItem> items;
     for (int sl : slots)
         for (int t = 0; t < g.desc_h[sl].ntiles; ++t)
@@ -1683,7 +1743,7 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
         if (v32)
             g.desc_h[slot].repl_factor = o.inner_tol > 0 ? o.inner_tol : 1e-3;
         PPCG_TRY(upload_desc(g, slot));
-        PPCG_HIP(hipMemsetAsync(g.st_d + slot, 0, sizeof(SysState), stream_));
+        clear_state(g, slot);
         j.stage = JS_NEED_INIT;
     } else if (mixed == MIX_VALUES32) {
         j.slotv = alloc_slot(gv_);
@@ -1699,7 +1759,7 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
             return fail(rc);
         gv_.desc_h[j.slotv].repl_factor = o.inner_tol > 0 ? o.inner_tol : 1e-3;
         PPCG_TRY(upload_desc(gv_, j.slotv));
-        PPCG_HIP(hipMemsetAsync(gv_.st_d + j.slotv, 0, sizeof(SysState), stream_));
+        clear_state(gv_, j.slotv);
         j.stage = JS_NEED_INIT;
     } else if (mixed == MIX_NONE && h->form == FORM_FUSED && h->frec && h->fmt == FMT_SELL) {
         j.fused = true;
@@ -1715,7 +1775,7 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
             return rc;
         }
         PPCG_TRY(upload_desc(gf_, j.slot64));
-        PPCG_HIP(hipMemsetAsync(gf_.st_d + j.slot64, 0, sizeof(SysState), stream_));
+        clear_state(gf_, j.slot64);
         j.stage = JS_NEED_INIT;
     } else if (mixed == MIX_NONE && h->fmt == FMT_SELL && h->n <= PPCG_SMALL_MAX_ROWS) {
         j.small = true;
@@ -1731,7 +1791,7 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
             return rc;
         }
         PPCG_TRY(upload_desc(gs_, j.slot64));
-        PPCG_HIP(hipMemsetAsync(gs_.st_d + j.slot64, 0, sizeof(SysState), stream_));
+        clear_state(gs_, j.slot64);
         j.stage = JS_NEED_INIT;
     } else {
         j.slot64 = alloc_slot(g64_);
@@ -1764,14 +1824,14 @@ ppcg_status Engine::add(ppcg_handle *h, int mixed, double tol, const double *, i
             gi.desc_h[j.slot32].pair = j.slot64;
             g64_.desc_h[j.slot64].pair = j.slot32;
             PPCG_TRY(upload_desc(gi, j.slot32));
-            PPCG_HIP(hipMemsetAsync(gi.st_d + j.slot32, 0, sizeof(SysState), stream_));
+            clear_state(gi, j.slot32);
             j.stage = JS_OUTER;
         } else {
             j.stage = JS_NEED_INIT;
         }
         PPCG_TRY(upload_desc(g64_, j.slot64));
         // A new solve starts from a clean state (iteration counters at zero).
-        PPCG_HIP(hipMemsetAsync(g64_.st_d + j.slot64, 0, sizeof(SysState), stream_));
+        clear_state(g64_, j.slot64);
     }
     jobs_.push_back(j);
     *job_id = (int)jobs_.size() - 1;
@@ -1835,6 +1895,7 @@ constexpr int kSmallChunkIters = 512;
 
 ppcg_status Engine::step(int graph_iters)
 {
+    PPCG_TRY(flush_uploads());
     // 1. Jobs that need a true residual: stopped FP64 / FP32-values jobs, and
     //    FP32-vector jobs at a pause of their sequence (after adding the correction).
     Group *const groups[] = {&g64_, &gv_, &gs_, &gp_, &gpv_, &gp32_, &gf_};
@@ -2003,6 +2064,7 @@ ppcg_status Engine::step(int graph_iters)
                 finals.push_back(g);
         }
     }
+    PPCG_TRY(flush_uploads());
     int nactive = 0;
     for (int k = 0; k < kGroups; ++k)
         nactive += !groups[k]->table_h.empty();
@@ -2172,6 +2234,83 @@ ppcg_status wait_user(ppcg_handle *h)
     return PPCG_OK;
 }
 
+// The moves of a batch's staging, all systems in one launch.
+static ppcg_status launch_stage(hipStream_t s, const BatchCtx &c, const StageItem *items_h, int off, int nitems,
+                                int64_t rows)
+{
+    if (nitems == 0)
+        return PPCG_OK;
+    PPCG_HIP(hipMemcpyAsync(c.items_d + off, items_h, sizeof(StageItem) * nitems, hipMemcpyHostToDevice, s));
+    // about 4 rows per thread on an average item; long items loop
+    const int64_t avg = rows / nitems;
+    const unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((avg + 1023) / 1024, 1), 256);
+    const unsigned gy = (unsigned)std::min(nitems, 65535);
+    k_stage_batch<<<dim3(gx, gy), 256, 0, s>>>(c.items_d + off, nitems);
+    PPCG_HIP(hipGetLastError());
+    return PPCG_OK;
+}
+
+// One batched solve on the cached engine: inputs staged (device vectors in
+// one launch, host vectors per system), all systems iterated together,
+// solutions copied out the same way.
+ppcg_status batch_run(BatchCtx &c, int count, ppcg_handle *const *hs, const double *const *b,
+                      const double *const *x0, double *const *x, ppcg_info *infos)
+{
+    hipStream_t s = hs[0]->stream;
+    Engine &E = *c.E;
+    E.reset();
+    // The previous batch on this context ended with a synchronisation, so
+    // the pinned table is free.  Regions: [0, 2 cap) inputs, [2 cap, 3 cap) outputs.
+    StageItem *in = c.items_h, *out = c.items_h + 2 * (size_t)c.cap;
+    int nin = 0, nout = 0;
+    int64_t rin = 0, rout = 0;
+    for (int i = 0; i < count; ++i) {
+        ppcg_handle *h = hs[i];
+        const double *xi0 = x0 ? x0[i] : nullptr;
+        if (h->opt.vec_mem == PPCG_MEM_HOST) {
+            hipStream_t keep = h->stream;
+            h->stream = s;
+            ppcg_status rc = stage_inputs(h, b[i], xi0);
+            h->stream = keep;
+            PPCG_TRY(rc);
+            continue;
+        }
+        h->x0_zero = xi0 == nullptr;
+        double *bi = (double *)h->f64.vec[VB], *xi = (double *)h->f64.vec[VX];
+        in[nin++] = StageItem{h->perm, b[i], bi, h->n, STAGE_GATHER};
+        in[nin++] = xi0 ? StageItem{h->perm, xi0, xi, h->n, STAGE_GATHER} : StageItem{nullptr, nullptr, xi, h->n, STAGE_ZERO};
+        rin += 2 * (int64_t)h->n;
+    }
+    PPCG_TRY(launch_stage(s, c, in, 0, nin, rin));
+    int gi = 128;
+    for (int i = 0; i < count; ++i) {
+        int id;
+        const int mixed = hs[i]->opt.precision == PPCG_MIXED_FP32 ? MIX_INNER32 : hs[i]->opt.precision == PPCG_MIXED_FP32_VALUES ? MIX_VALUES32 : MIX_NONE;
+        PPCG_TRY(E.add(hs[i], mixed, hs[i]->opt.tol, nullptr, &id));
+        gi = std::min(gi, auto_graph_iters(hs[i]));
+    }
+    PPCG_TRY(run_engine(E, std::max(gi, 16)));
+    for (int i = 0; i < count; ++i) {
+        ppcg_handle *h = hs[i];
+        if (h->opt.vec_mem == PPCG_MEM_HOST) {
+            hipStream_t keep = h->stream;
+            h->stream = s;
+            ppcg_status rc = unstage_x(h, x[i]);
+            h->stream = keep;
+            PPCG_TRY(rc);
+            continue;
+        }
+        out[nout++] = StageItem{h->perm, (const double *)h->f64.vec[VX], x[i], h->n, STAGE_SCATTER};
+        rout += h->n;
+    }
+    PPCG_TRY(launch_stage(s, c, out, 2 * c.cap, nout, rout));
+    PPCG_HIP(hipStreamSynchronize(s));
+    if (infos)
+        for (int i = 0; i < count; ++i)
+            fill_info(hs[i], E.job(i), &infos[i]);
+    return PPCG_OK;
+}
+
 ppcg_status run_engine(Engine &E, int graph_iters)
 {
     int guard = 0;
@@ -2271,6 +2410,8 @@ static void destroy_handle(ppcg_handle *h)
         (void)hipStreamSynchronize(h->stream);
     delete h->solo;
     h->solo = nullptr;
+    delete h->batch;
+    h->batch = nullptr;
     plain_free(h);
     free_matrix(h);
     if (h->dinv64)
@@ -2555,36 +2696,25 @@ ppcg_status ppcg_solve_batch(int32_t count, ppcg_handle *const *hs, const double
             PPCG_TRY(rc);
         }
     }
-    // All staging runs on the first handle's internal stream.
-    for (int i = 0; i < count; ++i) {
-        hipStream_t keep = hs[i]->stream;
-        hs[i]->stream = s;
-        ppcg_status rc = stage_inputs(hs[i], b[i], x0 ? x0[i] : nullptr);
-        hs[i]->stream = keep;
-        PPCG_TRY(rc);
+    // The first handle keeps the batch's engine and staging table for the
+    // next batch it leads (of at most as many systems).
+    if (!h0->batch || h0->batch->cap < count) {
+        delete h0->batch;
+        h0->batch = new BatchCtx;
+        BatchCtx &c = *h0->batch;
+        c.E = new Engine(s);
+        PPCG_TRY(c.E->init(count));
+        PPCG_HIP(hipMalloc(&c.items_d, sizeof(StageItem) * 3 * (size_t)count));
+        PPCG_HIP(hipHostMalloc((void **)&c.items_h, sizeof(StageItem) * 3 * (size_t)count, hipHostMallocDefault));
+        c.cap = count;  // usable only once complete
     }
-    Engine E(s);
-    PPCG_TRY(E.init(count));
-    int gi = 128;
-    for (int i = 0; i < count; ++i) {
-        int id;
-        const int mixed = hs[i]->opt.precision == PPCG_MIXED_FP32 ? MIX_INNER32 : hs[i]->opt.precision == PPCG_MIXED_FP32_VALUES ? MIX_VALUES32 : MIX_NONE;
-        PPCG_TRY(E.add(hs[i], mixed, hs[i]->opt.tol, nullptr, &id));
-        gi = std::min(gi, auto_graph_iters(hs[i]));
+    ppcg_status rc = batch_run(*h0->batch, count, hs, b, x0, x, infos);
+    if (rc < 0) {
+        // start the next batch from a fresh engine
+        delete h0->batch;
+        h0->batch = nullptr;
     }
-    PPCG_TRY(run_engine(E, std::max(gi, 16)));
-    for (int i = 0; i < count; ++i) {
-        hipStream_t keep = hs[i]->stream;
-        hs[i]->stream = s;
-        ppcg_status rc = unstage_x(hs[i], x[i]);
-        hs[i]->stream = keep;
-        PPCG_TRY(rc);
-    }
-    PPCG_HIP(hipStreamSynchronize(s));
-    if (infos)
-        for (int i = 0; i < count; ++i)
-            fill_info(hs[i], E.job(i), &infos[i]);
-    return PPCG_OK;
+    return rc;
 }
 
 ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
