@@ -136,9 +136,10 @@ def leg_c2(args, torch, ppcg, wl, oracle):
         for _ in range(reps):
             sync()
             t = time.perf_counter()
-            S.solve(bd, out=x)
+            _, inf = S.solve(bd, out=x)
             sync()
             ts.append(time.perf_counter() - t)
+            assert inf["iters"] == k, inf  # no early stop (breakdown past convergence)
         return min(ts)
 
     k1, k2 = 20, 520

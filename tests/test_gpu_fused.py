@@ -58,6 +58,10 @@ CASES = {
     "random_spd_30001_sorted": (lambda: random_spd(30001, seed=5), (5, 30), {}),
     "poisson125_12_vtab": (lambda: poisson125(12), (5, 15), {"flags": ppcg.FLAG_SELL_VALUE_TABLE}),
     "tile_and_68_rows": (lambda: shifted(poisson2d(46), 0.1), (1, 7, 30), {}),  # 2,116 rows: 4 tiles + 68
+    # 360,000 rows: 3 rows per thread (1,536-row tiles), 234 tiles + 576 rows
+    "poisson2d_600_three_rows": (lambda: poisson2d(600), (4, 45), {}),
+    # 200,000 rows: 2 rows per thread (1,024-row tiles), 195 tiles + 320 rows
+    "random_spd_200000_two_rows": (lambda: random_spd(200000, seed=7), (6,), {}),
 }
 
 
