@@ -84,9 +84,9 @@ def sync():
 
 # The 128^3 storage the autotuner picks in plain runs, pinned so that the
 # counter runs (kernels serialized, where timing-based choices can flip)
-# measure the kernels timed here: SELL, 32-bit columns, 8-byte values, and the
-# single-launch iteration.
-C2_FLAGS_NAMES = ("FLAG_SELL_COL32", "FLAG_SELL_FULL_VALUES", "FLAG_ITER_FUSED")
+# measure the kernels timed here: SELL, 16-bit column offsets, the one-byte
+# table of the matrix's distinct values, and the single-launch iteration.
+C2_FLAGS_NAMES = ("FLAG_SELL_COL16", "FLAG_SELL_VALUE_TABLE", "FLAG_ITER_FUSED")
 
 
 def survey_bytes_per_iter(n, nnz, fused):

@@ -497,6 +497,102 @@ __device__ __forceinline__ void sell_extent(const int64_t *__restrict__ cptr, in
     len = (int)((as_global(cptr)[c + 1] - base) / kSellC);
 }
 
+// Entries k0 .. k0 + L - 1 of one SELL row, L fixed at compile time: the
+// column and value loads of all L entries are issued back to back, with no
+// branch between them, then the L gathers, then the L products are added in
+// entry order.  (Guarding each entry by the row length instead puts every
+// load in a basic block of its own, and the compiler then waits after each
+// one-byte value index or 16-bit column before issuing the next entry.)
+// C16: columns as 16-bit offsets from the row, entries 2t and 2t + 1 in one
+// dword (pair t at cp[t * 64]); a chunk of odd padded length keeps its last
+// entry as one short at `odd`.
+template <int L, bool C16, bool VI, typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_span(const PPCG_AS1 int *c, const PPCG_AS1 unsigned *cp,
+                                          const PPCG_AS1 short *odd, const PPCG_AS1 VT *v,
+                                          const PPCG_AS1 unsigned char *vi, const double *tab,
+                                          const PPCG_AS1 T *const (&xg)[NX], int k0, int row, T (&acc)[NX])
+{
+    int cc[L];
+    VT vv[L];
+    if constexpr (C16) {
+#pragma unroll
+        for (int t = 0; t < L / 2; ++t) {
+            const unsigned pr = stream_load(cp + (size_t)((k0 >> 1) + t) * kSellC);
+            cc[2 * t] = row + (int)(short)(pr & 0xffffu);
+            cc[2 * t + 1] = row + ((int)pr >> 16);
+        }
+        if constexpr ((L & 1) != 0)
+            cc[L - 1] = row + (int)stream_load(odd);
+    } else {
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        vv[j] = sell_value<VI>(v, vi, tab, (size_t)(k0 + j) * kSellC);
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+        T xx[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            xx[j] = xg[q][cc[j]];
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            acc[q] = acc[q] + (T)vv[j] * xx[j];
+    }
+}
+
+// The last len - k0 (< M + 1) entries of a row: one uniform compare per
+// candidate length, then a straight span of exactly that length.
+template <int M, bool C16, bool VI, typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_tail(int rem, const PPCG_AS1 int *c, const PPCG_AS1 unsigned *cp,
+                                          const PPCG_AS1 short *odd, const PPCG_AS1 VT *v,
+                                          const PPCG_AS1 unsigned char *vi, const double *tab,
+                                          const PPCG_AS1 T *const (&xg)[NX], int k0, int row, T (&acc)[NX])
+{
+    if constexpr (M > 0) {
+        if (rem == M)
+            sell_span<M, C16, VI>(c, cp, odd, v, vi, tab, xg, k0, row, acc);
+        else
+            sell_tail<M - 1, C16, VI>(rem, c, cp, odd, v, vi, tab, xg, k0, row, acc);
+    }
+}
+
+// One SELL row (n = A x for NX vectors x): full spans of PPCG_SELL_BATCH
+// entries, then the remainder as one span of its exact length.  The row
+// length is the same in every lane of the wavefront, so every branch here is
+// uniform.  Same products, added in the same (stored) order, as the guarded
+// batch loop below.
+template <bool C16, bool VI, typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_row_straight(const int64_t *__restrict__ cptr, const int *__restrict__ col,
+                                                  const short *__restrict__ col16, const VT *__restrict__ val,
+                                                  const T *const (&xin)[NX], int chunk, int lane, T (&acc)[NX],
+                                                  const unsigned char *__restrict__ vidx, const double *tab)
+{
+    constexpr int B = PPCG_SELL_BATCH;
+    static_assert(B % 2 == 0, "spans of the 16-bit layout hold whole pairs");
+    int64_t base;
+    int len;
+    sell_extent(cptr, chunk, base, len);
+    const int row = chunk * kSellC + lane;
+    const PPCG_AS1 int *c = C16 ? nullptr : as_global(col + base + lane);
+    const PPCG_AS1 unsigned *cp = C16 ? as_global((const unsigned *)(col16 + base) + lane) : nullptr;
+    const PPCG_AS1 short *odd = C16 ? as_global(col16 + base + (size_t)(len & ~1) * kSellC + lane) : nullptr;
+    const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
+    const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
+    const PPCG_AS1 T *xg[NX];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+        acc[q] = (T)0;
+        xg[q] = as_global(xin[q]);
+    }
+    int k0 = 0;
+    for (; k0 + B <= len; k0 += B)
+        sell_span<B, C16, VI>(c, cp, odd, v, vi, tab, xg, k0, row, acc);
+    sell_tail<B - 1, C16, VI>(len - k0, c, cp, odd, v, vi, tab, xg, k0, row, acc);
+}
+
 // SELL-C-sigma, C = 64, one lane per row: entry k of the row (chunk c, lane
 // l) is at cptr[c] + k * 64 + l.  NX input vectors share one pass over the
 // matrix (NX = 2 for the replacement steps).  Entries are handled in
@@ -511,6 +607,12 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
                                          int lane, T (&acc)[NX], const unsigned char *__restrict__ vidx = nullptr,
                                          const double *tab = nullptr)
 {
+#if PPCG_SELL_STRAIGHT
+    // (32-bit columns with 8-byte values measured 2-3 % faster in the guarded
+    // loop below: their loads already issue back to back there)
+    if constexpr (VI)
+        return sell_row_straight<false, VI, VT, T, NX>(cptr, col, nullptr, val, xin, chunk, lane, acc, vidx, tab);
+#endif
     constexpr int B = PPCG_SELL_BATCH;
     int64_t base;
     int len;
@@ -587,6 +689,9 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
                                            int lane, T (&acc)[NX], const unsigned char *__restrict__ vidx = nullptr,
                                            const double *tab = nullptr)
 {
+#if PPCG_SELL_STRAIGHT
+    return sell_row_straight<true, VI, VT, T, NX>(cptr, nullptr, col16, val, xin, chunk, lane, acc, vidx, tab);
+#endif
     constexpr int B = PPCG_SELL_BATCH;
     int64_t base;
     int len;
@@ -635,6 +740,9 @@ __device__ __forceinline__ void sell_row16_pipe(const int64_t *__restrict__ cptr
                                                 const unsigned char *__restrict__ vidx = nullptr,
                                                 const double *tab = nullptr)
 {
+#if PPCG_SELL_STRAIGHT
+    return sell_row_straight<true, VI, VT, T, NX>(cptr, nullptr, col16, val, xin, chunk, lane, acc, vidx, tab);
+#endif
     constexpr int B = PPCG_SELL_PIPE_BATCH;  // two batches in flight: smaller than the plain batch
     int64_t base;
     int len;

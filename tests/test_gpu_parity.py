@@ -256,10 +256,13 @@ def c2():
     return A, b
 
 
-# the storage and iteration form bench.py pins for this matrix, the same
-# storage with two launches per iteration, and the autotuner's own choice
-C2_STORAGE = {"bench": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES |
+# the storage and iteration form bench.py pins for this matrix (16-bit
+# columns, one-byte value table, one launch per iteration), 32-bit columns
+# with 8-byte values in both iteration forms, and the autotuner's own choice
+C2_STORAGE = {"bench": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL16 | ppcg.FLAG_SELL_VALUE_TABLE |
                             ppcg.FLAG_ITER_FUSED),
+              "full_values_fused": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES |
+                                        ppcg.FLAG_ITER_FUSED),
               "two_launch": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES |
                                  ppcg.FLAG_ITER_TWO_LAUNCH),
               "auto": {}}
