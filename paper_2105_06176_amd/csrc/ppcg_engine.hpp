@@ -131,12 +131,12 @@ struct ppcg_handle {
     int *plain_cnt = nullptr;
     // Iteration form of FP64 PIPECG (IterForm): two launches per iteration or
     // the single-launch form, chosen at create time; the single-launch form's
-    // buffers (state and partial-sum slots, second m buffer).
+    // buffers (state and partial-sum slots, second w buffer).
     int form = 0;
     bool x0_zero = false;  // the last staged initial guess was zero (no x0 given)
     ppcg::SysState *frec = nullptr;
     double *fpart = nullptr;
-    double *m1 = nullptr;
+    double *w1 = nullptr;
     ppcg::DevArena fused_arena;
 };
 

@@ -13,32 +13,34 @@
 //      bit-identical scalars, with no grid-wide synchronisation;
 //   2. for each of its rows (SELL-64, one lane per row, up to
 //      kFusedRowsPerThread rows per thread) computes n = A m_i into a
-//      register and applies the
-//      fused vector updates of Section V-B with it, forming
-//      m_{i+1} = M^-1 w_{i+1};
+//      register and applies the fused vector updates of Section V-B with
+//      it.  With a constant diagonal m_i = M^-1 w_i is not stored: the SpMV
+//      gathers w_i and forms each m_i[col] = dinv[0] * w_i[col] itself, the
+//      same rounded product the update would have stored;
 //   3. writes its own partial sums.
 //
 // The kernel boundary is the only synchronisation.  Everything another
 // workgroup of the same launch may still read is double buffered by the
-// launch's parity `par`: m (read by the SpMV gathers of every tile), the
-// partial sums and the scalar state record.  Launch j of a captured chunk
-// has par = j & 1 and chunks have an even number of launches, so a running
-// system always starts a chunk with m in buffer 0 (the handle's m vector)
+// launch's parity `par`: what the SpMV gathers of every tile read (w, or m
+// for a diagonal that is not constant), the partial sums and the scalar
+// state record.  Launch j of a captured chunk has par = j & 1 and chunks
+// have an even number of launches, so a running system always starts a
+// chunk with that vector in buffer 0 (the handle's own w or m vector)
 // and its latest partials and state in slot 0; k_fused_begin, the first
 // node of every chunk, copies the canonical state record into slot 0 and,
 // right after an initialisation, folds the initialisation's 512-row
 // partials into the fused tiles' partials.
 //
-// Per iteration this saves the n round trip (16 bytes per row) and one
-// launch.  The cost is the partial-sum reduction every workgroup repeats:
-// 32 bytes per tile, read from the L2 (1,024 tiles at 2^21 rows: 32 KB per
-// workgroup).
+// Per iteration this saves the n round trip (16 bytes per row), with a
+// constant diagonal the m write (8 bytes per row), and one launch.  The cost
+// is the partial-sum reduction every workgroup repeats: 32 bytes per tile,
+// read from the L2 (1,024 tiles at 2^21 rows: 32 KB per workgroup).
 //
 // The arithmetic of one row is that of the two-launch form (same SpMV order,
-// same update formulas, x-updates paired in the same way); only the
-// association of the dot products differs (over the fused tiles), so results are
-// deterministic, identical alone and batched, but not bitwise equal to the
-// two-launch form.
+// same products, same update formulas, x-updates paired in the same way);
+// only the association of the dot products differs (over the fused tiles),
+// so results are deterministic, identical alone and batched, but not bitwise
+// equal to the two-launch form.
 #pragma once
 
 #include "ppcg_kernels.hpp"
@@ -61,33 +63,52 @@ struct FusedScalars {
     int go, x_pending, x_finish;
 };
 
-// SpMV of one SELL chunk row (n = A m) with the handle's storage variant.
-__device__ __forceinline__ double fused_row(const SysDesc &d, const double *min, int chunk, int lane,
-                                            const double *tab)
+// SpMV of one SELL chunk row with the handle's storage variant.  SC = 1: on
+// m formed from w on the fly, n_row = sum over the row's entries of
+// a * (d0 * w[col]), each d0 * w[col] the same rounded product the update
+// forms for m (a constant diagonal, d0 = dinv[0]); SC = 0: on m as stored.
+template <int SC>
+__device__ __forceinline__ double fused_row_sc(const SysDesc &d, const double *win, int chunk, int lane,
+                                               const double *tab, const double *dg, double d0)
 {
-    const double *xin[1] = {min};
+    const double *xin[1] = {win};
     double y[1];
     const double *val = (const double *)d.val;
     if (tab) {
         if (d.col16)
 #if PPCG_SELL_PIPE
-            sell_row16_pipe<double, double, 1, true>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab);
+            sell_row16_pipe<double, double, 1, true, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab, dg,
+                                                         d0);
 #else
-            sell_row16<double, double, 1, true>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab);
+            sell_row16<double, double, 1, true, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab, dg, d0);
 #endif
         else
-            sell_row<double, double, 1, true>(d.cptr, d.col, val, xin, chunk, lane, y, d.vidx, tab);
+            sell_row<double, double, 1, true, SC>(d.cptr, d.col, val, xin, chunk, lane, y, d.vidx, tab, dg, d0);
     } else {
         if (d.col16)
 #if PPCG_SELL_PIPE
-            sell_row16_pipe<double, double, 1>(d.cptr, d.col16, val, xin, chunk, lane, y);
+            sell_row16_pipe<double, double, 1, false, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, nullptr, nullptr,
+                                                          dg, d0);
 #else
-            sell_row16<double, double, 1>(d.cptr, d.col16, val, xin, chunk, lane, y);
+            sell_row16<double, double, 1, false, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, nullptr, nullptr, dg,
+                                                     d0);
 #endif
         else
-            sell_row<double, double, 1>(d.cptr, d.col, val, xin, chunk, lane, y);
+            sell_row<double, double, 1, false, SC>(d.cptr, d.col, val, xin, chunk, lane, y, nullptr, nullptr, dg, d0);
     }
     return y[0];
+}
+
+// Systems whose diagonal is constant gather w and scale it (m is never
+// stored); others gather the stored m.  (Gathering dinv next to w for a
+// general diagonal needs 14 more VGPRs in this kernel: 88 against 74, one
+// wavefront per SIMD fewer for every system.)
+__device__ __forceinline__ double fused_row(const SysDesc &d, const double *gin, int chunk, int lane,
+                                            const double *tab)
+{
+    if (d.dinv_const)
+        return fused_row_sc<1>(d, gin, chunk, lane, tab, nullptr, ((const double *)d.dinv)[0]);
+    return fused_row_sc<0>(d, gin, chunk, lane, tab, nullptr, 0.0);
 }
 
 __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const WorkItem *__restrict__ table,
@@ -117,8 +138,13 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
         return;
     }
     const int n = d.n;
-    const double *min = (const double *)(par ? d.m1 : d.m);
-    double *mout = (double *)(par ? d.m : d.m1);
+    // What the gathers read, double buffered by parity in the handle's m or
+    // w vector and the second buffer: w (constant diagonal: m is formed in
+    // the gathers and never stored) or m.
+    const bool wg = d.dinv_const != 0;
+    double *const v0 = (double *)(wg ? d.w : d.m), *const v1 = (double *)d.w1;
+    const double *gin = par ? v1 : v0;
+    double *gout = par ? v0 : v1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int row0 = wi.tile * d.frows;
     const double *tab = nullptr;
@@ -185,8 +211,10 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     const bool xp = sc.x_pending != 0;
     PPCG_AS1 double *__restrict__ X = as_global((double *)d.x);
     PPCG_AS1 double *__restrict__ Rv = as_global((double *)d.r);
-    PPCG_AS1 double *__restrict__ W = as_global((double *)d.w);
-    PPCG_AS1 double *__restrict__ M = as_global(mout);
+    // w is read and written in place when it is not what the gathers read
+    const PPCG_AS1 double *__restrict__ W = as_global(wg ? gin : (const double *)d.w);
+    PPCG_AS1 double *__restrict__ Wo = as_global(wg ? gout : (double *)d.w);
+    PPCG_AS1 double *__restrict__ M = as_global(gout);
     PPCG_AS1 double *__restrict__ Z = as_global((double *)d.z);
     PPCG_AS1 double *__restrict__ S = as_global((double *)d.s);
     PPCG_AS1 double *__restrict__ P = as_global((double *)d.p);
@@ -198,7 +226,7 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
         if (chunk * kSellC >= n)
             break;  // uniform per wavefront: no later chunk of this thread exists either
         const int i = chunk * kSellC + lane;
-        const double nv = fused_row(d, min, chunk, lane, tab);
+        const double nv = fused_row(d, gin, chunk, lane, tab);
         if (i < n) {
             double z = Z[i], w = W[i], s = S[i], p = P[i], r = Rv[i], u, mo;
             const double di = DI[d.dinv_const ? 0 : i];
@@ -209,8 +237,9 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
             S[i] = s;
             P[i] = p;
             Rv[i] = r;
-            W[i] = w;
-            M[i] = mo;
+            Wo[i] = w;
+            if (!wg)
+                M[i] = mo;  // otherwise m_{i+1} = M^-1 w_{i+1} is formed by the next launch's gathers
             if (xp) {
                 const double x1 = xo + ax * pold;
                 X[i] = x1 + sa * p;

@@ -497,6 +497,22 @@ __device__ __forceinline__ void sell_extent(const int64_t *__restrict__ cptr, in
     len = (int)((as_global(cptr)[c + 1] - base) / kSellC);
 }
 
+// One SpMV input entry x[col].  SC = 1, 2: the input is the preconditioned
+// vector m = M^-1 w formed on the fly from w, m[col] = dinv[col] * w[col]
+// with the same rounded product the update uses to form m (SC = 1: every
+// diagonal entry equal, d0; SC = 2: dinv gathered at dg[col]), so the
+// single-launch iteration need not store m.
+template <int SC, typename T>
+__device__ __forceinline__ T sell_in(const PPCG_AS1 T *x, int col, const double *dg, double d0)
+{
+    if constexpr (SC == 1)
+        return (T)d0 * x[col];
+    else if constexpr (SC == 2)
+        return (T)as_global(dg)[col] * x[col];
+    else
+        return x[col];
+}
+
 // Entries k0 .. k0 + L - 1 of one SELL row, L fixed at compile time: the
 // column and value loads of all L entries are issued back to back, with no
 // branch between them, then the L gathers, then the L products are added in
@@ -506,11 +522,12 @@ __device__ __forceinline__ void sell_extent(const int64_t *__restrict__ cptr, in
 // C16: columns as 16-bit offsets from the row, entries 2t and 2t + 1 in one
 // dword (pair t at cp[t * 64]); a chunk of odd padded length keeps its last
 // entry as one short at `odd`.
-template <int L, bool C16, bool VI, typename VT, typename T, int NX>
+template <int L, bool C16, bool VI, int SC, typename VT, typename T, int NX>
 __device__ __forceinline__ void sell_span(const PPCG_AS1 int *c, const PPCG_AS1 unsigned *cp,
                                           const PPCG_AS1 short *odd, const PPCG_AS1 VT *v,
                                           const PPCG_AS1 unsigned char *vi, const double *tab,
-                                          const PPCG_AS1 T *const (&xg)[NX], int k0, int row, T (&acc)[NX])
+                                          const PPCG_AS1 T *const (&xg)[NX], int k0, int row, T (&acc)[NX],
+                                          const double *dg, double d0)
 {
     int cc[L];
     VT vv[L];
@@ -536,7 +553,7 @@ __device__ __forceinline__ void sell_span(const PPCG_AS1 int *c, const PPCG_AS1 
         T xx[L];
 #pragma unroll
         for (int j = 0; j < L; ++j)
-            xx[j] = xg[q][cc[j]];
+            xx[j] = sell_in<SC>(xg[q], cc[j], dg, d0);
 #pragma unroll
         for (int j = 0; j < L; ++j)
             acc[q] = acc[q] + (T)vv[j] * xx[j];
@@ -545,17 +562,18 @@ __device__ __forceinline__ void sell_span(const PPCG_AS1 int *c, const PPCG_AS1 
 
 // The last len - k0 (< M + 1) entries of a row: one uniform compare per
 // candidate length, then a straight span of exactly that length.
-template <int M, bool C16, bool VI, typename VT, typename T, int NX>
+template <int M, bool C16, bool VI, int SC, typename VT, typename T, int NX>
 __device__ __forceinline__ void sell_tail(int rem, const PPCG_AS1 int *c, const PPCG_AS1 unsigned *cp,
                                           const PPCG_AS1 short *odd, const PPCG_AS1 VT *v,
                                           const PPCG_AS1 unsigned char *vi, const double *tab,
-                                          const PPCG_AS1 T *const (&xg)[NX], int k0, int row, T (&acc)[NX])
+                                          const PPCG_AS1 T *const (&xg)[NX], int k0, int row, T (&acc)[NX],
+                                          const double *dg, double d0)
 {
     if constexpr (M > 0) {
         if (rem == M)
-            sell_span<M, C16, VI>(c, cp, odd, v, vi, tab, xg, k0, row, acc);
+            sell_span<M, C16, VI, SC>(c, cp, odd, v, vi, tab, xg, k0, row, acc, dg, d0);
         else
-            sell_tail<M - 1, C16, VI>(rem, c, cp, odd, v, vi, tab, xg, k0, row, acc);
+            sell_tail<M - 1, C16, VI, SC>(rem, c, cp, odd, v, vi, tab, xg, k0, row, acc, dg, d0);
     }
 }
 
@@ -564,11 +582,12 @@ __device__ __forceinline__ void sell_tail(int rem, const PPCG_AS1 int *c, const 
 // length is the same in every lane of the wavefront, so every branch here is
 // uniform.  Same products, added in the same (stored) order, as the guarded
 // batch loop below.
-template <bool C16, bool VI, typename VT, typename T, int NX>
+template <bool C16, bool VI, int SC, typename VT, typename T, int NX>
 __device__ __forceinline__ void sell_row_straight(const int64_t *__restrict__ cptr, const int *__restrict__ col,
                                                   const short *__restrict__ col16, const VT *__restrict__ val,
                                                   const T *const (&xin)[NX], int chunk, int lane, T (&acc)[NX],
-                                                  const unsigned char *__restrict__ vidx, const double *tab)
+                                                  const unsigned char *__restrict__ vidx, const double *tab,
+                                                  const double *dg, double d0)
 {
     constexpr int B = PPCG_SELL_BATCH;
     static_assert(B % 2 == 0, "spans of the 16-bit layout hold whole pairs");
@@ -589,8 +608,8 @@ __device__ __forceinline__ void sell_row_straight(const int64_t *__restrict__ cp
     }
     int k0 = 0;
     for (; k0 + B <= len; k0 += B)
-        sell_span<B, C16, VI>(c, cp, odd, v, vi, tab, xg, k0, row, acc);
-    sell_tail<B - 1, C16, VI>(len - k0, c, cp, odd, v, vi, tab, xg, k0, row, acc);
+        sell_span<B, C16, VI, SC>(c, cp, odd, v, vi, tab, xg, k0, row, acc, dg, d0);
+    sell_tail<B - 1, C16, VI, SC>(len - k0, c, cp, odd, v, vi, tab, xg, k0, row, acc, dg, d0);
 }
 
 // SELL-C-sigma, C = 64, one lane per row: entry k of the row (chunk c, lane
@@ -601,17 +620,18 @@ __device__ __forceinline__ void sell_row_straight(const int64_t *__restrict__ cp
 // in flight; the products of every row are still added in stored
 // (ascending original column) order.  VT is the value type, T the vector
 // and accumulation type.
-template <typename VT, typename T, int NX, bool VI = false>
+template <typename VT, typename T, int NX, bool VI = false, int SC = 0>
 __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const int *__restrict__ col,
                                          const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
                                          int lane, T (&acc)[NX], const unsigned char *__restrict__ vidx = nullptr,
-                                         const double *tab = nullptr)
+                                         const double *tab = nullptr, const double *dg = nullptr, double d0 = 0.0)
 {
 #if PPCG_SELL_STRAIGHT
     // (32-bit columns with 8-byte values measured 2-3 % faster in the guarded
     // loop below: their loads already issue back to back there)
-    if constexpr (VI)
-        return sell_row_straight<false, VI, VT, T, NX>(cptr, col, nullptr, val, xin, chunk, lane, acc, vidx, tab);
+    if constexpr (VI || (SC != 0 && PPCG_SELL_STRAIGHT_SC))
+        return sell_row_straight<false, VI, SC, VT, T, NX>(cptr, col, nullptr, val, xin, chunk, lane, acc, vidx, tab,
+                                                           dg, d0);
 #endif
     constexpr int B = PPCG_SELL_BATCH;
     int64_t base;
@@ -645,7 +665,7 @@ __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const
             T xx[B];
 #pragma unroll
             for (int j = 0; j < B; ++j)
-                xx[j] = k0 + j < len ? xg[q][cc[j]] : (T)0;
+                xx[j] = k0 + j < len ? sell_in<SC>(xg[q], cc[j], dg, d0) : (T)0;
 #pragma unroll
             for (int j = 0; j < B; ++j)
                 if (k0 + j < len)
@@ -683,14 +703,15 @@ __device__ __forceinline__ void sell_cols16(const short *__restrict__ col16, int
 }
 
 // sell_row with 16-bit column offsets from the row.
-template <typename VT, typename T, int NX, bool VI = false>
+template <typename VT, typename T, int NX, bool VI = false, int SC = 0>
 __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, const short *__restrict__ col16,
                                            const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
                                            int lane, T (&acc)[NX], const unsigned char *__restrict__ vidx = nullptr,
-                                           const double *tab = nullptr)
+                                           const double *tab = nullptr, const double *dg = nullptr, double d0 = 0.0)
 {
 #if PPCG_SELL_STRAIGHT
-    return sell_row_straight<true, VI, VT, T, NX>(cptr, nullptr, col16, val, xin, chunk, lane, acc, vidx, tab);
+    return sell_row_straight<true, VI, SC, VT, T, NX>(cptr, nullptr, col16, val, xin, chunk, lane, acc, vidx, tab,
+                                                      dg, d0);
 #endif
     constexpr int B = PPCG_SELL_BATCH;
     int64_t base;
@@ -720,7 +741,7 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
             T xx[B];
 #pragma unroll
             for (int j = 0; j < B; ++j)
-                xx[j] = k0 + j < len ? xg[q][cc[j]] : (T)0;
+                xx[j] = k0 + j < len ? sell_in<SC>(xg[q], cc[j], dg, d0) : (T)0;
 #pragma unroll
             for (int j = 0; j < B; ++j)
                 if (k0 + j < len)
@@ -733,15 +754,17 @@ __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, con
 // issued before the column and value loads of batch k + 1, so the wait for
 // the gathers leaves the next batch's loads in flight.  Same products, same
 // order of the sums.
-template <typename VT, typename T, int NX, bool VI = false>
+template <typename VT, typename T, int NX, bool VI = false, int SC = 0>
 __device__ __forceinline__ void sell_row16_pipe(const int64_t *__restrict__ cptr, const short *__restrict__ col16,
                                                 const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
                                                 int lane, T (&acc)[NX],
                                                 const unsigned char *__restrict__ vidx = nullptr,
-                                                const double *tab = nullptr)
+                                                const double *tab = nullptr, const double *dg = nullptr,
+                                                double d0 = 0.0)
 {
 #if PPCG_SELL_STRAIGHT
-    return sell_row_straight<true, VI, VT, T, NX>(cptr, nullptr, col16, val, xin, chunk, lane, acc, vidx, tab);
+    return sell_row_straight<true, VI, SC, VT, T, NX>(cptr, nullptr, col16, val, xin, chunk, lane, acc, vidx, tab,
+                                                      dg, d0);
 #endif
     constexpr int B = PPCG_SELL_PIPE_BATCH;  // two batches in flight: smaller than the plain batch
     int64_t base;
@@ -775,7 +798,7 @@ __device__ __forceinline__ void sell_row16_pipe(const int64_t *__restrict__ cptr
         for (int q = 0; q < NX; ++q)
 #pragma unroll
             for (int j = 0; j < B; ++j)
-                xx[q][j] = k0 + j < len ? xg[q][cc[j]] : (T)0;
+                xx[q][j] = k0 + j < len ? sell_in<SC>(xg[q], cc[j], dg, d0) : (T)0;
         int cn[B];
         VT vn[B];
         if (k0 + B < len)

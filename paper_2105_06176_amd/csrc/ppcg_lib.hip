@@ -163,10 +163,12 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     // classic-PCG SpMV with FP32 values and FP64 vectors)
     const double ie = (h->col16 && !(pcg && prec == PREC_V32)) ? 2.0 : 4.0;
     bm.spmv = (me + ie) * (double)h->nnz + ptr + (pcg ? 4.0 : 2.0) * ve * n;
-    // the single-launch form keeps n in registers: neither written by the
-    // SpMV nor read by the update
+    // the single-launch form keeps n in registers (neither written by the
+    // SpMV nor read by the update) and, with a constant diagonal, forms
+    // m = M^-1 w in the next launch's gathers instead of writing it (the
+    // gathers read w in place of m)
     if (h->form == FORM_FUSED && prec == PREC_F64 && !pcg) {
-        bm.vma -= ve * n;
+        bm.vma -= (h->dinv_const ? 2.0 : 1.0) * ve * n;
         bm.spmv -= ve * n;
     }
     return bm;
@@ -339,7 +341,7 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->nftiles = (h->n + d->frows - 1) / d->frows;
     d->frec = h->frec;
     d->fpart = h->fpart;
-    d->m1 = h->m1;
+    d->w1 = h->w1;
     return PPCG_OK;
 }
 
@@ -358,7 +360,7 @@ ppcg_status ensure_fused(ppcg_handle *h)
     PPCG_TRY(h->fused_arena.alloc(2 * sizeof(SysState) + pb + vb + 3 * 256));
     h->frec = (SysState *)h->fused_arena.take(2 * sizeof(SysState));
     h->fpart = (double *)h->fused_arena.take(pb);
-    h->m1 = (double *)h->fused_arena.take(vb);
+    h->w1 = (double *)h->fused_arena.take(vb);
     return PPCG_OK;
 }
 
@@ -853,7 +855,7 @@ static void drop_fused(ppcg_handle *h)
     h->fused_arena.release();
     h->frec = nullptr;
     h->fpart = nullptr;
-    h->m1 = nullptr;
+    h->w1 = nullptr;
 }
 
 // Choose the iteration form of FP64 PIPECG for the stored matrix (SELL only):
