@@ -176,6 +176,20 @@ def leg_c2(args, torch, ppcg, wl, oracle):
             "traffic_source": "profiles/traffic.json (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE of this kernel "
                               "source)" if traffic else None,
             "kernel": kname, "bytes_per_launch": bytes_dom, "avg_launch_us": round(ms_dom * 1e3, 3), **other}
+    if fused:
+        # The same kernel on the byte-heavy storage (8-byte values, 32-bit
+        # columns; slower, more bytes): the fraction of the HBM peak the
+        # iteration reaches when bytes rather than latency bound it.
+        F = ppcg.Solver(A, fixed_iters=K, spmv_format="sell",
+                        flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES | ppcg.FLAG_ITER_FUSED)
+        mf = F.matrix_info()
+        msf, _ = F.time_kernels(bd, iters=100)
+        F.close()
+        af = mf["bytes_per_iter"] / (msf * 1e-3) / 1e9
+        roof["same_kernel_8byte_values_32bit_columns"] = {
+            "bytes_per_launch": mf["bytes_per_iter"], "avg_launch_us": round(msf * 1e3, 3),
+            "achieved": round(af, 1), "frac": round(af / PEAK_HBM_GBS, 4)}
+        log(f"k_fused with 8-byte values: {msf * 1e3:.2f} us, {af:.0f} GB/s")
     # tolerance run (after the fixed iterations; untimed in the main value)
     S.set_options(tol=1e-10, max_iter=10000)
     S.solve(bd)

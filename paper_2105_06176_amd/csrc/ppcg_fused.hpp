@@ -58,6 +58,14 @@ namespace ppcg {
 #define PPCG_FUSED_REMAP 1
 #endif
 
+// The 64-bit value that lane j holds, in scalar registers (j uniform).
+__device__ __forceinline__ int64_t lane_i64(int64_t v, int j)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(uint64_t)v, j);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((uint64_t)v >> 32), j);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 struct FusedScalars {
     double alpha, beta, alpha_x;
     int go, x_pending, x_finish;
@@ -69,7 +77,7 @@ struct FusedScalars {
 // forms for m (a constant diagonal, d0 = dinv[0]); SC = 0: on m as stored.
 template <int SC>
 __device__ __forceinline__ double fused_row_sc(const SysDesc &d, const double *win, int chunk, int lane,
-                                               const double *tab, const double *dg, double d0)
+                                               const double *tab, const double *dg, double d0, int64_t eb, int el)
 {
     const double *xin[1] = {win};
     double y[1];
@@ -78,23 +86,26 @@ __device__ __forceinline__ double fused_row_sc(const SysDesc &d, const double *w
         if (d.col16)
 #if PPCG_SELL_PIPE
             sell_row16_pipe<double, double, 1, true, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab, dg,
-                                                         d0);
+                                                         d0, eb, el);
 #else
-            sell_row16<double, double, 1, true, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab, dg, d0);
+            sell_row16<double, double, 1, true, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab, dg, d0,
+                                                    eb, el);
 #endif
         else
-            sell_row<double, double, 1, true, SC>(d.cptr, d.col, val, xin, chunk, lane, y, d.vidx, tab, dg, d0);
+            sell_row<double, double, 1, true, SC>(d.cptr, d.col, val, xin, chunk, lane, y, d.vidx, tab, dg, d0, eb,
+                                                  el);
     } else {
         if (d.col16)
 #if PPCG_SELL_PIPE
             sell_row16_pipe<double, double, 1, false, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, nullptr, nullptr,
-                                                          dg, d0);
+                                                          dg, d0, eb, el);
 #else
             sell_row16<double, double, 1, false, SC>(d.cptr, d.col16, val, xin, chunk, lane, y, nullptr, nullptr, dg,
-                                                     d0);
+                                                     d0, eb, el);
 #endif
         else
-            sell_row<double, double, 1, false, SC>(d.cptr, d.col, val, xin, chunk, lane, y, nullptr, nullptr, dg, d0);
+            sell_row<double, double, 1, false, SC>(d.cptr, d.col, val, xin, chunk, lane, y, nullptr, nullptr, dg, d0,
+                                                   eb, el);
     }
     return y[0];
 }
@@ -102,13 +113,14 @@ __device__ __forceinline__ double fused_row_sc(const SysDesc &d, const double *w
 // Systems whose diagonal is constant gather w and scale it (m is never
 // stored); others gather the stored m.  (Gathering dinv next to w for a
 // general diagonal needs 14 more VGPRs in this kernel: 88 against 74, one
-// wavefront per SIMD fewer for every system.)
+// wavefront per SIMD fewer for every system.)  eb, el: the chunk's first
+// stored slot and padded length.
 __device__ __forceinline__ double fused_row(const SysDesc &d, const double *gin, int chunk, int lane,
-                                            const double *tab)
+                                            const double *tab, int64_t eb, int el)
 {
     if (d.dinv_const)
-        return fused_row_sc<1>(d, gin, chunk, lane, tab, nullptr, ((const double *)d.dinv)[0]);
-    return fused_row_sc<0>(d, gin, chunk, lane, tab, nullptr, 0.0);
+        return fused_row_sc<1>(d, gin, chunk, lane, tab, nullptr, ((const double *)d.dinv)[0], eb, el);
+    return fused_row_sc<0>(d, gin, chunk, lane, tab, nullptr, 0.0, eb, el);
 }
 
 __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const WorkItem *__restrict__ table,
@@ -127,6 +139,41 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     const SysDesc &d = descs[wi.slot];
     const int R = d.frows / kFusedThreads;  // rows per thread, 1 .. kFusedRowsPerThread
     const SysState *rin = d.frec + par;
+    const int n = d.n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row0 = wi.tile * d.frows;
+    // Loads that need only the descriptor are issued before the stop check,
+    // so that their latencies overlap instead of following one another:
+    // the extents of this wavefront's chunks (row k of a thread lies in chunk
+    // c0 + k * kFusedThreads / 64: lane j < 2R holds cptr[c0 + (j >> 1) * 8 +
+    // (j & 1)]), this thread's first two partial-sum records, and its entry
+    // of the value table.
+    int64_t ext = 0;
+    {
+        const int c0 = row0 / kSellC + wave;
+        const int j = lane >> 1, e = lane & 1;
+        const int c = c0 + j * (kFusedThreads / kSellC) + e;
+        if (j < R && c <= (n + kSellC - 1) / kSellC)
+            ext = as_global(d.cptr)[c];
+    }
+    const int nft = d.nftiles;
+    const PPCG_AS1 dvec2 *PR = (const PPCG_AS1 dvec2 *)as_global(d.fpart + (size_t)par * nft * 4);
+    dvec2 pa0 = {0.0, 0.0}, pb0 = {0.0, 0.0}, pa1 = {0.0, 0.0}, pb1 = {0.0, 0.0};
+    const bool has0 = tid < nft, has1 = tid + kFusedThreads < nft;
+    if (has0) {
+        pa0 = PR[2 * tid];
+        pb0 = PR[2 * tid + 1];
+    }
+    if (has1) {
+        pa1 = PR[2 * (tid + kFusedThreads)];
+        pb1 = PR[2 * (tid + kFusedThreads) + 1];
+    }
+    static_assert(kMaxValueTable <= kFusedThreads, "one value-table entry per thread");
+    const bool vt = d.vidx != nullptr;
+    double tv = 0.0;
+    if (vt && tid < d.nvtab)
+        tv = d.vtab[tid];
+    __asm__ volatile("" ::: "memory");  // the loads above stay above the check
     if (rin->done) {
         // The launch that stopped the system published its record in this
         // launch's slot only.  Copy it into the other slot, so that the
@@ -137,7 +184,6 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
             d.frec[par ^ 1] = *rin;
         return;
     }
-    const int n = d.n;
     // What the gathers read, double buffered by parity in the handle's m or
     // w vector and the second buffer: w (constant diagonal: m is formed in
     // the gathers and never stored) or m.
@@ -145,22 +191,31 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     double *const v0 = (double *)(wg ? d.w : d.m), *const v1 = (double *)d.w1;
     const double *gin = par ? v1 : v0;
     double *gout = par ? v0 : v1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row0 = wi.tile * d.frows;
     const double *tab = nullptr;
-    if (d.vidx) {
-        for (int t = tid; t < d.nvtab; t += kFusedThreads)
-            vtab[t] = d.vtab[t];
+    if (vt) {
+        if (tid < d.nvtab)
+            vtab[tid] = tv;
         __syncthreads();
         tab = vtab;
     }
     // 1. The previous launch's partials, all tiles of the system, in tile
     // order per thread, then the fixed workgroup tree; the scalar recurrences.
     {
-        const PPCG_AS1 dvec2 *P = (const PPCG_AS1 dvec2 *)as_global(d.fpart + (size_t)par * d.nftiles * 4);
         double v[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
-        for (int t = tid; t < d.nftiles; t += kFusedThreads) {
-            const dvec2 a = P[2 * t], b = P[2 * t + 1];
+        if (has0) {
+            v[0] = v[0] + pa0[0];
+            v[1] = v[1] + pa0[1];
+            v[2] = v[2] + pb0[0];
+            v[3] = v[3] + pb0[1];
+        }
+        if (has1) {
+            v[0] = v[0] + pa1[0];
+            v[1] = v[1] + pa1[1];
+            v[2] = v[2] + pb1[0];
+            v[3] = v[3] + pb1[1];
+        }
+        for (int t = tid + 2 * kFusedThreads; t < nft; t += kFusedThreads) {
+            const dvec2 a = PR[2 * t], b = PR[2 * t + 1];
             v[0] = v[0] + a[0];
             v[1] = v[1] + a[1];
             v[2] = v[2] + b[0];
@@ -226,7 +281,9 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
         if (chunk * kSellC >= n)
             break;  // uniform per wavefront: no later chunk of this thread exists either
         const int i = chunk * kSellC + lane;
-        const double nv = fused_row(d, gin, chunk, lane, tab);
+        const int64_t eb = lane_i64(ext, 2 * k);
+        const int el = (int)((lane_i64(ext, 2 * k + 1) - eb) / kSellC);
+        const double nv = fused_row(d, gin, chunk, lane, tab, eb, el);
         if (i < n) {
             double z = Z[i], w = W[i], s = S[i], p = P[i], r = Rv[i], u, mo;
             const double di = DI[d.dinv_const ? 0 : i];

@@ -587,13 +587,18 @@ __device__ __forceinline__ void sell_row_straight(const int64_t *__restrict__ cp
                                                   const short *__restrict__ col16, const VT *__restrict__ val,
                                                   const T *const (&xin)[NX], int chunk, int lane, T (&acc)[NX],
                                                   const unsigned char *__restrict__ vidx, const double *tab,
-                                                  const double *dg, double d0)
+                                                  const double *dg, double d0, int64_t ebase = -1, int elen = 0)
 {
     constexpr int B = PPCG_SELL_BATCH;
     static_assert(B % 2 == 0, "spans of the 16-bit layout hold whole pairs");
     int64_t base;
     int len;
-    sell_extent(cptr, chunk, base, len);
+    if (ebase >= 0) {  // the chunk's extent, loaded by the caller
+        base = ebase;
+        len = elen;
+    } else {
+        sell_extent(cptr, chunk, base, len);
+    }
     const int row = chunk * kSellC + lane;
     const PPCG_AS1 int *c = C16 ? nullptr : as_global(col + base + lane);
     const PPCG_AS1 unsigned *cp = C16 ? as_global((const unsigned *)(col16 + base) + lane) : nullptr;
@@ -624,19 +629,25 @@ template <typename VT, typename T, int NX, bool VI = false, int SC = 0>
 __device__ __forceinline__ void sell_row(const int64_t *__restrict__ cptr, const int *__restrict__ col,
                                          const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
                                          int lane, T (&acc)[NX], const unsigned char *__restrict__ vidx = nullptr,
-                                         const double *tab = nullptr, const double *dg = nullptr, double d0 = 0.0)
+                                         const double *tab = nullptr, const double *dg = nullptr, double d0 = 0.0,
+                                         int64_t ebase = -1, int elen = 0)
 {
 #if PPCG_SELL_STRAIGHT
     // (32-bit columns with 8-byte values measured 2-3 % faster in the guarded
     // loop below: their loads already issue back to back there)
     if constexpr (VI || (SC != 0 && PPCG_SELL_STRAIGHT_SC))
         return sell_row_straight<false, VI, SC, VT, T, NX>(cptr, col, nullptr, val, xin, chunk, lane, acc, vidx, tab,
-                                                           dg, d0);
+                                                           dg, d0, ebase, elen);
 #endif
     constexpr int B = PPCG_SELL_BATCH;
     int64_t base;
     int len;
-    sell_extent(cptr, chunk, base, len);
+    if (ebase >= 0) {  // the chunk's extent, loaded by the caller
+        base = ebase;
+        len = elen;
+    } else {
+        sell_extent(cptr, chunk, base, len);
+    }
     const PPCG_AS1 int *c = as_global(col + base + lane);
     const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
     const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
@@ -707,16 +718,22 @@ template <typename VT, typename T, int NX, bool VI = false, int SC = 0>
 __device__ __forceinline__ void sell_row16(const int64_t *__restrict__ cptr, const short *__restrict__ col16,
                                            const VT *__restrict__ val, const T *const (&xin)[NX], int chunk,
                                            int lane, T (&acc)[NX], const unsigned char *__restrict__ vidx = nullptr,
-                                           const double *tab = nullptr, const double *dg = nullptr, double d0 = 0.0)
+                                           const double *tab = nullptr, const double *dg = nullptr, double d0 = 0.0,
+                                           int64_t ebase = -1, int elen = 0)
 {
 #if PPCG_SELL_STRAIGHT
     return sell_row_straight<true, VI, SC, VT, T, NX>(cptr, nullptr, col16, val, xin, chunk, lane, acc, vidx, tab,
-                                                      dg, d0);
+                                                      dg, d0, ebase, elen);
 #endif
     constexpr int B = PPCG_SELL_BATCH;
     int64_t base;
     int len;
-    sell_extent(cptr, chunk, base, len);
+    if (ebase >= 0) {  // the chunk's extent, loaded by the caller
+        base = ebase;
+        len = elen;
+    } else {
+        sell_extent(cptr, chunk, base, len);
+    }
     const int row = chunk * kSellC + lane;
     const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
     const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
@@ -760,16 +777,21 @@ __device__ __forceinline__ void sell_row16_pipe(const int64_t *__restrict__ cptr
                                                 int lane, T (&acc)[NX],
                                                 const unsigned char *__restrict__ vidx = nullptr,
                                                 const double *tab = nullptr, const double *dg = nullptr,
-                                                double d0 = 0.0)
+                                                double d0 = 0.0, int64_t ebase = -1, int elen = 0)
 {
 #if PPCG_SELL_STRAIGHT
     return sell_row_straight<true, VI, SC, VT, T, NX>(cptr, nullptr, col16, val, xin, chunk, lane, acc, vidx, tab,
-                                                      dg, d0);
+                                                      dg, d0, ebase, elen);
 #endif
     constexpr int B = PPCG_SELL_PIPE_BATCH;  // two batches in flight: smaller than the plain batch
     int64_t base;
     int len;
-    sell_extent(cptr, chunk, base, len);
+    if (ebase >= 0) {  // the chunk's extent, loaded by the caller
+        base = ebase;
+        len = elen;
+    } else {
+        sell_extent(cptr, chunk, base, len);
+    }
     const int row = chunk * kSellC + lane;
     const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
     const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;

@@ -187,13 +187,14 @@ def test_batch_fixed_iterates_match_oracle():
 
 def test_kernel_timing_reports_the_single_launch():
     A = poisson3d(48)
-    S = Solver(A, spmv_format="sell", flags=FUSED)
+    storage = ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES  # the same in both forms
+    S = Solver(A, spmv_format="sell", flags=FUSED | storage)
     tf, ts = S.time_kernels(dev(problem(A)), iters=10)
     assert tf > 0 and ts == 0.0
     mi = S.matrix_info()
     # n is neither written nor read (16 bytes per row fewer than two
     # launches), and with a constant diagonal m is not written (8 more)
-    T = Solver(A, spmv_format="sell", flags=ppcg.FLAG_ITER_TWO_LAUNCH)
+    T = Solver(A, spmv_format="sell", flags=ppcg.FLAG_ITER_TWO_LAUNCH | storage)
     assert mi["diag_const"] == 1
     assert abs((T.matrix_info()["bytes_per_iter"] - mi["bytes_per_iter"]) - 24.0 * A.n) < 1.0
 
