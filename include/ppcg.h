@@ -264,16 +264,21 @@ ppcg_status ppcg_set_options(ppcg_handle *h, const ppcg_options *opt);
 ppcg_status ppcg_solve(ppcg_handle *h, const double *b, const double *x0, double *x, ppcg_info *info);
 
 /* Solve count independent systems in one batched launch sequence: every
- * PIPECG iteration of all unconverged systems runs as one fused-update launch
- * and one SpMV launch over a table of (system, row tile) work items, captured
- * in HIP graphs; converged systems leave the table between graph launches.
- * hs: [count] distinct handles on one device; their streams may differ: the
- * batch waits for the work queued on every handle's stream before it reads
- * b[i] and x0[i], and returns once x[i] is written.  b, x0, x: [count] arrays
- * of per-system pointers as in ppcg_solve (x0[i] or x0 itself may be NULL).
- * infos: [count] or NULL.  Returns PPCG_OK when the batch ran;
- * per-system outcomes are in infos[i].status.  Each system's result is
- * bitwise identical to solving it alone with ppcg_solve. */
+ * PIPECG iteration of all unconverged systems runs over a table of (system,
+ * row tile) work items, captured in HIP graphs (one launch per iteration for
+ * the systems in the single-launch form, a fused-update launch and an SpMV
+ * launch for the others); converged systems leave the table between graph
+ * launches.  hs: [count] distinct handles on one device; their streams may
+ * differ: the batch waits for the work queued on every handle's stream
+ * before it reads b[i] and x0[i], and returns once x[i] is written.  b, x0,
+ * x: [count] arrays of per-system pointers as in ppcg_solve (x0[i] or x0
+ * itself may be NULL).  infos: [count] or NULL.  Returns PPCG_OK when the
+ * batch ran; per-system outcomes are in infos[i].status.  Each system's
+ * result is bitwise identical to solving it alone with ppcg_solve.
+ * Resources: hs[0] keeps the batch's engine (device buffers for count
+ * systems, its streams and captured graphs) until it leads a batch of more
+ * systems or is destroyed, so that the next batch it leads starts without
+ * allocating or capturing; an error during a batch releases them. */
 ppcg_status ppcg_solve_batch(int32_t count, ppcg_handle *const *hs, const double *const *b,
                              const double *const *x0, double *const *x, ppcg_info *infos);
 
