@@ -531,23 +531,31 @@ __device__ __forceinline__ void sell_span(const PPCG_AS1 int *c, const PPCG_AS1 
 {
     int cc[L];
     VT vv[L];
+    // one base address per stream for the span, the entries at constant
+    // offsets from it (immediate offsets of the load instructions, instead of
+    // a 64-bit address register per entry)
+    const size_t o0 = (size_t)k0 * kSellC;
     if constexpr (C16) {
+        const PPCG_AS1 unsigned *cpk = cp + o0 / 2;
 #pragma unroll
         for (int t = 0; t < L / 2; ++t) {
-            const unsigned pr = stream_load(cp + (size_t)((k0 >> 1) + t) * kSellC);
+            const unsigned pr = stream_load(cpk + t * kSellC);
             cc[2 * t] = row + (int)(short)(pr & 0xffffu);
             cc[2 * t + 1] = row + ((int)pr >> 16);
         }
         if constexpr ((L & 1) != 0)
             cc[L - 1] = row + (int)stream_load(odd);
     } else {
+        const PPCG_AS1 int *ck = c + o0;
 #pragma unroll
         for (int j = 0; j < L; ++j)
-            cc[j] = stream_load(c + (size_t)(k0 + j) * kSellC);
+            cc[j] = stream_load(ck + j * kSellC);
     }
+    const PPCG_AS1 VT *vk = VI ? nullptr : v + o0;
+    const PPCG_AS1 unsigned char *vik = VI ? vi + o0 : nullptr;
 #pragma unroll
     for (int j = 0; j < L; ++j)
-        vv[j] = sell_value<VI>(v, vi, tab, (size_t)(k0 + j) * kSellC);
+        vv[j] = sell_value<VI>(vk, vik, tab, (size_t)j * kSellC);
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
         T xx[L];
