@@ -94,13 +94,87 @@ __device__ __forceinline__ T *pcg_dir(const SysDesc &d, int k)
     return (T *)((k & 1) ? d.z : d.p);
 }
 
+// Entries k0 .. k0 + L - 1 of one row of s = A p (L fixed at compile time):
+// the column and value loads of all L entries back to back, then the gathers
+// of u and p_old, then the products added in entry order (the order of the
+// guarded loop below, so the same sums).  Bases at constant offsets per
+// entry, as in sell_span.
+template <int L, bool C16, typename T, typename VT>
+__device__ __forceinline__ void pcg_span(const PPCG_AS1 int *c, const PPCG_AS1 unsigned *cp,
+                                         const PPCG_AS1 short *odd, const PPCG_AS1 VT *v, int k0, int row, T beta,
+                                         const PPCG_AS1 T *__restrict__ U, const PPCG_AS1 T *__restrict__ Pold, T &y)
+{
+    int cc[L];
+    T vv[L], xx[L];
+    const size_t o0 = (size_t)k0 * kSellC;
+    if constexpr (C16) {
+        const PPCG_AS1 unsigned *cpk = cp + o0 / 2;
+#pragma unroll
+        for (int t = 0; t < L / 2; ++t) {
+            const unsigned pr = stream_load(cpk + t * kSellC);
+            cc[2 * t] = row + (int)(short)(pr & 0xffffu);
+            cc[2 * t + 1] = row + ((int)pr >> 16);
+        }
+        if constexpr ((L & 1) != 0)
+            cc[L - 1] = row + (int)stream_load(odd);
+    } else {
+        const PPCG_AS1 int *ck = c + o0;
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            cc[j] = stream_load(ck + j * kSellC);
+    }
+    const PPCG_AS1 VT *vk = v + o0;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        vv[j] = (T)stream_load(vk + j * kSellC);
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        xx[j] = U[cc[j]] + beta * Pold[cc[j]];
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        y = y + vv[j] * xx[j];
+}
+
+template <int M, bool C16, typename T, typename VT>
+__device__ __forceinline__ void pcg_tail(int rem, const PPCG_AS1 int *c, const PPCG_AS1 unsigned *cp,
+                                         const PPCG_AS1 short *odd, const PPCG_AS1 VT *v, int k0, int row, T beta,
+                                         const PPCG_AS1 T *__restrict__ U, const PPCG_AS1 T *__restrict__ Pold, T &y)
+{
+    if constexpr (M > 0) {
+        if (rem == M)
+            pcg_span<M, C16>(c, cp, odd, v, k0, row, beta, U, Pold, y);
+        else
+            pcg_tail<M - 1, C16>(rem, c, cp, odd, v, k0, row, beta, U, Pold, y);
+    }
+}
+
 // One SELL row of s = A p with p = u + beta p_old formed per gathered entry.
 // C16: 16-bit column offsets (the SELL pair layout) instead of 32-bit columns.
+// Full spans of 8 entries, then one span of the remaining length.
 template <bool C16, typename T, typename VT>
 __device__ __forceinline__ T pcg_sell_row(const SysDesc &d, const VT *__restrict__ val, int chunk, int lane,
                                           T beta, const PPCG_AS1 T *__restrict__ U,
                                           const PPCG_AS1 T *__restrict__ Pold)
 {
+#if PPCG_SELL_STRAIGHT
+    {
+        constexpr int B = 8;
+        int64_t base;
+        int len;
+        sell_extent(d.cptr, chunk, base, len);
+        const int row = chunk * kSellC + lane;
+        const PPCG_AS1 int *c = C16 ? nullptr : as_global(d.col + base + lane);
+        const PPCG_AS1 unsigned *cp = C16 ? as_global((const unsigned *)(d.col16 + base) + lane) : nullptr;
+        const PPCG_AS1 short *odd = C16 ? as_global(d.col16 + base + (size_t)(len & ~1) * kSellC + lane) : nullptr;
+        const PPCG_AS1 VT *v = as_global(val + base + lane);
+        T y = 0;
+        int k0 = 0;
+        for (; k0 + B <= len; k0 += B)
+            pcg_span<B, C16>(c, cp, odd, v, k0, row, beta, U, Pold, y);
+        pcg_tail<B - 1, C16>(len - k0, c, cp, odd, v, k0, row, beta, U, Pold, y);
+        return y;
+    }
+#endif
     constexpr int B = 8;
     const int64_t base = as_global(d.cptr)[chunk];
     const int len = (int)((as_global(d.cptr)[chunk + 1] - base) / kSellC);
