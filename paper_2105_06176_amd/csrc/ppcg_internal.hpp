@@ -96,6 +96,12 @@ static_assert(kFusedThreads % kSellC == 0, "each wavefront of a fused tile reads
 // 1: also the rows of 32-bit columns with 8-byte values whose gathers scale
 // w into m (the single-launch iteration with a constant diagonal) run as
 // straight spans: 128^3, 78.5 -> 66.7 us per iteration.
+// 1: the classic-PCG SpMV with FP32 values and FP64 vectors also reads the
+// 16-bit column offsets (0: 32-bit columns for that combination; the C3
+// solve with them, straight spans in both: 210.9 against 207.0 ms).
+#ifndef PPCG_PCG_V32_COL16
+#define PPCG_PCG_V32_COL16 0
+#endif
 #ifndef PPCG_SELL_STRAIGHT_SC
 #define PPCG_SELL_STRAIGHT_SC 1
 #endif

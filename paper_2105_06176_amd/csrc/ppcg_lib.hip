@@ -161,7 +161,7 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
     // the SpMVs read 16-bit column offsets when the matrix has them (not the
     // classic-PCG SpMV with FP32 values and FP64 vectors)
-    const double ie = (h->col16 && !(pcg && prec == PREC_V32)) ? 2.0 : 4.0;
+    const double ie = (h->col16 && (PPCG_PCG_V32_COL16 || !(pcg && prec == PREC_V32))) ? 2.0 : 4.0;
     bm.spmv = (me + ie) * (double)h->nnz + ptr + (pcg ? 4.0 : 2.0) * ve * n;
     // the single-launch form keeps n in registers (neither written by the
     // SpMV nor read by the update) and, with a constant diagonal, forms
@@ -2748,7 +2748,8 @@ ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
                        (h->vidx ? (double)h->nnz_stored + 8.0 * h->nvtab : 0.0);
     mi->setup_ms = h->setup_ms;
     mi->col_index_bytes =
-        (h->col16 && !(h->opt.method == PPCG_METHOD_PCG && h->opt.precision == PPCG_MIXED_FP32_VALUES)) ? 2 : 4;
+        (h->col16 && (PPCG_PCG_V32_COL16 ||
+                      !(h->opt.method == PPCG_METHOD_PCG && h->opt.precision == PPCG_MIXED_FP32_VALUES))) ? 2 : 4;
     mi->diag_const = h->dinv_const ? 1 : 0;
     const bool pcg = h->opt.method == PPCG_METHOD_PCG || h->opt.precision == PPCG_MIXED_FP32;
     mi->value_bytes = h->opt.precision == PPCG_MIXED_FP32 || h->opt.precision == PPCG_MIXED_FP32_VALUES ? 4

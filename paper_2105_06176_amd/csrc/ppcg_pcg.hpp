@@ -231,7 +231,7 @@ __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem
         if (chunk * kSellC < n) {
             // 16-bit columns measured slower for FP32 values with FP64
             // vectors (27-point case, 263 vs 242 ms), so that mix reads 32-bit ones
-            const bool c16 = d.col16 && !(sizeof(T) == 8 && sizeof(VT) == 4);
+            const bool c16 = d.col16 && (PPCG_PCG_V32_COL16 || !(sizeof(T) == 8 && sizeof(VT) == 4));
             const T y = c16 ? pcg_sell_row<true>(d, val, chunk, lane, beta, U, Pold)
                             : pcg_sell_row<false>(d, val, chunk, lane, beta, U, Pold);
             if (i < n) {
