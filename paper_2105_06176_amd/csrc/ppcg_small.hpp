@@ -12,12 +12,13 @@ namespace ppcg {
 // PIPECG iterations of one system per launch (work item = system).  Thread t
 // owns the rows t, t + kSmallThreads, ... (at most kSmallRowsPerThread) and
 // keeps their z, q, s, p, r, u, w and n in registers for the whole launch;
-// m, the only vector other rows read (the SpMV gathers), lives in LDS.  An
-// iteration touches global memory only for the matrix, the inverse diagonal
-// and x (read-modify-write; all L2-resident at these sizes): fused update, fixed-
-// order workgroup reduction and scalar update (thread 0), workgroup barrier,
-// SpMV from LDS, barrier.  Vectors are loaded at the start and stored at the
-// end of the launch, so the state in HBM is complete between launches.  SELL
+// m, the only vector other rows read (the SpMV gathers), and x live in LDS,
+// the scalar state record in LDS, the chunk extents in scalar registers.  An iteration touches global memory only for the matrix
+// and an inverse diagonal that is not constant (L2-resident at these sizes):
+// fused update, fixed-order workgroup reduction and scalar update (thread 0),
+// workgroup barrier, SpMV from LDS, barrier.  Vectors and the state are
+// loaded at the start and stored at the end of the launch, so the state in
+// HBM is complete between launches.  SELL
 // format only; rows of a wavefront form one SELL chunk, so chunk lengths are
 // uniform across each wavefront.
 constexpr int kSmallThreads = 512;
@@ -32,7 +33,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
     constexpr int R = kSmallRowsPerThread;
     __shared__ double lds[kSmallThreads / 64 * kNumPartials];
     __shared__ double lm[kSmallMaxRows];  // m
+    __shared__ double lx[kSmallMaxRows];  // x, written back at the end of the launch
     __shared__ double scal[2];            // alpha, beta of the next update
+    __shared__ SysState loc;              // the state record, written back at the end of the launch
     __shared__ int stop;
     if ((int)blockIdx.x >= *count)
         return;
@@ -68,29 +71,45 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
         u[j] = ok ? U[i] : 0.0;  // written back unchanged if no iteration runs
         w[j] = ok ? W[i] : 0.0;
         nv[j] = ok ? NVv[i] : 0.0;
-        if (ok)
+        if (ok) {
             lm[i] = M[i];
+            lx[i] = X[i];
+        }
     }
+    // The state record lives in LDS for the launch (written back at its end),
+    // the chunk extents in scalar registers.
     if (threadIdx.x == 0) {
-        stop = st->done;
-        scal[0] = st->alpha;
-        scal[1] = st->beta;
+        loc = *st;
+        stop = loc.done;
+        scal[0] = loc.alpha;
+        scal[1] = loc.beta;
     }
+    int base[R], len[R], maxlen = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int c = wave + j * (kSmallThreads / 64);
+        base[j] = 0;
+        len[j] = 0;
+        if (c * kSellC < n) {
+            base[j] = (int)cptr[c] + lane;
+            len[j] = (int)((cptr[c + 1] - cptr[c]) / kSellC);
+        }
+        maxlen = len[j] > maxlen ? len[j] : maxlen;
+    }
+    const bool dconst = d.dinv_const != 0;
+    const double d0 = DI[0];
     __syncthreads();
     for (int it = 0; it < iters && !stop; ++it) {
         const double sa = scal[0], sb = scal[1];
         double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
-        // all global loads of the update first (one memory latency), then the arithmetic
-        double xg[R], dg[R];
+        // the inverse diagonal: one value, or loaded first (one memory latency)
+        double dg[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int i = threadIdx.x + j * kSmallThreads;
-            xg[j] = 0.0;
-            dg[j] = 0.0;
-            if (i < n) {
-                xg[j] = X[i];
+            dg[j] = d0;
+            if (!dconst && i < n)
                 dg[j] = DI[i];
-            }
         }
 #pragma unroll
         for (int j = 0; j < R; ++j) {
@@ -98,34 +117,24 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
             if (i < n) {
                 double mo;
                 vma_elem<double, kNumPartials>(sa, sb, nv[j], z[j], w[j], s[j], p[j], r[j], dg[j], u[j], mo, acc);
-                X[i] = xg[j] + sa * p[j];  // this kernel updates x every iteration
-                lm[i] = mo;  // only this thread touches lm[i] until the barrier below
+                lx[i] = lx[i] + sa * p[j];  // this kernel updates x every iteration
+                lm[i] = mo;  // only this thread touches lm[i] and lx[i] until the barrier below
             }
         }
         block_sum<kSmallThreads, kNumPartials>(acc, lds);
         if (threadIdx.x == 0) {
-            scalar_update<kNumPartials>(d, st, acc);
-            stop = st->done;
-            scal[0] = st->alpha;
-            scal[1] = st->beta;
+            scalar_update<kNumPartials>(d, &loc, acc);
+            stop = loc.done;
+            scal[0] = loc.alpha;
+            scal[1] = loc.beta;
         }
         __syncthreads();  // m complete in LDS; the new scalars visible
         // SpMV from LDS: the wavefront's chunk for row slot j is wave + j *
         // (waves per workgroup); entry k of all its chunks is fetched together.
         // (stored entries of a system with at most kSmallMaxRows rows fit 32 bits)
-        int base[R], len[R], maxlen = 0;
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int c = wave + j * (kSmallThreads / 64);
-            base[j] = 0;
-            len[j] = 0;
-            if (c * kSellC < n) {
-                base[j] = (int)cptr[c] + lane;
-                len[j] = (int)((cptr[c + 1] - cptr[c]) / kSellC);
-            }
-            maxlen = len[j] > maxlen ? len[j] : maxlen;
+        for (int j = 0; j < R; ++j)
             nv[j] = 0.0;
-        }
         for (int k = 0; k < maxlen; ++k) {
             // entry k of every row slot: loads first, then the LDS gathers
             int cv[R];
@@ -159,8 +168,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
             W[i] = w[j];
             NVv[i] = nv[j];
             M[i] = lm[i];
+            X[i] = lx[i];
         }
     }
+    if (threadIdx.x == 0)
+        *st = loc;
 }
 
 }  // namespace ppcg
