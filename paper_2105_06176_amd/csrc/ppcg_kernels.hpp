@@ -88,12 +88,33 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// v of the lane that the DPP pattern CTRL names (within the lane's row of 16).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the wavefront: a butterfly over lane pairs at distance 32, 16,
+// 8, 4, 2, 1; each step adds a commuted pair, so the result is identical in
+// every lane.  The first two steps cross rows of 16 lanes (LDS permutes); the
+// other four stay inside a row and use DPP moves (a short dependency chain).
+// Rotating a row by 8 reaches lane i ^ 8; rotating it by 4 reaches i ^ 4 or
+// i ^ 4 ^ 8, which hold the same value once the distance-8 step is done; the
+// quad permutations reach i ^ 2 and i ^ 1 exactly.  So the sums are those of
+// the plain distance-32..1 butterfly, bit for bit.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v = v + __shfl_xor(v, off, 64);
-    return v;  // identical in every lane (each step adds a commuted pair)
+    v = v + __shfl_xor(v, 32, 64);
+    v = v + __shfl_xor(v, 16, 64);
+    v = v + dpp_f64<0x128>(v);  // row_ror:8
+    v = v + dpp_f64<0x124>(v);  // row_ror:4
+    v = v + dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]: lane i ^ 2
+    v = v + dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]: lane i ^ 1
+    return v;
 }
 
 // Sum NV values over the workgroup in a fixed order; result valid in thread 0.
