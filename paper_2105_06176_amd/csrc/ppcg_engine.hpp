@@ -91,6 +91,7 @@ struct StageItem;
 
 struct ppcg_handle {
     int device = 0;
+    int cus = 0;  // compute units of the device
     hipStream_t user_stream = nullptr;
     hipStream_t stream = nullptr;  // internal stream (capturable), ordered after user_stream
     ppcg_options opt{};
@@ -384,7 +385,7 @@ void launch_pipecg_init_fused(hipStream_t s, const WorkItem *tab, const int *cnt
 void launch_fused_chunk(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid, int iters);
 // Allocate the single-launch form's buffers of a handle (once).
 ppcg_status ensure_fused(ppcg_handle *h);
-// Fused tiles of a handle's system (fused_tile_rows rows each).
+// Fused tiles of a handle's system (fused_tile_rows(n, cus) rows each).
 int fused_tiles(const ppcg_handle *h);
 void launch_true_resid(hipStream_t s, const WorkItem *tab, const int *cnt, const SysDesc *dd, int grid);
 // CSR validation (ppcg_create's checks): dinv = 1 / diag, rowlen, and in

@@ -3,8 +3,9 @@
 //
 // The two-launch form (ppcg_kernels.hpp) writes n = A m in the SpMV launch
 // and reads it back in the next fused update.  Here each workgroup owns a
-// tile of frows rows (512 to 2,048, fused_tile_rows: as few rows per
-// thread as keep the tile count at or below 256) and, in one launch:
+// tile of frows rows (512 to 4,096, fused_tile_rows: 1 to 8 rows per
+// thread, chosen by the tile count and the compute units) and, in one
+// launch:
 //
 //   1. reduces, in one fixed order, the per-tile partial sums of (r,u),
 //      (w,u), (u,u), (r,r) that the previous launch wrote, and runs the scalar

@@ -29,30 +29,56 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 #define PPCG_FUSED_THREADS 512
 #endif
 #ifndef PPCG_FUSED_ROWS_PER_THREAD
-#define PPCG_FUSED_ROWS_PER_THREAD 4
+#define PPCG_FUSED_ROWS_PER_THREAD 8
 #endif
 constexpr int kFusedThreads = PPCG_FUSED_THREADS;
 constexpr int kFusedRowsPerThread = PPCG_FUSED_ROWS_PER_THREAD;  // at most
 constexpr int kFusedRows = kFusedThreads * kFusedRowsPerThread;    // at most
 static_assert(kFusedThreads == kTileRows, "a fused tile is a whole number of 512-row tiles");
+// Workgroups of the single-launch kernel one compute unit holds at once (its
+// 74 VGPRs allow 6 wavefronts per SIMD: 3 workgroups of 8 wavefronts).
+constexpr int kFusedResidentPerCU = 3;
 
-// Rows per fused tile for a system of n rows: as few rows per thread (1 to
-// kFusedRowsPerThread) as keep the tile count at or below 256, so that a
-// small system still spreads over many workgroups while every workgroup
-// re-reads few partial-sum records (one per tile).  Above 393,216 rows the
-// tiles have 2,048 rows (1,024 tiles at 2^21 rows).  Measured on 2-D
-// 5-point systems: 262,144 rows alone 3 % faster than with a target of
-// 1,024 tiles, 256 uneven systems batched 6 % faster; 128 tiles is slower
-// alone (fewer workgroups than compute units).
+// Rows per fused tile (R rows per thread) for a system of n rows on a GPU of
+// `cus` compute units.  The smallest candidate keeps the tile count at or
+// below 256 (at most 4 rows per thread), so that a small system still spreads
+// over many workgroups while every workgroup re-reads few partial-sum
+// records (one per tile).  Larger R (up to kFusedRowsPerThread) is taken
+// when it shortens the launch by the model below.
+//
+// Model: a compute unit gets w = ceil(tiles / cus) workgroups and holds
+// kFusedResidentPerCU at once.  With w at most that, its time is w tiles of
+// R rows; beyond it, its workgroups run in ceil(w / 3) rounds of 3, each round
+// costing as much as a full one (the last, partly filled round runs at low
+// occupancy).  Cost = R * w, or R * 3 * ceil(w / 3); the smallest R wins
+// ties.  Measured (us per iteration, 16-bit columns and value table):
+// 128^3 (2,097,152 rows) R = 8 (512 tiles) 51.9 against R = 4 55.0 and
+// R = 6 56.1; 2048^2 R = 4 95.6 against R = 8 101.3.
 #ifndef PPCG_FUSED_TILE_TARGET
 #define PPCG_FUSED_TILE_TARGET 256
 #endif
-__host__ __device__ inline int fused_tile_rows(int n)
+inline int fused_tile_rows(int n, int cus)
 {
     constexpr int kTarget = PPCG_FUSED_TILE_TARGET;
-    int r = (n + kTarget * kFusedThreads - 1) / (kTarget * kFusedThreads);
-    r = r < 1 ? 1 : r > kFusedRowsPerThread ? kFusedRowsPerThread : r;
-    return r * kFusedThreads;
+    int r0 = (n + kTarget * kFusedThreads - 1) / (kTarget * kFusedThreads);
+    r0 = r0 < 1 ? 1 : r0 > 4 ? 4 : r0;
+    if (cus < 1)
+        cus = 1;
+    int best = r0;
+    long long best_cost = -1;
+    for (int r = r0; r <= kFusedRowsPerThread; ++r) {
+        const long long rows = (long long)r * kFusedThreads;
+        const long long tiles = (n + rows - 1) / rows;
+        const long long w = (tiles + cus - 1) / cus;
+        const long long cost = w <= kFusedResidentPerCU
+                                   ? r * w
+                                   : r * kFusedResidentPerCU * ((w + kFusedResidentPerCU - 1) / kFusedResidentPerCU);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = r;
+        }
+    }
+    return best * kFusedThreads;
 }
 static_assert(kFusedThreads % kSellC == 0, "each wavefront of a fused tile reads whole SELL chunks");
 
@@ -192,7 +218,7 @@ struct SysDesc {
     SysState *st;
     // single-launch iteration (ppcg_fused.hpp); unused by the two-launch form
     int nftiles;          // fused tiles (of frows rows)
-    int frows;            // rows per fused tile (fused_tile_rows(n))
+    int frows;            // rows per fused tile (fused_tile_rows(n, compute units))
     SysState *frec;       // scalar state, 2 slots (launch parity)
     double *fpart;        // partial sums, 2 slots x nftiles x 4
     void *w1;             // second buffer of what the gathers read (w, or m for a diagonal that is not

@@ -337,7 +337,7 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->b = pd.vec[VB];
     d->part = prec == PREC_F64 ? h->part : h->part32;
     d->st = st;
-    d->frows = fused_tile_rows(h->n);
+    d->frows = fused_tile_rows(h->n, h->cus);
     d->nftiles = (h->n + d->frows - 1) / d->frows;
     d->frec = h->frec;
     d->fpart = h->fpart;
@@ -347,7 +347,7 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
 
 int fused_tiles(const ppcg_handle *h)
 {
-    const int fr = fused_tile_rows(h->n);
+    const int fr = fused_tile_rows(h->n, h->cus);
     return (h->n + fr - 1) / fr;
 }
 
@@ -2484,6 +2484,7 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
             return fail(s_);        \
     } while (0)
     CK(hipGetDevice(&h->device));
+    CK(hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device));
     CK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
     CK(hipEventCreateWithFlags(&h->ev_user, hipEventDisableTiming));
     hipStream_t s = h->stream;

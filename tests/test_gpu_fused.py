@@ -62,6 +62,9 @@ CASES = {
     "poisson2d_600_three_rows": (lambda: poisson2d(600), (4, 45), {}),
     # 200,000 rows: 2 rows per thread (1,024-row tiles), 195 tiles + 320 rows
     "random_spd_200000_two_rows": (lambda: random_spd(200000, seed=7), (6,), {}),
+    # 1,906,624 rows on 256 compute units: 5 rows per thread (2,560-row
+    # tiles, the tile model's choice), 744 tiles + 1,984 rows
+    "poisson3d_124_five_rows": (lambda: poisson3d(124), (3, 12), {}),
 }
 
 
