@@ -3,7 +3,7 @@
 //
 // The two-launch form (ppcg_kernels.hpp) writes n = A m in the SpMV launch
 // and reads it back in the next fused update.  Here each workgroup owns a
-// tile of frows rows (512 to 4,096, fused_tile_rows: 1 to 8 rows per
+// tile of frows rows (512 to 8,192, fused_tile_rows: 1 to 16 rows per
 // thread, chosen by the tile count and the compute units) and, in one
 // launch:
 //

@@ -29,7 +29,7 @@ constexpr int kPartStride = 8;     // doubles per tile partial record (replaceme
 #define PPCG_FUSED_THREADS 512
 #endif
 #ifndef PPCG_FUSED_ROWS_PER_THREAD
-#define PPCG_FUSED_ROWS_PER_THREAD 8
+#define PPCG_FUSED_ROWS_PER_THREAD 16
 #endif
 constexpr int kFusedThreads = PPCG_FUSED_THREADS;
 constexpr int kFusedRowsPerThread = PPCG_FUSED_ROWS_PER_THREAD;  // at most
@@ -53,7 +53,8 @@ constexpr int kFusedResidentPerCU = 3;
 // occupancy).  Cost = R * w, or R * 3 * ceil(w / 3); the smallest R wins
 // ties.  Measured (us per iteration, 16-bit columns and value table):
 // 128^3 (2,097,152 rows) R = 8 (512 tiles) 51.9 against R = 4 55.0 and
-// R = 6 56.1; 2048^2 R = 4 95.6 against R = 8 101.3.
+// R = 6 56.1; 2048^2 (4,194,304 rows) R = 16 (512 tiles) 91.4 against R = 4
+// 95.6 and R = 8 101.3; 160^3 7-point R = 16 94.1 against R = 4 98.0.
 #ifndef PPCG_FUSED_TILE_TARGET
 #define PPCG_FUSED_TILE_TARGET 256
 #endif

@@ -65,6 +65,8 @@ CASES = {
     # 1,906,624 rows on 256 compute units: 5 rows per thread (2,560-row
     # tiles, the tile model's choice), 744 tiles + 1,984 rows
     "poisson3d_124_five_rows": (lambda: poisson3d(124), (3, 12), {}),
+    # 4,000,000 rows: 16 rows per thread (8,192-row tiles), 488 tiles + 2,304 rows
+    "poisson2d_2000_sixteen_rows": (lambda: poisson2d(2000), (2, 9), {}),
 }
 
 
