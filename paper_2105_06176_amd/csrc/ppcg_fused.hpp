@@ -35,7 +35,8 @@
 // Per iteration this saves the n round trip (16 bytes per row), with a
 // constant diagonal the m write (8 bytes per row), and one launch.  The cost
 // is the partial-sum reduction every workgroup repeats: 32 bytes per tile,
-// read from the L2 (1,024 tiles at 2^21 rows: 32 KB per workgroup).
+// read from the L2 (512 tiles of 4,096 rows at 2^21 rows: 16 KB per
+// workgroup).
 //
 // The arithmetic of one row is that of the two-launch form (same SpMV order,
 // same products, same update formulas, x-updates paired in the same way);
