@@ -190,6 +190,17 @@ def leg_c2(args, torch, ppcg, wl, oracle):
             "bytes_per_launch": mf["bytes_per_iter"], "avg_launch_us": round(msf * 1e3, 3),
             "achieved": round(af, 1), "frac": round(af / PEAK_HBM_GBS, 4)}
         log(f"k_fused with 8-byte values: {msf * 1e3:.2f} us, {af:.0f} GB/s")
+        # ... and on the chunks' shared offset lists (no column stream)
+        F = ppcg.Solver(A, fixed_iters=K, spmv_format="sell", flags=ppcg.FLAG_SELL_SHARED_OFFSETS |
+                        ppcg.FLAG_SELL_VALUE_TABLE | ppcg.FLAG_ITER_FUSED)
+        mf = F.matrix_info()
+        msf, _ = F.time_kernels(bd, iters=100)
+        F.close()
+        af = mf["bytes_per_iter"] / (msf * 1e-3) / 1e9
+        roof["same_kernel_shared_offset_lists"] = {
+            "bytes_per_launch": mf["bytes_per_iter"], "avg_launch_us": round(msf * 1e3, 3),
+            "achieved": round(af, 1), "frac": round(af / PEAK_HBM_GBS, 4)}
+        log(f"k_fused on shared offset lists: {msf * 1e3:.2f} us, {af:.0f} GB/s")
     # tolerance run (after the fixed iterations; untimed in the main value)
     S.set_options(tol=1e-10, max_iter=10000)
     S.solve(bd)
@@ -515,6 +526,7 @@ def leg_p125(torch, ppcg, wl, side=165):
                       "algorithmic_gbs": round(mi["bytes_per_iter"] * info["iters"] / t / 1e9, 1),
                       "precond_norm": info["precond_norm"], "rel_resid_true": info["rel_resid_true"],
                       "spmv_format": mi["format"], "lanes_per_row": mi["lanes_per_row"],
+                      "sell_sigma": mi["sell_sigma"], "iter_launches": mi["iter_launches"],
                       "col_index_bytes": mi["col_index_bytes"], "value_bytes": mi["value_bytes"],
                       "distinct_values": mi["distinct_values"], "setup_ms": round(mi["setup_ms"], 1)}
         log(f"125-pt {label}: {out[label]}")

@@ -160,6 +160,20 @@ typedef struct {
                                       results differ from the two-launch form by rounding.  Read by
                                       ppcg_create only */
 #define PPCG_FLAG_ITER_TWO_LAUNCH 64u /* always two launches per iteration (not with ITER_FUSED) */
+#define PPCG_FLAG_SELL_SHARED_OFFSETS 128u /* SELL with rows in their own order: when the column
+                                      offsets (column minus row) of the 64 rows of every chunk,
+                                      merged, form one list (stencils in natural order; the chunk
+                                      then stores that many slots), the PIPECG SpMV with FP64
+                                      vectors (FP64 or FP32 values) reads the chunk's one offset
+                                      list instead of a column per entry, without timing it
+                                      against the per-entry columns (by default, unless SELL_COL16
+                                      or SELL_COL32 pins a column layout, both are timed at create
+                                      time and the faster is kept).  Rows missing an offset
+                                      of the list hold an explicit zero there, so the products and
+                                      their order are those of the CSR rows.  Read by ppcg_create
+                                      only */
+#define PPCG_FLAG_SELL_NO_SHARED_OFFSETS 256u /* SELL: never read shared offset lists (not with
+                                                 SELL_SHARED_OFFSETS) */
 
 /* Solver options; initialise with ppcg_default_options(). */
 typedef struct {
@@ -224,7 +238,9 @@ typedef struct {
     double device_bytes;     /* device memory held by the handle */
     double setup_ms;         /* time spent in ppcg_create (validation, conversion, tuning) */
     int32_t col_index_bytes; /* bytes per stored column index the iteration's SpMV reads: 2 when
-                                every SELL column fits a 16-bit offset from its row, else 4 */
+                                every SELL column fits a 16-bit offset from its row, 0 when the
+                                PIPECG SpMV with FP64 vectors reads the chunks' shared offset
+                                lists (PPCG_FLAG_SELL_SHARED_OFFSETS), else 4 */
     int32_t diag_const;      /* 1: every diagonal entry is equal; the fused update then reads
                                 the inverse diagonal as one cached value, not a vector */
     int32_t value_bytes;     /* bytes per stored value the iteration's SpMV reads: 1 with the

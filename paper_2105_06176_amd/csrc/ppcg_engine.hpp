@@ -111,6 +111,12 @@ struct ppcg_handle {
     unsigned char *vidx = nullptr;  // SELL: one-byte index of each stored value in vtab
     double *vtab = nullptr;   // the distinct values (ascending bit patterns) when vidx is set
     int nvtab = 0;
+    // SELL, rows in their own order: each chunk's shared offset list (the
+    // chunk's entry k of every row at column row + pats[cpat[c] + k]) when
+    // every chunk has one; shared_on: the FP64 PIPECG SpMV reads them
+    int *cpat = nullptr, *pats = nullptr;
+    int npats = 0;
+    bool shared_on = false;
     int *perm = nullptr, *invperm = nullptr;
     double *val64 = nullptr;  // FP64 values in the stored format
     float *val32 = nullptr;   // FP32 copy of the stored values (mixed modes)

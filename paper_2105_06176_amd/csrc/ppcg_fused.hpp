@@ -79,11 +79,21 @@ struct FusedScalars {
 // forms for m (a constant diagonal, d0 = dinv[0]); SC = 0: on m as stored.
 template <int SC>
 __device__ __forceinline__ double fused_row_sc(const SysDesc &d, const double *win, int chunk, int lane,
-                                               const double *tab, const double *dg, double d0, int64_t eb, int el)
+                                               const double *tab, const double *dg, double d0, int64_t eb, int el,
+                                               int ep)
 {
     const double *xin[1] = {win};
     double y[1];
     const double *val = (const double *)d.val;
+    if (d.cpat) {
+        if (tab)
+            sell_row_shared<double, double, 1, true, SC>(d.cptr, d.cpat, d.pats, val, xin, chunk, lane, d.n, y,
+                                                         d.vidx, tab, dg, d0, eb, el, ep);
+        else
+            sell_row_shared<double, double, 1, false, SC>(d.cptr, d.cpat, d.pats, val, xin, chunk, lane, d.n, y,
+                                                          nullptr, nullptr, dg, d0, eb, el, ep);
+        return y[0];
+    }
     if (tab) {
         if (d.col16)
 #if PPCG_SELL_PIPE
@@ -116,13 +126,13 @@ __device__ __forceinline__ double fused_row_sc(const SysDesc &d, const double *w
 // stored); others gather the stored m.  (Gathering dinv next to w for a
 // general diagonal needs 14 more VGPRs in this kernel: 88 against 74, one
 // wavefront per SIMD fewer for every system.)  eb, el: the chunk's first
-// stored slot and padded length.
+// stored slot and padded length; ep: the start of its shared offset list.
 __device__ __forceinline__ double fused_row(const SysDesc &d, const double *gin, int chunk, int lane,
-                                            const double *tab, int64_t eb, int el)
+                                            const double *tab, int64_t eb, int el, int ep)
 {
     if (d.dinv_const)
-        return fused_row_sc<1>(d, gin, chunk, lane, tab, nullptr, ((const double *)d.dinv)[0], eb, el);
-    return fused_row_sc<0>(d, gin, chunk, lane, tab, nullptr, 0.0, eb, el);
+        return fused_row_sc<1>(d, gin, chunk, lane, tab, nullptr, ((const double *)d.dinv)[0], eb, el, ep);
+    return fused_row_sc<0>(d, gin, chunk, lane, tab, nullptr, 0.0, eb, el, ep);
 }
 
 __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const WorkItem *__restrict__ table,
@@ -148,15 +158,23 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     // so that their latencies overlap instead of following one another:
     // the extents of this wavefront's chunks (row k of a thread lies in chunk
     // c0 + k * kFusedThreads / 64: lane j < 2R holds cptr[c0 + (j >> 1) * 8 +
-    // (j & 1)]), this thread's first two partial-sum records, and its entry
-    // of the value table.
+    // (j & 1)]) and, with shared offset lists, the lists' starts (lane
+    // 32 + k < 32 + R holds cpat[c0 + k * 8]), this thread's first two
+    // partial-sum records, and its entry of the value table.
+    static_assert(2 * kFusedRowsPerThread <= 32, "extents in lanes 0 .. 31, list starts in lanes 32 .. 63");
     int64_t ext = 0;
+    int pst = 0;
     {
         const int c0 = row0 / kSellC + wave;
+        const int nch = (n + kSellC - 1) / kSellC;
         const int j = lane >> 1, e = lane & 1;
         const int c = c0 + j * (kFusedThreads / kSellC) + e;
-        if (j < R && c <= (n + kSellC - 1) / kSellC)
+        if (j < R && c <= nch)
             ext = as_global(d.cptr)[c];
+        const int kp = lane - 32;
+        const int cp = c0 + kp * (kFusedThreads / kSellC);
+        if (d.cpat && kp >= 0 && kp < R && cp < nch)
+            pst = as_global(d.cpat)[cp];
     }
     const int nft = d.nftiles;
     const PPCG_AS1 dvec2 *PR = (const PPCG_AS1 dvec2 *)as_global(d.fpart + (size_t)par * nft * 4);
@@ -285,7 +303,8 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
         const int i = chunk * kSellC + lane;
         const int64_t eb = lane_i64(ext, 2 * k);
         const int el = (int)((lane_i64(ext, 2 * k + 1) - eb) / kSellC);
-        const double nv = fused_row(d, gin, chunk, lane, tab, eb, el);
+        const int ep = __builtin_amdgcn_readlane(pst, 32 + k);
+        const double nv = fused_row(d, gin, chunk, lane, tab, eb, el, ep);
         if (i < n) {
             double z = Z[i], w = W[i], s = S[i], p = P[i], r = Rv[i], u, mo;
             const double di = DI[d.dinv_const ? 0 : i];

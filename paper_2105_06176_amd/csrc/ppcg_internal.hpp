@@ -12,6 +12,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 namespace ppcg {
 
@@ -93,12 +94,24 @@ static_assert(kFusedThreads % kSellC == 0, "each wavefront of a fused tile reads
 #define PPCG_XCD_REMAP_SPMV 0
 #endif
 
-// 1: for SELL matrices whose column offsets from the row fit 16 bits, time
-// the SpMV with 16-bit offsets against 32-bit columns at setup and keep the
-// faster (0: 32-bit columns only).
 #ifndef PPCG_SELL_VTAB
 #define PPCG_SELL_VTAB 1  // one-byte value indices into a table of distinct values, when timed faster
 #endif
+// 1: rows in their own order are stored on chunk-shared offset lists when
+// every chunk has one, and the FP64 PIPECG SpMV reads the lists instead of a
+// column per entry when that timed faster (0: never).
+#ifndef PPCG_SELL_SHARED
+#define PPCG_SELL_SHARED 1
+#endif
+// Entries per straight span on shared offset lists.  16 would put more
+// gathers in flight per wavefront, but takes the single-launch kernel from
+// 74 to 105 VGPRs (4 wavefronts per SIMD instead of 6) and spills in the SpMV.
+#ifndef PPCG_SHARED_BATCH
+#define PPCG_SHARED_BATCH 8
+#endif
+// 1: for SELL matrices whose column offsets from the row fit 16 bits, time
+// the SpMV with 16-bit offsets against 32-bit columns at setup and keep the
+// faster (0: 32-bit columns only).
 #ifndef PPCG_SELL_COL16
 #define PPCG_SELL_COL16 1
 #endif
@@ -188,6 +201,9 @@ static_assert(sizeof(SysState) == 128, "SysState is one 128-byte record");
 // Per-system descriptor (device-resident copy per engine slot).
 // Largest value table: a one-byte index per stored entry.
 constexpr int kMaxValueTable = 256;
+// Longest concatenation of distinct shared offset lists kept (ints): the
+// lists are read through the scalar cache, so only a few KB of them are used.
+constexpr int kMaxSharedOffsets = 8192;
 
 struct SysDesc {
     int n;
@@ -210,6 +226,9 @@ struct SysDesc {
     const short *col16;   // SELL: column minus row as 16-bit offsets when every one fits (else NULL)
     const unsigned char *vidx;  // SELL, FP64 values: index of each stored value in vtab (else NULL)
     const double *vtab;   // the matrix's distinct values (at most kMaxValueTable), ascending bit patterns
+    const int *cpat;      // SELL: start of each chunk's shared offset list in pats, when the FP64
+                          // PIPECG SpMV reads them (else NULL)
+    const int *pats;      // the distinct offset lists, concatenated
     const void *val;      // matrix values (double or float)
     const float *val32;   // FP32 copy of the values (vals32 mode)
     const void *dinv;     // inverse diagonal (double or float)

@@ -646,6 +646,166 @@ __device__ __forceinline__ void sell_row_straight(const int64_t *__restrict__ cp
     sell_tail<B - 1, C16, VI, SC>(len - k0, c, cp, odd, v, vi, tab, xg, k0, row, acc, dg, d0);
 }
 
+// Chunk-shared offset lists.  They are written before any solver launch and
+// never during one, and the list of a chunk is the same for its 64 lanes:
+// read through the constant address space, so that the uniform loads become
+// scalar loads (the few distinct lists stay in the scalar cache) and the
+// gathers wait on no vector load.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_constant(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
+// Entries k0 .. k0 + L - 1 of a row stored on its chunk's shared offset list
+// `po`: the column of entry j is row + po[k0 + j], clamped into [0, last]
+// (an entry the row lacks is a zero value, at a column that may lie past the
+// matrix near its first and last rows).  Then as sell_span: the value loads,
+// the gathers, the products added in entry order.
+template <int L, bool VI, int SC, typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_span_sh(const __attribute__((address_space(4))) int *po,
+                                             const PPCG_AS1 VT *v, const PPCG_AS1 unsigned char *vi,
+                                             const double *tab, const PPCG_AS1 T *const (&xg)[NX], int k0, int row,
+                                             int last, T (&acc)[NX], const double *dg, double d0)
+{
+    int cc[L];
+    VT vv[L];
+    const size_t o0 = (size_t)k0 * kSellC;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        cc[j] = min(max(row + po[k0 + j], 0), last);
+    const PPCG_AS1 VT *vk = VI ? nullptr : v + o0;
+    const PPCG_AS1 unsigned char *vik = VI ? vi + o0 : nullptr;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        vv[j] = sell_value<VI>(vk, vik, tab, (size_t)j * kSellC);
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+        T xx[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            xx[j] = sell_in<SC>(xg[q], cc[j], dg, d0);
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            acc[q] = acc[q] + (T)vv[j] * xx[j];
+    }
+}
+
+// The same span for a chunk whose every column row + po[k] lies inside the
+// matrix (all chunks but a few at its first and last rows): no clamp; xr[q]
+// points at row's element of input q (and dr at dg's), and each gather
+// reads xr[q][po[k]].
+template <int L, bool VI, int SC, typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_span_in(const __attribute__((address_space(4))) int *po,
+                                             const PPCG_AS1 VT *v, const PPCG_AS1 unsigned char *vi,
+                                             const double *tab, const PPCG_AS1 T *const (&xr)[NX], int k0,
+                                             T (&acc)[NX], const PPCG_AS1 double *dr, double d0)
+{
+    int oo[L];
+    VT vv[L];
+    const size_t o0 = (size_t)k0 * kSellC;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        oo[j] = po[k0 + j];
+    const PPCG_AS1 VT *vk = VI ? nullptr : v + o0;
+    const PPCG_AS1 unsigned char *vik = VI ? vi + o0 : nullptr;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        vv[j] = sell_value<VI>(vk, vik, tab, (size_t)j * kSellC);
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+        T xx[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            const T xv = xr[q][oo[j]];
+            if constexpr (SC == 1)
+                xx[j] = (T)d0 * xv;
+            else if constexpr (SC == 2)
+                xx[j] = (T)dr[oo[j]] * xv;
+            else
+                xx[j] = xv;
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            acc[q] = acc[q] + (T)vv[j] * xx[j];
+    }
+}
+
+// The last rem (< M + 1) entries of a row on a shared list; IN: the chunk's
+// columns all lie inside the matrix (sell_span_in), else sell_span_sh.
+// (IN: xg holds the row pointers of sell_span_in, dr its pointer into dg.)
+template <int M, bool IN, bool VI, int SC, typename VT, typename T, int NX>
+__device__ __forceinline__ void sell_tail_sh(int rem, const __attribute__((address_space(4))) int *po,
+                                             const PPCG_AS1 VT *v, const PPCG_AS1 unsigned char *vi,
+                                             const double *tab, const PPCG_AS1 T *const (&xg)[NX], int k0, int row,
+                                             int last, T (&acc)[NX], const double *dg, const PPCG_AS1 double *dr,
+                                             double d0)
+{
+    if constexpr (M > 0) {
+        if (rem == M) {
+            if constexpr (IN)
+                sell_span_in<M, VI, SC>(po, v, vi, tab, xg, k0, acc, dr, d0);
+            else
+                sell_span_sh<M, VI, SC>(po, v, vi, tab, xg, k0, row, last, acc, dg, d0);
+        } else {
+            sell_tail_sh<M - 1, IN, VI, SC>(rem, po, v, vi, tab, xg, k0, row, last, acc, dg, dr, d0);
+        }
+    }
+}
+
+// One SELL row on its chunk's shared offset list (cpat[chunk]: the list's
+// start in pats), in straight spans like sell_row_straight.  ebase, elen,
+// epat: the chunk's extent and list start, when the caller loaded them.
+template <typename VT, typename T, int NX, bool VI = false, int SC = 0>
+__device__ __forceinline__ void sell_row_shared(const int64_t *__restrict__ cptr, const int *__restrict__ cpat,
+                                                const int *__restrict__ pats, const VT *__restrict__ val,
+                                                const T *const (&xin)[NX], int chunk, int lane, int n, T (&acc)[NX],
+                                                const unsigned char *__restrict__ vidx = nullptr,
+                                                const double *tab = nullptr, const double *dg = nullptr,
+                                                double d0 = 0.0, int64_t ebase = -1, int elen = 0, int epat = -1)
+{
+    constexpr int B = PPCG_SHARED_BATCH;
+    int64_t base;
+    int len;
+    if (ebase >= 0) {
+        base = ebase;
+        len = elen;
+    } else {
+        sell_extent(cptr, chunk, base, len);
+    }
+    const int ps = epat >= 0 ? epat : as_constant(cpat)[__builtin_amdgcn_readfirstlane(chunk)];
+    const __attribute__((address_space(4))) int *po = as_constant(pats) + ps;
+    const int row = chunk * kSellC + lane;
+    const PPCG_AS1 VT *v = VI ? nullptr : as_global(val + base + lane);
+    const PPCG_AS1 unsigned char *vi = VI ? as_global(vidx + base + lane) : nullptr;
+    const PPCG_AS1 T *xg[NX];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+        acc[q] = (T)0;
+        xg[q] = as_global(xin[q]);
+    }
+    if (len < 1)
+        return;
+    // the list ascends: its first and last offsets bound the chunk's columns
+    const int c0 = chunk * kSellC;
+    const bool inside = c0 + po[0] >= 0 && (int64_t)c0 + (kSellC - 1) + po[len - 1] < (int64_t)n;
+    int k0 = 0;
+    if (inside) {
+        const PPCG_AS1 T *xr[NX];
+#pragma unroll
+        for (int q = 0; q < NX; ++q)
+            xr[q] = xg[q] + row;
+        const PPCG_AS1 double *dr = SC == 2 ? as_global(dg) + row : nullptr;
+        for (; k0 + B <= len; k0 += B)
+            sell_span_in<B, VI, SC>(po, v, vi, tab, xr, k0, acc, dr, d0);
+        sell_tail_sh<B - 1, true, VI, SC>(len - k0, po, v, vi, tab, xr, k0, row, n - 1, acc, dg, dr, d0);
+    } else {
+        for (; k0 + B <= len; k0 += B)
+            sell_span_sh<B, VI, SC>(po, v, vi, tab, xg, k0, row, n - 1, acc, dg, d0);
+        sell_tail_sh<B - 1, false, VI, SC>(len - k0, po, v, vi, tab, xg, k0, row, n - 1, acc, dg, nullptr, d0);
+    }
+}
+
 // SELL-C-sigma, C = 64, one lane per row: entry k of the row (chunk c, lane
 // l) is at cptr[c] + k * 64 + l.  NX input vectors share one pass over the
 // matrix (NX = 2 for the replacement steps).  Entries are handled in
@@ -1065,8 +1225,24 @@ __device__ __forceinline__ void spmv_tile(const SysDesc &d, const VT *__restrict
         if (chunk * kSellC < n) {
             // both choices are uniform per system
             bool done = false;
+            // shared offset lists: FP64 vectors, FP64 values (with or
+            // without the value table) or FP32 values
+            if constexpr (std::is_same<T, double>::value && NX == 1) {
+                if (d.cpat) {
+                    if constexpr (std::is_same<VT, double>::value) {
+                        if (tab)
+                            sell_row_shared<VT, T, NX, true>(d.cptr, d.cpat, d.pats, val, xin, chunk, lane, n, y,
+                                                             d.vidx, tab);
+                        else
+                            sell_row_shared<VT, T, NX>(d.cptr, d.cpat, d.pats, val, xin, chunk, lane, n, y);
+                    } else {
+                        sell_row_shared<VT, T, NX>(d.cptr, d.cpat, d.pats, val, xin, chunk, lane, n, y);
+                    }
+                    done = true;
+                }
+            }
             if constexpr (std::is_same<VT, double>::value && NX == 1) {
-                if (tab) {
+                if (!done && tab) {
                     if (d.col16)
 #if PPCG_SELL_PIPE
                         sell_row16_pipe<VT, T, NX, true>(d.cptr, d.col16, val, xin, chunk, lane, y, d.vidx, tab);

@@ -161,8 +161,11 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
     // the SpMVs read 16-bit column offsets when the matrix has them (not the
     // classic-PCG SpMV with FP32 values and FP64 vectors)
-    const double ie = (h->col16 && (PPCG_PCG_V32_COL16 || !(pcg && prec == PREC_V32))) ? 2.0 : 4.0;
-    bm.spmv = (me + ie) * (double)h->nnz + ptr + (pcg ? 4.0 : 2.0) * ve * n;
+    // (none with the shared offset lists, read by the PIPECG SpMV with FP64
+    // vectors: 4 bytes per chunk)
+    const bool sh = h->shared_on && (prec == PREC_F64 || prec == PREC_V32) && !pcg;
+    const double ie = sh ? 0.0 : (h->col16 && (PPCG_PCG_V32_COL16 || !(pcg && prec == PREC_V32))) ? 2.0 : 4.0;
+    bm.spmv = (me + ie) * (double)h->nnz + ptr + (sh ? 4.0 * h->nchunks : 0.0) + (pcg ? 4.0 : 2.0) * ve * n;
     // the single-launch form keeps n in registers (neither written by the
     // SpMV nor read by the update) and, with a constant diagonal, forms
     // m = M^-1 w in the next launch's gathers instead of writing it (the
@@ -183,6 +186,8 @@ struct SellBuild {
     int *col = nullptr;
     double *val = nullptr;
     int *perm = nullptr, *invperm = nullptr;
+    int *cpat = nullptr, *pats = nullptr;  // shared offset lists (see k_sell_union)
+    int npats = 0;
     void free_all()
     {
         if (cptr) (void)dev_free(cptr);
@@ -190,6 +195,8 @@ struct SellBuild {
         if (val) (void)dev_free(val);
         if (perm) (void)dev_free(perm);
         if (invperm) (void)dev_free(invperm);
+        if (cpat) (void)dev_free(cpat);
+        if (pats) (void)dev_free(pats);
         *this = SellBuild();
     }
 };
@@ -230,8 +237,117 @@ static ppcg_status sell_size(hipStream_t s, int n, int sigma, const int *rowlen,
     return PPCG_OK;
 }
 
+// Chunk widths for the shared offset lists of an unsorted SELL layout: sz
+// holds 64 x each chunk's longest row (k_chunk_size); where a chunk's merged
+// list is longer, its width grows to the list's length.  *ok is false (sz
+// unchanged) when some chunk's list passes k_sell_union_count's cap or the
+// widths grow by more than 1/32 in total: the lists would cost more padding
+// than they save.
+static ppcg_status widen_for_shared(hipStream_t s, int n, int nchunks, const int *rp, const int *ci, int64_t *sz,
+                                    bool *ok)
+{
+    *ok = false;
+    int *cnt = nullptr;
+    PPCG_HIP(hipMalloc(&cnt, sizeof(int) * std::max(nchunks, 1)));
+    std::vector<int> cnt_h((size_t)nchunks);
+    std::vector<int64_t> sz_h((size_t)nchunks);
+    k_sell_union_count<<<nchunks, kSellC, 0, s>>>(n, nchunks, rp, ci, sz, cnt);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cnt_h.data(), cnt, sizeof(int) * nchunks, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sz_h.data(), sz, sizeof(int64_t) * nchunks, hipMemcpyDeviceToHost, s);
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = es;
+    (void)dev_free(cnt);
+    PPCG_HIP(e);
+    int64_t before = 0, after = 0;
+    for (int c = 0; c < nchunks; ++c) {
+        if (cnt_h[c] < 0)
+            return PPCG_OK;
+        const int64_t w = sz_h[c] / kSellC;
+        before += w;
+        after += std::max<int64_t>(w, cnt_h[c]);
+        sz_h[c] = std::max<int64_t>(w, cnt_h[c]) * kSellC;
+    }
+    if (after * 32 > before * 33)
+        return PPCG_OK;
+    PPCG_HIP(hipMemcpyAsync(sz, sz_h.data(), sizeof(int64_t) * nchunks, hipMemcpyHostToDevice, s));
+    PPCG_HIP(hipStreamSynchronize(s));
+    *ok = true;
+    return PPCG_OK;
+}
+
+// Shared offset lists of an unsorted SELL layout whose chunk extents sb.cptr
+// are set (widened by widen_for_shared): each chunk's merged list
+// (k_sell_union), the distinct lists concatenated on the host (a few KB for
+// a stencil: one list per kind of boundary), and each chunk's list start.
+// Leaves sb.cpat NULL when the distinct lists exceed kMaxSharedOffsets.
+static ppcg_status build_shared_lists(hipStream_t s, int n, const int *rp, const int *ci, SellBuild &sb)
+{
+    const int64_t nl = sb.stored / kSellC;
+    int *lists = nullptr;
+    unsigned *flag = nullptr;
+    auto clean = [&]() {
+        if (lists) (void)dev_free(lists);
+        if (flag) (void)dev_free(flag);
+    };
+    if (nl < 1 || sb.perm)
+        return PPCG_OK;
+    const unsigned zero = 0u;
+    unsigned bad = 1u;
+    PPCG_HIP_CLEAN(hipMalloc(&lists, sizeof(int) * nl), clean());
+    PPCG_HIP_CLEAN(hipMalloc(&flag, sizeof(unsigned)), clean());
+    PPCG_HIP_CLEAN(hipMemcpyAsync(flag, &zero, sizeof zero, hipMemcpyHostToDevice, s), clean());
+    k_sell_union<<<sb.nchunks, kSellC, 0, s>>>(n, sb.nchunks, rp, ci, sb.cptr, lists, flag);
+    PPCG_HIP_CLEAN(hipGetLastError(), clean());
+    PPCG_HIP_CLEAN(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s), clean());
+    PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());
+    if (bad) {
+        clean();
+        return PPCG_OK;
+    }
+    std::vector<int> lh((size_t)nl);
+    std::vector<int64_t> cp((size_t)sb.nchunks + 1);
+    PPCG_HIP_CLEAN(hipMemcpyAsync(lh.data(), lists, sizeof(int) * nl, hipMemcpyDeviceToHost, s), clean());
+    PPCG_HIP_CLEAN(hipMemcpyAsync(cp.data(), sb.cptr, sizeof(int64_t) * cp.size(), hipMemcpyDeviceToHost, s),
+                   clean());
+    PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());
+    clean();
+    lists = nullptr;
+    flag = nullptr;
+    std::map<std::string, int> seen;
+    std::vector<int> pats, cpat((size_t)sb.nchunks);
+    for (int c = 0; c < sb.nchunks; ++c) {
+        const int64_t a = cp[c] / kSellC, len = (cp[c + 1] - cp[c]) / kSellC;
+        std::string key((const char *)(lh.data() + a), (size_t)len * sizeof(int));
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            if ((int64_t)pats.size() + len > kMaxSharedOffsets)
+                return PPCG_OK;
+            it = seen.emplace(std::move(key), (int)pats.size()).first;
+            pats.insert(pats.end(), lh.begin() + a, lh.begin() + a + len);
+        }
+        cpat[c] = it->second;
+    }
+    if (pats.empty())
+        pats.push_back(0);
+    PPCG_HIP(hipMalloc(&sb.cpat, sizeof(int) * cpat.size()));
+    PPCG_HIP(hipMalloc(&sb.pats, sizeof(int) * pats.size()));
+    PPCG_HIP(hipMemcpyAsync(sb.cpat, cpat.data(), sizeof(int) * cpat.size(), hipMemcpyHostToDevice, s));
+    PPCG_HIP(hipMemcpyAsync(sb.pats, pats.data(), sizeof(int) * pats.size(), hipMemcpyHostToDevice, s));
+    PPCG_HIP(hipStreamSynchronize(s));
+    sb.npats = (int)pats.size();
+    return PPCG_OK;
+}
+
+// SELL-C-sigma storage of the CSR matrix.  shared: when the rows keep their
+// order (sigma = 1) and every chunk has a shared offset list, the entries
+// are placed on the lists (k_sell_fill_shared); the products of every row,
+// and their order, stay those of its CSR entries.
 static ppcg_status build_sell(hipStream_t s, int n, int sigma, const int *rp, const int *ci, const double *val,
-                              const int *rowlen, SellBuild *out)
+                              const int *rowlen, SellBuild *out, bool shared)
 {
     SellBuild sb;
     sb.sigma = sigma;
@@ -250,15 +366,57 @@ static ppcg_status build_sell(hipStream_t s, int n, int sigma, const int *rp, co
         k_invert_perm<<<blocks_for(n, 256), 256, 0, s>>>(n, sb.perm, sb.invperm);
     }
     k_chunk_size<<<blocks_for(sb.nchunks, 256), 256, 0, s>>>(n, sb.nchunks, sb.perm, rowlen, sz);
+    bool widened = false;
+    if (shared && sigma == 1) {
+        const ppcg_status rc = widen_for_shared(s, n, sb.nchunks, rp, ci, sz, &widened);
+        if (rc < 0) {
+            clean();
+            return rc;
+        }
+    }
     k_scan<<<1, 1024, 0, s>>>(sb.nchunks, sz, sb.cptr);
     PPCG_HIP_CLEAN(hipMemcpyAsync(&sb.stored, sb.cptr + sb.nchunks, sizeof(int64_t), hipMemcpyDeviceToHost, s),
                    clean());
     PPCG_HIP_CLEAN(hipStreamSynchronize(s), clean());
     PPCG_HIP_CLEAN(hipMalloc(&sb.col, sizeof(int) * std::max<int64_t>(sb.stored, 1)), clean());
     PPCG_HIP_CLEAN(hipMalloc(&sb.val, sizeof(double) * std::max<int64_t>(sb.stored, 1)), clean());
-    k_sell_fill<<<blocks_for((size_t)sb.nchunks * kSellC, 256), 256, 0, s>>>(
-        n, sb.nchunks, rp, ci, val, sb.perm, sb.invperm, sb.cptr, sb.col, sb.val);
-    PPCG_HIP_CLEAN(hipGetLastError(), clean());
+    if (widened) {
+        const ppcg_status rc = build_shared_lists(s, n, rp, ci, sb);
+        if (rc < 0) {
+            clean();
+            return rc;
+        }
+    }
+    if (sb.cpat) {
+        unsigned *flag = nullptr;
+        const unsigned zero = 0u;
+        unsigned bad = 1u;
+        hipError_t e = hipMalloc(&flag, sizeof(unsigned));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(flag, &zero, sizeof zero, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) {
+            k_sell_fill_shared<<<blocks_for((size_t)sb.nchunks * kSellC, 256), 256, 0, s>>>(
+                n, sb.nchunks, rp, ci, val, sb.cptr, sb.cpat, sb.pats, sb.col, sb.val, flag);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s);
+        const hipError_t es = hipStreamSynchronize(s);
+        if (e == hipSuccess)
+            e = es;
+        if (flag)
+            (void)dev_free(flag);
+        PPCG_HIP_CLEAN(e, clean());
+        if (bad) {
+            set_error("shared offset lists: an entry found no place");
+            clean();
+            return PPCG_ERR_DEVICE;
+        }
+    } else {
+        k_sell_fill<<<blocks_for((size_t)sb.nchunks * kSellC, 256), 256, 0, s>>>(
+            n, sb.nchunks, rp, ci, val, sb.perm, sb.invperm, sb.cptr, sb.col, sb.val);
+        PPCG_HIP_CLEAN(hipGetLastError(), clean());
+    }
     (void)dev_free(sz);
     sz = nullptr;
     *out = sb;
@@ -315,6 +473,8 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->vidx = h->vidx;
     d->vtab = h->vtab;
     d->nvtab = h->nvtab;
+    d->cpat = h->shared_on && prec == PREC_F64 ? h->cpat : nullptr;
+    d->pats = h->pats;
     d->val = pd.val;
     d->val32 = h->val32;
     d->vals32 = vals32;
@@ -444,6 +604,11 @@ static void free_matrix(ppcg_handle *h)
     if (h->val32) (void)dev_free(h->val32);
     if (h->perm) (void)dev_free(h->perm);
     if (h->invperm) (void)dev_free(h->invperm);
+    if (h->cpat) (void)dev_free(h->cpat);
+    if (h->pats) (void)dev_free(h->pats);
+    h->cpat = h->pats = nullptr;
+    h->npats = 0;
+    h->shared_on = false;
     h->cptr = nullptr;
     h->rp = h->col = h->perm = h->invperm = nullptr;
     h->val64 = nullptr;
@@ -463,6 +628,9 @@ static ppcg_status adopt_sell(ppcg_handle *h, SellBuild &sb)
     h->val64 = sb.val;
     h->perm = sb.perm;
     h->invperm = sb.invperm;
+    h->cpat = sb.cpat;
+    h->pats = sb.pats;
+    h->npats = sb.npats;
     sb = SellBuild();
     return PPCG_OK;
 }
@@ -781,6 +949,70 @@ static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const doubl
     return PPCG_OK;
 }
 
+// SELL on shared offset lists: whether the FP64 PIPECG SpMV reads each
+// chunk's list (through the scalar cache) instead of a column per entry.
+// It saves the column bytes (2 or 4 per entry) and the wait of every gather
+// on its column load, and costs a clamp per entry.  Timed like the value
+// table (alternated, best of two) and kept when 2 % faster; decisions are
+// cached per (rows, mean stored row length, value table, 16-bit columns)
+// signature.  PPCG_FLAG_SELL_SHARED_OFFSETS / _NO_SHARED_OFFSETS force it;
+// a forced column layout (PPCG_FLAG_SELL_COL16 / _COL32) leaves it off.
+static std::map<std::tuple<int, int, int, int>, bool> g_shared_kept;
+
+static ppcg_status tune_shared(ppcg_handle *h)
+{
+    h->shared_on = false;
+    const unsigned fl = h->opt.flags;
+    if (!h->cpat || h->fmt != FMT_SELL || (fl & PPCG_FLAG_SELL_NO_SHARED_OFFSETS))
+        return PPCG_OK;
+    if (fl & PPCG_FLAG_SELL_SHARED_OFFSETS) {
+        h->shared_on = true;
+        return PPCG_OK;
+    }
+    if (fl & (PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32))  // a column layout was pinned
+        return PPCG_OK;
+    const auto sig = std::make_tuple((int)std::log2((double)h->n), (int)std::lround((double)h->nnz_stored / h->n),
+                                     h->vidx ? 1 : 0, h->col16 ? 1 : 0);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_shared_kept.find(sig);
+        if (it != g_shared_kept.end()) {
+            h->shared_on = it->second;
+            return PPCG_OK;
+        }
+    }
+    double tc = 1e300, ts = 1e300;
+    for (int round = 0; round < 2; ++round) {
+        double t = 0.0;
+        h->shared_on = false;
+        PPCG_TRY(time_spmv(h, 5, &t));
+        tc = std::min(tc, t);
+        h->shared_on = true;
+        PPCG_TRY(time_spmv(h, 5, &t));
+        ts = std::min(ts, t);
+    }
+    h->shared_on = ts < 0.98 * tc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_shared_kept[sig] = h->shared_on;
+    return PPCG_OK;
+}
+
+// The single-launch form reads the shared lists whenever the matrix has them
+// (unless a column layout is pinned or the lists are refused): there the
+// SpMV's column loads sit in the chain of every row, and the lists measured
+// within 1 % or faster on every stencil tried, also where the two-launch
+// SpMV alone is a few percent slower with them (µs per iteration, per-entry
+// columns against lists: 7-point 128^3 51.0 / 50.5, 27-point 160^3
+// 298 / 260, 125-point 100^3 142 / 118, 5-point 2048^2 90.3 / 91.2; the 256
+// 2-D systems of a batch 67.8 / 65.0 ms).
+static void shared_for_fused(ppcg_handle *h)
+{
+    const unsigned fl = h->opt.flags;
+    if (h->form == FORM_FUSED && h->cpat && !h->shared_on &&
+        !(fl & (PPCG_FLAG_SELL_NO_SHARED_OFFSETS | PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32)))
+        h->shared_on = true;
+}
+
 // ---------------------------------------------------------------- iteration form
 // Time kIters iterations of each form of FP64 PIPECG on the handle's stored
 // matrix, after their initialisations, from b = 1 and x0 = 0 in fixed-
@@ -877,7 +1109,7 @@ static ppcg_status tune_form(ppcg_handle *h)
         return PPCG_OK;
     const auto key = std::make_tuple((int)std::log2((double)h->n),
                                      (int)std::lround((double)h->nnz_stored / h->n), h->col16 ? 1 : 0,
-                                     h->vidx ? 1 : 0, h->sigma > 1 ? 1 : 0);
+                                     h->vidx ? 1 : 0, h->sigma > 1 ? 1 : h->shared_on ? 2 : 0);
     {
         std::unique_lock<std::mutex> lk(g_tune_mu);
         g_tune_cv.wait(lk, [&] { return !g_form_tuning.count(key); });
@@ -965,6 +1197,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
     const ppcg_spmv_format want = h->opt.spmv_format;
     // a forced 16-bit column choice is not a timing result: not cached
     const bool forced16 = (h->opt.flags & (PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32)) != 0;
+    const bool shared = PPCG_SELL_SHARED && !(h->opt.flags & PPCG_FLAG_SELL_NO_SHARED_OFFSETS);
     // Row-length statistics.
     double sum = 0, sum2 = 0;
     int mx = 0;
@@ -987,7 +1220,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
         PPCG_TRY(sell_size(h->stream, h->n, 1, rowlen, &st1));
         const int sigma = (double)st1 > 1.05 * (double)h->nnz ? kSortWindow : 1;
         SellBuild sb;
-        PPCG_TRY(build_sell(h->stream, h->n, sigma, rp, ci, val, rowlen, &sb));
+        PPCG_TRY(build_sell(h->stream, h->n, sigma, rp, ci, val, rowlen, &sb, shared));
         PPCG_TRY(adopt_sell(h, sb));
         PPCG_TRY(bind_f64(h, dinv_orig));
         int c16 = 0;
@@ -1015,7 +1248,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
     if (hit) {
         if (tv.fmt == FMT_SELL) {
             SellBuild sb;
-            PPCG_TRY(build_sell(h->stream, h->n, tv.sigma, rp, ci, val, rowlen, &sb));
+            PPCG_TRY(build_sell(h->stream, h->n, tv.sigma, rp, ci, val, rowlen, &sb, shared));
             PPCG_TRY(adopt_sell(h, sb));
         } else {
             PPCG_TRY(adopt_csrv(h, tv.lanes, rp, ci, val));
@@ -1068,7 +1301,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
     for (const Cand &c : cands) {
         if (c.fmt == FMT_SELL) {
             SellBuild sb;
-            PPCG_TRY(build_sell(h->stream, h->n, c.sigma, rp, ci, val, rowlen, &sb));
+            PPCG_TRY(build_sell(h->stream, h->n, c.sigma, rp, ci, val, rowlen, &sb, shared));
             PPCG_TRY(adopt_sell(h, sb));
         } else {
             PPCG_TRY(adopt_csrv(h, c.lanes, rp, ci, val));
@@ -1085,7 +1318,7 @@ static ppcg_status choose_format(ppcg_handle *h, const int *rp, const int *ci, c
     if (!(last.fmt == bestc.fmt && last.sigma == bestc.sigma && last.lanes == bestc.lanes)) {
         if (bestc.fmt == FMT_SELL) {
             SellBuild sb;
-            PPCG_TRY(build_sell(h->stream, h->n, bestc.sigma, rp, ci, val, rowlen, &sb));
+            PPCG_TRY(build_sell(h->stream, h->n, bestc.sigma, rp, ci, val, rowlen, &sb, shared));
             PPCG_TRY(adopt_sell(h, sb));
         } else {
             PPCG_TRY(adopt_csrv(h, bestc.lanes, rp, ci, val));
@@ -2343,8 +2576,10 @@ ppcg_status check_options(const ppcg_options *o)
         (o->method != PPCG_METHOD_PIPECG && o->method != PPCG_METHOD_PCG) ||
         (o->flags & ~(PPCG_FLAG_BORROW_INPUTS | PPCG_FLAG_SELL_COL16 | PPCG_FLAG_SELL_COL32 |
                       PPCG_FLAG_SELL_VALUE_TABLE | PPCG_FLAG_SELL_FULL_VALUES | PPCG_FLAG_ITER_FUSED |
-                      PPCG_FLAG_ITER_TWO_LAUNCH)) != 0 ||
+                      PPCG_FLAG_ITER_TWO_LAUNCH | PPCG_FLAG_SELL_SHARED_OFFSETS |
+                      PPCG_FLAG_SELL_NO_SHARED_OFFSETS)) != 0 ||
         ((o->flags & PPCG_FLAG_ITER_FUSED) && (o->flags & PPCG_FLAG_ITER_TWO_LAUNCH)) ||
+        ((o->flags & PPCG_FLAG_SELL_SHARED_OFFSETS) && (o->flags & PPCG_FLAG_SELL_NO_SHARED_OFFSETS)) ||
         ((o->flags & PPCG_FLAG_SELL_COL16) && (o->flags & PPCG_FLAG_SELL_COL32)) ||
         ((o->flags & PPCG_FLAG_SELL_VALUE_TABLE) && (o->flags & PPCG_FLAG_SELL_FULL_VALUES))) {
         set_error("invalid option value");
@@ -2543,7 +2778,9 @@ ppcg_status ppcg_create(const ppcg_csr *A, const ppcg_options *opt, void *hip_st
     CKS(alloc_f64_vectors(h));
     CKS(choose_format(h, rp, ci, val, rowlen, dinv_orig, rowlen_h));
     CKS(tune_vtab(h, A->mem == PPCG_MEM_HOST ? A->values : nullptr, val));
+    CKS(tune_shared(h));
     CKS(tune_form(h));
+    shared_for_fused(h);
     if (opt->precision == PPCG_MIXED_FP32)
         CKS(ensure_f32(h));
     if (opt->precision == PPCG_MIXED_FP32_VALUES)
@@ -2746,11 +2983,15 @@ ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
                        (double)h->nnz_stored * 12.0 + 8.0 * h->n +
                        (h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (h->n + 1)) +
                        (h->perm ? 8.0 * h->n : 0.0) + (h->col16 ? 2.0 * (double)h->nnz_stored : 0.0) +
-                       (h->vidx ? (double)h->nnz_stored + 8.0 * h->nvtab : 0.0);
+                       (h->vidx ? (double)h->nnz_stored + 8.0 * h->nvtab : 0.0) +
+                       (h->cpat ? 4.0 * (h->nchunks + h->npats) : 0.0);
     mi->setup_ms = h->setup_ms;
     mi->col_index_bytes =
-        (h->col16 && (PPCG_PCG_V32_COL16 ||
-                      !(h->opt.method == PPCG_METHOD_PCG && h->opt.precision == PPCG_MIXED_FP32_VALUES))) ? 2 : 4;
+        (h->shared_on && h->opt.method == PPCG_METHOD_PIPECG &&
+         (h->opt.precision == PPCG_FP64 || h->opt.precision == PPCG_MIXED_FP32_VALUES)) ? 0
+        : (h->col16 && (PPCG_PCG_V32_COL16 ||
+                        !(h->opt.method == PPCG_METHOD_PCG && h->opt.precision == PPCG_MIXED_FP32_VALUES))) ? 2
+                                                                                                             : 4;
     mi->diag_const = h->dinv_const ? 1 : 0;
     const bool pcg = h->opt.method == PPCG_METHOD_PCG || h->opt.precision == PPCG_MIXED_FP32;
     mi->value_bytes = h->opt.precision == PPCG_MIXED_FP32 || h->opt.precision == PPCG_MIXED_FP32_VALUES ? 4

@@ -217,6 +217,126 @@ __global__ void k_sell_fill(int n, int nchunks, const int *__restrict__ rp, cons
     }
 }
 
+// Chunk-shared column offsets (stencil-like matrices, rows in their own
+// order).  The offsets col - row of a chunk's 64 rows, merged, form its
+// shared list; the chunk is stored with that many slots (at least its
+// longest row; more where rows of different kinds meet, e.g. the last grid
+// line of one plane and the first of the next), entry k of every row at
+// offset list[k] from the row, with a zero wherever the row has no entry
+// there.  A row's entries keep their ascending column order, so its products
+// are added in the order of its CSR entries, with exact zeros in between.
+//
+// Both kernels run one wavefront per chunk (blockDim 64) and merge the
+// rows' offset lists (each ascending, as validated) by repeated minimum.
+// k_sell_union_count: cnt[c] = the merged list's length, or -1 when it
+// exceeds cap(len) = 2 len + 2 for the chunk's longest row len (then the
+// matrix is not stored this way).
+__device__ __forceinline__ int wave_min_i32(int m)
+{
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1)
+        m = min(m, __shfl_xor(m, s, 64));
+    return m;
+}
+
+__global__ __launch_bounds__(64) void k_sell_union_count(int n, int nchunks, const int *__restrict__ rp,
+                                                         const int *__restrict__ ci, const int64_t *__restrict__ sz,
+                                                         int *__restrict__ cnt)
+{
+    const int c = blockIdx.x, l = threadIdx.x;
+    if (c >= nchunks)
+        return;
+    const int p = c * kSellC + l;
+    const int len = (int)(sz[c] / kSellC);
+    int a = 0, L = 0, h = 0;
+    if (p < n) {
+        a = rp[p];
+        L = rp[p + 1] - a;
+    }
+    const int cap = 2 * len + 2;
+    int k = 0;
+    for (; k <= cap; ++k) {
+        const int off = h < L ? ci[a + h] - p : INT_MAX;
+        const int m = wave_min_i32(off);
+        if (m == INT_MAX)
+            break;
+        if (off == m)
+            ++h;
+    }
+    if (l == 0)
+        cnt[c] = k > cap ? -1 : k;
+}
+
+// k_sell_union: the merged list of chunk c (len = its stored slots, from
+// cptr) at lists[cptr[c] / 64 ..], slots past the merged length set to 0;
+// flag[0] |= 1 if some row has entries left after len slots.
+__global__ __launch_bounds__(64) void k_sell_union(int n, int nchunks, const int *__restrict__ rp,
+                                                   const int *__restrict__ ci, const int64_t *__restrict__ cptr,
+                                                   int *__restrict__ lists, unsigned *__restrict__ flag)
+{
+    const int c = blockIdx.x, l = threadIdx.x;
+    if (c >= nchunks)
+        return;
+    const int p = c * kSellC + l;
+    const int64_t base = cptr[c];
+    const int len = (int)((cptr[c + 1] - base) / kSellC);
+    int a = 0, L = 0, h = 0;
+    if (p < n) {
+        a = rp[p];
+        L = rp[p + 1] - a;
+    }
+    int *out = lists + base / kSellC;
+    for (int k = 0; k < len; ++k) {
+        const int off = h < L ? ci[a + h] - p : INT_MAX;
+        const int m = wave_min_i32(off);
+        // (a slot past the merged length repeats the last offset: the list
+        // stays ascending, and such a slot holds zeros)
+        if (l == 0)
+            out[k] = m != INT_MAX ? m : k > 0 ? out[k - 1] : 0;
+        if (off == m && m != INT_MAX)
+            ++h;
+    }
+    if (h < L)
+        atomicOr(flag, 1u);
+}
+
+// Fill the SELL arrays on the chunks' shared offset lists: entry k of row p
+// is the row's entry at column p + list[k] when it has one, else value 0 at
+// that column clamped into [0, n - 1].  Sets flag[0] |= 1 if an entry of the
+// row found no place (cannot happen after k_sell_union succeeded).
+__global__ void k_sell_fill_shared(int n, int nchunks, const int *__restrict__ rp, const int *__restrict__ ci,
+                                   const double *__restrict__ val, const int64_t *__restrict__ cptr,
+                                   const int *__restrict__ cpat, const int *__restrict__ pats,
+                                   int *__restrict__ scol, double *__restrict__ sval, unsigned *__restrict__ flag)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nchunks * kSellC)
+        return;
+    const int c = p / kSellC, l = p % kSellC;
+    const int64_t base = cptr[c];
+    const int len = (int)((cptr[c + 1] - base) / kSellC);
+    const int *list = pats + cpat[c];
+    int a = 0, L = 0, h = 0;
+    if (p < n) {
+        a = rp[p];
+        L = rp[p + 1] - a;
+    }
+    for (int k = 0; k < len; ++k) {
+        const size_t o = (size_t)base + (size_t)k * kSellC + l;
+        const int t = p + list[k];
+        if (h < L && ci[a + h] == t) {
+            scol[o] = t;
+            sval[o] = val[a + h];
+            ++h;
+        } else {
+            scol[o] = min(max(t, 0), n - 1);
+            sval[o] = 0.0;
+        }
+    }
+    if (h < L)
+        atomicOr(flag, 1u);
+}
+
 // Permute the inverse diagonal into stored-row order.
 __global__ void k_permute_d(int n, const int *__restrict__ perm, const double *__restrict__ in,
                             double *__restrict__ out)

@@ -26,6 +26,7 @@ METHOD_PIPECG, METHOD_PCG = 0, 1
 FLAG_BORROW_INPUTS, FLAG_SELL_COL16, FLAG_SELL_COL32 = 1, 2, 4
 FLAG_SELL_VALUE_TABLE, FLAG_SELL_FULL_VALUES = 8, 16
 FLAG_ITER_FUSED, FLAG_ITER_TWO_LAUNCH = 32, 64
+FLAG_SELL_SHARED_OFFSETS, FLAG_SELL_NO_SHARED_OFFSETS = 128, 256
 SPMV_AUTO, SPMV_SELL, SPMV_CSR_VECTOR = 0, 1, 2
 
 _STOP = {"rel": STOP_REL_RESID, "abs": STOP_PRECOND_ABS}

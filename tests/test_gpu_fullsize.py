@@ -147,17 +147,25 @@ def p125():
     return A, rhs_from_solution(A, xstar_paper(A.n))
 
 
-@pytest.mark.parametrize("vflag", [ppcg.FLAG_SELL_VALUE_TABLE, ppcg.FLAG_SELL_FULL_VALUES])
+@pytest.mark.parametrize("vflag", [ppcg.FLAG_SELL_VALUE_TABLE, ppcg.FLAG_SELL_FULL_VALUES,
+                                   ppcg.FLAG_SELL_VALUE_TABLE | ppcg.FLAG_SELL_SHARED_OFFSETS,
+                                   ppcg.FLAG_SELL_VALUE_TABLE | ppcg.FLAG_SELL_NO_SHARED_OFFSETS])
 def test_table2_125pt_side165_full_size(p125, vflag):
     """Table 2's matrix at full size with its three distinct values read
     through the one-byte table (as the autotuner picks it) and as 8-byte
-    values: the SpMV equals the oracle's bit for bit, and x_5 and the
-    iteration count under the paper's protocol match the stored values."""
+    values, on the chunks' shared offset lists and on per-entry columns: the
+    SpMV equals the oracle's bit for bit, and x_5 and the iteration count
+    under the paper's protocol match the stored values."""
     A, b = p125
     vals, meta = _golden("p125_side165.txt", "x5")
     assert (meta["n"], meta["nnz"]) == (A.n, A.nnz)
     S = Solver(A, fixed_iters=5, flags=vflag)
-    assert S.matrix_info()["value_bytes"] == (1 if vflag == ppcg.FLAG_SELL_VALUE_TABLE else 8)
+    mi = S.matrix_info()
+    assert mi["value_bytes"] == (1 if vflag & ppcg.FLAG_SELL_VALUE_TABLE else 8)
+    if vflag & ppcg.FLAG_SELL_SHARED_OFFSETS:
+        assert mi["col_index_bytes"] == 0
+    if vflag & ppcg.FLAG_SELL_NO_SHARED_OFFSETS:
+        assert mi["col_index_bytes"] in (2, 4)
     xs = xstar_uniform(A.n, 5)
     assert np.array_equal(host(S.spmv(dev(xs))), oracle.spmv(A, xs))
     x, info = S.solve(dev(b))

@@ -101,7 +101,8 @@ def test_storage_choices_keep_results_exact(flags, expect16):
         S = Solver(A, spmv_format="sell", flags=flags)
         mi = S.matrix_info()
         if expect16 is None or not fits:
-            assert mi["col_index_bytes"] in ((2, 4) if fits else (4,)), A.name
+            # 0: the chunks' shared offset lists (stencils in natural order)
+            assert mi["col_index_bytes"] in ((0, 2, 4) if fits else (4,)), A.name
         else:
             assert mi["col_index_bytes"] == (2 if expect16 else 4), A.name
         assert mi["diag_const"] == const, A.name
@@ -258,13 +259,16 @@ def c2():
 
 # the storage and iteration form bench.py pins for this matrix (16-bit
 # columns, one-byte value table, one launch per iteration), 32-bit columns
-# with 8-byte values in both iteration forms, and the autotuner's own choice
+# with 8-byte values in both iteration forms, the chunks' shared offset lists
+# with the value table, and the autotuner's own choice
 C2_STORAGE = {"bench": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL16 | ppcg.FLAG_SELL_VALUE_TABLE |
                             ppcg.FLAG_ITER_FUSED),
               "full_values_fused": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES |
                                         ppcg.FLAG_ITER_FUSED),
               "two_launch": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_COL32 | ppcg.FLAG_SELL_FULL_VALUES |
                                  ppcg.FLAG_ITER_TWO_LAUNCH),
+              "shared_offsets_fused": dict(spmv_format="sell", flags=ppcg.FLAG_SELL_SHARED_OFFSETS |
+                                           ppcg.FLAG_SELL_VALUE_TABLE | ppcg.FLAG_ITER_FUSED),
               "auto": {}}
 
 
