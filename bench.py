@@ -17,6 +17,7 @@ precision on the 27-point 160^3 problem, the 256-system batch, serving).
 
 import argparse
 import hashlib
+import statistics
 import json
 import math
 import os
@@ -479,18 +480,23 @@ def leg_c4(torch, ppcg, wl, count=256):
     sync()
     t_seq = time.perf_counter() - t0
     ppcg.solve_batch(solvers, bs)  # warm-up
-    sync()
-    t0 = time.perf_counter()
-    xs, infos = ppcg.solve_batch(solvers, bs)
-    sync()
-    t_batch = time.perf_counter() - t0
+    # three timed batches: the median is reported, the best beside it
+    tb = []
+    for _ in range(3):
+        sync()
+        t0 = time.perf_counter()
+        xs, infos = ppcg.solve_batch(solvers, bs)
+        sync()
+        tb.append(time.perf_counter() - t0)
+    t_batch = statistics.median(tb)
     ok = sum(1 for i in infos if i["status"] == 0 and i["rel_resid_true"] <= 1e-10)
     bytes_total = sum(S.matrix_info()["bytes_per_iter"] * i["iters"] for S, i in zip(solvers, infos))
     for S in solvers:
         S.close()
     return {"workload": f"{count} shifted 2D 5-point Poisson systems, side U[32,512], shift U[0,0.5), tol 1e-10",
             "sum_n": int(sum(A.n for A in mats)), "sum_nnz": int(sum(A.nnz for A in mats)),
-            "batched_solves_per_s": round(count / t_batch, 2), "sequential_solves_per_s": round(count / t_seq, 2),
+            "batched_solves_per_s": round(count / t_batch, 2), "batched_solves_per_s_best_of_3": round(count / min(tb), 2),
+            "sequential_solves_per_s": round(count / t_seq, 2),
             "batch_speedup": round(t_seq / t_batch, 3), "batch_time_s": round(t_batch, 4),
             "sequential_time_s": round(t_seq, 4), "converged": ok, "total_iters": int(sum(i["iters"] for i in infos)),
             "algorithmic_gbs": round(bytes_total / t_batch / 1e9, 1), "setup_s": round(setup, 2)}
