@@ -161,9 +161,9 @@ static ByteModel byte_model(const ppcg_handle *h, int prec)
     const double ptr = h->fmt == FMT_SELL ? 8.0 * (h->nchunks + 1) : 4.0 * (n + 1);
     // the SpMVs read 16-bit column offsets when the matrix has them (not the
     // classic-PCG SpMV with FP32 values and FP64 vectors)
-    // (none with the shared offset lists, read by the PIPECG SpMV with FP64
-    // vectors: 4 bytes per chunk)
-    const bool sh = h->shared_on && (prec == PREC_F64 || prec == PREC_V32) && !pcg;
+    // (none with the shared offset lists, which every iteration SpMV reads
+    // when they are on: 4 bytes per chunk)
+    const bool sh = h->shared_on;
     const double ie = sh ? 0.0 : (h->col16 && (PPCG_PCG_V32_COL16 || !(pcg && prec == PREC_V32))) ? 2.0 : 4.0;
     bm.spmv = (me + ie) * (double)h->nnz + ptr + (sh ? 4.0 * h->nchunks : 0.0) + (pcg ? 4.0 : 2.0) * ve * n;
     // the single-launch form keeps n in registers (neither written by the
@@ -473,7 +473,7 @@ ppcg_status fill_desc(ppcg_handle *h, int prec, SysState *st, SysDesc *d, double
     d->vidx = h->vidx;
     d->vtab = h->vtab;
     d->nvtab = h->nvtab;
-    d->cpat = h->shared_on && prec == PREC_F64 ? h->cpat : nullptr;
+    d->cpat = h->shared_on ? h->cpat : nullptr;
     d->pats = h->pats;
     d->val = pd.val;
     d->val32 = h->val32;
@@ -2987,8 +2987,7 @@ ppcg_status ppcg_get_matrix_info(const ppcg_handle *h, ppcg_matrix_info *mi)
                        (h->cpat ? 4.0 * (h->nchunks + h->npats) : 0.0);
     mi->setup_ms = h->setup_ms;
     mi->col_index_bytes =
-        (h->shared_on && h->opt.method == PPCG_METHOD_PIPECG &&
-         (h->opt.precision == PPCG_FP64 || h->opt.precision == PPCG_MIXED_FP32_VALUES)) ? 0
+        h->shared_on ? 0
         : (h->col16 && (PPCG_PCG_V32_COL16 ||
                         !(h->opt.method == PPCG_METHOD_PCG && h->opt.precision == PPCG_MIXED_FP32_VALUES))) ? 2
                                                                                                              : 4;

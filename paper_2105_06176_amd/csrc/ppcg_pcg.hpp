@@ -99,15 +99,23 @@ __device__ __forceinline__ T *pcg_dir(const SysDesc &d, int k)
 // of u and p_old, then the products added in entry order (the order of the
 // guarded loop below, so the same sums).  Bases at constant offsets per
 // entry, as in sell_span.
-template <int L, bool C16, typename T, typename VT>
+// CM: the column layout, 0 = 32-bit columns, 1 = 16-bit offsets in pairs,
+// 2 = the chunk's shared offset list po (columns row + po[k], clamped into
+// [0, last]).
+template <int L, int CM, typename T, typename VT>
 __device__ __forceinline__ void pcg_span(const PPCG_AS1 int *c, const PPCG_AS1 unsigned *cp,
-                                         const PPCG_AS1 short *odd, const PPCG_AS1 VT *v, int k0, int row, T beta,
+                                         const PPCG_AS1 short *odd, const __attribute__((address_space(4))) int *po,
+                                         int last, const PPCG_AS1 VT *v, int k0, int row, T beta,
                                          const PPCG_AS1 T *__restrict__ U, const PPCG_AS1 T *__restrict__ Pold, T &y)
 {
     int cc[L];
     T vv[L], xx[L];
     const size_t o0 = (size_t)k0 * kSellC;
-    if constexpr (C16) {
+    if constexpr (CM == 2) {
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            cc[j] = min(max(row + po[k0 + j], 0), last);
+    } else if constexpr (CM == 1) {
         const PPCG_AS1 unsigned *cpk = cp + o0 / 2;
 #pragma unroll
         for (int t = 0; t < L / 2; ++t) {
@@ -135,27 +143,29 @@ __device__ __forceinline__ void pcg_span(const PPCG_AS1 int *c, const PPCG_AS1 u
         y = y + vv[j] * xx[j];
 }
 
-template <int M, bool C16, typename T, typename VT>
+template <int M, int CM, typename T, typename VT>
 __device__ __forceinline__ void pcg_tail(int rem, const PPCG_AS1 int *c, const PPCG_AS1 unsigned *cp,
-                                         const PPCG_AS1 short *odd, const PPCG_AS1 VT *v, int k0, int row, T beta,
+                                         const PPCG_AS1 short *odd, const __attribute__((address_space(4))) int *po,
+                                         int last, const PPCG_AS1 VT *v, int k0, int row, T beta,
                                          const PPCG_AS1 T *__restrict__ U, const PPCG_AS1 T *__restrict__ Pold, T &y)
 {
     if constexpr (M > 0) {
         if (rem == M)
-            pcg_span<M, C16>(c, cp, odd, v, k0, row, beta, U, Pold, y);
+            pcg_span<M, CM>(c, cp, odd, po, last, v, k0, row, beta, U, Pold, y);
         else
-            pcg_tail<M - 1, C16>(rem, c, cp, odd, v, k0, row, beta, U, Pold, y);
+            pcg_tail<M - 1, CM>(rem, c, cp, odd, po, last, v, k0, row, beta, U, Pold, y);
     }
 }
 
 // One SELL row of s = A p with p = u + beta p_old formed per gathered entry.
-// C16: 16-bit column offsets (the SELL pair layout) instead of 32-bit columns.
-// Full spans of 8 entries, then one span of the remaining length.
-template <bool C16, typename T, typename VT>
+// CM: the column layout (pcg_span).  Full spans of 8 entries, then one span
+// of the remaining length.
+template <int CM, typename T, typename VT>
 __device__ __forceinline__ T pcg_sell_row(const SysDesc &d, const VT *__restrict__ val, int chunk, int lane,
                                           T beta, const PPCG_AS1 T *__restrict__ U,
                                           const PPCG_AS1 T *__restrict__ Pold)
 {
+    constexpr bool C16 = CM == 1;
 #if PPCG_SELL_STRAIGHT
     {
         constexpr int B = 8;
@@ -163,18 +173,22 @@ __device__ __forceinline__ T pcg_sell_row(const SysDesc &d, const VT *__restrict
         int len;
         sell_extent(d.cptr, chunk, base, len);
         const int row = chunk * kSellC + lane;
-        const PPCG_AS1 int *c = C16 ? nullptr : as_global(d.col + base + lane);
+        const PPCG_AS1 int *c = CM == 0 ? as_global(d.col + base + lane) : nullptr;
         const PPCG_AS1 unsigned *cp = C16 ? as_global((const unsigned *)(d.col16 + base) + lane) : nullptr;
         const PPCG_AS1 short *odd = C16 ? as_global(d.col16 + base + (size_t)(len & ~1) * kSellC + lane) : nullptr;
+        const __attribute__((address_space(4))) int *po = nullptr;
+        if constexpr (CM == 2)
+            po = as_constant(d.pats) + as_constant(d.cpat)[__builtin_amdgcn_readfirstlane(chunk)];
         const PPCG_AS1 VT *v = as_global(val + base + lane);
         T y = 0;
         int k0 = 0;
         for (; k0 + B <= len; k0 += B)
-            pcg_span<B, C16>(c, cp, odd, v, k0, row, beta, U, Pold, y);
-        pcg_tail<B - 1, C16>(len - k0, c, cp, odd, v, k0, row, beta, U, Pold, y);
+            pcg_span<B, CM>(c, cp, odd, po, d.n - 1, v, k0, row, beta, U, Pold, y);
+        pcg_tail<B - 1, CM>(len - k0, c, cp, odd, po, d.n - 1, v, k0, row, beta, U, Pold, y);
         return y;
     }
 #endif
+    static_assert(CM != 2 || PPCG_SELL_STRAIGHT, "shared offset lists are read in straight spans");
     constexpr int B = 8;
     const int64_t base = as_global(d.cptr)[chunk];
     const int len = (int)((as_global(d.cptr)[chunk + 1] - base) / kSellC);
@@ -232,8 +246,9 @@ __device__ __forceinline__ double pcg_spmv_tile(const SysDesc &d, const WorkItem
             // 16-bit columns measured slower for FP32 values with FP64
             // vectors (27-point case, 263 vs 242 ms), so that mix reads 32-bit ones
             const bool c16 = d.col16 && (PPCG_PCG_V32_COL16 || !(sizeof(T) == 8 && sizeof(VT) == 4));
-            const T y = c16 ? pcg_sell_row<true>(d, val, chunk, lane, beta, U, Pold)
-                            : pcg_sell_row<false>(d, val, chunk, lane, beta, U, Pold);
+            const T y = d.cpat ? pcg_sell_row<2>(d, val, chunk, lane, beta, U, Pold)
+                        : c16  ? pcg_sell_row<1>(d, val, chunk, lane, beta, U, Pold)
+                               : pcg_sell_row<0>(d, val, chunk, lane, beta, U, Pold);
             if (i < n) {
                 const T pn = U[i] + beta * Pold[i];
                 Pnew[i] = pn;

@@ -214,3 +214,43 @@ def test_fp32_values_on_shared_lists_equal_per_entry_columns(gen):
         res.append((host(x), info["iters"], info["outer_iters"]))
         S.close()
     assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
+
+
+@pytest.mark.parametrize("name", ["poisson3d_40", "stencil27_40", "poisson2d_600_three_rows"])
+def test_classic_pcg_on_shared_lists(name):
+    """Algorithm 1's SpMV (s = A p with p formed per gathered entry) reads the
+    lists too: iterates equal the per-entry columns' bit for bit and meet the
+    1e-10 bar against the oracle's Algorithm 1."""
+    A = ITER_CASES[name][0]()
+    b = rhs_from_solution(A, xstar_uniform(A.n, 4))
+    S = Solver(A, fixed_iters=1, spmv_format="sell", method="pcg", flags=SH)
+    N = Solver(A, fixed_iters=1, spmv_format="sell", method="pcg", flags=NOSH)
+    assert S.matrix_info()["col_index_bytes"] == 0
+    for k in (5, 40):
+        S.set_options(fixed_iters=k)
+        N.set_options(fixed_iters=k)
+        xs, info = S.solve(dev(b))
+        xn, _ = N.solve(dev(b))
+        assert info["iters"] == k, info
+        assert np.array_equal(host(xs), host(xn)), (name, k)
+        assert relerr(host(xs), oracle.pcg(A, b, fixed_iters=k).x) <= 1e-10, (name, k)
+    S.close()
+    N.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "mixed_values"])
+def test_classic_pcg_fp32_modes_on_shared_lists(prec):
+    """FP32 Algorithm 1 (FP32 values and vectors, FP64 reliable updates) and
+    Algorithm 1 with FP32 values: solves to 1e-10 on the lists equal those on
+    per-entry columns bit for bit."""
+    A = stencil27_lognormal(40, seed=3)
+    b = rhs_from_solution(A, xstar_uniform(A.n, 5))
+    res = []
+    for f in (SH, NOSH):
+        S = Solver(A, tol=1e-10, precision=prec, method="pcg", spmv_format="sell", flags=f)
+        x, info = S.solve(dev(b))
+        assert info["status"] == ppcg.OK, info
+        assert oracle.true_relres(A, b, host(x)) <= 1e-10
+        res.append((host(x), info["iters"], info["outer_iters"]))
+        S.close()
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
