@@ -941,7 +941,9 @@ static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const doubl
         tv = std::min(tv, t);
     }
     const double t_update_ms = byte_model(h, PREC_F64).vma / 6.5e12 * 1e3;
-    const bool keep = tf - tv >= 0.05 * (tf + t_update_ms);
+    // systems the one-workgroup kernel iterates keep the table: it stages the
+    // matrix in LDS through it
+    const bool keep = tf - tv >= 0.05 * (tf + t_update_ms) || h->n <= PPCG_SMALL_MAX_ROWS;
     if (!keep)
         drop_vtab(h);
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -21,9 +21,18 @@ namespace ppcg {
 // HBM is complete between launches.  SELL
 // format only; rows of a wavefront form one SELL chunk, so chunk lengths are
 // uniform across each wavefront.
+//
+// With the one-byte value table (the matrix has at most 256 distinct values)
+// and at most kSmallLdsEntries stored entries, the matrix itself is staged
+// in LDS at the start of the launch, each entry as a 16-bit column offset
+// from its row and its value index: the SpMV of an iteration then reads
+// nothing from global memory, and its steps over a row's entries wait on
+// LDS instead of L2 round trips.  Same values and order, so the same sums.
 constexpr int kSmallThreads = 512;
 constexpr int kSmallRowsPerThread = 8;
 constexpr int kSmallMaxRows = kSmallThreads * kSmallRowsPerThread;
+constexpr int kSmallLdsEntries = 24576;
+static_assert(kSmallMaxRows <= 32768, "column offsets from the row fit 16 bits");
 static_assert(PPCG_SMALL_MAX_ROWS <= kSmallMaxRows, "small systems must fit the register-resident kernel");
 
 __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__restrict__ table,
@@ -37,6 +46,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
     __shared__ double scal[2];            // alpha, beta of the next update
     __shared__ SysState loc;              // the state record, written back at the end of the launch
     __shared__ int stop;
+    __shared__ short lco[kSmallLdsEntries];           // staged matrix: column - row
+    __shared__ unsigned char lvi[kSmallLdsEntries];   // and value index
+    __shared__ double ltab[kMaxValueTable];           // the value table
     if ((int)blockIdx.x >= *count)
         return;
     const WorkItem wi = table[blockIdx.x];
@@ -90,14 +102,29 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
         const int c = wave + j * (kSmallThreads / 64);
         base[j] = 0;
         len[j] = 0;
-        if (c * kSellC < n) {
-            base[j] = (int)cptr[c] + lane;
-            len[j] = (int)((cptr[c + 1] - cptr[c]) / kSellC);
+        if (c * kSellC < n) {  // c is the same in every lane: scalar registers
+            base[j] = __builtin_amdgcn_readfirstlane((int)cptr[c]);
+            len[j] = __builtin_amdgcn_readfirstlane((int)((cptr[c + 1] - cptr[c]) / kSellC));
         }
         maxlen = len[j] > maxlen ? len[j] : maxlen;
     }
     const bool dconst = d.dinv_const != 0;
     const double d0 = DI[0];
+    // staged matrix (uniform over the workgroup)
+    const bool staged = d.vidx != nullptr && cptr[(n + kSellC - 1) / kSellC] <= kSmallLdsEntries;
+    if (staged) {
+        for (int t = threadIdx.x; t < d.nvtab; t += kSmallThreads)
+            ltab[t] = d.vtab[t];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int row = threadIdx.x + j * kSmallThreads;
+            for (int k = 0; k < len[j]; ++k) {
+                const int o = base[j] + lane + k * kSellC;
+                lco[o] = (short)(col[o] - row);
+                lvi[o] = d.vidx[o];
+            }
+        }
+    }
     __syncthreads();
     for (int it = 0; it < iters && !stop; ++it) {
         const double sa = scal[0], sb = scal[1];
@@ -135,7 +162,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
 #pragma unroll
         for (int j = 0; j < R; ++j)
             nv[j] = 0.0;
-        for (int k = 0; k < maxlen; ++k) {
+        if (staged) {
+            for (int k = 0; k < maxlen; ++k) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    if (k < len[j]) {
+                        const int o = base[j] + lane + k * kSellC;
+                        nv[j] = nv[j] + ltab[lvi[o]] * lm[threadIdx.x + j * kSmallThreads + lco[o]];
+                    }
+                }
+            }
+        }
+        for (int k = 0; k < (staged ? 0 : maxlen); ++k) {
             // entry k of every row slot: loads first, then the LDS gathers
             int cv[R];
             double vv[R];
@@ -144,7 +182,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_iter(const WorkItem *__
                 cv[j] = 0;
                 vv[j] = 0.0;
                 if (k < len[j]) {
-                    const size_t o = (size_t)base[j] + (size_t)k * kSellC;
+                    const size_t o = (size_t)base[j] + lane + (size_t)k * kSellC;
                     cv[j] = col[o];
                     vv[j] = val[o];
                 }

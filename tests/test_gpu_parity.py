@@ -752,3 +752,24 @@ def test_fp32_values_batch_bitwise_equals_solo():
     for x, xs_, info in zip(xs, solo, infos):
         assert np.array_equal(host(x), xs_)
         assert info["status"] == ppcg.OK and info["rel_resid_true"] <= 1e-10
+
+
+@pytest.mark.parametrize("gen", [lambda: poisson2d(64), lambda: poisson2d(37), lambda: shifted(poisson3d(14), 0.1)])
+def test_small_kernel_matrix_in_lds_is_bitwise(gen):
+    """The one-workgroup kernel stages a matrix with a value table in LDS
+    (16-bit column offsets and one-byte value indices) and reads nothing else
+    per iteration; with 8-byte values forced it reads the matrix from memory.
+    Both add the same products in the same order: the solves are equal bit
+    for bit, and meet the tolerance."""
+    A = gen()
+    b, _ = problem(A)
+    res = []
+    for vflag in (ppcg.FLAG_SELL_VALUE_TABLE, ppcg.FLAG_SELL_FULL_VALUES):
+        S = Solver(A, tol=1e-10, spmv_format="sell", flags=vflag)
+        assert S.matrix_info()["value_bytes"] == (1 if vflag == ppcg.FLAG_SELL_VALUE_TABLE else 8)
+        x, info = S.solve(dev(b))
+        assert info["status"] == ppcg.OK
+        assert oracle.true_relres(A, b, host(x)) <= 1e-10
+        res.append((host(x), info["iters"]))
+        S.close()
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1] == res[1][1]
