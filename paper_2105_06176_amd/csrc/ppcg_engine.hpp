@@ -230,6 +230,7 @@ struct Group {
     int *stage_cnt_h = nullptr;
     int stage_cap = 0;
     std::vector<WorkItem> table_h;  // current iteration table
+    std::vector<WorkItem> table_up; // the table last uploaded to table_d (and sys_d)
     bool table_dirty = true;
     // classic PCG groups: one item (slot, 0) per iterating system, for the
     // per-system reduction kernels

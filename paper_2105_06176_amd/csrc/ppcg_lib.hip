@@ -1679,6 +1679,15 @@ ppcg_status Engine::ensure_table(Group &g)
 {
     if (!g.table_dirty)
         return PPCG_OK;
+    // the table on the device is already this one (e.g. the same system
+    // solved again after its table emptied on the host): nothing to send,
+    // and no wait for the staging buffer
+    if (g.table_h.size() == g.table_up.size() &&
+        std::equal(g.table_h.begin(), g.table_h.end(), g.table_up.begin(),
+                   [](const WorkItem &a, const WorkItem &b) { return a.slot == b.slot && a.tile == b.tile; })) {
+        g.table_dirty = false;
+        return PPCG_OK;
+    }
     PPCG_HIP(hipStreamSynchronize(stream_));  // table_d / staging may still be in use
     WorkItem *old = g.table_d;
     PPCG_TRY(grow_table(&g.table_d, &g.table_cap, (int)g.table_h.size()));
@@ -1697,6 +1706,7 @@ ppcg_status Engine::ensure_table(Group &g)
         PPCG_TRY(upload_table(stream_, g, sys, g.sys_d, g.sys_count_d, 2));
         g.nsys = (int)sys.size();
     }
+    g.table_up = g.table_h;
     g.table_dirty = false;
     return PPCG_OK;
 }
@@ -1833,6 +1843,11 @@ std::vector<int> Engine::chunk_plan(const Group &g, int max_iters, bool *covers)
     }
     int left = std::min(want, kFixedChunksPerPoll * cap);
     *covers = left == want;
+    // a run that fits one chunk gets a graph of its exact length (one graph
+    // per fixed-iteration count): no launch gap and chunk-start node between
+    // chunks of powers of two
+    if (left <= cap)
+        return {left};
     std::vector<int> plan;
     while (left > 0) {
         int c = 1;
