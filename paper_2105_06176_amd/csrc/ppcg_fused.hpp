@@ -54,6 +54,12 @@ namespace ppcg {
 #ifndef PPCG_FUSED_WAVES
 #define PPCG_FUSED_WAVES 4
 #endif
+// 1: a thread's first row gets its SpMV before the reduction of the previous
+// partials and the scalar update (it does not depend on this launch's
+// scalars), so its latency overlaps that chain.
+#ifndef PPCG_FUSED_ROW0_EARLY
+#define PPCG_FUSED_ROW0_EARLY 1
+#endif
 // XCD-aware tile order (each XCD a contiguous range of tiles): 1.7 % faster
 // on the 128^3 7-point system.
 #ifndef PPCG_FUSED_REMAP
@@ -218,6 +224,28 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
         __syncthreads();
         tab = vtab;
     }
+    PPCG_AS1 double *__restrict__ X = as_global((double *)d.x);
+    PPCG_AS1 double *__restrict__ Rv = as_global((double *)d.r);
+    // w is read and written in place when it is not what the gathers read
+    const PPCG_AS1 double *__restrict__ W = as_global(wg ? gin : (const double *)d.w);
+    PPCG_AS1 double *__restrict__ Wo = as_global(wg ? gout : (double *)d.w);
+    PPCG_AS1 double *__restrict__ M = as_global(gout);
+    PPCG_AS1 double *__restrict__ Z = as_global((double *)d.z);
+    PPCG_AS1 double *__restrict__ S = as_global((double *)d.s);
+    PPCG_AS1 double *__restrict__ P = as_global((double *)d.p);
+    const PPCG_AS1 double *__restrict__ DI = as_global((const double *)d.dinv);
+#if PPCG_FUSED_ROW0_EARLY
+    // 0. This thread's first row: n = A m_i.
+    double nv0 = 0.0;
+    {
+        const int chunk = row0 / kSellC + wave;
+        if (chunk * kSellC < n) {  // uniform per wavefront
+            const int64_t eb = lane_i64(ext, 0);
+            const int el = (int)((lane_i64(ext, 1) - eb) / kSellC);
+            nv0 = fused_row(d, gin, chunk, lane, tab, eb, el, __builtin_amdgcn_readlane(pst, 32));
+        }
+    }
+#endif
     // 1. The previous launch's partials, all tiles of the system, in tile
     // order per thread, then the fixed workgroup tree; the scalar recurrences.
     {
@@ -270,8 +298,6 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     if (!sc.go) {
         if (sc.x_finish) {
             const double a = sc.alpha_x;
-            PPCG_AS1 double *__restrict__ X = as_global((double *)d.x);
-            const PPCG_AS1 double *__restrict__ P = as_global((const double *)d.p);
             for (int k = 0; k < R; ++k) {
                 const int i = row0 + k * kFusedThreads + tid;
                 if (i < n)
@@ -284,16 +310,6 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
     // into a register, then the fused update with it.
     const double sa = sc.alpha, sb = sc.beta, ax = sc.alpha_x;
     const bool xp = sc.x_pending != 0;
-    PPCG_AS1 double *__restrict__ X = as_global((double *)d.x);
-    PPCG_AS1 double *__restrict__ Rv = as_global((double *)d.r);
-    // w is read and written in place when it is not what the gathers read
-    const PPCG_AS1 double *__restrict__ W = as_global(wg ? gin : (const double *)d.w);
-    PPCG_AS1 double *__restrict__ Wo = as_global(wg ? gout : (double *)d.w);
-    PPCG_AS1 double *__restrict__ M = as_global(gout);
-    PPCG_AS1 double *__restrict__ Z = as_global((double *)d.z);
-    PPCG_AS1 double *__restrict__ S = as_global((double *)d.s);
-    PPCG_AS1 double *__restrict__ P = as_global((double *)d.p);
-    const PPCG_AS1 double *__restrict__ DI = as_global((const double *)d.dinv);
     double acc[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int k = 0; k < R; ++k) {
@@ -304,7 +320,11 @@ __global__ __launch_bounds__(kFusedThreads, PPCG_FUSED_WAVES) void k_fused(const
         const int64_t eb = lane_i64(ext, 2 * k);
         const int el = (int)((lane_i64(ext, 2 * k + 1) - eb) / kSellC);
         const int ep = __builtin_amdgcn_readlane(pst, 32 + k);
+#if PPCG_FUSED_ROW0_EARLY
+        const double nv = k == 0 ? nv0 : fused_row(d, gin, chunk, lane, tab, eb, el, ep);
+#else
         const double nv = fused_row(d, gin, chunk, lane, tab, eb, el, ep);
+#endif
         if (i < n) {
             double z = Z[i], w = W[i], s = S[i], p = P[i], r = Rv[i], u, mo;
             const double di = DI[d.dinv_const ? 0 : i];
