@@ -7,6 +7,8 @@
 // thread, chosen by the tile count and the compute units) and, in one
 // launch:
 //
+//   0. computes its first row of n = A m_i (which needs none of this
+//      launch's scalars), so that the latency of that SpMV overlaps step 1;
 //   1. reduces, in one fixed order, the per-tile partial sums of (r,u),
 //      (w,u), (u,u), (r,r) that the previous launch wrote, and runs the scalar
 //      recurrences (the stopping test, beta, alpha, breakdown) itself: every
