@@ -23,6 +23,7 @@ import pytest
 import oracle
 from paper_2105_06176_amd import ppcg
 from paper_2105_06176_amd.ppcg import Solver, solve_batch
+from shared_rule import shared_eligible
 from workloads import (poisson125, poisson2d, poisson3d, random_spd, rhs_from_solution, shifted,
                        stencil27_lognormal, xstar_uniform)
 
@@ -34,8 +35,6 @@ VT = ppcg.FLAG_SELL_VALUE_TABLE
 FV = ppcg.FLAG_SELL_FULL_VALUES
 FUSED = ppcg.FLAG_ITER_FUSED
 TWO = ppcg.FLAG_ITER_TWO_LAUNCH
-C = 64
-MAX_LIST_INTS = 8192
 
 
 def dev(a):
@@ -50,29 +49,6 @@ def host(t):
 
 def relerr(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
-def shared_eligible(A) -> bool:
-    """Chunks of 64 consecutive rows: the union of a chunk's row offsets
-    col - row has at most 2 len + 2 members (len: its longest row); the
-    chunks widened to their unions hold at most 1/32 more slots than the
-    chunks of longest rows; the distinct unions together hold at most
-    MAX_LIST_INTS offsets."""
-    lists = set()
-    before = after = 0
-    for c0 in range(0, A.n, C):
-        offs = set()
-        longest = 0
-        for r in range(c0, min(c0 + C, A.n)):
-            cols = A.ci[A.rp[r]:A.rp[r + 1]]
-            longest = max(longest, len(cols))
-            offs.update((cols - r).tolist())
-        if len(offs) > 2 * longest + 2:
-            return False
-        before += longest
-        after += max(longest, len(offs))
-        lists.add(tuple(sorted(offs)))
-    return after * 32 <= before * 33 and sum(len(t) for t in lists) <= MAX_LIST_INTS
 
 
 MATS = {
