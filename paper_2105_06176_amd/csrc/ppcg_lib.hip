@@ -888,14 +888,14 @@ static void drop_vtab(ppcg_handle *h)
 // themselves, so the products are the same.  Constant-coefficient stencils
 // have two or three values; most assembled matrices have too many, and the
 // scan gives up early.  Both layouts are timed like the column layouts
-// (alternated), and the table is kept when the SpMV time it saves is at
-// least 5 % of an iteration (the SpMV plus the fused update, whose time is
-// estimated from its bytes at 6.5 TB/s): it costs a scan and a byte per
-// entry at setup, so a gain within run-to-run noise is not taken.  The short
-// rows of a 7-point stencil are bound by the latency of the column load and
-// the gather that depends on it: halving their bytes saved 2-3 % of the
-// SpMV, about 1 % of an iteration.  The 125-point rows' SpMV ran 1.45x
-// faster.  The decision is cached per (rows, mean row length) signature: a
+// (alternated), and the table is kept unless it made the SpMV more than 2 %
+// slower: the timed two-launch SpMV of a short-row system is bound by
+// latency and shows the saved bytes little (7-point rows: 2-3 %), while the
+// single-launch iteration, where most such systems end up, gains from them
+// (7-point 128^3: with the 16-bit columns 66.7 -> 56.6 us per iteration;
+// a batch of 256 2-D systems kept the table for 109 of them under a rule of
+// a 5 % gain per iteration).  The 125-point rows' SpMV ran 1.45x faster.
+// The decision is cached per (rows, mean row length) signature: a
 // matrix of a signature whose table lost is not scanned, one whose table
 // won keeps its table when it has one, untimed.  PPCG_FLAG_SELL_VALUE_TABLE /
 // _FULL_VALUES force the choice, and PPCG_SELL_VTAB = 0 switches it off.
@@ -940,10 +940,9 @@ static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const doubl
         PPCG_TRY(time_spmv(h, 5, &t));
         tv = std::min(tv, t);
     }
-    const double t_update_ms = byte_model(h, PREC_F64).vma / 6.5e12 * 1e3;
     // systems the one-workgroup kernel iterates keep the table: it stages the
     // matrix in LDS through it
-    const bool keep = tf - tv >= 0.05 * (tf + t_update_ms) || h->n <= PPCG_SMALL_MAX_ROWS;
+    const bool keep = tv <= 1.02 * tf || h->n <= PPCG_SMALL_MAX_ROWS;
     if (!keep)
         drop_vtab(h);
     std::lock_guard<std::mutex> lk(g_tune_mu);
