@@ -918,7 +918,8 @@ static ppcg_status tune_vtab(ppcg_handle *h, const double *val_host, const doubl
             kept = it->second;
         }
     }
-    if (known && !kept)
+    // (a system the one-workgroup kernel iterates always takes the table)
+    if (known && !kept && h->n > PPCG_SMALL_MAX_ROWS)
         return PPCG_OK;
     std::vector<uint64_t> keys;
     bool fits = false;
