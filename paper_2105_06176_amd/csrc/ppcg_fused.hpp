@@ -51,7 +51,7 @@
 
 namespace ppcg {
 
-// Waves per SIMD the kernel is compiled for: 4 lets it keep its 74 VGPRs
+// Waves per SIMD the kernel is compiled for: 4 lets it keep its 76 VGPRs
 // (6 waves per SIMD in practice); forcing 8 spills and was 14 % slower.
 #ifndef PPCG_FUSED_WAVES
 #define PPCG_FUSED_WAVES 4

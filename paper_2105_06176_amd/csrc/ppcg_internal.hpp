@@ -37,7 +37,7 @@ constexpr int kFusedRowsPerThread = PPCG_FUSED_ROWS_PER_THREAD;  // at most
 constexpr int kFusedRows = kFusedThreads * kFusedRowsPerThread;    // at most
 static_assert(kFusedThreads == kTileRows, "a fused tile is a whole number of 512-row tiles");
 // Workgroups of the single-launch kernel one compute unit holds at once (its
-// 74 VGPRs allow 6 wavefronts per SIMD: 3 workgroups of 8 wavefronts).
+// 76 VGPRs allow 6 wavefronts per SIMD: 3 workgroups of 8 wavefronts).
 constexpr int kFusedResidentPerCU = 3;
 
 // Rows per fused tile (R rows per thread) for a system of n rows on a GPU of
