@@ -137,7 +137,7 @@ static_assert(kFusedThreads % kSellC == 0, "each wavefront of a fused tile reads
 // w into m (the single-launch iteration with a constant diagonal) run as
 // straight spans: 128^3, 78.5 -> 66.7 us per iteration.
 // 1: the classic-PCG SpMV with FP32 values and FP64 vectors also reads the
-// 16-bit column offsets (0: 32-bit columns for that combination; the C3
+// 16-bit column offsets (0: 32-bit columns for that combination; the 27-point 160^3
 // solve with them, straight spans in both: 210.9 against 207.0 ms).
 #ifndef PPCG_PCG_V32_COL16
 #define PPCG_PCG_V32_COL16 0
