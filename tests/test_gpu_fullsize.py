@@ -1,6 +1,7 @@
 """Parity at the workloads' full sizes, in the configurations bench.py times:
 the 27-point lognormal stencil at 160^3 (FP64 and FP32 values), the 256-system
-batch, and Table 2's 125-point Poisson matrix at side 165.  Reference values
+batch, Table 2's 125-point Poisson matrix at side 165, and the 4.1M-row random
+sparse SPD matrix.  Reference values
 the oracle cannot afford at this size inline come from tests/golden (written by
 make_c3_p125_reference.py from the oracle only); the rest is checked through
 properties that hold at any size (true residual recomputed by the oracle,
@@ -14,8 +15,8 @@ import pytest
 import oracle
 from paper_2105_06176_amd import ppcg
 from paper_2105_06176_amd.ppcg import Solver, solve_batch
-from workloads import (batch_c4, poisson125, poisson2d, rhs_from_solution, shifted, stencil27_lognormal,
-                       xstar_paper, xstar_uniform)
+from workloads import (batch_c4, poisson125, poisson2d, random_spd, rhs_from_solution, shifted,
+                       stencil27_lognormal, xstar_paper, xstar_uniform)
 
 pytestmark = pytest.mark.gpu
 
@@ -176,4 +177,25 @@ def test_table2_125pt_side165_full_size(p125, vflag):
     assert info["status"] == ppcg.OK
     assert abs(info["iters"] - int(meta["abs1e-5_iters"])) <= 2
     assert info["precond_norm"] < 1e-5
+    S.close()
+
+
+def test_random_spd_4_1m_full_size():
+    """The random sparse SPD matrix of the throughput measurements at full
+    size (4,096,000 rows, about 17 entries per row, uniform random columns)
+    in the autotuned storage: the SpMV equals the oracle's bit for bit, 10
+    fixed iterates meet the 1e-10 bar against the oracle's, and the solve to
+    1e-10 meets it (true residual recomputed by the oracle)."""
+    A = random_spd(4_096_000, seed=0)
+    b = rhs_from_solution(A, xstar_uniform(A.n, 1))
+    S = Solver(A, fixed_iters=10)
+    xs = xstar_uniform(A.n, 5)
+    assert np.array_equal(host(S.spmv(dev(xs))), oracle.spmv(A, xs))
+    x, info = S.solve(dev(b))
+    assert info["status"] == ppcg.OK and info["iters"] == 10, info
+    assert relerr(host(x), oracle.pipecg(A, b, fixed_iters=10).x) <= 1e-10
+    S.set_options(fixed_iters=0, tol=1e-10)
+    x, info = S.solve(dev(b))
+    assert info["status"] == ppcg.OK, info
+    assert oracle.true_relres(A, b, host(x)) <= 1e-10
     S.close()
